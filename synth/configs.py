@@ -1,0 +1,155 @@
+"""The five named workloads, as seeded synthetic inputs.
+
+    small_uniform      2,000 vertices / 8,000 uniform edges, one 3-vertex GFD
+    powerlaw_1m        Chung-Lu 1M / 5M (gamma 2.1), 8 shape GFDs of 3-6 vertices
+    kg_4m              Chung-Lu 4M / 20M (gamma 2.1), 16 walk GFDs of 4-8 vertices
+    kg_4m_batch256     the kg_4m graph, 256 walk GFDs of 2-8 vertices
+    kg_4m_serving      the kg_4m graph, Poisson request stream (1-4 GFDs each)
+
+The paper measures on a public social graph (Twitch Gamers) that is not
+available here; these synthetic inputs stand in for it.  Every array comes from
+numpy PCG64 sub-streams of the stated seed.  Generated inputs are cached as
+.npz/.json under $GFD_SYNTH_CACHE (default /tmp/gfd_synth_cache), keyed by the
+generator version, and always re-verified against their sha256.
+"""
+from __future__ import annotations
+
+import json
+import os
+import hashlib
+
+import numpy as np
+
+from .graphs import Graph, make_graph
+from . import patterns as P
+
+GEN_VERSION = 1
+
+GRAPHS = {
+    "small_uniform": dict(seed=0, n=2_000, m=8_000, model="uniform", n_vlabels=5, n_elabels=3,
+                          label_zipf=None, n_attrs=1, attr_values=50, attr_zipf=None),
+    "powerlaw_1m": dict(seed=1, n=1_000_000, m=5_000_000, model="chung_lu", n_vlabels=30,
+                        n_elabels=10, label_zipf=1.1, n_attrs=3, attr_values=10_000,
+                        attr_zipf=1.1),
+    "kg_4m": dict(seed=2, n=4_000_000, m=20_000_000, model="chung_lu", n_vlabels=100,
+                  n_elabels=40, label_zipf=1.2, n_attrs=4, attr_values=100_000, attr_zipf=1.2),
+}
+
+CONFIG_GRAPH = {"small_uniform": "small_uniform", "powerlaw_1m": "powerlaw_1m",
+                "kg_4m": "kg_4m", "kg_4m_batch256": "kg_4m", "kg_4m_serving": "kg_4m"}
+CONFIG_ORDER = ["small_uniform", "powerlaw_1m", "kg_4m", "kg_4m_batch256", "kg_4m_serving"]
+
+
+def cache_dir() -> str:
+    d = os.environ.get("GFD_SYNTH_CACHE", "/tmp/gfd_synth_cache")
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def _save_graph(path, g: Graph):
+    np.savez(path, n=g.n, m=g.m, row_ptr=g.row_ptr, col=g.col, vlabel=g.vlabel,
+             elabel=g.elabel, attrs=g.attrs, meta=json.dumps(g.meta))
+
+
+def _load_graph(path) -> Graph:
+    z = np.load(path, allow_pickle=False)
+    return Graph(n=int(z["n"]), m=int(z["m"]), row_ptr=z["row_ptr"], col=z["col"],
+                 vlabel=z["vlabel"], elabel=z["elabel"], attrs=z["attrs"],
+                 meta=json.loads(str(z["meta"])))
+
+
+def graph(name: str, use_cache: bool = True) -> Graph:
+    """The named graph (regenerated, or read from the cache and re-hashed)."""
+    spec = dict(GRAPHS[name])
+    seed = spec.pop("seed")
+    n, m = spec.pop("n"), spec.pop("m")
+    key = hashlib.sha256(json.dumps([GEN_VERSION, name, seed, n, m, spec], sort_keys=True)
+                         .encode()).hexdigest()[:16]
+    path = os.path.join(cache_dir(), f"{name}_{key}.npz")
+    if use_cache and os.path.exists(path):
+        g = _load_graph(path)
+        if g.sha256() == g.meta.get("sha256"):
+            return g
+    g, _ = make_graph(seed, n, m, **spec)
+    g.meta["sha256"] = g.sha256()
+    if use_cache:
+        tmp = path + ".tmp.npz"
+        _save_graph(tmp, g)
+        os.replace(tmp, path)
+    return g
+
+
+def gfd_stream(name: str):
+    spec = GRAPHS[CONFIG_GRAPH[name]]
+    seed = {"small_uniform": 0, "powerlaw_1m": 1, "kg_4m": 2, "kg_4m_batch256": 3,
+            "kg_4m_serving": 4}[name]
+    ss = np.random.SeedSequence(seed).spawn(5)
+    return np.random.Generator(np.random.PCG64(ss[4])), spec
+
+
+def _gfds_uncached(name: str, g: Graph):
+    rng, spec = gfd_stream(name)
+    av, az = spec["attr_values"], spec["attr_zipf"]
+    if name == "small_uniform":
+        # x -[e0]-> y, x -[e0]-> z with labels (L0, L1, L1); {} -> y.name = z.name
+        return [{"k": 3, "vlabels": [0, 1, 1], "edges": [[0, 1, 0], [0, 2, 0]], "x": [],
+                 "y": [{"kind": "var", "var": 1, "attr": 0, "var2": 2, "attr2": 0}],
+                 "y_false": False, "meta": {"fixed": True}}]
+    view = P.GraphView(g)
+    out = []
+    if name == "powerlaw_1m":
+        for shape, krange in (("path", (3, 6)), ("star", (3, 6)), ("triangle", (3, 6)),
+                              ("cycle4", (4, 6))):
+            for _ in range(2):
+                k = int(rng.integers(krange[0], krange[1] + 1))
+                out.append(P.sample_shape_gfd(rng, view, shape, k, (1, 2), av, az,
+                                              label_zipf=spec["label_zipf"],
+                                              n_vlabels=spec["n_vlabels"],
+                                              n_elabels=spec["n_elabels"]))
+        return out
+    if name == "kg_4m":
+        for _ in range(16):
+            out.append(P.sample_walk_gfd(rng, view, (4, 8), (1, 3), av, az, core_range=(3, 5)))
+        return out
+    if name == "kg_4m_batch256":
+        for _ in range(256):
+            out.append(P.sample_walk_gfd(rng, view, (2, 8), (1, 3), av, az, cyc_range=(0, 3)))
+        return out
+    raise ValueError(name)
+
+
+def gfds(name: str, g: Graph | None = None, use_cache: bool = True):
+    """The named config's GFD list (JSON dicts), generated from its seed."""
+    if g is None:
+        g = graph(CONFIG_GRAPH[name], use_cache=use_cache)
+    path = os.path.join(cache_dir(), f"gfds_{name}_v{GEN_VERSION}_{g.sha256()[:16]}.json")
+    if use_cache and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    out = _gfds_uncached(name, g)
+    if use_cache:
+        with open(path + ".tmp", "w") as f:
+            json.dump(out, f)
+        os.replace(path + ".tmp", path)
+    return out
+
+
+def gfds_sha256(gl) -> str:
+    strip = [{k: v for k, v in d.items() if k != "meta"} for d in gl]
+    return hashlib.sha256(json.dumps(strip, sort_keys=True).encode()).hexdigest()
+
+
+def serving_requests(g: Graph, rate: float = 200.0, duration_s: float = 60.0, seed: int = 4):
+    """Poisson arrivals; each request holds 1-4 GFDs of 3-8 vertices (walk sampled)."""
+    rng, spec = gfd_stream("kg_4m_serving")
+    view = P.GraphView(g)
+    t, reqs = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration_s:
+            break
+        nq = int(rng.integers(1, 5))
+        reqs.append({"t": t, "gfds": [
+            P.sample_walk_gfd(rng, view, (3, 8), (1, 3), spec["attr_values"], spec["attr_zipf"],
+                              cyc_range=(0, 3)) for _ in range(nq)]})
+    return reqs
