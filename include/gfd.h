@@ -1,0 +1,188 @@
+/*
+ * gfd.h -- C ABI of the MI355X (gfx950) GFD-validation library.
+ *
+ * A graph functional dependency (GFD) phi = (Q[x], X -> Y) or (Q[x], X -> false)
+ * pairs a graph pattern Q with attribute literals (FastGFDs paper, Section II).
+ * Validation of a set of GFDs over a graph G finds the violations: matches h of
+ * Q in G with h |= X and h |/= Y (Section II, "the validation problem").  This
+ * library computes, per GFD, the exact match and violation counts, the
+ * satisfied flag, the lexicographically first K violating matches and two
+ * order-independent fingerprints, on one GPU.  The matching follows the
+ * Compact Path Index and Core-First decomposition the paper adopts in
+ * Section IV-B; those only prune and order the search, so results are those
+ * of the plain definition.
+ *
+ * Conventions
+ *   - Every call returns an int32_t status (GFD_OK or a negative GFD_E* code);
+ *     gfd_last_error() returns a thread-local message for the last failure.
+ *     No C++ exception crosses this boundary.
+ *   - Vertex ids are 0..n-1 (n < 2^31); edge count m < 2^32.
+ *   - Labels are int32 >= 0; GFD_WILDCARD (-1) in a pattern matches any label
+ *     (vertex labels: Section II's wildcard; edge labels: any label).
+ *   - Attributes are dictionary-encoded int32 columns; GFD_ABSENT (-1) means the
+ *     vertex has no such attribute.  A literal that touches a missing attribute
+ *     is false (Section II: such constraints hold trivially in X, and a
+ *     literal in Y demands that the attribute exist).
+ *   - Matching semantics: GFD_SEM_INDUCED (default) reads Section II's match
+ *     definition literally -- an ordered pair of matched vertices is a data
+ *     edge iff it is a pattern edge, with equal labels.  GFD_SEM_MONO drops
+ *     the "only if" (extra data edges between matched vertices allowed).
+ */
+#ifndef GFD_H
+#define GFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define GFD_OK 0
+#define GFD_EINVAL (-1)       /* malformed graph, spec or option */
+#define GFD_ENOMEM (-2)       /* device or host allocation failed, or budget too small */
+#define GFD_EDEVICE (-3)      /* HIP runtime error */
+#define GFD_EUNSUPPORTED (-4) /* valid input outside this build's limits */
+#define GFD_EOVERFLOW (-5)    /* a 64-bit counter would pass 2^63 */
+
+#define GFD_WILDCARD (-1)
+#define GFD_ABSENT (-1)
+#define GFD_MAX_K 8          /* pattern vertices per GFD */
+#define GFD_MAX_LITERALS 8   /* literals in X, and separately in Y */
+#define GFD_MAX_PATTERN_EDGES (GFD_MAX_K * (GFD_MAX_K - 1))
+
+#define GFD_LIT_CONST 0 /* x_var.attr = constant            (Section II, constant literal) */
+#define GFD_LIT_VAR 1   /* x_var.attr = x_var2.attr2         (Section II, variable literal) */
+
+#define GFD_SEM_INDUCED 0
+#define GFD_SEM_MONO 1
+
+typedef struct gfd_graph gfd_graph; /* opaque; device-resident graph */
+
+typedef struct {
+  int32_t kind;     /* GFD_LIT_CONST or GFD_LIT_VAR */
+  int32_t var;      /* pattern variable index, 0..num_vertices-1 */
+  int32_t attr;     /* attribute column, 0..num_attrs-1 */
+  int32_t var2;     /* GFD_LIT_VAR only */
+  int32_t attr2;    /* GFD_LIT_VAR only */
+  int32_t constant; /* GFD_LIT_CONST only; must be >= 0 */
+} gfd_literal;
+
+typedef struct {
+  int32_t src, dst; /* pattern variables; src != dst */
+  int32_t label;    /* edge label, or GFD_WILDCARD */
+} gfd_edge;
+
+/* One GFD.  Variable order x = (x_0 .. x_{k-1}) is the index order below; it is
+ * the order of every reported tuple.  The pattern must be connected (through
+ * edges in either direction); at most one edge per ordered pair. */
+typedef struct {
+  int32_t num_vertices;                 /* k, 1..GFD_MAX_K */
+  int32_t vertex_labels[GFD_MAX_K];     /* label or GFD_WILDCARD */
+  int32_t num_edges;
+  gfd_edge edges[GFD_MAX_PATTERN_EDGES];
+  int32_t num_x;
+  gfd_literal x[GFD_MAX_LITERALS];
+  int32_t num_y;
+  gfd_literal y[GFD_MAX_LITERALS];
+  int32_t y_is_false;                   /* nonzero: X -> false (Y ignored) */
+} gfd_spec;
+
+/* Per-GFD result.  violations is caller-owned with room for
+ * k_max * num_vertices int32 (row-major tuples in variable order); it may be
+ * NULL when k_max == 0. */
+typedef struct {
+  int32_t satisfied;        /* 1 iff violation_count == 0 */
+  int32_t num_reported;     /* min(k_max, violation_count) */
+  uint64_t match_count;     /* number of matches (embeddings, tuples in x order) */
+  uint64_t violation_count; /* matches with X true and Y false */
+  uint64_t match_fp;        /* sum over matches of H(t) mod 2^64 */
+  uint64_t violation_fp;    /* sum over violations of H(t) mod 2^64 */
+  int32_t* violations;      /* [k_max * num_vertices], ascending lexicographic */
+} gfd_result;
+/* H(t): splitmix64 finaliser mix (Steele, Lea & Flood 2014) chained over the
+ * tuple: h = 0x9E3779B97F4A7C15 * k; for each t_i: h = mix(h ^ (uint32)t_i). */
+
+typedef struct {
+  void* hip_stream; /* hipStream_t for the upload; NULL = the null stream */
+} gfd_load_opts;
+
+typedef struct {
+  int32_t k_max;            /* K: violations to report per GFD, >= 0 */
+  int32_t semantics;        /* GFD_SEM_INDUCED or GFD_SEM_MONO */
+  int64_t mem_budget_bytes; /* device bytes for frontiers and buffers; 0 = default */
+  void* hip_stream;         /* hipStream_t to run on; NULL = the null stream */
+  int32_t batched;          /* reserved, must be 0 */
+  int32_t flags;            /* GFD_FLAG_* bits */
+  int64_t frontier_cap;     /* testing: max partial matches per level (0 = from budget) */
+  int64_t violation_cap;    /* testing: violation staging capacity in tuples (0 = default) */
+} gfd_validate_opts;
+
+#define GFD_FLAG_FORCE_CHUNKED 1 /* skip the single-pass fast path */
+#define GFD_FLAG_TIMING 2        /* record per-kernel-class HIP event timings */
+
+/* Per-call work and timing statistics (filled when requested). */
+typedef struct {
+  double wall_ms;             /* host wall time of the call */
+  int32_t launches;           /* kernels launched */
+  int32_t chunked_gfds;       /* GFDs that needed the chunked (budgeted) path */
+  uint64_t attempts;          /* extension attempts over all enumeration levels */
+  uint64_t partials;          /* partial matches written over all levels */
+  uint64_t cpi_candidates;    /* sum of final candidate-set sizes */
+  uint64_t cpi_entries;       /* sum of CPI adjacency entries */
+  /* per kernel class: [0] candidate filter, [1] CPI marking, [2] CPI adjacency,
+   * [3] enumeration (inner levels), [4] enumeration + literal check (last level),
+   * [5] scans, [6] top-K selection, [7] other */
+  int32_t class_launches[8];
+  double class_ms[8];         /* summed HIP event time (GFD_FLAG_TIMING) */
+  uint64_t class_bytes[8];    /* algorithmic bytes moved */
+} gfd_stats;
+
+/* Load a graph given as out-CSR on the host.  Inputs are read and copied: the
+ * caller may free them on return.  Rows need not be sorted.  attr is an array
+ * of num_attrs pointers to columns of n int32 (values >= 0 or GFD_ABSENT).
+ * Errors: GFD_EINVAL for row_ptr not starting at 0 / not non-decreasing / not
+ * ending at m, col out of range, a self-loop, a duplicate ordered pair,
+ * negative labels, attribute values < -1, null pointers; GFD_EUNSUPPORTED for
+ * n >= 2^31 or m >= 2^32; GFD_ENOMEM / GFD_EDEVICE from the device.
+ * (Section II: E is a subset of V x V, one label per vertex and per edge,
+ * attributes on vertices only.) */
+int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                       const int32_t* vlabel, const int32_t* elabel, int32_t num_attrs,
+                       const int32_t* const* attr, const gfd_load_opts* opts,
+                       gfd_graph** out);
+
+/* Release a graph and every device buffer it owns.  NULL is ignored. */
+void gfd_free_graph(gfd_graph* g);
+
+/* Validate num_specs GFDs over g (Section II's validation problem, per GFD).
+ * Synchronous: returns once every result is on the host.  results is
+ * caller-allocated [num_specs], each with its violations buffer.  A malformed
+ * spec fails the whole call with GFD_EINVAL before any launch; a disconnected
+ * pattern is GFD_EUNSUPPORTED.  Concurrent calls on one graph are allowed on
+ * distinct streams. */
+int32_t gfd_validate(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
+                     const gfd_validate_opts* opts, gfd_result* results);
+
+/* gfd_validate plus per-call statistics (stats may be NULL). */
+int32_t gfd_validate_ex(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
+                        const gfd_validate_opts* opts, gfd_result* results, gfd_stats* stats);
+
+/* Graph facts: sizes and the device bytes it holds. */
+typedef struct {
+  int64_t n, m;
+  int32_t num_attrs, num_vertex_labels, num_edge_labels;
+  int64_t device_bytes;
+} gfd_graph_info;
+int32_t gfd_get_graph_info(const gfd_graph* g, gfd_graph_info* info);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* gfd_last_error(void);
+
+/* Library version, as major*10000 + minor*100 + patch. */
+int32_t gfd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFD_H */

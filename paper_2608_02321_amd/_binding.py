@@ -1,0 +1,259 @@
+"""ctypes binding of include/gfd.h (argument marshalling only).
+
+Every step of validation runs in libgfd.so's HIP kernels; this module only
+converts Python/numpy inputs into the C structs and back.  It raises at import
+time if the library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgfd.so")
+
+GFD_OK, GFD_EINVAL, GFD_ENOMEM, GFD_EDEVICE, GFD_EUNSUPPORTED, GFD_EOVERFLOW = 0, -1, -2, -3, -4, -5
+GFD_WILDCARD = GFD_ABSENT = -1
+GFD_MAX_K = 8
+GFD_MAX_LITERALS = 8
+GFD_MAX_PATTERN_EDGES = GFD_MAX_K * (GFD_MAX_K - 1)
+GFD_LIT_CONST, GFD_LIT_VAR = 0, 1
+GFD_SEM_INDUCED, GFD_SEM_MONO = 0, 1
+GFD_FLAG_FORCE_CHUNKED, GFD_FLAG_TIMING = 1, 2
+STATUS_NAMES = {0: "GFD_OK", -1: "GFD_EINVAL", -2: "GFD_ENOMEM", -3: "GFD_EDEVICE",
+                -4: "GFD_EUNSUPPORTED", -5: "GFD_EOVERFLOW"}
+KERNEL_CLASSES = ("filter", "mark", "adjacency", "extend", "extend_last", "scan", "topk", "other")
+
+
+class GfdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class gfd_literal(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("var", C.c_int32), ("attr", C.c_int32),
+                ("var2", C.c_int32), ("attr2", C.c_int32), ("constant", C.c_int32)]
+
+
+class gfd_edge(C.Structure):
+    _fields_ = [("src", C.c_int32), ("dst", C.c_int32), ("label", C.c_int32)]
+
+
+class gfd_spec(C.Structure):
+    _fields_ = [("num_vertices", C.c_int32), ("vertex_labels", C.c_int32 * GFD_MAX_K),
+                ("num_edges", C.c_int32), ("edges", gfd_edge * GFD_MAX_PATTERN_EDGES),
+                ("num_x", C.c_int32), ("x", gfd_literal * GFD_MAX_LITERALS),
+                ("num_y", C.c_int32), ("y", gfd_literal * GFD_MAX_LITERALS),
+                ("y_is_false", C.c_int32)]
+
+
+class gfd_result(C.Structure):
+    _fields_ = [("satisfied", C.c_int32), ("num_reported", C.c_int32),
+                ("match_count", C.c_uint64), ("violation_count", C.c_uint64),
+                ("match_fp", C.c_uint64), ("violation_fp", C.c_uint64),
+                ("violations", C.POINTER(C.c_int32))]
+
+
+class gfd_load_opts(C.Structure):
+    _fields_ = [("hip_stream", C.c_void_p)]
+
+
+class gfd_validate_opts(C.Structure):
+    _fields_ = [("k_max", C.c_int32), ("semantics", C.c_int32),
+                ("mem_budget_bytes", C.c_int64), ("hip_stream", C.c_void_p),
+                ("batched", C.c_int32), ("flags", C.c_int32),
+                ("frontier_cap", C.c_int64), ("violation_cap", C.c_int64)]
+
+
+class gfd_stats(C.Structure):
+    _fields_ = [("wall_ms", C.c_double), ("launches", C.c_int32), ("chunked_gfds", C.c_int32),
+                ("attempts", C.c_uint64), ("partials", C.c_uint64),
+                ("cpi_candidates", C.c_uint64), ("cpi_entries", C.c_uint64),
+                ("class_launches", C.c_int32 * 8), ("class_ms", C.c_double * 8),
+                ("class_bytes", C.c_uint64 * 8)]
+
+
+class gfd_graph_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("num_attrs", C.c_int32),
+                ("num_vertex_labels", C.c_int32), ("num_edge_labels", C.c_int32),
+                ("device_bytes", C.c_int64)]
+
+
+EXPORTS = ("gfd_load_graph", "gfd_free_graph", "gfd_validate", "gfd_validate_ex",
+           "gfd_get_graph_info", "gfd_last_error", "gfd_version")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python paper_2608_02321_amd/build.py); there is no CPU fallback")
+    L = C.CDLL(LIB_PATH)
+    L.gfd_load_graph.restype = C.c_int32
+    L.gfd_load_graph.argtypes = [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_int32, C.POINTER(C.c_void_p),
+                                 C.POINTER(gfd_load_opts), C.POINTER(C.c_void_p)]
+    L.gfd_free_graph.restype = None
+    L.gfd_free_graph.argtypes = [C.c_void_p]
+    L.gfd_validate.restype = C.c_int32
+    L.gfd_validate.argtypes = [C.c_void_p, C.POINTER(gfd_spec), C.c_int32,
+                               C.POINTER(gfd_validate_opts), C.POINTER(gfd_result)]
+    L.gfd_validate_ex.restype = C.c_int32
+    L.gfd_validate_ex.argtypes = [C.c_void_p, C.POINTER(gfd_spec), C.c_int32,
+                                  C.POINTER(gfd_validate_opts), C.POINTER(gfd_result),
+                                  C.POINTER(gfd_stats)]
+    L.gfd_get_graph_info.restype = C.c_int32
+    L.gfd_get_graph_info.argtypes = [C.c_void_p, C.POINTER(gfd_graph_info)]
+    L.gfd_last_error.restype = C.c_char_p
+    L.gfd_last_error.argtypes = []
+    L.gfd_version.restype = C.c_int32
+    L.gfd_version.argtypes = []
+    return L
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.gfd_last_error().decode()
+
+
+def version() -> int:
+    return int(lib.gfd_version())
+
+
+def _check(rc):
+    if rc != GFD_OK:
+        raise GfdError(rc, last_error())
+
+
+def _stream_handle(stream):
+    """hipStream_t of a torch stream (or an int handle); None = null stream."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def current_torch_stream():
+    import torch
+    if torch.cuda.is_available():
+        return torch.cuda.current_stream()
+    return None
+
+
+class GraphHandle:
+    """A graph resident on the device (gfd_load_graph / gfd_free_graph)."""
+
+    def __init__(self, h, info):
+        self._h = h
+        self.info = info
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("graph already freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib.gfd_free_graph(self._h)
+            self._h = None
+
+    __del__ = free
+
+
+def load_graph(n, m, row_ptr, col, vlabel, elabel, attrs=None, stream=None) -> GraphHandle:
+    """gfd_load_graph: out-CSR on the host; copies to the device."""
+    keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
+            np.ascontiguousarray(col, dtype=np.int32),
+            np.ascontiguousarray(vlabel, dtype=np.int32),
+            np.ascontiguousarray(elabel, dtype=np.int32)]
+    A = 0 if attrs is None else int(np.asarray(attrs).shape[0])
+    cols = [np.ascontiguousarray(np.asarray(attrs)[a], dtype=np.int32) for a in range(A)]
+    ptrs = (C.c_void_p * max(A, 1))(*[c.ctypes.data for c in cols])
+    opts = gfd_load_opts(_stream_handle(stream))
+    out = C.c_void_p()
+    rc = lib.gfd_load_graph(int(n), int(m), keep[0].ctypes.data, keep[1].ctypes.data,
+                            keep[2].ctypes.data, keep[3].ctypes.data, A, ptrs, C.byref(opts),
+                            C.byref(out))
+    _check(rc)
+    info = gfd_graph_info()
+    _check(lib.gfd_get_graph_info(out, C.byref(info)))
+    return GraphHandle(out.value, {f: getattr(info, f) for f, _ in gfd_graph_info._fields_})
+
+
+def load(g, stream=None) -> GraphHandle:
+    """Load an object with n, m, row_ptr, col, vlabel, elabel, attrs attributes."""
+    return load_graph(g.n, g.m, g.row_ptr, g.col, g.vlabel, g.elabel, g.attrs, stream=stream)
+
+
+def free_graph(gh: GraphHandle):
+    gh.free()
+
+
+def _lit(d) -> gfd_literal:
+    if d["kind"] in ("const", GFD_LIT_CONST):
+        return gfd_literal(GFD_LIT_CONST, d["var"], d["attr"], 0, 0, d["value"])
+    return gfd_literal(GFD_LIT_VAR, d["var"], d["attr"], d["var2"], d["attr2"], 0)
+
+
+def make_spec(gfd: dict) -> gfd_spec:
+    """GFD dict (k, vlabels, edges, x, y, y_false) -> gfd_spec."""
+    s = gfd_spec()
+    k = int(gfd["k"])
+    if len(gfd["vlabels"]) > GFD_MAX_K or len(gfd["edges"]) > GFD_MAX_PATTERN_EDGES or \
+            len(gfd.get("x", [])) > GFD_MAX_LITERALS or len(gfd.get("y", [])) > GFD_MAX_LITERALS:
+        raise GfdError(GFD_EUNSUPPORTED, "GFD exceeds the fixed spec capacity")
+    s.num_vertices = k
+    for i, l in enumerate(gfd["vlabels"]):
+        s.vertex_labels[i] = int(l)
+    s.num_edges = len(gfd["edges"])
+    for i, (a, b, l) in enumerate(gfd["edges"]):
+        s.edges[i] = gfd_edge(int(a), int(b), int(l))
+    xs, ys = gfd.get("x", []), gfd.get("y", [])
+    s.num_x, s.num_y = len(xs), len(ys)
+    for i, l in enumerate(xs):
+        s.x[i] = _lit(l)
+    for i, l in enumerate(ys):
+        s.y[i] = _lit(l)
+    s.y_is_false = int(bool(gfd.get("y_false", False)))
+    return s
+
+
+def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
+             mem_budget_bytes: int = 0, stream=None, flags: int = 0, frontier_cap: int = 0,
+             violation_cap: int = 0, stats: bool = False):
+    """gfd_validate(_ex): one result dict per GFD (plus a stats dict if asked)."""
+    n = len(gfds)
+    specs = (gfd_spec * max(n, 1))(*[make_spec(d) for d in gfds])
+    results = (gfd_result * max(n, 1))()
+    bufs = []
+    for i, d in enumerate(gfds):
+        b = np.zeros(max(1, K * int(d["k"])), dtype=np.int32)
+        bufs.append(b)
+        results[i].violations = b.ctypes.data_as(C.POINTER(C.c_int32))
+    opts = gfd_validate_opts(K, GFD_SEM_INDUCED if semantics == "induced" else GFD_SEM_MONO,
+                             int(mem_budget_bytes), _stream_handle(stream), 0, int(flags),
+                             int(frontier_cap), int(violation_cap))
+    st = gfd_stats()
+    rc = lib.gfd_validate_ex(graph.handle, specs, n, C.byref(opts), results,
+                             C.byref(st) if stats else None)
+    _check(rc)
+    out = []
+    for i, d in enumerate(gfds):
+        r = results[i]
+        k = int(d["k"])
+        out.append({"match_count": int(r.match_count), "violation_count": int(r.violation_count),
+                    "match_fp": int(r.match_fp), "violation_fp": int(r.violation_fp),
+                    "satisfied": bool(r.satisfied),
+                    "violations": bufs[i][:r.num_reported * k].reshape(-1, k).tolist()})
+    if stats:
+        sd = {f: getattr(st, f) for f, _ in gfd_stats._fields_}
+        for f in ("class_launches", "class_ms", "class_bytes"):
+            sd[f] = dict(zip(KERNEL_CLASSES, list(sd[f])))
+        return out, sd
+    return out

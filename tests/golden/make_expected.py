@@ -1,0 +1,36 @@
+"""Writes tests/golden/expected_<workload>.json: the CPU oracle's results for
+the full-size workloads (both matching readings, K = 1024), with the graph's
+sha256 and the exact GFD list they were computed for.  Calls only the seeded
+generators and oracle/.
+
+    python tests/golden/make_expected.py powerlaw_1m kg_4m
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from synth import configs  # noqa: E402
+
+
+def main(names, K=1024, threads=os.cpu_count() or 1):
+    for name in names:
+        g = configs.graph(configs.CONFIG_GRAPH[name])
+        gfds = [{k: v for k, v in d.items() if k != "meta"} for d in configs.gfds(name, g)]
+        og = O.OracleGraph(g)
+        out = {"workload": name, "graph_sha256": g.sha256(), "K": K, "gfds": gfds,
+               "results": {}, "oracle_threads": threads}
+        for sem in ("induced", "mono"):
+            t = time.time()
+            out["results"][sem] = [O.validate(og, d, sem, K=K, threads=threads) for d in gfds]
+            print(name, sem, f"{time.time() - t:.1f}s", flush=True)
+        with open(os.path.join(HERE, f"expected_{name}.json"), "w") as f:
+            json.dump(out, f, separators=(",", ":"))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["powerlaw_1m", "kg_4m"])

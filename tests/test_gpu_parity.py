@@ -1,0 +1,209 @@
+"""GPU path vs the CPU oracle, element by element (counts, satisfied flag,
+fingerprints, first-K violation tuples), through the C ABI.
+
+Sizes span many 256-thread tiles with ragged tails; special cases cover empty
+results, k = 1, wildcards, missing attributes, X -> false, K = 0 / 1 / max,
+the budget-bounded (chunked) path and violation-staging compaction.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import configs, from_edge_list
+from synth.small import random_graph, random_gfd
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SEMS = ("induced", "mono")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_02321_amd as P
+    return P
+
+
+def _check(P, g, gfds, sem, K=1024, gh=None, **kw):
+    own = gh is None
+    if own:
+        gh = P.load(g)
+    got = P.validate(gh, gfds, K=K, semantics=sem, **kw)
+    og = O.OracleGraph(g)
+    for i, (d, r) in enumerate(zip(gfds, got)):
+        exp = O.validate(og, d, sem, K=K, threads=4)
+        assert r == exp, (i, sem, d, {k: v for k, v in r.items() if k != "violations"},
+                          {k: v for k, v in exp.items() if k != "violations"})
+    if own:
+        gh.free()
+    return got
+
+
+@pytest.mark.parametrize("sem", SEMS)
+def test_st_petersburg_fixture(P, sem):
+    d = json.load(open(os.path.join(GOLDEN, "x1_st_petersburg.json")))
+    gr = d["graph"]
+    for extra, exp in [([], d["expected"][sem]),
+                       (d["variant_contains_place"]["extra_edges"],
+                        d["variant_contains_place"]["expected"][sem])]:
+        g = from_edge_list(gr["n"], [tuple(e) for e in gr["edges"] + extra], gr["vlabel"],
+                           [gr["name"]])
+        gh = P.load(g)
+        r = P.validate(gh, [d["gfd"]], semantics=sem)[0]
+        for key in ("match_count", "violation_count", "satisfied", "violations"):
+            assert r[key] == exp[key]
+        gh.free()
+
+
+@pytest.mark.parametrize("sem", SEMS)
+def test_small_uniform(P, sem):
+    g = configs.graph("small_uniform")
+    _check(P, g, configs.gfds("small_uniform", g), sem)
+
+
+def _tiny_case(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 30))
+    m = int(rng.integers(1, min(n * (n - 1), 150) + 1))
+    g = random_graph(seed, n, m, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3)
+    gfds = [random_gfd(seed * 10 + j, int(rng.integers(1, min(n, 6) + 1)), n_vlabels=2,
+                       n_elabels=2, n_attrs=2, attr_values=3) for j in range(6)]
+    return g, gfds
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_tiny(P, seed):
+    g, gfds = _tiny_case(seed)
+    for sem in SEMS:
+        _check(P, g, gfds, sem, K=7)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_medium(P, seed):
+    """2,000 vertices / 20,000 edges, dense enough for many tiles of matches."""
+    rng = np.random.default_rng(100 + seed)
+    g = random_graph(100 + seed, 2000, 20000, n_vlabels=2, n_elabels=2, n_attrs=2,
+                     attr_values=4, absent_frac=0.1)
+    gfds = [random_gfd(1000 + 10 * seed + j, int(rng.integers(2, 5)), n_vlabels=2, n_elabels=2,
+                       n_attrs=2, attr_values=4, wildcard_frac=0.1, extra_edge_frac=0.5)
+            for j in range(5)]
+    for sem in SEMS:
+        _check(P, g, gfds, sem, K=100)
+
+
+def test_chunked_paths_agree(P):
+    """Tiny frontier / staging budgets force the chunked path and compaction."""
+    g = random_graph(7, 300, 4000, n_vlabels=2, n_elabels=2, n_attrs=1, attr_values=3)
+    gfds = [random_gfd(70 + j, 4, n_vlabels=2, n_elabels=2, n_attrs=1, attr_values=3,
+                       wildcard_frac=0.3) for j in range(4)]
+    gh = P.load(g)
+    for sem in SEMS:
+        _check(P, g, gfds, sem, K=16, gh=gh, frontier_cap=97)
+        _check(P, g, gfds, sem, K=16, gh=gh, flags=P.GFD_FLAG_FORCE_CHUNKED)
+        _check(P, g, gfds, sem, K=16, gh=gh, violation_cap=40)
+        _check(P, g, gfds, sem, K=16, gh=gh, frontier_cap=61, violation_cap=17)
+    gh.free()
+
+
+def test_select_path(P):
+    """More than 2,048 staged violations: radix select of the first K."""
+    g = random_graph(8, 400, 12000, n_vlabels=1, n_elabels=1, n_attrs=1, attr_values=50,
+                     absent_frac=0.0)
+    gfd = {"k": 3, "vlabels": [0, 0, 0], "edges": [[0, 1, 0], [0, 2, 0]], "x": [],
+           "y": [{"kind": "var", "var": 1, "attr": 0, "var2": 2, "attr2": 0}], "y_false": False}
+    gh = P.load(g)
+    for K in (1024, 2048, 1, 0):
+        r = _check(P, g, [gfd], "mono", K=K, gh=gh)
+        assert r[0]["violation_count"] > 2048
+    _check(P, g, [gfd], "induced", K=333, gh=gh, violation_cap=3000)
+    gh.free()
+
+
+def test_single_vertex_patterns(P):
+    g = random_graph(9, 500, 2000, n_vlabels=3, n_attrs=2, attr_values=4, absent_frac=0.3)
+    gfds = [{"k": 1, "vlabels": [L], "edges": [], "x": [],
+             "y": [{"kind": "var", "var": 0, "attr": A, "var2": 0, "attr2": A}], "y_false": False}
+            for L in (0, 1, -1) for A in (0, 1)]
+    gfds.append({"k": 1, "vlabels": [2], "edges": [],
+                 "x": [{"kind": "const", "var": 0, "attr": 0, "value": 1}], "y": [],
+                 "y_false": True})
+    for sem in SEMS:
+        _check(P, g, gfds, sem, K=50)
+        _check(P, g, gfds, sem, K=50, violation_cap=60)
+
+
+def test_empty_results_and_labels_absent_from_graph(P):
+    g = random_graph(10, 50, 100, n_vlabels=2, n_elabels=2, n_attrs=1)
+    gfds = [{"k": 3, "vlabels": [7, 0, 1], "edges": [[0, 1, 0], [1, 2, 0]], "x": [], "y": [],
+             "y_false": False},
+            {"k": 2, "vlabels": [0, 1], "edges": [[0, 1, 9]], "x": [], "y": [], "y_false": True},
+            {"k": 4, "vlabels": [0, 0, 0, 0],
+             "edges": [[0, 1, 0], [1, 2, 0], [2, 3, 0], [3, 0, 0], [0, 2, 0], [1, 3, 0]],
+             "x": [], "y": [], "y_false": True}]
+    for sem in SEMS:
+        r = _check(P, g, gfds, sem)
+        assert r[0]["match_count"] == 0 and r[0]["satisfied"]
+
+
+def test_full_pattern_size(P):
+    """k = 8 (the maximum) with antiparallel pairs and wildcards."""
+    g = random_graph(11, 60, 1500, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3,
+                     reciprocal_frac=0.6)
+    gfds = [random_gfd(110 + j, 8, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3,
+                       wildcard_frac=0.5, extra_edge_frac=0.2) for j in range(3)]
+    gfds.append({"k": 8, "vlabels": [-1] * 8, "edges": [[i, i + 1, -1] for i in range(7)],
+                 "x": [], "y": [], "y_false": True})
+    for sem in SEMS:
+        _check(P, g, gfds, sem, K=64)
+
+
+def test_errors(P):
+    g = random_graph(12, 20, 40)
+    gh = P.load(g)
+    bad = [
+        ({"k": 3, "vlabels": [0, 0, 0], "edges": [[0, 1, 0]], "x": [], "y": []}, P.GfdError),
+        ({"k": 2, "vlabels": [0, 0], "edges": [[0, 0, 0]], "x": [], "y": []}, P.GfdError),
+        ({"k": 2, "vlabels": [0, 0], "edges": [[0, 1, 0], [0, 1, 1]], "x": [], "y": []},
+         P.GfdError),
+        ({"k": 2, "vlabels": [0, 0], "edges": [[0, 1, 0]],
+          "x": [{"kind": "const", "var": 0, "attr": 5, "value": 1}], "y": []}, P.GfdError),
+        ({"k": 2, "vlabels": [0, 0], "edges": [[0, 1, 0]],
+          "x": [{"kind": "const", "var": 0, "attr": 0, "value": -1}], "y": []}, P.GfdError),
+    ]
+    codes = []
+    for d, exc in bad:
+        with pytest.raises(exc) as ei:
+            P.validate(gh, [d])
+        codes.append(ei.value.code)
+    assert codes == [-4, -1, -1, -1, -1]
+    with pytest.raises(P.GfdError) as ei:
+        P.validate(gh, [{"k": 1, "vlabels": [0], "edges": [], "x": [], "y": []}], K=4096)
+    assert ei.value.code == -4
+    gh.free()
+
+
+def _expected(name):
+    return json.load(open(os.path.join(GOLDEN, f"expected_{name}.json")))
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["powerlaw_1m", "kg_4m"])
+def test_full_size_configs(P, name):
+    """Full-size workloads in the benchmark's launch configuration, against
+    oracle results stored by tests/golden/make_expected.py."""
+    exp = _expected(name)
+    g = configs.graph(name)
+    assert g.sha256() == exp["graph_sha256"], "generated graph differs from the stored one"
+    gfds = exp["gfds"]
+    gh = P.load(g)
+    for sem in SEMS:
+        got = P.validate(gh, gfds, K=exp["K"], semantics=sem)
+        for i, (r, e) in enumerate(zip(got, exp["results"][sem])):
+            assert r == e, (name, sem, i)
+    gh.free()
