@@ -87,6 +87,14 @@ EXPORTS = ("gfd_load_graph", "gfd_free_graph", "gfd_validate", "gfd_validate_ex"
 
 
 def _load():
+    # One HIP runtime per process: torch ships its own libamdhip64 (soname
+    # libamdhip64.so.7, loaded as libamdhip64.so).  Loading torch first lets
+    # libgfd.so bind to that same runtime; loading libgfd.so first would bring in
+    # a second HIP/HSA runtime that cannot see the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(python paper_2608_02321_amd/build.py); there is no CPU fallback")

@@ -1105,13 +1105,12 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
   const int K = o.k_max;
   Workspace* ws = nullptr;
   try {
+    int64_t per_slot = 0;
+    for (int i = 2; i < MAXK; i++) per_slot += 4 * i + 12;
+    if (o.mem_budget_bytes && o.mem_budget_bytes < 1024 * per_slot)
+      return set_error(GFD_ENOMEM, "mem_budget_bytes below %lld", (long long)(1024 * per_slot));
     int64_t budget = o.mem_budget_bytes ? o.mem_budget_bytes : default_budget();
-    if (o.frontier_cap) {
-      int64_t per_slot = 0;
-      for (int i = 2; i < MAXK; i++) per_slot += 4 * i + 12;
-      budget = std::max<int64_t>(1, o.frontier_cap) * per_slot;
-    }
-    if (budget < 1024 * 196) return set_error(GFD_ENOMEM, "mem_budget_bytes too small");
+    if (o.frontier_cap) budget = std::max<int64_t>(1024, o.frontier_cap) * per_slot;
     ws = acquire_ws(g, budget);
     ws->cap = ws->alloc_cap;
     if (o.frontier_cap) ws->cap = std::min<uint64_t>(ws->alloc_cap, (uint64_t)o.frontier_cap);

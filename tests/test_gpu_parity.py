@@ -152,7 +152,7 @@ def test_empty_results_and_labels_absent_from_graph(P):
 
 def test_full_pattern_size(P):
     """k = 8 (the maximum) with antiparallel pairs and wildcards."""
-    g = random_graph(11, 60, 1500, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3,
+    g = random_graph(11, 60, 300, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3,
                      reciprocal_frac=0.6)
     gfds = [random_gfd(110 + j, 8, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3,
                        wildcard_frac=0.5, extra_edge_frac=0.2) for j in range(3)]
