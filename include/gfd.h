@@ -119,7 +119,9 @@ typedef struct {
 } gfd_validate_opts;
 
 #define GFD_FLAG_FORCE_CHUNKED 1 /* skip the single-pass fast path */
-#define GFD_FLAG_TIMING 2        /* record per-kernel-class HIP event timings */
+#define GFD_FLAG_TIMING 2        /* record HIP event timings for every kernel class */
+/* record HIP event timings for kernel class c (0..7, see gfd_stats) only */
+#define GFD_FLAG_TIMING_CLASS(c) (1 << (8 + (c)))
 
 /* Per-call work and timing statistics (filled when requested). */
 typedef struct {
@@ -135,7 +137,9 @@ typedef struct {
    * [5] scans, [6] top-K selection, [7] other */
   int32_t class_launches[8];
   double class_ms[8];         /* summed HIP event time (GFD_FLAG_TIMING) */
-  uint64_t class_bytes[8];    /* algorithmic bytes moved */
+  uint64_t class_bytes[8];    /* algorithmic bytes of the fast path's kernels in that
+                                class (bytes each item must touch, counted on the
+                                device); chunked re-runs are not counted */
 } gfd_stats;
 
 /* Load a graph given as out-CSR on the host.  Inputs are read and copied: the

@@ -17,6 +17,7 @@
 #include <atomic>
 #include <chrono>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -95,7 +96,8 @@ struct Workspace {
   uint8_t* mem[MAXK] = {};
   uint8_t* mark[MAXK] = {};
   int32_t* posmap[MAXK] = {};
-  uint32_t* cpi_off[MAXK] = {};
+  uint32_t* cpi_beg[MAXK] = {};
+  uint32_t* cpi_len[MAXK] = {};
   int32_t* cpi_ent[MAXK] = {};
   uint64_t* rowP = nullptr;   // [n+1]
   uint64_t* masks = nullptr;  // [max(m, n)/64 + 2]
@@ -104,6 +106,7 @@ struct Workspace {
   uint64_t* P[MAXK] = {};
   uint32_t* beg[MAXK] = {};
   uint64_t* dcnt = nullptr;   // [2*MAXK] candidate counts, + scratch totals
+  unsigned long long* stat_bytes = nullptr;  // [8] algorithmic bytes per kernel class
   ScanWs scan{};
   // chunked-path violation staging and selection
   int32_t* vbig = nullptr;
@@ -127,12 +130,13 @@ struct Workspace {
     for (auto p : mem) dfree(p);
     for (auto p : mark) dfree(p);
     for (auto p : posmap) dfree(p);
-    for (auto p : cpi_off) dfree(p);
+    for (auto p : cpi_beg) dfree(p);
+    for (auto p : cpi_len) dfree(p);
     for (auto p : cpi_ent) dfree(p);
     for (auto p : cols) dfree(p);
     for (auto p : P) dfree(p);
     for (auto p : beg) dfree(p);
-    dfree(rowP); dfree(masks); dfree(pre); dfree(dcnt);
+    dfree(rowP); dfree(masks); dfree(pre); dfree(dcnt); dfree(stat_bytes);
     dfree(scan.tile_state); dfree(scan.ticket); dfree(scan.err);
     dfree(vbig); dfree(sel_state); dfree(sel_hist); dfree(sel_out);
     dfree(ctl); dfree(vsmall); dfree(res);
@@ -310,12 +314,6 @@ extern "C" int32_t gfd_version(void) { return 100; }
 // planner (host): Section IV-B -- root, spanning tree, core-first order
 // ---------------------------------------------------------------------------
 
-struct MarkStep {
-  int src;     // pattern vertex whose candidates push marks
-  int dir;     // 0 out-rows, 1 in-rows of src candidates
-  int32_t elab;
-};
-
 struct Plan {
   int k = 0, root = 0;
   int32_t qlab[MAXK];
@@ -323,7 +321,8 @@ struct Plan {
   int bfs[MAXK], parent[MAXK], order[MAXK], pos[MAXK];
   int min_out[MAXK], min_in[MAXK];
   bool core[MAXK];
-  std::vector<MarkStep> down[MAXK], up[MAXK];
+  // pattern neighbours processed before / after each vertex in BFS order
+  std::vector<int> down[MAXK], up[MAXK];
   // CPI adjacency for tree edge (parent[u], u)
   int adj_dir[MAXK];
   int32_t adj_prim[MAXK], adj_other[MAXK];
@@ -468,13 +467,8 @@ static void make_plan(const gfd_graph* g, const gfd_spec& s, bool induced, Plan&
     int u = p.bfs[j];
     for (int w = 0; w < k; w++) {
       if (!adj[u][w]) continue;
-      if (bidx[w] < j) {  // earlier neighbour pushes marks onto u
-        if (p.qe[w][u] != NOEDGE) p.down[u].push_back({w, 0, p.qe[w][u]});
-        else p.down[u].push_back({w, 1, p.qe[u][w]});
-      } else {            // later neighbour, bottom-up pass
-        if (p.qe[u][w] != NOEDGE) p.up[u].push_back({w, 1, p.qe[u][w]});
-        else p.up[u].push_back({w, 0, p.qe[w][u]});
-      }
+      if (bidx[w] < j) p.down[u].push_back(w);  // top-down: earlier neighbours
+      else p.up[u].push_back(w);                // bottom-up: later neighbours
     }
   }
   for (int u = 0; u < k; u++) {
@@ -531,6 +525,7 @@ static void make_plan(const gfd_graph* g, const gfd_spec& s, bool induced, Plan&
 
 struct Timer {
   bool on = false;
+  uint32_t mask = 0xFFu;  // kernel classes to time
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -545,7 +540,7 @@ struct Timer {
   template <class F>
   void run(int cls, F f) {
     launches[cls]++;
-    if (!on) { f(); return; }
+    if (!on || !((mask >> cls) & 1u)) { f(); return; }
     hipEvent_t a = get(), b = get();
     HIPCHK(hipEventRecord(a, st));
     f();
@@ -582,6 +577,7 @@ struct Ctx {
   int K;
   Timer tm;
   gfd_stats* stats;
+  unsigned long long* stat_bytes;  // device [8] per kernel class, or nullptr
 };
 
 static uint8_t next_ep(Workspace* ws) {
@@ -615,7 +611,8 @@ static void alloc_workspace(gfd_graph* g, Workspace* ws, int64_t budget) {
     ws->mem[j] = dalloc<uint8_t>(n, t);
     ws->mark[j] = dalloc<uint8_t>(n, t);
     ws->posmap[j] = dalloc<int32_t>(n, t);
-    ws->cpi_off[j] = dalloc<uint32_t>(n + 1, t);
+    ws->cpi_beg[j] = dalloc<uint32_t>(n, t);
+    ws->cpi_len[j] = dalloc<uint32_t>(n, t);
     ws->cpi_ent[j] = dalloc<int32_t>(m, t);
   }
   ws->rowP = dalloc<uint64_t>(n + 1, t);
@@ -628,6 +625,7 @@ static void alloc_workspace(gfd_graph* g, Workspace* ws, int64_t budget) {
     ws->beg[i] = dalloc<uint32_t>(ws->pcap, t);
   }
   ws->dcnt = dalloc<uint64_t>(4 * MAXK, t);
+  ws->stat_bytes = dalloc<unsigned long long>(8, t);
   uint64_t max_items = std::max<uint64_t>({ws->pcap, (uint64_t)m, (uint64_t)n}) + 1;
   ws->scan.max_tiles = max_items / SCAN_TILE + 2;
   ws->scan.tile_state = dalloc<uint64_t>(ws->scan.max_tiles, t);
@@ -686,26 +684,6 @@ struct CandRef {
   uint64_t* cnt(Workspace* ws, int u) const { return ws->dcnt + 2 * u + cur[u]; }
 };
 
-// Candidate filter + compaction into cand buffer (u, which), membership epoch returned.
-static uint8_t run_filter(Ctx& c, FilterArgs& fa, uint64_t items_ub, int32_t* out, uint64_t* d_out_n,
-                          int mem_u) {
-  Workspace* ws = c.ws;
-  fa.masks = ws->masks;
-  const int grid = grid_for(items_ub);
-  c.tm.run(K_FILTER, [&] { filter_flags(c.st, fa, grid); });
-  // count of words: uses fa.d_n / fa.n_host; pass through a device count
-  const uint64_t* dn = fa.d_n;
-  if (!dn) {  // host-known count: stage it in a scratch word for the scan
-    fill_u64(c.st, ws->dcnt + 2 * MAXK + 2, fa.n_host, 1);
-    dn = ws->dcnt + 2 * MAXK + 2;
-  }
-  const uint64_t cap = fa.d_n ? fa.cap : fa.n_host;
-  c.tm.run(K_SCAN, [&] { scan_popcounts(c.st, ws->scan, ws->masks, dn, cap, ws->pre, d_out_n); });
-  const uint8_t ep = next_ep(ws);
-  c.tm.run(K_FILTER, [&] { filter_emit(c.st, fa, ws->pre, out, ws->mem[mem_u], ep, grid); });
-  return ep;
-}
-
 struct GfdState {
   Plan plan;
   CandRef cr;
@@ -713,9 +691,22 @@ struct GfdState {
   uint64_t cand_ub[MAXK];
 };
 
-static uint64_t rows_ub(const gfd_graph* g, int32_t L, int dir) {
-  if (L == ANY || L >= g->nvl) return L == ANY ? (uint64_t)g->m : 0;
-  return dir ? g->lab_in_sum[L] : g->lab_out_sum[L];
+static int tiles_grid(uint64_t items) {
+  uint64_t t = (items + BS - 1) / BS;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(t, 512));
+}
+
+// Pull constraints on candidates of u from the current candidate sets of the
+// pattern neighbours `nbrs`: one per pattern edge between u and a neighbour.
+static void add_pull(Ctx& c, GfdState& S, int u, const std::vector<int>& nbrs, CandArgs& ca) {
+  const Plan& p = S.plan;
+  ca.ncons = 0;
+  for (int w : nbrs) {
+    if (p.qe[w][u] != NOEDGE)  // w -> u: v needs an in-neighbour in C(w)
+      ca.cons[ca.ncons++] = PullCons{1, p.qe[w][u], c.ws->mem[w], S.mem_ep[w]};
+    if (p.qe[u][w] != NOEDGE)  // u -> w: v needs an out-neighbour in C(w)
+      ca.cons[ca.ncons++] = PullCons{0, p.qe[u][w], c.ws->mem[w], S.mem_ep[w]};
+  }
 }
 
 // CPI construction (Section IV-B, step 1) for one GFD; all asynchronous.
@@ -725,100 +716,88 @@ static void build_cpi(Ctx& c, GfdState& S) {
   Plan& p = S.plan;
   const int k = p.k;
   epoch_guard(c);
-  for (int u = 0; u < k; u++) { S.cr.cur[u] = 0; S.cand_ub[u] = bucket_size(g, p.qlab[u]); }
-  uint64_t* d_tot = ws->dcnt + 2 * MAXK;  // scratch total
-  auto push_marks = [&](int target, const std::vector<MarkStep>& steps, FilterArgs& fa) {
-    fa.nmarks = 0;
-    for (const MarkStep& m : steps) {
-      const int j = fa.nmarks++;
-      const uint32_t* off = m.dir ? g->dg.in_off : g->dg.out_off;
-      const int32_t* list = S.cr.list(ws, m.src);
-      const uint64_t* dn = S.cr.cnt(ws, m.src);
-      c.tm.run(K_SCAN, [&] {
-        scan_row_lengths(c.st, ws->scan, list, dn, (uint64_t)g->n, off, ws->rowP, d_tot);
-      });
-      const uint8_t ep = next_ep(ws);
-      const uint64_t ub = std::min<uint64_t>(rows_ub(g, p.qlab[m.src], m.dir), (uint64_t)g->m);
-      c.tm.run(K_MARK, [&] {
-        mark_rows(c.st, g->dg, m.dir, list, dn, (uint64_t)g->n, ws->rowP, d_tot, (uint64_t)g->m,
-                  m.elab, p.qlab[target], ws->mark[j], ep, grid_for(ub));
-      });
-      fa.marks[j] = ws->mark[j];
-      fa.mark_ep[j] = ep;
-    }
-  };
-  // top-down, BFS order
+  for (int u = 0; u < k; u++) {
+    S.cr.cur[u] = 0;
+    S.cand_ub[u] = bucket_size(g, p.qlab[u]);
+  }
+  unsigned long long* by = c.stat_bytes;
+  // candidate and CPI-entry counters are atomic output cursors
+  fill_u64(c.st, ws->dcnt, 0, 2 * MAXK);
+  fill_u64(c.st, ws->dcnt + 2 * MAXK + 8, 0, MAXK);
+  // top-down, BFS order: label bucket, degree filter, adjacency to the
+  // candidates of every earlier pattern neighbour
   for (int j = 0; j < k; j++) {
     const int u = p.bfs[j];
-    FilterArgs fa{};
-    fa.g = g->dg;
-    push_marks(u, p.down[u], fa);
-    fa.min_out = p.min_out[u];
-    fa.min_in = p.min_in[u];
-    if (p.qlab[u] == ANY) {
-      fa.list = nullptr;
-      fa.n_host = (uint64_t)g->n;
-    } else {
-      uint64_t bs = bucket_size(g, p.qlab[u]);
-      fa.list = bs ? g->dg.lab_vtx + g->lab_off[p.qlab[u]] : g->dg.lab_vtx;
-      fa.n_host = bs;
-    }
-    fa.d_n = nullptr;
-    fa.cap = fa.n_host;
-    S.mem_ep[u] = run_filter(c, fa, fa.n_host, S.cr.list(ws, u), S.cr.cnt(ws, u), u);
+    CandArgs ca{};
+    ca.g = g->dg;
+    add_pull(c, S, u, p.down[u], ca);
+    ca.min_out = p.min_out[u];
+    ca.min_in = p.min_in[u];
+    const uint64_t bs = S.cand_ub[u];
+    if (p.qlab[u] == ANY) ca.list = nullptr;
+    else ca.list = g->dg.lab_vtx + (bs ? g->lab_off[p.qlab[u]] : 0);
+    ca.d_n = nullptr;
+    ca.n_host = ca.cap = bs;
+    ca.out = S.cr.list(ws, u);
+    ca.d_out_n = S.cr.cnt(ws, u);
+    ca.mem = ws->mem[u];
+    ca.mem_ep = S.mem_ep[u] = next_ep(ws);
+    ca.posmap = (p.up[u].empty() && p.is_parent[u]) ? ws->posmap[u] : nullptr;
+    ca.bytes = by ? by + K_FILTER : nullptr;
+    c.tm.run(K_FILTER, [&] { cand_filter(c.st, ca, tiles_grid(bs)); });
   }
-  // bottom-up, reverse BFS order (dead-end removal)
+  // bottom-up, reverse BFS order: drop dead ends (no neighbour in the
+  // candidate set of a later pattern neighbour)
   for (int j = k - 1; j >= 0; j--) {
     const int u = p.bfs[j];
     if (p.up[u].empty()) continue;
-    FilterArgs fa{};
-    fa.g = g->dg;
-    push_marks(u, p.up[u], fa);
-    fa.min_out = fa.min_in = 0;
-    fa.list = S.cr.list(ws, u);
-    fa.d_n = S.cr.cnt(ws, u);
-    fa.cap = S.cand_ub[u];
+    CandArgs ca{};
+    ca.g = g->dg;
+    add_pull(c, S, u, p.up[u], ca);
+    ca.list = S.cr.list(ws, u);
+    ca.d_n = S.cr.cnt(ws, u);
+    ca.cap = S.cand_ub[u];
     S.cr.cur[u] ^= 1;
-    S.mem_ep[u] = run_filter(c, fa, S.cand_ub[u], S.cr.list(ws, u), S.cr.cnt(ws, u), u);
+    ca.out = S.cr.list(ws, u);
+    ca.d_out_n = S.cr.cnt(ws, u);
+    ca.mem = ws->mem[u];
+    ca.mem_ep = S.mem_ep[u] = next_ep(ws);
+    ca.posmap = p.is_parent[u] ? ws->posmap[u] : nullptr;
+    ca.bytes = by ? by + K_FILTER : nullptr;
+    c.tm.run(K_FILTER, [&] { cand_filter(c.st, ca, tiles_grid(S.cand_ub[u])); });
   }
   // CPI adjacency lists per spanning-tree edge
   for (int u = 0; u < k; u++) {
     if (u == p.root) continue;
     const int q = p.parent[u];
-    AdjArgs a{};
+    CpiArgs a{};
     a.g = g->dg;
     a.dir = p.adj_dir[u];
     a.list = S.cr.list(ws, q);
     a.d_n = S.cr.cnt(ws, q);
     a.cap = S.cand_ub[q];
-    a.P = ws->rowP;
-    a.d_total = d_tot;
-    a.total_cap = (uint64_t)g->m;
     a.prim = p.adj_prim[u];
     a.other = p.adj_other[u];
     a.mem = ws->mem[u];
     a.ep = S.mem_ep[u];
-    a.masks = ws->masks;
-    const uint32_t* off = a.dir ? g->dg.in_off : g->dg.out_off;
-    c.tm.run(K_SCAN, [&] {
-      scan_row_lengths(c.st, ws->scan, a.list, a.d_n, a.cap, off, ws->rowP, d_tot);
-    });
-    const uint64_t ub = std::min<uint64_t>(rows_ub(g, p.qlab[q], a.dir), (uint64_t)g->m);
-    const int grid = grid_for(ub);
-    c.tm.run(K_ADJ, [&] { adj_flags(c.st, a, grid); });
-    uint64_t* d_entries = ws->dcnt + 2 * MAXK + 1;
-    c.tm.run(K_SCAN, [&] {
-      scan_popcounts(c.st, ws->scan, ws->masks, d_tot, (uint64_t)g->m, ws->pre, d_entries);
-    });
-    c.tm.run(K_ADJ, [&] { adj_emit(c.st, a, ws->pre, ws->cpi_ent[u], grid); });
-    c.tm.run(K_ADJ, [&] { adj_offsets(c.st, a, ws->pre, ws->cpi_off[u], grid_for(a.cap + 1)); });
+    a.cpi_beg = ws->cpi_beg[u];
+    a.cpi_len = ws->cpi_len[u];
+    a.cpi_ent = ws->cpi_ent[u];
+    a.d_entries = ws->dcnt + 2 * MAXK + 8 + u;
+    a.bytes = by ? by + K_ADJ : nullptr;
+    c.tm.run(K_ADJ, [&] { cpi_adjacency(c.st, a, tiles_grid(S.cand_ub[q])); });
   }
-  for (int u = 0; u < k; u++)
-    if (p.is_parent[u])
-      c.tm.run(K_OTHER, [&] {
-        pos_map(c.st, S.cr.list(ws, u), S.cr.cnt(ws, u), S.cand_ub[u], ws->posmap[u],
-                grid_for(S.cand_ub[u]));
-      });
+  if (getenv("GFD_DEBUG_CPI")) {  // diagnostics: sizes of the candidate sets and CPI lists
+    uint64_t h[4 * MAXK];
+    HIPCHK(hipMemcpyAsync(h, ws->dcnt, sizeof h, hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    fprintf(stderr, "[gfd] k=%d root=%d", k, p.root);
+    for (int u = 0; u < k; u++)
+      fprintf(stderr, " | u%d L%d bucket %llu cand %llu ent %llu", u, p.qlab[u],
+              (unsigned long long)S.cand_ub[u], (unsigned long long)h[2 * u + S.cr.cur[u]],
+              (unsigned long long)h[2 * MAXK + 8 + u]);
+    fprintf(stderr, "\n");
+  }
 }
 
 static void fill_ext_common(Ctx& c, GfdState& S, ExtArgs& a, int i) {
@@ -882,7 +861,7 @@ static void enumerate_fast(Ctx& c, GfdState& S, uint64_t* ctl, int32_t* vbuf, ui
     LevelView lv = level_view(c, S, i, ctl);
     const int32_t* par = lv.cols + (uint64_t)p.pos[q] * lv.stride;
     c.tm.run(K_SCAN, [&] {
-      scan_sources(c.st, ws->scan, par, lv.d_n, lv.cap, ws->posmap[q], ws->cpi_off[u], ws->beg[i],
+      scan_sources(c.st, ws->scan, par, lv.d_n, lv.cap, ws->posmap[q], ws->cpi_beg[u], ws->cpi_len[u], ws->beg[i],
                    ws->P[i], ctl + CTL_LEVEL_T + i);
     });
     fill_ext_common(c, S, a, i);
@@ -896,12 +875,13 @@ static void enumerate_fast(Ctx& c, GfdState& S, uint64_t* ctl, int32_t* vbuf, ui
     a.a_begin = 0;
     a.a_end = ~0ull;
     const bool last = i == p.k - 1;
+    a.bytes = c.stat_bytes ? c.stat_bytes + (last ? K_LAST : K_EXT) : nullptr;
     if (!last) {
       a.dst_cols = ws->cols[i + 1];
       a.dst_cap = ws->cap;
       a.d_ndst = ctl + CTL_LEVEL_N + i + 1;
     }
-    c.tm.run(last ? K_LAST : K_EXT, [&] { extend(c.st, a, last, 2048); });
+    c.tm.run(last ? K_LAST : K_EXT, [&] { extend(c.st, a, last, 1024); });
   }
 }
 
@@ -960,7 +940,7 @@ struct Chunked {
     LevelView lv = level_view(c, S, i, ctl);
     const int32_t* par = lv.cols + (uint64_t)p.pos[q] * lv.stride;
     c.tm.run(K_SCAN, [&] {
-      scan_sources(c.st, ws->scan, par, lv.d_n, lv.cap, ws->posmap[q], ws->cpi_off[u], ws->beg[i],
+      scan_sources(c.st, ws->scan, par, lv.d_n, lv.cap, ws->posmap[q], ws->cpi_beg[u], ws->cpi_len[u], ws->beg[i],
                    ws->P[i], ctl + CTL_LEVEL_T + i);
     });
     const uint64_t T = rd(CTL_LEVEL_T + i);
@@ -1119,9 +1099,13 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     vsmall = std::max<uint64_t>(vsmall, (uint64_t)K + 1);
     vbig = std::max<uint64_t>(vbig, (uint64_t)K + 64);
     ensure_per_gfd(ws, (size_t)num_specs, vsmall, K);
-    Ctx c{g, ws, (hipStream_t)o.hip_stream, o.semantics == GFD_SEM_INDUCED, K, Timer{}, stats};
-    c.tm.on = stats && (o.flags & GFD_FLAG_TIMING);
+    Ctx c{g, ws, (hipStream_t)o.hip_stream, o.semantics == GFD_SEM_INDUCED, K, Timer{}, stats,
+          stats ? ws->stat_bytes : nullptr};
+    const uint32_t cls_mask = ((uint32_t)o.flags >> 8) & 0xFFu;
+    c.tm.on = stats && ((o.flags & GFD_FLAG_TIMING) || cls_mask);
+    c.tm.mask = cls_mask ? cls_mask : 0xFFu;
     c.tm.st = c.st;
+    if (stats) fill_u64(c.st, (uint64_t*)ws->stat_bytes, 0, 8);
     std::vector<GfdState> S(num_specs);
     for (int32_t i = 0; i < num_specs; i++) make_plan(g, specs[i], c.induced, S[i].plan);
     HIPCHK(hipMemsetAsync(ws->scan.err, 0, 4, c.st));
@@ -1210,6 +1194,9 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       }
     }
     if (stats) {
+      unsigned long long hb[8];
+      HIPCHK(hipMemcpy(hb, ws->stat_bytes, sizeof hb, hipMemcpyDeviceToHost));
+      for (int j = 0; j < 8; j++) stats->class_bytes[j] = hb[j];
       if (c.tm.on) c.tm.collect(stats->class_ms);
       for (int j = 0; j < 8; j++) { stats->class_launches[j] = c.tm.launches[j]; stats->launches += c.tm.launches[j]; }
       stats->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

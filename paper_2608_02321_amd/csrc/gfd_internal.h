@@ -62,6 +62,7 @@ struct ExtArgs {
   const uint64_t* P;       // exclusive prefix of candidate-list lengths [nsrc+1]
   const uint32_t* beg;     // CPI list start per source
   const int32_t* cpi_ent;  // CPI entries (vertex ids)
+  unsigned long long* bytes;  // optional algorithmic-byte counter
   uint64_t a_begin, a_end; // attempt window (a_end clamped to P[nsrc])
   int32_t i;               // position being bound
   int32_t nchk;
@@ -96,68 +97,72 @@ struct ScanWs {
   uint64_t max_tiles;
 };
 
-// Scan sources: for each of n (device count, clamped to cap) list vertices,
-// length of its row in `off`; exclusive prefix -> P[0..n], total -> *d_total.
-void scan_row_lengths(hipStream_t st, ScanWs& ws, const int32_t* list, const uint64_t* d_n,
-                      uint64_t cap, const uint32_t* off, uint64_t* P, uint64_t* d_total);
-// Scan word popcounts (flags compaction): words = ceil(n/64).
-void scan_popcounts(hipStream_t st, ScanWs& ws, const uint64_t* masks, const uint64_t* d_n,
-                    uint64_t cap, uint64_t* pre, uint64_t* d_total);
 // Scan enumeration sources: list length of each partial's parent CPI list.
 void scan_sources(hipStream_t st, ScanWs& ws, const int32_t* par_col, const uint64_t* d_n,
-                  uint64_t cap, const int32_t* pos_map, const uint32_t* cpi_off,
-                  uint32_t* beg, uint64_t* P, uint64_t* d_total);
+                  uint64_t cap, const int32_t* pos_map, const uint32_t* cpi_beg,
+                  const uint32_t* cpi_len, uint32_t* beg, uint64_t* P, uint64_t* d_total);
 
-// Candidate filter (label bucket / list -> flags)
-struct FilterArgs {
+// Decoupled look-back state of one scan launch.
+struct TileScan {
+  uint64_t* state;
+  uint32_t* ticket;
+  uint32_t* err;
+  uint32_t epoch;
+};
+
+// A vertex v passes a pull constraint when some x adjacent to v (out-row if
+// dir == 0, in-row if dir == 1) through an edge of label elab (ANY = any) is a
+// member of another pattern vertex's candidate set (mem[x] == ep).
+struct PullCons {
+  int32_t dir;
+  int32_t elab;
+  const uint8_t* mem;
+  uint32_t ep;
+};
+
+// Candidate filter (Section IV-B: label candidates, degree filter, and the
+// BFS candidate-subgraph / dead-end conditions), compacted in one pass into a
+// set in no fixed order (*d_out_n must be zero at launch).
+struct CandArgs {
   DevGraph g;
-  const int32_t* list;   // nullptr: identity 0..n-1
+  const int32_t* list;   // nullptr: identity 0..n_host-1
   const uint64_t* d_n;   // device count (nullptr: n_host)
   uint64_t n_host, cap;
   int32_t min_out, min_in;
-  int32_t nmarks;
-  const uint8_t* marks[MAXK];
-  uint8_t mark_ep[MAXK];
-  uint64_t* masks;       // [ceil(cap/64)]
+  int32_t ncons;
+  PullCons cons[2 * MAXK];
+  int32_t* out;
+  uint64_t* d_out_n;     // atomic output counter
+  uint8_t* mem;          // mem[v] = mem_ep for kept v
+  uint32_t mem_ep;
+  int32_t* posmap;       // optional: posmap[v] = index of v in out
+  unsigned long long* bytes;  // optional algorithmic-byte counter
 };
-void filter_flags(hipStream_t st, const FilterArgs& a, int grid);
-void filter_emit(hipStream_t st, const FilterArgs& a, const uint64_t* pre, int32_t* out,
-                 uint8_t* mem, uint8_t mem_ep, int grid);
+void cand_filter(hipStream_t st, const CandArgs& a, int grid);
 
-// CPI marking: for rows (dir) of list C (device count), neighbours reached by
-// an edge of label elab (ANY = any) whose vertex label is vlab (ANY = any)
-// get mark[v] = ep.
-void mark_rows(hipStream_t st, const DevGraph& g, int dir, const int32_t* list,
-               const uint64_t* d_n, uint64_t cap, const uint64_t* P, const uint64_t* d_total,
-               uint64_t total_cap, int32_t elab, int32_t vlab, uint8_t* mark, uint8_t ep,
-               int grid);
-
-// CPI adjacency: rows (dir) of C(p); keep entries v with mem[v] == ep, edge
-// label `prim` and the other direction satisfying `other` (probe in the
-// opposite row of the parent vertex).
-struct AdjArgs {
+// CPI adjacency N_u^p(v_p) for spanning-tree edge (p, u): for each v_p in C(p)
+// the neighbours v (row direction dir) with mem[v] == ep, edge label prim and
+// the reverse direction satisfying `other`.  List of the i-th candidate of p:
+// cpi_ent[cpi_beg[i] .. cpi_beg[i] + cpi_len[i]) (*d_entries zero at launch).
+struct CpiArgs {
   DevGraph g;
-  int dir;               // 0: out rows of C(p), 1: in rows
+  int32_t dir;
   const int32_t* list;
   const uint64_t* d_n;
   uint64_t cap;
-  const uint64_t* P;     // row-length prefix over list
-  const uint64_t* d_total;
-  uint64_t total_cap;
-  int32_t prim;          // label constraint on the scanned edge (>= 0 or ANY)
-  int32_t other;         // constraint on the reverse direction (PC_* codes)
+  int32_t prim, other;
   const uint8_t* mem;
-  uint8_t ep;
-  uint64_t* masks;       // [ceil(total_cap/64)]
+  uint32_t ep;
+  uint32_t* cpi_beg;     // [|C(p)|]
+  uint32_t* cpi_len;     // [|C(p)|]
+  int32_t* cpi_ent;
+  uint64_t* d_entries;   // atomic entry counter
+  unsigned long long* bytes;
 };
-void adj_flags(hipStream_t st, const AdjArgs& a, int grid);
-void adj_emit(hipStream_t st, const AdjArgs& a, const uint64_t* pre, int32_t* ent, int grid);
-void adj_offsets(hipStream_t st, const AdjArgs& a, const uint64_t* pre, uint32_t* cpi_off,
-                 int grid);
-void pos_map(hipStream_t st, const int32_t* list, const uint64_t* d_n, uint64_t cap,
-             int32_t* pos, int grid);
+void cpi_adjacency(hipStream_t st, const CpiArgs& a, int grid);
 
-// Enumeration
+// Enumeration: one attempt window over a scanned frontier (P, beg), every
+// attempt of the window mapped to its source by load-balanced search.
 void extend(hipStream_t st, const ExtArgs& a, bool last, int grid);
 void single_vertex(hipStream_t st, const ExtArgs& a, const int32_t* list, const uint64_t* d_n,
                    uint64_t cap, int grid);

@@ -34,22 +34,44 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z;
 }
 
-// Binary search in one sorted adjacency row: label of the edge to `v`, or NOEDGE.
-__device__ __forceinline__ int32_t probe(const uint32_t* __restrict__ off,
-                                         const int32_t* __restrict__ nbr,
-                                         const int32_t* __restrict__ lab, int32_t u, int32_t v) {
-  uint32_t lo = off[u], hi = off[u + 1];
+
+
+// Label of data edge a -> b, or NOEDGE: binary search of the shorter of
+// out-row(a) (for b) and in-row(b) (for a).  Power-law hubs make the two
+// lengths differ by orders of magnitude.
+__device__ __forceinline__ int32_t edge_label(const DevGraph& g, int32_t a, int32_t b,
+                                              unsigned long long& by) {
+  const uint32_t oa = g.out_off[a], oa1 = g.out_off[a + 1];
+  const uint32_t ib = g.in_off[b], ib1 = g.in_off[b + 1];
+  by += 16;
+  const bool use_out = (oa1 - oa) <= (ib1 - ib);
+  const int32_t* nbr = use_out ? g.out_nbr : g.in_nbr;
+  const int32_t* lab = use_out ? g.out_lab : g.in_lab;
+  const int32_t key = use_out ? b : a;
+  uint32_t lo = use_out ? oa : ib, hi = use_out ? oa1 : ib1;
+  const uint32_t end = hi;
   while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (nbr[mid] < v) lo = mid + 1; else hi = mid;
+    const uint32_t mid = (lo + hi) >> 1;
+    by += 4;
+    if (nbr[mid] < key) lo = mid + 1; else hi = mid;
   }
-  return (lo < off[u + 1] && nbr[lo] == v) ? lab[lo] : NOEDGE;
+  if (lo < end && nbr[lo] == key) {
+    by += 8;
+    return lab[lo];
+  }
+  return NOEDGE;
 }
 
 __device__ __forceinline__ bool constraint_ok(int32_t found, int32_t code) {
   if (code == PC_FREE) return true;
   if (code == PC_ABSENT) return found == NOEDGE;
   return found != NOEDGE && (code == ANY || found == code);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
+  return x;
 }
 
 // ---------------------------------------------------------------------------
@@ -61,30 +83,70 @@ __device__ __forceinline__ uint64_t pack_state(uint32_t ep, uint32_t flag, uint6
   return ((uint64_t)(ep & 0xFFFFu) << 48) | ((uint64_t)flag << 46) | (v & VAL_MASK);
 }
 
-struct FnRowLen {
-  const int32_t* list;
-  const uint32_t* off;
-  __device__ uint32_t operator()(uint64_t i) const {
-    int32_t v = list[i];
-    return off[v + 1] - off[v];
-  }
-};
-struct FnPopc {
-  const uint64_t* masks;
-  __device__ uint32_t operator()(uint64_t i) const { return (uint32_t)__popcll(masks[i]); }
-};
 struct FnSrc {
   const int32_t* par;
   const int32_t* pos;
-  const uint32_t* cpi_off;
+  const uint32_t* cpi_beg;
+  const uint32_t* cpi_len;
   uint32_t* beg;
   __device__ uint32_t operator()(uint64_t i) const {
-    int32_t c = pos[par[i]];
-    uint32_t b = cpi_off[c];
-    beg[i] = b;
-    return cpi_off[c + 1] - b;
+    const int32_t c = pos[par[i]];
+    beg[i] = cpi_beg[c];
+    return cpi_len[c];
   }
 };
+
+// Exclusive prefix of tile aggregates in ticket order, computed by the 64
+// lanes of wave 0 together: each round loads the states of the 64 nearest
+// predecessors at once and sums back to the closest one that already holds its
+// inclusive prefix.  Tile t waits only on tiles with smaller tickets, which
+// running blocks own; the wait is bounded and reports an error instead of
+// hanging.  Each state word carries its whole message (epoch, flag, value), so
+// relaxed agent-scope atomics are enough: they are coherent across XCDs
+// without the L2 write-back/invalidate that release/acquire ordering costs.
+__device__ uint64_t tile_prefix_wave(const TileScan& ts, uint64_t t, uint64_t agg) {
+  if (t == 0) {
+    if (lane() == 0)
+      __hip_atomic_store(&ts.state[0], pack_state(ts.epoch, 2, agg), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  if (lane() == 0)
+    __hip_atomic_store(&ts.state[t], pack_state(ts.epoch, 1, agg), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t prefix = 0;
+  int64_t end = (int64_t)t;
+  uint32_t spins = 0;
+  for (;;) {
+    const int64_t j = end - 1 - (int64_t)lane();  // lane 0: nearest predecessor
+    uint32_t fl = 2;
+    uint64_t val = 0;
+    if (j >= 0) {
+      const uint64_t w = __hip_atomic_load(&ts.state[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      fl = ((uint32_t)(w >> 48) == (ts.epoch & 0xFFFFu)) ? ((uint32_t)(w >> 46) & 3u) : 0u;
+      val = w & VAL_MASK;
+    }
+    const uint64_t incl = __ballot(fl == 2);
+    const uint64_t waiting = __ballot(fl == 0);
+    const int first = incl ? __ffsll((long long)incl) - 1 : WAVE;  // closest inclusive
+    const uint64_t need = first >= WAVE - 1 ? ~0ull : ((2ull << first) - 1);
+    if (waiting & need) {
+      if (++spins > (1u << 22)) {
+        if (lane() == 0) atomicOr(ts.err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    prefix += wave_sum((int)lane() <= first ? val : 0ull);
+    if (first < WAVE) break;
+    end -= WAVE;
+  }
+  if (lane() == 0)
+    __hip_atomic_store(&ts.state[t], pack_state(ts.epoch, 2, prefix + agg), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  return prefix;
+}
 
 // Tiles are handed out by an atomic ticket, so a tile only ever waits on
 // tiles already owned by running blocks; the waits are bounded and report an
@@ -139,35 +201,10 @@ __global__ __launch_bounds__(BS) void k_scan(F f, const uint64_t* __restrict__ d
       if ((uint32_t)w < wv) wpre += s_w[w];
       agg += s_w[w];
     }
-    if (threadIdx.x == 0) {
-      uint64_t prefix = 0;
-      if (t == 0) {
-        __hip_atomic_store(&state[0], pack_state(epoch, 2, agg), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_store(&state[t], pack_state(epoch, 1, agg), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        int64_t j = (int64_t)t - 1;
-        uint32_t spins = 0;
-        while (j >= 0) {
-          uint64_t w = __hip_atomic_load(&state[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          uint32_t ep = (uint32_t)(w >> 48), fl = (uint32_t)(w >> 46) & 3u;
-          if (ep != (epoch & 0xFFFFu) || fl == 0) {
-            if (++spins > (1u << 24)) {
-              atomicOr(err, 1u);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          prefix += w & VAL_MASK;
-          if (fl == 2) break;
-          j--;
-        }
-        __hip_atomic_store(&state[t], pack_state(epoch, 2, prefix + agg), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-      s_pre = prefix;
+    if (threadIdx.x < WAVE) {
+      const TileScan ts{state, ticket, err, epoch};
+      const uint64_t pb = tile_prefix_wave(ts, t, agg);
+      if (threadIdx.x == 0) s_pre = pb;
     }
     __syncthreads();
     uint64_t run = s_pre + wpre + x - sum;
@@ -190,7 +227,7 @@ static void launch_scan(hipStream_t st, ScanWs& ws, F f, const uint64_t* d_n, ui
                         int per_word, uint64_t* out, uint64_t* d_total) {
   uint64_t items = per_word ? (cap + 63) / 64 : cap;
   uint64_t tiles = (items + SCAN_TILE - 1) / SCAN_TILE;
-  int grid = (int)(tiles < 1 ? 1 : (tiles > 512 ? 512 : tiles));
+  int grid = (int)(tiles < 1 ? 1 : (tiles > 64 ? 64 : tiles));
   ws.epoch = (ws.epoch + 1) & 0xFFFFu;
   if (ws.epoch == 0) {  // wrapped: stale tile states could alias the new epoch
     fill_u64(st, ws.tile_state, 0, ws.max_tiles);
@@ -200,18 +237,10 @@ static void launch_scan(hipStream_t st, ScanWs& ws, F f, const uint64_t* d_n, ui
                      ws.tile_state, ws.ticket, ws.epoch, ws.err);
 }
 
-void scan_row_lengths(hipStream_t st, ScanWs& ws, const int32_t* list, const uint64_t* d_n,
-                      uint64_t cap, const uint32_t* off, uint64_t* P, uint64_t* d_total) {
-  launch_scan(st, ws, FnRowLen{list, off}, d_n, cap, 0, P, d_total);
-}
-void scan_popcounts(hipStream_t st, ScanWs& ws, const uint64_t* masks, const uint64_t* d_n,
-                    uint64_t cap, uint64_t* pre, uint64_t* d_total) {
-  launch_scan(st, ws, FnPopc{masks}, d_n, cap, 1, pre, d_total);
-}
 void scan_sources(hipStream_t st, ScanWs& ws, const int32_t* par_col, const uint64_t* d_n,
-                  uint64_t cap, const int32_t* pos_map, const uint32_t* cpi_off, uint32_t* beg,
-                  uint64_t* P, uint64_t* d_total) {
-  launch_scan(st, ws, FnSrc{par_col, pos_map, cpi_off, beg}, d_n, cap, 0, P, d_total);
+                  uint64_t cap, const int32_t* pos_map, const uint32_t* cpi_beg,
+                  const uint32_t* cpi_len, uint32_t* beg, uint64_t* P, uint64_t* d_total) {
+  launch_scan(st, ws, FnSrc{par_col, pos_map, cpi_beg, cpi_len, beg}, d_n, cap, 0, P, d_total);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,182 +316,237 @@ void fill_u64(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n) { fill(st, p,
 void fill_u32(hipStream_t st, uint32_t* p, uint32_t v, uint64_t n) { fill(st, p, v, n); }
 
 // ---------------------------------------------------------------------------
-// candidate filter: label bucket (or list) -> flags -> compaction
-// (Section IV-B: label candidates and the degree filter)
+// block-level helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool filter_pass(const FilterArgs& a, int32_t v) {
-  if (a.min_out > 0 && (int64_t)(a.g.out_off[v + 1] - a.g.out_off[v]) < a.min_out) return false;
-  if (a.min_in > 0 && (int64_t)(a.g.in_off[v + 1] - a.g.in_off[v]) < a.min_in) return false;
-  for (int j = 0; j < a.nmarks; j++)
-    if (a.marks[j][v] != a.mark_ep[j]) return false;
-  return true;
-}
-
-__global__ __launch_bounds__(BS) void k_filter_flags(FilterArgs a) {
-  const uint64_t N = a.d_n ? (*a.d_n < a.cap ? *a.d_n : a.cap) : a.n_host;
-  const uint64_t nw = (N + 63) / 64;
-  const uint64_t wid = ((uint64_t)blockIdx.x * BS + threadIdx.x) / WAVE;
-  const uint64_t nwv = (uint64_t)gridDim.x * BS / WAVE;
-  for (uint64_t w = wid; w < nw; w += nwv) {
-    const uint64_t i = w * 64 + lane();
-    bool f = false;
-    if (i < N) f = filter_pass(a, a.list ? a.list[i] : (int32_t)i);
-    const uint64_t m = __ballot(f);
-    if (lane() == 0) a.masks[w] = m;
+// Adds every thread's x into *dst once per block (all threads must call).
+__device__ __forceinline__ void block_add(unsigned long long* dst, unsigned long long x) {
+  __shared__ unsigned long long s_part[BS / WAVE];
+  x = wave_sum(x);
+  __syncthreads();
+  if (lane() == 0) s_part[threadIdx.x / WAVE] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < BS / WAVE; w++) t += s_part[w];
+    if (t) atomicAdd(dst, t);
   }
 }
 
-__global__ __launch_bounds__(BS) void k_filter_emit(FilterArgs a, const uint64_t* __restrict__ pre,
-                                                    int32_t* __restrict__ out, uint8_t* mem,
-                                                    uint8_t mem_ep) {
-  const uint64_t N = a.d_n ? (*a.d_n < a.cap ? *a.d_n : a.cap) : a.n_host;
-  const uint64_t nw = (N + 63) / 64;
-  const uint64_t wid = ((uint64_t)blockIdx.x * BS + threadIdx.x) / WAVE;
-  const uint64_t nwv = (uint64_t)gridDim.x * BS / WAVE;
-  for (uint64_t w = wid; w < nw; w += nwv) {
-    const uint64_t i = w * 64 + lane();
-    const uint64_t m = a.masks[w];
-    if (i < N && ((m >> lane()) & 1ull)) {
-      const int32_t v = a.list ? a.list[i] : (int32_t)i;
-      out[pre[w] + rank_below(m)] = v;
-      if (mem) mem[v] = mem_ep;
+// Block-wide exclusive scan of one u32 per thread; returns the thread's prefix
+// and sets `total`.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total) {
+  __shared__ uint32_t s_w[BS / WAVE];
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    uint32_t y = __shfl_up(inc, (unsigned)d);
+    if (lane() >= (uint32_t)d) inc += y;
+  }
+  __syncthreads();
+  if (lane() == WAVE - 1) s_w[threadIdx.x / WAVE] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  const uint32_t wv = threadIdx.x / WAVE;
+#pragma unroll
+  for (int w = 0; w < BS / WAVE; w++) {
+    if ((uint32_t)w < wv) pre += s_w[w];
+    tot += s_w[w];
+  }
+  total = tot;
+  return pre + inc - x;
+}
+
+// Block-wide walk over the concatenation of BS rows (one row per thread, given
+// as start and length): every round maps BS consecutive entries to their rows
+// with a binary search in LDS, so each thread does a short chain of loads for
+// one entry instead of walking a whole row.  All threads must call it.
+struct FlatShared {
+  uint32_t pre[BS];
+  uint32_t beg[BS];
+};
+template <class F>
+__device__ __forceinline__ void block_flat(FlatShared& sh, uint32_t beg, uint32_t len, F f) {
+  uint32_t total;
+  const uint32_t pre = block_excl_scan(len, total);
+  sh.pre[threadIdx.x] = pre;
+  sh.beg[threadIdx.x] = beg;
+  __syncthreads();
+  for (uint32_t base = 0; base < total; base += BS) {
+    const uint32_t ai = base + threadIdx.x;
+    if (ai < total) {
+      uint32_t lo = 0, hi = BS - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (sh.pre[mid] <= ai) lo = mid; else hi = mid - 1;
+      }
+      f(lo, sh.beg[lo] + (ai - sh.pre[lo]));
     }
   }
-}
-
-void filter_flags(hipStream_t st, const FilterArgs& a, int grid) {
-  hipLaunchKernelGGL(k_filter_flags, dim3(grid), dim3(BS), 0, st, a);
-}
-void filter_emit(hipStream_t st, const FilterArgs& a, const uint64_t* pre, int32_t* out,
-                 uint8_t* mem, uint8_t mem_ep, int grid) {
-  hipLaunchKernelGGL(k_filter_emit, dim3(grid), dim3(BS), 0, st, a, pre, out, mem, mem_ep);
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// CPI marking (Section IV-B: BFS candidate subgraph and dead-end removal)
+// candidate filter (Section IV-B: label candidates, degree filter, BFS
+// candidate subgraph with dead-end removal as pull constraints)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(BS) void k_mark(DevGraph g, int dir, const int32_t* __restrict__ list,
-                                             const uint64_t* __restrict__ d_n, uint64_t cap,
-                                             const uint64_t* __restrict__ P,
-                                             const uint64_t* __restrict__ d_total,
-                                             uint64_t total_cap, int32_t elab, int32_t vlab,
-                                             uint8_t* __restrict__ mark, uint8_t ep) {
-  __shared__ LbsShared sh;
-  const uint64_t N = *d_n < cap ? *d_n : cap;
-  const uint64_t T = *d_total < total_cap ? *d_total : total_cap;
-  const uint32_t* off = dir ? g.in_off : g.out_off;
-  const int32_t* nbr = dir ? g.in_nbr : g.out_nbr;
-  const int32_t* lab = dir ? g.in_lab : g.out_lab;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * BS; t0 < T; t0 += (uint64_t)gridDim.x * BS) {
-    const uint64_t t1 = t0 + BS < T ? t0 + BS : T;
-    uint64_t s, o;
-    if (lbs_tile(P, N, t0, t1, sh, s, o)) {
-      const uint32_t e = off[list[s]] + (uint32_t)o;
-      const int32_t v = nbr[e];
-      if ((elab == ANY || lab[e] == elab) && (vlab == ANY || g.vlab[v] == vlab)) mark[v] = ep;
-    }
-  }
-}
-
-void mark_rows(hipStream_t st, const DevGraph& g, int dir, const int32_t* list,
-               const uint64_t* d_n, uint64_t cap, const uint64_t* P, const uint64_t* d_total,
-               uint64_t total_cap, int32_t elab, int32_t vlab, uint8_t* mark, uint8_t ep,
-               int grid) {
-  hipLaunchKernelGGL(k_mark, dim3(grid), dim3(BS), 0, st, g, dir, list, d_n, cap, P, d_total,
-                     total_cap, elab, vlab, mark, ep);
-}
-
-// ---------------------------------------------------------------------------
-// CPI adjacency N_u^p(v_p) for a spanning-tree edge (p, u)
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ bool adj_keep(const AdjArgs& a, uint64_t s, uint64_t o, int32_t& v) {
+// Output order is not fixed: each tile reserves its slots with one atomic add,
+// so no tile waits on another.  Candidate sets are sets; every later step
+// reads them through the position map or by scanning them whole.
+__global__ __launch_bounds__(BS) void k_cand(CandArgs a) {
+  const uint64_t N = a.d_n ? (*a.d_n < a.cap ? *a.d_n : a.cap) : a.n_host;
+  const uint64_t ntiles = (N + BS - 1) / BS;
+  __shared__ unsigned long long s_base;
+  __shared__ FlatShared fs;
+  __shared__ uint32_t s_found[BS];
+  unsigned long long by = 0;
   const DevGraph& g = a.g;
-  const int32_t vp = a.list[s];
-  const uint32_t* off = a.dir ? g.in_off : g.out_off;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t i = t * BS + threadIdx.x;
+    bool ok = i < N;
+    int32_t v = 0;
+    if (ok) {
+      v = a.list ? a.list[i] : (int32_t)i;
+      by += a.list ? 4 : 0;
+      if (a.min_out > 0) {
+        by += 8;
+        ok = (int32_t)(g.out_off[v + 1] - g.out_off[v]) >= a.min_out;
+      }
+      if (ok && a.min_in > 0) {
+        by += 8;
+        ok = (int32_t)(g.in_off[v + 1] - g.in_off[v]) >= a.min_in;
+      }
+    }
+    for (int c = 0; c < a.ncons; c++) {  // uniform loop: every thread takes part
+      const PullCons cs = a.cons[c];
+      const uint32_t* off = cs.dir ? g.in_off : g.out_off;
+      const int32_t* nbr = cs.dir ? g.in_nbr : g.out_nbr;
+      const int32_t* lab = cs.dir ? g.in_lab : g.out_lab;
+      uint32_t rb = 0, rl = 0;
+      if (ok) {
+        rb = off[v];
+        rl = off[v + 1] - rb;
+        by += 8;
+      }
+      s_found[threadIdx.x] = 0;
+      block_flat(fs, rb, rl, [&](uint32_t item, uint32_t x) {
+        if (s_found[item]) return;  // some neighbour already qualified
+        if (cs.elab != ANY) {
+          by += 4;
+          if (lab[x] != cs.elab) return;
+        }
+        by += 5;
+        if (cs.mem[nbr[x]] == (uint8_t)cs.ep) s_found[item] = 1;
+      });
+      ok = ok && s_found[threadIdx.x] != 0;
+      __syncthreads();
+    }
+    uint32_t total;
+    const uint32_t rank = block_excl_scan(ok ? 1u : 0u, total);
+    if (threadIdx.x == 0)
+      s_base = total ? atomicAdd((unsigned long long*)a.d_out_n, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    if (ok) {
+      const uint64_t idx = s_base + rank;
+      a.out[idx] = v;
+      a.mem[v] = (uint8_t)a.mem_ep;
+      by += 5;
+      if (a.posmap) {
+        a.posmap[v] = (int32_t)idx;
+        by += 4;
+      }
+    }
+    __syncthreads();
+  }
+  if (a.bytes) block_add(a.bytes, by);
+}
+
+void cand_filter(hipStream_t st, const CandArgs& a, int grid) {
+  hipLaunchKernelGGL(k_cand, dim3(grid), dim3(BS), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// CPI adjacency lists for one spanning-tree edge (p, u)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool cpi_keep(const CpiArgs& a, int32_t vp, uint32_t x,
+                                         unsigned long long& by) {
+  const DevGraph& g = a.g;
   const int32_t* nbr = a.dir ? g.in_nbr : g.out_nbr;
   const int32_t* lab = a.dir ? g.in_lab : g.out_lab;
-  const uint32_t e = off[vp] + (uint32_t)o;
-  v = nbr[e];
-  if (a.mem[v] != a.ep) return false;
-  if (a.prim != ANY && lab[e] != a.prim) return false;
+  const int32_t v = nbr[x];
+  by += 5;
+  if (a.mem[v] != (uint8_t)a.ep) return false;
+  if (a.prim != ANY) {
+    by += 4;
+    if (lab[x] != a.prim) return false;
+  }
   if (a.other == PC_FREE) return true;
-  // reverse direction: scanned out-row (vp -> v) => look for v in vp's in-row
-  const int32_t r = a.dir ? probe(g.out_off, g.out_nbr, g.out_lab, vp, v)
-                          : probe(g.in_off, g.in_nbr, g.in_lab, vp, v);
+  // the reverse direction of the scanned edge: dir 0 scanned vp -> v, so the
+  // reverse is v -> vp; dir 1 scanned v -> vp, so the reverse is vp -> v
+  const int32_t r = a.dir ? edge_label(g, vp, v, by) : edge_label(g, v, vp, by);
   return constraint_ok(r, a.other);
 }
 
-__global__ __launch_bounds__(BS) void k_adj_flags(AdjArgs a) {
-  __shared__ LbsShared sh;
+// Two walks over each tile's rows: count the kept entries per row, reserve
+// the tile's entries with one atomic add, then write them.  A list is
+// (begin, length) per parent candidate; lists of one tile are contiguous.  The
+// order of entries inside one list is not fixed; nothing downstream needs it.
+__global__ __launch_bounds__(BS) void k_cpi(CpiArgs a) {
   const uint64_t N = *a.d_n < a.cap ? *a.d_n : a.cap;
-  const uint64_t T = *a.d_total < a.total_cap ? *a.d_total : a.total_cap;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * BS; t0 < T; t0 += (uint64_t)gridDim.x * BS) {
-    const uint64_t t1 = t0 + BS < T ? t0 + BS : T;
-    uint64_t s, o;
-    int32_t v;
-    bool f = false;
-    if (lbs_tile(a.P, N, t0, t1, sh, s, o)) f = adj_keep(a, s, o, v);
-    const uint64_t m = __ballot(f);
-    const uint64_t w = (t0 + threadIdx.x) / 64;
-    if (lane() == 0 && t0 + threadIdx.x < T) a.masks[w] = m;
-  }
-}
-
-__global__ __launch_bounds__(BS) void k_adj_emit(AdjArgs a, const uint64_t* __restrict__ pre,
-                                                 int32_t* __restrict__ ent) {
-  __shared__ LbsShared sh;
-  const uint64_t N = *a.d_n < a.cap ? *a.d_n : a.cap;
-  const uint64_t T = *a.d_total < a.total_cap ? *a.d_total : a.total_cap;
-  const DevGraph& g = a.g;
-  const uint32_t* off = a.dir ? g.in_off : g.out_off;
-  const int32_t* nbr = a.dir ? g.in_nbr : g.out_nbr;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * BS; t0 < T; t0 += (uint64_t)gridDim.x * BS) {
-    const uint64_t t1 = t0 + BS < T ? t0 + BS : T;
-    uint64_t s, o;
-    if (lbs_tile(a.P, N, t0, t1, sh, s, o)) {
-      const uint64_t pos = t0 + threadIdx.x, w = pos / 64;
-      const uint64_t m = a.masks[w];
-      if ((m >> lane()) & 1ull) ent[pre[w] + rank_below(m)] = nbr[off[a.list[s]] + (uint32_t)o];
+  const uint64_t ntiles = (N + BS - 1) / BS;
+  __shared__ unsigned long long s_base;
+  __shared__ FlatShared fs;
+  __shared__ uint32_t s_cnt[BS];
+  __shared__ int32_t s_vp[BS];
+  unsigned long long by = 0, dummy = 0;
+  const uint32_t* off = a.dir ? a.g.in_off : a.g.out_off;
+  const int32_t* nbr = a.dir ? a.g.in_nbr : a.g.out_nbr;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t s = t * BS + threadIdx.x;
+    const bool valid = s < N;
+    int32_t vp = 0;
+    uint32_t b = 0, len = 0;
+    if (valid) {
+      vp = a.list[s];
+      b = off[vp];
+      len = off[vp + 1] - b;
+      by += 12;
     }
+    s_vp[threadIdx.x] = vp;
+    s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    block_flat(fs, b, len, [&](uint32_t item, uint32_t x) {
+      if (cpi_keep(a, s_vp[item], x, by)) atomicAdd(&s_cnt[item], 1u);
+    });
+    const uint32_t cnt = s_cnt[threadIdx.x];
+    uint32_t total;
+    const uint32_t pre = block_excl_scan(cnt, total);
+    if (threadIdx.x == 0)
+      s_base = total ? atomicAdd((unsigned long long*)a.d_entries, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    const uint64_t base = s_base;
+    if (valid) {
+      a.cpi_beg[s] = (uint32_t)(base + pre);
+      a.cpi_len[s] = cnt;
+      by += 8;
+    }
+    s_cnt[threadIdx.x] = pre;  // becomes the running write position of each row
+    __syncthreads();
+    block_flat(fs, b, len, [&](uint32_t item, uint32_t x) {
+      if (cpi_keep(a, s_vp[item], x, dummy)) {
+        const uint32_t at = atomicAdd(&s_cnt[item], 1u);
+        a.cpi_ent[base + at] = nbr[x];
+        by += 4;
+      }
+    });
   }
+  if (a.bytes) block_add(a.bytes, by);
 }
 
-__global__ __launch_bounds__(BS) void k_adj_offsets(AdjArgs a, const uint64_t* __restrict__ pre,
-                                                    uint32_t* __restrict__ cpi_off) {
-  const uint64_t N = *a.d_n < a.cap ? *a.d_n : a.cap;
-  for (uint64_t s = (uint64_t)blockIdx.x * BS + threadIdx.x; s <= N;
-       s += (uint64_t)gridDim.x * BS) {
-    const uint64_t p = a.P[s], w = p / 64, b = p % 64;
-    uint64_t r = pre[w];
-    if (b) r += (uint64_t)__popcll(a.masks[w] & ((1ull << b) - 1));
-    cpi_off[s] = (uint32_t)r;
-  }
-}
-
-__global__ __launch_bounds__(BS) void k_pos_map(const int32_t* __restrict__ list,
-                                                const uint64_t* __restrict__ d_n, uint64_t cap,
-                                                int32_t* __restrict__ pos) {
-  const uint64_t N = *d_n < cap ? *d_n : cap;
-  for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (uint64_t)gridDim.x * BS)
-    pos[list[i]] = (int32_t)i;
-}
-
-void adj_flags(hipStream_t st, const AdjArgs& a, int grid) {
-  hipLaunchKernelGGL(k_adj_flags, dim3(grid), dim3(BS), 0, st, a);
-}
-void adj_emit(hipStream_t st, const AdjArgs& a, const uint64_t* pre, int32_t* ent, int grid) {
-  hipLaunchKernelGGL(k_adj_emit, dim3(grid), dim3(BS), 0, st, a, pre, ent);
-}
-void adj_offsets(hipStream_t st, const AdjArgs& a, const uint64_t* pre, uint32_t* cpi_off,
-                 int grid) {
-  hipLaunchKernelGGL(k_adj_offsets, dim3(grid), dim3(BS), 0, st, a, pre, cpi_off);
-}
-void pos_map(hipStream_t st, const int32_t* list, const uint64_t* d_n, uint64_t cap, int32_t* pos,
-             int grid) {
-  hipLaunchKernelGGL(k_pos_map, dim3(grid), dim3(BS), 0, st, list, d_n, cap, pos);
+void cpi_adjacency(hipStream_t st, const CpiArgs& a, int grid) {
+  hipLaunchKernelGGL(k_cpi, dim3(grid), dim3(BS), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -547,12 +631,6 @@ __device__ __forceinline__ void stage(const ExtArgs& a, bool want, const int32_t
   }
 }
 
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
-#pragma unroll
-  for (int d = WAVE / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
-  return x;
-}
-
 __device__ __forceinline__ void flush_acc(const ExtArgs& a, FinalAcc acc) {
   __shared__ unsigned long long s_acc[4][BS / WAVE];
   acc.match = wave_sum(acc.match);
@@ -581,6 +659,7 @@ __global__ __launch_bounds__(BS) void k_extend(ExtArgs a) {
   __shared__ unsigned long long s_base;
   const uint64_t N = *a.d_nsrc < a.src_cap ? *a.d_nsrc : a.src_cap;
   FinalAcc acc{0, 0, 0, 0};
+  unsigned long long by = 0;
   int32_t thr[MAXK];
   bool thr_on = false;
   if (LAST) {
@@ -601,6 +680,8 @@ __global__ __launch_bounds__(BS) void k_extend(ExtArgs a) {
       bool ok = false;
       if (valid) {
         const int32_t v = a.cpi_ent[a.beg[s] + o];
+        // CPI entry, plus the source's list start, prefix and partial once per source
+        by += 4 + (o == 0 ? 12ull + 4ull * (uint64_t)a.i : 0ull);
         ok = true;
 #pragma unroll
         for (int j = 0; j < MAXK; j++) {
@@ -610,9 +691,9 @@ __global__ __launch_bounds__(BS) void k_extend(ExtArgs a) {
         for (int c = 0; c < a.nchk && ok; c++) {
           const int32_t hw = pick(h, a.chk_pos[c]);
           if (a.chk_fwd[c] != PC_FREE)
-            ok = constraint_ok(probe(a.g.out_off, a.g.out_nbr, a.g.out_lab, hw, v), a.chk_fwd[c]);
+            ok = constraint_ok(edge_label(a.g, hw, v, by), a.chk_fwd[c]);
           if (ok && a.chk_bwd[c] != PC_FREE)
-            ok = constraint_ok(probe(a.g.in_off, a.g.in_nbr, a.g.in_lab, hw, v), a.chk_bwd[c]);
+            ok = constraint_ok(edge_label(a.g, v, hw, by), a.chk_bwd[c]);
         }
       }
       if (!LAST) {
@@ -633,6 +714,7 @@ __global__ __launch_bounds__(BS) void k_extend(ExtArgs a) {
 #pragma unroll
             for (int j = 0; j < MAXK; j++)
               if (j <= a.i) a.dst_cols[(uint64_t)j * a.dst_cap + slot] = h[j];
+            by += 4ull * (uint64_t)(a.i + 1);
           } else {
             atomicOr(a.d_flags, 1u);
           }
@@ -643,6 +725,7 @@ __global__ __launch_bounds__(BS) void k_extend(ExtArgs a) {
         if (ok) {
           FinalAcc one{0, 0, 0, 0};
           want = finalize(a, h, t, one, thr_on, thr);
+          by += 4ull * (uint64_t)(2 * a.nx + 2 * a.ny);
           if (!a.collect_only) {
             acc.match += one.match;
             acc.viol += one.viol;
@@ -655,6 +738,7 @@ __global__ __launch_bounds__(BS) void k_extend(ExtArgs a) {
     }
   }
   if (LAST && !a.collect_only) flush_acc(a, acc);
+  if (a.bytes) block_add(a.bytes, by);
 }
 
 // k == 1: every candidate of the single pattern vertex is a match.
@@ -816,23 +900,37 @@ __global__ __launch_bounds__(BS) void k_select_hist(const int32_t* __restrict__ 
     if (sh[b]) atomicAdd(&hist[b], sh[b]);
 }
 
-__global__ void k_select_pick(int word, int shift, int bits, uint32_t* state, uint32_t* hist) {
-  if (threadIdx.x == 0) {
-    uint32_t r = state[MAXK], cum = 0;
-    const uint32_t nb = 1u << bits;
-    uint32_t d = nb - 1;
-    for (uint32_t b = 0; b < nb; b++) {
-      if (cum + hist[b] >= r) {
-        d = b;
+// Finds the bin holding the remaining rank with a block-wide scan of the
+// histogram (BS threads x RADIX_BINS / BS bins each), then clears it.
+__global__ __launch_bounds__(BS) void k_select_pick(int word, int shift, int bits,
+                                                    uint32_t* state, uint32_t* hist) {
+  constexpr int PER = RADIX_BINS / BS;
+  const uint32_t nb = 1u << bits;
+  const uint32_t r = state[MAXK];  // read before the scan's barriers; one thread rewrites it
+  uint32_t h[PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < PER; j++) {
+    const uint32_t bin = threadIdx.x * PER + j;
+    h[j] = bin < nb ? hist[bin] : 0u;
+    sum += h[j];
+  }
+  uint32_t total;
+  const uint32_t pre = block_excl_scan(sum, total);
+  if (pre < r && r <= pre + sum) {  // exactly one thread
+    uint32_t cum = pre, d = threadIdx.x * PER;
+    for (int j = 0; j < PER; j++) {
+      if (cum + h[j] >= r) {
+        d = threadIdx.x * PER + j;
         break;
       }
-      cum += hist[b];
+      cum += h[j];
     }
     state[MAXK] = r - cum;
     state[word] |= d << shift;
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < RADIX_BINS; b += blockDim.x) hist[b] = 0;
+#pragma unroll
+  for (int j = 0; j < PER; j++) hist[threadIdx.x * PER + j] = 0;
 }
 
 __global__ __launch_bounds__(BS) void k_select_compact(const int32_t* __restrict__ vbuf,

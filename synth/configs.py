@@ -118,10 +118,34 @@ def _gfds_uncached(name: str, g: Graph):
     raise ValueError(name)
 
 
-def gfds(name: str, g: Graph | None = None, use_cache: bool = True):
+FROZEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+def frozen_path(name: str) -> str:
+    return os.path.join(FROZEN_DIR, f"gfds_{name}.json")
+
+
+def freeze(name: str) -> str:
+    """Store the sampled GFD list next to this module (sampling the larger
+    workloads takes minutes); gfds() reads it back when the graph matches."""
+    g = graph(CONFIG_GRAPH[name])
+    gl = gfds(name, g, use_frozen=False)
+    os.makedirs(FROZEN_DIR, exist_ok=True)
+    with open(frozen_path(name), "w") as f:
+        json.dump({"workload": name, "gen_version": GEN_VERSION, "graph_sha256": g.sha256(),
+                   "gfds": gl}, f)
+    return frozen_path(name)
+
+
+def gfds(name: str, g: Graph | None = None, use_cache: bool = True, use_frozen: bool = True):
     """The named config's GFD list (JSON dicts), generated from its seed."""
     if g is None:
         g = graph(CONFIG_GRAPH[name], use_cache=use_cache)
+    if use_frozen and os.path.exists(frozen_path(name)):
+        with open(frozen_path(name)) as f:
+            d = json.load(f)
+        if d.get("gen_version") == GEN_VERSION and d.get("graph_sha256") == g.sha256():
+            return d["gfds"]
     path = os.path.join(cache_dir(), f"gfds_{name}_v{GEN_VERSION}_{g.sha256()[:16]}.json")
     if use_cache and os.path.exists(path):
         with open(path) as f:
@@ -153,3 +177,10 @@ def serving_requests(g: Graph, rate: float = 200.0, duration_s: float = 60.0, se
             P.sample_walk_gfd(rng, view, (3, 8), (1, 3), spec["attr_values"], spec["attr_zipf"],
                               cyc_range=(0, 3)) for _ in range(nq)]})
     return reqs
+
+
+if __name__ == "__main__":
+    import sys
+    if len(sys.argv) >= 3 and sys.argv[1] == "freeze":
+        for nm in sys.argv[2:]:
+            print(freeze(nm))
