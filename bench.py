@@ -4,9 +4,13 @@
 One step = one gfd_validate call over the workload's whole GFD set: candidate
 filtering and CPI construction, core-first enumeration, the fused X -> Y check
 and first-K selection for every GFD, with the graph already resident in HBM.
-Prints one JSON line (rank 0).
 
-    python bench.py [--steps K] [--warmup W] [--workload kg_4m] [--semantics induced]
+Default workload: the 4M-vertex / 20M-edge knowledge-graph-shaped graph with
+256 GFDs of 2-8 vertices, validated in batched form; the same 256 GFDs are
+also timed one at a time (256 sequential single-GFD calls) for the
+batched-vs-one-at-a-time ratio.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload kg_4m_batch256|kg_4m|powerlaw_1m]
 """
 from __future__ import annotations
 
@@ -30,7 +34,8 @@ def log(*a):
 
 def cpu_baseline(g, gfds, semantics, frac, threads):
     """The oracle (naive backtracking) on a bounded sample of the same job:
-    only matches whose first variable lies in the first `frac` of vertex ids."""
+    every GFD, with the first pattern variable restricted to the first `frac`
+    of the vertex ids."""
     from oracle import oracle as O
     og = O.OracleGraph(g)
     hi = max(1, int(g.n * frac))
@@ -42,31 +47,38 @@ def cpu_baseline(g, gfds, semantics, frac, threads):
     dt = time.perf_counter() - t
     return {"value": matches / dt, "unit": "embeddings/s", "cores": threads, "kind": "oracle",
             "sample": f"all {len(gfds)} GFDs, first variable restricted to vertex ids "
-                      f"[0, {hi}) ({frac:.0%} of {g.n}); {matches} matches in {dt:.2f} s",
+                      f"[0, {hi}) ({frac:.1%} of {g.n}); {matches} matches in {dt:.2f} s",
             "gfds_per_s": len(gfds) * frac / dt}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="kg_4m")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="kg_4m_batch256")
+    ap.add_argument("--mode", choices=["batched", "plain"], default=None,
+                    help="default: batched for the 256-GFD workload, plain otherwise")
     ap.add_argument("--semantics", default="induced", choices=["induced", "mono"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frac", type=float, default=0.25)
+    ap.add_argument("--cpu-frac", type=float, default=None)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the one-at-a-time comparison")
     ap.add_argument("--no-timing", action="store_true",
-                    help="do not record per-kernel HIP events during the timed steps")
+                    help="no HIP events at all (no roofline line)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
-                                   "design note, not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU only; how the path would shard "
+                                   "across GPUs is a design note, not an implemented path",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
+    mode = args.mode or ("batched" if args.workload.endswith("batch256") else "plain")
 
     import torch
     torch.cuda.set_device(0)
     import paper_2608_02321_amd as P
+    from paper_2608_02321_amd._binding import KERNEL_CLASSES
     from synth import configs
 
     t = time.perf_counter()
@@ -78,58 +90,83 @@ def main():
     gh = P.load(g, stream=stream)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t
-    flags = 0 if args.no_timing else P.GFD_FLAG_TIMING
+    batched = mode == "batched"
 
-    def step():
-        return P.validate(gh, gfds, K=K_REPORT, semantics=args.semantics, stream=stream,
-                          flags=flags, stats=True)
+    def call(specs, flags=0, stats=True):
+        return P.validate(gh, specs, K=K_REPORT, semantics=args.semantics, stream=stream,
+                          flags=flags, stats=stats, batched=batched)
 
-    for _ in range(args.warmup):
-        step()
+    # warm-up; the last warm-up step records every kernel class to find the dominant one
+    for w in range(args.warmup):
+        res, st = call(gfds, flags=0 if args.no_timing or w < args.warmup - 1 else P.GFD_FLAG_TIMING)
+    torch.cuda.synchronize()
+    dom = None
+    if not args.no_timing:
+        dom = max(range(8), key=lambda c: st["class_ms"][KERNEL_CLASSES[c]])
+        log("warm-up per-class ms: " + ", ".join(f"{k} {v:.2f}" for k, v in st["class_ms"].items()))
+    flags = 0 if dom is None else (1 << (8 + dom))  # HIP events around the dominant class only
+    agg_ms = agg_bytes = agg_launch = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    agg = None
     for _ in range(args.steps):
-        res, st = step()
-        if agg is None:
-            agg = {k: dict(v) if isinstance(v, dict) else v for k, v in st.items()}
-        else:
-            for cls in st["class_ms"]:
-                agg["class_ms"][cls] += st["class_ms"][cls]
-                agg["class_launches"][cls] += st["class_launches"][cls]
-                agg["class_bytes"][cls] += st["class_bytes"][cls]
+        res, st = call(gfds, flags=flags)
+        if dom is not None:
+            name = KERNEL_CLASSES[dom]
+            agg_ms += st["class_ms"][name]
+            agg_bytes += st["class_bytes"][name]
+            agg_launch += st["class_launches"][name]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
     matches = sum(r["match_count"] for r in res)
     value = matches * args.steps / elapsed
     gfds_per_s = len(gfds) * args.steps / elapsed
-    log(f"step {ms_per_step:.3f} ms, {matches} matches, {value:.4g} embeddings/s, "
-        f"{gfds_per_s:.1f} GFDs/s, launches/step {st['launches']}")
-    for cls in agg["class_ms"]:
-        log(f"  {cls:12s} launches {agg['class_launches'][cls] // args.steps:5d} "
-            f"ms/step {agg['class_ms'][cls] / args.steps:8.4f}")
+    log(f"{mode}: step {ms_per_step:.3f} ms, {matches} matches, {value:.4g} embeddings/s, "
+        f"{gfds_per_s:.1f} GFDs/s, launches/step {st['launches']}, "
+        f"bounded re-runs {st['chunked_gfds']}")
 
     roofline = None
-    if not args.no_timing:
-        dom = max(agg["class_ms"], key=lambda c: agg["class_ms"][c])
-        ms = agg["class_ms"][dom] / agg["class_launches"][dom] if agg["class_launches"][dom] else 0
-        byts = agg["class_bytes"][dom] / max(1, agg["class_launches"][dom])
-        ach = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        roofline = {"bound": "hbm", "kernel_class": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+    if dom is not None and agg_launch:
+        name = KERNEL_CLASSES[dom]
+        avg_ms = agg_ms / agg_launch
+        per_launch = agg_bytes / agg_launch
+        ach = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        roofline = {"bound": "hbm", "kernel_class": name, "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                    "avg_launch_ms": ms, "alg_bytes_per_launch": byts}
+                    "avg_launch_ms": avg_ms, "alg_bytes_per_launch": per_launch,
+                    "launches_per_step": agg_launch / args.steps}
+
+    compare = None
+    if batched and not args.no_compare:
+        # the same GFDs, one gfd_validate call each (one-at-a-time)
+        for d in gfds[:8]:
+            P.validate(gh, [d], K=K_REPORT, semantics=args.semantics, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        seq = [P.validate(gh, [d], K=K_REPORT, semantics=args.semantics, stream=stream)[0]
+               for d in gfds]
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        assert seq == res, "one-at-a-time results differ from the batched call"
+        compare = {"one_at_a_time_s": dt1, "one_at_a_time_gfds_per_s": len(gfds) / dt1,
+                   "one_at_a_time_embeddings_per_s": matches / dt1,
+                   "batched_over_one_at_a_time": (len(gfds) * args.steps / elapsed) / (len(gfds) / dt1)}
+        log(f"one-at-a-time: {dt1 * 1e3:.1f} ms for {len(gfds)} calls; ratio "
+            f"{compare['batched_over_one_at_a_time']:.2f}x")
 
     out = {"metric": METRIC, "value": value, "unit": "embeddings/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
            "data": "synthetic", "gfds_per_s": gfds_per_s, "matches_per_step": matches,
-           "config": {"workload": args.workload, "n": g.n, "m": g.m, "gfds": len(gfds),
-                      "semantics": args.semantics, "K": K_REPORT, "parallelism": "single_gpu"},
-           "load_s": load_s, "roofline": roofline}
+           "config": {"workload": args.workload, "mode": mode, "n": g.n, "m": g.m,
+                      "gfds": len(gfds), "semantics": args.semantics, "K": K_REPORT,
+                      "parallelism": "single_gpu"},
+           "load_s": load_s, "roofline": roofline, "compare": compare}
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
-        out["cpu_baseline"] = cpu_baseline(g, gfds, args.semantics, args.cpu_frac, threads)
+        frac = args.cpu_frac if args.cpu_frac is not None else (
+            0.02 if args.workload.endswith("batch256") else 0.25)
+        out["cpu_baseline"] = cpu_baseline(g, gfds, args.semantics, frac, threads)
     gh.free()
     print(json.dumps(out), flush=True)
 

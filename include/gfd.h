@@ -112,7 +112,8 @@ typedef struct {
   int32_t semantics;        /* GFD_SEM_INDUCED or GFD_SEM_MONO */
   int64_t mem_budget_bytes; /* device bytes for frontiers and buffers; 0 = default */
   void* hip_stream;         /* hipStream_t to run on; NULL = the null stream */
-  int32_t batched;          /* reserved, must be 0 */
+  int32_t batched;          /* 0: one GFD after another; 1: GFDs run together in
+                               batches, one launch per kernel per phase of a batch */
   int32_t flags;            /* GFD_FLAG_* bits */
   int64_t frontier_cap;     /* testing: max partial matches per level (0 = from budget) */
   int64_t violation_cap;    /* testing: violation staging capacity in tuples (0 = default) */
@@ -132,14 +133,13 @@ typedef struct {
   uint64_t partials;          /* partial matches written over all levels */
   uint64_t cpi_candidates;    /* sum of final candidate-set sizes */
   uint64_t cpi_entries;       /* sum of CPI adjacency entries */
-  /* per kernel class: [0] candidate filter, [1] CPI marking, [2] CPI adjacency,
-   * [3] enumeration (inner levels), [4] enumeration + literal check (last level),
-   * [5] scans, [6] top-K selection, [7] other */
+  /* per kernel class: [0] candidate compaction, [1] candidate pull constraints,
+   * [2] CPI adjacency, [3] enumeration (inner levels), [4] enumeration + literal
+   * check (last level), [5] scans, [6] top-K selection, [7] other */
   int32_t class_launches[8];
   double class_ms[8];         /* summed HIP event time (GFD_FLAG_TIMING) */
-  uint64_t class_bytes[8];    /* algorithmic bytes of the fast path's kernels in that
-                                class (bytes each item must touch, counted on the
-                                device); chunked re-runs are not counted */
+  uint64_t class_bytes[8];    /* algorithmic bytes of that class (bytes each item
+                                must touch, counted on the device) */
 } gfd_stats;
 
 /* Load a graph given as out-CSR on the host.  Inputs are read and copied: the

@@ -24,7 +24,7 @@ GFD_SEM_INDUCED, GFD_SEM_MONO = 0, 1
 GFD_FLAG_FORCE_CHUNKED, GFD_FLAG_TIMING = 1, 2
 STATUS_NAMES = {0: "GFD_OK", -1: "GFD_EINVAL", -2: "GFD_ENOMEM", -3: "GFD_EDEVICE",
                 -4: "GFD_EUNSUPPORTED", -5: "GFD_EOVERFLOW"}
-KERNEL_CLASSES = ("filter", "mark", "adjacency", "extend", "extend_last", "scan", "topk", "other")
+KERNEL_CLASSES = ("filter", "pull", "cpi", "extend", "extend_last", "scan", "topk", "other")
 
 
 class GfdError(RuntimeError):
@@ -234,7 +234,7 @@ def make_spec(gfd: dict) -> gfd_spec:
 
 def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
              mem_budget_bytes: int = 0, stream=None, flags: int = 0, frontier_cap: int = 0,
-             violation_cap: int = 0, stats: bool = False):
+             violation_cap: int = 0, stats: bool = False, batched: bool = False):
     """gfd_validate(_ex): one result dict per GFD (plus a stats dict if asked)."""
     n = len(gfds)
     specs = (gfd_spec * max(n, 1))(*[make_spec(d) for d in gfds])
@@ -245,7 +245,8 @@ def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced"
         bufs.append(b)
         results[i].violations = b.ctypes.data_as(C.POINTER(C.c_int32))
     opts = gfd_validate_opts(K, GFD_SEM_INDUCED if semantics == "induced" else GFD_SEM_MONO,
-                             int(mem_budget_bytes), _stream_handle(stream), 0, int(flags),
+                             int(mem_budget_bytes), _stream_handle(stream), int(bool(batched)),
+                             int(flags),
                              int(frontier_cap), int(violation_cap))
     st = gfd_stats()
     rc = lib.gfd_validate_ex(graph.handle, specs, n, C.byref(opts), results,

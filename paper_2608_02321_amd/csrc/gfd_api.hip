@@ -75,71 +75,46 @@ static void dfree(void* p) {
 }
 
 // ---------------------------------------------------------------------------
-// workspace: device scratch for one validate call at a time
+// workspace: device memory for one validate call at a time
 // ---------------------------------------------------------------------------
 
 constexpr int CTL_WORDS = 64;
-// control block layout (uint64 words)
+// per-job control block layout (uint64 words)
 enum {
   CTL_MATCH = 0, CTL_VIOL = 1, CTL_MFP = 2, CTL_VFP = 3, CTL_VCOUNT = 4, CTL_FLAGS = 5,
   CTL_NEEDSEL = 6, CTL_THRVALID = 7, CTL_LEVEL_N = 8 /* +i */, CTL_LEVEL_T = 16 /* +i */,
-  CTL_ENTRIES = 24 /* +u */, CTL_OUTCOUNT = 32, CTL_THR = 40 /* 4 words = 8 int32 */
+  CTL_TOTAL = 24, CTL_OUTCOUNT = 25, CTL_TICKET = 26, CTL_CAND = 32 /* +2u+b */,
+  CTL_THR = 48 /* 4 words = 8 int32 */
 };
 
 struct Workspace {
-  int64_t n = 0, m = 0;
-  uint64_t cap = 0;          // frontier partials per level in use
-  uint64_t alloc_cap = 0;    // frontier partials per level allocated
-  uint64_t pcap = 0;         // prefix/beg entries per level (>= n, >= cap)
-  int64_t bytes = 0;
-  int32_t* cand[2 * MAXK] = {};
-  uint8_t* mem[MAXK] = {};
-  uint8_t* mark[MAXK] = {};
-  int32_t* posmap[MAXK] = {};
-  uint32_t* cpi_beg[MAXK] = {};
-  uint32_t* cpi_len[MAXK] = {};
-  int32_t* cpi_ent[MAXK] = {};
-  uint64_t* rowP = nullptr;   // [n+1]
-  uint64_t* masks = nullptr;  // [max(m, n)/64 + 2]
-  uint64_t* pre = nullptr;    // [max(m, n)/64 + 2]
-  int32_t* cols[MAXK] = {};   // level i columns (i >= 2)
-  uint64_t* P[MAXK] = {};
-  uint32_t* beg[MAXK] = {};
-  uint64_t* dcnt = nullptr;   // [2*MAXK] candidate counts, + scratch totals
-  unsigned long long* stat_bytes = nullptr;  // [8] algorithmic bytes per kernel class
-  ScanWs scan{};
-  // chunked-path violation staging and selection
+  uint8_t* arena = nullptr;         // per-job regions of the current batch
+  size_t arena_bytes = 0;
+  int32_t* cpi_arena = nullptr;     // CPI entries of every job of a batch
+  uint64_t cpi_cap = 0;
+  uint8_t* jobrec = nullptr;        // device job records
+  size_t jobrec_bytes = 0;
+  uint8_t* hjobrec = nullptr;       // pinned staging for the records
+  size_t hjobrec_bytes = 0;
+  uint64_t* hctl = nullptr;         // pinned mirror of control blocks
+  size_t hctl_words = 0;
+  unsigned long long* misc = nullptr;  // [0] CPI cursor, [8..15] bytes per class
+  uint32_t* err = nullptr;
+  uint32_t epoch = 0;
+  // bounded path: per-level prefixes, violation staging, selection
+  uint8_t* chunk = nullptr;
+  size_t chunk_bytes = 0;
   int32_t* vbig = nullptr;
   uint64_t vbig_cap = 0;
   uint32_t* sel_state = nullptr;
   uint32_t* sel_hist = nullptr;
   int32_t* sel_out = nullptr;
-  // per-GFD blocks for the fast path (grown on demand)
-  uint64_t* ctl = nullptr;
-  int32_t* vsmall = nullptr;
-  int32_t* res = nullptr;
-  size_t ngfd_cap = 0;
-  uint64_t vsmall_cap = 0;  // tuples per GFD
-  int res_K = 0;
-  uint64_t* hctl = nullptr; // pinned mirror of ctl
-  uint8_t ep = 0;           // u8 epoch counter for mem/mark arrays
   int64_t budget = 0;
 
   ~Workspace() {
-    for (auto p : cand) dfree(p);
-    for (auto p : mem) dfree(p);
-    for (auto p : mark) dfree(p);
-    for (auto p : posmap) dfree(p);
-    for (auto p : cpi_beg) dfree(p);
-    for (auto p : cpi_len) dfree(p);
-    for (auto p : cpi_ent) dfree(p);
-    for (auto p : cols) dfree(p);
-    for (auto p : P) dfree(p);
-    for (auto p : beg) dfree(p);
-    dfree(rowP); dfree(masks); dfree(pre); dfree(dcnt); dfree(stat_bytes);
-    dfree(scan.tile_state); dfree(scan.ticket); dfree(scan.err);
+    dfree(arena); dfree(cpi_arena); dfree(jobrec); dfree(misc); dfree(err); dfree(chunk);
     dfree(vbig); dfree(sel_state); dfree(sel_hist); dfree(sel_out);
-    dfree(ctl); dfree(vsmall); dfree(res);
+    if (hjobrec) (void)hipHostFree(hjobrec);
     if (hctl) (void)hipHostFree(hctl);
   }
 };
@@ -520,8 +495,11 @@ static void make_plan(const gfd_graph* g, const gfd_spec& s, bool induced, Plan&
 }
 
 // ---------------------------------------------------------------------------
-// driver
+// driver: GFDs run in batches of jobs; every phase of a batch is one launch
+// per kernel, whatever the number of jobs in it
 // ---------------------------------------------------------------------------
+
+enum { K_FILTER = 0, K_PULL = 1, K_CPI = 2, K_EXT = 3, K_LAST = 4, K_SCAN = 5, K_TOPK = 6, K_OTHER = 7 };
 
 struct Timer {
   bool on = false;
@@ -562,11 +540,120 @@ struct Timer {
     for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
-enum { K_FILTER = 0, K_MARK = 1, K_ADJ = 2, K_EXT = 3, K_LAST = 4, K_SCAN = 5, K_TOPK = 6, K_OTHER = 7 };
 
-static int grid_for(uint64_t items) {
-  uint64_t b = (items + BS - 1) / BS;
-  return (int)std::max<uint64_t>(1, std::min<uint64_t>(b, 2048));
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Host-side capacities of one job.
+struct JobCaps {
+  uint64_t cap_u[MAXK];
+  uint64_t cap_f;   // frontier partial matches per level
+  uint64_t pcap;    // largest scan (items) + 1
+  uint64_t tiles;   // scan tile states
+  uint64_t hits, begs, vcap;
+  size_t bytes;     // region size (excluding control block, tile states, results)
+};
+
+struct JobMem {
+  int32_t* pos[MAXK];
+  uint32_t* bits[MAXK][2];
+  int32_t* cand[MAXK][2];
+  uint32_t* hits;
+  uint64_t* P;
+  uint32_t* cpi_beg[MAXK];
+  uint32_t* cpi_len[MAXK];
+  uint32_t* cpi_cur[MAXK];
+  int32_t* cols[MAXK];
+  uint32_t* begs;
+  int32_t* vbuf;
+  uint64_t* ctl;
+  uint64_t* tstate;
+  int32_t* res;
+};
+
+struct Job {
+  int spec;       // index of the GFD in the call
+  Plan plan;
+  JobCaps caps;
+  JobMem mem;
+  int cur[MAXK];  // which candidate buffer holds C(u) at the current step
+};
+
+static int pattern_edges_between(const Plan& p, int u, const std::vector<int>& nbrs) {
+  int c = 0;
+  for (int w : nbrs) c += (p.qe[w][u] != NOEDGE) + (p.qe[u][w] != NOEDGE);
+  return c;
+}
+
+static uint64_t per_slot_bytes(int k) {
+  uint64_t b = 12;  // prefix + list start of one source
+  for (int i = 2; i < k; i++) b += 4ull * i;
+  return b;
+}
+
+static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t vcap, JobCaps& c) {
+  const int k = p.k;
+  uint64_t items = 1, hits = 1;
+  for (int u = 0; u < k; u++) {
+    c.cap_u[u] = bucket_size(g, p.qlab[u]);
+    hits = std::max(hits, c.cap_u[u]);
+    const uint64_t nc = (uint64_t)std::max(pattern_edges_between(p, u, p.down[u]),
+                                           pattern_edges_between(p, u, p.up[u]));
+    items = std::max(items, c.cap_u[u] * std::max<uint64_t>(nc, 1));
+  }
+  c.cap_f = k > 2 ? cap_f : 1;
+  items = std::max(items, c.cap_f);
+  c.pcap = items + 1;
+  c.tiles = items / SCAN_TILE + 2;
+  c.hits = hits;
+  c.begs = std::max(c.cap_u[p.root], c.cap_f);
+  c.vcap = vcap;
+  size_t b = 0;
+  b += align_up(sizeof(int32_t) * (size_t)g->n) * k;                   // positions
+  b += 2 * align_up(4 * ((size_t)g->n / 32 + 1)) * k;                  // membership bitmaps
+  for (int u = 0; u < k; u++) b += 2 * align_up(4 * c.cap_u[u]);       // candidate lists
+  b += align_up(4 * c.hits);
+  b += align_up(8 * c.pcap);
+  for (int u = 0; u < k; u++)
+    if (u != p.root) b += 3 * align_up(4 * c.cap_u[p.parent[u]]);    // CPI list heads
+  for (int i = 2; i < k; i++) b += align_up(4ull * i * c.cap_f);      // frontier columns
+  b += align_up(4 * c.begs);
+  b += align_up(4 * c.vcap * k);
+  c.bytes = b;
+}
+
+static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const JobCaps& c,
+                       JobMem& m) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    uint8_t* q = base + off;
+    off += align_up(bytes);
+    return q;
+  };
+  const int k = p.k;
+  std::memset(&m.pos, 0, sizeof m.pos);
+  for (int u = 0; u < k; u++) m.pos[u] = (int32_t*)take(sizeof(int32_t) * (size_t)g->n);
+  for (int u = 0; u < k; u++) {
+    m.bits[u][0] = (uint32_t*)take(4 * ((size_t)g->n / 32 + 1));
+    m.bits[u][1] = (uint32_t*)take(4 * ((size_t)g->n / 32 + 1));
+  }
+  for (int u = 0; u < k; u++) {
+    m.cand[u][0] = (int32_t*)take(4 * c.cap_u[u]);
+    m.cand[u][1] = (int32_t*)take(4 * c.cap_u[u]);
+  }
+  m.hits = (uint32_t*)take(4 * c.hits);
+  m.P = (uint64_t*)take(8 * c.pcap);
+  for (int u = 0; u < k; u++) {
+    m.cpi_beg[u] = m.cpi_len[u] = m.cpi_cur[u] = nullptr;
+    if (u == p.root) continue;
+    const uint64_t cp = c.cap_u[p.parent[u]];
+    m.cpi_beg[u] = (uint32_t*)take(4 * cp);
+    m.cpi_len[u] = (uint32_t*)take(4 * cp);
+    m.cpi_cur[u] = (uint32_t*)take(4 * cp);
+  }
+  for (int i = 0; i < MAXK; i++) m.cols[i] = nullptr;
+  for (int i = 2; i < k; i++) m.cols[i] = (int32_t*)take(4ull * i * c.cap_f);
+  m.begs = (uint32_t*)take(4 * c.begs);
+  m.vbuf = (int32_t*)take(4 * c.vcap * k);
 }
 
 struct Ctx {
@@ -580,309 +667,438 @@ struct Ctx {
   unsigned long long* stat_bytes;  // device [8] per kernel class, or nullptr
 };
 
-static uint8_t next_ep(Workspace* ws) {
-  if (ws->ep == 255) ws->ep = 0;  // callers reset per GFD before this can happen
-  return ++ws->ep;
+static uint32_t next_epoch(Ctx& c) {
+  c.ws->epoch = (c.ws->epoch + 1) & 0xFFFFu;
+  if (c.ws->epoch == 0) c.ws->epoch = 1;
+  return c.ws->epoch;
 }
 
-// Clears the epoch-tagged byte arrays when the epoch counter is close to wrapping.
-static void epoch_guard(Ctx& c) {
+static CandSet cand_set(const Job& J, int u) {
+  return CandSet{J.mem.cand[u][J.cur[u]], J.mem.ctl + CTL_CAND + 2 * u + J.cur[u], J.mem.pos[u],
+                 J.mem.bits[u][J.cur[u]]};
+}
+
+static JobScan job_scan_rec(Ctx& c, const Job& J, uint64_t* d_total, uint32_t epoch) {
+  return JobScan{J.mem.P, d_total, J.mem.tstate, (uint32_t*)(J.mem.ctl + CTL_TICKET), c.ws->err,
+                 epoch};
+}
+
+static void add_pulls(const Job& J, int u, const std::vector<int>& nbrs, FilterJob& f) {
+  const Plan& p = J.plan;
+  f.ncons = 0;
+  for (int w : nbrs) {
+    if (p.qe[w][u] != NOEDGE)  // w -> u: v needs an in-neighbour in C(w)
+      f.cons[f.ncons++] = PullC{1, p.qe[w][u], cand_set(J, w)};
+    if (p.qe[u][w] != NOEDGE)  // u -> w: v needs an out-neighbour in C(w)
+      f.cons[f.ncons++] = PullC{0, p.qe[u][w], cand_set(J, w)};
+  }
+}
+
+static int gx_for(uint64_t items, int njobs, int cap = 256) {
+  const uint64_t want = (items + BS - 1) / BS;
+  const int per_job = std::max(8, std::min(cap, 4096 / std::max(1, njobs)));
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)per_job));
+}
+static int gx_scan(uint64_t items) {
+  const uint64_t t = (items + SCAN_TILE - 1) / SCAN_TILE;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(t, 64));
+}
+
+static uint64_t rows_ub(const gfd_graph* g, int32_t L, int dir) {
+  if (L == ANY) return (uint64_t)g->m;
+  if (L >= g->nvl) return 0;
+  return dir ? g->lab_in_sum[L] : g->lab_out_sum[L];
+}
+
+// Job records of every step of a batch, staged host side and uploaded once.
+struct Recs {
+  std::vector<uint8_t> blob;
+  template <class T>
+  size_t add(const std::vector<T>& v) {
+    size_t off = align_up(blob.size());
+    blob.resize(off + sizeof(T) * v.size());
+    std::memcpy(blob.data() + off, v.data(), sizeof(T) * v.size());
+    return off;
+  }
+};
+
+static void ensure_recs(Workspace* ws, size_t bytes) {
+  if (ws->jobrec_bytes < bytes) {
+    dfree(ws->jobrec);
+    ws->jobrec = nullptr;
+    ws->jobrec_bytes = 0;
+    ws->jobrec = dalloc<uint8_t>(bytes);
+    ws->jobrec_bytes = bytes;
+  }
+  if (ws->hjobrec_bytes < bytes) {
+    if (ws->hjobrec) (void)hipHostFree(ws->hjobrec);
+    ws->hjobrec = nullptr;
+    ws->hjobrec_bytes = 0;
+    HIPCHK(hipHostMalloc((void**)&ws->hjobrec, bytes, hipHostMallocDefault));
+    ws->hjobrec_bytes = bytes;
+  }
+}
+
+// Phase plan of a batch: which kernels run, on which record arrays.
+struct Launch {
+  int kind;     // 0 filter, 1 cpi, 2 ext, 3 single, 4 topk
+  size_t off;   // record array offset
+  int njobs;
+  int gx_scan, gx_work, gx_item, gx_clear;
+  bool scan, last_any, inner_any;
+};
+
+// Builds every record of the CPI construction and the fast enumeration of
+// `jobs` (Section IV-B steps 1 and 2) into `R` and the launch list `L`.
+static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Launch>& L,
+                       bool fast_enum) {
+  const gfd_graph* g = c.g;
+  const int nj = (int)jobs.size();
+  int maxk = 0;
+  for (auto& J : jobs) {
+    maxk = std::max(maxk, J.plan.k);
+    for (int u = 0; u < MAXK; u++) J.cur[u] = 0;
+  }
+  unsigned long long* by = c.stat_bytes;
+  // top-down, BFS order
+  for (int j = 0; j < maxk; j++) {
+    std::vector<FilterJob> F(nj);
+    uint64_t items = 1, pull_ub = 1, pairs = 1;
+    bool any_cons = false;
+    const uint32_t ep = next_epoch(c);
+    for (int x = 0; x < nj; x++) {
+      Job& J = jobs[x];
+      const Plan& p = J.plan;
+      FilterJob& f = F[x];
+      f = FilterJob{};
+      if (j >= p.k) continue;
+      const int u = p.bfs[j];
+      f.active = 1;
+      add_pulls(J, u, p.down[u], f);
+      f.min_out = p.min_out[u];
+      f.min_in = p.min_in[u];
+      const uint64_t bs = J.caps.cap_u[u];
+      f.list = p.qlab[u] == ANY ? nullptr : g->dg.lab_vtx + (bs ? g->lab_off[p.qlab[u]] : 0);
+      f.d_n = nullptr;
+      f.n_host = f.cap = bs;
+      f.hits = J.mem.hits;
+      f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
+      J.cur[u] = 0;
+      f.out = J.mem.cand[u][0];
+      f.d_out_n = J.mem.ctl + CTL_CAND + 2 * u;
+      f.pos = J.mem.pos[u];
+      f.bits = J.mem.bits[u][0];
+      f.nwords = (uint64_t)g->n / 32 + 1;
+      f.bytes = by ? by + K_FILTER : nullptr;
+      items = std::max(items, bs);
+      pairs = std::max(pairs, bs * (uint64_t)std::max(f.ncons, 1));
+      for (int q = 0; q < f.ncons; q++) pull_ub = std::max(pull_ub, rows_ub(g, p.qlab[u], f.cons[q].dir));
+      any_cons |= f.ncons > 0;
+    }
+    L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), gx_for(pull_ub, nj), gx_for(items, nj),
+                       gx_for((uint64_t)g->n / 32 + 1, nj, 64), any_cons, false, false});
+  }
+  // bottom-up, reverse BFS order: drop dead ends
+  for (int j = maxk - 1; j >= 0; j--) {
+    std::vector<FilterJob> F(nj);
+    uint64_t items = 1, pull_ub = 1, pairs = 1;
+    bool any = false;
+    const uint32_t ep = next_epoch(c);
+    for (int x = 0; x < nj; x++) {
+      Job& J = jobs[x];
+      const Plan& p = J.plan;
+      FilterJob& f = F[x];
+      f = FilterJob{};
+      if (j >= p.k) continue;
+      const int u = p.bfs[j];
+      if (p.up[u].empty()) continue;
+      f.active = 1;
+      add_pulls(J, u, p.up[u], f);
+      const CandSet cur = cand_set(J, u);
+      f.list = cur.list;
+      f.d_n = cur.cnt;
+      f.cap = J.caps.cap_u[u];
+      f.hits = J.mem.hits;
+      f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
+      J.cur[u] ^= 1;
+      f.out = J.mem.cand[u][J.cur[u]];
+      f.d_out_n = J.mem.ctl + CTL_CAND + 2 * u + J.cur[u];
+      f.pos = J.mem.pos[u];
+      f.bits = J.mem.bits[u][J.cur[u]];
+      f.nwords = (uint64_t)g->n / 32 + 1;
+      f.bytes = by ? by + K_FILTER : nullptr;
+      items = std::max(items, f.cap);
+      pairs = std::max(pairs, f.cap * (uint64_t)f.ncons);
+      for (int q = 0; q < f.ncons; q++) pull_ub = std::max(pull_ub, rows_ub(g, p.qlab[u], f.cons[q].dir));
+      any = true;
+    }
+    if (any)
+      L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), gx_for(pull_ub, nj), gx_for(items, nj),
+                         gx_for((uint64_t)g->n / 32 + 1, nj, 64), true, false, false});
+  }
+  // CPI adjacency lists per spanning-tree edge, in BFS order
+  for (int j = 1; j < maxk; j++) {
+    std::vector<CpiJob> C(nj);
+    uint64_t items = 1, rows = 1;
+    bool any = false;
+    const uint32_t ep = next_epoch(c);
+    for (int x = 0; x < nj; x++) {
+      Job& J = jobs[x];
+      const Plan& p = J.plan;
+      CpiJob& a = C[x];
+      a = CpiJob{};
+      if (j >= p.k) continue;
+      const int u = p.bfs[j], q = p.parent[u];
+      a.active = 1;
+      a.dir = p.adj_dir[u];
+      a.prim = p.adj_prim[u];
+      a.other = p.adj_other[u];
+      a.p = cand_set(J, q);
+      a.u = cand_set(J, u);
+      a.cap_p = J.caps.cap_u[q];
+      a.beg = J.mem.cpi_beg[u];
+      a.len = J.mem.cpi_len[u];
+      a.cur = J.mem.cpi_cur[u];
+      a.arena = c.ws->cpi_arena;
+      a.arena_cursor = c.ws->misc;
+      a.arena_cap = c.ws->cpi_cap;
+      a.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
+      a.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
+      a.bytes = by ? by + K_CPI : nullptr;
+      items = std::max(items, a.cap_p);
+      rows = std::max(rows, rows_ub(g, p.qlab[q], a.dir));
+      any = true;
+    }
+    if (any)
+      L.push_back(Launch{1, R.add(C), nj, gx_scan(items), gx_for(rows, nj), gx_for(items, nj), 0,
+                         true, false, false});
+  }
+  if (!fast_enum) return;
+  // enumeration levels (core-first matching order) with the fused check
+  for (int i = 1; i < maxk; i++) {
+    std::vector<ExtJob> E(nj);
+    uint64_t srcs = 1;
+    bool any_last = false, any_inner = false;
+    const uint32_t ep = next_epoch(c);
+    for (int x = 0; x < nj; x++) {
+      Job& J = jobs[x];
+      const Plan& p = J.plan;
+      ExtJob& e = E[x];
+      e = ExtJob{};
+      if (i >= p.k) continue;
+      const int u = p.order[i], q = p.parent[u];
+      e.active = 1;
+      e.i = i;
+      e.k = p.k;
+      e.last = i == p.k - 1;
+      if (i == 1) {
+        const CandSet r = cand_set(J, p.root);
+        e.src_cols = r.list;
+        e.src_stride = 0;
+        e.d_nsrc = r.cnt;
+        e.src_cap = J.caps.cap_u[p.root];
+      } else {
+        e.src_cols = J.mem.cols[i];
+        e.src_stride = J.caps.cap_f;
+        e.d_nsrc = J.mem.ctl + CTL_LEVEL_N + i;
+        e.src_cap = J.caps.cap_f;
+      }
+      e.par_pos = p.pos[q];
+      e.par_posmap = J.mem.pos[q];
+      e.cpi_beg = J.mem.cpi_beg[u];
+      e.cpi_len = J.mem.cpi_len[u];
+      e.cpi_ent = c.ws->cpi_arena;
+      e.begs = J.mem.begs;
+      e.sc = job_scan_rec(c, J, J.mem.ctl + CTL_LEVEL_T + i, ep);
+      e.a_begin = 0;
+      e.a_end = ~0ull;
+      e.nchk = p.nchk[i];
+      for (int t = 0; t < MAXK; t++) {
+        e.chk_pos[t] = t < p.nchk[i] ? p.chk_pos[i][t] : 0;
+        e.chk_fwd[t] = t < p.nchk[i] ? p.chk_fwd[i][t] : PC_FREE;
+        e.chk_bwd[t] = t < p.nchk[i] ? p.chk_bwd[i][t] : PC_FREE;
+      }
+      if (!e.last) {
+        e.dst_cols = J.mem.cols[i + 1];
+        e.dst_cap = J.caps.cap_f;
+        e.d_ndst = J.mem.ctl + CTL_LEVEL_N + i + 1;
+      }
+      e.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
+      for (int v = 0; v < MAXK; v++) e.var_pos[v] = v < p.k ? p.pos[v] : 0;
+      e.nx = p.nx;
+      e.ny = p.ny;
+      e.y_false = p.y_false;
+      for (int t = 0; t < 2 * MAXLIT; t++) e.lit[t] = p.lit[t];
+      e.counters = (unsigned long long*)(J.mem.ctl + CTL_MATCH);
+      e.vbuf = J.mem.vbuf;
+      e.d_vcount = J.mem.ctl + CTL_VCOUNT;
+      e.vcap = c.K > 0 ? J.caps.vcap : 0;
+      e.thr = nullptr;
+      e.d_thr_valid = (const uint32_t*)(J.mem.ctl + CTL_THRVALID);
+      e.bytes = by ? by + (e.last ? K_LAST : K_EXT) : nullptr;
+      srcs = std::max(srcs, e.src_cap);
+      any_last |= e.last != 0;
+      any_inner |= e.last == 0;
+    }
+    L.push_back(Launch{2, R.add(E), nj, gx_scan(srcs), gx_for(1u << 30, nj), 0, 0, true, any_last,
+                       any_inner});
+  }
+  // single-vertex patterns
+  {
+    std::vector<ExtJob> E(nj);
+    bool any = false;
+    uint64_t items = 1;
+    for (int x = 0; x < nj; x++) {
+      Job& J = jobs[x];
+      const Plan& p = J.plan;
+      ExtJob& e = E[x];
+      e = ExtJob{};
+      if (p.k != 1) continue;
+      const CandSet r = cand_set(J, p.root);
+      e.active = 1;
+      e.k = 1;
+      e.last = 1;
+      e.src_cols = r.list;
+      e.d_nsrc = r.cnt;
+      e.src_cap = J.caps.cap_u[p.root];
+      e.a_begin = 0;
+      e.a_end = ~0ull;
+      e.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
+      e.var_pos[0] = 0;
+      e.nx = p.nx;
+      e.ny = p.ny;
+      e.y_false = p.y_false;
+      for (int t = 0; t < 2 * MAXLIT; t++) e.lit[t] = p.lit[t];
+      e.counters = (unsigned long long*)(J.mem.ctl + CTL_MATCH);
+      e.vbuf = J.mem.vbuf;
+      e.d_vcount = J.mem.ctl + CTL_VCOUNT;
+      e.vcap = c.K > 0 ? J.caps.vcap : 0;
+      e.d_thr_valid = (const uint32_t*)(J.mem.ctl + CTL_THRVALID);
+      e.bytes = by ? by + K_LAST : nullptr;
+      items = std::max(items, e.src_cap);
+      any = true;
+    }
+    if (any) L.push_back(Launch{3, R.add(E), nj, 0, gx_for(items, nj), 0, 0, false, true, false});
+  }
+  if (c.K > 0) {
+    std::vector<TopkJob> T(nj);
+    for (int x = 0; x < nj; x++) {
+      Job& J = jobs[x];
+      T[x] = TopkJob{1, J.plan.k, c.K, J.mem.vbuf, J.mem.ctl + CTL_VCOUNT, J.caps.vcap, J.mem.res,
+                     (uint32_t*)(J.mem.ctl + CTL_NEEDSEL)};
+    }
+    L.push_back(Launch{4, R.add(T), nj, 0, 0, 0, 0, false, false, false});
+  }
+}
+
+static void run_launches(Ctx& c, const std::vector<Launch>& L) {
+  const DevGraph& g = c.g->dg;
+  uint8_t* base = c.ws->jobrec;
+  for (const Launch& l : L) {
+    switch (l.kind) {
+      case 0: {
+        auto* r = (const FilterJob*)(base + l.off);
+        if (l.scan) {
+          c.tm.run(K_SCAN, [&] { filter_scan(c.st, g, r, l.njobs, l.gx_scan); });
+          c.tm.run(K_PULL, [&] { filter_pull(c.st, g, r, l.njobs, l.gx_work); });
+        }
+        c.tm.run(K_OTHER, [&] { filter_clear(c.st, r, l.njobs, l.gx_clear); });
+        c.tm.run(K_FILTER, [&] { filter_compact(c.st, g, r, l.njobs, l.gx_item); });
+        break;
+      }
+      case 1: {
+        auto* r = (const CpiJob*)(base + l.off);
+        c.tm.run(K_SCAN, [&] { cpi_scan(c.st, g, r, l.njobs, l.gx_scan); });
+        c.tm.run(K_CPI, [&] { cpi_count(c.st, g, r, l.njobs, l.gx_work); });
+        c.tm.run(K_CPI, [&] { cpi_alloc(c.st, g, r, l.njobs, l.gx_item); });
+        c.tm.run(K_CPI, [&] { cpi_fill(c.st, g, r, l.njobs, l.gx_work); });
+        break;
+      }
+      case 2: {
+        auto* r = (const ExtJob*)(base + l.off);
+        c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, r, l.njobs, l.gx_scan); });
+        if (l.inner_any) c.tm.run(K_EXT, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, false); });
+        if (l.last_any) c.tm.run(K_LAST, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, true); });
+        break;
+      }
+      case 3: {
+        auto* r = (const ExtJob*)(base + l.off);
+        c.tm.run(K_LAST, [&] { ext_single(c.st, g, r, l.njobs, l.gx_work); });
+        break;
+      }
+      case 4: {
+        auto* r = (const TopkJob*)(base + l.off);
+        c.tm.run(K_TOPK, [&] { topk_small(c.st, r, l.njobs); });
+        break;
+      }
+    }
+  }
+}
+
+static void upload_recs(Ctx& c, const Recs& R) {
+  ensure_recs(c.ws, std::max<size_t>(R.blob.size(), 256));
+  std::memcpy(c.ws->hjobrec, R.blob.data(), R.blob.size());
+  HIPCHK(hipMemcpyAsync(c.ws->jobrec, c.ws->hjobrec, R.blob.size(), hipMemcpyHostToDevice, c.st));
+}
+
+// Arena of a batch: [control blocks][tile states][results][job regions].
+static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
   Workspace* ws = c.ws;
-  if (ws->ep < 160) return;
-  for (int j = 0; j < MAXK; j++) {
-    fill_u8(c.st, ws->mem[j], 0, ws->n);
-    fill_u8(c.st, ws->mark[j], 0, ws->n);
+  const size_t nj = jobs.size();
+  uint64_t tiles = 0;
+  size_t body = 0;
+  for (auto& J : jobs) {
+    tiles = std::max(tiles, J.caps.tiles);
+    body += align_up(J.caps.bytes);
   }
-  ws->ep = 0;
+  const size_t ctl_b = align_up(sizeof(uint64_t) * CTL_WORDS * nj);
+  const size_t ts_b = align_up(sizeof(uint64_t) * tiles * nj);
+  const size_t res_b = align_up(sizeof(int32_t) * (size_t)std::max(c.K, 1) * MAXK * nj);
+  const size_t total = ctl_b + ts_b + res_b + body;
+  if (ws->arena_bytes < total) {
+    dfree(ws->arena);
+    ws->arena = nullptr;
+    ws->arena_bytes = 0;
+    ws->arena = dalloc<uint8_t>(total);
+    ws->arena_bytes = total;
+  }
+  uint8_t* p = ws->arena + ctl_b + ts_b + res_b;
+  for (size_t x = 0; x < nj; x++) {
+    Job& J = jobs[x];
+    J.mem.ctl = (uint64_t*)ws->arena + CTL_WORDS * x;
+    J.mem.tstate = (uint64_t*)(ws->arena + ctl_b) + tiles * x;
+    J.mem.res = (int32_t*)(ws->arena + ctl_b + ts_b) + (size_t)std::max(c.K, 1) * MAXK * x;
+    job_layout(p, c.g, J.plan, J.caps, J.mem);
+    p += align_up(J.caps.bytes);
+  }
+  if (ws->hctl_words < CTL_WORDS * nj) {
+    if (ws->hctl) (void)hipHostFree(ws->hctl);
+    ws->hctl = nullptr;
+    ws->hctl_words = 0;
+    HIPCHK(hipHostMalloc((void**)&ws->hctl, sizeof(uint64_t) * CTL_WORDS * nj, hipHostMallocDefault));
+    ws->hctl_words = CTL_WORDS * nj;
+  }
+  // zero the control blocks and tile states; the CPI arena starts empty
+  fill_u64(c.st, (uint64_t*)ws->arena, 0, (ctl_b + ts_b) / 8);
+  fill_u64(c.st, (uint64_t*)ws->misc, 0, 1);
 }
 
-static void alloc_workspace(gfd_graph* g, Workspace* ws, int64_t budget) {
-  const int64_t n = g->n, m = g->m;
-  ws->n = n; ws->m = m; ws->budget = budget;
-  // frontier levels 2..7: 4*i bytes of columns + 12 bytes (prefix, begin) per slot
-  int64_t per_slot = 0;
-  for (int i = 2; i < MAXK; i++) per_slot += 4 * i + 12;
-  ws->cap = (uint64_t)std::max<int64_t>(1024, budget / per_slot);
-  ws->alloc_cap = ws->cap;
-  ws->pcap = std::max<uint64_t>(ws->cap, (uint64_t)n) + 1;
-  int64_t* t = &ws->bytes;
-  for (int j = 0; j < 2 * MAXK; j++) ws->cand[j] = dalloc<int32_t>(n, t);
-  for (int j = 0; j < MAXK; j++) {
-    ws->mem[j] = dalloc<uint8_t>(n, t);
-    ws->mark[j] = dalloc<uint8_t>(n, t);
-    ws->posmap[j] = dalloc<int32_t>(n, t);
-    ws->cpi_beg[j] = dalloc<uint32_t>(n, t);
-    ws->cpi_len[j] = dalloc<uint32_t>(n, t);
-    ws->cpi_ent[j] = dalloc<int32_t>(m, t);
-  }
-  ws->rowP = dalloc<uint64_t>(n + 1, t);
-  uint64_t words = (uint64_t)std::max(n, m) / 64 + 2;
-  ws->masks = dalloc<uint64_t>(words, t);
-  ws->pre = dalloc<uint64_t>(words + 1, t);
-  for (int i = 1; i < MAXK; i++) {
-    if (i >= 2) ws->cols[i] = dalloc<int32_t>((size_t)i * ws->cap, t);
-    ws->P[i] = dalloc<uint64_t>(ws->pcap + 1, t);
-    ws->beg[i] = dalloc<uint32_t>(ws->pcap, t);
-  }
-  ws->dcnt = dalloc<uint64_t>(4 * MAXK, t);
-  ws->stat_bytes = dalloc<unsigned long long>(8, t);
-  uint64_t max_items = std::max<uint64_t>({ws->pcap, (uint64_t)m, (uint64_t)n}) + 1;
-  ws->scan.max_tiles = max_items / SCAN_TILE + 2;
-  ws->scan.tile_state = dalloc<uint64_t>(ws->scan.max_tiles, t);
-  ws->scan.ticket = dalloc<uint32_t>(1, t);
-  ws->scan.err = dalloc<uint32_t>(1, t);
-  ws->scan.epoch = 0;
-  ws->sel_state = dalloc<uint32_t>(MAXK + 2, t);
-  ws->sel_hist = dalloc<uint32_t>(RADIX_BINS, t);
-  ws->sel_out = dalloc<int32_t>((size_t)SORT_MAX * MAXK, t);
-  HIPCHK(hipMemset(ws->scan.tile_state, 0, sizeof(uint64_t) * ws->scan.max_tiles));
-  HIPCHK(hipMemset(ws->scan.ticket, 0, 4));
-  HIPCHK(hipMemset(ws->scan.err, 0, 4));
-  HIPCHK(hipMemset(ws->sel_hist, 0, 4 * RADIX_BINS));
-  for (int j = 0; j < MAXK; j++) {
-    HIPCHK(hipMemset(ws->mem[j], 0, std::max<int64_t>(n, 1)));
-    HIPCHK(hipMemset(ws->mark[j], 0, std::max<int64_t>(n, 1)));
-  }
-  HIPCHK(hipHostMalloc((void**)&ws->hctl, sizeof(uint64_t) * CTL_WORDS, hipHostMallocDefault));
-  HIPCHK(hipDeviceSynchronize());
+static void ensure_chunk(Workspace* ws, size_t bytes) {
+  if (ws->chunk_bytes >= bytes) return;
+  dfree(ws->chunk);
+  ws->chunk = nullptr;
+  ws->chunk_bytes = 0;
+  ws->chunk = dalloc<uint8_t>(bytes);
+  ws->chunk_bytes = bytes;
 }
 
 static void ensure_vbig(Workspace* ws, uint64_t vcap) {
   if (ws->vbig_cap >= vcap) return;
   dfree(ws->vbig);
   ws->vbig = nullptr;
+  ws->vbig_cap = 0;
   ws->vbig = dalloc<int32_t>((size_t)vcap * MAXK);
   ws->vbig_cap = vcap;
-}
-
-static void ensure_per_gfd(Workspace* ws, size_t ngfd, uint64_t vsmall, int K) {
-  if (ws->ngfd_cap >= ngfd && ws->vsmall_cap >= vsmall && ws->res_K >= K) return;
-  // every region is laid out with these strides, so allocate with them
-  const size_t want = std::max(ngfd, ws->ngfd_cap);
-  const uint64_t vs = std::max<uint64_t>({vsmall, ws->vsmall_cap, 1});
-  const int rk = std::max({K, ws->res_K, 1});
-  dfree(ws->ctl);
-  dfree(ws->vsmall);
-  dfree(ws->res);
-  ws->ctl = nullptr;
-  ws->vsmall = nullptr;
-  ws->res = nullptr;
-  ws->ngfd_cap = 0;
-  if (ws->hctl) { (void)hipHostFree(ws->hctl); ws->hctl = nullptr; }
-  ws->ctl = dalloc<uint64_t>(want * CTL_WORDS);
-  ws->vsmall = dalloc<int32_t>(want * vs * MAXK);
-  ws->res = dalloc<int32_t>(want * (size_t)rk * MAXK);
-  HIPCHK(hipHostMalloc((void**)&ws->hctl, sizeof(uint64_t) * CTL_WORDS * want, hipHostMallocDefault));
-  ws->ngfd_cap = want;
-  ws->vsmall_cap = vs;
-  ws->res_K = rk;
-}
-
-struct CandRef {
-  int cur[MAXK];
-  int32_t* list(Workspace* ws, int u) const { return ws->cand[2 * u + cur[u]]; }
-  uint64_t* cnt(Workspace* ws, int u) const { return ws->dcnt + 2 * u + cur[u]; }
-};
-
-struct GfdState {
-  Plan plan;
-  CandRef cr;
-  uint8_t mem_ep[MAXK];
-  uint64_t cand_ub[MAXK];
-};
-
-static int tiles_grid(uint64_t items) {
-  uint64_t t = (items + BS - 1) / BS;
-  return (int)std::max<uint64_t>(1, std::min<uint64_t>(t, 512));
-}
-
-// Pull constraints on candidates of u from the current candidate sets of the
-// pattern neighbours `nbrs`: one per pattern edge between u and a neighbour.
-static void add_pull(Ctx& c, GfdState& S, int u, const std::vector<int>& nbrs, CandArgs& ca) {
-  const Plan& p = S.plan;
-  ca.ncons = 0;
-  for (int w : nbrs) {
-    if (p.qe[w][u] != NOEDGE)  // w -> u: v needs an in-neighbour in C(w)
-      ca.cons[ca.ncons++] = PullCons{1, p.qe[w][u], c.ws->mem[w], S.mem_ep[w]};
-    if (p.qe[u][w] != NOEDGE)  // u -> w: v needs an out-neighbour in C(w)
-      ca.cons[ca.ncons++] = PullCons{0, p.qe[u][w], c.ws->mem[w], S.mem_ep[w]};
-  }
-}
-
-// CPI construction (Section IV-B, step 1) for one GFD; all asynchronous.
-static void build_cpi(Ctx& c, GfdState& S) {
-  const gfd_graph* g = c.g;
-  Workspace* ws = c.ws;
-  Plan& p = S.plan;
-  const int k = p.k;
-  epoch_guard(c);
-  for (int u = 0; u < k; u++) {
-    S.cr.cur[u] = 0;
-    S.cand_ub[u] = bucket_size(g, p.qlab[u]);
-  }
-  unsigned long long* by = c.stat_bytes;
-  // candidate and CPI-entry counters are atomic output cursors
-  fill_u64(c.st, ws->dcnt, 0, 2 * MAXK);
-  fill_u64(c.st, ws->dcnt + 2 * MAXK + 8, 0, MAXK);
-  // top-down, BFS order: label bucket, degree filter, adjacency to the
-  // candidates of every earlier pattern neighbour
-  for (int j = 0; j < k; j++) {
-    const int u = p.bfs[j];
-    CandArgs ca{};
-    ca.g = g->dg;
-    add_pull(c, S, u, p.down[u], ca);
-    ca.min_out = p.min_out[u];
-    ca.min_in = p.min_in[u];
-    const uint64_t bs = S.cand_ub[u];
-    if (p.qlab[u] == ANY) ca.list = nullptr;
-    else ca.list = g->dg.lab_vtx + (bs ? g->lab_off[p.qlab[u]] : 0);
-    ca.d_n = nullptr;
-    ca.n_host = ca.cap = bs;
-    ca.out = S.cr.list(ws, u);
-    ca.d_out_n = S.cr.cnt(ws, u);
-    ca.mem = ws->mem[u];
-    ca.mem_ep = S.mem_ep[u] = next_ep(ws);
-    ca.posmap = (p.up[u].empty() && p.is_parent[u]) ? ws->posmap[u] : nullptr;
-    ca.bytes = by ? by + K_FILTER : nullptr;
-    c.tm.run(K_FILTER, [&] { cand_filter(c.st, ca, tiles_grid(bs)); });
-  }
-  // bottom-up, reverse BFS order: drop dead ends (no neighbour in the
-  // candidate set of a later pattern neighbour)
-  for (int j = k - 1; j >= 0; j--) {
-    const int u = p.bfs[j];
-    if (p.up[u].empty()) continue;
-    CandArgs ca{};
-    ca.g = g->dg;
-    add_pull(c, S, u, p.up[u], ca);
-    ca.list = S.cr.list(ws, u);
-    ca.d_n = S.cr.cnt(ws, u);
-    ca.cap = S.cand_ub[u];
-    S.cr.cur[u] ^= 1;
-    ca.out = S.cr.list(ws, u);
-    ca.d_out_n = S.cr.cnt(ws, u);
-    ca.mem = ws->mem[u];
-    ca.mem_ep = S.mem_ep[u] = next_ep(ws);
-    ca.posmap = p.is_parent[u] ? ws->posmap[u] : nullptr;
-    ca.bytes = by ? by + K_FILTER : nullptr;
-    c.tm.run(K_FILTER, [&] { cand_filter(c.st, ca, tiles_grid(S.cand_ub[u])); });
-  }
-  // CPI adjacency lists per spanning-tree edge
-  for (int u = 0; u < k; u++) {
-    if (u == p.root) continue;
-    const int q = p.parent[u];
-    CpiArgs a{};
-    a.g = g->dg;
-    a.dir = p.adj_dir[u];
-    a.list = S.cr.list(ws, q);
-    a.d_n = S.cr.cnt(ws, q);
-    a.cap = S.cand_ub[q];
-    a.prim = p.adj_prim[u];
-    a.other = p.adj_other[u];
-    a.mem = ws->mem[u];
-    a.ep = S.mem_ep[u];
-    a.cpi_beg = ws->cpi_beg[u];
-    a.cpi_len = ws->cpi_len[u];
-    a.cpi_ent = ws->cpi_ent[u];
-    a.d_entries = ws->dcnt + 2 * MAXK + 8 + u;
-    a.bytes = by ? by + K_ADJ : nullptr;
-    c.tm.run(K_ADJ, [&] { cpi_adjacency(c.st, a, tiles_grid(S.cand_ub[q])); });
-  }
-  if (getenv("GFD_DEBUG_CPI")) {  // diagnostics: sizes of the candidate sets and CPI lists
-    uint64_t h[4 * MAXK];
-    HIPCHK(hipMemcpyAsync(h, ws->dcnt, sizeof h, hipMemcpyDeviceToHost, c.st));
-    HIPCHK(hipStreamSynchronize(c.st));
-    fprintf(stderr, "[gfd] k=%d root=%d", k, p.root);
-    for (int u = 0; u < k; u++)
-      fprintf(stderr, " | u%d L%d bucket %llu cand %llu ent %llu", u, p.qlab[u],
-              (unsigned long long)S.cand_ub[u], (unsigned long long)h[2 * u + S.cr.cur[u]],
-              (unsigned long long)h[2 * MAXK + 8 + u]);
-    fprintf(stderr, "\n");
-  }
-}
-
-static void fill_ext_common(Ctx& c, GfdState& S, ExtArgs& a, int i) {
-  const Plan& p = S.plan;
-  a.g = c.g->dg;
-  a.i = i;
-  a.nchk = p.nchk[i];
-  for (int j = 0; j < MAXK; j++) {
-    a.chk_pos[j] = j < p.nchk[i] ? p.chk_pos[i][j] : 0;
-    a.chk_fwd[j] = j < p.nchk[i] ? p.chk_fwd[i][j] : PC_FREE;
-    a.chk_bwd[j] = j < p.nchk[i] ? p.chk_bwd[i][j] : PC_FREE;
-  }
-  a.k = p.k;
-  for (int v = 0; v < MAXK; v++) a.var_pos[v] = v < p.k ? p.pos[v] : 0;
-  a.nx = p.nx;
-  a.ny = p.ny;
-  a.y_false = p.y_false;
-  for (int j = 0; j < 2 * MAXLIT; j++) a.lit[j] = p.lit[j];
-}
-
-struct LevelView {
-  const int32_t* cols;
-  uint64_t stride;
-  const uint64_t* d_n;
-  uint64_t cap;
-};
-
-static LevelView level_view(Ctx& c, GfdState& S, int i, uint64_t* ctl) {
-  Workspace* ws = c.ws;
-  if (i == 1) {
-    int r = S.plan.root;
-    return {S.cr.list(ws, r), 0, S.cr.cnt(ws, r), S.cand_ub[r]};
-  }
-  return {ws->cols[i], ws->cap, ctl + CTL_LEVEL_N + i, ws->cap};
-}
-
-// Fast path: every level in one pass, nothing read back.
-static void enumerate_fast(Ctx& c, GfdState& S, uint64_t* ctl, int32_t* vbuf, uint64_t vcap) {
-  Workspace* ws = c.ws;
-  const Plan& p = S.plan;
-  ExtArgs a{};
-  fill_ext_common(c, S, a, 0);
-  a.counters = (unsigned long long*)(ctl + CTL_MATCH);
-  a.vbuf = vbuf;
-  a.d_vcount = ctl + CTL_VCOUNT;
-  a.vcap = c.K > 0 ? vcap : 0;
-  a.thr = nullptr;
-  a.d_thr_valid = (const uint32_t*)(ctl + CTL_THRVALID);
-  a.d_flags = (uint32_t*)(ctl + CTL_FLAGS);
-  if (p.k == 1) {
-    const int r = p.root;
-    a.a_begin = 0;
-    a.a_end = ~0ull;
-    c.tm.run(K_LAST, [&] {
-      single_vertex(c.st, a, S.cr.list(ws, r), S.cr.cnt(ws, r), S.cand_ub[r], grid_for(S.cand_ub[r]));
-    });
-    return;
-  }
-  for (int i = 1; i < p.k; i++) {
-    const int u = p.order[i], q = p.parent[u];
-    LevelView lv = level_view(c, S, i, ctl);
-    const int32_t* par = lv.cols + (uint64_t)p.pos[q] * lv.stride;
-    c.tm.run(K_SCAN, [&] {
-      scan_sources(c.st, ws->scan, par, lv.d_n, lv.cap, ws->posmap[q], ws->cpi_beg[u], ws->cpi_len[u], ws->beg[i],
-                   ws->P[i], ctl + CTL_LEVEL_T + i);
-    });
-    fill_ext_common(c, S, a, i);
-    a.src_cols = lv.cols;
-    a.src_stride = lv.stride;
-    a.d_nsrc = lv.d_n;
-    a.src_cap = lv.cap;
-    a.P = ws->P[i];
-    a.beg = ws->beg[i];
-    a.cpi_ent = ws->cpi_ent[u];
-    a.a_begin = 0;
-    a.a_end = ~0ull;
-    const bool last = i == p.k - 1;
-    a.bytes = c.stat_bytes ? c.stat_bytes + (last ? K_LAST : K_EXT) : nullptr;
-    if (!last) {
-      a.dst_cols = ws->cols[i + 1];
-      a.dst_cap = ws->cap;
-      a.d_ndst = ctl + CTL_LEVEL_N + i + 1;
-    }
-    c.tm.run(last ? K_LAST : K_EXT, [&] { extend(c.st, a, last, 1024); });
-  }
 }
 
 // Radix select of the K-th smallest staged tuple, then the first K sorted into
@@ -891,7 +1107,7 @@ static void select_first_k(Ctx& c, const int32_t* vbuf, const uint64_t* d_vcount
                            int k, uint64_t* ctl) {
   Workspace* ws = c.ws;
   c.tm.run(K_TOPK, [&] { select_begin(c.st, ws->sel_state, c.K); });
-  const int grid = grid_for(vcap);
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((vcap + BS - 1) / BS, 1024));
   for (int w = 0; w < k; w++) {
     const int shifts[3] = {21, 10, 0}, bits[3] = {11, 11, 10};
     for (int ps = 0; ps < 3; ps++)
@@ -908,143 +1124,221 @@ static void select_first_k(Ctx& c, const int32_t* vbuf, const uint64_t* d_vcount
   c.tm.run(K_TOPK, [&] { sort_tuples(c.st, ws->sel_out, ctl + CTL_OUTCOUNT, k); });
 }
 
-// Chunked path: frontier levels processed in windows that fit the budget;
-// violation staging compacted to the first K whenever it could overflow.
-struct Chunked {
+// Bounded path for one job whose fast pass overflowed: the frontier of every
+// level is processed in windows of attempts that fit the job's capacity, and
+// violation staging is cut to the first K whenever it could overflow.
+struct Bounded {
   Ctx& c;
-  GfdState& S;
-  uint64_t* ctl;
-  uint64_t* h;  // pinned mirror
+  Job& J;
+  uint64_t* P[MAXK];
+  uint32_t* begs[MAXK];
   uint64_t rd(int word) {
-    HIPCHK(hipMemcpyAsync(h + word, ctl + word, 8, hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(c.ws->hctl + word, J.mem.ctl + word, 8, hipMemcpyDeviceToHost, c.st));
     HIPCHK(hipStreamSynchronize(c.st));
-    return h[word];
+    return c.ws->hctl[word];
+  }
+  void upload_one(const ExtJob& e) {
+    ensure_recs(c.ws, sizeof(ExtJob));
+    HIPCHK(hipStreamSynchronize(c.st));  // the staging buffer is reused per launch
+    std::memcpy(c.ws->hjobrec, &e, sizeof e);
+    HIPCHK(hipMemcpyAsync(c.ws->jobrec, c.ws->hjobrec, sizeof e, hipMemcpyHostToDevice, c.st));
   }
   void compact_if_needed(uint64_t incoming) {
     Workspace* ws = c.ws;
-    const int k = S.plan.k;
-    uint64_t vc = rd(CTL_VCOUNT);
+    const int k = J.plan.k;
+    const uint64_t vc = rd(CTL_VCOUNT);
     if (vc + incoming <= ws->vbig_cap || vc <= (uint64_t)c.K) return;
-    select_first_k(c, ws->vbig, ctl + CTL_VCOUNT, ws->vbig_cap, k, ctl);
-    // keep the first K, threshold = the K-th
-    HIPCHK(hipMemcpyAsync(ws->vbig, ws->sel_out, sizeof(int32_t) * c.K * k, hipMemcpyDeviceToDevice, c.st));
-    HIPCHK(hipMemcpyAsync((int32_t*)(ctl + CTL_THR), ws->sel_out + (size_t)(c.K - 1) * k,
+    select_first_k(c, ws->vbig, J.mem.ctl + CTL_VCOUNT, ws->vbig_cap, k, J.mem.ctl);
+    // keep the first K; the K-th becomes the staging threshold
+    HIPCHK(hipMemcpyAsync(ws->vbig, ws->sel_out, sizeof(int32_t) * c.K * k,
+                          hipMemcpyDeviceToDevice, c.st));
+    HIPCHK(hipMemcpyAsync((int32_t*)(J.mem.ctl + CTL_THR), ws->sel_out + (size_t)(c.K - 1) * k,
                           sizeof(int32_t) * k, hipMemcpyDeviceToDevice, c.st));
-    fill_u64(c.st, ctl + CTL_VCOUNT, (uint64_t)c.K, 1);
-    fill_u64(c.st, ctl + CTL_THRVALID, 1, 1);
+    fill_u64(c.st, J.mem.ctl + CTL_VCOUNT, (uint64_t)c.K, 1);
+    fill_u64(c.st, J.mem.ctl + CTL_THRVALID, 1, 1);
+  }
+  ExtJob base(int i) {
+    const Plan& p = J.plan;
+    ExtJob e{};
+    e.active = 1;
+    e.i = i;
+    e.k = p.k;
+    e.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
+    for (int v = 0; v < MAXK; v++) e.var_pos[v] = v < p.k ? p.pos[v] : 0;
+    e.nx = p.nx;
+    e.ny = p.ny;
+    e.y_false = p.y_false;
+    for (int t = 0; t < 2 * MAXLIT; t++) e.lit[t] = p.lit[t];
+    e.counters = (unsigned long long*)(J.mem.ctl + CTL_MATCH);
+    e.vbuf = c.ws->vbig;
+    e.d_vcount = J.mem.ctl + CTL_VCOUNT;
+    e.vcap = c.K > 0 ? c.ws->vbig_cap : 0;
+    e.thr = (const int32_t*)(J.mem.ctl + CTL_THR);
+    e.d_thr_valid = (const uint32_t*)(J.mem.ctl + CTL_THRVALID);
+    return e;
   }
   void level(int i) {
-    Workspace* ws = c.ws;
-    const Plan& p = S.plan;
+    const Plan& p = J.plan;
     const int u = p.order[i], q = p.parent[u];
-    LevelView lv = level_view(c, S, i, ctl);
-    const int32_t* par = lv.cols + (uint64_t)p.pos[q] * lv.stride;
-    c.tm.run(K_SCAN, [&] {
-      scan_sources(c.st, ws->scan, par, lv.d_n, lv.cap, ws->posmap[q], ws->cpi_beg[u], ws->cpi_len[u], ws->beg[i],
-                   ws->P[i], ctl + CTL_LEVEL_T + i);
-    });
+    ExtJob e = base(i);
+    e.last = i == p.k - 1;
+    if (i == 1) {
+      const CandSet r = cand_set(J, p.root);
+      e.src_cols = r.list;
+      e.src_stride = 0;
+      e.d_nsrc = r.cnt;
+      e.src_cap = J.caps.cap_u[p.root];
+    } else {
+      e.src_cols = J.mem.cols[i];
+      e.src_stride = J.caps.cap_f;
+      e.d_nsrc = J.mem.ctl + CTL_LEVEL_N + i;
+      e.src_cap = J.caps.cap_f;
+    }
+    e.par_pos = p.pos[q];
+    e.par_posmap = J.mem.pos[q];
+    e.cpi_beg = J.mem.cpi_beg[u];
+    e.cpi_len = J.mem.cpi_len[u];
+    e.cpi_ent = c.ws->cpi_arena;
+    e.begs = begs[i];
+    e.sc = JobScan{P[i], J.mem.ctl + CTL_LEVEL_T + i, J.mem.tstate,
+                   (uint32_t*)(J.mem.ctl + CTL_TICKET), c.ws->err, next_epoch(c)};
+    e.nchk = p.nchk[i];
+    for (int t = 0; t < MAXK; t++) {
+      e.chk_pos[t] = t < p.nchk[i] ? p.chk_pos[i][t] : 0;
+      e.chk_fwd[t] = t < p.nchk[i] ? p.chk_fwd[i][t] : PC_FREE;
+      e.chk_bwd[t] = t < p.nchk[i] ? p.chk_bwd[i][t] : PC_FREE;
+    }
+    if (!e.last) {
+      e.dst_cols = J.mem.cols[i + 1];
+      e.dst_cap = J.caps.cap_f;
+      e.d_ndst = J.mem.ctl + CTL_LEVEL_N + i + 1;
+    }
+    upload_one(e);
+    const DevGraph& g = c.g->dg;
+    const ExtJob* rec = (const ExtJob*)c.ws->jobrec;
+    c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, rec, 1, gx_scan(e.src_cap)); });
     const uint64_t T = rd(CTL_LEVEL_T + i);
     if (c.stats) c.stats->attempts += T;
-    ExtArgs a{};
-    fill_ext_common(c, S, a, i);
-    a.src_cols = lv.cols;
-    a.src_stride = lv.stride;
-    a.d_nsrc = lv.d_n;
-    a.src_cap = lv.cap;
-    a.P = ws->P[i];
-    a.beg = ws->beg[i];
-    a.cpi_ent = ws->cpi_ent[u];
-    a.d_flags = (uint32_t*)(ctl + CTL_FLAGS);
-    const bool last = i == p.k - 1;
-    if (last) {
-      a.counters = (unsigned long long*)(ctl + CTL_MATCH);
-      a.vbuf = ws->vbig;
-      a.d_vcount = ctl + CTL_VCOUNT;
-      a.vcap = c.K > 0 ? ws->vbig_cap : 0;
-      a.thr = (const int32_t*)(ctl + CTL_THR);
-      a.d_thr_valid = (const uint32_t*)(ctl + CTL_THRVALID);
-      const uint64_t W = c.K > 0 ? ws->vbig_cap - (uint64_t)c.K : T;
-      for (uint64_t A0 = 0; A0 < T; A0 += W) {
-        const uint64_t A1 = std::min(T, A0 + W);
-        if (c.K > 0) compact_if_needed(A1 - A0);
-        a.a_begin = A0;
-        a.a_end = A1;
-        c.tm.run(K_LAST, [&] { extend(c.st, a, true, grid_for(A1 - A0)); });
+    const uint64_t W = e.last ? (c.K > 0 ? c.ws->vbig_cap - (uint64_t)c.K : std::max<uint64_t>(T, 1))
+                              : J.caps.cap_f;
+    for (uint64_t A0 = 0; A0 < T; A0 += W) {
+      const uint64_t A1 = std::min(T, A0 + W);
+      if (e.last && c.K > 0) compact_if_needed(A1 - A0);
+      if (!e.last) fill_u64(c.st, J.mem.ctl + CTL_LEVEL_N + i + 1, 0, 1);
+      e.a_begin = A0;
+      e.a_end = A1;
+      upload_one(e);
+      const int gx = (int)std::max<uint64_t>(1, std::min<uint64_t>((A1 - A0 + BS - 1) / BS, 1024));
+      c.tm.run(e.last ? K_LAST : K_EXT, [&] { ext_run(c.st, g, rec, 1, gx, e.last != 0); });
+      if (!e.last) {
+        const uint64_t N = rd(CTL_LEVEL_N + i + 1);
+        if (c.stats) c.stats->partials += N;
+        if (N) level(i + 1);
       }
-      return;
     }
-    a.dst_cols = ws->cols[i + 1];
-    a.dst_cap = ws->cap;
-    a.d_ndst = ctl + CTL_LEVEL_N + i + 1;
-    for (uint64_t A0 = 0; A0 < T; A0 += ws->cap) {
-      const uint64_t A1 = std::min(T, A0 + ws->cap);
-      fill_u64(c.st, ctl + CTL_LEVEL_N + i + 1, 0, 1);
-      a.a_begin = A0;
-      a.a_end = A1;
-      c.tm.run(K_EXT, [&] { extend(c.st, a, false, grid_for(A1 - A0)); });
-      const uint64_t N = rd(CTL_LEVEL_N + i + 1);
-      if (c.stats) c.stats->partials += N;
-      if (N) level(i + 1);
+  }
+  void single() {
+    const Plan& p = J.plan;
+    ExtJob e = base(0);
+    const CandSet r = cand_set(J, p.root);
+    e.k = 1;
+    e.last = 1;
+    e.src_cols = r.list;
+    e.d_nsrc = r.cnt;
+    e.src_cap = J.caps.cap_u[p.root];
+    HIPCHK(hipMemcpyAsync(c.ws->hctl, r.cnt, 8, hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    const uint64_t N = c.ws->hctl[0];
+    const uint64_t W = c.K > 0 ? c.ws->vbig_cap - (uint64_t)c.K : std::max<uint64_t>(N, 1);
+    for (uint64_t A0 = 0; A0 < N; A0 += W) {
+      const uint64_t A1 = std::min(N, A0 + W);
+      if (c.K > 0) compact_if_needed(A1 - A0);
+      e.a_begin = A0;
+      e.a_end = A1;
+      upload_one(e);
+      const ExtJob* rec = (const ExtJob*)c.ws->jobrec;
+      c.tm.run(K_LAST, [&] {
+        ext_single(c.st, c.g->dg, rec, 1,
+                   (int)std::max<uint64_t>(1, std::min<uint64_t>((A1 - A0 + BS - 1) / BS, 1024)));
+      });
     }
   }
 };
 
-static void enumerate_chunked(Ctx& c, GfdState& S, uint64_t* ctl, uint64_t* hmirror) {
+static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
   Workspace* ws = c.ws;
-  const Plan& p = S.plan;
-  fill_u64(c.st, ctl, 0, CTL_WORDS);
-  if (p.k == 1) {
-    ExtArgs a{};
-    fill_ext_common(c, S, a, 0);
-    a.counters = (unsigned long long*)(ctl + CTL_MATCH);
-    a.vbuf = ws->vbig;
-    a.d_vcount = ctl + CTL_VCOUNT;
-    a.vcap = c.K > 0 ? ws->vbig_cap : 0;
-    a.thr = nullptr;
-    a.d_thr_valid = (const uint32_t*)(ctl + CTL_THRVALID);
-    a.d_flags = (uint32_t*)(ctl + CTL_FLAGS);
-    const int r = p.root;
-    Chunked ch{c, S, ctl, hmirror};
-    HIPCHK(hipMemcpyAsync(hmirror, S.cr.cnt(ws, r), 8, hipMemcpyDeviceToHost, c.st));
-    HIPCHK(hipStreamSynchronize(c.st));
-    const uint64_t N = hmirror[0];
-    a.thr = (const int32_t*)(ctl + CTL_THR);
-    const uint64_t W = c.K > 0 ? ws->vbig_cap - (uint64_t)c.K : std::max<uint64_t>(N, 1);
-    for (uint64_t A0 = 0; A0 < N; A0 += W) {
-      const uint64_t A1 = std::min(N, A0 + W);
-      if (c.K > 0) ch.compact_if_needed(A1 - A0);
-      a.a_begin = A0;
-      a.a_end = A1;
-      c.tm.run(K_LAST, [&] {
-        single_vertex(c.st, a, S.cr.list(ws, r), S.cr.cnt(ws, r), S.cand_ub[r], grid_for(A1 - A0));
-      });
-    }
-    return;
+  std::vector<Job> one{J};
+  layout_batch(c, one);
+  Job& B = one[0];
+  Recs R;
+  std::vector<Launch> L;
+  plan_batch(c, one, R, L, false);
+  upload_recs(c, R);
+  run_launches(c, L);
+  HIPCHK(hipMemcpyAsync(ws->hctl, B.mem.ctl, sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  if (ws->hctl[CTL_FLAGS] & 4u)
+    throw GfdError{GFD_ENOMEM, "CPI lists exceed the entry arena; raise mem_budget_bytes"};
+  ensure_vbig(ws, vbig);
+  Bounded b{c, B, {}, {}};
+  const uint64_t pc = B.caps.begs + 1;
+  ensure_chunk(ws, (size_t)MAXK * (align_up(8 * (pc + 1)) + align_up(4 * pc)));
+  uint8_t* p = ws->chunk;
+  for (int i = 0; i < MAXK; i++) {
+    b.P[i] = (uint64_t*)p;
+    p += align_up(8 * (pc + 1));
+    b.begs[i] = (uint32_t*)p;
+    p += align_up(4 * pc);
   }
-  Chunked ch{c, S, ctl, hmirror};
-  ch.level(1);
+  if (B.plan.k == 1) b.single();
+  else b.level(1);
+  if (c.K > 0) {
+    std::vector<TopkJob> T{TopkJob{1, B.plan.k, c.K, ws->vbig, B.mem.ctl + CTL_VCOUNT, ws->vbig_cap,
+                                   B.mem.res, (uint32_t*)(B.mem.ctl + CTL_NEEDSEL)}};
+    ensure_recs(ws, sizeof(TopkJob));
+    HIPCHK(hipStreamSynchronize(c.st));
+    std::memcpy(ws->hjobrec, T.data(), sizeof(TopkJob));
+    HIPCHK(hipMemcpyAsync(ws->jobrec, ws->hjobrec, sizeof(TopkJob), hipMemcpyHostToDevice, c.st));
+    c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)ws->jobrec, 1); });
+    HIPCHK(hipMemcpyAsync(ws->hctl, B.mem.ctl, sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    if (ws->hctl[CTL_NEEDSEL]) {
+      select_first_k(c, ws->vbig, B.mem.ctl + CTL_VCOUNT, ws->vbig_cap, B.plan.k, B.mem.ctl);
+      HIPCHK(hipMemcpyAsync(B.mem.res, ws->sel_out, sizeof(int32_t) * c.K * B.plan.k,
+                            hipMemcpyDeviceToDevice, c.st));
+    }
+  }
+  J.mem = B.mem;
 }
 
 static int64_t default_budget() {
   size_t fr = 0, tot = 0;
-  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return int64_t(2) << 30;
-  int64_t b = (int64_t)(fr / 8);
-  return std::max<int64_t>(int64_t(64) << 20, std::min<int64_t>(b, int64_t(8) << 30));
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return int64_t(4) << 30;
+  const int64_t b = (int64_t)(fr / 3);
+  return std::max<int64_t>(int64_t(256) << 20, std::min<int64_t>(b, int64_t(48) << 30));
 }
 
 static Workspace* acquire_ws(gfd_graph* g, int64_t budget) {
   {
     std::lock_guard<std::mutex> lk(g->mu);
-    for (size_t i = 0; i < g->pool.size(); i++)
-      if (g->pool[i]->budget == budget) {
-        Workspace* w = g->pool[i];
-        g->pool.erase(g->pool.begin() + i);
-        return w;
-      }
+    if (!g->pool.empty()) {
+      Workspace* w = g->pool.back();
+      g->pool.pop_back();
+      w->budget = budget;
+      return w;
+    }
   }
   Workspace* w = new Workspace();
   try {
-    alloc_workspace(g, w, budget);
+    w->budget = budget;
+    w->misc = dalloc<unsigned long long>(16);
+    w->err = dalloc<uint32_t>(1);
+    w->sel_state = dalloc<uint32_t>(MAXK + 2);
+    w->sel_hist = dalloc<uint32_t>(RADIX_BINS);
+    w->sel_out = dalloc<int32_t>((size_t)SORT_MAX * MAXK);
+    HIPCHK(hipMemset(w->sel_hist, 0, 4 * RADIX_BINS));
+    HIPCHK(hipMemset(w->err, 0, 4));
+    HIPCHK(hipDeviceSynchronize());
   } catch (...) {
     delete w;
     throw;
@@ -1062,7 +1356,7 @@ static void release_ws(gfd_graph* g, Workspace* w) {
 extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, int32_t num_specs,
                                    const gfd_validate_opts* opts, gfd_result* results,
                                    gfd_stats* stats) {
-  auto t_start = std::chrono::steady_clock::now();
+  const auto t_start = std::chrono::steady_clock::now();
   gfd_graph* g = const_cast<gfd_graph*>(gc);
   if (!g) return set_error(GFD_EINVAL, "graph is NULL");
   if (num_specs < 0 || (num_specs > 0 && (!specs || !results)))
@@ -1071,105 +1365,136 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
   o.k_max = 1024;
   o.semantics = GFD_SEM_INDUCED;
   if (opts) o = *opts;
-  if (o.k_max < 0 || o.k_max > SORT_MAX) return set_error(o.k_max < 0 ? GFD_EINVAL : GFD_EUNSUPPORTED, "k_max %d (max %d)", o.k_max, SORT_MAX);
+  if (o.k_max < 0 || o.k_max > SORT_MAX)
+    return set_error(o.k_max < 0 ? GFD_EINVAL : GFD_EUNSUPPORTED, "k_max %d (max %d)", o.k_max, SORT_MAX);
   if (o.semantics != GFD_SEM_INDUCED && o.semantics != GFD_SEM_MONO) return set_error(GFD_EINVAL, "semantics");
-  if (o.batched != 0) return set_error(GFD_EUNSUPPORTED, "batched must be 0");
+  if (o.batched != 0 && o.batched != 1) return set_error(GFD_EINVAL, "batched must be 0 or 1");
   if (o.mem_budget_bytes < 0 || o.frontier_cap < 0 || o.violation_cap < 0) return set_error(GFD_EINVAL, "negative option");
   for (int32_t i = 0; i < num_specs; i++) {
-    int32_t rc = check_spec(g, specs[i], i);
+    const int32_t rc = check_spec(g, specs[i], i);
     if (rc) return rc;
     if (o.k_max > 0 && !results[i].violations) return set_error(GFD_EINVAL, "result %d: violations buffer is NULL", i);
   }
   if (stats) std::memset(stats, 0, sizeof *stats);
   if (num_specs == 0) return GFD_OK;
+  if (o.mem_budget_bytes && o.mem_budget_bytes < (int64_t(64) << 20))
+    return set_error(GFD_ENOMEM, "mem_budget_bytes below 64 MiB");
   const int K = o.k_max;
   Workspace* ws = nullptr;
   try {
-    int64_t per_slot = 0;
-    for (int i = 2; i < MAXK; i++) per_slot += 4 * i + 12;
-    if (o.mem_budget_bytes && o.mem_budget_bytes < 1024 * per_slot)
-      return set_error(GFD_ENOMEM, "mem_budget_bytes below %lld", (long long)(1024 * per_slot));
-    int64_t budget = o.mem_budget_bytes ? o.mem_budget_bytes : default_budget();
-    if (o.frontier_cap) budget = std::max<int64_t>(1024, o.frontier_cap) * per_slot;
+    const int64_t budget = o.mem_budget_bytes ? o.mem_budget_bytes : default_budget();
     ws = acquire_ws(g, budget);
-    ws->cap = ws->alloc_cap;
-    if (o.frontier_cap) ws->cap = std::min<uint64_t>(ws->alloc_cap, (uint64_t)o.frontier_cap);
-    uint64_t vsmall = o.violation_cap ? (uint64_t)o.violation_cap : 32768;
-    uint64_t vbig = o.violation_cap ? (uint64_t)o.violation_cap : (uint64_t)(4u << 20);
-    vsmall = std::max<uint64_t>(vsmall, (uint64_t)K + 1);
-    vbig = std::max<uint64_t>(vbig, (uint64_t)K + 64);
-    ensure_per_gfd(ws, (size_t)num_specs, vsmall, K);
+    if (ws->cpi_cap == 0) {
+      ws->cpi_cap = (uint64_t)std::max<int64_t>(1 << 20, std::min<int64_t>(budget / 16, int64_t(1) << 30) / 4);
+      ws->cpi_arena = dalloc<int32_t>(ws->cpi_cap);
+    }
+    const uint64_t vsmall = std::max<uint64_t>(o.violation_cap ? (uint64_t)o.violation_cap : 16384,
+                                               (uint64_t)K + 1);
+    const uint64_t vbig = std::max<uint64_t>(o.violation_cap ? (uint64_t)o.violation_cap : (4u << 20),
+                                             (uint64_t)K + 64);
     Ctx c{g, ws, (hipStream_t)o.hip_stream, o.semantics == GFD_SEM_INDUCED, K, Timer{}, stats,
-          stats ? ws->stat_bytes : nullptr};
+          stats ? ws->misc + 8 : nullptr};
     const uint32_t cls_mask = ((uint32_t)o.flags >> 8) & 0xFFu;
     c.tm.on = stats && ((o.flags & GFD_FLAG_TIMING) || cls_mask);
     c.tm.mask = cls_mask ? cls_mask : 0xFFu;
     c.tm.st = c.st;
-    if (stats) fill_u64(c.st, (uint64_t*)ws->stat_bytes, 0, 8);
-    std::vector<GfdState> S(num_specs);
-    for (int32_t i = 0; i < num_specs; i++) make_plan(g, specs[i], c.induced, S[i].plan);
-    HIPCHK(hipMemsetAsync(ws->scan.err, 0, 4, c.st));
-    fill_u64(c.st, ws->ctl, 0, (uint64_t)num_specs * CTL_WORDS);
-    const bool force_chunked = (o.flags & GFD_FLAG_FORCE_CHUNKED) != 0;
-    std::vector<char> redo(num_specs, force_chunked ? 1 : 0);
-    if (!force_chunked) {
-      for (int32_t i = 0; i < num_specs; i++) {
-        uint64_t* ctl = ws->ctl + (size_t)i * CTL_WORDS;
-        int32_t* vb = ws->vsmall + (size_t)i * ws->vsmall_cap * MAXK;
-        build_cpi(c, S[i]);
-        enumerate_fast(c, S[i], ctl, vb, vsmall);
-        if (K > 0)
-          c.tm.run(K_TOPK, [&] {
-            topk_small(c.st, vb, ctl + CTL_VCOUNT, vsmall, S[i].plan.k, K,
-                       ws->res + (size_t)i * ws->res_K * MAXK, (uint32_t*)(ctl + CTL_NEEDSEL));
-          });
-      }
-    }
-    HIPCHK(hipMemcpyAsync(ws->hctl, ws->ctl, sizeof(uint64_t) * CTL_WORDS * num_specs,
-                          hipMemcpyDeviceToHost, c.st));
-    HIPCHK(hipStreamSynchronize(c.st));
-    std::vector<uint64_t> H(ws->hctl, ws->hctl + (size_t)CTL_WORDS * num_specs);
-    for (int32_t i = 0; i < num_specs && !force_chunked; i++) {
-      const uint64_t* h = &H[(size_t)i * CTL_WORDS];
-      if ((h[CTL_FLAGS] & 3u) || h[CTL_VCOUNT] > vsmall) redo[i] = 1;
-    }
+    if (stats) fill_u64(c.st, (uint64_t*)(ws->misc + 8), 0, 8);
+    HIPCHK(hipMemsetAsync(ws->err, 0, 4, c.st));
+    // plans, capacities and batches
+    std::vector<Job> all(num_specs);
+    const int max_batch = o.batched ? 64 : 1;
+    const int64_t njobs_hint = std::min<int64_t>(num_specs, max_batch);
+    uint64_t cap_f = o.frontier_cap ? (uint64_t)o.frontier_cap
+                                    : (uint64_t)std::max<int64_t>(
+                                          4096, std::min<int64_t>(budget / (4 * njobs_hint), int64_t(2) << 30) /
+                                                    (int64_t)per_slot_bytes(MAXK));
     for (int32_t i = 0; i < num_specs; i++) {
-      uint64_t* ctl = ws->ctl + (size_t)i * CTL_WORDS;
-      int32_t* res = ws->res + (size_t)i * ws->res_K * MAXK;
-      const int k = S[i].plan.k;
-      if (redo[i]) {
-        if (stats) stats->chunked_gfds++;
-        ensure_vbig(ws, vbig);
-        build_cpi(c, S[i]);
-        enumerate_chunked(c, S[i], ctl, ws->hctl);
-        if (K > 0) {
-          c.tm.run(K_TOPK, [&] {
-            topk_small(c.st, ws->vbig, ctl + CTL_VCOUNT, ws->vbig_cap, k, K, res,
-                       (uint32_t*)(ctl + CTL_NEEDSEL));
-          });
+      all[i].spec = i;
+      make_plan(g, specs[i], c.induced, all[i].plan);
+      job_caps(g, all[i].plan, cap_f, vsmall, all[i].caps);
+    }
+    std::vector<std::vector<int>> batches;
+    {
+      std::vector<int> cur;
+      int64_t used = 0;
+      for (int32_t i = 0; i < num_specs; i++) {
+        const int64_t b = (int64_t)all[i].caps.bytes + 4096 * CTL_WORDS;
+        if (!cur.empty() && ((int)cur.size() >= max_batch || used + b > budget)) {
+          batches.push_back(cur);
+          cur.clear();
+          used = 0;
         }
-        HIPCHK(hipMemcpyAsync(&H[(size_t)i * CTL_WORDS], ctl, sizeof(uint64_t) * CTL_WORDS,
+        cur.push_back(i);
+        used += b;
+      }
+      if (!cur.empty()) batches.push_back(cur);
+    }
+    const bool force_bounded = (o.flags & GFD_FLAG_FORCE_CHUNKED) != 0;
+    std::vector<uint64_t> H((size_t)num_specs * CTL_WORDS);
+    std::vector<int32_t> hres((size_t)num_specs * std::max(K, 1) * MAXK);
+    uint64_t cpi_entries = 0;
+    for (const auto& bidx : batches) {
+      std::vector<Job> jobs;
+      for (int i : bidx) jobs.push_back(all[i]);
+      layout_batch(c, jobs);
+      std::vector<char> redo(jobs.size(), force_bounded ? 1 : 0);
+      if (!force_bounded) {
+        Recs R;
+        std::vector<Launch> L;
+        plan_batch(c, jobs, R, L, true);
+        upload_recs(c, R);
+        run_launches(c, L);
+        HIPCHK(hipMemcpyAsync(ws->hctl, jobs[0].mem.ctl, sizeof(uint64_t) * CTL_WORDS * jobs.size(),
                               hipMemcpyDeviceToHost, c.st));
+        unsigned long long cursor = 0;
+        HIPCHK(hipMemcpyAsync(&cursor, ws->misc, 8, hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipStreamSynchronize(c.st));
-        if (K > 0 && H[(size_t)i * CTL_WORDS + CTL_NEEDSEL]) {
-          select_first_k(c, ws->vbig, ctl + CTL_VCOUNT, ws->vbig_cap, k, ctl);
-          HIPCHK(hipMemcpyAsync(res, ws->sel_out, sizeof(int32_t) * K * k, hipMemcpyDeviceToDevice, c.st));
+        cpi_entries += cursor;
+        for (size_t x = 0; x < jobs.size(); x++) {
+          const uint64_t* h = ws->hctl + CTL_WORDS * x;
+          std::memcpy(&H[(size_t)jobs[x].spec * CTL_WORDS], h, sizeof(uint64_t) * CTL_WORDS);
+          if ((h[CTL_FLAGS] & 7u) || h[CTL_VCOUNT] > vsmall) redo[x] = 1;
         }
-      } else if (K > 0 && H[(size_t)i * CTL_WORDS + CTL_NEEDSEL]) {
-        int32_t* vb = ws->vsmall + (size_t)i * ws->vsmall_cap * MAXK;
-        select_first_k(c, vb, ctl + CTL_VCOUNT, vsmall, k, ctl);
-        HIPCHK(hipMemcpyAsync(res, ws->sel_out, sizeof(int32_t) * K * k, hipMemcpyDeviceToDevice, c.st));
+        // staged violations beyond one workgroup's sort: radix select
+        for (size_t x = 0; x < jobs.size(); x++) {
+          if (redo[x] || K == 0 || !H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL]) continue;
+          select_first_k(c, jobs[x].mem.vbuf, jobs[x].mem.ctl + CTL_VCOUNT, vsmall, jobs[x].plan.k,
+                         jobs[x].mem.ctl);
+          HIPCHK(hipMemcpyAsync(jobs[x].mem.res, ws->sel_out, sizeof(int32_t) * K * jobs[x].plan.k,
+                                hipMemcpyDeviceToDevice, c.st));
+        }
+        if (K > 0)
+          for (size_t x = 0; x < jobs.size(); x++)
+            if (!redo[x])
+              HIPCHK(hipMemcpyAsync(hres.data() + (size_t)jobs[x].spec * K * MAXK, jobs[x].mem.res,
+                                    sizeof(int32_t) * K * jobs[x].plan.k, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        if (stats)
+          for (size_t x = 0; x < jobs.size(); x++) {
+            if (redo[x]) continue;
+            const uint64_t* h = &H[(size_t)jobs[x].spec * CTL_WORDS];
+            for (int l = 1; l < MAXK; l++) {
+              stats->attempts += h[CTL_LEVEL_T + l];
+              if (l >= 2) stats->partials += h[CTL_LEVEL_N + l];
+            }
+            for (int u = 0; u < jobs[x].plan.k; u++)
+              stats->cpi_candidates += h[CTL_CAND + 2 * u + jobs[x].cur[u]];
+          }
+      }
+      for (size_t x = 0; x < jobs.size(); x++) {
+        if (!redo[x]) continue;
+        if (stats) stats->chunked_gfds++;
+        run_bounded(c, jobs[x], vbig);
+        HIPCHK(hipMemcpyAsync(&H[(size_t)jobs[x].spec * CTL_WORDS], jobs[x].mem.ctl,
+                              sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
+        if (K > 0)
+          HIPCHK(hipMemcpyAsync(hres.data() + (size_t)jobs[x].spec * K * MAXK, jobs[x].mem.res,
+                                sizeof(int32_t) * K * jobs[x].plan.k, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
       }
     }
-    // results
     uint32_t err = 0;
-    HIPCHK(hipMemcpyAsync(&err, ws->scan.err, 4, hipMemcpyDeviceToHost, c.st));
-    std::vector<int32_t> hres((size_t)num_specs * std::max(K, 1) * MAXK);
-    if (K > 0)
-      for (int32_t i = 0; i < num_specs; i++)
-        HIPCHK(hipMemcpyAsync(hres.data() + (size_t)i * K * MAXK, ws->res + (size_t)i * ws->res_K * MAXK,
-                              sizeof(int32_t) * K * S[i].plan.k, hipMemcpyDeviceToHost, c.st));
-    HIPCHK(hipStreamSynchronize(c.st));
+    HIPCHK(hipMemcpy(&err, ws->err, 4, hipMemcpyDeviceToHost));
     if (err) throw GfdError{GFD_EDEVICE, "scan look-back did not complete"};
     int32_t rc = GFD_OK;
     for (int32_t i = 0; i < num_specs; i++) {
@@ -1183,23 +1508,22 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       r.num_reported = (int32_t)std::min<uint64_t>((uint64_t)K, r.violation_count);
       if (K > 0 && r.num_reported)
         std::memcpy(r.violations, hres.data() + (size_t)i * K * MAXK,
-                    sizeof(int32_t) * r.num_reported * S[i].plan.k);
+                    sizeof(int32_t) * r.num_reported * specs[i].num_vertices);
       if ((r.match_count >> 63) || (r.violation_count >> 63))
         rc = set_error(GFD_EOVERFLOW, "spec %d: counter passed 2^63", i);
-      if (stats) {
-        for (int l = 1; l < MAXK; l++) {
-          if (!redo[i]) stats->attempts += h[CTL_LEVEL_T + l];
-          if (!redo[i] && l >= 2) stats->partials += h[CTL_LEVEL_N + l];
-        }
-      }
     }
     if (stats) {
       unsigned long long hb[8];
-      HIPCHK(hipMemcpy(hb, ws->stat_bytes, sizeof hb, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(hb, ws->misc + 8, sizeof hb, hipMemcpyDeviceToHost));
       for (int j = 0; j < 8; j++) stats->class_bytes[j] = hb[j];
+      stats->cpi_entries = cpi_entries;
       if (c.tm.on) c.tm.collect(stats->class_ms);
-      for (int j = 0; j < 8; j++) { stats->class_launches[j] = c.tm.launches[j]; stats->launches += c.tm.launches[j]; }
-      stats->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+      for (int j = 0; j < 8; j++) {
+        stats->class_launches[j] = c.tm.launches[j];
+        stats->launches += c.tm.launches[j];
+      }
+      stats->wall_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
     release_ws(g, ws);
     return rc;

@@ -1,5 +1,10 @@
 // Internal declarations shared by the host driver (gfd_api.hip) and the
 // kernels (gfd_kernels.hip).  Not part of the public ABI.
+//
+// Every kernel works on a batch of independent jobs (one per GFD): the grid is
+// (x tiles, jobs); block row y reads its job's parameters from a device array.
+// Within a job, work is spread evenly over the x blocks by a prefix over the
+// job's items and a load-balanced search, so power-law hubs do not serialise.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -8,13 +13,14 @@ namespace gfd {
 
 constexpr int MAXK = 8;
 constexpr int MAXLIT = 8;
+constexpr int MAXCONS = 2 * (MAXK - 1);  // pull constraints on one pattern vertex
 constexpr int32_t ABSENT = -1;
 constexpr int32_t ANY = -1;
 constexpr int32_t NOEDGE = -2;
 
 // Constraint on one direction of one vertex pair, checked by a probe:
-//   >= 0     a data edge with exactly this label must exist
-//   ANY      a data edge with any label must exist
+//   >= 0       a data edge with exactly this label must exist
+//   ANY        a data edge with any label must exist
 //   PC_ABSENT  no data edge may exist (induced reading, no pattern edge)
 //   PC_FREE    no constraint (non-induced reading, no pattern edge)
 constexpr int32_t PC_ABSENT = -2;
@@ -45,144 +51,151 @@ struct DevGraph {
   const int32_t* lab_vtx;   // [n], vertices grouped by label, ascending ids
 };
 
+// A candidate set C(u): its members (list, *cnt), their positions in the list
+// (pos[x], meaningful for members only) and an n-bit membership bitmap, small
+// enough to stay in L2 (512 KB for 4M vertices).
+struct CandSet {
+  const int32_t* list;
+  const uint64_t* cnt;
+  const int32_t* pos;    // [n]
+  const uint32_t* bits;  // [ceil(n/32)]
+};
+
+// Prefix over one job's items, computed by a single-pass scan with a
+// decoupled look-back (per-job tile states and ticket).
+struct JobScan {
+  uint64_t* P;         // exclusive prefix [items+1]
+  uint64_t* d_total;
+  uint64_t* tstate;    // [tiles]
+  uint32_t* ticket;    // zero at rest
+  uint32_t* err;
+  uint32_t epoch;
+};
+
+// Pull constraint: v passes when some x adjacent to v (out-row if dir == 0,
+// in-row if dir == 1) through an edge of label elab (ANY = any) is in C(w).
+struct PullC {
+  int32_t dir, elab;
+  CandSet w;
+};
+
+// Candidate filter of one pattern vertex u (Section IV-B: label candidates,
+// degree filter, and the BFS candidate-subgraph / dead-end conditions).
+struct FilterJob {
+  int32_t active;
+  int32_t ncons;
+  int32_t min_out, min_in;
+  const int32_t* list;   // items: nullptr = identity 0..n_host-1
+  const uint64_t* d_n;   // device item count (nullptr: n_host)
+  uint64_t n_host, cap;  // cap bounds the item count
+  PullC cons[MAXCONS];
+  uint32_t* hits;        // [cap], bit c set when constraint c is met
+  JobScan sc;            // over (constraint, item) pairs
+  int32_t* out;          // the new C(u): list, count (atomic cursor), positions, bits
+  uint64_t* d_out_n;
+  int32_t* pos;
+  uint32_t* bits;        // cleared by filter_clear before the compaction
+  uint64_t nwords;
+  unsigned long long* bytes;
+};
+
+// CPI adjacency for spanning-tree edge (p, u): for each v_p in C(p) the
+// neighbours v (row direction dir) in C(u) through an edge of label prim whose
+// reverse direction satisfies `other`.  The list of the i-th member of C(p) is
+// arena[beg[i] .. beg[i] + len[i]).
+struct CpiJob {
+  int32_t active;
+  int32_t dir, prim, other;
+  CandSet p, u;
+  uint64_t cap_p;
+  uint32_t* beg;
+  uint32_t* len;
+  uint32_t* cur;
+  int32_t* arena;
+  unsigned long long* arena_cursor;
+  uint64_t arena_cap;
+  uint32_t* flags;       // bit 2: arena overflow
+  JobScan sc;            // over rows of C(p)
+  unsigned long long* bytes;
+};
+
 struct DevLit {
   int32_t kind;  // 0 const, 1 var
   int32_t pos, attr, pos2, attr2, value;  // pos/pos2: matching-order positions
 };
 
-// Arguments of the enumeration kernels: extend level i (i bound vertices) by
-// the vertex at matching-order position i.
-struct ExtArgs {
-  DevGraph g;
-  // source frontier: column j (j < i) at src_cols + j * src_stride
-  const int32_t* src_cols;
+// One enumeration level of one job: extend partial matches of i vertices by
+// the vertex at matching-order position i (Section IV-B, matching over the
+// CPI); the last level evaluates X -> Y on every match (Section II).
+struct ExtJob {
+  int32_t active, i, last, k;
+  const int32_t* src_cols;  // column j (j < i) at src_cols + j * src_stride
   uint64_t src_stride;
-  const uint64_t* d_nsrc;  // sources (device count), clamped to src_cap
+  const uint64_t* d_nsrc;
   uint64_t src_cap;
-  const uint64_t* P;       // exclusive prefix of candidate-list lengths [nsrc+1]
-  const uint32_t* beg;     // CPI list start per source
-  const int32_t* cpi_ent;  // CPI entries (vertex ids)
-  unsigned long long* bytes;  // optional algorithmic-byte counter
-  uint64_t a_begin, a_end; // attempt window (a_end clamped to P[nsrc])
-  int32_t i;               // position being bound
+  int32_t par_pos;          // position of the spanning-tree parent
+  const int32_t* par_posmap;  // C(parent) positions
+  const uint32_t* cpi_beg;
+  const uint32_t* cpi_len;
+  const int32_t* cpi_ent;
+  uint32_t* begs;           // [src_cap] list start per source
+  JobScan sc;               // over sources
+  uint64_t a_begin, a_end;  // attempt window
   int32_t nchk;
   int32_t chk_pos[MAXK];
-  int32_t chk_fwd[MAXK];   // constraint on data edge h(x_pos) -> v
-  int32_t chk_bwd[MAXK];   // constraint on data edge v -> h(x_pos)
-  // inner levels
+  int32_t chk_fwd[MAXK];    // constraint on data edge h(x_pos) -> v
+  int32_t chk_bwd[MAXK];    // constraint on data edge v -> h(x_pos)
   int32_t* dst_cols;
   uint64_t dst_cap;
   uint64_t* d_ndst;
-  uint32_t* d_flags;       // bit0: frontier overflow; bit1: violation buffer overflow
-  // last level
-  int32_t k;
-  int32_t var_pos[MAXK];   // matching-order position of variable x_v
-  int32_t nx, ny, y_false;
-  DevLit lit[2 * MAXLIT];  // X literals then Y literals
+  uint32_t* flags;          // bit0: frontier overflow; bit1: violation staging overflow
+  int32_t var_pos[MAXK];
+  int32_t nx, ny, y_false, collect_only;
+  DevLit lit[2 * MAXLIT];
   unsigned long long* counters;  // [4] match, violation, match_fp, violation_fp
-  int32_t* vbuf;           // violation staging [vcap * k], tuples in variable order
+  int32_t* vbuf;
   uint64_t* d_vcount;
   uint64_t vcap;
-  const int32_t* thr;      // threshold tuple (variable order)
+  const int32_t* thr;
   const uint32_t* d_thr_valid;
-  int32_t collect_only;    // 1: only stage tuples, do not touch counters
-};
-
-// Launch wrappers (gfd_kernels.hip).  All are asynchronous on `st`.
-struct ScanWs {
-  uint64_t* tile_state;  // [max tiles]
-  uint32_t* ticket;      // zero at rest
-  uint32_t* err;
-  uint32_t epoch;        // host side, bumped per launch
-  uint64_t max_tiles;
-};
-
-// Scan enumeration sources: list length of each partial's parent CPI list.
-void scan_sources(hipStream_t st, ScanWs& ws, const int32_t* par_col, const uint64_t* d_n,
-                  uint64_t cap, const int32_t* pos_map, const uint32_t* cpi_beg,
-                  const uint32_t* cpi_len, uint32_t* beg, uint64_t* P, uint64_t* d_total);
-
-// Decoupled look-back state of one scan launch.
-struct TileScan {
-  uint64_t* state;
-  uint32_t* ticket;
-  uint32_t* err;
-  uint32_t epoch;
-};
-
-// A vertex v passes a pull constraint when some x adjacent to v (out-row if
-// dir == 0, in-row if dir == 1) through an edge of label elab (ANY = any) is a
-// member of another pattern vertex's candidate set (mem[x] == ep).
-struct PullCons {
-  int32_t dir;
-  int32_t elab;
-  const uint8_t* mem;
-  uint32_t ep;
-};
-
-// Candidate filter (Section IV-B: label candidates, degree filter, and the
-// BFS candidate-subgraph / dead-end conditions), compacted in one pass into a
-// set in no fixed order (*d_out_n must be zero at launch).
-struct CandArgs {
-  DevGraph g;
-  const int32_t* list;   // nullptr: identity 0..n_host-1
-  const uint64_t* d_n;   // device count (nullptr: n_host)
-  uint64_t n_host, cap;
-  int32_t min_out, min_in;
-  int32_t ncons;
-  PullCons cons[2 * MAXK];
-  int32_t* out;
-  uint64_t* d_out_n;     // atomic output counter
-  uint8_t* mem;          // mem[v] = mem_ep for kept v
-  uint32_t mem_ep;
-  int32_t* posmap;       // optional: posmap[v] = index of v in out
-  unsigned long long* bytes;  // optional algorithmic-byte counter
-};
-void cand_filter(hipStream_t st, const CandArgs& a, int grid);
-
-// CPI adjacency N_u^p(v_p) for spanning-tree edge (p, u): for each v_p in C(p)
-// the neighbours v (row direction dir) with mem[v] == ep, edge label prim and
-// the reverse direction satisfying `other`.  List of the i-th candidate of p:
-// cpi_ent[cpi_beg[i] .. cpi_beg[i] + cpi_len[i]) (*d_entries zero at launch).
-struct CpiArgs {
-  DevGraph g;
-  int32_t dir;
-  const int32_t* list;
-  const uint64_t* d_n;
-  uint64_t cap;
-  int32_t prim, other;
-  const uint8_t* mem;
-  uint32_t ep;
-  uint32_t* cpi_beg;     // [|C(p)|]
-  uint32_t* cpi_len;     // [|C(p)|]
-  int32_t* cpi_ent;
-  uint64_t* d_entries;   // atomic entry counter
   unsigned long long* bytes;
 };
-void cpi_adjacency(hipStream_t st, const CpiArgs& a, int grid);
 
-// Enumeration: one attempt window over a scanned frontier (P, beg), every
-// attempt of the window mapped to its source by load-balanced search.
-void extend(hipStream_t st, const ExtArgs& a, bool last, int grid);
-void single_vertex(hipStream_t st, const ExtArgs& a, const int32_t* list, const uint64_t* d_n,
-                   uint64_t cap, int grid);
+struct TopkJob {
+  int32_t active, k, K;
+  const int32_t* vbuf;
+  const uint64_t* d_vcount;
+  uint64_t vcap;
+  int32_t* res;
+  uint32_t* d_need_select;
+};
 
-// Top-K
-// Sort the staged tuples when count <= SORT_MAX, writing the first min(K,count)
-// to `res`; otherwise sets *d_need_select = 1.
-void topk_small(hipStream_t st, const int32_t* vbuf, const uint64_t* d_vcount, uint64_t vcap,
-                int k, int K, int32_t* res, uint32_t* d_need_select);
-// Radix select: find the K-th smallest tuple of vbuf[0..count) (count > K).
-// state: [k + 2] words (prefix tuple, remaining rank, pass); hist: [RADIX_BINS].
+// Launch wrappers (gfd_kernels.hip).  All asynchronous on `st`; `jobs` points
+// to `njobs` device-resident job records; gx = blocks per job.
+void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
+void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
+void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
+// zero the output bitmap of every active job
+void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx);
+void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
+void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
+void cpi_alloc(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
+void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
+void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx);
+void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx, bool last);
+// k == 1: every member of the root's candidate set is a match.
+void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx);
+void topk_small(hipStream_t st, const TopkJob* jobs, int njobs);
+
+// Radix select of the K-th smallest staged tuple (one job, host driven).
+// state: [MAXK + 1] words; hist: [RADIX_BINS], zero at rest.
 void select_begin(hipStream_t st, uint32_t* state, int K);
 void select_pass(hipStream_t st, const int32_t* vbuf, const uint64_t* d_vcount, uint64_t vcap,
-                 int k, int word, int shift, int bits, uint32_t* state, uint32_t* hist,
-                 int grid);
-// Keep tuples <= threshold (state prefix) in vbuf order into out; exactly K.
-void select_compact(hipStream_t st, const int32_t* vbuf, const uint64_t* d_vcount,
-                    uint64_t vcap, int k, const uint32_t* state, int32_t* out,
-                    uint64_t* d_outcount, int grid);
-// Sort exactly n_host (<= SORT_MAX) tuples in place.
+                 int k, int word, int shift, int bits, uint32_t* state, uint32_t* hist, int grid);
+// Tuples <= the selected threshold into out (exactly K of them).
+void select_compact(hipStream_t st, const int32_t* vbuf, const uint64_t* d_vcount, uint64_t vcap,
+                    int k, const uint32_t* state, int32_t* out, uint64_t* d_outcount, int grid);
+// Sort *d_n (<= SORT_MAX) tuples in place.
 void sort_tuples(hipStream_t st, int32_t* buf, const uint64_t* d_n, int k);
 
 void fill_u8(hipStream_t st, uint8_t* p, uint8_t v, uint64_t n);

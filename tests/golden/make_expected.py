@@ -28,8 +28,14 @@ def main(names, K=1024, threads=os.cpu_count() or 1):
             t = time.time()
             out["results"][sem] = [O.validate(og, d, sem, K=K, threads=threads) for d in gfds]
             print(name, sem, f"{time.time() - t:.1f}s", flush=True)
-        with open(os.path.join(HERE, f"expected_{name}.json"), "w") as f:
-            json.dump(out, f, separators=(",", ":"))
+        text = json.dumps(out, separators=(",", ":"))
+        if len(text) > 1 << 20:  # large result sets are stored compressed
+            import gzip
+            with gzip.open(os.path.join(HERE, f"expected_{name}.json.gz"), "wt") as f:
+                f.write(text)
+        else:
+            with open(os.path.join(HERE, f"expected_{name}.json"), "w") as f:
+                f.write(text)
 
 
 if __name__ == "__main__":

@@ -187,23 +187,44 @@ def test_errors(P):
     gh.free()
 
 
+def test_batched_matches_oracle(P):
+    """Many GFDs of uneven size in one batched call (one launch per kernel per phase)."""
+    g = random_graph(13, 1500, 15000, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=4,
+                     absent_frac=0.1)
+    rng = np.random.default_rng(13)
+    gfds = [random_gfd(1300 + j, int(rng.integers(1, 7)), n_vlabels=2, n_elabels=2, n_attrs=2,
+                       attr_values=4, wildcard_frac=0.15, extra_edge_frac=0.3)
+            for j in range(24)]
+    gh = P.load(g)
+    for sem in SEMS:
+        _check(P, g, gfds, sem, K=40, gh=gh, batched=True)
+        _check(P, g, gfds, sem, K=40, gh=gh, batched=True, frontier_cap=500, violation_cap=100)
+    gh.free()
+
+
 def _expected(name):
-    return json.load(open(os.path.join(GOLDEN, f"expected_{name}.json")))
+    path = os.path.join(GOLDEN, f"expected_{name}.json")
+    if os.path.exists(path):
+        return json.load(open(path))
+    import gzip
+    with gzip.open(path + ".gz", "rt") as f:
+        return json.load(f)
 
 
 @pytest.mark.slow
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("name", ["powerlaw_1m", "kg_4m"])
+@pytest.mark.parametrize("name", ["powerlaw_1m", "kg_4m", "kg_4m_batch256"])
 def test_full_size_configs(P, name):
     """Full-size workloads in the benchmark's launch configuration, against
     oracle results stored by tests/golden/make_expected.py."""
     exp = _expected(name)
-    g = configs.graph(name)
+    g = configs.graph(configs.CONFIG_GRAPH[name])
     assert g.sha256() == exp["graph_sha256"], "generated graph differs from the stored one"
     gfds = exp["gfds"]
     gh = P.load(g)
     for sem in SEMS:
-        got = P.validate(gh, gfds, K=exp["K"], semantics=sem)
-        for i, (r, e) in enumerate(zip(got, exp["results"][sem])):
-            assert r == e, (name, sem, i)
+        for batched in ((True,) if len(gfds) > 64 else (False, True)):
+            got = P.validate(gh, gfds, K=exp["K"], semantics=sem, batched=batched)
+            for i, (r, e) in enumerate(zip(got, exp["results"][sem])):
+                assert r == e, (name, sem, batched, i)
     gh.free()
