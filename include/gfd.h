@@ -128,7 +128,8 @@ typedef struct {
 typedef struct {
   double wall_ms;             /* host wall time of the call */
   int32_t launches;           /* kernels launched */
-  int32_t chunked_gfds;       /* GFDs that needed the chunked (budgeted) path */
+  int32_t chunked_gfds;       /* GFDs that needed the chunked (budgeted) path: a
+                                 frontier or the CPI entry arena overflowed */
   uint64_t attempts;          /* extension attempts over all enumeration levels */
   uint64_t partials;          /* partial matches written over all levels */
   uint64_t cpi_candidates;    /* sum of final candidate-set sizes */
@@ -140,6 +141,10 @@ typedef struct {
   double class_ms[8];         /* summed HIP event time (GFD_FLAG_TIMING) */
   uint64_t class_bytes[8];    /* algorithmic bytes of that class (bytes each item
                                 must touch, counted on the device) */
+  int32_t threshold_gfds;     /* GFDs whose violation staging overflowed: their last
+                                 enumeration level ran again, collecting only the
+                                 violations up to a bound on the K-th smallest */
+  int32_t threshold_passes;   /* such re-runs (one launch each for all those GFDs) */
 } gfd_stats;
 
 /* Load a graph given as out-CSR on the host.  Inputs are read and copied: the

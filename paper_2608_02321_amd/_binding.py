@@ -73,7 +73,8 @@ class gfd_stats(C.Structure):
                 ("attempts", C.c_uint64), ("partials", C.c_uint64),
                 ("cpi_candidates", C.c_uint64), ("cpi_entries", C.c_uint64),
                 ("class_launches", C.c_int32 * 8), ("class_ms", C.c_double * 8),
-                ("class_bytes", C.c_uint64 * 8)]
+                ("class_bytes", C.c_uint64 * 8), ("threshold_gfds", C.c_int32),
+                ("threshold_passes", C.c_int32)]
 
 
 class gfd_graph_info(C.Structure):

@@ -87,6 +87,9 @@ enum {
   CTL_THR = 48 /* 4 words = 8 int32 */
 };
 
+constexpr int SEL_JOBS = 64;         // jobs per batched selection (= largest batch)
+constexpr int SEL_STATE_WORDS = 16;
+
 struct Workspace {
   uint8_t* arena = nullptr;         // per-job regions of the current batch
   size_t arena_bytes = 0;
@@ -106,15 +109,19 @@ struct Workspace {
   size_t chunk_bytes = 0;
   int32_t* vbig = nullptr;
   uint64_t vbig_cap = 0;
-  uint32_t* sel_state = nullptr;
-  uint32_t* sel_hist = nullptr;
-  int32_t* sel_out = nullptr;
+  // batched radix select: per-job state and histograms, records
+  uint32_t* sel_state = nullptr;    // [SEL_JOBS * SEL_STATE_WORDS]
+  uint32_t* sel_hist = nullptr;     // [SEL_JOBS * RADIX_BINS], zero at rest
+  int32_t* sel_out = nullptr;       // [SORT_MAX * MAXK]
+  uint8_t* selrec = nullptr;        // [SEL_JOBS] SelJob records
+  uint8_t* hselrec = nullptr;       // pinned staging for them
   int64_t budget = 0;
 
   ~Workspace() {
     dfree(arena); dfree(cpi_arena); dfree(jobrec); dfree(misc); dfree(err); dfree(chunk);
-    dfree(vbig); dfree(sel_state); dfree(sel_hist); dfree(sel_out);
+    dfree(vbig); dfree(sel_state); dfree(sel_hist); dfree(sel_out); dfree(selrec);
     if (hjobrec) (void)hipHostFree(hjobrec);
+    if (hselrec) (void)hipHostFree(hselrec);
     if (hctl) (void)hipHostFree(hctl);
   }
 };
@@ -576,6 +583,8 @@ struct Job {
   JobCaps caps;
   JobMem mem;
   int cur[MAXK];  // which candidate buffer holds C(u) at the current step
+  size_t last_rec = SIZE_MAX;  // offset of its last-level record in the batch's records
+  bool last_single = false;    // that record is a single-vertex (k == 1) one
 };
 
 static int pattern_edges_between(const Plan& p, int u, const std::vector<int>& nbrs) {
@@ -699,6 +708,12 @@ static int gx_for(uint64_t items, int njobs, int cap = 256) {
   const int per_job = std::max(8, std::min(cap, 4096 / std::max(1, njobs)));
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)per_job));
 }
+// blocks per job for flat (load-balanced) work over `items` positions
+static int gx_flat(uint64_t items, int njobs, int cap = 256) {
+  const uint64_t want = (items + LBS_CHUNK - 1) / LBS_CHUNK;
+  const int per_job = std::max(8, std::min(cap, 4096 / std::max(1, njobs)));
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)per_job));
+}
 static int gx_scan(uint64_t items) {
   const uint64_t t = (items + SCAN_TILE - 1) / SCAN_TILE;
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(t, 64));
@@ -795,7 +810,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       for (int q = 0; q < f.ncons; q++) pull_ub = std::max(pull_ub, rows_ub(g, p.qlab[u], f.cons[q].dir));
       any_cons |= f.ncons > 0;
     }
-    L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), gx_for(pull_ub, nj), gx_for(items, nj),
+    L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), gx_flat(pull_ub, nj), gx_for(items, nj),
                        gx_for((uint64_t)g->n / 32 + 1, nj, 64), any_cons, false, false});
   }
   // bottom-up, reverse BFS order: drop dead ends
@@ -833,7 +848,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       any = true;
     }
     if (any)
-      L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), gx_for(pull_ub, nj), gx_for(items, nj),
+      L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), gx_flat(pull_ub, nj), gx_for(items, nj),
                          gx_for((uint64_t)g->n / 32 + 1, nj, 64), true, false, false});
   }
   // CPI adjacency lists per spanning-tree edge, in BFS order
@@ -870,7 +885,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       any = true;
     }
     if (any)
-      L.push_back(Launch{1, R.add(C), nj, gx_scan(items), gx_for(rows, nj), gx_for(items, nj), 0,
+      L.push_back(Launch{1, R.add(C), nj, gx_scan(items), gx_flat(rows, nj), gx_for(items, nj), 0,
                          true, false, false});
   }
   if (!fast_enum) return;
@@ -940,7 +955,10 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       any_last |= e.last != 0;
       any_inner |= e.last == 0;
     }
-    L.push_back(Launch{2, R.add(E), nj, gx_scan(srcs), gx_for(1u << 30, nj), 0, 0, true, any_last,
+    const size_t off = R.add(E);
+    for (int x = 0; x < nj; x++)
+      if (E[x].active && E[x].last) jobs[x].last_rec = off + sizeof(ExtJob) * x;
+    L.push_back(Launch{2, off, nj, gx_scan(srcs), gx_flat(1ull << 40, nj), 0, 0, true, any_last,
                        any_inner});
   }
   // single-vertex patterns
@@ -978,7 +996,15 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       items = std::max(items, e.src_cap);
       any = true;
     }
-    if (any) L.push_back(Launch{3, R.add(E), nj, 0, gx_for(items, nj), 0, 0, false, true, false});
+    if (any) {
+      const size_t off = R.add(E);
+      for (int x = 0; x < nj; x++)
+        if (E[x].active) {
+          jobs[x].last_rec = off + sizeof(ExtJob) * x;
+          jobs[x].last_single = true;
+        }
+      L.push_back(Launch{3, off, nj, 0, gx_for(items, nj), 0, 0, false, true, false});
+    }
   }
   if (c.K > 0) {
     std::vector<TopkJob> T(nj);
@@ -1101,27 +1127,61 @@ static void ensure_vbig(Workspace* ws, uint64_t vcap) {
   ws->vbig_cap = vcap;
 }
 
-// Radix select of the K-th smallest staged tuple, then the first K sorted into
-// ws->sel_out.  Requires count > K.
-static void select_first_k(Ctx& c, const int32_t* vbuf, const uint64_t* d_vcount, uint64_t vcap,
-                           int k, uint64_t* ctl) {
+// Batched radix select over the jobs in S (at most SEL_JOBS; each with more
+// than K staged tuples).  threshold == false: the first K of each job, sorted,
+// into S[j].out.  threshold == true: the K-th tuple becomes the job's staging
+// threshold (inclusive) and its staging count restarts at zero.
+static void run_select(Ctx& c, std::vector<SelJob>& S, bool threshold) {
   Workspace* ws = c.ws;
-  c.tm.run(K_TOPK, [&] { select_begin(c.st, ws->sel_state, c.K); });
-  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((vcap + BS - 1) / BS, 1024));
-  for (int w = 0; w < k; w++) {
-    const int shifts[3] = {21, 10, 0}, bits[3] = {11, 11, 10};
-    for (int ps = 0; ps < 3; ps++)
-      c.tm.run(K_TOPK, [&] {
-        select_pass(c.st, vbuf, d_vcount, vcap, k, w, shifts[ps], bits[ps], ws->sel_state,
-                    ws->sel_hist, grid);
-      });
+  const int nj = (int)S.size();
+  if (nj == 0) return;
+  if (nj > SEL_JOBS) throw GfdError{GFD_EINVAL, "internal: selection batch too large"};
+  int maxk = 0;
+  uint64_t maxcap = 1;
+  for (int j = 0; j < nj; j++) {
+    S[j].state = ws->sel_state + (size_t)j * SEL_STATE_WORDS;
+    S[j].hist = ws->sel_hist + (size_t)j * RADIX_BINS;
+    if (S[j].active) {
+      maxk = std::max(maxk, S[j].k);
+      maxcap = std::max(maxcap, S[j].vcap);
+    }
   }
-  fill_u64(c.st, ctl + CTL_OUTCOUNT, 0, 1);
-  c.tm.run(K_TOPK, [&] {
-    select_compact(c.st, vbuf, d_vcount, vcap, k, ws->sel_state, ws->sel_out, ctl + CTL_OUTCOUNT,
-                   grid);
-  });
-  c.tm.run(K_TOPK, [&] { sort_tuples(c.st, ws->sel_out, ctl + CTL_OUTCOUNT, k); });
+  HIPCHK(hipStreamSynchronize(c.st));  // the pinned staging is reused per call
+  std::memcpy(ws->hselrec, S.data(), sizeof(SelJob) * nj);
+  HIPCHK(hipMemcpyAsync(ws->selrec, ws->hselrec, sizeof(SelJob) * nj, hipMemcpyHostToDevice, c.st));
+  const SelJob* r = (const SelJob*)ws->selrec;
+  const int gx = (int)std::max<uint64_t>(
+      1, std::min<uint64_t>((maxcap + BS - 1) / BS, (uint64_t)std::max(4, 1024 / nj)));
+  c.tm.run(K_TOPK, [&] { sel_begin(c.st, r, nj); });
+  const int shifts[3] = {21, 10, 0}, bits[3] = {11, 11, 10};
+  for (int w = 0; w < maxk; w++)
+    for (int ps = 0; ps < 3; ps++)
+      c.tm.run(K_TOPK, [&] { sel_pass(c.st, r, nj, w, shifts[ps], bits[ps], gx); });
+  if (threshold) c.tm.run(K_TOPK, [&] { sel_threshold(c.st, r, nj); });
+  else c.tm.run(K_TOPK, [&] { sel_first_k(c.st, r, nj, gx); });
+}
+
+static SelJob sel_job(Ctx& c, int k, const int32_t* vbuf, uint64_t* ctl, uint64_t vcap) {
+  SelJob s{};
+  s.active = 1;
+  s.k = k;
+  s.K = c.K;
+  s.d_vcount = ctl + CTL_VCOUNT;
+  s.vbuf = vbuf;
+  s.vcap = vcap;
+  s.d_outcount = (unsigned long long*)(ctl + CTL_OUTCOUNT);
+  s.thr = (int32_t*)(ctl + CTL_THR);
+  s.d_thr_valid = (uint32_t*)(ctl + CTL_THRVALID);
+  s.flags = (uint32_t*)(ctl + CTL_FLAGS);
+  return s;
+}
+
+// First K of one job's staged tuples, sorted, into ws->sel_out.  Requires
+// count > K.
+static void select_first_k(Ctx& c, const int32_t* vbuf, uint64_t vcap, int k, uint64_t* ctl) {
+  std::vector<SelJob> S{sel_job(c, k, vbuf, ctl, vcap)};
+  S[0].out = c.ws->sel_out;
+  run_select(c, S, false);
 }
 
 // Bounded path for one job whose fast pass overflowed: the frontier of every
@@ -1148,7 +1208,7 @@ struct Bounded {
     const int k = J.plan.k;
     const uint64_t vc = rd(CTL_VCOUNT);
     if (vc + incoming <= ws->vbig_cap || vc <= (uint64_t)c.K) return;
-    select_first_k(c, ws->vbig, J.mem.ctl + CTL_VCOUNT, ws->vbig_cap, k, J.mem.ctl);
+    select_first_k(c, ws->vbig, ws->vbig_cap, k, J.mem.ctl);
     // keep the first K; the K-th becomes the staging threshold
     HIPCHK(hipMemcpyAsync(ws->vbig, ws->sel_out, sizeof(int32_t) * c.K * k,
                           hipMemcpyDeviceToDevice, c.st));
@@ -1175,6 +1235,7 @@ struct Bounded {
     e.vcap = c.K > 0 ? c.ws->vbig_cap : 0;
     e.thr = (const int32_t*)(J.mem.ctl + CTL_THR);
     e.d_thr_valid = (const uint32_t*)(J.mem.ctl + CTL_THRVALID);
+    e.thr_incl = 0;  // the first K are kept apart; later tuples must precede the K-th
     return e;
   }
   void level(int i) {
@@ -1228,7 +1289,7 @@ struct Bounded {
       e.a_begin = A0;
       e.a_end = A1;
       upload_one(e);
-      const int gx = (int)std::max<uint64_t>(1, std::min<uint64_t>((A1 - A0 + BS - 1) / BS, 1024));
+      const int gx = (int)std::max<uint64_t>(1, std::min<uint64_t>((A1 - A0 + LBS_CHUNK - 1) / LBS_CHUNK, 1024));
       c.tm.run(e.last ? K_LAST : K_EXT, [&] { ext_run(c.st, g, rec, 1, gx, e.last != 0); });
       if (!e.last) {
         const uint64_t N = rd(CTL_LEVEL_N + i + 1);
@@ -1303,12 +1364,82 @@ static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
     HIPCHK(hipMemcpyAsync(ws->hctl, B.mem.ctl, sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
     HIPCHK(hipStreamSynchronize(c.st));
     if (ws->hctl[CTL_NEEDSEL]) {
-      select_first_k(c, ws->vbig, B.mem.ctl + CTL_VCOUNT, ws->vbig_cap, B.plan.k, B.mem.ctl);
+      select_first_k(c, ws->vbig, ws->vbig_cap, B.plan.k, B.mem.ctl);
       HIPCHK(hipMemcpyAsync(B.mem.res, ws->sel_out, sizeof(int32_t) * c.K * B.plan.k,
                             hipMemcpyDeviceToDevice, c.st));
     }
   }
   J.mem = B.mem;
+}
+
+// Jobs whose fast pass overflowed only the violation staging: their counts
+// and fingerprints are exact, only the first K are missing.  The K-th smallest
+// staged tuple bounds the K-th smallest violation from above, so the last
+// level is run again over its kept frontier, collecting only violations up to
+// that threshold; repeated (each pass strictly lowers the threshold) until the
+// collected ones fit.  Every pass is one launch for all such jobs of a batch.
+// Leaves each finished job's control block in ws->hctl; jobs still over after
+// the pass limit go to the bounded path (redo).
+static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> over, const Recs& R,
+                              uint64_t vsmall, std::vector<char>& redo) {
+  Workspace* ws = c.ws;
+  const DevGraph& g = c.g->dg;
+  for (int pass = 0; !over.empty(); pass++) {
+    if (pass == 8) {
+      for (int x : over) redo[x] = 1;
+      return;
+    }
+    std::vector<SelJob> S;
+    for (int x : over) S.push_back(sel_job(c, jobs[x].plan.k, jobs[x].mem.vbuf, jobs[x].mem.ctl, vsmall));
+    run_select(c, S, true);
+    // last-level records in collect-only form, multi-vertex and single-vertex
+    std::vector<ExtJob> E[2];
+    for (int x : over) {
+      ExtJob e;
+      std::memcpy(&e, R.blob.data() + jobs[x].last_rec, sizeof e);
+      e.collect_only = 1;
+      e.thr = (const int32_t*)(jobs[x].mem.ctl + CTL_THR);
+      e.thr_incl = 1;
+      E[jobs[x].last_single ? 1 : 0].push_back(e);
+    }
+    const size_t b0 = align_up(sizeof(ExtJob) * E[0].size());
+    const size_t bytes = b0 + sizeof(ExtJob) * E[1].size() + sizeof(TopkJob) * over.size();
+    ensure_recs(ws, bytes);
+    HIPCHK(hipStreamSynchronize(c.st));
+    std::memcpy(ws->hjobrec, E[0].data(), sizeof(ExtJob) * E[0].size());
+    std::memcpy(ws->hjobrec + b0, E[1].data(), sizeof(ExtJob) * E[1].size());
+    std::vector<TopkJob> T;
+    for (int x : over)
+      T.push_back(TopkJob{1, jobs[x].plan.k, c.K, jobs[x].mem.vbuf, jobs[x].mem.ctl + CTL_VCOUNT,
+                          vsmall, jobs[x].mem.res, (uint32_t*)(jobs[x].mem.ctl + CTL_NEEDSEL)});
+    const size_t bt = b0 + sizeof(ExtJob) * E[1].size();
+    std::memcpy(ws->hjobrec + bt, T.data(), sizeof(TopkJob) * T.size());
+    HIPCHK(hipMemcpyAsync(ws->jobrec, ws->hjobrec, bytes, hipMemcpyHostToDevice, c.st));
+    const int n0 = (int)E[0].size(), n1 = (int)E[1].size();
+    if (n0)
+      c.tm.run(K_LAST, [&] {
+        ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, gx_flat(1ull << 40, n0), true);
+      });
+    if (n1) {
+      uint64_t items = 1;
+      for (auto& e : E[1]) items = std::max(items, e.src_cap);
+      c.tm.run(K_LAST, [&] {
+        ext_single(c.st, g, (const ExtJob*)(ws->jobrec + b0), n1, gx_for(items, n1));
+      });
+    }
+    // the jobs whose collection now fits get their first K (sorted, or flagged
+    // for the radix select)
+    c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)(ws->jobrec + bt), (int)T.size()); });
+    for (int x : over)
+      HIPCHK(hipMemcpyAsync(ws->hctl + CTL_WORDS * x, jobs[x].mem.ctl, sizeof(uint64_t) * CTL_WORDS,
+                            hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    if (c.stats) c.stats->threshold_passes++;
+    std::vector<int> next;
+    for (int x : over)
+      if (ws->hctl[CTL_WORDS * x + CTL_VCOUNT] > vsmall) next.push_back(x);
+    over.swap(next);
+  }
 }
 
 static int64_t default_budget() {
@@ -1333,10 +1464,12 @@ static Workspace* acquire_ws(gfd_graph* g, int64_t budget) {
     w->budget = budget;
     w->misc = dalloc<unsigned long long>(16);
     w->err = dalloc<uint32_t>(1);
-    w->sel_state = dalloc<uint32_t>(MAXK + 2);
-    w->sel_hist = dalloc<uint32_t>(RADIX_BINS);
+    w->sel_state = dalloc<uint32_t>((size_t)SEL_JOBS * SEL_STATE_WORDS);
+    w->sel_hist = dalloc<uint32_t>((size_t)SEL_JOBS * RADIX_BINS);
     w->sel_out = dalloc<int32_t>((size_t)SORT_MAX * MAXK);
-    HIPCHK(hipMemset(w->sel_hist, 0, 4 * RADIX_BINS));
+    w->selrec = dalloc<uint8_t>(sizeof(SelJob) * SEL_JOBS);
+    HIPCHK(hipHostMalloc((void**)&w->hselrec, sizeof(SelJob) * SEL_JOBS, hipHostMallocDefault));
+    HIPCHK(hipMemset(w->sel_hist, 0, 4 * (size_t)SEL_JOBS * RADIX_BINS));
     HIPCHK(hipMemset(w->err, 0, 4));
     HIPCHK(hipDeviceSynchronize());
   } catch (...) {
@@ -1388,7 +1521,12 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       ws->cpi_cap = (uint64_t)std::max<int64_t>(1 << 20, std::min<int64_t>(budget / 16, int64_t(1) << 30) / 4);
       ws->cpi_arena = dalloc<int32_t>(ws->cpi_cap);
     }
-    const uint64_t vsmall = std::max<uint64_t>(o.violation_cap ? (uint64_t)o.violation_cap : 16384,
+    const int max_batch = o.batched ? SEL_JOBS : 1;
+    const int64_t njobs_hint = std::min<int64_t>(num_specs, max_batch);
+    // violation staging per job: a sixteenth of the budget over a full batch
+    const uint64_t vdef = (uint64_t)std::max<int64_t>(
+        16384, std::min<int64_t>(budget / (16 * njobs_hint) / (4 * MAXK), int64_t(1) << 18));
+    const uint64_t vsmall = std::max<uint64_t>(o.violation_cap ? (uint64_t)o.violation_cap : vdef,
                                                (uint64_t)K + 1);
     const uint64_t vbig = std::max<uint64_t>(o.violation_cap ? (uint64_t)o.violation_cap : (4u << 20),
                                              (uint64_t)K + 64);
@@ -1402,8 +1540,6 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     HIPCHK(hipMemsetAsync(ws->err, 0, 4, c.st));
     // plans, capacities and batches
     std::vector<Job> all(num_specs);
-    const int max_batch = o.batched ? 64 : 1;
-    const int64_t njobs_hint = std::min<int64_t>(num_specs, max_batch);
     uint64_t cap_f = o.frontier_cap ? (uint64_t)o.frontier_cap
                                     : (uint64_t)std::max<int64_t>(
                                           4096, std::min<int64_t>(budget / (4 * njobs_hint), int64_t(2) << 30) /
@@ -1450,24 +1586,36 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
         HIPCHK(hipMemcpyAsync(&cursor, ws->misc, 8, hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipStreamSynchronize(c.st));
         cpi_entries += cursor;
+        std::vector<int> over;  // only the violation staging overflowed
         for (size_t x = 0; x < jobs.size(); x++) {
           const uint64_t* h = ws->hctl + CTL_WORDS * x;
           std::memcpy(&H[(size_t)jobs[x].spec * CTL_WORDS], h, sizeof(uint64_t) * CTL_WORDS);
-          if ((h[CTL_FLAGS] & 7u) || h[CTL_VCOUNT] > vsmall) redo[x] = 1;
+          if (h[CTL_FLAGS] & 5u) redo[x] = 1;  // frontier or CPI arena overflow
+          else if (K > 0 && h[CTL_VCOUNT] > vsmall) over.push_back((int)x);
         }
-        // staged violations beyond one workgroup's sort: radix select
-        for (size_t x = 0; x < jobs.size(); x++) {
-          if (redo[x] || K == 0 || !H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL]) continue;
-          select_first_k(c, jobs[x].mem.vbuf, jobs[x].mem.ctl + CTL_VCOUNT, vsmall, jobs[x].plan.k,
-                         jobs[x].mem.ctl);
-          HIPCHK(hipMemcpyAsync(jobs[x].mem.res, ws->sel_out, sizeof(int32_t) * K * jobs[x].plan.k,
-                                hipMemcpyDeviceToDevice, c.st));
+        if (!over.empty()) {
+          if (stats) stats->threshold_gfds += (int32_t)over.size();
+          rerun_last_levels(c, jobs, over, R, vsmall, redo);
+          for (int x : over)
+            if (!redo[x]) {
+              H[(size_t)jobs[x].spec * CTL_WORDS + CTL_VCOUNT] = ws->hctl[CTL_WORDS * x + CTL_VCOUNT];
+              H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL] = ws->hctl[CTL_WORDS * x + CTL_NEEDSEL];
+            }
         }
-        if (K > 0)
+        // staged violations beyond one workgroup's sort: batched radix select
+        if (K > 0) {
+          std::vector<SelJob> S;
+          for (size_t x = 0; x < jobs.size(); x++) {
+            if (redo[x] || !H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL]) continue;
+            S.push_back(sel_job(c, jobs[x].plan.k, jobs[x].mem.vbuf, jobs[x].mem.ctl, vsmall));
+            S.back().out = jobs[x].mem.res;
+          }
+          run_select(c, S, false);
           for (size_t x = 0; x < jobs.size(); x++)
             if (!redo[x])
               HIPCHK(hipMemcpyAsync(hres.data() + (size_t)jobs[x].spec * K * MAXK, jobs[x].mem.res,
                                     sizeof(int32_t) * K * jobs[x].plan.k, hipMemcpyDeviceToHost, c.st));
+        }
         HIPCHK(hipStreamSynchronize(c.st));
         if (stats)
           for (size_t x = 0; x < jobs.size(); x++) {

@@ -30,6 +30,8 @@ constexpr int BS = 256;        // threads per block everywhere
 constexpr int WAVE = 64;       // CDNA wavefront
 constexpr int SCAN_IPT = 8;    // items per thread in the scan
 constexpr int SCAN_TILE = BS * SCAN_IPT;
+constexpr int LBS_ROUNDS = 8;  // flat work: rounds of BS positions per located chunk
+constexpr uint64_t LBS_CHUNK = (uint64_t)BS * LBS_ROUNDS;
 constexpr int SORT_MAX = 2048; // violation tuples sorted in one workgroup
 constexpr int RADIX_BITS = 11;
 constexpr int RADIX_BINS = 1 << RADIX_BITS;
@@ -151,6 +153,7 @@ struct ExtJob {
   uint32_t* flags;          // bit0: frontier overflow; bit1: violation staging overflow
   int32_t var_pos[MAXK];
   int32_t nx, ny, y_false, collect_only;
+  int32_t thr_incl;         // stage t <= thr instead of t < thr
   DevLit lit[2 * MAXLIT];
   unsigned long long* counters;  // [4] match, violation, match_fp, violation_fp
   int32_t* vbuf;
@@ -170,6 +173,23 @@ struct TopkJob {
   uint32_t* d_need_select;
 };
 
+// Radix select of the K-th smallest staged tuple of one job (lexicographic on
+// unsigned ids), then either the first K sorted into `out`, or the K-th tuple
+// written to `thr` as the job's staging threshold (staging then restarts).
+struct SelJob {
+  int32_t active, k, K;
+  uint64_t* d_vcount;
+  const int32_t* vbuf;
+  uint64_t vcap;
+  uint32_t* state;                 // [MAXK + 1]
+  uint32_t* hist;                  // [RADIX_BINS], zero at rest
+  int32_t* out;                    // [K * k]
+  unsigned long long* d_outcount;
+  int32_t* thr;                    // [k]
+  uint32_t* d_thr_valid;
+  uint32_t* flags;                 // staging overflow bit (2) cleared with the threshold
+};
+
 // Launch wrappers (gfd_kernels.hip).  All asynchronous on `st`; `jobs` points
 // to `njobs` device-resident job records; gx = blocks per job.
 void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
@@ -187,16 +207,13 @@ void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, i
 void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx);
 void topk_small(hipStream_t st, const TopkJob* jobs, int njobs);
 
-// Radix select of the K-th smallest staged tuple (one job, host driven).
-// state: [MAXK + 1] words; hist: [RADIX_BINS], zero at rest.
-void select_begin(hipStream_t st, uint32_t* state, int K);
-void select_pass(hipStream_t st, const int32_t* vbuf, const uint64_t* d_vcount, uint64_t vcap,
-                 int k, int word, int shift, int bits, uint32_t* state, uint32_t* hist, int grid);
-// Tuples <= the selected threshold into out (exactly K of them).
-void select_compact(hipStream_t st, const int32_t* vbuf, const uint64_t* d_vcount, uint64_t vcap,
-                    int k, const uint32_t* state, int32_t* out, uint64_t* d_outcount, int grid);
-// Sort *d_n (<= SORT_MAX) tuples in place.
-void sort_tuples(hipStream_t st, int32_t* buf, const uint64_t* d_n, int k);
+// Batched radix select (grid row = job); requires more than K staged tuples
+// per active job.  sel_pass decides `bits` bits of tuple word `word` starting
+// at bit `shift` (jobs with k <= word are skipped).
+void sel_begin(hipStream_t st, const SelJob* jobs, int njobs);
+void sel_pass(hipStream_t st, const SelJob* jobs, int njobs, int word, int shift, int bits, int gx);
+void sel_first_k(hipStream_t st, const SelJob* jobs, int njobs, int gx);
+void sel_threshold(hipStream_t st, const SelJob* jobs, int njobs);
 
 void fill_u8(hipStream_t st, uint8_t* p, uint8_t v, uint64_t n);
 void fill_u64(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);

@@ -250,7 +250,7 @@ __device__ void job_scan(uint64_t N, F f, const JobScan& sc) {
 // load-balanced search: map a tile of flat work positions to (source, offset)
 // ---------------------------------------------------------------------------
 
-constexpr int LBS_SLOTS = BS + 1 + 63;
+constexpr int LBS_SLOTS = (int)LBS_CHUNK + 2;  // prefix entries staged in LDS
 struct LbsShared {
   uint64_t p[LBS_SLOTS];
   uint64_t lo, hi;
@@ -266,51 +266,74 @@ __device__ __forceinline__ uint64_t last_le(const uint64_t* __restrict__ P, uint
   return lo;
 }
 
-// Every thread of the block must call this with the same (t0, t1), t0 < t1,
-// N >= 1 and P[N] >= t1.
-__device__ __forceinline__ bool lbs_tile(const uint64_t* __restrict__ P, uint64_t N, uint64_t t0,
-                                         uint64_t t1, LbsShared& sh, uint64_t& s, uint64_t& off) {
-  if (threadIdx.x == 0) sh.lo = last_le(P, 0, N - 1, t0);
-  if (threadIdx.x == 1) sh.hi = last_le(P, 0, N - 1, t1 - 1);
-  __syncthreads();
-  const uint64_t lo = sh.lo, hi = sh.hi;
-  const uint64_t span = hi - lo + 2;  // P[lo .. hi+1]
-  const bool in_lds = span <= (uint64_t)LBS_SLOTS;
-  if (in_lds)
-    for (uint64_t j = threadIdx.x; j < span; j += BS) sh.p[j] = P[lo + j];
-  __syncthreads();
-  const uint64_t a = t0 + threadIdx.x;
-  const bool valid = a < t1;
-  if (valid) {
-    if (in_lds) {
-      uint32_t l = 0, h = (uint32_t)(span - 2);
-      while (l < h) {
-        const uint32_t mid = (l + h + 1) >> 1;
-        if (sh.p[mid] <= a) l = mid; else h = mid - 1;
-      }
-      s = lo + l;
-      off = a - sh.p[l];
-    } else {
-      s = last_le(P, lo, hi, a);
-      off = a - P[s];
-    }
+// The same search done by one whole wave: every round samples 64 evenly spaced
+// prefix values at once and keeps the stretch that holds the answer, so a
+// search over N sources costs about log64(N) dependent loads.
+__device__ __forceinline__ uint64_t wave_last_le(const uint64_t* __restrict__ P, uint64_t lo,
+                                                 uint64_t hi, uint64_t a) {
+  while (hi - lo >= WAVE) {
+    const uint64_t step = (hi - lo) / WAVE + 1;
+    uint64_t idx = lo + (uint64_t)(lane() + 1) * step;
+    if (idx > hi) idx = hi;
+    // lanes past hi all sample P[hi]; the votes form a prefix of the lanes
+    const uint64_t cnt = (uint64_t)__popcll(__ballot(P[idx] <= a));
+    const uint64_t nlo = lo + cnt * step;
+    const uint64_t nhi = lo + (cnt + 1) * step - 1;
+    lo = nlo < hi ? nlo : hi;
+    hi = nhi < hi ? nhi : hi;
   }
-  __syncthreads();
-  return valid;
+  const bool le = lo + lane() <= hi && P[lo + lane()] <= a;
+  return lo + (uint64_t)__popcll(__ballot(le)) - 1;
 }
 
-// Iterates the flat positions [A0, A1) of one job row in tiles of BS, every
-// tile mapped to (source, offset) by lbs_tile.  f(valid, s, o) is called by
-// every thread of every tile (uniform trip count).
+// Iterates the flat positions [A0, A1) of one job row: each block takes chunks
+// of LBS_CHUNK positions, locates the chunk's first and last source with two
+// wave-parallel searches, stages their prefix values in LDS and maps each
+// position to (source, offset) with a binary search there.  f(valid, s, o) is
+// called by every thread LBS_ROUNDS times per chunk (uniform trip count).
+// Requires P[N] >= A1.
 template <class F>
-__device__ __forceinline__ void flat_tiles(const uint64_t* P, uint64_t N, uint64_t A0, uint64_t A1,
-                                           LbsShared& sh, F f) {
+__device__ __forceinline__ void flat_tiles(const uint64_t* __restrict__ P, uint64_t N, uint64_t A0,
+                                           uint64_t A1, LbsShared& sh, F f) {
   if (N == 0) return;
-  for (uint64_t t0 = A0 + (uint64_t)blockIdx.x * BS; t0 < A1; t0 += (uint64_t)gridDim.x * BS) {
-    const uint64_t t1 = t0 + BS < A1 ? t0 + BS : A1;
-    uint64_t s = 0, o = 0;
-    const bool valid = lbs_tile(P, N, t0, t1, sh, s, o);
-    f(valid, s, o);
+  for (uint64_t c0 = A0 + (uint64_t)blockIdx.x * LBS_CHUNK; c0 < A1;
+       c0 += (uint64_t)gridDim.x * LBS_CHUNK) {
+    const uint64_t c1 = c0 + LBS_CHUNK < A1 ? c0 + LBS_CHUNK : A1;
+    if (threadIdx.x < WAVE) {
+      const uint64_t lo = wave_last_le(P, 0, N - 1, c0);
+      if (threadIdx.x == 0) sh.lo = lo;
+    } else if (threadIdx.x < 2 * WAVE) {
+      const uint64_t hi = wave_last_le(P, 0, N - 1, c1 - 1);
+      if (threadIdx.x == WAVE) sh.hi = hi;
+    }
+    __syncthreads();
+    const uint64_t lo = sh.lo, hi = sh.hi;
+    const uint64_t span = hi - lo + 2;  // P[lo .. hi+1]
+    const bool in_lds = span <= (uint64_t)LBS_SLOTS;
+    if (in_lds)
+      for (uint64_t j = threadIdx.x; j < span; j += BS) sh.p[j] = P[lo + j];
+    __syncthreads();
+    for (int r = 0; r < LBS_ROUNDS; r++) {
+      const uint64_t a = c0 + (uint64_t)r * BS + threadIdx.x;
+      const bool valid = a < c1;
+      uint64_t s = 0, o = 0;
+      if (valid) {
+        if (in_lds) {
+          uint32_t l = 0, h = (uint32_t)(span - 2);
+          while (l < h) {
+            const uint32_t mid = (l + h + 1) >> 1;
+            if (sh.p[mid] <= a) l = mid; else h = mid - 1;
+          }
+          s = lo + l;
+          o = a - sh.p[l];
+        } else {
+          s = last_le(P, lo, hi, a);
+          o = a - P[s];
+        }
+      }
+      f(valid, s, o);
+    }
+    __syncthreads();
   }
 }
 
@@ -578,9 +601,9 @@ void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, 
 // check (Section II: h |= X implies h |= Y)
 // ---------------------------------------------------------------------------
 
-template <int N>
-__device__ __forceinline__ int32_t pick(const int32_t (&h)[N], int idx) {
-  int32_t r = h[0];
+template <class T, int N>
+__device__ __forceinline__ T pick(const T (&h)[N], int idx) {
+  T r = h[0];
 #pragma unroll
   for (int j = 1; j < N; j++)
     if (j == idx) r = h[j];
@@ -628,7 +651,7 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
   acc.viol += 1;
   acc.vfp += hs;
   if (J.vcap == 0) return false;
-  if (thr_on) {  // stage only if t < thr lexicographically (unsigned ids)
+  if (thr_on) {  // stage only if t < thr (t <= thr when thr_incl), lexicographically on unsigned ids
     int c = 0;
 #pragma unroll
     for (int v = 0; v < MAXK; v++)
@@ -636,7 +659,7 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
         const uint32_t x = (uint32_t)t[v], y = (uint32_t)thr[v];
         c = x < y ? -1 : (x > y ? 1 : 0);
       }
-    if (c >= 0) return false;
+    if (c > 0 || (c == 0 && !J.thr_incl)) return false;
   }
   return true;
 }
@@ -897,72 +920,72 @@ __global__ __launch_bounds__(SORT_THREADS) void k_topk_small(const TopkJob* __re
   for (uint32_t i = threadIdx.x; i < out * (uint32_t)k; i += blockDim.x) J.res[i] = (int32_t)s[i];
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_tuples(int32_t* buf,
-                                                              const uint64_t* __restrict__ d_n,
-                                                              int k) {
-  __shared__ uint32_t s[SORT_MAX * MAXK];
-  const uint64_t cnt = *d_n < (uint64_t)SORT_MAX ? *d_n : (uint64_t)SORT_MAX;
-  uint32_t p2 = 1;
-  while (p2 < cnt) p2 <<= 1;
-  for (uint32_t i = threadIdx.x; i < p2 * (uint32_t)k; i += blockDim.x)
-    s[i] = (i / k < cnt) ? (uint32_t)buf[i] : 0xFFFFFFFFu;
-  bitonic_lds(s, p2, k);
-  for (uint32_t i = threadIdx.x; i < cnt * (uint32_t)k; i += blockDim.x) buf[i] = (int32_t)s[i];
-}
-
 void topk_small(hipStream_t st, const TopkJob* jobs, int njobs) {
   hipLaunchKernelGGL(k_topk_small, dim3(1, njobs), dim3(SORT_THREADS), 0, st, jobs);
 }
-void sort_tuples(hipStream_t st, int32_t* buf, const uint64_t* d_n, int k) {
-  hipLaunchKernelGGL(k_sort_tuples, dim3(1), dim3(SORT_THREADS), 0, st, buf, d_n, k);
+
+// Radix select, batched over jobs (grid row y = job).  State words of a job:
+// [0..MAXK) the tuple being decided, [MAXK] the remaining rank (1-based) among
+// staged tuples that agree with it so far.
+__global__ void k_sel_begin(const SelJob* __restrict__ jobs) {
+  const SelJob& J = jobs[blockIdx.y];
+  if (!J.active) return;
+  if (threadIdx.x < MAXK) J.state[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    J.state[MAXK] = (uint32_t)J.K;
+    if (J.d_outcount) *J.d_outcount = 0;
+  }
 }
 
-// Radix select state words: [0..MAXK) the tuple being decided,
-// [MAXK] remaining rank (1-based) among tuples that match it so far.
-__global__ void k_select_begin(uint32_t* state, int K) {
-  if (threadIdx.x < MAXK) state[threadIdx.x] = 0;
-  if (threadIdx.x == 0) state[MAXK] = (uint32_t)K;
+__device__ __forceinline__ uint64_t sel_count(const SelJob& J) {
+  return *J.d_vcount < J.vcap ? *J.d_vcount : J.vcap;
 }
 
 // Tuples that agree with the decided prefix (words < word, and the decided
-// high bits of `word`) vote for the next digit.
-__global__ __launch_bounds__(BS) void k_select_hist(const int32_t* __restrict__ vbuf,
-                                                    const uint64_t* __restrict__ d_vcount,
-                                                    uint64_t vcap, int k, int word, int shift,
-                                                    int bits, const uint32_t* __restrict__ state,
-                                                    uint32_t* __restrict__ hist) {
+// high bits of `word`) vote for the next digit of `word`.
+__global__ __launch_bounds__(BS) void k_sel_hist(const SelJob* __restrict__ jobs, int word,
+                                                 int shift, int bits) {
   __shared__ uint32_t sh[RADIX_BINS];
+  const SelJob& J = jobs[blockIdx.y];
+  if (!J.active || word >= J.k) return;
   for (int b = threadIdx.x; b < RADIX_BINS; b += BS) sh[b] = 0;
+  uint32_t st[MAXK];
+#pragma unroll
+  for (int w = 0; w < MAXK; w++) st[w] = J.state[w];
   __syncthreads();
-  const uint64_t cnt = *d_vcount < vcap ? *d_vcount : vcap;
+  const int k = J.k;
+  const uint64_t cnt = sel_count(J);
   const uint32_t hi_mask = (shift + bits >= 32) ? 0u : (0xFFFFFFFFu << (shift + bits));
+  const uint32_t want_hi = pick(st, word) & hi_mask;
   for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < cnt;
        i += (uint64_t)gridDim.x * BS) {
-    const uint32_t* t = (const uint32_t*)vbuf + i * (uint64_t)k;
+    const uint32_t* t = (const uint32_t*)J.vbuf + i * (uint64_t)k;
     bool match = true;
-    for (int w = 0; w < word && match; w++) match = t[w] == state[w];
+    for (int w = 0; w < word && match; w++) match = t[w] == pick(st, w);
     if (!match) continue;
     const uint32_t x = t[word];
-    if ((x & hi_mask) != (state[word] & hi_mask)) continue;
+    if ((x & hi_mask) != want_hi) continue;
     atomicAdd(&sh[(x >> shift) & ((1u << bits) - 1)], 1u);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < RADIX_BINS; b += BS)
-    if (sh[b]) atomicAdd(&hist[b], sh[b]);
+    if (sh[b]) atomicAdd(&J.hist[b], sh[b]);
 }
 
 // Finds the bin holding the remaining rank with a block-wide scan of the
 // histogram (BS threads x RADIX_BINS / BS bins each), then clears it.
-__global__ __launch_bounds__(BS) void k_select_pick(int word, int shift, int bits,
-                                                    uint32_t* state, uint32_t* hist) {
+__global__ __launch_bounds__(BS) void k_sel_pick(const SelJob* __restrict__ jobs, int word,
+                                                 int shift, int bits) {
   constexpr int PER = RADIX_BINS / BS;
+  const SelJob& J = jobs[blockIdx.y];
+  if (!J.active || word >= J.k) return;
   const uint32_t nb = 1u << bits;
-  const uint32_t r = state[MAXK];  // read before the scan's barriers; one thread rewrites it
+  const uint32_t r = J.state[MAXK];  // read before the scan's barriers; one thread rewrites it
   uint32_t h[PER], sum = 0;
 #pragma unroll
   for (int j = 0; j < PER; j++) {
     const uint32_t bin = threadIdx.x * PER + j;
-    h[j] = bin < nb ? hist[bin] : 0u;
+    h[j] = bin < nb ? J.hist[bin] : 0u;
     sum += h[j];
   }
   uint32_t total;
@@ -976,47 +999,81 @@ __global__ __launch_bounds__(BS) void k_select_pick(int word, int shift, int bit
       }
       cum += h[j];
     }
-    state[MAXK] = r - cum;
-    state[word] |= d << shift;
+    J.state[MAXK] = r - cum;
+    J.state[word] |= d << shift;
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < PER; j++) hist[threadIdx.x * PER + j] = 0;
+  for (int j = 0; j < PER; j++) J.hist[threadIdx.x * PER + j] = 0;
 }
 
-__global__ __launch_bounds__(BS) void k_select_compact(const int32_t* __restrict__ vbuf,
-                                                       const uint64_t* __restrict__ d_vcount,
-                                                       uint64_t vcap, int k,
-                                                       const uint32_t* __restrict__ state,
-                                                       int32_t* __restrict__ out,
-                                                       unsigned long long* d_outcount) {
-  const uint64_t cnt = *d_vcount < vcap ? *d_vcount : vcap;
+// Staged tuples <= the selected one (exactly K of them, tuples being
+// distinct) into out.
+__global__ __launch_bounds__(BS) void k_sel_compact(const SelJob* __restrict__ jobs) {
+  const SelJob& J = jobs[blockIdx.y];
+  if (!J.active) return;
+  const int k = J.k;
+  uint32_t st[MAXK];
+#pragma unroll
+  for (int w = 0; w < MAXK; w++) st[w] = J.state[w];
+  const uint64_t cnt = sel_count(J);
   for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < cnt;
        i += (uint64_t)gridDim.x * BS) {
-    const uint32_t* t = (const uint32_t*)vbuf + i * (uint64_t)k;
+    const uint32_t* t = (const uint32_t*)J.vbuf + i * (uint64_t)k;
     int c = 0;
-    for (int w = 0; w < k && c == 0; w++) c = t[w] < state[w] ? -1 : (t[w] > state[w] ? 1 : 0);
+    for (int w = 0; w < k && c == 0; w++) {
+      const uint32_t y = pick(st, w);
+      c = t[w] < y ? -1 : (t[w] > y ? 1 : 0);
+    }
     if (c <= 0) {
-      const unsigned long long slot = atomicAdd(d_outcount, 1ull);
-      if (slot < (unsigned long long)SORT_MAX)
-        for (int w = 0; w < k; w++) out[slot * k + w] = (int32_t)t[w];
+      const unsigned long long slot = atomicAdd(J.d_outcount, 1ull);
+      if (slot < (unsigned long long)J.K)
+        for (int w = 0; w < k; w++) J.out[slot * k + w] = (int32_t)t[w];
     }
   }
 }
 
-void select_begin(hipStream_t st, uint32_t* state, int K) {
-  hipLaunchKernelGGL(k_select_begin, dim3(1), dim3(64), 0, st, state, K);
+// Sorts the K selected tuples of every job in place.
+__global__ __launch_bounds__(SORT_THREADS) void k_sel_sort(const SelJob* __restrict__ jobs) {
+  __shared__ uint32_t s[SORT_MAX * MAXK];
+  const SelJob& J = jobs[blockIdx.y];
+  if (!J.active) return;
+  const int k = J.k;
+  const uint64_t n = *J.d_outcount < (uint64_t)J.K ? *J.d_outcount : (uint64_t)J.K;
+  uint32_t p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  for (uint32_t i = threadIdx.x; i < p2 * (uint32_t)k; i += blockDim.x)
+    s[i] = (i / k < n) ? (uint32_t)J.out[i] : 0xFFFFFFFFu;
+  bitonic_lds(s, p2, k);
+  for (uint32_t i = threadIdx.x; i < n * (uint32_t)k; i += blockDim.x) J.out[i] = (int32_t)s[i];
 }
-void select_pass(hipStream_t st, const int32_t* vbuf, const uint64_t* d_vcount, uint64_t vcap,
-                 int k, int word, int shift, int bits, uint32_t* state, uint32_t* hist, int grid) {
-  hipLaunchKernelGGL(k_select_hist, dim3(grid), dim3(BS), 0, st, vbuf, d_vcount, vcap, k, word,
-                     shift, bits, state, hist);
-  hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(BS), 0, st, word, shift, bits, state, hist);
+
+// The selected tuple becomes the job's staging threshold; staging restarts.
+__global__ void k_sel_thr(const SelJob* __restrict__ jobs) {
+  const SelJob& J = jobs[blockIdx.y];
+  if (!J.active) return;
+  if (threadIdx.x < (uint32_t)J.k) J.thr[threadIdx.x] = (int32_t)J.state[threadIdx.x];
+  if (threadIdx.x == 0) {
+    *J.d_thr_valid = 1;
+    *J.d_vcount = 0;
+    atomicAnd(J.flags, ~2u);
+  }
 }
-void select_compact(hipStream_t st, const int32_t* vbuf, const uint64_t* d_vcount, uint64_t vcap,
-                    int k, const uint32_t* state, int32_t* out, uint64_t* d_outcount, int grid) {
-  hipLaunchKernelGGL(k_select_compact, dim3(grid), dim3(BS), 0, st, vbuf, d_vcount, vcap, k, state,
-                     out, (unsigned long long*)d_outcount);
+
+void sel_begin(hipStream_t st, const SelJob* jobs, int njobs) {
+  hipLaunchKernelGGL(k_sel_begin, dim3(1, njobs), dim3(64), 0, st, jobs);
+}
+void sel_pass(hipStream_t st, const SelJob* jobs, int njobs, int word, int shift, int bits,
+              int gx) {
+  hipLaunchKernelGGL(k_sel_hist, dim3(gx, njobs), dim3(BS), 0, st, jobs, word, shift, bits);
+  hipLaunchKernelGGL(k_sel_pick, dim3(1, njobs), dim3(BS), 0, st, jobs, word, shift, bits);
+}
+void sel_first_k(hipStream_t st, const SelJob* jobs, int njobs, int gx) {
+  hipLaunchKernelGGL(k_sel_compact, dim3(gx, njobs), dim3(BS), 0, st, jobs);
+  hipLaunchKernelGGL(k_sel_sort, dim3(1, njobs), dim3(SORT_THREADS), 0, st, jobs);
+}
+void sel_threshold(hipStream_t st, const SelJob* jobs, int njobs) {
+  hipLaunchKernelGGL(k_sel_thr, dim3(1, njobs), dim3(64), 0, st, jobs);
 }
 
 }  // namespace gfd

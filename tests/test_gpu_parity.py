@@ -124,6 +124,33 @@ def test_select_path(P):
     gh.free()
 
 
+def test_threshold_rerun(P):
+    """Violation staging overflow alone: the last level runs again, collecting
+    only violations up to a bound on the K-th smallest (possibly several passes,
+    and the bounded path once the pass limit is reached)."""
+    g = random_graph(8, 400, 12000, n_vlabels=1, n_elabels=1, n_attrs=1, attr_values=50,
+                     absent_frac=0.0)
+    gfds = [{"k": 3, "vlabels": [0, 0, 0], "edges": [[0, 1, 0], [0, 2, 0]], "x": [],
+             "y": [{"kind": "var", "var": 1, "attr": 0, "var2": 2, "attr2": 0}], "y_false": False},
+            {"k": 1, "vlabels": [0], "edges": [], "x": [], "y": [], "y_false": True},
+            {"k": 2, "vlabels": [0, 0], "edges": [[0, 1, 0]], "x": [], "y": [], "y_false": True}]
+    gh = P.load(g)
+    for batched in (False, True):
+        for K, cap in ((16, 40), (300, 2000), (1024, 1025)):
+            got, st = P.validate(gh, gfds, K=K, semantics="mono", violation_cap=cap,
+                                 batched=batched, stats=True)
+            og = O.OracleGraph(g)
+            exp = [O.validate(og, d, "mono", K=K, threads=4) for d in gfds]
+            assert got == exp
+            over = sum(e["violation_count"] > max(cap, K + 1) for e in exp)
+            assert over >= 2 and st["threshold_gfds"] == over and st["threshold_passes"] >= 1
+            if cap == 2000:  # about 7x fewer kept per pass: done well within the pass limit
+                assert st["chunked_gfds"] == 0
+            if cap == K + 1:  # one fewer per pass at worst: the bounded path takes over
+                assert st["chunked_gfds"] >= 1
+    gh.free()
+
+
 def test_single_vertex_patterns(P):
     g = random_graph(9, 500, 2000, n_vlabels=3, n_attrs=2, attr_values=4, absent_frac=0.3)
     gfds = [{"k": 1, "vlabels": [L], "edges": [], "x": [],
@@ -199,6 +226,7 @@ def test_batched_matches_oracle(P):
     for sem in SEMS:
         _check(P, g, gfds, sem, K=40, gh=gh, batched=True)
         _check(P, g, gfds, sem, K=40, gh=gh, batched=True, frontier_cap=500, violation_cap=100)
+        _check(P, g, gfds, sem, K=40, gh=gh, batched=True, violation_cap=60)
     gh.free()
 
 
