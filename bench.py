@@ -66,6 +66,9 @@ def main():
                     help="skip the one-at-a-time comparison")
     ap.add_argument("--no-timing", action="store_true",
                     help="no HIP events at all (no roofline line)")
+    ap.add_argument("--per-gfd", type=int, default=0, metavar="N",
+                    help="diagnostic: validate each GFD alone with statistics and print the "
+                         "N slowest to stderr")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -92,24 +95,31 @@ def main():
     load_s = time.perf_counter() - t
     batched = mode == "batched"
 
-    def call(specs, flags=0, stats=True):
-        return P.validate(gh, specs, K=K_REPORT, semantics=args.semantics, stream=stream,
-                          flags=flags, stats=stats, batched=batched)
+    # specs, options and result buffers are marshalled once; a step is one
+    # gfd_validate_ex call through the C ABI
+    pc = P.PreparedCall(gh, gfds, K=K_REPORT, semantics=args.semantics, stream=stream,
+                        batched=batched)
 
     # warm-up; the last warm-up step records every kernel class to find the dominant one
-    for w in range(args.warmup):
-        res, st = call(gfds, flags=0 if args.no_timing or w < args.warmup - 1 else P.GFD_FLAG_TIMING)
+    for w in range(max(1, args.warmup)):
+        st = pc.run(flags=0 if args.no_timing or w < args.warmup - 1 else P.GFD_FLAG_TIMING)
     torch.cuda.synchronize()
+    res = pc.results()
     dom = None
     if not args.no_timing:
         dom = max(range(8), key=lambda c: st["class_ms"][KERNEL_CLASSES[c]])
-        log("warm-up per-class ms: " + ", ".join(f"{k} {v:.2f}" for k, v in st["class_ms"].items()))
+        log("warm-up per class: " + ", ".join(
+            f"{k} {v:.2f} ms/{st['class_launches'][k]} launches/"
+            f"{st['class_bytes'][k] / max(v, 1e-9) / 1e6:.0f} GB/s"
+            for k, v in st["class_ms"].items()))
+        log(f"warm-up: wall {st['wall_ms']:.1f} ms, kernel time {sum(st['class_ms'].values()):.1f} ms, "
+            f"chunked {st['chunked_gfds']}, threshold {st['threshold_gfds']}/{st['threshold_passes']}")
     flags = 0 if dom is None else (1 << (8 + dom))  # HIP events around the dominant class only
     agg_ms = agg_bytes = agg_launch = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res, st = call(gfds, flags=flags)
+        st = pc.run(flags=flags)
         if dom is not None:
             name = KERNEL_CLASSES[dom]
             agg_ms += st["class_ms"][name]
@@ -118,6 +128,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
+    assert pc.results() == res, "results changed between steps"
     matches = sum(r["match_count"] for r in res)
     value = matches * args.steps / elapsed
     gfds_per_s = len(gfds) * args.steps / elapsed
@@ -136,17 +147,36 @@ def main():
                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": per_launch,
                     "launches_per_step": agg_launch / args.steps}
 
+    if args.per_gfd:
+        rows = []
+        for i, d in enumerate(gfds):
+            r, s1 = P.validate(gh, [d], K=K_REPORT, semantics=args.semantics, stream=stream,
+                               flags=P.GFD_FLAG_TIMING, stats=True)
+            rows.append((s1["wall_ms"], i, d, r[0], s1))
+        rows.sort(key=lambda x: -x[0])
+        log(f"per-GFD (alone, with events), total {sum(x[0] for x in rows):.1f} ms")
+        for wall, i, d, r, s1 in rows[:args.per_gfd]:
+            cm = " ".join(f"{k}={v:.2f}" for k, v in s1["class_ms"].items() if v >= 0.05)
+            log(f"  #{i} k={d['k']} e={len(d['edges'])} wall={wall:.2f}ms match={r['match_count']} "
+                f"viol={r['violation_count']} att={s1['attempts']} part={s1['partials']} "
+                f"cand={s1['cpi_candidates']} cpi={s1['cpi_entries']} chunked={s1['chunked_gfds']} "
+                f"thr={s1['threshold_gfds']}/{s1['threshold_passes']} | {cm}")
+
     compare = None
     if batched and not args.no_compare:
-        # the same GFDs, one gfd_validate call each (one-at-a-time)
-        for d in gfds[:8]:
-            P.validate(gh, [d], K=K_REPORT, semantics=args.semantics, stream=stream)
+        # the same GFDs, one gfd_validate call each (one-at-a-time), marshalled
+        # up front like the batched call
+        one = [P.PreparedCall(gh, [d], K=K_REPORT, semantics=args.semantics, stream=stream)
+               for d in gfds]
+        for q in one[:8]:
+            q.run(stats=False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        seq = [P.validate(gh, [d], K=K_REPORT, semantics=args.semantics, stream=stream)[0]
-               for d in gfds]
+        for q in one:
+            q.run(stats=False)
         torch.cuda.synchronize()
         dt1 = time.perf_counter() - t1
+        seq = [q.results()[0] for q in one]
         assert seq == res, "one-at-a-time results differ from the batched call"
         compare = {"one_at_a_time_s": dt1, "one_at_a_time_gfds_per_s": len(gfds) / dt1,
                    "one_at_a_time_embeddings_per_s": matches / dt1,

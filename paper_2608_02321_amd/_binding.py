@@ -233,6 +233,56 @@ def make_spec(gfd: dict) -> gfd_spec:
     return s
 
 
+class PreparedCall:
+    """One gfd_validate_ex call with its specs, options and result buffers
+    marshalled once, for repeated calls (serving loops, timing): run() only
+    calls the C ABI and returns the stats; results() converts the last
+    call's outputs to the dicts validate() returns."""
+
+    def __init__(self, graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
+                 mem_budget_bytes: int = 0, stream=None, flags: int = 0, batched: bool = False):
+        self.graph, self.gfds, self.K = graph, list(gfds), int(K)
+        n = len(self.gfds)
+        self.n = n
+        self.specs = (gfd_spec * max(n, 1))(*[make_spec(d) for d in self.gfds])
+        self.res = (gfd_result * max(n, 1))()
+        self.ks = [int(d["k"]) for d in self.gfds]
+        self.buf = np.zeros((max(n, 1), max(1, self.K * GFD_MAX_K)), dtype=np.int32)
+        for i in range(n):
+            self.res[i].violations = self.buf[i].ctypes.data_as(C.POINTER(C.c_int32))
+        self.opts = gfd_validate_opts(self.K, GFD_SEM_INDUCED if semantics == "induced"
+                                      else GFD_SEM_MONO, int(mem_budget_bytes),
+                                      _stream_handle(stream), int(bool(batched)), int(flags), 0, 0)
+        self.st = gfd_stats()
+
+    def run(self, flags=None, stats=True):
+        if flags is not None:
+            self.opts.flags = int(flags)
+        rc = lib.gfd_validate_ex(self.graph.handle, self.specs, self.n, C.byref(self.opts),
+                                 self.res, C.byref(self.st) if stats else None)
+        _check(rc)
+        if not stats:
+            return None
+        sd = {f: getattr(self.st, f) for f, _ in gfd_stats._fields_}
+        for f in ("class_launches", "class_ms", "class_bytes"):
+            sd[f] = dict(zip(KERNEL_CLASSES, list(sd[f])))
+        return sd
+
+    def match_count(self):
+        return sum(int(self.res[i].match_count) for i in range(self.n))
+
+    def results(self):
+        out = []
+        for i in range(self.n):
+            r, k = self.res[i], self.ks[i]
+            out.append({"match_count": int(r.match_count),
+                        "violation_count": int(r.violation_count),
+                        "match_fp": int(r.match_fp), "violation_fp": int(r.violation_fp),
+                        "satisfied": bool(r.satisfied),
+                        "violations": self.buf[i][:r.num_reported * k].reshape(-1, k).tolist()})
+        return out
+
+
 def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
              mem_budget_bytes: int = 0, stream=None, flags: int = 0, frontier_cap: int = 0,
              violation_cap: int = 0, stats: bool = False, batched: bool = False):

@@ -87,7 +87,7 @@ enum {
   CTL_THR = 48 /* 4 words = 8 int32 */
 };
 
-constexpr int SEL_JOBS = 64;         // jobs per batched selection (= largest batch)
+constexpr int MAX_JOBS = 64;         // jobs per batched selection (= largest batch)
 constexpr int SEL_STATE_WORDS = 16;
 
 struct Workspace {
@@ -110,10 +110,10 @@ struct Workspace {
   int32_t* vbig = nullptr;
   uint64_t vbig_cap = 0;
   // batched radix select: per-job state and histograms, records
-  uint32_t* sel_state = nullptr;    // [SEL_JOBS * SEL_STATE_WORDS]
-  uint32_t* sel_hist = nullptr;     // [SEL_JOBS * RADIX_BINS], zero at rest
+  uint32_t* sel_state = nullptr;    // [MAX_JOBS * SEL_STATE_WORDS]
+  uint32_t* sel_hist = nullptr;     // [MAX_JOBS * RADIX_BINS], zero at rest
   int32_t* sel_out = nullptr;       // [SORT_MAX * MAXK]
-  uint8_t* selrec = nullptr;        // [SEL_JOBS] SelJob records
+  uint8_t* selrec = nullptr;        // [MAX_JOBS] SelJob records
   uint8_t* hselrec = nullptr;       // pinned staging for them
   int64_t budget = 0;
 
@@ -676,6 +676,10 @@ struct Ctx {
   unsigned long long* stat_bytes;  // device [8] per kernel class, or nullptr
 };
 
+static unsigned long long* cls_bytes(Ctx& c, int cls) {
+  return c.stat_bytes ? c.stat_bytes + cls : nullptr;
+}
+
 static uint32_t next_epoch(Ctx& c) {
   c.ws->epoch = (c.ws->epoch + 1) & 0xFFFFu;
   if (c.ws->epoch == 0) c.ws->epoch = 1;
@@ -708,11 +712,12 @@ static int gx_for(uint64_t items, int njobs, int cap = 256) {
   const int per_job = std::max(8, std::min(cap, 4096 / std::max(1, njobs)));
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)per_job));
 }
-// blocks per job for flat (load-balanced) work over `items` positions
-static int gx_flat(uint64_t items, int njobs, int cap = 256) {
-  const uint64_t want = (items + LBS_CHUNK - 1) / LBS_CHUNK;
-  const int per_job = std::max(8, std::min(cap, 4096 / std::max(1, njobs)));
-  return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)per_job));
+// 1-D grid of a flat (load-balanced) launch whose jobs together have at most
+// `chunks` chunks of LBS_CHUNK positions: enough blocks to fill the chip.
+constexpr uint64_t FLAT_GRID_MAX = 2048;
+static uint64_t chunks_of(uint64_t positions) { return (positions + LBS_CHUNK - 1) / LBS_CHUNK; }
+static int flat_grid(uint64_t chunks) {
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, FLAT_GRID_MAX));
 }
 static int gx_scan(uint64_t items) {
   const uint64_t t = (items + SCAN_TILE - 1) / SCAN_TILE;
@@ -774,11 +779,10 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
     maxk = std::max(maxk, J.plan.k);
     for (int u = 0; u < MAXK; u++) J.cur[u] = 0;
   }
-  unsigned long long* by = c.stat_bytes;
   // top-down, BFS order
   for (int j = 0; j < maxk; j++) {
     std::vector<FilterJob> F(nj);
-    uint64_t items = 1, pull_ub = 1, pairs = 1;
+    uint64_t items = 1, pull_ub = 0, pairs = 1;  // pull_ub: chunks over all jobs
     bool any_cons = false;
     const uint32_t ep = next_epoch(c);
     for (int x = 0; x < nj; x++) {
@@ -804,19 +808,18 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.pos = J.mem.pos[u];
       f.bits = J.mem.bits[u][0];
       f.nwords = (uint64_t)g->n / 32 + 1;
-      f.bytes = by ? by + K_FILTER : nullptr;
       items = std::max(items, bs);
       pairs = std::max(pairs, bs * (uint64_t)std::max(f.ncons, 1));
-      for (int q = 0; q < f.ncons; q++) pull_ub = std::max(pull_ub, rows_ub(g, p.qlab[u], f.cons[q].dir));
+      for (int q = 0; q < f.ncons; q++) pull_ub += chunks_of(rows_ub(g, p.qlab[u], f.cons[q].dir));
       any_cons |= f.ncons > 0;
     }
-    L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), gx_flat(pull_ub, nj), gx_for(items, nj),
+    L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), gx_for(items, nj),
                        gx_for((uint64_t)g->n / 32 + 1, nj, 64), any_cons, false, false});
   }
   // bottom-up, reverse BFS order: drop dead ends
   for (int j = maxk - 1; j >= 0; j--) {
     std::vector<FilterJob> F(nj);
-    uint64_t items = 1, pull_ub = 1, pairs = 1;
+    uint64_t items = 1, pull_ub = 0, pairs = 1;  // pull_ub: chunks over all jobs
     bool any = false;
     const uint32_t ep = next_epoch(c);
     for (int x = 0; x < nj; x++) {
@@ -841,20 +844,19 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.pos = J.mem.pos[u];
       f.bits = J.mem.bits[u][J.cur[u]];
       f.nwords = (uint64_t)g->n / 32 + 1;
-      f.bytes = by ? by + K_FILTER : nullptr;
       items = std::max(items, f.cap);
       pairs = std::max(pairs, f.cap * (uint64_t)f.ncons);
-      for (int q = 0; q < f.ncons; q++) pull_ub = std::max(pull_ub, rows_ub(g, p.qlab[u], f.cons[q].dir));
+      for (int q = 0; q < f.ncons; q++) pull_ub += chunks_of(rows_ub(g, p.qlab[u], f.cons[q].dir));
       any = true;
     }
     if (any)
-      L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), gx_flat(pull_ub, nj), gx_for(items, nj),
+      L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), gx_for(items, nj),
                          gx_for((uint64_t)g->n / 32 + 1, nj, 64), true, false, false});
   }
   // CPI adjacency lists per spanning-tree edge, in BFS order
   for (int j = 1; j < maxk; j++) {
     std::vector<CpiJob> C(nj);
-    uint64_t items = 1, rows = 1;
+    uint64_t items = 1, rows = 0;  // rows: chunks over all jobs
     bool any = false;
     const uint32_t ep = next_epoch(c);
     for (int x = 0; x < nj; x++) {
@@ -879,13 +881,12 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       a.arena_cap = c.ws->cpi_cap;
       a.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
       a.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
-      a.bytes = by ? by + K_CPI : nullptr;
       items = std::max(items, a.cap_p);
-      rows = std::max(rows, rows_ub(g, p.qlab[q], a.dir));
+      rows += chunks_of(rows_ub(g, p.qlab[q], a.dir));
       any = true;
     }
     if (any)
-      L.push_back(Launch{1, R.add(C), nj, gx_scan(items), gx_flat(rows, nj), gx_for(items, nj), 0,
+      L.push_back(Launch{1, R.add(C), nj, gx_scan(items), flat_grid(rows), gx_for(items, nj), 0,
                          true, false, false});
   }
   if (!fast_enum) return;
@@ -950,7 +951,6 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       e.vcap = c.K > 0 ? J.caps.vcap : 0;
       e.thr = nullptr;
       e.d_thr_valid = (const uint32_t*)(J.mem.ctl + CTL_THRVALID);
-      e.bytes = by ? by + (e.last ? K_LAST : K_EXT) : nullptr;
       srcs = std::max(srcs, e.src_cap);
       any_last |= e.last != 0;
       any_inner |= e.last == 0;
@@ -958,7 +958,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
     const size_t off = R.add(E);
     for (int x = 0; x < nj; x++)
       if (E[x].active && E[x].last) jobs[x].last_rec = off + sizeof(ExtJob) * x;
-    L.push_back(Launch{2, off, nj, gx_scan(srcs), gx_flat(1ull << 40, nj), 0, 0, true, any_last,
+    L.push_back(Launch{2, off, nj, gx_scan(srcs), flat_grid(FLAT_GRID_MAX), 0, 0, true, any_last,
                        any_inner});
   }
   // single-vertex patterns
@@ -992,7 +992,6 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       e.d_vcount = J.mem.ctl + CTL_VCOUNT;
       e.vcap = c.K > 0 ? J.caps.vcap : 0;
       e.d_thr_valid = (const uint32_t*)(J.mem.ctl + CTL_THRVALID);
-      e.bytes = by ? by + K_LAST : nullptr;
       items = std::max(items, e.src_cap);
       any = true;
     }
@@ -1026,30 +1025,33 @@ static void run_launches(Ctx& c, const std::vector<Launch>& L) {
         auto* r = (const FilterJob*)(base + l.off);
         if (l.scan) {
           c.tm.run(K_SCAN, [&] { filter_scan(c.st, g, r, l.njobs, l.gx_scan); });
-          c.tm.run(K_PULL, [&] { filter_pull(c.st, g, r, l.njobs, l.gx_work); });
+          c.tm.run(K_PULL, [&] { filter_pull(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_PULL)); });
         }
         c.tm.run(K_OTHER, [&] { filter_clear(c.st, r, l.njobs, l.gx_clear); });
-        c.tm.run(K_FILTER, [&] { filter_compact(c.st, g, r, l.njobs, l.gx_item); });
+        c.tm.run(K_FILTER,
+                 [&] { filter_compact(c.st, g, r, l.njobs, l.gx_item, cls_bytes(c, K_FILTER)); });
         break;
       }
       case 1: {
         auto* r = (const CpiJob*)(base + l.off);
         c.tm.run(K_SCAN, [&] { cpi_scan(c.st, g, r, l.njobs, l.gx_scan); });
-        c.tm.run(K_CPI, [&] { cpi_count(c.st, g, r, l.njobs, l.gx_work); });
+        c.tm.run(K_CPI, [&] { cpi_count(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_CPI)); });
         c.tm.run(K_CPI, [&] { cpi_alloc(c.st, g, r, l.njobs, l.gx_item); });
-        c.tm.run(K_CPI, [&] { cpi_fill(c.st, g, r, l.njobs, l.gx_work); });
+        c.tm.run(K_CPI, [&] { cpi_fill(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_CPI)); });
         break;
       }
       case 2: {
         auto* r = (const ExtJob*)(base + l.off);
         c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, r, l.njobs, l.gx_scan); });
-        if (l.inner_any) c.tm.run(K_EXT, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, false); });
-        if (l.last_any) c.tm.run(K_LAST, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, true); });
+        if (l.inner_any)
+          c.tm.run(K_EXT, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, false, cls_bytes(c, K_EXT)); });
+        if (l.last_any)
+          c.tm.run(K_LAST, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, true, cls_bytes(c, K_LAST)); });
         break;
       }
       case 3: {
         auto* r = (const ExtJob*)(base + l.off);
-        c.tm.run(K_LAST, [&] { ext_single(c.st, g, r, l.njobs, l.gx_work); });
+        c.tm.run(K_LAST, [&] { ext_single(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_LAST)); });
         break;
       }
       case 4: {
@@ -1127,7 +1129,7 @@ static void ensure_vbig(Workspace* ws, uint64_t vcap) {
   ws->vbig_cap = vcap;
 }
 
-// Batched radix select over the jobs in S (at most SEL_JOBS; each with more
+// Batched radix select over the jobs in S (at most MAX_JOBS; each with more
 // than K staged tuples).  threshold == false: the first K of each job, sorted,
 // into S[j].out.  threshold == true: the K-th tuple becomes the job's staging
 // threshold (inclusive) and its staging count restarts at zero.
@@ -1135,7 +1137,7 @@ static void run_select(Ctx& c, std::vector<SelJob>& S, bool threshold) {
   Workspace* ws = c.ws;
   const int nj = (int)S.size();
   if (nj == 0) return;
-  if (nj > SEL_JOBS) throw GfdError{GFD_EINVAL, "internal: selection batch too large"};
+  if (nj > MAX_JOBS) throw GfdError{GFD_EINVAL, "internal: selection batch too large"};
   int maxk = 0;
   uint64_t maxcap = 1;
   for (int j = 0; j < nj; j++) {
@@ -1172,7 +1174,6 @@ static SelJob sel_job(Ctx& c, int k, const int32_t* vbuf, uint64_t* ctl, uint64_
   s.d_outcount = (unsigned long long*)(ctl + CTL_OUTCOUNT);
   s.thr = (int32_t*)(ctl + CTL_THR);
   s.d_thr_valid = (uint32_t*)(ctl + CTL_THRVALID);
-  s.flags = (uint32_t*)(ctl + CTL_FLAGS);
   return s;
 }
 
@@ -1289,8 +1290,10 @@ struct Bounded {
       e.a_begin = A0;
       e.a_end = A1;
       upload_one(e);
-      const int gx = (int)std::max<uint64_t>(1, std::min<uint64_t>((A1 - A0 + LBS_CHUNK - 1) / LBS_CHUNK, 1024));
-      c.tm.run(e.last ? K_LAST : K_EXT, [&] { ext_run(c.st, g, rec, 1, gx, e.last != 0); });
+      const int cls = e.last ? K_LAST : K_EXT;
+      c.tm.run(cls, [&] {
+        ext_run(c.st, g, rec, 1, flat_grid(chunks_of(A1 - A0)), e.last != 0, cls_bytes(c, cls));
+      });
       if (!e.last) {
         const uint64_t N = rd(CTL_LEVEL_N + i + 1);
         if (c.stats) c.stats->partials += N;
@@ -1320,7 +1323,8 @@ struct Bounded {
       const ExtJob* rec = (const ExtJob*)c.ws->jobrec;
       c.tm.run(K_LAST, [&] {
         ext_single(c.st, c.g->dg, rec, 1,
-                   (int)std::max<uint64_t>(1, std::min<uint64_t>((A1 - A0 + BS - 1) / BS, 1024)));
+                   (int)std::max<uint64_t>(1, std::min<uint64_t>((A1 - A0 + BS - 1) / BS, 1024)),
+                   cls_bytes(c, K_LAST));
       });
     }
   }
@@ -1418,13 +1422,15 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     const int n0 = (int)E[0].size(), n1 = (int)E[1].size();
     if (n0)
       c.tm.run(K_LAST, [&] {
-        ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, gx_flat(1ull << 40, n0), true);
+        ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, flat_grid(FLAT_GRID_MAX), true,
+                cls_bytes(c, K_LAST));
       });
     if (n1) {
       uint64_t items = 1;
       for (auto& e : E[1]) items = std::max(items, e.src_cap);
       c.tm.run(K_LAST, [&] {
-        ext_single(c.st, g, (const ExtJob*)(ws->jobrec + b0), n1, gx_for(items, n1));
+        ext_single(c.st, g, (const ExtJob*)(ws->jobrec + b0), n1, gx_for(items, n1),
+                   cls_bytes(c, K_LAST));
       });
     }
     // the jobs whose collection now fits get their first K (sorted, or flagged
@@ -1464,12 +1470,12 @@ static Workspace* acquire_ws(gfd_graph* g, int64_t budget) {
     w->budget = budget;
     w->misc = dalloc<unsigned long long>(16);
     w->err = dalloc<uint32_t>(1);
-    w->sel_state = dalloc<uint32_t>((size_t)SEL_JOBS * SEL_STATE_WORDS);
-    w->sel_hist = dalloc<uint32_t>((size_t)SEL_JOBS * RADIX_BINS);
+    w->sel_state = dalloc<uint32_t>((size_t)MAX_JOBS * SEL_STATE_WORDS);
+    w->sel_hist = dalloc<uint32_t>((size_t)MAX_JOBS * RADIX_BINS);
     w->sel_out = dalloc<int32_t>((size_t)SORT_MAX * MAXK);
-    w->selrec = dalloc<uint8_t>(sizeof(SelJob) * SEL_JOBS);
-    HIPCHK(hipHostMalloc((void**)&w->hselrec, sizeof(SelJob) * SEL_JOBS, hipHostMallocDefault));
-    HIPCHK(hipMemset(w->sel_hist, 0, 4 * (size_t)SEL_JOBS * RADIX_BINS));
+    w->selrec = dalloc<uint8_t>(sizeof(SelJob) * MAX_JOBS);
+    HIPCHK(hipHostMalloc((void**)&w->hselrec, sizeof(SelJob) * MAX_JOBS, hipHostMallocDefault));
+    HIPCHK(hipMemset(w->sel_hist, 0, 4 * (size_t)MAX_JOBS * RADIX_BINS));
     HIPCHK(hipMemset(w->err, 0, 4));
     HIPCHK(hipDeviceSynchronize());
   } catch (...) {
@@ -1521,7 +1527,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       ws->cpi_cap = (uint64_t)std::max<int64_t>(1 << 20, std::min<int64_t>(budget / 16, int64_t(1) << 30) / 4);
       ws->cpi_arena = dalloc<int32_t>(ws->cpi_cap);
     }
-    const int max_batch = o.batched ? SEL_JOBS : 1;
+    const int max_batch = o.batched ? MAX_JOBS : 1;
     const int64_t njobs_hint = std::min<int64_t>(num_specs, max_batch);
     // violation staging per job: a sixteenth of the budget over a full batch
     const uint64_t vdef = (uint64_t)std::max<int64_t>(
@@ -1540,13 +1546,19 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     HIPCHK(hipMemsetAsync(ws->err, 0, 4, c.st));
     // plans, capacities and batches
     std::vector<Job> all(num_specs);
-    uint64_t cap_f = o.frontier_cap ? (uint64_t)o.frontier_cap
-                                    : (uint64_t)std::max<int64_t>(
-                                          4096, std::min<int64_t>(budget / (4 * njobs_hint), int64_t(2) << 30) /
-                                                    (int64_t)per_slot_bytes(MAXK));
+    // a quarter of the budget holds frontiers, shared evenly by the jobs of a
+    // batch that have any (k > 2), each sized for its own pattern size
+    int64_t deep = 0;
+    for (int32_t i = 0; i < num_specs; i++) deep += specs[i].num_vertices > 2;
+    const int64_t fbytes = std::min<int64_t>(
+        budget / (4 * std::max<int64_t>(1, std::min<int64_t>(deep, max_batch))), int64_t(8) << 30);
     for (int32_t i = 0; i < num_specs; i++) {
       all[i].spec = i;
       make_plan(g, specs[i], c.induced, all[i].plan);
+      const uint64_t cap_f =
+          o.frontier_cap ? (uint64_t)o.frontier_cap
+                         : (uint64_t)std::max<int64_t>(
+                               4096, fbytes / (int64_t)per_slot_bytes(all[i].plan.k));
       job_caps(g, all[i].plan, cap_f, vsmall, all[i].caps);
     }
     std::vector<std::vector<int>> batches;

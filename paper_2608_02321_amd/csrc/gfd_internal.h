@@ -30,6 +30,7 @@ constexpr int BS = 256;        // threads per block everywhere
 constexpr int WAVE = 64;       // CDNA wavefront
 constexpr int SCAN_IPT = 8;    // items per thread in the scan
 constexpr int SCAN_TILE = BS * SCAN_IPT;
+constexpr int MAX_JOBS = 64;   // jobs per launch (one batch)
 constexpr int LBS_ROUNDS = 8;  // flat work: rounds of BS positions per located chunk
 constexpr uint64_t LBS_CHUNK = (uint64_t)BS * LBS_ROUNDS;
 constexpr int SORT_MAX = 2048; // violation tuples sorted in one workgroup
@@ -98,7 +99,6 @@ struct FilterJob {
   int32_t* pos;
   uint32_t* bits;        // cleared by filter_clear before the compaction
   uint64_t nwords;
-  unsigned long long* bytes;
 };
 
 // CPI adjacency for spanning-tree edge (p, u): for each v_p in C(p) the
@@ -118,7 +118,6 @@ struct CpiJob {
   uint64_t arena_cap;
   uint32_t* flags;       // bit 2: arena overflow
   JobScan sc;            // over rows of C(p)
-  unsigned long long* bytes;
 };
 
 struct DevLit {
@@ -150,7 +149,8 @@ struct ExtJob {
   int32_t* dst_cols;
   uint64_t dst_cap;
   uint64_t* d_ndst;
-  uint32_t* flags;          // bit0: frontier overflow; bit1: violation staging overflow
+  uint32_t* flags;          // bit0: frontier overflow (a staging overflow shows as
+                            // *d_vcount > vcap)
   int32_t var_pos[MAXK];
   int32_t nx, ny, y_false, collect_only;
   int32_t thr_incl;         // stage t <= thr instead of t < thr
@@ -161,7 +161,6 @@ struct ExtJob {
   uint64_t vcap;
   const int32_t* thr;
   const uint32_t* d_thr_valid;
-  unsigned long long* bytes;
 };
 
 struct TopkJob {
@@ -187,24 +186,32 @@ struct SelJob {
   unsigned long long* d_outcount;
   int32_t* thr;                    // [k]
   uint32_t* d_thr_valid;
-  uint32_t* flags;                 // staging overflow bit (2) cleared with the threshold
 };
 
 // Launch wrappers (gfd_kernels.hip).  All asynchronous on `st`; `jobs` points
-// to `njobs` device-resident job records; gx = blocks per job.
+// to `njobs` (<= MAX_JOBS) device-resident job records.  Per-job kernels run
+// on a (gx, njobs) grid; the flat (load-balanced) ones on a 1-D grid of `grid`
+// blocks shared by all jobs.  `bytes`, when not null, accumulates the
+// algorithmic bytes the kernel touched.
 void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
-void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
-void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
+void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
+                 unsigned long long* bytes);
+void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx,
+                    unsigned long long* bytes);
 // zero the output bitmap of every active job
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx);
 void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
-void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
+void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
+               unsigned long long* bytes);
 void cpi_alloc(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
-void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
+void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
+              unsigned long long* bytes);
 void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx);
-void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx, bool last);
+void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
+             unsigned long long* bytes);
 // k == 1: every member of the root's candidate set is a match.
-void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx);
+void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
+                unsigned long long* bytes);
 void topk_small(hipStream_t st, const TopkJob* jobs, int njobs);
 
 // Batched radix select (grid row = job); requires more than K staged tuples

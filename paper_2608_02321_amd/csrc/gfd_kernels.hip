@@ -286,55 +286,86 @@ __device__ __forceinline__ uint64_t wave_last_le(const uint64_t* __restrict__ P,
   return lo + (uint64_t)__popcll(__ballot(le)) - 1;
 }
 
-// Iterates the flat positions [A0, A1) of one job row: each block takes chunks
-// of LBS_CHUNK positions, locates the chunk's first and last source with two
-// wave-parallel searches, stages their prefix values in LDS and maps each
-// position to (source, offset) with a binary search there.  f(valid, s, o) is
-// called by every thread LBS_ROUNDS times per chunk (uniform trip count).
-// Requires P[N] >= A1.
+// Maps the flat positions [c0, c1) of one job row (c0 < c1, at most
+// LBS_CHUNK of them, P[N] >= c1) to (source, offset): the chunk's first and
+// last source come from two wave-parallel searches, their prefix values are
+// staged in LDS and each position is placed by a binary search there.
+// f(valid, s, o) is called by every thread LBS_ROUNDS times (uniform trip
+// count); the call ends with a barrier.
 template <class F>
-__device__ __forceinline__ void flat_tiles(const uint64_t* __restrict__ P, uint64_t N, uint64_t A0,
-                                           uint64_t A1, LbsShared& sh, F f) {
-  if (N == 0) return;
-  for (uint64_t c0 = A0 + (uint64_t)blockIdx.x * LBS_CHUNK; c0 < A1;
-       c0 += (uint64_t)gridDim.x * LBS_CHUNK) {
-    const uint64_t c1 = c0 + LBS_CHUNK < A1 ? c0 + LBS_CHUNK : A1;
-    if (threadIdx.x < WAVE) {
-      const uint64_t lo = wave_last_le(P, 0, N - 1, c0);
-      if (threadIdx.x == 0) sh.lo = lo;
-    } else if (threadIdx.x < 2 * WAVE) {
-      const uint64_t hi = wave_last_le(P, 0, N - 1, c1 - 1);
-      if (threadIdx.x == WAVE) sh.hi = hi;
-    }
-    __syncthreads();
-    const uint64_t lo = sh.lo, hi = sh.hi;
-    const uint64_t span = hi - lo + 2;  // P[lo .. hi+1]
-    const bool in_lds = span <= (uint64_t)LBS_SLOTS;
-    if (in_lds)
-      for (uint64_t j = threadIdx.x; j < span; j += BS) sh.p[j] = P[lo + j];
-    __syncthreads();
-    for (int r = 0; r < LBS_ROUNDS; r++) {
-      const uint64_t a = c0 + (uint64_t)r * BS + threadIdx.x;
-      const bool valid = a < c1;
-      uint64_t s = 0, o = 0;
-      if (valid) {
-        if (in_lds) {
-          uint32_t l = 0, h = (uint32_t)(span - 2);
-          while (l < h) {
-            const uint32_t mid = (l + h + 1) >> 1;
-            if (sh.p[mid] <= a) l = mid; else h = mid - 1;
-          }
-          s = lo + l;
-          o = a - sh.p[l];
-        } else {
-          s = last_le(P, lo, hi, a);
-          o = a - P[s];
-        }
-      }
-      f(valid, s, o);
-    }
-    __syncthreads();
+__device__ __forceinline__ void flat_chunk(const uint64_t* __restrict__ P, uint64_t N, uint64_t c0,
+                                           uint64_t c1, LbsShared& sh, F f) {
+  if (threadIdx.x < WAVE) {
+    const uint64_t lo = wave_last_le(P, 0, N - 1, c0);
+    if (threadIdx.x == 0) sh.lo = lo;
+  } else if (threadIdx.x < 2 * WAVE) {
+    const uint64_t hi = wave_last_le(P, 0, N - 1, c1 - 1);
+    if (threadIdx.x == WAVE) sh.hi = hi;
   }
+  __syncthreads();
+  const uint64_t lo = sh.lo, hi = sh.hi;
+  const uint64_t span = hi - lo + 2;  // P[lo .. hi+1]
+  const bool in_lds = span <= (uint64_t)LBS_SLOTS;
+  if (in_lds)
+    for (uint64_t j = threadIdx.x; j < span; j += BS) sh.p[j] = P[lo + j];
+  __syncthreads();
+  for (int r = 0; r < LBS_ROUNDS; r++) {
+    const uint64_t a = c0 + (uint64_t)r * BS + threadIdx.x;
+    const bool valid = a < c1;
+    uint64_t s = 0, o = 0;
+    if (valid) {
+      if (in_lds) {
+        uint32_t l = 0, h = (uint32_t)(span - 2);
+        while (l < h) {
+          const uint32_t mid = (l + h + 1) >> 1;
+          if (sh.p[mid] <= a) l = mid; else h = mid - 1;
+        }
+        s = lo + l;
+        o = a - sh.p[l];
+      } else {
+        s = last_le(P, lo, hi, a);
+        o = a - P[s];
+      }
+    }
+    f(valid, s, o);
+  }
+  __syncthreads();
+}
+
+// The flat work of every job of a launch shares one chunk space: job j owns
+// ceil(width_j / LBS_CHUNK) consecutive chunks and the 1-D grid strides over
+// all of them, so the blocks keep working on whichever jobs still have chunks
+// and one large job never runs on a fixed slice of the chip.
+struct ChunkMap {
+  uint64_t cs[MAX_JOBS + 1];  // first chunk of every job; cs[njobs] = total
+};
+
+// Lane j of wave 0 evaluates width(j) (flat positions of job j); ends with a
+// barrier.  njobs <= MAX_JOBS.
+template <class W>
+__device__ __forceinline__ void chunk_map_build(ChunkMap& m, int njobs, W width) {
+  if (threadIdx.x < WAVE) {
+    const int j = (int)threadIdx.x;
+    uint64_t c = j < njobs ? (width(j) + LBS_CHUNK - 1) / LBS_CHUNK : 0ull;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const uint64_t y = __shfl_up(c, (unsigned)d);
+      if (j >= d) c += y;
+    }
+    m.cs[j + 1] = c;
+    if (j == 0) m.cs[0] = 0;
+  }
+  __syncthreads();
+}
+
+// The job owning chunk c (< cs[njobs]): the largest j with cs[j] <= c.
+__device__ __forceinline__ int chunk_job(const ChunkMap& m, int njobs, uint64_t c) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (m.cs[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -392,37 +423,47 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
 }
 
 // One thread per adjacency entry: mark constraint c of item i as met.
-__global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob* __restrict__ jobs) {
+__global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob* __restrict__ jobs,
+                                                    int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
-  const FilterJob& J = jobs[blockIdx.y];
-  if (!J.active || J.ncons == 0) return;
-  const uint64_t NP = filter_items(J) * (uint64_t)J.ncons;
-  const uint64_t T = *J.sc.d_total;
-  const uint32_t nc = (uint32_t)J.ncons;
-  unsigned long long by = 0;
-  flat_tiles(J.sc.P, NP, 0, T, sh, [&](bool valid, uint64_t q, uint64_t o) {
-    if (!valid) return;
-    const uint64_t i = q / nc;
-    const uint32_t c = (uint32_t)(q - i * nc);
-    const PullC& cs = J.cons[c];
-    const int32_t v = filter_item(J, i);
-    const uint32_t* off = cs.dir ? g.in_off : g.out_off;
-    const uint32_t x = off[v] + (uint32_t)o;
-    by += 8;
-    if (cs.elab != ANY) {
-      by += 4;
-      if ((cs.dir ? g.in_lab : g.out_lab)[x] != cs.elab) return;
-    }
-    by += 4;
-    if (member(cs.w, (cs.dir ? g.in_nbr : g.out_nbr)[x], by)) atomicOr(&J.hits[i], 1u << c);
+  __shared__ ChunkMap cm;
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t {
+    return (jobs[j].active && jobs[j].ncons) ? *jobs[j].sc.d_total : 0ull;
   });
-  if (J.bytes) block_add(J.bytes, by);
+  unsigned long long by = 0;
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+    const int jb = chunk_job(cm, njobs, ch);
+    const FilterJob& J = jobs[jb];
+    const uint32_t nc = (uint32_t)J.ncons;
+    const uint64_t NP = filter_items(J) * (uint64_t)nc;
+    const uint64_t T = *J.sc.d_total;
+    const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
+    const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
+    flat_chunk(J.sc.P, NP, c0, c1, sh, [&](bool valid, uint64_t q, uint64_t o) {
+      if (!valid) return;
+      const uint64_t i = q / nc;
+      const uint32_t c = (uint32_t)(q - i * nc);
+      const PullC& cs = J.cons[c];
+      const int32_t v = filter_item(J, i);
+      const uint32_t* off = cs.dir ? g.in_off : g.out_off;
+      const uint32_t x = off[v] + (uint32_t)o;
+      by += 8;
+      if (cs.elab != ANY) {
+        by += 4;
+        if ((cs.dir ? g.in_lab : g.out_lab)[x] != cs.elab) return;
+      }
+      by += 4;
+      if (member(cs.w, (cs.dir ? g.in_nbr : g.out_nbr)[x], by)) atomicOr(&J.hits[i], 1u << c);
+    });
+  }
+  if (bytes) block_add(bytes, by);
 }
 
 // Items meeting the degree filter and every constraint join C(u); each tile
 // reserves its output slots with one atomic add (a set: no fixed order).
 __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
-                                                       const FilterJob* __restrict__ jobs) {
+                                                       const FilterJob* __restrict__ jobs,
+                                                       unsigned long long* bytes) {
   __shared__ unsigned long long s_base;
   const FilterJob& J = jobs[blockIdx.y];
   if (!J.active) return;
@@ -457,7 +498,7 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
     }
     __syncthreads();
   }
-  if (J.bytes) block_add(J.bytes, by);
+  if (bytes) block_add(bytes, by);
 }
 
 __global__ __launch_bounds__(BS) void k_filter_clear(const FilterJob* __restrict__ jobs) {
@@ -471,11 +512,13 @@ __global__ __launch_bounds__(BS) void k_filter_clear(const FilterJob* __restrict
 void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_filter_scan, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
 }
-void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_filter_pull, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
+                 unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_filter_pull, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
-void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_filter_compact, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx,
+                    unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_filter_compact, dim3(gx, njobs), dim3(BS), 0, st, g, jobs, bytes);
 }
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_filter_clear, dim3(gx, njobs), dim3(BS), 0, st, jobs);
@@ -519,20 +562,33 @@ __global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __res
   }, J.sc);
 }
 
-__global__ __launch_bounds__(BS) void k_cpi_count(DevGraph g, const CpiJob* __restrict__ jobs) {
+// Chunk space of the CPI kernels: every adjacency entry of every member of C(p).
+__device__ __forceinline__ uint64_t cpi_width(const CpiJob& J) {
+  return J.active ? *J.sc.d_total : 0ull;
+}
+
+__global__ __launch_bounds__(BS) void k_cpi_count(DevGraph g, const CpiJob* __restrict__ jobs,
+                                                  int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
-  const CpiJob& J = jobs[blockIdx.y];
-  if (!J.active) return;
-  const uint32_t* off = J.dir ? g.in_off : g.out_off;
+  __shared__ ChunkMap cm;
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return cpi_width(jobs[j]); });
   unsigned long long by = 0;
-  flat_tiles(J.sc.P, cpi_sources(J), 0, *J.sc.d_total, sh, [&](bool valid, uint64_t s, uint64_t o) {
-    if (!valid) return;
-    const int32_t vp = J.p.list[s];
-    int32_t v;
-    by += 8;
-    if (cpi_keep(g, J, vp, off[vp] + (uint32_t)o, v, by)) atomicAdd(&J.len[s], 1u);
-  });
-  if (J.bytes) block_add(J.bytes, by);
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+    const int jb = chunk_job(cm, njobs, ch);
+    const CpiJob& J = jobs[jb];
+    const uint32_t* off = J.dir ? g.in_off : g.out_off;
+    const uint64_t T = *J.sc.d_total;
+    const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
+    const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
+    flat_chunk(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o) {
+      if (!valid) return;
+      const int32_t vp = J.p.list[s];
+      int32_t v;
+      by += 8;
+      if (cpi_keep(g, J, vp, off[vp] + (uint32_t)o, v, by)) atomicAdd(&J.len[s], 1u);
+    });
+  }
+  if (bytes) block_add(bytes, by);
 }
 
 // Each tile of sources reserves its lists in the arena with one atomic add.
@@ -562,38 +618,48 @@ __global__ __launch_bounds__(BS) void k_cpi_alloc(DevGraph g, const CpiJob* __re
   }
 }
 
-__global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __restrict__ jobs) {
+__global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __restrict__ jobs,
+                                                 int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
-  const CpiJob& J = jobs[blockIdx.y];
-  if (!J.active) return;
-  const uint32_t* off = J.dir ? g.in_off : g.out_off;
+  __shared__ ChunkMap cm;
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return cpi_width(jobs[j]); });
   unsigned long long by = 0, dummy = 0;
-  flat_tiles(J.sc.P, cpi_sources(J), 0, *J.sc.d_total, sh, [&](bool valid, uint64_t s, uint64_t o) {
-    if (!valid) return;
-    const int32_t vp = J.p.list[s];
-    int32_t v;
-    if (cpi_keep(g, J, vp, off[vp] + (uint32_t)o, v, dummy)) {
-      const uint32_t at = atomicAdd(&J.cur[s], 1u);
-      if (at < J.len[s]) {
-        J.arena[(uint64_t)J.beg[s] + at] = v;
-        by += 4;
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+    const int jb = chunk_job(cm, njobs, ch);
+    const CpiJob& J = jobs[jb];
+    const uint32_t* off = J.dir ? g.in_off : g.out_off;
+    const uint64_t T = *J.sc.d_total;
+    const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
+    const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
+    flat_chunk(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o) {
+      if (!valid) return;
+      const int32_t vp = J.p.list[s];
+      int32_t v;
+      if (cpi_keep(g, J, vp, off[vp] + (uint32_t)o, v, dummy)) {
+        const uint32_t at = atomicAdd(&J.cur[s], 1u);
+        if (at < J.len[s]) {
+          J.arena[(uint64_t)J.beg[s] + at] = v;
+          by += 4;
+        }
       }
-    }
-  });
-  if (J.bytes) block_add(J.bytes, by);
+    });
+  }
+  if (bytes) block_add(bytes, by);
 }
 
 void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_cpi_scan, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
 }
-void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_cpi_count, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
+               unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_cpi_count, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void cpi_alloc(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_cpi_alloc, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
 }
-void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_cpi_fill, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
+              unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_cpi_fill, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,14 +731,22 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
 }
 
 // Wave-aggregated append of violating tuples to the job's staging buffer.
-__device__ __forceinline__ void stage(const ExtJob& J, bool want, const int32_t (&t)[MAXK]) {
+// `full` (wave-uniform) becomes true once this wave has seen the buffer fill
+// up; from then on the wave only notes the overflow, so a GFD with millions
+// of violations does not keep hammering one counter.  The count only grows
+// within a pass, and every overflowing append pushes it past vcap, which is
+// how the host detects the overflow.
+__device__ __forceinline__ void stage(const ExtJob& J, bool want, const int32_t (&t)[MAXK],
+                                      bool& full) {
   const uint64_t m = __ballot(want);
   if (m == 0) return;
+  if (full) return;
   const int leader = __ffsll((long long)m) - 1;
+  const unsigned long long cnt = (unsigned long long)__popcll(m);
   unsigned long long base = 0;
-  if ((int)lane() == leader)
-    base = atomicAdd((unsigned long long*)J.d_vcount, (unsigned long long)__popcll(m));
+  if ((int)lane() == leader) base = atomicAdd((unsigned long long*)J.d_vcount, cnt);
   base = __shfl(base, leader);
+  if (base + cnt >= J.vcap) full = true;
   if (want) {
     const uint64_t slot = base + rank_below(m);
     if (slot < J.vcap) {
@@ -680,11 +754,10 @@ __device__ __forceinline__ void stage(const ExtJob& J, bool want, const int32_t 
 #pragma unroll
       for (int v = 0; v < MAXK; v++)
         if (v < J.k) dst[v] = t[v];
-    } else {
-      atomicOr(J.flags, 2u);
     }
   }
 }
+
 
 __device__ __forceinline__ void flush_acc(unsigned long long* counters, FinalAcc acc) {
   __shared__ unsigned long long s_acc[4][BS / WAVE];
@@ -724,93 +797,115 @@ __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __res
   }, J.sc);
 }
 
+// Attempt window of one job in the launch's chunk space (0 for a job of the
+// other variant: a job at its last level has no next frontier, and the
+// inner-level variant skips it, and the other way round).
 template <bool LAST>
-__global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __restrict__ jobs) {
-  __shared__ LbsShared sh;
-  __shared__ unsigned long long s_wcnt[BS / WAVE];
-  __shared__ unsigned long long s_base;
-  const ExtJob& J = jobs[blockIdx.y];
-  // one launch per variant: a job whose level is its last is skipped by the
-  // inner-level variant (it has no next frontier) and the other way round
-  if (!J.active || (J.last != 0) != LAST) return;
-  const uint64_t N = ext_sources(J);
-  const uint64_t T = N ? *J.sc.d_total : 0;
+__device__ __forceinline__ uint64_t ext_width(const ExtJob& J) {
+  if (!J.active || (J.last != 0) != LAST) return 0;
+  const uint64_t T = ext_sources(J) ? *J.sc.d_total : 0ull;
   const uint64_t A1 = J.a_end < T ? J.a_end : T;
-  FinalAcc acc{0, 0, 0, 0};
-  unsigned long long by = 0;
-  int32_t thr[MAXK];
-  bool thr_on = false;
-  if (LAST) {
-    thr_on = J.thr != nullptr && *J.d_thr_valid != 0;
-#pragma unroll
-    for (int v = 0; v < MAXK; v++) thr[v] = thr_on && v < J.k ? J.thr[v] : 0;
-  }
+  return A1 > J.a_begin ? A1 - J.a_begin : 0ull;
+}
+
+template <bool LAST>
+__global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __restrict__ jobs,
+                                                int njobs, unsigned long long* bytes) {
+  __shared__ LbsShared sh;
+  __shared__ ChunkMap cm;
+  __shared__ unsigned long long s_wcnt[BS / WAVE];
+  __shared__ unsigned long long s_woff[BS / WAVE];
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return ext_width<LAST>(jobs[j]); });
   const uint32_t wv = threadIdx.x / WAVE;
-  const int i = J.i;
-  flat_tiles(J.sc.P, N, J.a_begin, A1, sh, [&](bool valid, uint64_t s, uint64_t o) {
-    int32_t h[MAXK];
-    bool ok = false;
-    if (valid) {
-      const int32_t v = J.cpi_ent[(uint64_t)J.begs[s] + o];
-      // the CPI entry; the source's list start, prefix and partial once per source
-      by += 4 + (o == 0 ? 12ull + 4ull * (uint64_t)i : 0ull);
-      ok = true;
+  unsigned long long by = 0;
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+    const int jb = chunk_job(cm, njobs, ch);
+    const ExtJob& J = jobs[jb];
+    const uint64_t N = ext_sources(J);
+    const uint64_t T = *J.sc.d_total;  // N > 0: the job owns chunks
+    const uint64_t A1 = J.a_end < T ? J.a_end : T;
+    const uint64_t c0 = J.a_begin + (ch - cm.cs[jb]) * LBS_CHUNK;
+    const uint64_t c1 = c0 + LBS_CHUNK < A1 ? c0 + LBS_CHUNK : A1;
+    const int i = J.i;
+    FinalAcc acc{0, 0, 0, 0};
+    int32_t thr[MAXK];
+    bool thr_on = false, full = false;
+    if (LAST) {
+      thr_on = J.thr != nullptr && *J.d_thr_valid != 0;
 #pragma unroll
-      for (int j = 0; j < MAXK; j++) {
-        h[j] = (j < i) ? J.src_cols[(uint64_t)j * J.src_stride + s] : v;
-        if (j < i && h[j] == v) ok = false;
-      }
-      for (int c = 0; c < J.nchk && ok; c++) {
-        const int32_t hw = pick(h, J.chk_pos[c]);
-        if (J.chk_fwd[c] != PC_FREE) ok = constraint_ok(edge_label(g, hw, v, by), J.chk_fwd[c]);
-        if (ok && J.chk_bwd[c] != PC_FREE)
-          ok = constraint_ok(edge_label(g, v, hw, by), J.chk_bwd[c]);
-      }
+      for (int v = 0; v < MAXK; v++) thr[v] = thr_on && v < J.k ? J.thr[v] : 0;
     }
-    if (!LAST) {  // block-aggregated append to the next frontier
-      const uint64_t m = __ballot(ok);
-      if (lane() == 0) s_wcnt[wv] = (unsigned long long)__popcll(m);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        unsigned long long tot = 0;
-        for (int w = 0; w < BS / WAVE; w++) tot += s_wcnt[w];
-        s_base = tot ? atomicAdd((unsigned long long*)J.d_ndst, tot) : 0ull;
-      }
-      __syncthreads();
-      if (ok) {
-        unsigned long long slot = s_base + rank_below(m);
-        for (uint32_t w = 0; w < wv; w++) slot += s_wcnt[w];
-        if (slot < J.dst_cap) {
+    flat_chunk(J.sc.P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o) {
+      int32_t h[MAXK];
+      bool ok = false;
+      if (valid) {
+        const int32_t v = J.cpi_ent[(uint64_t)J.begs[s] + o];
+        // the CPI entry; the source's list start, prefix and partial once per source
+        by += 4 + (o == 0 ? 12ull + 4ull * (uint64_t)i : 0ull);
+        ok = true;
 #pragma unroll
-          for (int j = 0; j < MAXK; j++)
-            if (j <= i) J.dst_cols[(uint64_t)j * J.dst_cap + slot] = h[j];
-          by += 4ull * (uint64_t)(i + 1);
-        } else {
-          atomicOr(J.flags, 1u);
+        for (int j = 0; j < MAXK; j++) {
+          h[j] = (j < i) ? J.src_cols[(uint64_t)j * J.src_stride + s] : v;
+          if (j < i && h[j] == v) ok = false;
+        }
+        for (int c = 0; c < J.nchk && ok; c++) {
+          const int32_t hw = pick(h, J.chk_pos[c]);
+          if (J.chk_fwd[c] != PC_FREE) ok = constraint_ok(edge_label(g, hw, v, by), J.chk_fwd[c]);
+          if (ok && J.chk_bwd[c] != PC_FREE)
+            ok = constraint_ok(edge_label(g, v, hw, by), J.chk_bwd[c]);
         }
       }
-    } else {
-      int32_t t[MAXK];
-      bool want = false;
-      if (ok) {
-        FinalAcc one{0, 0, 0, 0};
-        want = finalize(g, J, h, t, one, thr_on, thr, by);
-        if (!J.collect_only) {
-          acc.match += one.match;
-          acc.viol += one.viol;
-          acc.mfp += one.mfp;
-          acc.vfp += one.vfp;
+      if (!LAST) {  // block-aggregated append to the next frontier
+        // s_wcnt is read only by thread 0 before the second barrier and s_woff
+        // only written by it between the barriers, so a wave running ahead
+        // into the next round cannot overwrite what a slower wave still reads
+        const uint64_t m = __ballot(ok);
+        if (lane() == 0) s_wcnt[wv] = (unsigned long long)__popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          unsigned long long tot = 0;
+          for (int w = 0; w < BS / WAVE; w++) tot += s_wcnt[w];
+          unsigned long long base = tot ? atomicAdd((unsigned long long*)J.d_ndst, tot) : 0ull;
+          if (tot && base + tot > J.dst_cap) atomicOr(J.flags, 1u);  // the job is redone bounded
+          for (int w = 0; w < BS / WAVE; w++) {
+            s_woff[w] = base;
+            base += s_wcnt[w];
+          }
         }
+        __syncthreads();
+        if (ok) {
+          const unsigned long long slot = s_woff[wv] + rank_below(m);
+          if (slot < J.dst_cap) {
+#pragma unroll
+            for (int j = 0; j < MAXK; j++)
+              if (j <= i) J.dst_cols[(uint64_t)j * J.dst_cap + slot] = h[j];
+            by += 4ull * (uint64_t)(i + 1);
+          }
+        }
+      } else {
+        int32_t t[MAXK];
+        bool want = false;
+        if (ok) {
+          FinalAcc one{0, 0, 0, 0};
+          want = finalize(g, J, h, t, one, thr_on, thr, by);
+          if (!J.collect_only) {
+            acc.match += one.match;
+            acc.viol += one.viol;
+            acc.mfp += one.mfp;
+            acc.vfp += one.vfp;
+          }
+        }
+        stage(J, want, t, full);
       }
-      stage(J, want, t);
-    }
-  });
-  if (LAST && !J.collect_only) flush_acc(J.counters, acc);
-  if (J.bytes) block_add(J.bytes, by);
+    });
+    if (LAST && !J.collect_only) flush_acc(J.counters, acc);
+  }
+  if (bytes) block_add(bytes, by);
 }
 
 // k == 1: every member of C(root) is a match; the window is over list indices.
-__global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __restrict__ jobs) {
+__global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __restrict__ jobs,
+                                                   unsigned long long* bytes) {
   const ExtJob& J = jobs[blockIdx.y];
   if (!J.active) return;
   uint64_t N = ext_sources(J);
@@ -822,6 +917,7 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
   const bool thr_on = J.thr != nullptr && *J.d_thr_valid != 0;
 #pragma unroll
   for (int v = 0; v < MAXK; v++) thr[v] = thr_on && v < J.k ? J.thr[v] : 0;
+  bool full = false;
   const uint64_t stride = (uint64_t)gridDim.x * BS;
   const uint64_t rounds = (N - I0 + stride - 1) / stride;  // uniform trip count for the ballot
   for (uint64_t r = 0; r < rounds; r++) {
@@ -842,23 +938,25 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
         acc.vfp += one.vfp;
       }
     }
-    stage(J, want, t);
+    stage(J, want, t, full);
   }
   if (!J.collect_only) flush_acc(J.counters, acc);
-  if (J.bytes) block_add(J.bytes, by);
+  if (bytes) block_add(bytes, by);
 }
 
 void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_ext_scan, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
 }
-void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx, bool last) {
+void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
+             unsigned long long* bytes) {
   if (last)
-    hipLaunchKernelGGL(k_ext_run<true>, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+    hipLaunchKernelGGL(k_ext_run<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
   else
-    hipLaunchKernelGGL(k_ext_run<false>, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+    hipLaunchKernelGGL(k_ext_run<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
-void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_ext_single, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
+                unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_ext_single, dim3(gx, njobs), dim3(BS), 0, st, g, jobs, bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -1056,7 +1154,6 @@ __global__ void k_sel_thr(const SelJob* __restrict__ jobs) {
   if (threadIdx.x == 0) {
     *J.d_thr_valid = 1;
     *J.d_vcount = 0;
-    atomicAnd(J.flags, ~2u);
   }
 }
 
