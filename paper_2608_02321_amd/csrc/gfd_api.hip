@@ -87,7 +87,6 @@ enum {
   CTL_THR = 48 /* 4 words = 8 int32 */
 };
 
-constexpr int MAX_JOBS = 64;         // jobs per batched selection (= largest batch)
 constexpr int SEL_STATE_WORDS = 16;
 
 struct Workspace {

@@ -112,8 +112,9 @@ __device__ __forceinline__ bool constraint_ok(int32_t found, int32_t code) {
   return found != NOEDGE && (code == ANY || found == code);
 }
 
-__device__ __forceinline__ bool member(const CandSet& c, int32_t x, unsigned long long& by) {
-  by += 4;
+// Membership bitmaps (n bits, 512 KB at 4M vertices) stay in L2: their probes
+// count no algorithmic HBM bytes.
+__device__ __forceinline__ bool member(const CandSet& c, int32_t x) {
   return (c.bits[(uint32_t)x >> 5] >> ((uint32_t)x & 31u)) & 1u;
 }
 
@@ -447,13 +448,10 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const int32_t v = filter_item(J, i);
       const uint32_t* off = cs.dir ? g.in_off : g.out_off;
       const uint32_t x = off[v] + (uint32_t)o;
-      by += 8;
-      if (cs.elab != ANY) {
-        by += 4;
-        if ((cs.dir ? g.in_lab : g.out_lab)[x] != cs.elab) return;
-      }
-      by += 4;
-      if (member(cs.w, (cs.dir ? g.in_nbr : g.out_nbr)[x], by)) atomicOr(&J.hits[i], 1u << c);
+      // per row: item and its two offsets; per entry: neighbour (+ label)
+      by += (o == 0 ? 12 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
+      if (cs.elab != ANY && (cs.dir ? g.in_lab : g.out_lab)[x] != cs.elab) return;
+      if (member(cs.w, (cs.dir ? g.in_nbr : g.out_nbr)[x])) atomicOr(&J.hits[i], 1u << c);
     });
   }
   if (bytes) block_add(bytes, by);
@@ -542,7 +540,7 @@ __device__ __forceinline__ bool cpi_keep(const DevGraph& g, const CpiJob& J, int
     by += 4;
     if ((J.dir ? g.in_lab : g.out_lab)[x] != J.prim) return false;
   }
-  if (!member(J.u, v, by)) return false;
+  if (!member(J.u, v)) return false;
   if (J.other == PC_FREE) return true;
   // dir 0 scanned vp -> v, so the reverse is v -> vp; dir 1 the opposite
   const int32_t r = J.dir ? edge_label(g, vp, v, by) : edge_label(g, v, vp, by);
@@ -704,12 +702,12 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
   bool X = true, Y = !J.y_false;
   for (int j = 0; j < J.nx && X; j++) {
     X = literal_holds(g, J.lit[j], h);
-    by += 8;
+    by += J.lit[j].kind == 0 ? 4 : 8;  // the attribute values read
   }
   if (X && Y)
     for (int j = 0; j < J.ny && Y; j++) {
       Y = literal_holds(g, J.lit[J.nx + j], h);
-      by += 8;
+      by += J.lit[J.nx + j].kind == 0 ? 4 : 8;
     }
   acc.match += 1;
   acc.mfp += hs;
