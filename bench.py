@@ -66,6 +66,9 @@ def main():
                     help="skip the one-at-a-time comparison")
     ap.add_argument("--no-timing", action="store_true",
                     help="no HIP events at all (no roofline line)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB read + 1 GiB write elementwise kernel "
+                         "(int32 negation) three times: the calibration run for HBM counters")
     ap.add_argument("--per-gfd", type=int, default=0, metavar="N",
                     help="diagnostic: validate each GFD alone with statistics and print the "
                          "N slowest to stderr")
@@ -80,6 +83,16 @@ def main():
 
     import torch
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = 1 << 28  # int32 elements: 1 GiB in, 1 GiB out per launch
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe": {"launches": 3, "read_bytes_per_launch": 4 * n,
+                                         "write_bytes_per_launch": 4 * n}}), flush=True)
+        return
     import paper_2608_02321_amd as P
     from paper_2608_02321_amd._binding import KERNEL_CLASSES
     from synth import configs
