@@ -238,6 +238,24 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     std::vector<uint32_t> fill(lab_off.begin(), lab_off.end() - 1);
     for (int64_t v = 0; v < n; v++) lab_vtx[fill[vlabel[v]]++] = (int32_t)v;
   }
+  // label-ordered view: the rows of lab_vtx[0..n) laid out in that order, so
+  // the rows of one label bucket form one contiguous slice
+  std::vector<uint32_t> lv_out_off(n + 1, 0), lv_in_off(n + 1, 0);
+  std::vector<int32_t> lv_out_nbr(m), lv_out_lab(m), lv_in_nbr(m), lv_in_lab(m);
+  for (int64_t p = 0; p < n; p++) {
+    const int32_t v = lab_vtx[p];
+    lv_out_off[p + 1] = lv_out_off[p] + (out_off[v + 1] - out_off[v]);
+    lv_in_off[p + 1] = lv_in_off[p] + (in_off[v + 1] - in_off[v]);
+  }
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int64_t p = a; p < b; p++) {
+      const int32_t v = lab_vtx[p];
+      std::memcpy(&lv_out_nbr[lv_out_off[p]], &out_nbr[out_off[v]], 4 * (out_off[v + 1] - out_off[v]));
+      std::memcpy(&lv_out_lab[lv_out_off[p]], &out_lab[out_off[v]], 4 * (out_off[v + 1] - out_off[v]));
+      std::memcpy(&lv_in_nbr[lv_in_off[p]], &in_nbr[in_off[v]], 4 * (in_off[v + 1] - in_off[v]));
+      std::memcpy(&lv_in_lab[lv_in_off[p]], &in_lab[in_off[v]], 4 * (in_off[v + 1] - in_off[v]));
+    }
+  });
   std::vector<int32_t> attr_flat((size_t)num_attrs * n);
   for (int32_t a = 0; a < num_attrs; a++)
     std::memcpy(attr_flat.data() + (size_t)a * n, attr[a], sizeof(int32_t) * n);
@@ -266,6 +284,12 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     g->dg.attr = (const int32_t*)up(attr_flat.data(), 4 * attr_flat.size());
     g->dg.lab_off = (const uint32_t*)up(lab_off.data(), 4 * lab_off.size());
     g->dg.lab_vtx = (const int32_t*)up(lab_vtx.data(), 4 * n);
+    g->dg.lv_out_off = (const uint32_t*)up(lv_out_off.data(), 4 * (n + 1));
+    g->dg.lv_out_nbr = (const int32_t*)up(lv_out_nbr.data(), 4 * m);
+    g->dg.lv_out_lab = (const int32_t*)up(lv_out_lab.data(), 4 * m);
+    g->dg.lv_in_off = (const uint32_t*)up(lv_in_off.data(), 4 * (n + 1));
+    g->dg.lv_in_nbr = (const int32_t*)up(lv_in_nbr.data(), 4 * m);
+    g->dg.lv_in_lab = (const int32_t*)up(lv_in_lab.data(), 4 * m);
     HIPCHK(hipStreamSynchronize(st));
     g->lab_off = std::move(lab_off);
     g->lab_out_sum = std::move(lab_out);
@@ -796,7 +820,11 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.min_out = p.min_out[u];
       f.min_in = p.min_in[u];
       const uint64_t bs = J.caps.cap_u[u];
-      f.list = p.qlab[u] == ANY ? nullptr : g->dg.lab_vtx + (bs ? g->lab_off[p.qlab[u]] : 0);
+      // top-down items: the whole bucket, i.e. consecutive rows of the
+      // label-ordered view (all of V for a wildcard)
+      f.base = (p.qlab[u] == ANY || bs == 0) ? 0u : g->lab_off[p.qlab[u]];
+      f.list = p.qlab[u] == ANY ? nullptr : g->dg.lab_vtx + f.base;
+      f.direct = 1;
       f.d_n = nullptr;
       f.n_host = f.cap = bs;
       f.hits = J.mem.hits;

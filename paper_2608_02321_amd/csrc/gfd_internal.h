@@ -52,6 +52,14 @@ struct DevGraph {
   const int32_t* attr;      // [num_attrs * n]
   const uint32_t* lab_off;  // [num_vlabels+1]
   const int32_t* lab_vtx;   // [n], vertices grouped by label, ascending ids
+  // label-ordered view: row p is the row of lab_vtx[p], so one label bucket's
+  // rows are one contiguous slice of these arrays
+  const uint32_t* lv_out_off;  // [n+1]
+  const int32_t* lv_out_nbr;   // [m]
+  const int32_t* lv_out_lab;   // [m]
+  const uint32_t* lv_in_off;   // [n+1]
+  const int32_t* lv_in_nbr;    // [m]
+  const int32_t* lv_in_lab;    // [m]
 };
 
 // A candidate set C(u): its members (list, *cnt), their positions in the list
@@ -91,6 +99,11 @@ struct FilterJob {
   const int32_t* list;   // items: nullptr = identity 0..n_host-1
   const uint64_t* d_n;   // device item count (nullptr: n_host)
   uint64_t n_host, cap;  // cap bounds the item count
+  // direct: the items are the consecutive rows base .. base+n_host-1 of the
+  // label-ordered view (list = lab_vtx + base), or of the plain CSR when list
+  // is nullptr; their adjacency is then one contiguous slice and needs no scan
+  int32_t direct;
+  uint32_t base;
   PullC cons[MAXCONS];
   uint32_t* hits;        // [cap], bit c set when constraint c is met
   JobScan sc;            // over (constraint, item) pairs

@@ -258,8 +258,9 @@ struct LbsShared {
 };
 
 // largest s in [lo, hi] with P[s] <= a (P non-decreasing, P[lo] <= a)
-__device__ __forceinline__ uint64_t last_le(const uint64_t* __restrict__ P, uint64_t lo,
-                                            uint64_t hi, uint64_t a) {
+template <class T>
+__device__ __forceinline__ uint64_t last_le(const T* __restrict__ P, uint64_t lo, uint64_t hi,
+                                            uint64_t a) {
   while (lo < hi) {
     const uint64_t mid = (lo + hi + 1) >> 1;
     if (P[mid] <= a) lo = mid; else hi = mid - 1;
@@ -270,8 +271,9 @@ __device__ __forceinline__ uint64_t last_le(const uint64_t* __restrict__ P, uint
 // The same search done by one whole wave: every round samples 64 evenly spaced
 // prefix values at once and keeps the stretch that holds the answer, so a
 // search over N sources costs about log64(N) dependent loads.
-__device__ __forceinline__ uint64_t wave_last_le(const uint64_t* __restrict__ P, uint64_t lo,
-                                                 uint64_t hi, uint64_t a) {
+template <class T>
+__device__ __forceinline__ uint64_t wave_last_le(const T* __restrict__ P, uint64_t lo, uint64_t hi,
+                                                 uint64_t a) {
   while (hi - lo >= WAVE) {
     const uint64_t step = (hi - lo) / WAVE + 1;
     uint64_t idx = lo + (uint64_t)(lane() + 1) * step;
@@ -287,14 +289,14 @@ __device__ __forceinline__ uint64_t wave_last_le(const uint64_t* __restrict__ P,
   return lo + (uint64_t)__popcll(__ballot(le)) - 1;
 }
 
-// Maps the flat positions [c0, c1) of one job row (c0 < c1, at most
-// LBS_CHUNK of them, P[N] >= c1) to (source, offset): the chunk's first and
-// last source come from two wave-parallel searches, their prefix values are
-// staged in LDS and each position is placed by a binary search there.
-// f(valid, s, o) is called by every thread LBS_ROUNDS times (uniform trip
-// count); the call ends with a barrier.
-template <class F>
-__device__ __forceinline__ void flat_chunk(const uint64_t* __restrict__ P, uint64_t N, uint64_t c0,
+// Maps the flat positions [c0, c1) of one job row (P[0] <= c0 < c1 <= P[N],
+// at most LBS_CHUNK of them) to (source, offset): the chunk's first and last
+// source come from two wave-parallel searches, their prefix values are staged
+// in LDS and each position is placed by a binary search there.
+// f(valid, s, o, a) -- position a = P[s] + o -- is called by every thread
+// LBS_ROUNDS times (uniform trip count); the call ends with a barrier.
+template <class T, class F>
+__device__ __forceinline__ void flat_chunk(const T* __restrict__ P, uint64_t N, uint64_t c0,
                                            uint64_t c1, LbsShared& sh, F f) {
   if (threadIdx.x < WAVE) {
     const uint64_t lo = wave_last_le(P, 0, N - 1, c0);
@@ -328,7 +330,7 @@ __device__ __forceinline__ void flat_chunk(const uint64_t* __restrict__ P, uint6
         o = a - P[s];
       }
     }
-    f(valid, s, o);
+    f(valid, s, o, a);
   }
   __syncthreads();
 }
@@ -341,13 +343,17 @@ struct ChunkMap {
   uint64_t cs[MAX_JOBS + 1];  // first chunk of every job; cs[njobs] = total
 };
 
-// Lane j of wave 0 evaluates width(j) (flat positions of job j); ends with a
+__device__ __forceinline__ uint64_t chunks_of(uint64_t positions) {
+  return (positions + LBS_CHUNK - 1) / LBS_CHUNK;
+}
+
+// Lane j of wave 0 evaluates chunks(j), the chunk count of job j; ends with a
 // barrier.  njobs <= MAX_JOBS.
 template <class W>
-__device__ __forceinline__ void chunk_map_build(ChunkMap& m, int njobs, W width) {
+__device__ __forceinline__ void chunk_map_build(ChunkMap& m, int njobs, W chunks) {
   if (threadIdx.x < WAVE) {
     const int j = (int)threadIdx.x;
-    uint64_t c = j < njobs ? (width(j) + LBS_CHUNK - 1) / LBS_CHUNK : 0ull;
+    uint64_t c = j < njobs ? chunks(j) : 0ull;
 #pragma unroll
     for (int d = 1; d < WAVE; d <<= 1) {
       const uint64_t y = __shfl_up(c, (unsigned)d);
@@ -400,27 +406,71 @@ __device__ __forceinline__ uint64_t filter_items(const FilterJob& J) {
 __device__ __forceinline__ int32_t filter_item(const FilterJob& J, uint64_t i) {
   return J.list ? J.list[i] : (int32_t)i;
 }
-__device__ __forceinline__ bool degree_ok(const DevGraph& g, const FilterJob& J, int32_t v) {
-  if (J.min_out > 0 && (int32_t)(g.out_off[v + 1] - g.out_off[v]) < J.min_out) return false;
-  if (J.min_in > 0 && (int32_t)(g.in_off[v + 1] - g.in_off[v]) < J.min_in) return false;
+
+// Adjacency rows of one direction.
+struct Rows {
+  const uint32_t* off;
+  const int32_t* nbr;
+  const int32_t* lab;
+};
+__device__ __forceinline__ Rows plain_rows(const DevGraph& g, int dir) {
+  return dir ? Rows{g.in_off, g.in_nbr, g.in_lab} : Rows{g.out_off, g.out_nbr, g.out_lab};
+}
+// Rows of a direct job's items, indexed base + i.
+__device__ __forceinline__ Rows direct_rows(const DevGraph& g, const FilterJob& J, int dir) {
+  if (!J.list) return plain_rows(g, dir);
+  return dir ? Rows{g.lv_in_off, g.lv_in_nbr, g.lv_in_lab}
+             : Rows{g.lv_out_off, g.lv_out_nbr, g.lv_out_lab};
+}
+
+// Degree filter of item i (vertex v): for a direct job the row offsets are
+// read in item order (coalesced), otherwise gathered by vertex id.
+__device__ __forceinline__ bool degree_ok(const DevGraph& g, const FilterJob& J, uint64_t i,
+                                          int32_t v, unsigned long long& by) {
+  const uint64_t r = J.direct ? J.base + i : (uint64_t)v;
+  if (J.min_out > 0) {
+    const uint32_t* off = J.direct ? direct_rows(g, J, 0).off : g.out_off;
+    by += 8;
+    if ((int32_t)(off[r + 1] - off[r]) < J.min_out) return false;
+  }
+  if (J.min_in > 0) {
+    const uint32_t* off = J.direct ? direct_rows(g, J, 1).off : g.in_off;
+    by += 8;
+    if ((int32_t)(off[r + 1] - off[r]) < J.min_in) return false;
+  }
   return true;
 }
 
-// Row lengths of (item, constraint) pairs, item-major; clears the hit masks.
+// Row lengths of (item, constraint) pairs, item-major, and cleared hit masks.
+// A direct job needs no scan (its rows are contiguous): only the clearing.
 __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob* __restrict__ jobs) {
   const FilterJob& J = jobs[blockIdx.y];
   if (!J.active || J.ncons == 0) return;
   const uint64_t N = filter_items(J);
+  if (J.direct) {
+    for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < N;
+         i += (uint64_t)gridDim.x * BS)
+      J.hits[i] = 0;
+    return;
+  }
   const uint32_t nc = (uint32_t)J.ncons;
+  unsigned long long by = 0;
   job_scan(N * nc, [&](uint64_t q) -> uint32_t {
     const uint64_t i = q / nc;
     const uint32_t c = (uint32_t)(q - i * nc);
     const int32_t v = filter_item(J, i);
     if (c == 0) J.hits[i] = 0;
-    if (!degree_ok(g, J, v)) return 0u;
+    if (!degree_ok(g, J, i, v, by)) return 0u;
     const uint32_t* off = J.cons[c].dir ? g.in_off : g.out_off;
     return off[v + 1] - off[v];
   }, J.sc);
+}
+
+// Flat entries of constraint c of a direct job: its items' rows in one slice.
+__device__ __forceinline__ uint64_t direct_span(const DevGraph& g, const FilterJob& J, int c,
+                                                const uint32_t*& P) {
+  P = direct_rows(g, J, J.cons[c].dir).off + J.base;
+  return (uint64_t)(P[J.n_host] - P[0]);
 }
 
 // One thread per adjacency entry: mark constraint c of item i as met.
@@ -429,30 +479,59 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
   __shared__ LbsShared sh;
   __shared__ ChunkMap cm;
   chunk_map_build(cm, njobs, [&](int j) -> uint64_t {
-    return (jobs[j].active && jobs[j].ncons) ? *jobs[j].sc.d_total : 0ull;
+    const FilterJob& J = jobs[j];
+    if (!J.active || !J.ncons) return 0ull;
+    if (!J.direct) return chunks_of(*J.sc.d_total);
+    uint64_t ch = 0;
+    const uint32_t* P;
+    for (int c = 0; c < J.ncons; c++) ch += chunks_of(direct_span(g, J, c, P));
+    return ch;
   });
   unsigned long long by = 0;
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
     const int jb = chunk_job(cm, njobs, ch);
     const FilterJob& J = jobs[jb];
-    const uint32_t nc = (uint32_t)J.ncons;
-    const uint64_t NP = filter_items(J) * (uint64_t)nc;
-    const uint64_t T = *J.sc.d_total;
-    const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
-    const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
-    flat_chunk(J.sc.P, NP, c0, c1, sh, [&](bool valid, uint64_t q, uint64_t o) {
-      if (!valid) return;
-      const uint64_t i = q / nc;
-      const uint32_t c = (uint32_t)(q - i * nc);
+    uint64_t r = ch - cm.cs[jb];
+    if (J.direct) {
+      // constraint c, chunk r of its slice; positions are entries of the view
+      int c = 0;
+      const uint32_t* P;
+      uint64_t T = direct_span(g, J, 0, P);
+      while (r >= chunks_of(T)) {
+        r -= chunks_of(T);
+        T = direct_span(g, J, ++c, P);
+      }
       const PullC& cs = J.cons[c];
-      const int32_t v = filter_item(J, i);
-      const uint32_t* off = cs.dir ? g.in_off : g.out_off;
-      const uint32_t x = off[v] + (uint32_t)o;
-      // per row: item and its two offsets; per entry: neighbour (+ label)
-      by += (o == 0 ? 12 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
-      if (cs.elab != ANY && (cs.dir ? g.in_lab : g.out_lab)[x] != cs.elab) return;
-      if (member(cs.w, (cs.dir ? g.in_nbr : g.out_nbr)[x])) atomicOr(&J.hits[i], 1u << c);
-    });
+      const Rows rw = direct_rows(g, J, cs.dir);
+      const uint64_t c0 = P[0] + r * LBS_CHUNK;
+      const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
+      flat_chunk(P, J.n_host, c0, c1, sh, [&](bool valid, uint64_t i, uint64_t o, uint64_t x) {
+        if (!valid) return;
+        // per entry: neighbour (+ label); the items' offsets stream once
+        by += (o == 0 ? 4 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
+        if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
+        if (member(cs.w, rw.nbr[x])) atomicOr(&J.hits[i], 1u << c);
+      });
+    } else {
+      const uint32_t nc = (uint32_t)J.ncons;
+      const uint64_t NP = filter_items(J) * (uint64_t)nc;
+      const uint64_t T = *J.sc.d_total;
+      const uint64_t c0 = r * LBS_CHUNK;
+      const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
+      flat_chunk(J.sc.P, NP, c0, c1, sh, [&](bool valid, uint64_t q, uint64_t o, uint64_t) {
+        if (!valid) return;
+        const uint64_t i = q / nc;
+        const uint32_t c = (uint32_t)(q - i * nc);
+        const PullC& cs = J.cons[c];
+        const int32_t v = filter_item(J, i);
+        const Rows rw = plain_rows(g, cs.dir);
+        const uint32_t x = rw.off[v] + (uint32_t)o;
+        // per row: item and its two offsets; per entry: neighbour (+ label)
+        by += (o == 0 ? 12 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
+        if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
+        if (member(cs.w, rw.nbr[x])) atomicOr(&J.hits[i], 1u << c);
+      });
+    }
   }
   if (bytes) block_add(bytes, by);
 }
@@ -475,8 +554,7 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
     if (ok) {
       v = filter_item(J, i);
       by += J.list ? 4 : 0;
-      by += (J.min_out > 0 ? 8 : 0) + (J.min_in > 0 ? 8 : 0);
-      ok = degree_ok(g, J, v);
+      ok = degree_ok(g, J, i, v, by);
       if (ok && J.ncons) {
         by += 4;
         ok = J.hits[i] == full;
@@ -569,7 +647,7 @@ __global__ __launch_bounds__(BS) void k_cpi_count(DevGraph g, const CpiJob* __re
                                                   int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
   __shared__ ChunkMap cm;
-  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return cpi_width(jobs[j]); });
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(cpi_width(jobs[j])); });
   unsigned long long by = 0;
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
     const int jb = chunk_job(cm, njobs, ch);
@@ -578,7 +656,7 @@ __global__ __launch_bounds__(BS) void k_cpi_count(DevGraph g, const CpiJob* __re
     const uint64_t T = *J.sc.d_total;
     const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
     const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
-    flat_chunk(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o) {
+    flat_chunk(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
       if (!valid) return;
       const int32_t vp = J.p.list[s];
       int32_t v;
@@ -620,7 +698,7 @@ __global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __res
                                                  int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
   __shared__ ChunkMap cm;
-  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return cpi_width(jobs[j]); });
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(cpi_width(jobs[j])); });
   unsigned long long by = 0, dummy = 0;
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
     const int jb = chunk_job(cm, njobs, ch);
@@ -629,7 +707,7 @@ __global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __res
     const uint64_t T = *J.sc.d_total;
     const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
     const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
-    flat_chunk(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o) {
+    flat_chunk(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
       if (!valid) return;
       const int32_t vp = J.p.list[s];
       int32_t v;
@@ -813,7 +891,7 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
   __shared__ ChunkMap cm;
   __shared__ unsigned long long s_wcnt[BS / WAVE];
   __shared__ unsigned long long s_woff[BS / WAVE];
-  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return ext_width<LAST>(jobs[j]); });
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(ext_width<LAST>(jobs[j])); });
   const uint32_t wv = threadIdx.x / WAVE;
   unsigned long long by = 0;
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
@@ -833,7 +911,7 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
 #pragma unroll
       for (int v = 0; v < MAXK; v++) thr[v] = thr_on && v < J.k ? J.thr[v] : 0;
     }
-    flat_chunk(J.sc.P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o) {
+    flat_chunk(J.sc.P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
       int32_t h[MAXK];
       bool ok = false;
       if (valid) {
