@@ -640,7 +640,8 @@ static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t
   c.begs = std::max(c.cap_u[p.root], c.cap_f);
   c.vcap = vcap;
   size_t b = 0;
-  b += align_up(sizeof(int32_t) * (size_t)g->n) * k;                   // positions
+  for (int u = 0; u < k; u++)                                          // positions (parents)
+    if (p.is_parent[u]) b += align_up(sizeof(int32_t) * (size_t)g->n);
   b += 2 * align_up(4 * ((size_t)g->n / 32 + 1)) * k;                  // membership bitmaps
   for (int u = 0; u < k; u++) b += 2 * align_up(4 * c.cap_u[u]);       // candidate lists
   b += align_up(4 * c.hits);
@@ -663,7 +664,9 @@ static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const J
   };
   const int k = p.k;
   std::memset(&m.pos, 0, sizeof m.pos);
-  for (int u = 0; u < k; u++) m.pos[u] = (int32_t*)take(sizeof(int32_t) * (size_t)g->n);
+  // position maps are read only through the CPI lists of tree children
+  for (int u = 0; u < k; u++)
+    m.pos[u] = p.is_parent[u] ? (int32_t*)take(sizeof(int32_t) * (size_t)g->n) : nullptr;
   for (int u = 0; u < k; u++) {
     m.bits[u][0] = (uint32_t*)take(4 * ((size_t)g->n / 32 + 1));
     m.bits[u][1] = (uint32_t*)take(4 * ((size_t)g->n / 32 + 1));
@@ -1478,8 +1481,8 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
 static int64_t default_budget() {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return int64_t(4) << 30;
-  const int64_t b = (int64_t)(fr / 3);
-  return std::max<int64_t>(int64_t(256) << 20, std::min<int64_t>(b, int64_t(48) << 30));
+  const int64_t b = (int64_t)(fr / 2);
+  return std::max<int64_t>(int64_t(256) << 20, std::min<int64_t>(b, int64_t(128) << 30));
 }
 
 static Workspace* acquire_ws(gfd_graph* g, int64_t budget) {
@@ -1573,19 +1576,21 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     HIPCHK(hipMemsetAsync(ws->err, 0, 4, c.st));
     // plans, capacities and batches
     std::vector<Job> all(num_specs);
-    // a quarter of the budget holds frontiers, shared evenly by the jobs of a
+    // half of the budget holds frontiers, shared evenly by the jobs of a
     // batch that have any (k > 2), each sized for its own pattern size
     int64_t deep = 0;
     for (int32_t i = 0; i < num_specs; i++) deep += specs[i].num_vertices > 2;
     const int64_t fbytes = std::min<int64_t>(
-        budget / (4 * std::max<int64_t>(1, std::min<int64_t>(deep, max_batch))), int64_t(8) << 30);
+        budget / (2 * std::max<int64_t>(1, std::min<int64_t>(deep, max_batch))), int64_t(8) << 30);
     for (int32_t i = 0; i < num_specs; i++) {
       all[i].spec = i;
       make_plan(g, specs[i], c.induced, all[i].plan);
+      // (64 partial matches per data edge bounds what small graphs can need)
       const uint64_t cap_f =
           o.frontier_cap ? (uint64_t)o.frontier_cap
                          : (uint64_t)std::max<int64_t>(
-                               4096, fbytes / (int64_t)per_slot_bytes(all[i].plan.k));
+                               4096, std::min<int64_t>(fbytes / (int64_t)per_slot_bytes(all[i].plan.k),
+                                                       64 * g->m));
       job_caps(g, all[i].plan, cap_f, vsmall, all[i].caps);
     }
     std::vector<std::vector<int>> batches;

@@ -30,7 +30,7 @@ constexpr int BS = 256;        // threads per block everywhere
 constexpr int WAVE = 64;       // CDNA wavefront
 constexpr int SCAN_IPT = 8;    // items per thread in the scan
 constexpr int SCAN_TILE = BS * SCAN_IPT;
-constexpr int MAX_JOBS = 64;   // jobs per launch (one batch)
+constexpr int MAX_JOBS = 256;  // jobs per launch (one batch); at most BS
 constexpr int LBS_ROUNDS = 8;  // flat work: rounds of BS positions per located chunk
 constexpr uint64_t LBS_CHUNK = (uint64_t)BS * LBS_ROUNDS;
 constexpr int SORT_MAX = 2048; // violation tuples sorted in one workgroup

@@ -290,12 +290,16 @@ __device__ __forceinline__ uint64_t wave_last_le(const T* __restrict__ P, uint64
 }
 
 // Maps the flat positions [c0, c1) of one job row (P[0] <= c0 < c1 <= P[N],
-// at most LBS_CHUNK of them) to (source, offset): the chunk's first and last
-// source come from two wave-parallel searches, their prefix values are staged
-// in LDS and each position is placed by a binary search there.
+// at most LBS_CHUNK of them) to (source, offset).  The chunk's first and last
+// source come from two wave-parallel searches and their prefix values are
+// staged in LDS.  SERIAL: thread t takes the LBS_ROUNDS consecutive
+// positions c0 + t*LBS_ROUNDS ..; one binary search places the first and the
+// rest walk forward, so short rows (most of a power-law graph) cost no search
+// each.  Otherwise round r gives thread t position c0 + r*BS + t (coalesced
+// loads across the wave), each placed by its own binary search.
 // f(valid, s, o, a) -- position a = P[s] + o -- is called by every thread
 // LBS_ROUNDS times (uniform trip count); the call ends with a barrier.
-template <class T, class F>
+template <bool SERIAL, class T, class F>
 __device__ __forceinline__ void flat_chunk(const T* __restrict__ P, uint64_t N, uint64_t c0,
                                            uint64_t c1, LbsShared& sh, F f) {
   if (threadIdx.x < WAVE) {
@@ -312,17 +316,27 @@ __device__ __forceinline__ void flat_chunk(const T* __restrict__ P, uint64_t N, 
   if (in_lds)
     for (uint64_t j = threadIdx.x; j < span; j += BS) sh.p[j] = P[lo + j];
   __syncthreads();
+  // largest l in [from, span-2] with sh.p[l] <= a
+  auto lds_search = [&](uint32_t from, uint64_t a) -> uint32_t {
+    uint32_t l = from, h = (uint32_t)(span - 2);
+    while (l < h) {
+      const uint32_t mid = (l + h + 1) >> 1;
+      if (sh.p[mid] <= a) l = mid; else h = mid - 1;
+    }
+    return l;
+  };
+  const uint64_t a0 = SERIAL ? c0 + (uint64_t)threadIdx.x * LBS_ROUNDS : c0 + threadIdx.x;
+  uint32_t l = (SERIAL && in_lds && a0 < c1) ? lds_search(0, a0) : 0u;  // source lo + l
   for (int r = 0; r < LBS_ROUNDS; r++) {
-    const uint64_t a = c0 + (uint64_t)r * BS + threadIdx.x;
+    const uint64_t a = SERIAL ? a0 + (uint64_t)r : a0 + (uint64_t)r * BS;
     const bool valid = a < c1;
     uint64_t s = 0, o = 0;
     if (valid) {
       if (in_lds) {
-        uint32_t l = 0, h = (uint32_t)(span - 2);
-        while (l < h) {
-          const uint32_t mid = (l + h + 1) >> 1;
-          if (sh.p[mid] <= a) l = mid; else h = mid - 1;
-        }
+        if (SERIAL)
+          while (sh.p[l + 1] <= a) l++;  // a < P[hi+1], so this stops inside the slice
+        else
+          l = lds_search(l, a);  // positions only grow: search from the last source
         s = lo + l;
         o = a - sh.p[l];
       } else {
@@ -347,21 +361,24 @@ __device__ __forceinline__ uint64_t chunks_of(uint64_t positions) {
   return (positions + LBS_CHUNK - 1) / LBS_CHUNK;
 }
 
-// Lane j of wave 0 evaluates chunks(j), the chunk count of job j; ends with a
-// barrier.  njobs <= MAX_JOBS.
+// Thread j evaluates chunks(j), the chunk count of job j, and the block scans
+// them into m.cs; ends with a barrier.  njobs <= MAX_JOBS = BS.
 template <class W>
 __device__ __forceinline__ void chunk_map_build(ChunkMap& m, int njobs, W chunks) {
-  if (threadIdx.x < WAVE) {
-    const int j = (int)threadIdx.x;
-    uint64_t c = j < njobs ? chunks(j) : 0ull;
+  __shared__ uint64_t s_wtot[BS / WAVE];
+  const int j = (int)threadIdx.x;
+  uint64_t c = j < njobs ? chunks(j) : 0ull;
 #pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-      const uint64_t y = __shfl_up(c, (unsigned)d);
-      if (j >= d) c += y;
-    }
-    m.cs[j + 1] = c;
-    if (j == 0) m.cs[0] = 0;
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint64_t y = __shfl_up(c, (unsigned)d);
+    if ((int)lane() >= d) c += y;
   }
+  const uint32_t wv = threadIdx.x / WAVE;
+  if (lane() == WAVE - 1) s_wtot[wv] = c;
+  __syncthreads();
+  for (uint32_t w = 0; w < wv; w++) c += s_wtot[w];
+  m.cs[j + 1] = c;
+  if (j == 0) m.cs[0] = 0;
   __syncthreads();
 }
 
@@ -505,7 +522,7 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const Rows rw = direct_rows(g, J, cs.dir);
       const uint64_t c0 = P[0] + r * LBS_CHUNK;
       const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
-      flat_chunk(P, J.n_host, c0, c1, sh, [&](bool valid, uint64_t i, uint64_t o, uint64_t x) {
+      flat_chunk<true>(P, J.n_host, c0, c1, sh, [&](bool valid, uint64_t i, uint64_t o, uint64_t x) {
         if (!valid) return;
         // per entry: neighbour (+ label); the items' offsets stream once
         by += (o == 0 ? 4 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
@@ -518,7 +535,7 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const uint64_t T = *J.sc.d_total;
       const uint64_t c0 = r * LBS_CHUNK;
       const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
-      flat_chunk(J.sc.P, NP, c0, c1, sh, [&](bool valid, uint64_t q, uint64_t o, uint64_t) {
+      flat_chunk<true>(J.sc.P, NP, c0, c1, sh, [&](bool valid, uint64_t q, uint64_t o, uint64_t) {
         if (!valid) return;
         const uint64_t i = q / nc;
         const uint32_t c = (uint32_t)(q - i * nc);
@@ -568,7 +585,7 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
     if (ok) {
       const uint64_t idx = s_base + rank;
       J.out[idx] = v;
-      J.pos[v] = (int32_t)idx;
+      if (J.pos) J.pos[v] = (int32_t)idx;
       atomicOr(&J.bits[(uint32_t)v >> 5], 1u << ((uint32_t)v & 31u));
       by += 12;
     }
@@ -656,7 +673,7 @@ __global__ __launch_bounds__(BS) void k_cpi_count(DevGraph g, const CpiJob* __re
     const uint64_t T = *J.sc.d_total;
     const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
     const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
-    flat_chunk(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
+    flat_chunk<true>(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
       if (!valid) return;
       const int32_t vp = J.p.list[s];
       int32_t v;
@@ -707,7 +724,7 @@ __global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __res
     const uint64_t T = *J.sc.d_total;
     const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
     const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
-    flat_chunk(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
+    flat_chunk<true>(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
       if (!valid) return;
       const int32_t vp = J.p.list[s];
       int32_t v;
@@ -760,6 +777,20 @@ __device__ __forceinline__ bool literal_holds(const DevGraph& g, const DevLit& l
   return x != ABSENT && y != ABSENT && x == y;
 }
 
+// Whether the complete match h (matching order) orders after the staging
+// threshold in variable order (or equals it when the threshold is exclusive).
+__device__ __forceinline__ bool past_threshold(const ExtJob& J, const int32_t (&h)[MAXK],
+                                               const int32_t (&thr)[MAXK]) {
+  int c = 0;
+#pragma unroll
+  for (int v = 0; v < MAXK; v++)
+    if (c == 0 && v < J.k) {
+      const uint32_t x = (uint32_t)pick(h, J.var_pos[v]), y = (uint32_t)thr[v];
+      c = x < y ? -1 : (x > y ? 1 : 0);
+    }
+  return c > 0 || (c == 0 && !J.thr_incl);
+}
+
 struct FinalAcc {
   unsigned long long match, viol, mfp, vfp;
 };
@@ -793,25 +824,16 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
   acc.viol += 1;
   acc.vfp += hs;
   if (J.vcap == 0) return false;
-  if (thr_on) {  // stage only if t < thr (t <= thr when thr_incl), lexicographically on unsigned ids
-    int c = 0;
-#pragma unroll
-    for (int v = 0; v < MAXK; v++)
-      if (c == 0 && v < J.k) {
-        const uint32_t x = (uint32_t)t[v], y = (uint32_t)thr[v];
-        c = x < y ? -1 : (x > y ? 1 : 0);
-      }
-    if (c > 0 || (c == 0 && !J.thr_incl)) return false;
-  }
-  return true;
+  // stage only if t < thr (t <= thr when thr_incl), lexicographically on unsigned ids
+  return !(thr_on && past_threshold(J, h, thr));
 }
 
 // Wave-aggregated append of violating tuples to the job's staging buffer.
-// `full` (wave-uniform) becomes true once this wave has seen the buffer fill
-// up; from then on the wave only notes the overflow, so a GFD with millions
-// of violations does not keep hammering one counter.  The count only grows
-// within a pass, and every overflowing append pushes it past vcap, which is
-// how the host detects the overflow.
+// `full` (wave-uniform) becomes true once this wave's append has pushed the
+// count past vcap; from then on the wave drops its tuples without touching
+// the counter, so a GFD with millions of violations does not keep hammering
+// one address.  The host detects the overflow as count > vcap, which holds
+// from the first dropped tuple on (an exactly full buffer is not an overflow).
 __device__ __forceinline__ void stage(const ExtJob& J, bool want, const int32_t (&t)[MAXK],
                                       bool& full) {
   const uint64_t m = __ballot(want);
@@ -822,7 +844,8 @@ __device__ __forceinline__ void stage(const ExtJob& J, bool want, const int32_t 
   unsigned long long base = 0;
   if ((int)lane() == leader) base = atomicAdd((unsigned long long*)J.d_vcount, cnt);
   base = __shfl(base, leader);
-  if (base + cnt >= J.vcap) full = true;
+  // only once the count is past vcap: the host then sees the overflow
+  if (base + cnt > J.vcap) full = true;
   if (want) {
     const uint64_t slot = base + rank_below(m);
     if (slot < J.vcap) {
@@ -911,7 +934,7 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
 #pragma unroll
       for (int v = 0; v < MAXK; v++) thr[v] = thr_on && v < J.k ? J.thr[v] : 0;
     }
-    flat_chunk(J.sc.P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
+    flat_chunk<false>(J.sc.P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
       int32_t h[MAXK];
       bool ok = false;
       if (valid) {
@@ -924,6 +947,9 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
           h[j] = (j < i) ? J.src_cols[(uint64_t)j * J.src_stride + s] : v;
           if (j < i && h[j] == v) ok = false;
         }
+        // a collect-only pass keeps nothing past its threshold: such tuples
+        // skip the edge probes and the literal check
+        if (LAST && ok && thr_on && J.collect_only) ok = !past_threshold(J, h, thr);
         for (int c = 0; c < J.nchk && ok; c++) {
           const int32_t hw = pick(h, J.chk_pos[c]);
           if (J.chk_fwd[c] != PC_FREE) ok = constraint_ok(edge_label(g, hw, v, by), J.chk_fwd[c]);

@@ -151,6 +151,26 @@ def test_threshold_rerun(P):
     gh.free()
 
 
+def test_staging_caps_near_the_violation_count(P):
+    """Staging capacities just below, at and above the exact violation count:
+    an exactly full buffer is no overflow, one tuple more is."""
+    g = random_graph(8, 400, 12000, n_vlabels=1, n_elabels=1, n_attrs=1, attr_values=50,
+                     absent_frac=0.0)
+    gfds = [{"k": 1, "vlabels": [0], "edges": [], "x": [], "y": [], "y_false": True},
+            {"k": 2, "vlabels": [0, 0], "edges": [[0, 1, 0]], "x": [], "y": [], "y_false": True}]
+    og = O.OracleGraph(g)
+    gh = P.load(g)
+    for d in gfds:
+        exp = O.validate(og, d, "induced", K=16, threads=4)
+        v = exp["violation_count"]
+        for cap in (v - 3, v - 1, v, v + 1):
+            for batched in (False, True):
+                got = P.validate(gh, [d], K=16, semantics="induced", violation_cap=cap,
+                                 batched=batched)
+                assert got[0] == exp, (d["k"], cap, batched)
+    gh.free()
+
+
 def test_single_vertex_patterns(P):
     g = random_graph(9, 500, 2000, n_vlabels=3, n_attrs=2, attr_values=4, absent_frac=0.3)
     gfds = [{"k": 1, "vlabels": [L], "edges": [], "x": [],
