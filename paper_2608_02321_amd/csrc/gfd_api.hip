@@ -131,6 +131,7 @@ struct gfd_graph {
   int64_t n = 0, m = 0;
   int32_t num_attrs = 0, nvl = 0, nel = 0;
   std::vector<uint32_t> lab_off;       // host copy [nvl+1]
+  std::vector<uint32_t> elb_blk[2];    // host: first row of each (vertex label, edge label) block
   std::vector<uint64_t> lab_out_sum;   // sum of out-degrees per vertex label
   std::vector<uint64_t> lab_in_sum;
   std::vector<void*> owned;
@@ -256,6 +257,76 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
       std::memcpy(&lv_in_lab[lv_in_off[p]], &in_lab[in_off[v]], 4 * (in_off[v + 1] - in_off[v]));
     }
   });
+  // edge-label blocks per direction: for every (vertex label, edge label) the
+  // bucket rows with such edges, in bucket order, and those edges' far ends
+  const int32_t nel = maxel + 1;
+  std::vector<uint32_t> elb_row[2], elb_start[2];
+  std::vector<int32_t> elb_nbr[2];
+  std::vector<uint32_t> elb_blk[2];  // [nvl * nel + 1] first row of each block
+  for (int d = 0; d < 2; d++) {
+    const std::vector<uint32_t>& off = d ? lv_in_off : lv_out_off;
+    const std::vector<int32_t>& nb = d ? lv_in_nbr : lv_out_nbr;
+    const std::vector<int32_t>& lb = d ? lv_in_lab : lv_out_lab;
+    const size_t nblk = (size_t)nvl * (size_t)std::max(nel, 1);
+    std::vector<uint64_t> rows(nblk + 1, 0), ents(nblk + 1, 0);
+    // a row's entries grouped by edge label (neighbour order kept within a label)
+    auto grouped = [&](uint32_t p, std::vector<std::pair<int32_t, int32_t>>& es) {
+      es.clear();
+      for (uint32_t e = off[p]; e < off[p + 1]; e++) es.push_back({lb[e], nb[e]});
+      std::stable_sort(es.begin(), es.end(),
+                       [](const std::pair<int32_t, int32_t>& x, const std::pair<int32_t, int32_t>& y) {
+                         return x.first < y.first;
+                       });
+    };
+    parallel_for(nvl, [&](int64_t l0, int64_t l1) {  // blocks of one vertex label are disjoint
+      std::vector<std::pair<int32_t, int32_t>> es;
+      for (int64_t L = l0; L < l1; L++)
+        for (uint32_t p = lab_off[L]; p < lab_off[L + 1]; p++) {
+          grouped(p, es);
+          for (size_t i = 0; i < es.size(); i++) {
+            const size_t b = (size_t)L * nel + es[i].first;
+            ents[b + 1]++;
+            if (i == 0 || es[i].first != es[i - 1].first) rows[b + 1]++;
+          }
+        }
+    });
+    for (size_t b = 0; b < nblk; b++) {
+      rows[b + 1] += rows[b];
+      ents[b + 1] += ents[b];
+    }
+    elb_row[d].assign(rows[nblk], 0);
+    elb_start[d].assign(rows[nblk] + 1, 0);
+    elb_nbr[d].assign(ents[nblk], 0);
+    elb_blk[d].assign(rows.begin(), rows.end());
+    std::vector<uint64_t> rcur(rows.begin(), rows.end() - 1), ecur(ents.begin(), ents.end() - 1);
+    parallel_for(nvl, [&](int64_t l0, int64_t l1) {
+      std::vector<std::pair<int32_t, int32_t>> es;
+      for (int64_t L = l0; L < l1; L++)
+        for (uint32_t p = lab_off[L]; p < lab_off[L + 1]; p++) {
+          grouped(p, es);
+          for (size_t i = 0; i < es.size(); i++) {
+            const size_t b = (size_t)L * nel + es[i].first;
+            if (i == 0 || es[i].first != es[i - 1].first) {
+              const uint64_t r = rcur[b]++;
+              elb_row[d][r] = p - lab_off[L];
+              elb_start[d][r] = (uint32_t)ecur[b];
+            }
+            elb_nbr[d][ecur[b]++] = es[i].second;
+          }
+        }
+    });
+    elb_start[d][rows[nblk]] = (uint32_t)ents[nblk];
+  }
+  // edge filter: one bit per hashed ordered pair, at least 8 bits per edge
+  int ef_lg = 16;
+  while ((1ull << ef_lg) < 8ull * (uint64_t)m) ef_lg++;
+  std::vector<uint32_t> ef_bits((1ull << ef_lg) / 32, 0u);
+  for (int64_t v = 0; v < n; v++)
+    for (uint32_t e = out_off[v]; e < out_off[v + 1]; e++) {
+      const uint64_t key = ((uint64_t)(uint32_t)v << 32) | (uint32_t)out_nbr[e];
+      const uint64_t bit = (key * 0x9E3779B97F4A7C15ull) >> (64 - ef_lg);
+      ef_bits[bit >> 5] |= 1u << (bit & 31);
+    }
   std::vector<int32_t> attr_flat((size_t)num_attrs * n);
   for (int32_t a = 0; a < num_attrs; a++)
     std::memcpy(attr_flat.data() + (size_t)a * n, attr[a], sizeof(int32_t) * n);
@@ -290,6 +361,15 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     g->dg.lv_in_off = (const uint32_t*)up(lv_in_off.data(), 4 * (n + 1));
     g->dg.lv_in_nbr = (const int32_t*)up(lv_in_nbr.data(), 4 * m);
     g->dg.lv_in_lab = (const int32_t*)up(lv_in_lab.data(), 4 * m);
+    g->dg.ef_bits = (const uint32_t*)up(ef_bits.data(), 4 * ef_bits.size());
+    for (int d = 0; d < 2; d++) {
+      g->dg.elb_row[d] = (const uint32_t*)up(elb_row[d].data(), 4 * elb_row[d].size());
+      g->dg.elb_start[d] = (const uint32_t*)up(elb_start[d].data(), 4 * elb_start[d].size());
+      g->dg.elb_nbr[d] = (const int32_t*)up(elb_nbr[d].data(), 4 * elb_nbr[d].size());
+      g->elb_blk[d] = std::move(elb_blk[d]);
+    }
+    g->dg.ef_mask = (1ull << ef_lg) - 1;
+    g->dg.ef_shift = (uint32_t)(64 - ef_lg);
     HIPCHK(hipStreamSynchronize(st));
     g->lab_off = std::move(lab_off);
     g->lab_out_sum = std::move(lab_out);
@@ -808,7 +888,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
   // top-down, BFS order
   for (int j = 0; j < maxk; j++) {
     std::vector<FilterJob> F(nj);
-    uint64_t items = 1, pull_ub = 0, pairs = 1;  // pull_ub: chunks over all jobs
+    uint64_t items = 1, pull_ub = 0, pairs = 1, item_ch = 0;  // *_ub, *_ch: chunks over all jobs
     bool any_cons = false;
     const uint32_t ep = next_epoch(c);
     for (int x = 0; x < nj; x++) {
@@ -828,6 +908,16 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.base = (p.qlab[u] == ANY || bs == 0) ? 0u : g->lab_off[p.qlab[u]];
       f.list = p.qlab[u] == ANY ? nullptr : g->dg.lab_vtx + f.base;
       f.direct = 1;
+      // a labelled vertex and edge read only that edge label's block
+      for (int q = 0; q < f.ncons; q++) {
+        PullC& pc = f.cons[q];
+        pc.blk = 0;
+        if (p.qlab[u] == ANY || pc.elab == ANY || p.qlab[u] >= g->nvl || pc.elab >= g->nel) continue;
+        const size_t b = (size_t)p.qlab[u] * g->nel + pc.elab;
+        pc.blk = 1;
+        pc.rb = g->elb_blk[pc.dir][b];
+        pc.re = g->elb_blk[pc.dir][b + 1];
+      }
       f.d_n = nullptr;
       f.n_host = f.cap = bs;
       f.hits = J.mem.hits;
@@ -839,17 +929,18 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.bits = J.mem.bits[u][0];
       f.nwords = (uint64_t)g->n / 32 + 1;
       items = std::max(items, bs);
+      item_ch += chunks_of(bs);
       pairs = std::max(pairs, bs * (uint64_t)std::max(f.ncons, 1));
       for (int q = 0; q < f.ncons; q++) pull_ub += chunks_of(rows_ub(g, p.qlab[u], f.cons[q].dir));
       any_cons |= f.ncons > 0;
     }
-    L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), gx_for(items, nj),
+    L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), flat_grid(item_ch),
                        gx_for((uint64_t)g->n / 32 + 1, nj, 64), any_cons, false, false});
   }
   // bottom-up, reverse BFS order: drop dead ends
   for (int j = maxk - 1; j >= 0; j--) {
     std::vector<FilterJob> F(nj);
-    uint64_t items = 1, pull_ub = 0, pairs = 1;  // pull_ub: chunks over all jobs
+    uint64_t items = 1, pull_ub = 0, pairs = 1, item_ch = 0;  // *_ub, *_ch: chunks over all jobs
     bool any = false;
     const uint32_t ep = next_epoch(c);
     for (int x = 0; x < nj; x++) {
@@ -875,12 +966,13 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.bits = J.mem.bits[u][J.cur[u]];
       f.nwords = (uint64_t)g->n / 32 + 1;
       items = std::max(items, f.cap);
+      item_ch += chunks_of(f.cap);
       pairs = std::max(pairs, f.cap * (uint64_t)f.ncons);
       for (int q = 0; q < f.ncons; q++) pull_ub += chunks_of(rows_ub(g, p.qlab[u], f.cons[q].dir));
       any = true;
     }
     if (any)
-      L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), gx_for(items, nj),
+      L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), flat_grid(item_ch),
                          gx_for((uint64_t)g->n / 32 + 1, nj, 64), true, false, false});
   }
   // CPI adjacency lists per spanning-tree edge, in BFS order

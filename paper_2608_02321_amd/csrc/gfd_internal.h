@@ -60,6 +60,19 @@ struct DevGraph {
   const uint32_t* lv_in_off;   // [n+1]
   const int32_t* lv_in_nbr;    // [m]
   const int32_t* lv_in_lab;    // [m]
+  // edge-label blocks of the label-ordered view, per direction d: block
+  // (vertex label L, edge label e) lists the rows of bucket L that have
+  // e-labelled edges (row position within the bucket, ascending) and those
+  // edges' far ends.  Rows [rb, re) of a block own entries
+  // [elb_start[d][rb], elb_start[d][re]) of elb_nbr[d].
+  const uint32_t* elb_row[2];    // [rows_d] bucket position of the row
+  const uint32_t* elb_start[2];  // [rows_d + 1]
+  const int32_t* elb_nbr[2];     // [m]
+  // edge filter: bit hash(a, b) is set for every edge a -> b, so a clear bit
+  // proves that a -> b is no edge (a set bit proves nothing)
+  const uint32_t* ef_bits;     // [(ef_mask + 1) / 32]
+  uint64_t ef_mask;            // bits - 1 (bits a power of two, >= 8 m)
+  uint32_t ef_shift;           // 64 - log2(bits)
 };
 
 // A candidate set C(u): its members (list, *cnt), their positions in the list
@@ -88,6 +101,9 @@ struct JobScan {
 struct PullC {
   int32_t dir, elab;
   CandSet w;
+  // direct jobs with a labelled vertex and edge: the edge-label block's rows
+  uint32_t rb, re;
+  int32_t blk;
 };
 
 // Candidate filter of one pattern vertex u (Section IV-B: label candidates,
@@ -209,7 +225,7 @@ struct SelJob {
 void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                  unsigned long long* bytes);
-void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx,
+void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                     unsigned long long* bytes);
 // zero the output bitmap of every active job
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx);

@@ -112,6 +112,25 @@ __device__ __forceinline__ bool constraint_ok(int32_t found, int32_t code) {
   return found != NOEDGE && (code == ANY || found == code);
 }
 
+// Whether a -> b may be an edge: false is certain (its filter bit is clear).
+// The 8-bits-per-edge filter stays in the last-level cache.
+__device__ __forceinline__ bool maybe_edge(const DevGraph& g, int32_t a, int32_t b,
+                                           unsigned long long& by) {
+  const uint64_t key = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+  const uint64_t bit = (key * 0x9E3779B97F4A7C15ull) >> g.ef_shift;
+  by += 4;
+  return (g.ef_bits[bit >> 5] >> (bit & 31)) & 1u;
+}
+
+// Constraint `code` on data edge a -> b; an absence requirement is settled by
+// the edge filter whenever its bit is clear, without searching a row.
+__device__ __forceinline__ bool pair_ok(const DevGraph& g, int32_t a, int32_t b, int32_t code,
+                                        unsigned long long& by) {
+  if (code == PC_FREE) return true;
+  if (code == PC_ABSENT && !maybe_edge(g, a, b, by)) return true;
+  return constraint_ok(edge_label(g, a, b, by), code);
+}
+
 // Membership bitmaps (n bits, 512 KB at 4M vertices) stay in L2: their probes
 // count no algorithmic HBM bytes.
 __device__ __forceinline__ bool member(const CandSet& c, int32_t x) {
@@ -483,11 +502,19 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
   }, J.sc);
 }
 
-// Flat entries of constraint c of a direct job: its items' rows in one slice.
+// Flat entries of constraint c of a direct job: its items' rows in one slice
+// (the prefix P has N + 1 entries), or the rows of its edge-label block.
 __device__ __forceinline__ uint64_t direct_span(const DevGraph& g, const FilterJob& J, int c,
-                                                const uint32_t*& P) {
-  P = direct_rows(g, J, J.cons[c].dir).off + J.base;
-  return (uint64_t)(P[J.n_host] - P[0]);
+                                                const uint32_t*& P, uint64_t& N) {
+  const PullC& cs = J.cons[c];
+  if (cs.blk) {
+    P = g.elb_start[cs.dir] + cs.rb;
+    N = cs.re - cs.rb;
+  } else {
+    P = direct_rows(g, J, cs.dir).off + J.base;
+    N = J.n_host;
+  }
+  return (uint64_t)(P[N] - P[0]);
 }
 
 // One thread per adjacency entry: mark constraint c of item i as met.
@@ -499,9 +526,9 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
     const FilterJob& J = jobs[j];
     if (!J.active || !J.ncons) return 0ull;
     if (!J.direct) return chunks_of(*J.sc.d_total);
-    uint64_t ch = 0;
+    uint64_t ch = 0, N;
     const uint32_t* P;
-    for (int c = 0; c < J.ncons; c++) ch += chunks_of(direct_span(g, J, c, P));
+    for (int c = 0; c < J.ncons; c++) ch += chunks_of(direct_span(g, J, c, P, N));
     return ch;
   });
   unsigned long long by = 0;
@@ -513,22 +540,33 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       // constraint c, chunk r of its slice; positions are entries of the view
       int c = 0;
       const uint32_t* P;
-      uint64_t T = direct_span(g, J, 0, P);
+      uint64_t N;
+      uint64_t T = direct_span(g, J, 0, P, N);
       while (r >= chunks_of(T)) {
         r -= chunks_of(T);
-        T = direct_span(g, J, ++c, P);
+        T = direct_span(g, J, ++c, P, N);
       }
       const PullC& cs = J.cons[c];
-      const Rows rw = direct_rows(g, J, cs.dir);
       const uint64_t c0 = P[0] + r * LBS_CHUNK;
       const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
-      flat_chunk<true>(P, J.n_host, c0, c1, sh, [&](bool valid, uint64_t i, uint64_t o, uint64_t x) {
-        if (!valid) return;
-        // per entry: neighbour (+ label); the items' offsets stream once
-        by += (o == 0 ? 4 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
-        if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
-        if (member(cs.w, rw.nbr[x])) atomicOr(&J.hits[i], 1u << c);
-      });
+      if (cs.blk) {  // only e-labelled entries; the block names each row's item
+        const uint32_t* rows = g.elb_row[cs.dir] + cs.rb;
+        const int32_t* nbr = g.elb_nbr[cs.dir];
+        flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t x) {
+          if (!valid) return;
+          by += (o == 0 ? 8 : 0) + 4;  // per row: item and start; per entry: neighbour
+          if (member(cs.w, nbr[x])) atomicOr(&J.hits[rows[s]], 1u << c);
+        });
+      } else {
+        const Rows rw = direct_rows(g, J, cs.dir);
+        flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t i, uint64_t o, uint64_t x) {
+          if (!valid) return;
+          // per entry: neighbour (+ label); the items' offsets stream once
+          by += (o == 0 ? 4 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
+          if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
+          if (member(cs.w, rw.nbr[x])) atomicOr(&J.hits[i], 1u << c);
+        });
+      }
     } else {
       const uint32_t nc = (uint32_t)J.ncons;
       const uint64_t NP = filter_items(J) * (uint64_t)nc;
@@ -553,42 +591,68 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
   if (bytes) block_add(bytes, by);
 }
 
-// Items meeting the degree filter and every constraint join C(u); each tile
-// reserves its output slots with one atomic add (a set: no fixed order).
+// Items meeting the degree filter and every constraint join C(u) (a set: no
+// fixed order).  The items of all jobs share one chunk space; thread t of a
+// block takes 8 consecutive items of the chunk, the block reserves the chunk's
+// output with one atomic add, and runs of members in one bitmap word are set
+// with one atomic.
 __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
                                                        const FilterJob* __restrict__ jobs,
-                                                       unsigned long long* bytes) {
+                                                       int njobs, unsigned long long* bytes) {
+  constexpr int IPT = (int)(LBS_CHUNK / BS);
+  __shared__ ChunkMap cm;
   __shared__ unsigned long long s_base;
-  const FilterJob& J = jobs[blockIdx.y];
-  if (!J.active) return;
-  const uint64_t N = filter_items(J);
-  const uint32_t full = J.ncons ? (J.ncons >= 32 ? ~0u : ((1u << J.ncons) - 1)) : 0u;
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t {
+    return jobs[j].active ? chunks_of(filter_items(jobs[j])) : 0ull;
+  });
   unsigned long long by = 0;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * BS; t0 < N; t0 += (uint64_t)gridDim.x * BS) {
-    const uint64_t i = t0 + threadIdx.x;
-    bool ok = i < N;
-    int32_t v = 0;
-    if (ok) {
-      v = filter_item(J, i);
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+    const int jb = chunk_job(cm, njobs, ch);
+    const FilterJob& J = jobs[jb];
+    const uint64_t N = filter_items(J);
+    const uint32_t full = J.ncons ? (J.ncons >= 32 ? ~0u : ((1u << J.ncons) - 1)) : 0u;
+    const uint64_t i0 = (ch - cm.cs[jb]) * LBS_CHUNK + (uint64_t)threadIdx.x * IPT;
+    uint32_t keep = 0;  // bit r: item i0 + r joins
+    int32_t vv[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; r++) {
+      const uint64_t i = i0 + r;
+      vv[r] = 0;
+      if (i >= N) continue;
+      const int32_t v = filter_item(J, i);
+      vv[r] = v;
       by += J.list ? 4 : 0;
-      ok = degree_ok(g, J, i, v, by);
+      bool ok = degree_ok(g, J, i, v, by);
       if (ok && J.ncons) {
         by += 4;
         ok = J.hits[i] == full;
       }
+      keep |= (ok ? 1u : 0u) << r;
     }
     uint32_t total;
-    const uint32_t rank = block_excl_scan(ok ? 1u : 0u, total);
+    const uint32_t rank = block_excl_scan((uint32_t)__popc(keep), total);
     if (threadIdx.x == 0)
       s_base = total ? atomicAdd((unsigned long long*)J.d_out_n, (unsigned long long)total) : 0ull;
     __syncthreads();
-    if (ok) {
-      const uint64_t idx = s_base + rank;
+    uint64_t idx = s_base + rank;
+    uint32_t word = 0xFFFFFFFFu, mask = 0;
+#pragma unroll
+    for (int r = 0; r < IPT; r++) {
+      if (!((keep >> r) & 1u)) continue;
+      const int32_t v = vv[r];
       J.out[idx] = v;
       if (J.pos) J.pos[v] = (int32_t)idx;
-      atomicOr(&J.bits[(uint32_t)v >> 5], 1u << ((uint32_t)v & 31u));
+      idx++;
       by += 12;
+      const uint32_t w = (uint32_t)v >> 5;
+      if (w != word) {
+        if (mask) atomicOr(&J.bits[word], mask);
+        word = w;
+        mask = 0;
+      }
+      mask |= 1u << ((uint32_t)v & 31u);
     }
+    if (mask) atomicOr(&J.bits[word], mask);
     __syncthreads();
   }
   if (bytes) block_add(bytes, by);
@@ -609,9 +673,9 @@ void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int n
                  unsigned long long* bytes) {
   hipLaunchKernelGGL(k_filter_pull, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
-void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx,
+void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                     unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_filter_compact, dim3(gx, njobs), dim3(BS), 0, st, g, jobs, bytes);
+  hipLaunchKernelGGL(k_filter_compact, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_filter_clear, dim3(gx, njobs), dim3(BS), 0, st, jobs);
@@ -638,8 +702,7 @@ __device__ __forceinline__ bool cpi_keep(const DevGraph& g, const CpiJob& J, int
   if (!member(J.u, v)) return false;
   if (J.other == PC_FREE) return true;
   // dir 0 scanned vp -> v, so the reverse is v -> vp; dir 1 the opposite
-  const int32_t r = J.dir ? edge_label(g, vp, v, by) : edge_label(g, v, vp, by);
-  return constraint_ok(r, J.other);
+  return J.dir ? pair_ok(g, vp, v, J.other, by) : pair_ok(g, v, vp, J.other, by);
 }
 
 // Row lengths of the members of C(p); clears the per-source counters.
@@ -952,9 +1015,7 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
         if (LAST && ok && thr_on && J.collect_only) ok = !past_threshold(J, h, thr);
         for (int c = 0; c < J.nchk && ok; c++) {
           const int32_t hw = pick(h, J.chk_pos[c]);
-          if (J.chk_fwd[c] != PC_FREE) ok = constraint_ok(edge_label(g, hw, v, by), J.chk_fwd[c]);
-          if (ok && J.chk_bwd[c] != PC_FREE)
-            ok = constraint_ok(edge_label(g, v, hw, by), J.chk_bwd[c]);
+          ok = pair_ok(g, hw, v, J.chk_fwd[c], by) && pair_ok(g, v, hw, J.chk_bwd[c], by);
         }
       }
       if (!LAST) {  // block-aggregated append to the next frontier
