@@ -1526,6 +1526,8 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
       e.collect_only = 1;
       e.thr = (const int32_t*)(jobs[x].mem.ctl + CTL_THR);
       e.thr_incl = 1;
+      e.prune = 1;
+      e.sc.epoch = next_epoch(c);
       E[jobs[x].last_single ? 1 : 0].push_back(e);
     }
     const size_t b0 = align_up(sizeof(ExtJob) * E[0].size());
@@ -1542,6 +1544,10 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     std::memcpy(ws->hjobrec + bt, T.data(), sizeof(TopkJob) * T.size());
     HIPCHK(hipMemcpyAsync(ws->jobrec, ws->hjobrec, bytes, hipMemcpyHostToDevice, c.st));
     const int n0 = (int)E[0].size(), n1 = (int)E[1].size();
+    uint64_t srcs = 1;
+    for (auto& e : E[0]) srcs = std::max(srcs, e.src_cap);
+    if (n0)  // attempts again, without the sources the threshold rules out
+      c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, (const ExtJob*)ws->jobrec, n0, gx_scan(srcs)); });
     if (n0)
       c.tm.run(K_LAST, [&] {
         ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, flat_grid(FLAT_GRID_MAX), true,

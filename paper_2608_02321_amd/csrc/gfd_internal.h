@@ -183,6 +183,8 @@ struct ExtJob {
   int32_t var_pos[MAXK];
   int32_t nx, ny, y_false, collect_only;
   int32_t thr_incl;         // stage t <= thr instead of t < thr
+  int32_t prune;            // scan: sources whose bound variables already order
+                            // them past thr get no attempts (collect-only passes)
   DevLit lit[2 * MAXLIT];
   unsigned long long* counters;  // [4] match, violation, match_fp, violation_fp
   int32_t* vbuf;

@@ -622,11 +622,12 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
       const int32_t v = filter_item(J, i);
       vv[r] = v;
       by += J.list ? 4 : 0;
-      bool ok = degree_ok(g, J, i, v, by);
-      if (ok && J.ncons) {
+      bool ok = true;
+      if (J.ncons) {  // the hit mask first: most items fail it
         by += 4;
         ok = J.hits[i] == full;
       }
+      ok = ok && degree_ok(g, J, i, v, by);
       keep |= (ok ? 1u : 0u) << r;
     }
     uint32_t total;
@@ -947,14 +948,34 @@ __device__ __forceinline__ uint64_t ext_sources(const ExtJob& J) {
   return *J.d_nsrc < J.src_cap ? *J.d_nsrc : J.src_cap;
 }
 
+// Whether every extension of source s orders past the threshold: its bound
+// variables, read in variable order up to the first unbound one, already
+// exceed thr.
+__device__ __forceinline__ bool source_past(const ExtJob& J, uint64_t s,
+                                            const int32_t (&thr)[MAXK]) {
+  for (int v = 0; v < J.k; v++) {
+    const int p = J.var_pos[v];
+    if (p >= J.i) return false;  // unbound: undecided
+    const uint32_t x = (uint32_t)J.src_cols[(uint64_t)p * J.src_stride + s];
+    const uint32_t y = (uint32_t)thr[v];
+    if (x != y) return x > y;
+  }
+  return false;
+}
+
 // CPI list length of every partial match's spanning-tree parent.
 __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __restrict__ jobs) {
   const ExtJob& J = jobs[blockIdx.y];
   if (!J.active) return;
   const int32_t* par = J.src_cols + (uint64_t)J.par_pos * J.src_stride;
+  const bool prune = J.prune && J.thr != nullptr && *J.d_thr_valid != 0;
+  int32_t thr[MAXK];
+#pragma unroll
+  for (int v = 0; v < MAXK; v++) thr[v] = prune && v < J.k ? J.thr[v] : 0;
   job_scan(ext_sources(J), [&](uint64_t s) -> uint32_t {
     const int32_t c = J.par_posmap[par[s]];
     J.begs[s] = J.cpi_beg[c];
+    if (prune && source_past(J, s, thr)) return 0u;
     return J.cpi_len[c];
   }, J.sc);
 }
