@@ -317,16 +317,6 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     });
     elb_start[d][rows[nblk]] = (uint32_t)ents[nblk];
   }
-  // edge filter: one bit per hashed ordered pair, at least 8 bits per edge
-  int ef_lg = 16;
-  while ((1ull << ef_lg) < 8ull * (uint64_t)m) ef_lg++;
-  std::vector<uint32_t> ef_bits((1ull << ef_lg) / 32, 0u);
-  for (int64_t v = 0; v < n; v++)
-    for (uint32_t e = out_off[v]; e < out_off[v + 1]; e++) {
-      const uint64_t key = ((uint64_t)(uint32_t)v << 32) | (uint32_t)out_nbr[e];
-      const uint64_t bit = (key * 0x9E3779B97F4A7C15ull) >> (64 - ef_lg);
-      ef_bits[bit >> 5] |= 1u << (bit & 31);
-    }
   std::vector<int32_t> attr_flat((size_t)num_attrs * n);
   for (int32_t a = 0; a < num_attrs; a++)
     std::memcpy(attr_flat.data() + (size_t)a * n, attr[a], sizeof(int32_t) * n);
@@ -361,15 +351,12 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     g->dg.lv_in_off = (const uint32_t*)up(lv_in_off.data(), 4 * (n + 1));
     g->dg.lv_in_nbr = (const int32_t*)up(lv_in_nbr.data(), 4 * m);
     g->dg.lv_in_lab = (const int32_t*)up(lv_in_lab.data(), 4 * m);
-    g->dg.ef_bits = (const uint32_t*)up(ef_bits.data(), 4 * ef_bits.size());
     for (int d = 0; d < 2; d++) {
       g->dg.elb_row[d] = (const uint32_t*)up(elb_row[d].data(), 4 * elb_row[d].size());
       g->dg.elb_start[d] = (const uint32_t*)up(elb_start[d].data(), 4 * elb_start[d].size());
       g->dg.elb_nbr[d] = (const int32_t*)up(elb_nbr[d].data(), 4 * elb_nbr[d].size());
       g->elb_blk[d] = std::move(elb_blk[d]);
     }
-    g->dg.ef_mask = (1ull << ef_lg) - 1;
-    g->dg.ef_shift = (uint32_t)(64 - ef_lg);
     HIPCHK(hipStreamSynchronize(st));
     g->lab_off = std::move(lab_off);
     g->lab_out_sum = std::move(lab_out);

@@ -68,11 +68,6 @@ struct DevGraph {
   const uint32_t* elb_row[2];    // [rows_d] bucket position of the row
   const uint32_t* elb_start[2];  // [rows_d + 1]
   const int32_t* elb_nbr[2];     // [m]
-  // edge filter: bit hash(a, b) is set for every edge a -> b, so a clear bit
-  // proves that a -> b is no edge (a set bit proves nothing)
-  const uint32_t* ef_bits;     // [(ef_mask + 1) / 32]
-  uint64_t ef_mask;            // bits - 1 (bits a power of two, >= 8 m)
-  uint32_t ef_shift;           // 64 - log2(bits)
 };
 
 // A candidate set C(u): its members (list, *cnt), their positions in the list

@@ -80,55 +80,43 @@ __device__ __forceinline__ void block_add(unsigned long long* dst, unsigned long
   }
 }
 
-// Label of data edge a -> b, or NOEDGE: binary search of the shorter of
-// out-row(a) (for b) and in-row(b) (for a).  Power-law hubs make the two
-// lengths differ by orders of magnitude.
-__device__ __forceinline__ int32_t edge_label(const DevGraph& g, int32_t a, int32_t b,
-                                              unsigned long long& by) {
-  const uint32_t oa = g.out_off[a], oa1 = g.out_off[a + 1];
-  const uint32_t ib = g.in_off[b], ib1 = g.in_off[b + 1];
-  by += 16;
-  const bool use_out = (oa1 - oa) <= (ib1 - ib);
-  const int32_t* nbr = use_out ? g.out_nbr : g.in_nbr;
-  const int32_t* lab = use_out ? g.out_lab : g.in_lab;
-  const int32_t key = use_out ? b : a;
-  uint32_t lo = use_out ? oa : ib, hi = use_out ? oa1 : ib1;
-  const uint32_t end = hi;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    by += 4;
-    if (nbr[mid] < key) lo = mid + 1; else hi = mid;
-  }
-  if (lo < end && nbr[lo] == key) {
-    by += 8;
-    return lab[lo];
-  }
-  return NOEDGE;
-}
-
 __device__ __forceinline__ bool constraint_ok(int32_t found, int32_t code) {
   if (code == PC_FREE) return true;
   if (code == PC_ABSENT) return found == NOEDGE;
   return found != NOEDGE && (code == ANY || found == code);
 }
 
-// Whether a -> b may be an edge: false is certain (its filter bit is clear).
-// The 8-bits-per-edge filter stays in the last-level cache.
-__device__ __forceinline__ bool maybe_edge(const DevGraph& g, int32_t a, int32_t b,
-                                           unsigned long long& by) {
-  const uint64_t key = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
-  const uint64_t bit = (key * 0x9E3779B97F4A7C15ull) >> g.ef_shift;
-  by += 4;
-  return (g.ef_bits[bit >> 5] >> (bit & 31)) & 1u;
+// Label of data edge a -> b, or NOEDGE, searching the row of `anchor` (a's
+// out-row when anchor == a, else b's in-row).  Enumeration and CPI probes
+// anchor on the vertex that neighbouring threads share (the earlier matched
+// vertex, the CPI source), so the searched row stays in cache across the
+// wave instead of each thread fetching its own candidate's row.
+__device__ __forceinline__ int32_t edge_label_at(const DevGraph& g, int32_t a, int32_t b,
+                                                 bool anchor_a, unsigned long long& by) {
+  const uint32_t* off = anchor_a ? g.out_off : g.in_off;
+  const int32_t* nbr = anchor_a ? g.out_nbr : g.in_nbr;
+  const int32_t* lab = anchor_a ? g.out_lab : g.in_lab;
+  const int32_t row = anchor_a ? a : b, key = anchor_a ? b : a;
+  uint32_t lo = off[row], hi = off[row + 1];
+  const uint32_t end = hi;
+  by += 8;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    by += 4;
+    if (nbr[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  if (lo < end && nbr[lo] == key) {
+    by += 4;
+    return lab[lo];
+  }
+  return NOEDGE;
 }
 
-// Constraint `code` on data edge a -> b; an absence requirement is settled by
-// the edge filter whenever its bit is clear, without searching a row.
-__device__ __forceinline__ bool pair_ok(const DevGraph& g, int32_t a, int32_t b, int32_t code,
-                                        unsigned long long& by) {
+// Constraint `code` on data edge a -> b, probed in the anchor's row.
+__device__ __forceinline__ bool pair_ok(const DevGraph& g, int32_t a, int32_t b, bool anchor_a,
+                                        int32_t code, unsigned long long& by) {
   if (code == PC_FREE) return true;
-  if (code == PC_ABSENT && !maybe_edge(g, a, b, by)) return true;
-  return constraint_ok(edge_label(g, a, b, by), code);
+  return constraint_ok(edge_label_at(g, a, b, anchor_a, by), code);
 }
 
 // Membership bitmaps (n bits, 512 KB at 4M vertices) stay in L2: their probes
@@ -703,7 +691,8 @@ __device__ __forceinline__ bool cpi_keep(const DevGraph& g, const CpiJob& J, int
   if (!member(J.u, v)) return false;
   if (J.other == PC_FREE) return true;
   // dir 0 scanned vp -> v, so the reverse is v -> vp; dir 1 the opposite
-  return J.dir ? pair_ok(g, vp, v, J.other, by) : pair_ok(g, v, vp, J.other, by);
+  // in the row of the source vp, shared by the threads of its entries
+  return J.dir ? pair_ok(g, vp, v, true, J.other, by) : pair_ok(g, v, vp, false, J.other, by);
 }
 
 // Row lengths of the members of C(p); clears the per-source counters.
@@ -1036,7 +1025,9 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
         if (LAST && ok && thr_on && J.collect_only) ok = !past_threshold(J, h, thr);
         for (int c = 0; c < J.nchk && ok; c++) {
           const int32_t hw = pick(h, J.chk_pos[c]);
-          ok = pair_ok(g, hw, v, J.chk_fwd[c], by) && pair_ok(g, v, hw, J.chk_bwd[c], by);
+          // both directions in rows of hw, which the wave's threads share
+          ok = pair_ok(g, hw, v, true, J.chk_fwd[c], by) &&
+               pair_ok(g, v, hw, false, J.chk_bwd[c], by);
         }
       }
       if (!LAST) {  // block-aggregated append to the next frontier
