@@ -28,6 +28,28 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 K_REPORT = 1024
 
 
+# HBM traffic of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this workload scaled by the same counters on a plain
+# 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
+# for the kernel sources it was measured on (sha256 of the two files below).
+TRAFFIC = {
+    "sources_sha256": None,
+    "workload": "kg_4m_batch256",
+    "kernel_class": "extend_last",
+    "bytes_per_launch": None,
+}
+TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -69,10 +91,15 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write elementwise kernel "
                          "(int32 negation) three times: the calibration run for HBM counters")
+    ap.add_argument("--sources-sha256", action="store_true",
+                    help="print the hash of the kernel sources that counter figures are keyed on")
     ap.add_argument("--per-gfd", type=int, default=0, metavar="N",
                     help="diagnostic: validate each GFD alone with statistics and print the "
                          "N slowest to stderr")
     args = ap.parse_args()
+    if args.sources_sha256:
+        print(sources_sha256())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; how the path would shard "
@@ -155,8 +182,13 @@ def main():
         avg_ms = agg_ms / agg_launch
         per_launch = agg_bytes / agg_launch
         ach = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        traffic = None
+        if (TRAFFIC["bytes_per_launch"] and TRAFFIC["kernel_class"] == name
+                and TRAFFIC["workload"] == args.workload
+                and TRAFFIC["sources_sha256"] == sources_sha256()):
+            traffic = TRAFFIC["bytes_per_launch"]
         roofline = {"bound": "hbm", "kernel_class": name, "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": per_launch,
                     "launches_per_step": agg_launch / args.steps}
 

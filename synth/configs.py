@@ -5,6 +5,9 @@
     kg_4m              Chung-Lu 4M / 20M (gamma 2.1), 16 walk GFDs of 4-8 vertices
     kg_4m_batch256     the kg_4m graph, 256 walk GFDs of 2-8 vertices
     kg_4m_serving      the kg_4m graph, Poisson request stream (1-4 GFDs each)
+    twitch_trio        undirected Chung-Lu 20,000 vertices / 92,798 edges (each as two
+                       antiparallel edges), two language labels, boolean 'abandoned'
+                       and 'affiliate'; the paper's path, star and triangle GFDs
 
 The paper measures on a public social graph (Twitch Gamers) that is not
 available here; these synthetic inputs stand in for it.  Every array comes from
@@ -33,11 +36,16 @@ GRAPHS = {
                         attr_zipf=1.1),
     "kg_4m": dict(seed=2, n=4_000_000, m=20_000_000, model="chung_lu", n_vlabels=100,
                   n_elabels=40, label_zipf=1.2, n_attrs=4, attr_values=100_000, attr_zipf=1.2),
+    # vertex labels: 0 = EN, 1 = RU; attributes: 0 = abandoned, 1 = affiliate (0 = F, 1 = T)
+    "twitch_20k": dict(seed=5, n=20_000, m=2 * 92_798, model="chung_lu_sym", n_vlabels=2,
+                       n_elabels=1, label_zipf=None, n_attrs=2, attr_values=2, attr_zipf=None),
 }
 
 CONFIG_GRAPH = {"small_uniform": "small_uniform", "powerlaw_1m": "powerlaw_1m",
-                "kg_4m": "kg_4m", "kg_4m_batch256": "kg_4m", "kg_4m_serving": "kg_4m"}
-CONFIG_ORDER = ["small_uniform", "powerlaw_1m", "kg_4m", "kg_4m_batch256", "kg_4m_serving"]
+                "kg_4m": "kg_4m", "kg_4m_batch256": "kg_4m", "kg_4m_serving": "kg_4m",
+                "twitch_trio": "twitch_20k"}
+CONFIG_ORDER = ["small_uniform", "powerlaw_1m", "kg_4m", "kg_4m_batch256", "kg_4m_serving",
+                "twitch_trio"]
 
 
 def cache_dir() -> str:
@@ -82,7 +90,7 @@ def graph(name: str, use_cache: bool = True) -> Graph:
 def gfd_stream(name: str):
     spec = GRAPHS[CONFIG_GRAPH[name]]
     seed = {"small_uniform": 0, "powerlaw_1m": 1, "kg_4m": 2, "kg_4m_batch256": 3,
-            "kg_4m_serving": 4}[name]
+            "kg_4m_serving": 4, "twitch_trio": 5}[name]
     ss = np.random.SeedSequence(seed).spawn(5)
     return np.random.Generator(np.random.PCG64(ss[4])), spec
 
@@ -95,6 +103,8 @@ def _gfds_uncached(name: str, g: Graph):
         return [{"k": 3, "vlabels": [0, 1, 1], "edges": [[0, 1, 0], [0, 2, 0]], "x": [],
                  "y": [{"kind": "var", "var": 1, "attr": 0, "var2": 2, "attr2": 0}],
                  "y_false": False, "meta": {"fixed": True}}]
+    if name == "twitch_trio":
+        return twitch_trio()
     view = P.GraphView(g)
     out = []
     if name == "powerlaw_1m":
@@ -116,6 +126,29 @@ def _gfds_uncached(name: str, g: Graph):
             out.append(P.sample_walk_gfd(rng, view, (2, 8), (1, 3), av, az, cyc_range=(0, 3)))
         return out
     raise ValueError(name)
+
+
+def _undirected(pairs, label=0):
+    """Pattern edges of undirected pairs: one antiparallel pair each."""
+    return [e for a, b in pairs for e in ([a, b, label], [b, a, label])]
+
+
+def twitch_trio():
+    """The three queries of the paper's evaluation (Section V): on a followship
+    graph with language labels EN (0) / RU (1) and boolean attributes abandoned
+    (0) and affiliate (1), T = 1, F = 0.  Each also appears as X -> false."""
+    T, F = 1, 0
+    ab = lambda v, c: {"kind": "const", "var": v, "attr": 0, "value": c}  # noqa: E731
+    af = lambda v, c: {"kind": "const", "var": v, "attr": 1, "value": c}  # noqa: E731
+    path = {"k": 3, "vlabels": [0, 0, 0], "edges": _undirected([(0, 1), (1, 2)]),
+            "x": [ab(0, T), ab(1, T), ab(2, T)], "y": [af(1, T)], "y_false": False}
+    star = {"k": 4, "vlabels": [1, 1, 1, 1], "edges": _undirected([(0, 1), (0, 2), (0, 3)]),
+            "x": [], "y": [ab(0, F)], "y_false": False}
+    tri = {"k": 3, "vlabels": [0, 0, 0], "edges": _undirected([(0, 1), (1, 2), (0, 2)]),
+           "x": [ab(0, T), ab(1, T)], "y": [ab(2, T)], "y_false": False}
+    out = [path, star, tri]
+    out += [dict(d, y=[], y_false=True) for d in (path, star, tri)]
+    return out
 
 
 FROZEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")

@@ -135,21 +135,55 @@ def chung_lu_edges(rng, n: int, m: int, gamma: float) -> np.ndarray:
     return _distinct_pairs(rng, n, m, draw)
 
 
+def chung_lu_symmetric_pairs(rng, n: int, m_pairs: int, gamma: float) -> np.ndarray:
+    """Undirected Chung-Lu: both endpoints ~ w (one permutation), expected degree
+    w_i (capped at sqrt of the directed edge count); returns m_pairs distinct
+    unordered pairs as keys min*n+max, in order of first occurrence."""
+    w = chung_lu_weights(n, 2 * m_pairs, gamma)[rng.permutation(n)]
+    c = np.cumsum(w)
+    t = c[-1]
+
+    def inverse_cdf(b):
+        r = rng.random(b) * t
+        order = np.argsort(r, kind="stable")
+        out = np.empty(b, dtype=np.int64)
+        out[order] = np.searchsorted(c, r[order], side="right")
+        return np.minimum(out, n - 1)
+
+    def draw(b):
+        a, z = inverse_cdf(b), inverse_cdf(b)
+        return np.minimum(a, z), np.maximum(a, z)
+    return _distinct_pairs(rng, n, m_pairs, draw)
+
+
 def make_graph(seed: int, n: int, m: int, *, model: str, n_vlabels: int, n_elabels: int,
                label_zipf: float | None, n_attrs: int, attr_values: int,
                attr_zipf: float | None, gamma: float = 2.1,
                absent_frac: float = 0.0) -> tuple[Graph, np.random.Generator]:
     """Build one graph; returns it with the (unused) GFD sub-stream."""
     rs = sub_streams(seed)
-    if model == "uniform":
-        keys = uniform_edges(rs["edges"], n, m)
-    elif model == "chung_lu":
-        keys = chung_lu_edges(rs["edges"], n, m, gamma)
+    if model == "chung_lu_sym":
+        # every undirected pair becomes two antiparallel edges with one label
+        if m % 2:
+            raise ValueError("a symmetric graph has an even edge count")
+        pairs = chung_lu_symmetric_pairs(rs["edges"], n, m // 2, gamma)
+        plab = draw_codes(rs["elabels"], n_elabels, m // 2, label_zipf)
+        lo, hi = pairs // n, pairs % n
+        keys = np.concatenate([lo * n + hi, hi * n + lo])
+        labs = np.concatenate([plab, plab])
+        order = np.argsort(keys, kind="stable")
+        keys, elabel = keys[order], labs[order].astype(np.int32)
+        row_ptr, col = _csr_from_keys(keys, n)
     else:
-        raise ValueError(model)
-    row_ptr, col = _csr_from_keys(keys, n)
+        if model == "uniform":
+            keys = uniform_edges(rs["edges"], n, m)
+        elif model == "chung_lu":
+            keys = chung_lu_edges(rs["edges"], n, m, gamma)
+        else:
+            raise ValueError(model)
+        row_ptr, col = _csr_from_keys(keys, n)
+        elabel = draw_codes(rs["elabels"], n_elabels, m, label_zipf)
     vlabel = draw_codes(rs["vlabels"], n_vlabels, n, label_zipf)
-    elabel = draw_codes(rs["elabels"], n_elabels, m, label_zipf)
     attrs = np.empty((n_attrs, n), dtype=np.int32)
     for a in range(n_attrs):
         attrs[a] = draw_codes(rs["attrs"], attr_values, n, attr_zipf)
@@ -158,8 +192,8 @@ def make_graph(seed: int, n: int, m: int, *, model: str, n_vlabels: int, n_elabe
         attrs[holes] = ABSENT
     meta = dict(seed=seed, n=n, m=m, model=model, n_vlabels=n_vlabels, n_elabels=n_elabels,
                 label_zipf=label_zipf, n_attrs=n_attrs, attr_values=attr_values,
-                attr_zipf=attr_zipf, gamma=gamma if model == "chung_lu" else None,
-                degree_cap=float(np.sqrt(m)) if model == "chung_lu" else None,
+                attr_zipf=attr_zipf, gamma=gamma if model.startswith("chung_lu") else None,
+                degree_cap=float(np.sqrt(m)) if model.startswith("chung_lu") else None,
                 absent_frac=absent_frac)
     g = Graph(n=n, m=m, row_ptr=row_ptr, col=col, vlabel=vlabel, elabel=elabel,
               attrs=attrs, meta=meta)

@@ -261,7 +261,7 @@ def _expected(name):
 
 @pytest.mark.slow
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("name", ["powerlaw_1m", "kg_4m", "kg_4m_batch256"])
+@pytest.mark.parametrize("name", ["powerlaw_1m", "kg_4m", "kg_4m_batch256", "twitch_trio"])
 def test_full_size_configs(P, name):
     """Full-size workloads in the benchmark's launch configuration, against
     oracle results stored by tests/golden/make_expected.py."""
