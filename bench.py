@@ -10,7 +10,12 @@ Default workload: the 4M-vertex / 20M-edge knowledge-graph-shaped graph with
 also timed one at a time (256 sequential single-GFD calls) for the
 batched-vs-one-at-a-time ratio.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload kg_4m_batch256|kg_4m|powerlaw_1m]
+    python bench.py [--steps K] [--warmup W] [--workload kg_4m_batch256|kg_4m|powerlaw_1m|twitch_trio]
+    python bench.py --workload kg_4m_serving [--serve-seconds S]
+
+The serving workload replays Poisson arrivals (200 requests/s, each 1-4 GFDs
+of 3-8 vertices drawn from the 256-GFD pool) against gfd_server_* with
+continuous batching and reports p50/p99 latency beside throughput.
 """
 from __future__ import annotations
 
@@ -73,6 +78,80 @@ def cpu_baseline(g, gfds, semantics, frac, threads):
             "gfds_per_s": len(gfds) * frac / dt}
 
 
+def serve(args, torch, P, g, gh):
+    """Continuous-batching server under Poisson arrivals; every served result is
+    checked against the same GFD validated alone."""
+    import threading
+    import numpy as np
+    from synth import configs
+    pool = [{k: v for k, v in d.items() if k != "meta"} for d in configs.gfds("kg_4m_batch256", g)
+            if d["k"] >= 3]
+    rng = np.random.default_rng(4)
+    t, arrivals = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / args.serve_rate))
+        if t >= args.serve_seconds:
+            break
+        arrivals.append((t, [int(i) for i in rng.integers(0, len(pool), int(rng.integers(1, 5)))]))
+    log(f"serving: {len(arrivals)} requests over {args.serve_seconds} s from a pool of {len(pool)}")
+    # each pool GFD alone (the reference for the served results)
+    alone = []
+    for d in pool:
+        q = P.PreparedCall(gh, [d], K=K_REPORT, semantics=args.semantics)
+        q.run(stats=False)
+        alone.append(q.results()[0])
+    srv = P.Server(gh, K=K_REPORT, semantics=args.semantics, workers=args.serve_workers)
+    for w in range(3):  # warm-up: workspaces and first launches
+        srv.wait(srv.submit([pool[i] for i in arrivals[w][1]]))
+    done = [None] * len(arrivals)
+    ids = [None] * len(arrivals)
+    ready = [threading.Event() for _ in arrivals]
+
+    def waiter():
+        for j in range(len(arrivals)):
+            ready[j].wait()
+            done[j] = srv.wait(ids[j])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for j, (ta, req) in enumerate(arrivals):
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        ids[j] = srv.submit([pool[i] for i in req])
+        ready[j].set()
+    th.join()
+    srv.close()
+    lat = np.array([(info["done_ns"] - info["submit_ns"]) / 1e6 for _, info in done])
+    first = min(info["submit_ns"] for _, info in done)
+    last = max(info["done_ns"] for _, info in done)
+    wall = (last - first) / 1e9
+    ngfd = sum(len(req) for _, req in arrivals)
+    matches = 0
+    for (res, _), (_, req) in zip(done, arrivals):
+        assert res == [alone[i] for i in req], "a served result differs from the GFD alone"
+        matches += sum(r["match_count"] for r in res)
+    batches = {info["batch_id"]: info["batch_gfds"] for _, info in done}
+    out = {"metric": METRIC, "value": matches / wall, "unit": "embeddings/s", "n_gpus": 1,
+           "steps": len(arrivals), "warmup": 3, "ms_per_step": float(np.mean(lat)),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic", "gfds_per_s": ngfd / wall,
+           "config": {"workload": "kg_4m_serving", "mode": "serving", "n": g.n, "m": g.m,
+                      "rate_per_s": args.serve_rate, "seconds": args.serve_seconds,
+                      "semantics": args.semantics, "K": K_REPORT, "workers": args.serve_workers,
+                      "parallelism": "single_gpu"},
+           "serving": {"requests": len(arrivals), "gfds": ngfd, "p50_ms": float(np.percentile(lat, 50)),
+                       "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+                       "batches": len(batches),
+                       "mean_batch_gfds": float(np.mean(list(batches.values()))),
+                       "identical_to_alone": True},
+           "roofline": None}
+    log(f"serving: p50 {out['serving']['p50_ms']:.1f} ms, p99 {out['serving']['p99_ms']:.1f} ms, "
+        f"{out['gfds_per_s']:.0f} GFDs/s, {len(batches)} batches")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +162,9 @@ def main():
                     help="default: batched for the 256-GFD workload, plain otherwise")
     ap.add_argument("--semantics", default="induced", choices=["induced", "mono"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--cpu-frac", type=float, default=None)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the one-at-a-time comparison")
@@ -126,13 +208,18 @@ def main():
 
     t = time.perf_counter()
     g = configs.graph(configs.CONFIG_GRAPH[args.workload])
-    gfds = [{k: v for k, v in d.items() if k != "meta"} for d in configs.gfds(args.workload, g)]
+    gfds = [] if args.workload == "kg_4m_serving" else \
+        [{k: v for k, v in d.items() if k != "meta"} for d in configs.gfds(args.workload, g)]
     log(f"inputs: {args.workload} n={g.n} m={g.m} gfds={len(gfds)} ({time.perf_counter() - t:.1f}s)")
     stream = torch.cuda.current_stream()
     t = time.perf_counter()
     gh = P.load(g, stream=stream)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t
+    if args.workload == "kg_4m_serving":
+        serve(args, torch, P, g, gh)
+        gh.free()
+        return
     batched = mode == "batched"
 
     # specs, options and result buffers are marshalled once; a step is one

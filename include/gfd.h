@@ -44,6 +44,7 @@ extern "C" {
 #define GFD_EDEVICE (-3)      /* HIP runtime error */
 #define GFD_EUNSUPPORTED (-4) /* valid input outside this build's limits */
 #define GFD_EOVERFLOW (-5)    /* a 64-bit counter would pass 2^63 */
+#define GFD_EAGAIN (-6)       /* a server request did not finish within the wait's timeout */
 
 #define GFD_WILDCARD (-1)
 #define GFD_ABSENT (-1)
@@ -184,6 +185,57 @@ typedef struct {
   int64_t device_bytes;
 } gfd_graph_info;
 int32_t gfd_get_graph_info(const gfd_graph* g, gfd_graph_info* info);
+
+/* ---------------------------------------------------------------------------
+ * Serving: the graph stays resident and validation requests (each a list of
+ * GFDs) arrive over time.  Worker threads, each with its own HIP stream and
+ * workspace, take every request waiting in arrival order -- as many as fit the
+ * GFD limit and the per-worker memory budget by their estimated device bytes
+ * (candidate sets, CPI lists, frontiers, violation staging) -- and validate
+ * them as one batch (gfd_validate with batched = 1).  A request that arrives
+ * while batches run joins the next batch a worker forms, and batches on
+ * different workers overlap on the GPU.  Results are exactly those of
+ * gfd_validate on the request alone (Section II's validation problem per
+ * GFD; batching changes only the schedule).
+ * ------------------------------------------------------------------------- */
+typedef struct gfd_server gfd_server; /* opaque */
+
+typedef struct {
+  int32_t workers;          /* batches in flight at once (1..8); 0 = 2 */
+  int32_t max_batch_gfds;   /* GFDs per batch (1..256); 0 = 256 */
+  int64_t mem_budget_bytes; /* device bytes per worker; 0 = default share */
+  int32_t k_max;            /* violations reported per GFD (0..2048) */
+  int32_t semantics;        /* GFD_SEM_INDUCED or GFD_SEM_MONO */
+} gfd_server_opts;
+
+typedef struct {
+  int64_t submit_ns, start_ns, done_ns; /* steady clock: queued, batch start, batch end */
+  uint64_t batch_id;                    /* the batch that served the request */
+  int32_t batch_gfds, batch_requests;   /* that batch's size */
+  int32_t worker;
+} gfd_request_info;
+
+/* Start a server on a loaded graph (which must outlive it).  Errors: GFD_EINVAL
+ * for options out of range, GFD_EDEVICE / GFD_ENOMEM from the device. */
+int32_t gfd_server_create(const gfd_graph* g, const gfd_server_opts* opts, gfd_server** out);
+
+/* Queue one request of num_specs (1..max_batch_gfds) GFDs; specs are copied.
+ * A malformed spec fails the submit with GFD_EINVAL (nothing is queued); a
+ * disconnected pattern with GFD_EUNSUPPORTED.  Thread-safe. */
+int32_t gfd_server_submit(gfd_server* s, const gfd_spec* specs, int32_t num_specs,
+                          uint64_t* request_id);
+
+/* Wait for a request: timeout_ms < 0 waits without limit; GFD_EAGAIN if it has
+ * not finished in time (wait again later).  On completion fills results
+ * [num_specs] (each violations buffer caller-owned, room for k_max tuples of
+ * that GFD) and info (may be NULL), forgets the request and returns the
+ * status of its batch.  Each request is waited for successfully once. */
+int32_t gfd_server_wait(gfd_server* s, uint64_t request_id, int32_t timeout_ms,
+                        gfd_result* results, gfd_request_info* info);
+
+/* Finish every queued request, stop the workers and free the server (results
+ * never waited for are dropped).  NULL is ignored. */
+void gfd_server_destroy(gfd_server* s);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* gfd_last_error(void);

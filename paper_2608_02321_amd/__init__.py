@@ -4,8 +4,8 @@ behind the C ABI in include/gfd.h.  This package is the thin Python binding.
 """
 from ._binding import (GFD_ABSENT, GFD_FLAG_FORCE_CHUNKED, GFD_FLAG_TIMING, GFD_MAX_K,
                        GFD_SEM_INDUCED, GFD_SEM_MONO, GFD_WILDCARD, GfdError, GraphHandle,
-                       PreparedCall, free_graph, last_error, load, load_graph, make_spec, validate, version)
+                       PreparedCall, Server, free_graph, last_error, load, load_graph, make_spec, validate, version)
 
 __all__ = ["GFD_ABSENT", "GFD_FLAG_FORCE_CHUNKED", "GFD_FLAG_TIMING", "GFD_MAX_K",
            "GFD_SEM_INDUCED", "GFD_SEM_MONO", "GFD_WILDCARD", "GfdError", "GraphHandle",
-           "PreparedCall", "free_graph", "last_error", "load", "load_graph", "make_spec", "validate", "version"]
+           "PreparedCall", "Server", "free_graph", "last_error", "load", "load_graph", "make_spec", "validate", "version"]

@@ -15,6 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libgfd.so")
 
 GFD_OK, GFD_EINVAL, GFD_ENOMEM, GFD_EDEVICE, GFD_EUNSUPPORTED, GFD_EOVERFLOW = 0, -1, -2, -3, -4, -5
+GFD_EAGAIN = -6
 GFD_WILDCARD = GFD_ABSENT = -1
 GFD_MAX_K = 8
 GFD_MAX_LITERALS = 8
@@ -23,7 +24,7 @@ GFD_LIT_CONST, GFD_LIT_VAR = 0, 1
 GFD_SEM_INDUCED, GFD_SEM_MONO = 0, 1
 GFD_FLAG_FORCE_CHUNKED, GFD_FLAG_TIMING = 1, 2
 STATUS_NAMES = {0: "GFD_OK", -1: "GFD_EINVAL", -2: "GFD_ENOMEM", -3: "GFD_EDEVICE",
-                -4: "GFD_EUNSUPPORTED", -5: "GFD_EOVERFLOW"}
+                -4: "GFD_EUNSUPPORTED", -5: "GFD_EOVERFLOW", -6: "GFD_EAGAIN"}
 KERNEL_CLASSES = ("filter", "pull", "cpi", "extend", "extend_last", "scan", "topk", "other")
 
 
@@ -83,8 +84,20 @@ class gfd_graph_info(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
+class gfd_server_opts(C.Structure):
+    _fields_ = [("workers", C.c_int32), ("max_batch_gfds", C.c_int32),
+                ("mem_budget_bytes", C.c_int64), ("k_max", C.c_int32), ("semantics", C.c_int32)]
+
+
+class gfd_request_info(C.Structure):
+    _fields_ = [("submit_ns", C.c_int64), ("start_ns", C.c_int64), ("done_ns", C.c_int64),
+                ("batch_id", C.c_uint64), ("batch_gfds", C.c_int32),
+                ("batch_requests", C.c_int32), ("worker", C.c_int32)]
+
+
 EXPORTS = ("gfd_load_graph", "gfd_free_graph", "gfd_validate", "gfd_validate_ex",
-           "gfd_get_graph_info", "gfd_last_error", "gfd_version")
+           "gfd_get_graph_info", "gfd_server_create", "gfd_server_submit", "gfd_server_wait",
+           "gfd_server_destroy", "gfd_last_error", "gfd_version")
 
 
 def _load():
@@ -119,6 +132,16 @@ def _load():
     L.gfd_last_error.argtypes = []
     L.gfd_version.restype = C.c_int32
     L.gfd_version.argtypes = []
+    L.gfd_server_create.restype = C.c_int32
+    L.gfd_server_create.argtypes = [C.c_void_p, C.POINTER(gfd_server_opts), C.POINTER(C.c_void_p)]
+    L.gfd_server_submit.restype = C.c_int32
+    L.gfd_server_submit.argtypes = [C.c_void_p, C.POINTER(gfd_spec), C.c_int32,
+                                    C.POINTER(C.c_uint64)]
+    L.gfd_server_wait.restype = C.c_int32
+    L.gfd_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(gfd_result),
+                                  C.POINTER(gfd_request_info)]
+    L.gfd_server_destroy.restype = None
+    L.gfd_server_destroy.argtypes = [C.c_void_p]
     return L
 
 
@@ -317,3 +340,67 @@ def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced"
             sd[f] = dict(zip(KERNEL_CLASSES, list(sd[f])))
         return out, sd
     return out
+
+
+class Server:
+    """gfd_server_*: a resident graph serving validation requests with
+    continuous batching.  submit() returns a request id; wait() returns the
+    request's result dicts (as validate() gives them) and its timing info."""
+
+    def __init__(self, graph: GraphHandle, K: int = 1024, semantics: str = "induced",
+                 workers: int = 2, max_batch_gfds: int = 256, mem_budget_bytes: int = 0):
+        self.graph, self.K = graph, int(K)
+        opts = gfd_server_opts(int(workers), int(max_batch_gfds), int(mem_budget_bytes), self.K,
+                               GFD_SEM_INDUCED if semantics == "induced" else GFD_SEM_MONO)
+        h = C.c_void_p()
+        _check(lib.gfd_server_create(graph.handle, C.byref(opts), C.byref(h)))
+        self.handle = h
+        self.pending = {}
+
+    def submit(self, gfds) -> int:
+        n = len(gfds)
+        specs = (gfd_spec * max(n, 1))(*[make_spec(d) for d in gfds])
+        rid = C.c_uint64()
+        _check(lib.gfd_server_submit(self.handle, specs, n, C.byref(rid)))
+        self.pending[rid.value] = [int(d["k"]) for d in gfds]
+        return rid.value
+
+    def wait(self, rid: int, timeout_ms: int = -1):
+        """(results, info) once the request is done; None if not done within
+        timeout_ms (timeout_ms < 0: wait as long as it takes)."""
+        ks = self.pending.get(rid)
+        if ks is None:  # not submitted here: the library reports it
+            _check(lib.gfd_server_wait(self.handle, rid, int(timeout_ms), None, None))
+            raise GfdError(GFD_EINVAL, f"request {rid} unknown")
+        n = len(ks)
+        res = (gfd_result * n)()
+        bufs = []
+        for i, k in enumerate(ks):
+            b = np.zeros(max(1, self.K * k), dtype=np.int32)
+            bufs.append(b)
+            res[i].violations = b.ctypes.data_as(C.POINTER(C.c_int32))
+        info = gfd_request_info()
+        rc = lib.gfd_server_wait(self.handle, rid, int(timeout_ms), res, C.byref(info))
+        if rc == GFD_EAGAIN:
+            return None
+        del self.pending[rid]
+        _check(rc)
+        out = []
+        for i, k in enumerate(ks):
+            r = res[i]
+            out.append({"match_count": int(r.match_count), "violation_count": int(r.violation_count),
+                        "match_fp": int(r.match_fp), "violation_fp": int(r.violation_fp),
+                        "satisfied": bool(r.satisfied),
+                        "violations": bufs[i][:r.num_reported * k].reshape(-1, k).tolist()})
+        return out, {f: getattr(info, f) for f, _ in gfd_request_info._fields_}
+
+    def close(self):
+        if self.handle:
+            lib.gfd_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

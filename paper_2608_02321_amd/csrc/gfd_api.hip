@@ -16,14 +16,17 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "gfd.h"
@@ -1179,6 +1182,16 @@ static void upload_recs(Ctx& c, const Recs& R) {
 }
 
 // Arena of a batch: [control blocks][tile states][results][job regions].
+// The batch arena only grows (allocations of this size are slow).
+static void ensure_arena(Workspace* ws, size_t bytes) {
+  if (ws->arena_bytes >= bytes) return;
+  dfree(ws->arena);
+  ws->arena = nullptr;
+  ws->arena_bytes = 0;
+  ws->arena = dalloc<uint8_t>(bytes);
+  ws->arena_bytes = bytes;
+}
+
 static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
   Workspace* ws = c.ws;
   const size_t nj = jobs.size();
@@ -1192,13 +1205,7 @@ static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
   const size_t ts_b = align_up(sizeof(uint64_t) * tiles * nj);
   const size_t res_b = align_up(sizeof(int32_t) * (size_t)std::max(c.K, 1) * MAXK * nj);
   const size_t total = ctl_b + ts_b + res_b + body;
-  if (ws->arena_bytes < total) {
-    dfree(ws->arena);
-    ws->arena = nullptr;
-    ws->arena_bytes = 0;
-    ws->arena = dalloc<uint8_t>(total);
-    ws->arena_bytes = total;
-  }
+  ensure_arena(ws, total);
   uint8_t* p = ws->arena + ctl_b + ts_b + res_b;
   for (size_t x = 0; x < nj; x++) {
     Job& J = jobs[x];
@@ -1563,6 +1570,37 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
   }
 }
 
+// Capacities of one call: violation staging per job (vsmall), the bounded
+// path's staging (vbig) and the frontier bytes of each deep job (fbytes).
+struct Sizing {
+  uint64_t vsmall, vbig;
+  int64_t fbytes;
+};
+static Sizing call_sizing(int64_t budget, int64_t njobs, int64_t deep, int K, int64_t violation_cap) {
+  Sizing z;
+  njobs = std::max<int64_t>(1, njobs);
+  // violation staging per job: a sixteenth of the budget over the batch, at
+  // most 2^24 tuples shared by the batch's jobs (2^18 each from 64 jobs on:
+  // every radix-select pass reads what is staged)
+  const int64_t vmax = std::max<int64_t>(int64_t(1) << 18, (int64_t(1) << 24) / njobs);
+  const uint64_t vdef = (uint64_t)std::max<int64_t>(
+      16384, std::min<int64_t>(budget / (16 * njobs) / (4 * MAXK), vmax));
+  z.vsmall = std::max<uint64_t>(violation_cap ? (uint64_t)violation_cap : vdef, (uint64_t)K + 1);
+  z.vbig = std::max<uint64_t>(violation_cap ? (uint64_t)violation_cap : (4u << 20), (uint64_t)K + 64);
+  // half of the budget holds frontiers, shared evenly by the jobs of a batch
+  // that have any (k > 2), each sized for its own pattern size
+  z.fbytes = std::min<int64_t>(budget / (2 * std::max<int64_t>(1, deep)), int64_t(8) << 30);
+  return z;
+}
+
+// Frontier capacity of one job (64 partial matches per data edge bounds what
+// small graphs can need).
+static uint64_t frontier_cap_of(const gfd_graph* g, const Plan& p, int64_t fbytes, int64_t forced) {
+  if (forced) return (uint64_t)forced;
+  return (uint64_t)std::max<int64_t>(
+      4096, std::min<int64_t>(fbytes / (int64_t)per_slot_bytes(p.k), 64 * g->m));
+}
+
 static int64_t default_budget() {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return int64_t(4) << 30;
@@ -1644,13 +1682,11 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     }
     const int max_batch = o.batched ? MAX_JOBS : 1;
     const int64_t njobs_hint = std::min<int64_t>(num_specs, max_batch);
-    // violation staging per job: a sixteenth of the budget over a full batch
-    const uint64_t vdef = (uint64_t)std::max<int64_t>(
-        16384, std::min<int64_t>(budget / (16 * njobs_hint) / (4 * MAXK), int64_t(1) << 18));
-    const uint64_t vsmall = std::max<uint64_t>(o.violation_cap ? (uint64_t)o.violation_cap : vdef,
-                                               (uint64_t)K + 1);
-    const uint64_t vbig = std::max<uint64_t>(o.violation_cap ? (uint64_t)o.violation_cap : (4u << 20),
-                                             (uint64_t)K + 64);
+    int64_t deep = 0;
+    for (int32_t i = 0; i < num_specs; i++) deep += specs[i].num_vertices > 2;
+    const Sizing sz = call_sizing(budget, njobs_hint, std::min<int64_t>(deep, max_batch), K,
+                                  o.violation_cap);
+    const uint64_t vsmall = sz.vsmall, vbig = sz.vbig;
     Ctx c{g, ws, (hipStream_t)o.hip_stream, o.semantics == GFD_SEM_INDUCED, K, Timer{}, stats,
           stats ? ws->misc + 8 : nullptr};
     const uint32_t cls_mask = ((uint32_t)o.flags >> 8) & 0xFFu;
@@ -1661,22 +1697,11 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     HIPCHK(hipMemsetAsync(ws->err, 0, 4, c.st));
     // plans, capacities and batches
     std::vector<Job> all(num_specs);
-    // half of the budget holds frontiers, shared evenly by the jobs of a
-    // batch that have any (k > 2), each sized for its own pattern size
-    int64_t deep = 0;
-    for (int32_t i = 0; i < num_specs; i++) deep += specs[i].num_vertices > 2;
-    const int64_t fbytes = std::min<int64_t>(
-        budget / (2 * std::max<int64_t>(1, std::min<int64_t>(deep, max_batch))), int64_t(8) << 30);
     for (int32_t i = 0; i < num_specs; i++) {
       all[i].spec = i;
       make_plan(g, specs[i], c.induced, all[i].plan);
-      // (64 partial matches per data edge bounds what small graphs can need)
-      const uint64_t cap_f =
-          o.frontier_cap ? (uint64_t)o.frontier_cap
-                         : (uint64_t)std::max<int64_t>(
-                               4096, std::min<int64_t>(fbytes / (int64_t)per_slot_bytes(all[i].plan.k),
-                                                       64 * g->m));
-      job_caps(g, all[i].plan, cap_f, vsmall, all[i].caps);
+      job_caps(g, all[i].plan, frontier_cap_of(g, all[i].plan, sz.fbytes, o.frontier_cap), vsmall,
+               all[i].caps);
     }
     std::vector<std::vector<int>> batches;
     {
@@ -1816,4 +1841,270 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
 extern "C" int32_t gfd_validate(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
                                 const gfd_validate_opts* opts, gfd_result* results) {
   return gfd_validate_ex(g, specs, num_specs, opts, results, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// serving: a resident graph, a request queue and worker threads that batch
+// whatever is waiting whenever they are free (continuous batching)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct ServerReq {
+  uint64_t id = 0;
+  std::vector<gfd_spec> specs;
+  std::vector<gfd_result> res;
+  std::vector<int32_t> viol;  // [num_specs * k_max * GFD_MAX_K]
+  int64_t est_bytes = 0;
+  gfd_request_info info{};
+  int32_t status = GFD_OK;
+  std::string err;
+  bool done = false;
+};
+
+}  // namespace
+
+struct gfd_server {
+  gfd_graph* g = nullptr;
+  gfd_server_opts o{};
+  int64_t budget = 0;  // per worker
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<ServerReq*> queue;
+  std::unordered_map<uint64_t, ServerReq*> reqs;
+  uint64_t next_id = 1, next_batch = 1;
+  bool stop = false;
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+
+  void work(int w) {
+    (void)hipSetDevice(g->device);
+    for (;;) {
+      std::vector<ServerReq*> batch;
+      uint64_t bid = 0;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        if (queue.empty()) return;  // stopping
+        // admit waiting requests in arrival order while the batch stays within
+        // the GFD limit and the estimated device bytes of its jobs
+        int64_t n = 0, bytes = 0;
+        while (!queue.empty()) {
+          ServerReq* r = queue.front();
+          const int64_t rn = (int64_t)r->specs.size();
+          if (!batch.empty() && (n + rn > o.max_batch_gfds || bytes + r->est_bytes > budget)) break;
+          batch.push_back(r);
+          queue.pop_front();
+          n += rn;
+          bytes += r->est_bytes;
+        }
+        bid = next_batch++;
+      }
+      const int64_t t_start = now_ns();
+      std::vector<gfd_spec> specs;
+      std::vector<gfd_result> res;
+      for (ServerReq* r : batch) {
+        specs.insert(specs.end(), r->specs.begin(), r->specs.end());
+        for (size_t i = 0; i < r->specs.size(); i++) {
+          gfd_result x{};
+          x.violations = r->viol.data() + i * (size_t)std::max(o.k_max, 1) * GFD_MAX_K;
+          res.push_back(x);
+        }
+      }
+      gfd_validate_opts vo{};
+      vo.k_max = o.k_max;
+      vo.semantics = o.semantics;
+      vo.mem_budget_bytes = budget;
+      vo.hip_stream = streams[w];
+      vo.batched = 1;
+      const int32_t rc = gfd_validate(g, specs.data(), (int32_t)specs.size(), &vo, res.data());
+      const std::string msg = rc ? gfd_last_error() : "";
+      const int64_t t_done = now_ns();
+      std::lock_guard<std::mutex> lk(mu);
+      size_t at = 0;
+      for (ServerReq* r : batch) {
+        for (size_t i = 0; i < r->specs.size(); i++) r->res[i] = res[at++];
+        r->status = rc;
+        r->err = msg;
+        r->info.start_ns = t_start;
+        r->info.done_ns = t_done;
+        r->info.batch_id = bid;
+        r->info.batch_gfds = (int32_t)specs.size();
+        r->info.batch_requests = (int32_t)batch.size();
+        r->info.worker = w;
+        r->done = true;
+      }
+      cv_done.notify_all();
+    }
+  }
+};
+
+extern "C" int32_t gfd_server_create(const gfd_graph* gc, const gfd_server_opts* opts,
+                                     gfd_server** out) {
+  if (!out) return set_error(GFD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!gc) return set_error(GFD_EINVAL, "graph is NULL");
+  gfd_server_opts o{};
+  o.workers = 2;
+  o.max_batch_gfds = MAX_JOBS;
+  o.k_max = 1024;
+  o.semantics = GFD_SEM_INDUCED;
+  if (opts) o = *opts;
+  if (o.workers == 0) o.workers = 2;
+  if (o.max_batch_gfds == 0) o.max_batch_gfds = MAX_JOBS;
+  if (o.workers < 1 || o.workers > 8) return set_error(GFD_EINVAL, "workers must be 1..8");
+  if (o.max_batch_gfds < 1 || o.max_batch_gfds > MAX_JOBS)
+    return set_error(GFD_EINVAL, "max_batch_gfds must be 1..%d", MAX_JOBS);
+  if (o.k_max < 0 || o.k_max > SORT_MAX) return set_error(GFD_EINVAL, "k_max");
+  if (o.semantics != GFD_SEM_INDUCED && o.semantics != GFD_SEM_MONO) return set_error(GFD_EINVAL, "semantics");
+  if (o.mem_budget_bytes < 0) return set_error(GFD_EINVAL, "negative budget");
+  gfd_server* s = new gfd_server();
+  s->g = const_cast<gfd_graph*>(gc);
+  s->o = o;
+  try {
+    HIPCHK(hipSetDevice(s->g->device));
+    if (o.mem_budget_bytes) {
+      s->budget = o.mem_budget_bytes;
+    } else {  // the workers share what the default budget of one call would take
+      s->budget = std::max<int64_t>(int64_t(256) << 20, default_budget() / o.workers);
+    }
+    for (int w = 0; w < o.workers; w++) {
+      hipStream_t st = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      s->streams.push_back(st);
+    }
+    // one workspace per worker, its batch arena reserved up front for a full
+    // batch of the largest patterns (8 wildcard vertices on a path), within the
+    // budget: growing it while serving would stall a batch for seconds
+    int64_t reserve = 0;
+    {
+      gfd_spec path{};
+      path.num_vertices = MAXK;
+      for (int i = 0; i < MAXK; i++) path.vertex_labels[i] = GFD_WILDCARD;
+      path.num_edges = MAXK - 1;
+      for (int i = 0; i + 1 < MAXK; i++) path.edges[i] = gfd_edge{i, i + 1, GFD_WILDCARD};
+      const Sizing sz = call_sizing(s->budget, o.max_batch_gfds, o.max_batch_gfds, o.k_max, 0);
+      Plan p;
+      make_plan(s->g, path, o.semantics == GFD_SEM_INDUCED, p);
+      JobCaps caps;
+      job_caps(s->g, p, frontier_cap_of(s->g, p, sz.fbytes, 0), sz.vsmall, caps);
+      reserve = std::min<int64_t>(s->budget, (int64_t)o.max_batch_gfds * (int64_t)align_up(caps.bytes) +
+                                                 (int64_t(64) << 20));
+    }
+    std::vector<Workspace*> ws;
+    try {
+      for (int w = 0; w < o.workers; w++) {
+        ws.push_back(acquire_ws(s->g, s->budget));
+        ensure_arena(ws.back(), (size_t)reserve);
+      }
+    } catch (...) {
+      for (Workspace* x : ws) release_ws(s->g, x);
+      throw;
+    }
+    for (Workspace* x : ws) release_ws(s->g, x);
+    for (int w = 0; w < o.workers; w++) s->workers.emplace_back([s, w] { s->work(w); });
+  } catch (const GfdError& e) {
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    delete s;
+    return set_error(e.code, "%s", e.msg.c_str());
+  }
+  *out = s;
+  return GFD_OK;
+}
+
+extern "C" int32_t gfd_server_submit(gfd_server* s, const gfd_spec* specs, int32_t num_specs,
+                                     uint64_t* request_id) {
+  if (!s || !request_id || num_specs < 1 || !specs) return set_error(GFD_EINVAL, "server/specs/id");
+  if (num_specs > s->o.max_batch_gfds)
+    return set_error(GFD_EINVAL, "request of %d GFDs exceeds max_batch_gfds", num_specs);
+  auto* r = new ServerReq();
+  try {
+    const bool induced = s->o.semantics == GFD_SEM_INDUCED;
+    // estimated device bytes of the request's jobs, sized as in a full batch
+    const Sizing sz = call_sizing(s->budget, s->o.max_batch_gfds, s->o.max_batch_gfds, s->o.k_max, 0);
+    for (int32_t i = 0; i < num_specs; i++) {
+      const int32_t rc = check_spec(s->g, specs[i], i);
+      if (rc) {
+        delete r;
+        return rc;
+      }
+      Plan p;
+      make_plan(s->g, specs[i], induced, p);
+      JobCaps caps;
+      job_caps(s->g, p, frontier_cap_of(s->g, p, sz.fbytes, 0), sz.vsmall, caps);
+      r->est_bytes += (int64_t)caps.bytes;
+    }
+  } catch (const GfdError& e) {
+    delete r;
+    return set_error(e.code, "%s", e.msg.c_str());
+  }
+  r->specs.assign(specs, specs + num_specs);
+  r->res.resize(num_specs);
+  r->viol.resize((size_t)num_specs * std::max(s->o.k_max, 1) * GFD_MAX_K);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      delete r;
+      return set_error(GFD_EINVAL, "server is stopping");
+    }
+    r->id = s->next_id++;
+    r->info.submit_ns = now_ns();
+    s->reqs[r->id] = r;
+    s->queue.push_back(r);
+    *request_id = r->id;
+  }
+  s->cv_work.notify_one();
+  return GFD_OK;
+}
+
+extern "C" int32_t gfd_server_wait(gfd_server* s, uint64_t request_id, int32_t timeout_ms,
+                                   gfd_result* results, gfd_request_info* info) {
+  if (!s) return set_error(GFD_EINVAL, "server is NULL");
+  ServerReq* r = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(request_id);
+    if (it == s->reqs.end()) return set_error(GFD_EINVAL, "unknown request %llu", (unsigned long long)request_id);
+    r = it->second;
+    auto ready = [&] { return r->done; };
+    if (timeout_ms < 0) s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+      return set_error(GFD_EAGAIN, "request %llu not finished", (unsigned long long)request_id);
+    s->reqs.erase(it);
+  }
+  const int32_t rc = r->status;
+  if (rc) set_error(rc, "%s", r->err.c_str());
+  if (!rc && results) {
+    const int K = s->o.k_max;
+    for (size_t i = 0; i < r->specs.size(); i++) {
+      int32_t* dst = results[i].violations;
+      results[i] = r->res[i];
+      results[i].violations = dst;
+      if (K > 0 && dst && r->res[i].num_reported)
+        std::memcpy(dst, r->res[i].violations,
+                    sizeof(int32_t) * r->res[i].num_reported * r->specs[i].num_vertices);
+    }
+  }
+  if (info) *info = r->info;
+  delete r;
+  return rc;
+}
+
+extern "C" void gfd_server_destroy(gfd_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (auto& t : s->workers) t.join();
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  for (auto& kv : s->reqs) delete kv.second;
+  delete s;
 }

@@ -38,7 +38,8 @@ STRUCTS = {
     "gfd_literal": B.gfd_literal, "gfd_edge": B.gfd_edge, "gfd_spec": B.gfd_spec,
     "gfd_result": B.gfd_result, "gfd_load_opts": B.gfd_load_opts,
     "gfd_validate_opts": B.gfd_validate_opts, "gfd_stats": B.gfd_stats,
-    "gfd_graph_info": B.gfd_graph_info,
+    "gfd_graph_info": B.gfd_graph_info, "gfd_server_opts": B.gfd_server_opts,
+    "gfd_request_info": B.gfd_request_info,
 }
 
 
@@ -117,3 +118,14 @@ def test_validate_null_graph():
 
 def test_version():
     assert P.version() >= 100
+
+
+def test_server_rejects_bad_arguments():
+    h = C.c_void_p()
+    assert B.lib.gfd_server_create(None, None, C.byref(h)) == B.GFD_EINVAL
+    assert B.lib.gfd_server_create(None, None, None) == B.GFD_EINVAL
+    rid = C.c_uint64()
+    spec = B.make_spec({"k": 1, "vlabels": [0], "edges": [], "x": [], "y": []})
+    assert B.lib.gfd_server_submit(None, C.byref(spec), 1, C.byref(rid)) == B.GFD_EINVAL
+    assert B.lib.gfd_server_wait(None, 1, 0, None, None) == B.GFD_EINVAL
+    B.lib.gfd_server_destroy(None)  # ignored
