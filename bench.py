@@ -38,10 +38,11 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": None,
+    "sources_sha256": "43c75c685516df640b8a3a776e729c036092720b063d667f2df550b10f0145a9",
     "workload": "kg_4m_batch256",
-    "kernel_class": "extend_last",
-    "bytes_per_launch": None,
+    "kernel_class": "extend_last",  # k_ext_run<true>
+    # (1,488.58 MB read + 551.44 MB written) per dispatch, calibrated
+    "bytes_per_launch": 2.04002e9,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
