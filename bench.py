@@ -171,6 +171,9 @@ def main():
                     help="skip the one-at-a-time comparison")
     ap.add_argument("--no-timing", action="store_true",
                     help="no HIP events at all (no roofline line)")
+    ap.add_argument("--count-only", action="store_true",
+                    help="counts and satisfied flags only (K = 0, no fingerprints): postponed "
+                         "leaves are counted, not enumerated (with --semantics mono)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write elementwise kernel "
                          "(int32 negation) three times: the calibration run for HBM counters")
@@ -225,12 +228,15 @@ def main():
 
     # specs, options and result buffers are marshalled once; a step is one
     # gfd_validate_ex call through the C ABI
-    pc = P.PreparedCall(gh, gfds, K=K_REPORT, semantics=args.semantics, stream=stream,
+    K = 0 if args.count_only else K_REPORT
+    base_flags = P.GFD_FLAG_COUNT_ONLY if args.count_only else 0
+    pc = P.PreparedCall(gh, gfds, K=K, semantics=args.semantics, stream=stream,
                         batched=batched)
 
     # warm-up; the last warm-up step records every kernel class to find the dominant one
     for w in range(max(1, args.warmup)):
-        st = pc.run(flags=0 if args.no_timing or w < args.warmup - 1 else P.GFD_FLAG_TIMING)
+        st = pc.run(flags=base_flags | (0 if args.no_timing or w < args.warmup - 1
+                                        else P.GFD_FLAG_TIMING))
     torch.cuda.synchronize()
     res = pc.results()
     dom = None
@@ -241,8 +247,9 @@ def main():
             f"{st['class_bytes'][k] / max(v, 1e-9) / 1e6:.0f} GB/s"
             for k, v in st["class_ms"].items()))
         log(f"warm-up: wall {st['wall_ms']:.1f} ms, kernel time {sum(st['class_ms'].values()):.1f} ms, "
-            f"chunked {st['chunked_gfds']}, threshold {st['threshold_gfds']}/{st['threshold_passes']}")
-    flags = 0 if dom is None else (1 << (8 + dom))  # HIP events around the dominant class only
+            f"chunked {st['chunked_gfds']}, threshold {st['threshold_gfds']}/{st['threshold_passes']}, "
+            f"counted leaves {st['leaf_gfds']}")
+    flags = base_flags | (0 if dom is None else (1 << (8 + dom)))  # events: dominant class only
     agg_ms = agg_bytes = agg_launch = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -299,14 +306,14 @@ def main():
     if batched and not args.no_compare:
         # the same GFDs, one gfd_validate call each (one-at-a-time), marshalled
         # up front like the batched call
-        one = [P.PreparedCall(gh, [d], K=K_REPORT, semantics=args.semantics, stream=stream)
+        one = [P.PreparedCall(gh, [d], K=K, semantics=args.semantics, stream=stream)
                for d in gfds]
         for q in one[:8]:
-            q.run(stats=False)
+            q.run(flags=base_flags, stats=False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for q in one:
-            q.run(stats=False)
+            q.run(flags=base_flags, stats=False)
         torch.cuda.synchronize()
         dt1 = time.perf_counter() - t1
         seq = [q.results()[0] for q in one]
@@ -322,7 +329,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
            "data": "synthetic", "gfds_per_s": gfds_per_s, "matches_per_step": matches,
            "config": {"workload": args.workload, "mode": mode, "n": g.n, "m": g.m,
-                      "gfds": len(gfds), "semantics": args.semantics, "K": K_REPORT,
+                      "gfds": len(gfds), "semantics": args.semantics, "K": K,
+                      "count_only": bool(args.count_only),
                       "parallelism": "single_gpu"},
            "load_s": load_s, "roofline": roofline, "compare": compare}
     if not args.no_cpu_baseline:

@@ -122,6 +122,13 @@ typedef struct {
 
 #define GFD_FLAG_FORCE_CHUNKED 1 /* skip the single-pass fast path */
 #define GFD_FLAG_TIMING 2        /* record HIP event timings for every kernel class */
+/* Counts only: match and violation counts and satisfied flags, with k_max = 0
+ * (no tuples) and both fingerprints reported as 0.  Under GFD_SEM_MONO, a
+ * pattern whose matching order ends in up to 3 leaves with one parent, equal
+ * labels and edges, and literals on themselves alone has those leaves counted
+ * per partial match (inclusion-exclusion over their candidate lists) instead
+ * of enumerated: the leaf postponement of CFL-Match that Section IV-B adopts. */
+#define GFD_FLAG_COUNT_ONLY 4
 /* record HIP event timings for kernel class c (0..7, see gfd_stats) only */
 #define GFD_FLAG_TIMING_CLASS(c) (1 << (8 + (c)))
 
@@ -146,6 +153,7 @@ typedef struct {
                                  enumeration level ran again, collecting only the
                                  violations up to a bound on the K-th smallest */
   int32_t threshold_passes;   /* such re-runs (one launch each for all those GFDs) */
+  int32_t leaf_gfds;          /* GFDs whose last leaves were counted (GFD_FLAG_COUNT_ONLY) */
 } gfd_stats;
 
 /* Load a graph given as out-CSR on the host.  Inputs are read and copied: the

@@ -22,7 +22,7 @@ GFD_MAX_LITERALS = 8
 GFD_MAX_PATTERN_EDGES = GFD_MAX_K * (GFD_MAX_K - 1)
 GFD_LIT_CONST, GFD_LIT_VAR = 0, 1
 GFD_SEM_INDUCED, GFD_SEM_MONO = 0, 1
-GFD_FLAG_FORCE_CHUNKED, GFD_FLAG_TIMING = 1, 2
+GFD_FLAG_FORCE_CHUNKED, GFD_FLAG_TIMING, GFD_FLAG_COUNT_ONLY = 1, 2, 4
 STATUS_NAMES = {0: "GFD_OK", -1: "GFD_EINVAL", -2: "GFD_ENOMEM", -3: "GFD_EDEVICE",
                 -4: "GFD_EUNSUPPORTED", -5: "GFD_EOVERFLOW", -6: "GFD_EAGAIN"}
 KERNEL_CLASSES = ("filter", "pull", "cpi", "extend", "extend_last", "scan", "topk", "other")
@@ -75,7 +75,7 @@ class gfd_stats(C.Structure):
                 ("cpi_candidates", C.c_uint64), ("cpi_entries", C.c_uint64),
                 ("class_launches", C.c_int32 * 8), ("class_ms", C.c_double * 8),
                 ("class_bytes", C.c_uint64 * 8), ("threshold_gfds", C.c_int32),
-                ("threshold_passes", C.c_int32)]
+                ("threshold_passes", C.c_int32), ("leaf_gfds", C.c_int32)]
 
 
 class gfd_graph_info(C.Structure):

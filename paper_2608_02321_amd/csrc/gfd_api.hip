@@ -407,6 +407,10 @@ struct Plan {
   int32_t chk_pos[MAXK][MAXK], chk_fwd[MAXK][MAXK], chk_bwd[MAXK][MAXK];
   int nx = 0, ny = 0, y_false = 0;
   DevLit lit[2 * MAXLIT];
+  // leaf postponement (count-only calls): the last leaf_r vertices of the
+  // matching order are counted, not enumerated; k_enum vertices are enumerated
+  int leaf_r = 0, k_enum = 0, leaf_par = -1;
+  int32_t lit_leaf[2 * MAXLIT];
 };
 
 static int32_t pair_code(const Plan& p, int a, int b, bool induced) {
@@ -668,6 +672,7 @@ struct JobMem {
   uint64_t* ctl;
   uint64_t* tstate;
   int32_t* res;
+  uint32_t* leaf_cnt;  // leaf postponement: [|C(parent)| * LEAF_WORDS]
 };
 
 struct Job {
@@ -721,6 +726,7 @@ static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t
   for (int i = 2; i < k; i++) b += align_up(4ull * i * c.cap_f);      // frontier columns
   b += align_up(4 * c.begs);
   b += align_up(4 * c.vcap * k);
+  if (p.leaf_r) b += align_up(4ull * LEAF_WORDS * c.cap_u[p.leaf_par]);
   c.bytes = b;
 }
 
@@ -759,6 +765,7 @@ static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const J
   for (int i = 2; i < k; i++) m.cols[i] = (int32_t*)take(4ull * i * c.cap_f);
   m.begs = (uint32_t*)take(4 * c.begs);
   m.vbuf = (int32_t*)take(4 * c.vcap * k);
+  m.leaf_cnt = p.leaf_r ? (uint32_t*)take(4ull * LEAF_WORDS * c.cap_u[p.leaf_par]) : nullptr;
 }
 
 struct Ctx {
@@ -857,7 +864,7 @@ static void ensure_recs(Workspace* ws, size_t bytes) {
 
 // Phase plan of a batch: which kernels run, on which record arrays.
 struct Launch {
-  int kind;     // 0 filter, 1 cpi, 2 ext, 3 single, 4 topk
+  int kind;     // 0 filter, 1 cpi, 2 ext, 3 single, 4 topk, 5 leaf counts
   size_t off;   // record array offset
   int njobs;
   int gx_scan, gx_work, gx_item, gx_clear;
@@ -1013,12 +1020,12 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       const Plan& p = J.plan;
       ExtJob& e = E[x];
       e = ExtJob{};
-      if (i >= p.k) continue;
+      if (i >= p.k_enum) continue;  // postponed leaves are counted, not enumerated
       const int u = p.order[i], q = p.parent[u];
       e.active = 1;
       e.i = i;
       e.k = p.k;
-      e.last = i == p.k - 1;
+      e.last = p.leaf_r == 0 && i == p.k - 1;
       if (i == 1) {
         const CandSet r = cand_set(J, p.root);
         e.src_cols = r.list;
@@ -1117,6 +1124,60 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       L.push_back(Launch{3, off, nj, 0, gx_for(items, nj), 0, 0, false, true, false});
     }
   }
+  // postponed leaves: completions counted per partial match of the inner part
+  {
+    std::vector<LeafJob> F(nj);
+    bool any = false;
+    uint64_t np = 1, srcs = 1;
+    for (int x = 0; x < nj; x++) {
+      Job& J = jobs[x];
+      const Plan& p = J.plan;
+      LeafJob& f = F[x];
+      f = LeafJob{};
+      if (!p.leaf_r) continue;
+      const int u0 = p.order[p.k - 1], q = p.leaf_par;
+      f.active = 1;
+      f.i = p.k_enum;
+      f.r = p.leaf_r;
+      if (p.k_enum == 1) {
+        const CandSet r = cand_set(J, p.root);
+        f.src_cols = r.list;
+        f.src_stride = 0;
+        f.d_nsrc = r.cnt;
+        f.src_cap = J.caps.cap_u[p.root];
+      } else {
+        f.src_cols = J.mem.cols[p.k_enum];
+        f.src_stride = J.caps.cap_f;
+        f.d_nsrc = J.mem.ctl + CTL_LEVEL_N + p.k_enum;
+        f.src_cap = J.caps.cap_f;
+      }
+      f.par_pos = p.pos[q];
+      f.par_posmap = J.mem.pos[q];
+      const CandSet pc = cand_set(J, q);
+      f.d_np = pc.cnt;
+      f.cap_p = J.caps.cap_u[q];
+      f.cpi_beg = J.mem.cpi_beg[u0];
+      f.cpi_len = J.mem.cpi_len[u0];
+      f.cpi_ent = c.ws->cpi_arena;
+      f.u = cand_set(J, u0);
+      f.dir = p.adj_dir[u0];
+      f.prim = p.adj_prim[u0];
+      f.other = p.adj_other[u0];
+      f.cnt = J.mem.leaf_cnt;
+      f.nx = p.nx;
+      f.ny = p.ny;
+      f.y_false = p.y_false;
+      for (int t = 0; t < 2 * MAXLIT; t++) {
+        f.lit[t] = p.lit[t];
+        f.lit_leaf[t] = p.lit_leaf[t];
+      }
+      f.counters = (unsigned long long*)(J.mem.ctl + CTL_MATCH);
+      np = std::max(np, f.cap_p);
+      srcs = std::max(srcs, f.src_cap);
+      any = true;
+    }
+    if (any) L.push_back(Launch{5, R.add(F), nj, 0, gx_for(srcs, nj), gx_for(np, nj), 0, false, false, false});
+  }
   if (c.K > 0) {
     std::vector<TopkJob> T(nj);
     for (int x = 0; x < nj; x++) {
@@ -1164,6 +1225,12 @@ static void run_launches(Ctx& c, const std::vector<Launch>& L) {
       case 3: {
         auto* r = (const ExtJob*)(base + l.off);
         c.tm.run(K_LAST, [&] { ext_single(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_LAST)); });
+        break;
+      }
+      case 5: {
+        auto* r = (const LeafJob*)(base + l.off);
+        c.tm.run(K_OTHER, [&] { leaf_prep(c.st, g, r, l.njobs, l.gx_item); });
+        c.tm.run(K_LAST, [&] { leaf_count(c.st, g, r, l.njobs, l.gx_work); });
         break;
       }
       case 4: {
@@ -1570,6 +1637,46 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
   }
 }
 
+// Leaf postponement for a count-only call under the non-induced reading: the
+// longest tail of the matching order made of leaves (skeleton degree 1) with
+// one common parent, the same vertex label and the same edges to it, and
+// literals that touch no vertex but themselves.  Their completions of a
+// partial match are then counted per parent candidate instead of enumerated.
+// (Under the induced reading a leaf must also avoid edges to every other
+// matched vertex, which the per-list counts cannot see.)
+static void plan_leaves(const gfd_spec& s, bool induced, bool count_only, Plan& p) {
+  p.leaf_r = 0;
+  p.k_enum = p.k;
+  p.leaf_par = -1;
+  for (int t = 0; t < 2 * MAXLIT; t++) p.lit_leaf[t] = -1;
+  if (!count_only || induced || p.k < 2) return;
+  int deg[MAXK] = {};
+  for (int a = 0; a < p.k; a++)
+    for (int b = 0; b < p.k; b++)
+      if (a != b && (p.qe[a][b] != NOEDGE || p.qe[b][a] != NOEDGE)) deg[a]++;
+  int r = 0;
+  for (int i = p.k - 1; i >= 1 && r < MAX_LEAVES; i--) {
+    const int u = p.order[i], u0 = p.order[p.k - 1], q = p.parent[u];
+    if (deg[u] != 1 || p.core[u] || q != p.parent[u0] || p.pos[q] >= p.k - 1 - r) break;
+    if (p.qlab[u] != p.qlab[u0] || p.qe[q][u] != p.qe[q][u0] || p.qe[u][q] != p.qe[u0][q]) break;
+    r++;
+  }
+  if (r == 0) return;
+  // literals: each on one leaf alone, or on inner vertices alone
+  int32_t lit_leaf[2 * MAXLIT];
+  for (int t = 0; t < s.num_x + s.num_y; t++) {
+    const gfd_literal& l = t < s.num_x ? s.x[t] : s.y[t - s.num_x];
+    const bool a = p.pos[l.var] >= p.k - r;
+    const bool b = l.kind == GFD_LIT_VAR && p.pos[l.var2] >= p.k - r;
+    if (l.kind == GFD_LIT_VAR && (a != b || (a && l.var2 != l.var))) return;
+    lit_leaf[t] = a ? p.pos[l.var] - (p.k - r) : -1;
+  }
+  p.leaf_r = r;
+  p.k_enum = p.k - r;
+  p.leaf_par = p.parent[p.order[p.k - 1]];
+  for (int t = 0; t < s.num_x + s.num_y; t++) p.lit_leaf[t] = lit_leaf[t];
+}
+
 // Capacities of one call: violation staging per job (vsmall), the bounded
 // path's staging (vbig) and the frontier bytes of each deep job (fbytes).
 struct Sizing {
@@ -1662,6 +1769,8 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
   if (o.semantics != GFD_SEM_INDUCED && o.semantics != GFD_SEM_MONO) return set_error(GFD_EINVAL, "semantics");
   if (o.batched != 0 && o.batched != 1) return set_error(GFD_EINVAL, "batched must be 0 or 1");
   if (o.mem_budget_bytes < 0 || o.frontier_cap < 0 || o.violation_cap < 0) return set_error(GFD_EINVAL, "negative option");
+  const bool count_only = (o.flags & GFD_FLAG_COUNT_ONLY) != 0;
+  if (count_only && o.k_max != 0) return set_error(GFD_EINVAL, "a count-only call needs k_max = 0");
   for (int32_t i = 0; i < num_specs; i++) {
     const int32_t rc = check_spec(g, specs[i], i);
     if (rc) return rc;
@@ -1700,6 +1809,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     for (int32_t i = 0; i < num_specs; i++) {
       all[i].spec = i;
       make_plan(g, specs[i], c.induced, all[i].plan);
+      plan_leaves(specs[i], c.induced, count_only, all[i].plan);
       job_caps(g, all[i].plan, frontier_cap_of(g, all[i].plan, sz.fbytes, o.frontier_cap), vsmall,
                all[i].caps);
     }
@@ -1781,6 +1891,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
             }
             for (int u = 0; u < jobs[x].plan.k; u++)
               stats->cpi_candidates += h[CTL_CAND + 2 * u + jobs[x].cur[u]];
+            stats->leaf_gfds += jobs[x].plan.leaf_r > 0;
           }
       }
       for (size_t x = 0; x < jobs.size(); x++) {
@@ -1804,8 +1915,8 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       gfd_result& r = results[i];
       r.match_count = h[CTL_MATCH];
       r.violation_count = h[CTL_VIOL];
-      r.match_fp = h[CTL_MFP];
-      r.violation_fp = h[CTL_VFP];
+      r.match_fp = count_only ? 0 : h[CTL_MFP];  // not computed for postponed leaves
+      r.violation_fp = count_only ? 0 : h[CTL_VFP];
       r.satisfied = r.violation_count == 0;
       r.num_reported = (int32_t)std::min<uint64_t>((uint64_t)K, r.violation_count);
       if (K > 0 && r.num_reported)

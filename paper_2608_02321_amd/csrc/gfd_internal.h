@@ -189,6 +189,37 @@ struct ExtJob {
   const uint32_t* d_thr_valid;
 };
 
+// Leaf postponement (count-only calls): the last r (<= MAX_LEAVES) vertices
+// of the matching order are structurally identical leaves under one parent p,
+// each carrying only literals on itself.  Their injective completions of a
+// partial match are counted, not enumerated, from per-list counts of the
+// members meeting each subset of leaf predicates.
+constexpr int MAX_LEAVES = 3;
+constexpr int LEAF_SUBSETS = 1 << MAX_LEAVES;  // masks 1 .. 2^r - 1 are used
+constexpr int LEAF_FAMILIES = 3;               // no literal, X, X and Y
+constexpr int LEAF_WORDS = LEAF_FAMILIES * LEAF_SUBSETS;
+struct LeafJob {
+  int32_t active, i, r;       // i: matched vertices in a source; r: leaves
+  const int32_t* src_cols;    // column j (j < i) at src_cols + j * src_stride
+  uint64_t src_stride;
+  const uint64_t* d_nsrc;
+  uint64_t src_cap;
+  int32_t par_pos;            // the parent's position in a source
+  const int32_t* par_posmap;  // C(p) positions
+  const uint64_t* d_np;       // |C(p)|
+  uint64_t cap_p;
+  const uint32_t* cpi_beg;    // the leaves' CPI lists (one set: the leaves are identical)
+  const uint32_t* cpi_len;
+  const int32_t* cpi_ent;
+  CandSet u;                  // the leaves' candidate set
+  int32_t dir, prim, other;   // the tree edge p - leaf, as in CpiJob
+  uint32_t* cnt;              // [cap_p * LEAF_WORDS]
+  int32_t nx, ny, y_false;
+  DevLit lit[2 * MAXLIT];
+  int32_t lit_leaf[2 * MAXLIT];  // leaf slot of a literal, or -1 (inner vertices)
+  unsigned long long* counters;  // match, violation
+};
+
 struct TopkJob {
   int32_t active, k, K;
   const int32_t* vbuf;
@@ -239,6 +270,10 @@ void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, i
 void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
                 unsigned long long* bytes);
 void topk_small(hipStream_t st, const TopkJob* jobs, int njobs);
+// per member of C(p): how many of its leaf-list members meet each predicate subset
+void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx);
+// per partial match: its injective leaf completions, counted into the job's counters
+void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx);
 
 // Batched radix select (grid row = job); requires more than K staged tuples
 // per active job.  sel_pass decides `bits` bits of tuple word `word` starting

@@ -1135,6 +1135,148 @@ void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs
 }
 
 // ---------------------------------------------------------------------------
+// leaf postponement (count-only): completions by leaves counted, not enumerated
+// ---------------------------------------------------------------------------
+
+// A literal whose variables are all one leaf, evaluated at vertex x.
+__device__ __forceinline__ bool leaf_literal(const DevGraph& g, const DevLit& l, int32_t x) {
+  const int32_t a = g.attr[(int64_t)l.attr * g.n + x];
+  if (l.kind == 0) return a != ABSENT && a == l.value;
+  const int32_t b = g.attr[(int64_t)l.attr2 * g.n + x];
+  return a != ABSENT && b != ABSENT && a == b;
+}
+
+// Predicate masks of vertex x over the leaf slots: bit j of mx when leaf j's X
+// literals hold at x, of mxy when its X and Y literals do.
+__device__ __forceinline__ void leaf_masks(const DevGraph& g, const LeafJob& J, int32_t x,
+                                           uint32_t& mx, uint32_t& mxy) {
+  const uint32_t all = (1u << J.r) - 1;
+  uint32_t failx = 0, faily = 0;
+  for (int t = 0; t < J.nx + J.ny; t++) {
+    const int j = J.lit_leaf[t];
+    if (j < 0) continue;
+    if (!leaf_literal(g, J.lit[t], x)) {
+      if (t < J.nx) failx |= 1u << j;
+      else faily |= 1u << j;
+    }
+  }
+  mx = all & ~failx;
+  mxy = all & ~(failx | faily);
+}
+
+// One thread per member c of C(p): cnt[c][f][B] = members of c's leaf list
+// whose family-f masks contain B (f = 0: every member, 1: X, 2: X and Y).
+__global__ __launch_bounds__(BS) void k_leaf_prep(DevGraph g, const LeafJob* __restrict__ jobs) {
+  const LeafJob& J = jobs[blockIdx.y];
+  if (!J.active) return;
+  const uint64_t np = *J.d_np < J.cap_p ? *J.d_np : J.cap_p;
+  const uint32_t nsub = 1u << J.r;
+  for (uint64_t c = (uint64_t)blockIdx.x * BS + threadIdx.x; c < np; c += (uint64_t)gridDim.x * BS) {
+    uint32_t cx[LEAF_SUBSETS] = {}, cxy[LEAF_SUBSETS] = {};
+    const uint32_t b = J.cpi_beg[c], len = J.cpi_len[c];
+    for (uint32_t e = 0; e < len; e++) {
+      uint32_t mx, mxy;
+      leaf_masks(g, J, J.cpi_ent[(uint64_t)b + e], mx, mxy);
+#pragma unroll
+      for (uint32_t B = 1; B < LEAF_SUBSETS; B++) {
+        cx[B] += (B < nsub && (mx & B) == B) ? 1u : 0u;
+        cxy[B] += (B < nsub && (mxy & B) == B) ? 1u : 0u;
+      }
+    }
+    uint32_t* out = J.cnt + c * LEAF_WORDS;
+#pragma unroll
+    for (uint32_t B = 0; B < LEAF_SUBSETS; B++) {
+      out[B] = B ? len : 0u;
+      out[LEAF_SUBSETS + B] = cx[B];
+      out[2 * LEAF_SUBSETS + B] = cxy[B];
+    }
+  }
+}
+
+// Injective assignments of r leaves to sets A_0 .. A_{r-1}, from c[B] =
+// |intersection of A_j, j in B|: the sum over set partitions of the leaves of
+// the product over blocks of (-1)^(|B|-1) (|B|-1)! c[B] (Moebius inversion on
+// the partition lattice).
+__device__ __forceinline__ int64_t injective(int r, const int64_t (&c)[LEAF_SUBSETS]) {
+  if (r == 1) return c[1];
+  if (r == 2) return c[1] * c[2] - c[3];
+  return c[1] * c[2] * c[4] - c[3] * c[4] - c[5] * c[2] - c[6] * c[1] + 2 * c[7];
+}
+
+__global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __restrict__ jobs) {
+  __shared__ unsigned long long s_acc[2][BS / WAVE];
+  const LeafJob& J = jobs[blockIdx.y];
+  if (!J.active) return;
+  const uint64_t N = *J.d_nsrc < J.src_cap ? *J.d_nsrc : J.src_cap;
+  const uint32_t nsub = 1u << J.r;
+  unsigned long long matches = 0, viol = 0;
+  for (uint64_t s = (uint64_t)blockIdx.x * BS + threadIdx.x; s < N; s += (uint64_t)gridDim.x * BS) {
+    int32_t h[MAXK];
+#pragma unroll
+    for (int j = 0; j < MAXK; j++) h[j] = j < J.i ? J.src_cols[(uint64_t)j * J.src_stride + s] : 0;
+    const int32_t vp = pick(h, J.par_pos);
+    const uint32_t* cc = J.cnt + (uint64_t)J.par_posmap[vp] * LEAF_WORDS;
+    int64_t c[LEAF_FAMILIES][LEAF_SUBSETS];
+#pragma unroll
+    for (int f = 0; f < LEAF_FAMILIES; f++)
+#pragma unroll
+      for (int B = 0; B < LEAF_SUBSETS; B++) c[f][B] = cc[f * LEAF_SUBSETS + B];
+    // matched inner vertices that sit in vp's leaf list are not available
+    unsigned long long by = 0;
+    for (int j = 0; j < J.i; j++) {
+      const int32_t x = h[j];
+      if (x == vp || !member(J.u, x)) continue;
+      // the list holds x iff the tree edge and its reverse constraint hold
+      const bool in = J.dir ? (constraint_ok(edge_label_at(g, x, vp, false, by), J.prim) &&
+                               pair_ok(g, vp, x, true, J.other, by))
+                            : (constraint_ok(edge_label_at(g, vp, x, true, by), J.prim) &&
+                               pair_ok(g, x, vp, false, J.other, by));
+      if (!in) continue;
+      uint32_t mx, mxy;
+      leaf_masks(g, J, x, mx, mxy);
+#pragma unroll
+      for (uint32_t B = 1; B < LEAF_SUBSETS; B++) {
+        if (B >= nsub) continue;
+        c[0][B] -= 1;
+        if ((mx & B) == B) c[1][B] -= 1;
+        if ((mxy & B) == B) c[2][B] -= 1;
+      }
+    }
+    bool X = true, Y = !J.y_false;
+    for (int t = 0; t < J.nx + J.ny; t++) {
+      if (J.lit_leaf[t] >= 0) continue;
+      const bool v = literal_holds(g, J.lit[t], h);
+      if (t < J.nx) X = X && v;
+      else Y = Y && v;
+    }
+    matches += (unsigned long long)injective(J.r, c[0]);
+    if (X) {
+      const int64_t ix = injective(J.r, c[1]);
+      viol += (unsigned long long)(Y ? ix - injective(J.r, c[2]) : ix);
+    }
+  }
+  matches = wave_sum(matches);
+  viol = wave_sum(viol);
+  if (lane() == 0) {
+    s_acc[0][threadIdx.x / WAVE] = matches;
+    s_acc[1][threadIdx.x / WAVE] = viol;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    unsigned long long t = 0;
+    for (int w = 0; w < BS / WAVE; w++) t += s_acc[threadIdx.x][w];
+    if (t) atomicAdd(&J.counters[threadIdx.x], t);
+  }
+}
+
+void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx) {
+  hipLaunchKernelGGL(k_leaf_prep, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+}
+void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx) {
+  hipLaunchKernelGGL(k_leaf_count, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+}
+
+// ---------------------------------------------------------------------------
 // lexicographic first-K of the staged violations
 // ---------------------------------------------------------------------------
 

@@ -1,0 +1,126 @@
+"""Leaf postponement in count-only calls (GFD_FLAG_COUNT_ONLY): the last leaves
+of the matching order are counted, not enumerated.  Counts and satisfied flags
+must equal the oracle's exactly; fingerprints are 0 and no tuples are listed.
+Statistics show which GFDs took the counting path."""
+import json
+import os
+
+import pytest
+
+from oracle import oracle as O
+from synth import configs
+from synth.small import random_graph
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_02321_amd as P
+    return P
+
+
+def c(var, attr, value):
+    return {"kind": "const", "var": var, "attr": attr, "value": value}
+
+
+def v(var, attr, var2, attr2):
+    return {"kind": "var", "var": var, "attr": attr, "var2": var2, "attr2": attr2}
+
+
+def und(pairs, label=0):
+    return [e for a, b in pairs for e in ([a, b, label], [b, a, label])]
+
+
+# (gfd, whether its last leaves qualify for counting under the non-induced reading)
+CASES = [
+    # star, 3 identical leaves, literals on the centre and on single leaves
+    ({"k": 4, "vlabels": [0, 1, 1, 1], "edges": [[0, 1, 0], [0, 2, 0], [0, 3, 0]],
+      "x": [c(0, 0, 1), c(1, 0, 2)], "y": [c(2, 1, 0), v(3, 0, 3, 1)], "y_false": False}, True),
+    # star with 2 leaves, X -> false
+    ({"k": 3, "vlabels": [1, 0, 0], "edges": [[1, 0, 1], [2, 0, 1]],
+      "x": [c(1, 1, 1)], "y": [], "y_false": True}, True),
+    # path: one end is the last leaf; the variable literal pairs the inner vertices
+    ({"k": 4, "vlabels": [0, 1, 0, 1], "edges": [[0, 1, 0], [1, 2, 1], [2, 3, 0]],
+      "x": [v(1, 0, 2, 0)], "y": [c(3, 1, 2)], "y_false": False}, True),
+    # undirected star (antiparallel pattern edges), wildcard leaves
+    ({"k": 4, "vlabels": [1, -1, -1, -1], "edges": und([(0, 1), (0, 2), (0, 3)]),
+      "x": [], "y": [c(0, 0, 0), c(1, 1, 3)], "y_false": False}, True),
+    # triangle with a pendant leaf
+    ({"k": 4, "vlabels": [0, 0, 1, 1], "edges": [[0, 1, 0], [1, 2, 0], [2, 0, 1], [2, 3, 2]],
+      "x": [c(3, 0, 1)], "y": [c(0, 1, 1)], "y_false": False}, True),
+    # a literal tying a leaf to the centre: enumerated
+    ({"k": 3, "vlabels": [0, 1, 1], "edges": [[0, 1, 0], [0, 2, 0]],
+      "x": [], "y": [v(1, 0, 0, 0)], "y_false": False}, False),
+    # leaves of different labels: only the identical tail is postponed
+    ({"k": 4, "vlabels": [0, 1, 2, 2], "edges": [[0, 1, 0], [0, 2, 0], [0, 3, 0]],
+      "x": [], "y": [c(1, 0, 1)], "y_false": False}, True),
+]
+
+
+def _oracle_counts(og, d, sem):
+    r = O.validate(og, d, sem, K=0, threads=4)
+    return {"match_count": r["match_count"], "violation_count": r["violation_count"],
+            "satisfied": r["satisfied"], "match_fp": 0, "violation_fp": 0, "violations": []}
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_counted_leaves_match_oracle(P, batched):
+    g = random_graph(31, 500, 9000, n_vlabels=3, n_elabels=3, n_attrs=2, attr_values=4,
+                     absent_frac=0.1, reciprocal_frac=0.3)
+    og = O.OracleGraph(g)
+    gh = P.load(g)
+    gfds = [d for d, _ in CASES]
+    for sem in ("mono", "induced"):
+        got, st = P.validate(gh, gfds, K=0, semantics=sem, flags=P.GFD_FLAG_COUNT_ONLY,
+                             stats=True, batched=batched)
+        for i, (d, r) in enumerate(zip(gfds, got)):
+            assert r == _oracle_counts(og, d, sem), (sem, i)
+        want = sum(q for _, q in CASES) if sem == "mono" else 0
+        assert st["leaf_gfds"] == want, (sem, st["leaf_gfds"])
+    # the same GFDs enumerated (no flag) give the same counts
+    full = P.validate(gh, gfds, K=0, semantics="mono", batched=batched)
+    cnt = P.validate(gh, gfds, K=0, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
+                     batched=batched)
+    for a, b in zip(full, cnt):
+        assert (a["match_count"], a["violation_count"]) == (b["match_count"], b["violation_count"])
+    with pytest.raises(P.GfdError) as ei:
+        P.validate(gh, gfds[:1], K=4, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY)
+    assert ei.value.code == -1
+    gh.free()
+
+
+def test_counted_leaves_under_frontier_overflow(P):
+    """A job whose inner frontier overflows is redone on the bounded path,
+    which enumerates everything: counts stay exact."""
+    g = random_graph(32, 400, 8000, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3)
+    og = O.OracleGraph(g)
+    gh = P.load(g)
+    gfds = [d for d, q in CASES if q]
+    got = P.validate(gh, gfds, K=0, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
+                     frontier_cap=50, batched=True)
+    for d, r in zip(gfds, got):
+        assert r == _oracle_counts(og, d, "mono")
+    gh.free()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_twitch_star_counted(P):
+    """The paper's star query on the Twitch-shaped graph: 394M matches counted
+    from the leaves' candidate lists, equal to the stored oracle counts."""
+    exp = json.load(open(os.path.join(GOLDEN, "expected_twitch_trio.json")))
+    g = configs.graph(configs.CONFIG_GRAPH["twitch_trio"])
+    assert g.sha256() == exp["graph_sha256"]
+    gh = P.load(g)
+    got, st = P.validate(gh, exp["gfds"], K=0, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
+                         stats=True)
+    for r, e in zip(got, exp["results"]["mono"]):
+        assert (r["match_count"], r["violation_count"], r["satisfied"]) == \
+            (e["match_count"], e["violation_count"], e["satisfied"])
+    assert st["leaf_gfds"] >= 2  # both star forms
+    gh.free()
