@@ -103,6 +103,8 @@ struct Workspace {
   size_t hjobrec_bytes = 0;
   uint64_t* hctl = nullptr;         // pinned mirror of control blocks
   size_t hctl_words = 0;
+  int32_t* hres = nullptr;          // pinned mirror of a batch's first-K slots
+  size_t hres_words = 0;
   unsigned long long* misc = nullptr;  // [0] CPI cursor, [8..15] bytes per class
   uint32_t* err = nullptr;
   uint32_t epoch = 0;
@@ -125,6 +127,7 @@ struct Workspace {
     if (hjobrec) (void)hipHostFree(hjobrec);
     if (hselrec) (void)hipHostFree(hselrec);
     if (hctl) (void)hipHostFree(hctl);
+    if (hres) (void)hipHostFree(hres);
   }
 };
 
@@ -1249,6 +1252,15 @@ static void upload_recs(Ctx& c, const Recs& R) {
 }
 
 // Arena of a batch: [control blocks][tile states][results][job regions].
+static void ensure_hres(Workspace* ws, size_t words) {
+  if (ws->hres_words >= words) return;
+  if (ws->hres) (void)hipHostFree(ws->hres);
+  ws->hres = nullptr;
+  ws->hres_words = 0;
+  HIPCHK(hipHostMalloc((void**)&ws->hres, sizeof(int32_t) * words, hipHostMallocDefault));
+  ws->hres_words = words;
+}
+
 // The batch arena only grows (allocations of this size are slow).
 static void ensure_arena(Workspace* ws, size_t bytes) {
   if (ws->arena_bytes >= bytes) return;
@@ -1875,12 +1887,18 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
             S.back().out = jobs[x].mem.res;
           }
           run_select(c, S, false);
-          for (size_t x = 0; x < jobs.size(); x++)
-            if (!redo[x])
-              HIPCHK(hipMemcpyAsync(hres.data() + (size_t)jobs[x].spec * K * MAXK, jobs[x].mem.res,
-                                    sizeof(int32_t) * K * jobs[x].plan.k, hipMemcpyDeviceToHost, c.st));
+          // the batch's result slots are contiguous: one copy into pinned memory
+          const size_t words = (size_t)K * MAXK * jobs.size();
+          ensure_hres(ws, words);
+          HIPCHK(hipMemcpyAsync(ws->hres, jobs[0].mem.res, sizeof(int32_t) * words,
+                                hipMemcpyDeviceToHost, c.st));
         }
         HIPCHK(hipStreamSynchronize(c.st));
+        if (K > 0)
+          for (size_t x = 0; x < jobs.size(); x++)
+            if (!redo[x])
+              std::memcpy(hres.data() + (size_t)jobs[x].spec * K * MAXK, ws->hres + (size_t)x * K * MAXK,
+                          sizeof(int32_t) * K * jobs[x].plan.k);
         if (stats)
           for (size_t x = 0; x < jobs.size(); x++) {
             if (redo[x]) continue;
