@@ -813,6 +813,26 @@ static void add_pulls(const Job& J, int u, const std::vector<int>& nbrs, FilterJ
   }
 }
 
+// A filter over the whole bucket of u (all of V for a wildcard): consecutive
+// rows of the label-ordered view, each labelled constraint read from its
+// edge-label block.
+static void make_direct(const gfd_graph* g, const Plan& p, int u, uint64_t bs, FilterJob& f) {
+  f.base = (p.qlab[u] == ANY || bs == 0) ? 0u : g->lab_off[p.qlab[u]];
+  f.list = p.qlab[u] == ANY ? nullptr : g->dg.lab_vtx + f.base;
+  f.direct = 1;
+  f.d_n = nullptr;
+  f.n_host = f.cap = bs;
+  for (int q = 0; q < f.ncons; q++) {
+    PullC& pc = f.cons[q];
+    pc.blk = 0;
+    if (p.qlab[u] == ANY || pc.elab == ANY || p.qlab[u] >= g->nvl || pc.elab >= g->nel) continue;
+    const size_t b = (size_t)p.qlab[u] * g->nel + pc.elab;
+    pc.blk = 1;
+    pc.rb = g->elb_blk[pc.dir][b];
+    pc.re = g->elb_blk[pc.dir][b + 1];
+  }
+}
+
 static int gx_for(uint64_t items, int njobs, int cap = 256) {
   const uint64_t want = (items + BS - 1) / BS;
   const int per_job = std::max(8, std::min(cap, 4096 / std::max(1, njobs)));
@@ -903,23 +923,8 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.min_out = p.min_out[u];
       f.min_in = p.min_in[u];
       const uint64_t bs = J.caps.cap_u[u];
-      // top-down items: the whole bucket, i.e. consecutive rows of the
-      // label-ordered view (all of V for a wildcard)
-      f.base = (p.qlab[u] == ANY || bs == 0) ? 0u : g->lab_off[p.qlab[u]];
-      f.list = p.qlab[u] == ANY ? nullptr : g->dg.lab_vtx + f.base;
-      f.direct = 1;
-      // a labelled vertex and edge read only that edge label's block
-      for (int q = 0; q < f.ncons; q++) {
-        PullC& pc = f.cons[q];
-        pc.blk = 0;
-        if (p.qlab[u] == ANY || pc.elab == ANY || p.qlab[u] >= g->nvl || pc.elab >= g->nel) continue;
-        const size_t b = (size_t)p.qlab[u] * g->nel + pc.elab;
-        pc.blk = 1;
-        pc.rb = g->elb_blk[pc.dir][b];
-        pc.re = g->elb_blk[pc.dir][b + 1];
-      }
-      f.d_n = nullptr;
-      f.n_host = f.cap = bs;
+      // top-down items: the whole bucket
+      make_direct(g, p, u, bs, f);
       f.hits = J.mem.hits;
       f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       J.cur[u] = 0;
@@ -954,9 +959,16 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.active = 1;
       add_pulls(J, u, p.up[u], f);
       const CandSet cur = cand_set(J, u);
-      f.list = cur.list;
-      f.d_n = cur.cnt;
-      f.cap = J.caps.cap_u[u];
+      if (p.down[u].empty()) {
+        // C(u) is its bucket less the degree filter (no top-down constraint):
+        // stream the bucket directly and keep the current members
+        make_direct(g, p, u, J.caps.cap_u[u], f);
+        f.keep = cur.bits;
+      } else {
+        f.list = cur.list;
+        f.d_n = cur.cnt;
+        f.cap = J.caps.cap_u[u];
+      }
       f.hits = J.mem.hits;
       f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       J.cur[u] ^= 1;
@@ -1699,11 +1711,11 @@ static Sizing call_sizing(int64_t budget, int64_t njobs, int64_t deep, int K, in
   Sizing z;
   njobs = std::max<int64_t>(1, njobs);
   // violation staging per job: a sixteenth of the budget over the batch, at
-  // most 2^24 tuples shared by the batch's jobs (2^18 each from 64 jobs on:
-  // every radix-select pass reads what is staged)
-  const int64_t vmax = std::max<int64_t>(int64_t(1) << 18, (int64_t(1) << 24) / njobs);
+  // most 2^18 tuples.  Every radix-select pass reads what is staged, while a
+  // threshold re-run skips the sources its bound rules out, so a small
+  // sample and another re-run beat a large sample.
   const uint64_t vdef = (uint64_t)std::max<int64_t>(
-      16384, std::min<int64_t>(budget / (16 * njobs) / (4 * MAXK), vmax));
+      16384, std::min<int64_t>(budget / (16 * njobs) / (4 * MAXK), int64_t(1) << 18));
   z.vsmall = std::max<uint64_t>(violation_cap ? (uint64_t)violation_cap : vdef, (uint64_t)K + 1);
   z.vbig = std::max<uint64_t>(violation_cap ? (uint64_t)violation_cap : (4u << 20), (uint64_t)K + 64);
   // half of the budget holds frontiers, shared evenly by the jobs of a batch

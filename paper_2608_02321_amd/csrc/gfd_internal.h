@@ -115,6 +115,7 @@ struct FilterJob {
   // is nullptr; their adjacency is then one contiguous slice and needs no scan
   int32_t direct;
   uint32_t base;
+  const uint32_t* keep;  // if set, only members of this bitmap may be kept
   PullC cons[MAXCONS];
   uint32_t* hits;        // [cap], bit c set when constraint c is met
   JobScan sc;            // over (constraint, item) pairs

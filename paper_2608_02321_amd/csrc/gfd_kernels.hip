@@ -610,8 +610,8 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
       const int32_t v = filter_item(J, i);
       vv[r] = v;
       by += J.list ? 4 : 0;
-      bool ok = true;
-      if (J.ncons) {  // the hit mask first: most items fail it
+      bool ok = !J.keep || ((J.keep[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u);
+      if (ok && J.ncons) {  // the hit mask first: most items fail it
         by += 4;
         ok = J.hits[i] == full;
       }
