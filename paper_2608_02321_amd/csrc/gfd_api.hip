@@ -1015,6 +1015,14 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       a.arena_cap = c.ws->cpi_cap;
       a.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
       a.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
+      a.blk = 0;
+      if (p.qlab[q] != ANY && a.prim != ANY && p.qlab[q] < g->nvl && a.prim < g->nel) {
+        const size_t b = (size_t)p.qlab[q] * g->nel + a.prim;
+        a.blk = 1;
+        a.rb = g->elb_blk[a.dir][b];
+        a.re = g->elb_blk[a.dir][b + 1];
+        a.base = g->lab_off[p.qlab[q]];
+      }
       items = std::max(items, a.cap_p);
       rows += chunks_of(rows_ub(g, p.qlab[q], a.dir));
       any = true;

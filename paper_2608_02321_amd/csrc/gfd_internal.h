@@ -143,6 +143,10 @@ struct CpiJob {
   uint64_t arena_cap;
   uint32_t* flags;       // bit 2: arena overflow
   JobScan sc;            // over rows of C(p)
+  // labelled p and prim: the edge-label block (p's bucket, prim) of direction
+  // dir is rows [rb, re); bucket base position `base`
+  int32_t blk;
+  uint32_t rb, re, base;
 };
 
 struct DevLit {

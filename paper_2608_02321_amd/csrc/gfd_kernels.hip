@@ -708,31 +708,82 @@ __global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __res
   }, J.sc);
 }
 
-// Chunk space of the CPI kernels: every adjacency entry of every member of C(p).
-__device__ __forceinline__ uint64_t cpi_width(const CpiJob& J) {
-  return J.active ? *J.sc.d_total : 0ull;
+// Entry v (far end, label already prim) of the row of v_p in an edge-label
+// block: kept when v is in C(u) and the reverse direction meets `other`.
+__device__ __forceinline__ bool cpi_keep_v(const DevGraph& g, const CpiJob& J, int32_t vp,
+                                           int32_t v, unsigned long long& by) {
+  if (!member(J.u, v)) return false;
+  if (J.other == PC_FREE) return true;
+  return J.dir ? pair_ok(g, vp, v, true, J.other, by) : pair_ok(g, v, vp, false, J.other, by);
 }
 
-__global__ __launch_bounds__(BS) void k_cpi_count(DevGraph g, const CpiJob* __restrict__ jobs,
-                                                  int njobs, unsigned long long* bytes) {
-  __shared__ LbsShared sh;
-  __shared__ ChunkMap cm;
-  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(cpi_width(jobs[j])); });
-  unsigned long long by = 0;
-  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
-    const int jb = chunk_job(cm, njobs, ch);
-    const CpiJob& J = jobs[jb];
+// Whether the job streams the edge-label block of p's bucket (entries labelled
+// prim only, members of C(p) picked out by its bitmap) instead of the whole
+// rows of C(p)'s members: when the block is at most twice those rows.
+__device__ __forceinline__ bool cpi_direct(const DevGraph& g, const CpiJob& J) {
+  if (!J.blk) return false;
+  const uint32_t* P = g.elb_start[J.dir];
+  return (uint64_t)(P[J.re] - P[J.rb]) <= 2ull * *J.sc.d_total;
+}
+
+// Chunk space of the CPI kernels: the block's entries, or every adjacency
+// entry of every member of C(p).
+__device__ __forceinline__ uint64_t cpi_chunks(const DevGraph& g, const CpiJob& J) {
+  if (!J.active) return 0ull;
+  if (cpi_direct(g, J)) {
+    const uint32_t* P = g.elb_start[J.dir];
+    return chunks_of(P[J.re] - P[J.rb]);
+  }
+  return chunks_of(*J.sc.d_total);
+}
+
+// Runs f(valid, s, v) over chunk r of job J: s the member's index in C(p), v
+// a kept entry of its list (valid false for positions outside the job or
+// entries that are not kept; uniform call count).
+template <class F>
+__device__ __forceinline__ void cpi_chunk(const DevGraph& g, const CpiJob& J, uint64_t r,
+                                          LbsShared& sh, unsigned long long& by, F f) {
+  if (cpi_direct(g, J)) {
+    const uint32_t* P = g.elb_start[J.dir] + J.rb;
+    const uint64_t N = J.re - J.rb, T = P[N] - P[0];
+    const uint64_t c0 = P[0] + r * LBS_CHUNK;
+    const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
+    const uint32_t* rows = g.elb_row[J.dir] + J.rb;
+    const int32_t* nbr = g.elb_nbr[J.dir];
+    flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t x) {
+      if (!valid) return;
+      const int32_t vp = g.lab_vtx[J.base + rows[s]];
+      by += (o == 0 ? 12 : 0);  // per row: position, start, vertex
+      if (!member(J.p, vp)) return;
+      const int32_t v = nbr[x];
+      by += 4;
+      if (cpi_keep_v(g, J, vp, v, by)) f((uint64_t)J.p.pos[vp], v);
+    });
+  } else {
     const uint32_t* off = J.dir ? g.in_off : g.out_off;
     const uint64_t T = *J.sc.d_total;
-    const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
+    const uint64_t c0 = r * LBS_CHUNK;
     const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
     flat_chunk<true>(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
       if (!valid) return;
       const int32_t vp = J.p.list[s];
       int32_t v;
       by += 8;
-      if (cpi_keep(g, J, vp, off[vp] + (uint32_t)o, v, by)) atomicAdd(&J.len[s], 1u);
+      if (cpi_keep(g, J, vp, off[vp] + (uint32_t)o, v, by)) f(s, v);
     });
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_cpi_count(DevGraph g, const CpiJob* __restrict__ jobs,
+                                                  int njobs, unsigned long long* bytes) {
+  __shared__ LbsShared sh;
+  __shared__ ChunkMap cm;
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return cpi_chunks(g, jobs[j]); });
+  unsigned long long by = 0;
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+    const int jb = chunk_job(cm, njobs, ch);
+    const CpiJob& J = jobs[jb];
+    cpi_chunk(g, J, ch - cm.cs[jb], sh, by, [&](uint64_t s, int32_t) { atomicAdd(&J.len[s], 1u); });
   }
   if (bytes) block_add(bytes, by);
 }
@@ -768,25 +819,16 @@ __global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __res
                                                  int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
   __shared__ ChunkMap cm;
-  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(cpi_width(jobs[j])); });
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return cpi_chunks(g, jobs[j]); });
   unsigned long long by = 0, dummy = 0;
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
     const int jb = chunk_job(cm, njobs, ch);
     const CpiJob& J = jobs[jb];
-    const uint32_t* off = J.dir ? g.in_off : g.out_off;
-    const uint64_t T = *J.sc.d_total;
-    const uint64_t c0 = (ch - cm.cs[jb]) * LBS_CHUNK;
-    const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
-    flat_chunk<true>(J.sc.P, cpi_sources(J), c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
-      if (!valid) return;
-      const int32_t vp = J.p.list[s];
-      int32_t v;
-      if (cpi_keep(g, J, vp, off[vp] + (uint32_t)o, v, dummy)) {
-        const uint32_t at = atomicAdd(&J.cur[s], 1u);
-        if (at < J.len[s]) {
-          J.arena[(uint64_t)J.beg[s] + at] = v;
-          by += 4;
-        }
+    cpi_chunk(g, J, ch - cm.cs[jb], sh, dummy, [&](uint64_t s, int32_t v) {
+      const uint32_t at = atomicAdd(&J.cur[s], 1u);
+      if (at < J.len[s]) {
+        J.arena[(uint64_t)J.beg[s] + at] = v;
+        by += 4;
       }
     });
   }
