@@ -38,11 +38,11 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "43c75c685516df640b8a3a776e729c036092720b063d667f2df550b10f0145a9",
+    "sources_sha256": "9eaff960c6300a4519420243dcd16919563c965c05afd9531e518e70b107f901",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true>
-    # (1,488.58 MB read + 551.44 MB written) per dispatch, calibrated
-    "bytes_per_launch": 2.04002e9,
+    # (1,483.46 MB read + 551.04 MB written) per dispatch, calibrated
+    "bytes_per_launch": 2.0345e9,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
