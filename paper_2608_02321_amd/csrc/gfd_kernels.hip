@@ -356,6 +356,60 @@ __device__ __forceinline__ void flat_chunk(const T* __restrict__ P, uint64_t N, 
   __syncthreads();
 }
 
+// flat_chunk<false> split in two phases: every round's position is placed and
+// its value loaded by pre(s, o) first -- LBS_ROUNDS independent loads in
+// flight per thread -- and only then f(valid, s, o, value) runs per round.
+template <class T, class Pre, class F>
+__device__ __forceinline__ void flat_chunk_pre(const T* __restrict__ P, uint64_t N, uint64_t c0,
+                                               uint64_t c1, LbsShared& sh, Pre pre, F f) {
+  if (threadIdx.x < WAVE) {
+    const uint64_t lo = wave_last_le(P, 0, N - 1, c0);
+    if (threadIdx.x == 0) sh.lo = lo;
+  } else if (threadIdx.x < 2 * WAVE) {
+    const uint64_t hi = wave_last_le(P, 0, N - 1, c1 - 1);
+    if (threadIdx.x == WAVE) sh.hi = hi;
+  }
+  __syncthreads();
+  const uint64_t lo = sh.lo, hi = sh.hi;
+  const uint64_t span = hi - lo + 2;  // P[lo .. hi+1]
+  const bool in_lds = span <= (uint64_t)LBS_SLOTS;
+  if (in_lds)
+    for (uint64_t j = threadIdx.x; j < span; j += BS) sh.p[j] = P[lo + j];
+  __syncthreads();
+  uint32_t ss[LBS_ROUNDS], oo[LBS_ROUNDS];
+  int32_t pv[LBS_ROUNDS];
+  uint32_t valid = 0;
+  uint32_t l = 0;  // in_lds: source lo + l
+#pragma unroll
+  for (int r = 0; r < LBS_ROUNDS; r++) {
+    const uint64_t a = c0 + (uint64_t)r * BS + threadIdx.x;
+    ss[r] = 0;
+    oo[r] = 0;
+    if (a < c1) {
+      valid |= 1u << r;
+      uint64_t sx;
+      if (in_lds) {
+        uint32_t h = (uint32_t)(span - 2);
+        while (l < h) {  // positions only grow: search from the last source
+          const uint32_t mid = (l + h + 1) >> 1;
+          if (sh.p[mid] <= a) l = mid; else h = mid - 1;
+        }
+        sx = lo + l;
+        oo[r] = (uint32_t)(a - sh.p[l]);
+      } else {
+        sx = last_le(P, lo, hi, a);
+        oo[r] = (uint32_t)(a - P[sx]);
+      }
+      ss[r] = (uint32_t)sx;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < LBS_ROUNDS; r++) pv[r] = ((valid >> r) & 1u) ? pre(ss[r], oo[r]) : 0;
+#pragma unroll
+  for (int r = 0; r < LBS_ROUNDS; r++) f(((valid >> r) & 1u) != 0, (uint64_t)ss[r], (uint64_t)oo[r], pv[r]);
+  __syncthreads();
+}
+
 // The flat work of every job of a launch shares one chunk space: job j owns
 // ceil(width_j / LBS_CHUNK) consecutive chunks and the 1-D grid strides over
 // all of them, so the blocks keep working on whichever jobs still have chunks
@@ -1049,11 +1103,14 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
 #pragma unroll
       for (int v = 0; v < MAXK; v++) thr[v] = thr_on && v < J.k ? J.thr[v] : 0;
     }
-    flat_chunk<false>(J.sc.P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t) {
+    auto cpi_entry = [&](uint32_t s, uint32_t o) -> int32_t {
+      return J.cpi_ent[(uint64_t)J.begs[s] + o];
+    };
+    flat_chunk_pre(J.sc.P, N, c0, c1, sh, cpi_entry, [&](bool valid, uint64_t s, uint64_t o,
+                                                          int32_t v) {
       int32_t h[MAXK];
       bool ok = false;
       if (valid) {
-        const int32_t v = J.cpi_ent[(uint64_t)J.begs[s] + o];
         // the CPI entry; the source's list start, prefix and partial once per source
         by += 4 + (o == 0 ? 12ull + 4ull * (uint64_t)i : 0ull);
         ok = true;

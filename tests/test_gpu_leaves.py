@@ -124,3 +124,24 @@ def test_twitch_star_counted(P):
             (e["match_count"], e["violation_count"], e["satisfied"])
     assert st["leaf_gfds"] >= 2  # both star forms
     gh.free()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_counted_leaves_full_size_batch(P):
+    """The 256-GFD workload under the non-induced reading in one batched
+    count-only call: over half the GFDs have their last leaves counted; all
+    counts equal the stored oracle results."""
+    import gzip
+    with gzip.open(os.path.join(GOLDEN, "expected_kg_4m_batch256.json.gz"), "rt") as f:
+        exp = json.load(f)
+    g = configs.graph("kg_4m")
+    assert g.sha256() == exp["graph_sha256"]
+    gh = P.load(g)
+    got, st = P.validate(gh, exp["gfds"], K=0, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
+                         stats=True, batched=True)
+    for i, (r, e) in enumerate(zip(got, exp["results"]["mono"])):
+        assert (r["match_count"], r["violation_count"], r["satisfied"]) == \
+            (e["match_count"], e["violation_count"], e["satisfied"]), i
+    assert st["leaf_gfds"] > 100
+    gh.free()
