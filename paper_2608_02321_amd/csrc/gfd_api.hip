@@ -842,8 +842,12 @@ static int gx_for(uint64_t items, int njobs, int cap = 256) {
 // `chunks` chunks of LBS_CHUNK positions: enough blocks to fill the chip.
 constexpr uint64_t FLAT_GRID_MAX = 2048;
 static uint64_t chunks_of(uint64_t positions) { return (positions + LBS_CHUNK - 1) / LBS_CHUNK; }
+// A grid of at least NXCD blocks is rounded up to a multiple of NXCD (the
+// kernels then give each die a contiguous slice of the chunks).
 static int flat_grid(uint64_t chunks) {
-  return (int)std::max<uint64_t>(1, std::min<uint64_t>(chunks, FLAT_GRID_MAX));
+  uint64_t g = std::max<uint64_t>(1, std::min<uint64_t>(chunks, FLAT_GRID_MAX));
+  if (g >= (uint64_t)NXCD) g = std::min<uint64_t>((g + NXCD - 1) / NXCD * NXCD, FLAT_GRID_MAX);
+  return (int)g;
 }
 static int gx_scan(uint64_t items) {
   const uint64_t t = (items + SCAN_TILE - 1) / SCAN_TILE;

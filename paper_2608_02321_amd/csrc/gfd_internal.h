@@ -33,6 +33,7 @@ constexpr int SCAN_TILE = BS * SCAN_IPT;
 constexpr int MAX_JOBS = 256;  // jobs per launch (one batch); at most BS
 constexpr int LBS_ROUNDS = 8;  // flat work: rounds of BS positions per located chunk
 constexpr uint64_t LBS_CHUNK = (uint64_t)BS * LBS_ROUNDS;
+constexpr int NXCD = 8;        // accelerator dies (XCDs), each with its own L2
 constexpr int SORT_MAX = 2048; // violation tuples sorted in one workgroup
 constexpr int RADIX_BITS = 11;
 constexpr int RADIX_BINS = 1 << RADIX_BITS;

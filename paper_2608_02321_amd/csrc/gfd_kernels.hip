@@ -443,6 +443,18 @@ __device__ __forceinline__ void chunk_map_build(ChunkMap& m, int njobs, W chunks
   __syncthreads();
 }
 
+// Chunk order with L2 locality.  The workgroups of a 1-D launch are handed
+// round-robin to the NXCD dies (workgroup b to die b % NXCD).  Every pass of
+// the grid over the chunk space covers gridDim.x consecutive chunks; when the
+// grid is a multiple of NXCD, die x takes the x-th contiguous part of each
+// pass, so the per-job data those chunks read at random (candidate bitmaps,
+// CPI lists) is held in one die's L2 rather than in all of them, while the
+// passes keep all dies on the same region of the chunk space.
+__device__ __forceinline__ uint64_t first_chunk() {
+  if (gridDim.x % NXCD) return blockIdx.x;
+  return (uint64_t)(blockIdx.x % NXCD) * (gridDim.x / NXCD) + blockIdx.x / NXCD;
+}
+
 // The job owning chunk c (< cs[njobs]): the largest j with cs[j] <= c.
 __device__ __forceinline__ int chunk_job(const ChunkMap& m, int njobs, uint64_t c) {
   int lo = 0, hi = njobs - 1;
@@ -574,7 +586,7 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
     return ch;
   });
   unsigned long long by = 0;
-  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+  for (uint64_t ch = first_chunk(); ch < cm.cs[njobs]; ch += gridDim.x) {
     const int jb = chunk_job(cm, njobs, ch);
     const FilterJob& J = jobs[jb];
     uint64_t r = ch - cm.cs[jb];
