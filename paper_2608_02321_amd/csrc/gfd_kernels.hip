@@ -571,6 +571,26 @@ __device__ __forceinline__ uint64_t direct_span(const DevGraph& g, const FilterJ
   return (uint64_t)(P[N] - P[0]);
 }
 
+// Constraint bits met by one thread's run of positions on the same item.  A
+// thread's positions are consecutive, so their items never decrease: the bits
+// are gathered while the item stays the same and written with one atomic when
+// it changes, instead of one atomic per matching entry.
+struct HitRun {
+  uint64_t item = ~0ull;
+  uint32_t mask = 0;
+  // Index map: the hit word of item t is hits[rows ? rows[t] : t].
+  __device__ void flush(uint32_t* hits, const uint32_t* rows = nullptr) {
+    if (mask) atomicOr(&hits[rows ? (uint64_t)rows[item] : item], mask);
+    mask = 0;
+  }
+  __device__ void at(uint32_t* hits, uint64_t t, const uint32_t* rows = nullptr) {
+    if (t != item) {
+      flush(hits, rows);
+      item = t;
+    }
+  }
+};
+
 // One thread per adjacency entry: mark constraint c of item i as met.
 __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob* __restrict__ jobs,
                                                     int njobs, unsigned long long* bytes) {
@@ -603,23 +623,30 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const PullC& cs = J.cons[c];
       const uint64_t c0 = P[0] + r * LBS_CHUNK;
       const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
+      const uint32_t bit = 1u << c;
       if (cs.blk) {  // only e-labelled entries; the block names each row's item
         const uint32_t* rows = g.elb_row[cs.dir] + cs.rb;
         const int32_t* nbr = g.elb_nbr[cs.dir];
+        HitRun run;
         flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t x) {
           if (!valid) return;
           by += (o == 0 ? 8 : 0) + 4;  // per row: item and start; per entry: neighbour
-          if (member(cs.w, nbr[x])) atomicOr(&J.hits[rows[s]], 1u << c);
+          run.at(J.hits, s, rows);
+          if (member(cs.w, nbr[x])) run.mask |= bit;
         });
+        run.flush(J.hits, rows);
       } else {
         const Rows rw = direct_rows(g, J, cs.dir);
+        HitRun run;
         flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t i, uint64_t o, uint64_t x) {
           if (!valid) return;
           // per entry: neighbour (+ label); the items' offsets stream once
           by += (o == 0 ? 4 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
+          run.at(J.hits, i);
           if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
-          if (member(cs.w, rw.nbr[x])) atomicOr(&J.hits[i], 1u << c);
+          if (member(cs.w, rw.nbr[x])) run.mask |= bit;
         });
+        run.flush(J.hits);
       }
     } else {
       const uint32_t nc = (uint32_t)J.ncons;
@@ -627,6 +654,7 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const uint64_t T = *J.sc.d_total;
       const uint64_t c0 = r * LBS_CHUNK;
       const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
+      HitRun run;
       flat_chunk<true>(J.sc.P, NP, c0, c1, sh, [&](bool valid, uint64_t q, uint64_t o, uint64_t) {
         if (!valid) return;
         const uint64_t i = q / nc;
@@ -637,9 +665,11 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
         const uint32_t x = rw.off[v] + (uint32_t)o;
         // per row: item and its two offsets; per entry: neighbour (+ label)
         by += (o == 0 ? 12 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
+        run.at(J.hits, i);
         if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
-        if (member(cs.w, rw.nbr[x])) atomicOr(&J.hits[i], 1u << c);
+        if (member(cs.w, rw.nbr[x])) run.mask |= 1u << c;
       });
+      run.flush(J.hits);
     }
   }
   if (bytes) block_add(bytes, by);
