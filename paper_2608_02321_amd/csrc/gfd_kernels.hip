@@ -953,10 +953,11 @@ void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, 
 
 template <class T, int N>
 __device__ __forceinline__ T pick(const T (&h)[N], int idx) {
-  T r = h[0];
+  // masks, not selects: a select chain over a runtime index is turned back
+  // into an indexed private array, which lives in scratch memory
+  T r = 0;
 #pragma unroll
-  for (int j = 1; j < N; j++)
-    if (j == idx) r = h[j];
+  for (int j = 0; j < N; j++) r |= h[j] & (T)(0 - (T)(j == idx));
   return r;
 }
 

@@ -1,0 +1,53 @@
+"""Compiler resource report of every device kernel (host-only: hipcc
+cross-compiles for gfx950 without a GPU).  No kernel may use per-lane scratch
+memory: a tuple held in a runtime-indexed private array ends up there, and
+every enumeration attempt then stores and reloads it through the memory
+hierarchy.  The enumeration kernels must also keep enough waves per SIMD to
+hide the latency of their random loads."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2608_02321_amd import build as B
+
+KERNELS = os.path.join(B.CSRC, "gfd_kernels.hip")
+
+
+@pytest.fixture(scope="module")
+def report(tmp_path_factory):
+    if not shutil.which(B.HIPCC) and not os.path.exists(B.HIPCC):
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("ru") / "k.o"
+    flags = [f for f in B.FLAGS if f != "-Wall"]
+    r = subprocess.run([B.HIPCC, *flags, "--cuda-device-only", "-Rpass-analysis=kernel-resource-usage",
+                        "-c", KERNELS, "-o", str(out)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    kernels, cur = {}, None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark:\s+(.*?)\s+\[-Rpass-analysis", line)
+        if not m:
+            continue
+        key, _, val = m.group(1).partition(":")
+        if key == "Function Name":
+            cur = val.strip()
+            kernels[cur] = {}
+        elif cur is not None:
+            kernels[cur][key.strip()] = val.strip()
+    assert kernels, "no resource remarks"
+    return kernels
+
+
+def test_no_kernel_uses_scratch(report):
+    bad = {k: v.get("ScratchSize [bytes/lane]") for k, v in report.items()
+           if v.get("ScratchSize [bytes/lane]") != "0"}
+    assert not bad, bad
+
+
+def test_enumeration_occupancy(report):
+    ext = {k: int(v["Occupancy [waves/SIMD]"]) for k, v in report.items() if "k_ext_run" in k}
+    assert len(ext) == 2, list(report)
+    for k, occ in ext.items():
+        assert occ >= 4, (k, occ)
