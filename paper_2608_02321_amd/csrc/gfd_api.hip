@@ -263,6 +263,37 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
       std::memcpy(&lv_in_lab[lv_in_off[p]], &in_lab[in_off[v]], 4 * (in_off[v + 1] - in_off[v]));
     }
   });
+  // combined rows: for every vertex the ascending union of its out- and
+  // in-neighbours, each with the labels of both edges (v -> w, w -> v), so one
+  // search answers a constraint on both directions of a pair
+  std::vector<uint64_t> sym_off(n + 1, 0);
+  auto merge_row = [&](int64_t v, int32_t* nb, int32_t* lb) -> uint64_t {
+    uint32_t i = out_off[v], ie = out_off[v + 1], j = in_off[v], je = in_off[v + 1];
+    uint64_t c = 0;
+    while (i < ie || j < je) {
+      const int32_t a = i < ie ? out_nbr[i] : INT32_MAX, b = j < je ? in_nbr[j] : INT32_MAX;
+      const int32_t w = a < b ? a : b;
+      int32_t lo = NOEDGE, li = NOEDGE;
+      if (a == w) lo = out_lab[i++];
+      if (b == w) li = in_lab[j++];
+      if (nb) {
+        nb[c] = w;
+        lb[2 * c] = lo;
+        lb[2 * c + 1] = li;
+      }
+      c++;
+    }
+    return c;
+  };
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int64_t v = a; v < b; v++) sym_off[v + 1] = merge_row(v, nullptr, nullptr);
+  });
+  for (int64_t v = 0; v < n; v++) sym_off[v + 1] += sym_off[v];
+  std::vector<int32_t> sym_nbr(sym_off[n]), sym_lab(2 * sym_off[n]);
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int64_t v = a; v < b; v++)
+      merge_row(v, sym_nbr.data() + sym_off[v], sym_lab.data() + 2 * sym_off[v]);
+  });
   // edge-label blocks per direction: for every (vertex label, edge label) the
   // bucket rows with such edges, in bucket order, and those edges' far ends
   const int32_t nel = maxel + 1;
@@ -357,6 +388,9 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     g->dg.lv_in_off = (const uint32_t*)up(lv_in_off.data(), 4 * (n + 1));
     g->dg.lv_in_nbr = (const int32_t*)up(lv_in_nbr.data(), 4 * m);
     g->dg.lv_in_lab = (const int32_t*)up(lv_in_lab.data(), 4 * m);
+    g->dg.sym_off = (const uint64_t*)up(sym_off.data(), 8 * (n + 1));
+    g->dg.sym_nbr = (const int32_t*)up(sym_nbr.data(), 4 * sym_nbr.size());
+    g->dg.sym_lab = (const int2*)up(sym_lab.data(), 4 * sym_lab.size());
     for (int d = 0; d < 2; d++) {
       g->dg.elb_row[d] = (const uint32_t*)up(elb_row[d].data(), 4 * elb_row[d].size());
       g->dg.elb_start[d] = (const uint32_t*)up(elb_start[d].data(), 4 * elb_start[d].size());

@@ -69,6 +69,11 @@ struct DevGraph {
   const uint32_t* elb_row[2];    // [rows_d] bucket position of the row
   const uint32_t* elb_start[2];  // [rows_d + 1]
   const int32_t* elb_nbr[2];     // [m]
+  // combined rows: row v is the ascending union of v's out- and in-neighbours
+  // w, with sym_lab = (label of v -> w, label of w -> v), NOEDGE where absent
+  const uint64_t* sym_off;  // [n+1]
+  const int32_t* sym_nbr;   // [sym_off[n]]
+  const int2* sym_lab;      // [sym_off[n]]
 };
 
 // A candidate set C(u): its members (list, *cnt), their positions in the list

@@ -112,6 +112,25 @@ __device__ __forceinline__ int32_t edge_label_at(const DevGraph& g, int32_t a, i
   return NOEDGE;
 }
 
+// Labels of both data edges between a and b, (a -> b, b -> a), NOEDGE where
+// absent: one search of a's combined row instead of one in each direction.
+__device__ __forceinline__ int2 edge_labels_both(const DevGraph& g, int32_t a, int32_t b,
+                                                 unsigned long long& by) {
+  uint64_t lo = g.sym_off[a], hi = g.sym_off[a + 1];
+  const uint64_t end = hi;
+  by += 16;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    by += 4;
+    if (g.sym_nbr[mid] < b) lo = mid + 1; else hi = mid;
+  }
+  if (lo < end && g.sym_nbr[lo] == b) {
+    by += 8;
+    return g.sym_lab[lo];
+  }
+  return make_int2(NOEDGE, NOEDGE);
+}
+
 // Constraint `code` on data edge a -> b, probed in the anchor's row.
 __device__ __forceinline__ bool pair_ok(const DevGraph& g, int32_t a, int32_t b, bool anchor_a,
                                         int32_t code, unsigned long long& by) {
@@ -1167,9 +1186,15 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
         if (LAST && ok && thr_on && J.collect_only) ok = !past_threshold(J, h, thr);
         for (int c = 0; c < J.nchk && ok; c++) {
           const int32_t hw = pick(h, J.chk_pos[c]);
-          // both directions in rows of hw, which the wave's threads share
-          ok = pair_ok(g, hw, v, true, J.chk_fwd[c], by) &&
-               pair_ok(g, v, hw, false, J.chk_bwd[c], by);
+          const int32_t cf = J.chk_fwd[c], cb = J.chk_bwd[c];
+          // rows of hw, which the wave's threads share: the combined row when
+          // both directions are constrained, else the one direction's row
+          if (cf != PC_FREE && cb != PC_FREE) {
+            const int2 l = edge_labels_both(g, hw, v, by);
+            ok = constraint_ok(l.x, cf) && constraint_ok(l.y, cb);
+          } else {
+            ok = pair_ok(g, hw, v, true, cf, by) && pair_ok(g, v, hw, false, cb, by);
+          }
         }
       }
       if (!LAST) {  // block-aggregated append to the next frontier
