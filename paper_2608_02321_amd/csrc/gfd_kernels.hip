@@ -395,15 +395,17 @@ __device__ __forceinline__ void flat_chunk_pre(const T* __restrict__ P, uint64_t
   if (in_lds)
     for (uint64_t j = threadIdx.x; j < span; j += BS) sh.p[j] = P[lo + j];
   __syncthreads();
-  uint32_t ss[LBS_ROUNDS], oo[LBS_ROUNDS];
+  // per round only the source is kept; its offset is recomputed from the
+  // staged prefix when the value is loaded, and f learns only whether it is
+  // the source's first position
+  uint32_t ss[LBS_ROUNDS];
   int32_t pv[LBS_ROUNDS];
-  uint32_t valid = 0;
+  uint32_t valid = 0, first = 0;
   uint32_t l = 0;  // in_lds: source lo + l
 #pragma unroll
   for (int r = 0; r < LBS_ROUNDS; r++) {
     const uint64_t a = c0 + (uint64_t)r * BS + threadIdx.x;
     ss[r] = 0;
-    oo[r] = 0;
     if (a < c1) {
       valid |= 1u << r;
       uint64_t sx;
@@ -414,18 +416,25 @@ __device__ __forceinline__ void flat_chunk_pre(const T* __restrict__ P, uint64_t
           if (sh.p[mid] <= a) l = mid; else h = mid - 1;
         }
         sx = lo + l;
-        oo[r] = (uint32_t)(a - sh.p[l]);
       } else {
         sx = last_le(P, lo, hi, a);
-        oo[r] = (uint32_t)(a - P[sx]);
       }
       ss[r] = (uint32_t)sx;
     }
   }
 #pragma unroll
-  for (int r = 0; r < LBS_ROUNDS; r++) pv[r] = ((valid >> r) & 1u) ? pre(ss[r], oo[r]) : 0;
+  for (int r = 0; r < LBS_ROUNDS; r++) {
+    pv[r] = 0;
+    if ((valid >> r) & 1u) {
+      const uint64_t a = c0 + (uint64_t)r * BS + threadIdx.x;
+      const uint32_t o = (uint32_t)(a - (in_lds ? sh.p[ss[r] - lo] : (uint64_t)P[ss[r]]));
+      first |= (o == 0 ? 1u : 0u) << r;
+      pv[r] = pre(ss[r], o);
+    }
+  }
 #pragma unroll
-  for (int r = 0; r < LBS_ROUNDS; r++) f(((valid >> r) & 1u) != 0, (uint64_t)ss[r], (uint64_t)oo[r], pv[r]);
+  for (int r = 0; r < LBS_ROUNDS; r++)
+    f(((valid >> r) & 1u) != 0, (uint64_t)ss[r], ((first >> r) & 1u) != 0, pv[r]);
   __syncthreads();
 }
 
@@ -991,7 +1000,7 @@ __device__ __forceinline__ bool literal_holds(const DevGraph& g, const DevLit& l
 // Whether the complete match h (matching order) orders after the staging
 // threshold in variable order (or equals it when the threshold is exclusive).
 __device__ __forceinline__ bool past_threshold(const ExtJob& J, const int32_t (&h)[MAXK],
-                                               const int32_t (&thr)[MAXK]) {
+                                               const int32_t* thr) {
   int c = 0;
 #pragma unroll
   for (int v = 0; v < MAXK; v++)
@@ -1011,7 +1020,7 @@ struct FinalAcc {
 // precedes the current threshold); `t` then holds it in variable order.
 __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
                                          const int32_t (&h)[MAXK], int32_t (&t)[MAXK],
-                                         FinalAcc& acc, bool thr_on, const int32_t (&thr)[MAXK],
+                                         FinalAcc& acc, bool thr_on, const int32_t* thr,
                                          unsigned long long& by) {
   uint64_t hs = 0x9E3779B97F4A7C15ull * (uint64_t)J.k;
 #pragma unroll
@@ -1145,6 +1154,7 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
   __shared__ ChunkMap cm;
   __shared__ unsigned long long s_wcnt[BS / WAVE];
   __shared__ unsigned long long s_woff[BS / WAVE];
+  __shared__ int32_t s_thr[MAXK];
   chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(ext_width<LAST>(jobs[j])); });
   const uint32_t wv = threadIdx.x / WAVE;
   unsigned long long by = 0;
@@ -1158,23 +1168,25 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
     const uint64_t c1 = c0 + LBS_CHUNK < A1 ? c0 + LBS_CHUNK : A1;
     const int i = J.i;
     FinalAcc acc{0, 0, 0, 0};
-    int32_t thr[MAXK];
     bool thr_on = false, full = false;
     if (LAST) {
+      // the staging threshold, shared through LDS: written before the first
+      // barrier of the chunk (the previous chunk ended on one), read after it
       thr_on = J.thr != nullptr && *J.d_thr_valid != 0;
-#pragma unroll
-      for (int v = 0; v < MAXK; v++) thr[v] = thr_on && v < J.k ? J.thr[v] : 0;
+      if (threadIdx.x < MAXK)
+        s_thr[threadIdx.x] = thr_on && (int)threadIdx.x < J.k ? J.thr[threadIdx.x] : 0;
     }
+    const int32_t* thr = s_thr;
     auto cpi_entry = [&](uint32_t s, uint32_t o) -> int32_t {
       return J.cpi_ent[(uint64_t)J.begs[s] + o];
     };
-    flat_chunk_pre(J.sc.P, N, c0, c1, sh, cpi_entry, [&](bool valid, uint64_t s, uint64_t o,
+    flat_chunk_pre(J.sc.P, N, c0, c1, sh, cpi_entry, [&](bool valid, uint64_t s, bool first,
                                                           int32_t v) {
       int32_t h[MAXK];
       bool ok = false;
       if (valid) {
         // the CPI entry; the source's list start, prefix and partial once per source
-        by += 4 + (o == 0 ? 12ull + 4ull * (uint64_t)i : 0ull);
+        by += 4 + (first ? 12ull + 4ull * (uint64_t)i : 0ull);
         ok = true;
 #pragma unroll
         for (int j = 0; j < MAXK; j++) {
