@@ -114,8 +114,23 @@ __device__ __forceinline__ int32_t edge_label_at(const DevGraph& g, int32_t a, i
 
 // Labels of both data edges between a and b, (a -> b, b -> a), NOEDGE where
 // absent: one search of a's combined row instead of one in each direction.
+// A long row is first looked up in its neighbour table, which settles the
+// common case (not adjacent) in about one access; the row search then runs
+// only for neighbours, to read their labels.
 __device__ __forceinline__ int2 edge_labels_both(const DevGraph& g, int32_t a, int32_t b,
                                                  unsigned long long& by) {
+  const uint64_t t0 = g.hub_off[a], t1 = g.hub_off[a + 1];
+  by += 16;
+  if (t1 > t0) {
+    const uint64_t mask = t1 - t0 - 1;
+    // at least half the slots are free, so the probe sequence ends
+    for (uint64_t i = hub_slot(b, t1 - t0);; i = (i + 1) & mask) {
+      const int32_t e = g.hub_tab[t0 + i];
+      by += 4;
+      if (e == b) break;
+      if (e == HUB_EMPTY) return make_int2(NOEDGE, NOEDGE);
+    }
+  }
   uint64_t lo = g.sym_off[a], hi = g.sym_off[a + 1];
   const uint64_t end = hi;
   by += 16;
@@ -1048,6 +1063,14 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
   return !(thr_on && past_threshold(J, h, thr));
 }
 
+// Whether a job's staging is already past its capacity: a wave that starts
+// work on such a job drops its tuples without touching the counter (the
+// count already shows the overflow).  A stale read only costs one more
+// atomic add.
+__device__ __forceinline__ bool staging_past_cap(const ExtJob& J) {
+  return __hip_atomic_load(J.d_vcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > J.vcap;
+}
+
 // Wave-aggregated append of violating tuples to the job's staging buffer.
 // `full` (wave-uniform) becomes true once this wave's append has pushed the
 // count past vcap; from then on the wave drops its tuples without touching
@@ -1168,7 +1191,7 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
     const uint64_t c1 = c0 + LBS_CHUNK < A1 ? c0 + LBS_CHUNK : A1;
     const int i = J.i;
     FinalAcc acc{0, 0, 0, 0};
-    bool thr_on = false, full = false;
+    bool thr_on = false, full = LAST && staging_past_cap(J);
     if (LAST) {
       // the staging threshold, shared through LDS: written before the first
       // barrier of the chunk (the previous chunk ended on one), read after it
@@ -1271,7 +1294,7 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
   const bool thr_on = J.thr != nullptr && *J.d_thr_valid != 0;
 #pragma unroll
   for (int v = 0; v < MAXK; v++) thr[v] = thr_on && v < J.k ? J.thr[v] : 0;
-  bool full = false;
+  bool full = staging_past_cap(J);
   const uint64_t stride = (uint64_t)gridDim.x * BS;
   const uint64_t rounds = (N - I0 + stride - 1) / stride;  // uniform trip count for the ballot
   for (uint64_t r = 0; r < rounds; r++) {
