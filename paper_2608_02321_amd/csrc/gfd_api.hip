@@ -1434,10 +1434,17 @@ static void run_select(Ctx& c, std::vector<SelJob>& S, bool threshold) {
   const int gx = (int)std::max<uint64_t>(
       1, std::min<uint64_t>((maxcap + BS - 1) / BS, (uint64_t)std::max(4, 1024 / nj)));
   c.tm.run(K_TOPK, [&] { sel_begin(c.st, r, nj); });
-  const int shifts[3] = {21, 10, 0}, bits[3] = {11, 11, 10};
+  // tuple words are vertex ids < n: digits of at most RADIX_BITS cover the
+  // id's bit width, from the top
+  int idbits = 1;
+  while (idbits < 31 && (int64_t(1) << idbits) < (int64_t)c.g->n) idbits++;
+  const int npass = (idbits + RADIX_BITS - 1) / RADIX_BITS;
   for (int w = 0; w < maxk; w++)
-    for (int ps = 0; ps < 3; ps++)
-      c.tm.run(K_TOPK, [&] { sel_pass(c.st, r, nj, w, shifts[ps], bits[ps], gx); });
+    for (int ps = 0; ps < npass; ps++) {
+      const int shift = std::max(0, idbits - RADIX_BITS * (ps + 1));
+      const int bits = idbits - RADIX_BITS * ps - shift;
+      c.tm.run(K_TOPK, [&] { sel_pass(c.st, r, nj, w, shift, bits, gx); });
+    }
   if (threshold) c.tm.run(K_TOPK, [&] { sel_threshold(c.st, r, nj); });
   else c.tm.run(K_TOPK, [&] { sel_first_k(c.st, r, nj, gx); });
 }

@@ -262,7 +262,7 @@ struct SelJob {
   uint64_t* d_vcount;
   const int32_t* vbuf;
   uint64_t vcap;
-  uint32_t* state;                 // [MAXK + 1]
+  uint32_t* state;                 // [MAXK + 2]: tuple, rank, blocks done
   uint32_t* hist;                  // [RADIX_BINS], zero at rest
   int32_t* out;                    // [K * k]
   unsigned long long* d_outcount;

@@ -1484,12 +1484,33 @@ void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njob
 
 constexpr int SORT_THREADS = 1024;
 
+// Tuples being sorted in one workgroup sit in LDS as k columns: word w of
+// tuple j at s[w * SORT_MAX + j], so the threads of a compare-exchange step,
+// which take consecutive j, hit consecutive banks.
 __device__ __forceinline__ int cmp_lds(const uint32_t* s, uint32_t x, uint32_t y, int k) {
   for (int w = 0; w < k; w++) {
-    const uint32_t a = s[x * k + w], b = s[y * k + w];
+    const uint32_t a = s[w * SORT_MAX + x], b = s[w * SORT_MAX + y];
     if (a != b) return a < b ? -1 : 1;
   }
   return 0;
+}
+
+// Loads n tuples (k words each, row-major) into the columns, padding up to p2
+// with all-ones tuples, which order last.
+__device__ __forceinline__ void sort_load(uint32_t* s, const int32_t* src, uint32_t n, uint32_t p2,
+                                          int k) {
+  for (uint32_t q = threadIdx.x; q < p2 * (uint32_t)k; q += blockDim.x) {
+    const uint32_t j = q / (uint32_t)k, w = q - j * (uint32_t)k;
+    s[w * SORT_MAX + j] = j < n ? (uint32_t)src[q] : 0xFFFFFFFFu;
+  }
+}
+
+// Writes the first n tuples back row-major.
+__device__ __forceinline__ void sort_store(const uint32_t* s, int32_t* dst, uint32_t n, int k) {
+  for (uint32_t q = threadIdx.x; q < n * (uint32_t)k; q += blockDim.x) {
+    const uint32_t j = q / (uint32_t)k, w = q - j * (uint32_t)k;
+    dst[q] = (int32_t)s[w * SORT_MAX + j];
+  }
 }
 
 // Bitonic sort of p2 (power of two) tuples held in LDS, ascending.
@@ -1503,9 +1524,9 @@ __device__ void bitonic_lds(uint32_t* s, uint32_t p2, int k) {
         const int c = cmp_lds(s, lo, hi, k);
         if (c != 0 && (c > 0) == asc) {
           for (int w = 0; w < k; w++) {
-            const uint32_t tmp = s[lo * k + w];
-            s[lo * k + w] = s[hi * k + w];
-            s[hi * k + w] = tmp;
+            const uint32_t tmp = s[w * SORT_MAX + lo];
+            s[w * SORT_MAX + lo] = s[w * SORT_MAX + hi];
+            s[w * SORT_MAX + hi] = tmp;
           }
         }
       }
@@ -1527,14 +1548,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_topk_small(const TopkJob* __re
     return;
   }
   if (threadIdx.x == 0) *J.d_need_select = 0;
-  const int k = J.k;
   uint32_t p2 = 1;
   while (p2 < cnt) p2 <<= 1;
-  for (uint32_t i = threadIdx.x; i < p2 * (uint32_t)k; i += blockDim.x)
-    s[i] = (i / k < cnt) ? (uint32_t)J.vbuf[i] : 0xFFFFFFFFu;
-  bitonic_lds(s, p2, k);
-  const uint64_t out = cnt < (uint64_t)J.K ? cnt : (uint64_t)J.K;
-  for (uint32_t i = threadIdx.x; i < out * (uint32_t)k; i += blockDim.x) J.res[i] = (int32_t)s[i];
+  sort_load(s, J.vbuf, (uint32_t)cnt, p2, J.k);
+  bitonic_lds(s, p2, J.k);
+  sort_store(s, J.res, (uint32_t)(cnt < (uint64_t)J.K ? cnt : (uint64_t)J.K), J.k);
 }
 
 void topk_small(hipStream_t st, const TopkJob* jobs, int njobs) {
@@ -1543,13 +1561,15 @@ void topk_small(hipStream_t st, const TopkJob* jobs, int njobs) {
 
 // Radix select, batched over jobs (grid row y = job).  State words of a job:
 // [0..MAXK) the tuple being decided, [MAXK] the remaining rank (1-based) among
-// staged tuples that agree with it so far.
+// staged tuples that agree with it so far, [MAXK + 1] blocks done in the
+// current pass.
 __global__ void k_sel_begin(const SelJob* __restrict__ jobs) {
   const SelJob& J = jobs[blockIdx.y];
   if (!J.active) return;
   if (threadIdx.x < MAXK) J.state[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     J.state[MAXK] = (uint32_t)J.K;
+    J.state[MAXK + 1] = 0;
     if (J.d_outcount) *J.d_outcount = 0;
   }
 }
@@ -1558,17 +1578,29 @@ __device__ __forceinline__ uint64_t sel_count(const SelJob& J) {
   return *J.d_vcount < J.vcap ? *J.d_vcount : J.vcap;
 }
 
-// Tuples that agree with the decided prefix (words < word, and the decided
-// high bits of `word`) vote for the next digit of `word`.
-__global__ __launch_bounds__(BS) void k_sel_hist(const SelJob* __restrict__ jobs, int word,
+// One digit of the radix select.  Tuples that agree with the decided prefix
+// (words < word, and the decided high bits of `word`) vote for the next digit
+// of `word`; the last block of a job to add its votes (per-job counter
+// state[MAXK + 1]) finds the bin holding the remaining rank with a block-wide
+// scan of the histogram, records the digit and clears the histogram and the
+// counter for the next pass.  Ordering without a cache-flushing fence: the
+// histogram adds are agent-scope atomics whose returned values feed the LDS
+// before the barrier, so they have been performed before the block's counter
+// add is issued; the last block reads the bins with agent-scope atomic loads
+// issued after it has seen the final count.
+__global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs, int word,
                                                  int shift, int bits) {
+  constexpr int PER = RADIX_BINS / BS;
   __shared__ uint32_t sh[RADIX_BINS];
+  __shared__ uint32_t s_last, s_seen;
   const SelJob& J = jobs[blockIdx.y];
   if (!J.active || word >= J.k) return;
   for (int b = threadIdx.x; b < RADIX_BINS; b += BS) sh[b] = 0;
+  if (threadIdx.x == 0) s_seen = 0;
   uint32_t st[MAXK];
 #pragma unroll
   for (int w = 0; w < MAXK; w++) st[w] = J.state[w];
+  const uint32_t r = J.state[MAXK];  // read before any block can be the last
   __syncthreads();
   const int k = J.k;
   const uint64_t cnt = sel_count(J);
@@ -1585,24 +1617,24 @@ __global__ __launch_bounds__(BS) void k_sel_hist(const SelJob* __restrict__ jobs
     atomicAdd(&sh[(x >> shift) & ((1u << bits) - 1)], 1u);
   }
   __syncthreads();
+  uint32_t seen = 0;
   for (int b = threadIdx.x; b < RADIX_BINS; b += BS)
-    if (sh[b]) atomicAdd(&J.hist[b], sh[b]);
-}
-
-// Finds the bin holding the remaining rank with a block-wide scan of the
-// histogram (BS threads x RADIX_BINS / BS bins each), then clears it.
-__global__ __launch_bounds__(BS) void k_sel_pick(const SelJob* __restrict__ jobs, int word,
-                                                 int shift, int bits) {
-  constexpr int PER = RADIX_BINS / BS;
-  const SelJob& J = jobs[blockIdx.y];
-  if (!J.active || word >= J.k) return;
+    if (sh[b])
+      seen |= __hip_atomic_fetch_add(&J.hist[b], sh[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  atomicOr(&s_seen, seen);  // waits for the adds' return values
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(&J.state[MAXK + 1], 1u, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
   const uint32_t nb = 1u << bits;
-  const uint32_t r = J.state[MAXK];  // read before the scan's barriers; one thread rewrites it
   uint32_t h[PER], sum = 0;
 #pragma unroll
   for (int j = 0; j < PER; j++) {
     const uint32_t bin = threadIdx.x * PER + j;
-    h[j] = bin < nb ? J.hist[bin] : 0u;
+    h[j] = bin < nb ? __hip_atomic_load(&J.hist[bin], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : 0u;
     sum += h[j];
   }
   uint32_t total;
@@ -1619,9 +1651,9 @@ __global__ __launch_bounds__(BS) void k_sel_pick(const SelJob* __restrict__ jobs
     J.state[MAXK] = r - cum;
     J.state[word] |= d << shift;
   }
-  __syncthreads();
 #pragma unroll
   for (int j = 0; j < PER; j++) J.hist[threadIdx.x * PER + j] = 0;
+  if (threadIdx.x == 0) J.state[MAXK + 1] = 0;
 }
 
 // Staged tuples <= the selected one (exactly K of them, tuples being
@@ -1655,14 +1687,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sel_sort(const SelJob* __restr
   __shared__ uint32_t s[SORT_MAX * MAXK];
   const SelJob& J = jobs[blockIdx.y];
   if (!J.active) return;
-  const int k = J.k;
   const uint64_t n = *J.d_outcount < (uint64_t)J.K ? *J.d_outcount : (uint64_t)J.K;
   uint32_t p2 = 1;
   while (p2 < n) p2 <<= 1;
-  for (uint32_t i = threadIdx.x; i < p2 * (uint32_t)k; i += blockDim.x)
-    s[i] = (i / k < n) ? (uint32_t)J.out[i] : 0xFFFFFFFFu;
-  bitonic_lds(s, p2, k);
-  for (uint32_t i = threadIdx.x; i < n * (uint32_t)k; i += blockDim.x) J.out[i] = (int32_t)s[i];
+  sort_load(s, J.out, (uint32_t)n, p2, J.k);
+  bitonic_lds(s, p2, J.k);  // every tuple is in LDS before any is written back
+  sort_store(s, J.out, (uint32_t)n, J.k);
 }
 
 // The selected tuple becomes the job's staging threshold; staging restarts.
@@ -1681,8 +1711,7 @@ void sel_begin(hipStream_t st, const SelJob* jobs, int njobs) {
 }
 void sel_pass(hipStream_t st, const SelJob* jobs, int njobs, int word, int shift, int bits,
               int gx) {
-  hipLaunchKernelGGL(k_sel_hist, dim3(gx, njobs), dim3(BS), 0, st, jobs, word, shift, bits);
-  hipLaunchKernelGGL(k_sel_pick, dim3(1, njobs), dim3(BS), 0, st, jobs, word, shift, bits);
+  hipLaunchKernelGGL(k_sel_pass, dim3(gx, njobs), dim3(BS), 0, st, jobs, word, shift, bits);
 }
 void sel_first_k(hipStream_t st, const SelJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_sel_compact, dim3(gx, njobs), dim3(BS), 0, st, jobs);
