@@ -138,6 +138,8 @@ struct gfd_graph {
   int32_t num_attrs = 0, nvl = 0, nel = 0;
   std::vector<uint32_t> lab_off;       // host copy [nvl+1]
   std::vector<uint32_t> elb_blk[2];    // host: first row of each (vertex label, edge label) block
+  std::vector<uint32_t> elt_blk[2];    // host: the same per (vertex label, edge label, far label)
+  bool triples = false;                // elt_* built
   std::vector<uint64_t> lab_out_sum;   // sum of out-degrees per vertex label
   std::vector<uint64_t> lab_in_sum;
   std::vector<void*> owned;
@@ -319,64 +321,78 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     }
   });
   // edge-label blocks per direction: for every (vertex label, edge label) the
-  // bucket rows with such edges, in bucket order, and those edges' far ends
+  // bucket rows with such edges, in bucket order, and those edges' far ends;
+  // and the same keyed by (vertex label, edge label, far end's label), built
+  // when there are at most LABEL_TRIPLES_MAX such keys.  A block's rows list a
+  // bucket row once per run of entries with the block's key.
   const int32_t nel = maxel + 1;
-  std::vector<uint32_t> elb_row[2], elb_start[2];
-  std::vector<int32_t> elb_nbr[2];
-  std::vector<uint32_t> elb_blk[2];  // [nvl * nel + 1] first row of each block
-  for (int d = 0; d < 2; d++) {
+  const size_t npair = (size_t)nvl * (size_t)std::max(nel, 1);
+  const bool triples = npair * (size_t)nvl <= LABEL_TRIPLES_MAX;
+  struct Blocks {
+    std::vector<uint32_t> row, start, blk;  // blk: [keys + 1] first row of each block
+    std::vector<int32_t> nbr;
+  };
+  Blocks elb[2], elt[2];
+  auto build_blocks = [&](int d, bool tri, Blocks& B) {
     const std::vector<uint32_t>& off = d ? lv_in_off : lv_out_off;
     const std::vector<int32_t>& nb = d ? lv_in_nbr : lv_out_nbr;
     const std::vector<int32_t>& lb = d ? lv_in_lab : lv_out_lab;
-    const size_t nblk = (size_t)nvl * (size_t)std::max(nel, 1);
-    std::vector<uint64_t> rows(nblk + 1, 0), ents(nblk + 1, 0);
-    // a row's entries grouped by edge label (neighbour order kept within a label)
-    auto grouped = [&](uint32_t p, std::vector<std::pair<int32_t, int32_t>>& es) {
+    const size_t nkeys = tri ? npair * (size_t)nvl : npair;
+    std::vector<uint64_t> rows(nkeys + 1, 0), ents(nkeys + 1, 0);
+    // a row's entries as (key within the bucket, neighbour), grouped by key with
+    // the neighbour order kept within a key
+    auto grouped = [&](uint32_t p, std::vector<std::pair<int64_t, int32_t>>& es) {
       es.clear();
-      for (uint32_t e = off[p]; e < off[p + 1]; e++) es.push_back({lb[e], nb[e]});
+      for (uint32_t e = off[p]; e < off[p + 1]; e++)
+        es.push_back({tri ? (int64_t)lb[e] * nvl + vlabel[nb[e]] : (int64_t)lb[e], nb[e]});
       std::stable_sort(es.begin(), es.end(),
-                       [](const std::pair<int32_t, int32_t>& x, const std::pair<int32_t, int32_t>& y) {
+                       [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
                          return x.first < y.first;
                        });
     };
+    const size_t per_label = tri ? (size_t)nel * nvl : (size_t)nel;
     parallel_for(nvl, [&](int64_t l0, int64_t l1) {  // blocks of one vertex label are disjoint
-      std::vector<std::pair<int32_t, int32_t>> es;
+      std::vector<std::pair<int64_t, int32_t>> es;
       for (int64_t L = l0; L < l1; L++)
         for (uint32_t p = lab_off[L]; p < lab_off[L + 1]; p++) {
           grouped(p, es);
           for (size_t i = 0; i < es.size(); i++) {
-            const size_t b = (size_t)L * nel + es[i].first;
+            const size_t b = (size_t)L * per_label + es[i].first;
             ents[b + 1]++;
             if (i == 0 || es[i].first != es[i - 1].first) rows[b + 1]++;
           }
         }
     });
-    for (size_t b = 0; b < nblk; b++) {
+    for (size_t b = 0; b < nkeys; b++) {
       rows[b + 1] += rows[b];
       ents[b + 1] += ents[b];
     }
-    elb_row[d].assign(rows[nblk], 0);
-    elb_start[d].assign(rows[nblk] + 1, 0);
-    elb_nbr[d].assign(ents[nblk], 0);
-    elb_blk[d].assign(rows.begin(), rows.end());
+    B.row.assign(rows[nkeys], 0);
+    B.start.assign(rows[nkeys] + 1, 0);
+    B.nbr.assign(ents[nkeys], 0);
+    B.blk.assign(rows.begin(), rows.end());
     std::vector<uint64_t> rcur(rows.begin(), rows.end() - 1), ecur(ents.begin(), ents.end() - 1);
     parallel_for(nvl, [&](int64_t l0, int64_t l1) {
-      std::vector<std::pair<int32_t, int32_t>> es;
+      std::vector<std::pair<int64_t, int32_t>> es;
       for (int64_t L = l0; L < l1; L++)
         for (uint32_t p = lab_off[L]; p < lab_off[L + 1]; p++) {
           grouped(p, es);
           for (size_t i = 0; i < es.size(); i++) {
-            const size_t b = (size_t)L * nel + es[i].first;
+            const size_t b = (size_t)L * per_label + es[i].first;
             if (i == 0 || es[i].first != es[i - 1].first) {
               const uint64_t r = rcur[b]++;
-              elb_row[d][r] = p - lab_off[L];
-              elb_start[d][r] = (uint32_t)ecur[b];
+              B.row[r] = p - lab_off[L];
+              B.start[r] = (uint32_t)ecur[b];
             }
-            elb_nbr[d][ecur[b]++] = es[i].second;
+            B.nbr[ecur[b]++] = es[i].second;
           }
         }
     });
-    elb_start[d][rows[nblk]] = (uint32_t)ents[nblk];
+    B.start[rows[nkeys]] = (uint32_t)ents[nkeys];
+  };
+  for (int d = 0; d < 2; d++) {
+    build_blocks(d, false, elb[d]);
+    if (triples) build_blocks(d, true, elt[d]);
   }
   std::vector<int32_t> attr_flat((size_t)num_attrs * n);
   for (int32_t a = 0; a < num_attrs; a++)
@@ -418,11 +434,18 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     g->dg.sym_nbr = (const int32_t*)up(sym_nbr.data(), 4 * sym_nbr.size());
     g->dg.sym_lab = (const int2*)up(sym_lab.data(), 4 * sym_lab.size());
     for (int d = 0; d < 2; d++) {
-      g->dg.elb_row[d] = (const uint32_t*)up(elb_row[d].data(), 4 * elb_row[d].size());
-      g->dg.elb_start[d] = (const uint32_t*)up(elb_start[d].data(), 4 * elb_start[d].size());
-      g->dg.elb_nbr[d] = (const int32_t*)up(elb_nbr[d].data(), 4 * elb_nbr[d].size());
-      g->elb_blk[d] = std::move(elb_blk[d]);
+      g->dg.elb_row[d] = (const uint32_t*)up(elb[d].row.data(), 4 * elb[d].row.size());
+      g->dg.elb_start[d] = (const uint32_t*)up(elb[d].start.data(), 4 * elb[d].start.size());
+      g->dg.elb_nbr[d] = (const int32_t*)up(elb[d].nbr.data(), 4 * elb[d].nbr.size());
+      g->elb_blk[d] = std::move(elb[d].blk);
+      if (triples) {
+        g->dg.elt_row[d] = (const uint32_t*)up(elt[d].row.data(), 4 * elt[d].row.size());
+        g->dg.elt_start[d] = (const uint32_t*)up(elt[d].start.data(), 4 * elt[d].start.size());
+        g->dg.elt_nbr[d] = (const int32_t*)up(elt[d].nbr.data(), 4 * elt[d].nbr.size());
+        g->elt_blk[d] = std::move(elt[d].blk);
+      }
     }
+    g->triples = triples;
     HIPCHK(hipStreamSynchronize(st));
     g->lab_off = std::move(lab_off);
     g->lab_out_sum = std::move(lab_out);
@@ -867,9 +890,27 @@ static void add_pulls(const Job& J, int u, const std::vector<int>& nbrs, FilterJ
   f.ncons = 0;
   for (int w : nbrs) {
     if (p.qe[w][u] != NOEDGE)  // w -> u: v needs an in-neighbour in C(w)
-      f.cons[f.ncons++] = PullC{1, p.qe[w][u], cand_set(J, w)};
+      f.cons[f.ncons++] = PullC{1, p.qe[w][u], cand_set(J, w), 0, 0, 0, p.qlab[w]};
     if (p.qe[u][w] != NOEDGE)  // u -> w: v needs an out-neighbour in C(w)
-      f.cons[f.ncons++] = PullC{0, p.qe[u][w], cand_set(J, w)};
+      f.cons[f.ncons++] = PullC{0, p.qe[u][w], cand_set(J, w), 0, 0, 0, p.qlab[w]};
+  }
+}
+
+// The edge-label block of bucket L's rows in direction dir for edge label e
+// (both labelled): keyed by the far end's label too when that label is known
+// (far labels ANY or absent from the graph keep the pair block).
+static void set_block(const gfd_graph* g, int32_t L, int32_t e, int32_t far, int32_t dir,
+                      int32_t& blk, uint32_t& rb, uint32_t& re) {
+  const size_t b = (size_t)L * g->nel + e;
+  if (g->triples && far != ANY && far < g->nvl) {
+    const size_t t = b * g->nvl + far;
+    blk = 2;
+    rb = g->elt_blk[dir][t];
+    re = g->elt_blk[dir][t + 1];
+  } else {
+    blk = 1;
+    rb = g->elb_blk[dir][b];
+    re = g->elb_blk[dir][b + 1];
   }
 }
 
@@ -886,10 +927,7 @@ static void make_direct(const gfd_graph* g, const Plan& p, int u, uint64_t bs, F
     PullC& pc = f.cons[q];
     pc.blk = 0;
     if (p.qlab[u] == ANY || pc.elab == ANY || p.qlab[u] >= g->nvl || pc.elab >= g->nel) continue;
-    const size_t b = (size_t)p.qlab[u] * g->nel + pc.elab;
-    pc.blk = 1;
-    pc.rb = g->elb_blk[pc.dir][b];
-    pc.re = g->elb_blk[pc.dir][b + 1];
+    set_block(g, p.qlab[u], pc.elab, pc.nlab, pc.dir, pc.blk, pc.rb, pc.re);
   }
 }
 
@@ -1081,10 +1119,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       a.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       a.blk = 0;
       if (p.qlab[q] != ANY && a.prim != ANY && p.qlab[q] < g->nvl && a.prim < g->nel) {
-        const size_t b = (size_t)p.qlab[q] * g->nel + a.prim;
-        a.blk = 1;
-        a.rb = g->elb_blk[a.dir][b];
-        a.re = g->elb_blk[a.dir][b + 1];
+        set_block(g, p.qlab[q], a.prim, p.qlab[u], a.dir, a.blk, a.rb, a.re);
         a.base = g->lab_off[p.qlab[q]];
       }
       items = std::max(items, a.cap_p);

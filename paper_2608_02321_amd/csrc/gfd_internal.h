@@ -33,6 +33,7 @@ constexpr int SCAN_TILE = BS * SCAN_IPT;
 constexpr int MAX_JOBS = 256;  // jobs per launch (one batch); at most BS
 constexpr int LBS_ROUNDS = 8;  // flat work: rounds of BS positions per located chunk
 constexpr uint64_t LBS_CHUNK = (uint64_t)BS * LBS_ROUNDS;
+constexpr size_t LABEL_TRIPLES_MAX = size_t(1) << 24;  // keys of the label-triple blocks
 constexpr int NXCD = 8;        // accelerator dies (XCDs), each with its own L2
 constexpr int SORT_MAX = 2048; // violation tuples sorted in one workgroup
 constexpr int RADIX_BITS = 11;
@@ -69,6 +70,10 @@ struct DevGraph {
   const uint32_t* elb_row[2];    // [rows_d] bucket position of the row
   const uint32_t* elb_start[2];  // [rows_d + 1]
   const int32_t* elb_nbr[2];     // [m]
+  // the same keyed by (vertex label, edge label, far end's label), when built
+  const uint32_t* elt_row[2];
+  const uint32_t* elt_start[2];
+  const int32_t* elt_nbr[2];
   // combined rows: row v is the ascending union of v's out- and in-neighbours
   // w, with sym_lab = (label of v -> w, label of w -> v), NOEDGE where absent
   const uint64_t* sym_off;  // [n+1]
@@ -117,8 +122,11 @@ struct PullC {
   int32_t dir, elab;
   CandSet w;
   // direct jobs with a labelled vertex and edge: the edge-label block's rows
+  // [rb, re); blk 1 the (vertex label, edge label) blocks, 2 those keyed by
+  // the far end's label too, 0 none
   uint32_t rb, re;
   int32_t blk;
+  int32_t nlab;  // label of the constraining pattern vertex (ANY: wildcard)
 };
 
 // Candidate filter of one pattern vertex u (Section IV-B: label candidates,

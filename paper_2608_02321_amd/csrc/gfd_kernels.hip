@@ -599,13 +599,25 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
   }, J.sc);
 }
 
+// Arrays of the edge-label blocks a job uses (blk 1: keyed by vertex and edge
+// label; 2: by the far end's label too).
+struct BlockArrays {
+  const uint32_t* row;
+  const uint32_t* start;
+  const int32_t* nbr;
+};
+__device__ __forceinline__ BlockArrays block_arrays(const DevGraph& g, int blk, int dir) {
+  return blk == 2 ? BlockArrays{g.elt_row[dir], g.elt_start[dir], g.elt_nbr[dir]}
+                  : BlockArrays{g.elb_row[dir], g.elb_start[dir], g.elb_nbr[dir]};
+}
+
 // Flat entries of constraint c of a direct job: its items' rows in one slice
 // (the prefix P has N + 1 entries), or the rows of its edge-label block.
 __device__ __forceinline__ uint64_t direct_span(const DevGraph& g, const FilterJob& J, int c,
                                                 const uint32_t*& P, uint64_t& N) {
   const PullC& cs = J.cons[c];
   if (cs.blk) {
-    P = g.elb_start[cs.dir] + cs.rb;
+    P = block_arrays(g, cs.blk, cs.dir).start + cs.rb;
     N = cs.re - cs.rb;
   } else {
     P = direct_rows(g, J, cs.dir).off + J.base;
@@ -668,8 +680,9 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
       const uint32_t bit = 1u << c;
       if (cs.blk) {  // only e-labelled entries; the block names each row's item
-        const uint32_t* rows = g.elb_row[cs.dir] + cs.rb;
-        const int32_t* nbr = g.elb_nbr[cs.dir];
+        const BlockArrays ba = block_arrays(g, cs.blk, cs.dir);
+        const uint32_t* rows = ba.row + cs.rb;
+        const int32_t* nbr = ba.nbr;
         HitRun run;
         flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t x) {
           if (!valid) return;
@@ -861,7 +874,7 @@ __device__ __forceinline__ bool cpi_keep_v(const DevGraph& g, const CpiJob& J, i
 // rows of C(p)'s members: when the block is at most twice those rows.
 __device__ __forceinline__ bool cpi_direct(const DevGraph& g, const CpiJob& J) {
   if (!J.blk) return false;
-  const uint32_t* P = g.elb_start[J.dir];
+  const uint32_t* P = block_arrays(g, J.blk, J.dir).start;
   return (uint64_t)(P[J.re] - P[J.rb]) <= 2ull * *J.sc.d_total;
 }
 
@@ -870,7 +883,7 @@ __device__ __forceinline__ bool cpi_direct(const DevGraph& g, const CpiJob& J) {
 __device__ __forceinline__ uint64_t cpi_chunks(const DevGraph& g, const CpiJob& J) {
   if (!J.active) return 0ull;
   if (cpi_direct(g, J)) {
-    const uint32_t* P = g.elb_start[J.dir];
+    const uint32_t* P = block_arrays(g, J.blk, J.dir).start;
     return chunks_of(P[J.re] - P[J.rb]);
   }
   return chunks_of(*J.sc.d_total);
@@ -883,12 +896,13 @@ template <class F>
 __device__ __forceinline__ void cpi_chunk(const DevGraph& g, const CpiJob& J, uint64_t r,
                                           LbsShared& sh, unsigned long long& by, F f) {
   if (cpi_direct(g, J)) {
-    const uint32_t* P = g.elb_start[J.dir] + J.rb;
+    const BlockArrays ba = block_arrays(g, J.blk, J.dir);
+    const uint32_t* P = ba.start + J.rb;
     const uint64_t N = J.re - J.rb, T = P[N] - P[0];
     const uint64_t c0 = P[0] + r * LBS_CHUNK;
     const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
-    const uint32_t* rows = g.elb_row[J.dir] + J.rb;
-    const int32_t* nbr = g.elb_nbr[J.dir];
+    const uint32_t* rows = ba.row + J.rb;
+    const int32_t* nbr = ba.nbr;
     flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t x) {
       if (!valid) return;
       const int32_t vp = g.lab_vtx[J.base + rows[s]];
