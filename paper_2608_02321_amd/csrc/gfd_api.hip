@@ -104,6 +104,9 @@ struct Workspace {
   uint64_t* hctl = nullptr;         // pinned mirror of control blocks
   size_t hctl_words = 0;
   int32_t* hres = nullptr;          // pinned mirror of a batch's first-K slots
+  uint32_t* hitpool = nullptr;      // filter hit bitmaps of a batch, zero at rest
+  size_t hitpool_words = 0;
+  bool hitpool_dirty = false;       // a call using it did not finish: clear before use
   size_t hres_words = 0;
   unsigned long long* misc = nullptr;  // [0] CPI cursor, [8..15] bytes per class
   uint32_t* err = nullptr;
@@ -122,7 +125,7 @@ struct Workspace {
   int64_t budget = 0;
 
   ~Workspace() {
-    dfree(arena); dfree(cpi_arena); dfree(jobrec); dfree(misc); dfree(err); dfree(chunk);
+    dfree(arena); dfree(cpi_arena); dfree(hitpool); dfree(jobrec); dfree(misc); dfree(err); dfree(chunk);
     dfree(vbig); dfree(sel_state); dfree(sel_hist); dfree(sel_out); dfree(selrec);
     if (hjobrec) (void)hipHostFree(hjobrec);
     if (hselrec) (void)hipHostFree(hselrec);
@@ -740,6 +743,8 @@ struct JobCaps {
   uint64_t pcap;    // largest scan (items) + 1
   uint64_t tiles;   // scan tile states
   uint64_t hits, begs, vcap;
+  uint64_t hit_words, hit_cons;  // hit bitmaps: words per constraint, constraints
+  uint64_t hit_region;           // words of the job's hit region (either layout)
   size_t bytes;     // region size (excluding control block, tile states, results)
 };
 
@@ -785,14 +790,18 @@ static uint64_t per_slot_bytes(int k) {
 
 static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t vcap, JobCaps& c) {
   const int k = p.k;
-  uint64_t items = 1, hits = 1;
+  uint64_t items = 1, hits = 1, cons = 1;
   for (int u = 0; u < k; u++) {
     c.cap_u[u] = bucket_size(g, p.qlab[u]);
     hits = std::max(hits, c.cap_u[u]);
     const uint64_t nc = (uint64_t)std::max(pattern_edges_between(p, u, p.down[u]),
                                            pattern_edges_between(p, u, p.up[u]));
+    cons = std::max(cons, nc);
     items = std::max(items, c.cap_u[u] * std::max<uint64_t>(nc, 1));
   }
+  c.hit_words = hits / 32 + 1;
+  c.hit_cons = cons;
+  c.hit_region = cons * c.hit_words * 8;  // hit bytes (32 * hit_words per constraint) or bitmaps
   c.cap_f = k > 2 ? cap_f : 1;
   items = std::max(items, c.cap_f);
   c.pcap = items + 1;
@@ -805,7 +814,6 @@ static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t
     if (p.is_parent[u]) b += align_up(sizeof(int32_t) * (size_t)g->n);
   b += 2 * align_up(4 * ((size_t)g->n / 32 + 1)) * k;                  // membership bitmaps
   for (int u = 0; u < k; u++) b += 2 * align_up(4 * c.cap_u[u]);       // candidate lists
-  b += align_up(4 * c.hits);
   b += align_up(8 * c.pcap);
   for (int u = 0; u < k; u++)
     if (u != p.root) b += 3 * align_up(4 * c.cap_u[p.parent[u]]);    // CPI list heads
@@ -837,7 +845,6 @@ static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const J
     m.cand[u][0] = (int32_t*)take(4 * c.cap_u[u]);
     m.cand[u][1] = (int32_t*)take(4 * c.cap_u[u]);
   }
-  m.hits = (uint32_t*)take(4 * c.hits);
   m.P = (uint64_t*)take(8 * c.pcap);
   for (int u = 0; u < k; u++) {
     m.cpi_beg[u] = m.cpi_len[u] = m.cpi_cur[u] = nullptr;
@@ -994,6 +1001,7 @@ struct Launch {
   int njobs;
   int gx_scan, gx_work, gx_item, gx_clear;
   bool scan, last_any, inner_any;
+  bool row_scan = false;  // filter: some job's pull needs the (item, constraint) row scan
 };
 
 // Builds every record of the CPI construction and the fast enumeration of
@@ -1028,6 +1036,8 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       // top-down items: the whole bucket
       make_direct(g, p, u, bs, f);
       f.hits = J.mem.hits;
+      f.hit_words = J.caps.hit_words;
+      f.hitmode = 1;  // top-down: few items meet a constraint
       f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       J.cur[u] = 0;
       f.out = J.mem.cand[u][0];
@@ -1036,7 +1046,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.bits = J.mem.bits[u][0];
       f.nwords = (uint64_t)g->n / 32 + 1;
       items = std::max(items, bs);
-      item_ch += chunks_of(bs);
+      item_ch += f.ncons ? (bs + 32ull * BS - 1) / (32ull * BS) : chunks_of(bs);
       pairs = std::max(pairs, bs * (uint64_t)std::max(f.ncons, 1));
       for (int q = 0; q < f.ncons; q++) pull_ub += chunks_of(rows_ub(g, p.qlab[u], f.cons[q].dir));
       any_cons |= f.ncons > 0;
@@ -1048,7 +1058,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
   for (int j = maxk - 1; j >= 0; j--) {
     std::vector<FilterJob> F(nj);
     uint64_t items = 1, pull_ub = 0, pairs = 1, item_ch = 0;  // *_ub, *_ch: chunks over all jobs
-    bool any = false;
+    bool any = false, row_scan = false;
     const uint32_t ep = next_epoch(c);
     for (int x = 0; x < nj; x++) {
       Job& J = jobs[x];
@@ -1072,6 +1082,8 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
         f.cap = J.caps.cap_u[u];
       }
       f.hits = J.mem.hits;
+      f.hit_words = J.caps.hit_words;
+      f.hitmode = 0;  // bottom-up: most current members meet their constraints
       f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       J.cur[u] ^= 1;
       f.out = J.mem.cand[u][J.cur[u]];
@@ -1081,13 +1093,14 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.nwords = (uint64_t)g->n / 32 + 1;
       items = std::max(items, f.cap);
       item_ch += chunks_of(f.cap);
+      row_scan |= !f.direct && f.ncons > 0;
       pairs = std::max(pairs, f.cap * (uint64_t)f.ncons);
       for (int q = 0; q < f.ncons; q++) pull_ub += chunks_of(rows_ub(g, p.qlab[u], f.cons[q].dir));
       any = true;
     }
     if (any)
       L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), flat_grid(item_ch),
-                         gx_for((uint64_t)g->n / 32 + 1, nj, 64), true, false, false});
+                         gx_for((uint64_t)g->n / 32 + 1, nj, 64), true, false, false, row_scan});
   }
   // CPI adjacency lists per spanning-tree edge, in BFS order
   for (int j = 1; j < maxk; j++) {
@@ -1319,7 +1332,7 @@ static void run_launches(Ctx& c, const std::vector<Launch>& L) {
       case 0: {
         auto* r = (const FilterJob*)(base + l.off);
         if (l.scan) {
-          c.tm.run(K_SCAN, [&] { filter_scan(c.st, g, r, l.njobs, l.gx_scan); });
+          if (l.row_scan) c.tm.run(K_SCAN, [&] { filter_scan(c.st, g, r, l.njobs, l.gx_scan); });
           c.tm.run(K_PULL, [&] { filter_pull(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_PULL)); });
         }
         c.tm.run(K_OTHER, [&] { filter_clear(c.st, r, l.njobs, l.gx_clear); });
@@ -1405,8 +1418,23 @@ static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
   const size_t total = ctl_b + ts_b + res_b + body;
   ensure_arena(ws, total);
   uint8_t* p = ws->arena + ctl_b + ts_b + res_b;
+  // hit bitmaps live outside the arena, in a pool that every compaction leaves
+  // zeroed, so no step clears them
+  size_t hw = 0;
+  for (auto& J : jobs) hw += (J.caps.hit_region + 63) / 64 * 64;
+  if (ws->hitpool_words < hw) {
+    dfree(ws->hitpool);
+    ws->hitpool = nullptr;
+    ws->hitpool_words = 0;
+    ws->hitpool = dalloc<uint32_t>(hw);
+    ws->hitpool_words = hw;
+    fill_u32(c.st, ws->hitpool, 0u, hw);
+  }
+  size_t hoff = 0;
   for (size_t x = 0; x < nj; x++) {
     Job& J = jobs[x];
+    J.mem.hits = ws->hitpool + hoff;
+    hoff += (J.caps.hit_region + 63) / 64 * 64;
     J.mem.ctl = (uint64_t*)ws->arena + CTL_WORDS * x;
     J.mem.tstate = (uint64_t*)(ws->arena + ctl_b) + tiles * x;
     J.mem.res = (int32_t*)(ws->arena + ctl_b + ts_b) + (size_t)std::max(c.K, 1) * MAXK * x;
@@ -1923,6 +1951,9 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
   try {
     const int64_t budget = o.mem_budget_bytes ? o.mem_budget_bytes : default_budget();
     ws = acquire_ws(g, budget);
+    if (ws->hitpool_dirty && ws->hitpool)  // an earlier call stopped midway
+      fill_u32((hipStream_t)o.hip_stream, ws->hitpool, 0u, ws->hitpool_words);
+    ws->hitpool_dirty = true;
     if (ws->cpi_cap == 0) {
       ws->cpi_cap = (uint64_t)std::max<int64_t>(1 << 20, std::min<int64_t>(budget / 16, int64_t(1) << 30) / 4);
       ws->cpi_arena = dalloc<int32_t>(ws->cpi_cap);
@@ -2082,6 +2113,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       stats->wall_ms =
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
+    ws->hitpool_dirty = false;
     release_ws(g, ws);
     return rc;
   } catch (const GfdError& e) {

@@ -145,7 +145,15 @@ struct FilterJob {
   uint32_t base;
   const uint32_t* keep;  // if set, only members of this bitmap may be kept
   PullC cons[MAXCONS];
-  uint32_t* hits;        // [cap], bit c set when constraint c is met
+  // constraint hits, zero at rest (the compaction clears every non-zero word
+  // it reads).  hitmode 1: one bitmap per constraint over the item indices,
+  // bit i of hits[c * hit_words + i / 32] set when item i meets constraint c
+  // (compact, set by atomics: for sparse hits); hitmode 0: one byte per
+  // constraint and item, byte c * 32 * hit_words + i of hits set to 1 by a
+  // plain store (no atomics, no line fetch: for dense hits).
+  uint32_t* hits;
+  uint64_t hit_words;
+  int32_t hitmode;
   JobScan sc;            // over (constraint, item) pairs
   int32_t* out;          // the new C(u): list, count (atomic cursor), positions, bits
   uint64_t* d_out_n;

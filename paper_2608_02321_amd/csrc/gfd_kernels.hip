@@ -574,25 +574,18 @@ __device__ __forceinline__ bool degree_ok(const DevGraph& g, const FilterJob& J,
   return true;
 }
 
-// Row lengths of (item, constraint) pairs, item-major, and cleared hit masks.
-// A direct job needs no scan (its rows are contiguous): only the clearing.
+// Row lengths of (item, constraint) pairs, item-major.  A direct job needs no
+// scan: its rows are contiguous.
 __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob* __restrict__ jobs) {
   const FilterJob& J = jobs[blockIdx.y];
-  if (!J.active || J.ncons == 0) return;
+  if (!J.active || J.ncons == 0 || J.direct) return;
   const uint64_t N = filter_items(J);
-  if (J.direct) {
-    for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < N;
-         i += (uint64_t)gridDim.x * BS)
-      J.hits[i] = 0;
-    return;
-  }
   const uint32_t nc = (uint32_t)J.ncons;
   unsigned long long by = 0;
   job_scan(N * nc, [&](uint64_t q) -> uint32_t {
     const uint64_t i = q / nc;
     const uint32_t c = (uint32_t)(q - i * nc);
     const int32_t v = filter_item(J, i);
-    if (c == 0) J.hits[i] = 0;
     if (!degree_ok(g, J, i, v, by)) return 0u;
     const uint32_t* off = J.cons[c].dir ? g.in_off : g.out_off;
     return off[v + 1] - off[v];
@@ -626,22 +619,66 @@ __device__ __forceinline__ uint64_t direct_span(const DevGraph& g, const FilterJ
   return (uint64_t)(P[N] - P[0]);
 }
 
-// Constraint bits met by one thread's run of positions on the same item.  A
-// thread's positions are consecutive, so their items never decrease: the bits
-// are gathered while the item stays the same and written with one atomic when
-// it changes, instead of one atomic per matching entry.
-struct HitRun {
-  uint64_t item = ~0ull;
-  uint32_t mask = 0;
-  // Index map: the hit word of item t is hits[rows ? rows[t] : t].
-  __device__ void flush(uint32_t* hits, const uint32_t* rows = nullptr) {
-    if (mask) atomicOr(&hits[rows ? (uint64_t)rows[item] : item], mask);
-    mask = 0;
+// Hits found by one thread, gathered per bitmap word.  A thread's positions
+// are consecutive, so the words it sets (per bitmap) never decrease: it keeps
+// its two latest words and masks, writing an older one out when a third
+// appears.  At the end of a chunk (a point all lanes reach) the wave merges
+// equal words across lanes, which hold neighbouring positions, so one lane
+// per word issues the atomic instead of every lane that hit it.
+__device__ __forceinline__ void wave_or_flush(uint32_t* p, uint32_t m) {
+  // key of an empty slot: unique per lane, so it merges with nothing
+  const uint64_t key = (p && m) ? (uint64_t)p : ~(uint64_t)lane();
+  uint32_t acc = m;
+  for (int off = 1; off < WAVE; off <<= 1) {
+    const uint64_t k2 = __shfl_down(key, off);
+    const uint32_t m2 = __shfl_down(acc, off);
+    if ((int)lane() + off < WAVE && k2 == key) acc |= m2;
   }
-  __device__ void at(uint32_t* hits, uint64_t t, const uint32_t* rows = nullptr) {
-    if (t != item) {
-      flush(hits, rows);
-      item = t;
+  const uint64_t kp = __shfl_up(key, 1);
+  // the first lane of a run of equal words writes the run's bits (a lane that
+  // follows an empty slot may write bits already written: OR is idempotent)
+  if (p && m && (lane() == 0 || kp != key)) atomicOr(p, acc);
+}
+
+struct HitRun {
+  uint32_t* at[2] = {nullptr, nullptr};
+  uint32_t mask[2] = {0, 0};
+  // item t meets the constraint whose bitmap is hb
+  __device__ void set(uint32_t* hb, uint64_t t) {
+    uint32_t* w = hb + (t >> 5);
+    const uint32_t bit = 1u << (t & 31u);
+    if (w == at[1]) {
+      mask[1] |= bit;
+    } else if (w == at[0]) {
+      mask[0] |= bit;
+    } else {
+      if (at[0] && mask[0]) atomicOr(at[0], mask[0]);
+      at[0] = at[1];
+      mask[0] = mask[1];
+      at[1] = w;
+      mask[1] = bit;
+    }
+  }
+  // called by every lane of the wave
+  __device__ void flush_wave() {
+    wave_or_flush(at[0], mask[0]);
+    wave_or_flush(at[1], mask[1]);
+    at[0] = at[1] = nullptr;
+    mask[0] = mask[1] = 0;
+  }
+};
+
+// Hit bytes (hitmode 0): byte c * hit_bytes + i of hits is set to 1 by a
+// plain store, once per run of a thread's positions on one (constraint, item).
+__device__ __forceinline__ uint8_t* hit_bytes(const FilterJob& J, int c) {
+  return (uint8_t*)J.hits + (uint64_t)c * 32 * J.hit_words;
+}
+struct ItemRun {
+  uint8_t* last = nullptr;
+  __device__ void set(uint8_t* b) {
+    if (b != last) {
+      *b = 1;
+      last = b;
     }
   }
 };
@@ -678,95 +715,144 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const PullC& cs = J.cons[c];
       const uint64_t c0 = P[0] + r * LBS_CHUNK;
       const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
-      const uint32_t bit = 1u << c;
+      // the job's fields in registers: the hit stores below cannot make the
+      // compiler reload them
+      const bool bitmaps = J.hitmode != 0;
+      uint32_t* const hb = J.hits + (uint64_t)c * J.hit_words;
+      uint8_t* const hb8 = hit_bytes(J, c);
+      const CandSet w = cs.w;
+      const int32_t elab = cs.elab;
+      HitRun run;
+      ItemRun irun;
+      auto hit = [&](uint64_t item) {
+        if (bitmaps) run.set(hb, item);
+        else irun.set(hb8 + item);
+      };
       if (cs.blk) {  // only e-labelled entries; the block names each row's item
         const BlockArrays ba = block_arrays(g, cs.blk, cs.dir);
         const uint32_t* rows = ba.row + cs.rb;
         const int32_t* nbr = ba.nbr;
-        HitRun run;
         flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t s, uint64_t o, uint64_t x) {
           if (!valid) return;
           by += (o == 0 ? 8 : 0) + 4;  // per row: item and start; per entry: neighbour
-          run.at(J.hits, s, rows);
-          if (member(cs.w, nbr[x])) run.mask |= bit;
+          if (member(w, nbr[x])) hit(rows[s]);
         });
-        run.flush(J.hits, rows);
       } else {
         const Rows rw = direct_rows(g, J, cs.dir);
-        HitRun run;
         flat_chunk<true>(P, N, c0, c1, sh, [&](bool valid, uint64_t i, uint64_t o, uint64_t x) {
           if (!valid) return;
           // per entry: neighbour (+ label); the items' offsets stream once
-          by += (o == 0 ? 4 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
-          run.at(J.hits, i);
-          if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
-          if (member(cs.w, rw.nbr[x])) run.mask |= bit;
+          by += (o == 0 ? 4 : 0) + 4 + (elab != ANY ? 4 : 0);
+          if (elab != ANY && rw.lab[x] != elab) return;
+          if (member(w, rw.nbr[x])) hit(i);
         });
-        run.flush(J.hits);
       }
+      if (bitmaps) run.flush_wave();
     } else {
       const uint32_t nc = (uint32_t)J.ncons;
       const uint64_t NP = filter_items(J) * (uint64_t)nc;
       const uint64_t T = *J.sc.d_total;
       const uint64_t c0 = r * LBS_CHUNK;
       const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
+      const bool bitmaps = J.hitmode != 0;
+      uint32_t* const hits = J.hits;
+      const uint64_t hwords = J.hit_words;
+      const int32_t* const list = J.list;
       HitRun run;
+      ItemRun irun;
       flat_chunk<true>(J.sc.P, NP, c0, c1, sh, [&](bool valid, uint64_t q, uint64_t o, uint64_t) {
         if (!valid) return;
         const uint64_t i = q / nc;
         const uint32_t c = (uint32_t)(q - i * nc);
         const PullC& cs = J.cons[c];
-        const int32_t v = filter_item(J, i);
+        const int32_t v = list ? list[i] : (int32_t)i;
         const Rows rw = plain_rows(g, cs.dir);
         const uint32_t x = rw.off[v] + (uint32_t)o;
         // per row: item and its two offsets; per entry: neighbour (+ label)
         by += (o == 0 ? 12 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
-        run.at(J.hits, i);
         if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
-        if (member(cs.w, rw.nbr[x])) run.mask |= 1u << c;
+        if (!member(cs.w, rw.nbr[x])) return;
+        if (bitmaps) run.set(hits + (uint64_t)c * hwords, i);
+        else irun.set((uint8_t*)hits + (uint64_t)c * 32 * hwords + i);
       });
-      run.flush(J.hits);
+      if (bitmaps) run.flush_wave();
     }
   }
   if (bytes) block_add(bytes, by);
 }
 
 // Items meeting the degree filter and every constraint join C(u) (a set: no
-// fixed order).  The items of all jobs share one chunk space; thread t of a
-// block takes 8 consecutive items of the chunk, the block reserves the chunk's
-// output with one atomic add, and runs of members in one bitmap word are set
-// with one atomic.
+// fixed order).  The items of all jobs share one chunk space: a chunk is
+// LBS_CHUNK items of a job with hit bytes (8 consecutive items per thread),
+// or 32 * BS items of a job with hit bitmaps (one 32-item word per thread,
+// whose constraint words, ANDed, pick the items to examine, so items no
+// constraint touched cost a bit, not a load).  Hit bytes and words are
+// cleared as they are read.  A block reserves its output with one atomic add, and runs of
+// members in one bitmap word are set with one atomic.
+__device__ __forceinline__ bool filter_bitmaps(const FilterJob& J) {
+  return J.hitmode && J.ncons;
+}
+__device__ __forceinline__ uint64_t compact_chunk_items(const FilterJob& J) {
+  return filter_bitmaps(J) ? 32ull * BS : LBS_CHUNK;
+}
+
 __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
                                                        const FilterJob* __restrict__ jobs,
                                                        int njobs, unsigned long long* bytes) {
   constexpr int IPT = (int)(LBS_CHUNK / BS);
+  static_assert(IPT == 8, "hit bytes are read as one 8-byte word per thread and constraint");
   __shared__ ChunkMap cm;
   __shared__ unsigned long long s_base;
   chunk_map_build(cm, njobs, [&](int j) -> uint64_t {
-    return jobs[j].active ? chunks_of(filter_items(jobs[j])) : 0ull;
+    const FilterJob& J = jobs[j];
+    if (!J.active) return 0ull;
+    const uint64_t per = compact_chunk_items(J);
+    return (filter_items(J) + per - 1) / per;
   });
   unsigned long long by = 0;
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
-    const int jb = chunk_job(cm, njobs, ch);
+    const int jb = __builtin_amdgcn_readfirstlane(chunk_job(cm, njobs, ch));
     const FilterJob& J = jobs[jb];
     const uint64_t N = filter_items(J);
-    const uint32_t full = J.ncons ? (J.ncons >= 32 ? ~0u : ((1u << J.ncons) - 1)) : 0u;
-    const uint64_t i0 = (ch - cm.cs[jb]) * LBS_CHUNK + (uint64_t)threadIdx.x * IPT;
-    uint32_t keep = 0;  // bit r: item i0 + r joins
-    int32_t vv[IPT];
+    const bool bm = filter_bitmaps(J);
+    // candidates of this thread: items i0 + r for the set bits r of m
+    uint64_t i0;
+    uint32_t m = 0;
+    if (bm) {
+      const uint64_t wi = (ch - cm.cs[jb]) * BS + threadIdx.x;
+      i0 = 32 * wi;
+      if (i0 < N) m = N - i0 >= 32 ? ~0u : ((1u << (N - i0)) - 1u);
+      if (m)
+        for (int c = 0; c < J.ncons; c++) {
+          uint32_t* hw = J.hits + (uint64_t)c * J.hit_words + wi;
+          const uint32_t x = *hw;
+          by += 4;
+          if (x) *hw = 0;
+          m &= x;
+        }
+    } else {
+      // IPT == 8 items: one aligned 8-byte word of hit bytes per constraint
+      i0 = (ch - cm.cs[jb]) * LBS_CHUNK + (uint64_t)threadIdx.x * IPT;
+      if (i0 < N) m = N - i0 >= IPT ? (1u << IPT) - 1u : ((1u << (N - i0)) - 1u);
+      if (m)
+        for (int c = 0; c < J.ncons; c++) {
+          uint64_t* hw = (uint64_t*)(hit_bytes(J, c) + i0);
+          const uint64_t x = *hw;
+          by += 8;
+          if (x) *hw = 0;
+          uint32_t nz = 0;
 #pragma unroll
-    for (int r = 0; r < IPT; r++) {
+          for (int r = 0; r < IPT; r++) nz |= (((x >> (8 * r)) & 0xFFu) != 0 ? 1u : 0u) << r;
+          m &= nz;
+        }
+    }
+    uint32_t keep = 0;  // bit r: item i0 + r joins
+    for (uint32_t q = m; q; q &= q - 1) {
+      const int r = __ffs(q) - 1;
       const uint64_t i = i0 + r;
-      vv[r] = 0;
-      if (i >= N) continue;
       const int32_t v = filter_item(J, i);
-      vv[r] = v;
       by += J.list ? 4 : 0;
       bool ok = !J.keep || ((J.keep[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u);
-      if (ok && J.ncons) {  // the hit mask first: most items fail it
-        by += 4;
-        ok = J.hits[i] == full;
-      }
       ok = ok && degree_ok(g, J, i, v, by);
       keep |= (ok ? 1u : 0u) << r;
     }
@@ -777,10 +863,9 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
     __syncthreads();
     uint64_t idx = s_base + rank;
     uint32_t word = 0xFFFFFFFFu, mask = 0;
-#pragma unroll
-    for (int r = 0; r < IPT; r++) {
-      if (!((keep >> r) & 1u)) continue;
-      const int32_t v = vv[r];
+    for (uint32_t q = keep; q; q &= q - 1) {
+      const int r = __ffs(q) - 1;
+      const int32_t v = filter_item(J, i0 + r);
       J.out[idx] = v;
       if (J.pos) J.pos[v] = (int32_t)idx;
       idx++;
