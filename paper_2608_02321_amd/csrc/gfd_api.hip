@@ -1002,6 +1002,7 @@ struct Launch {
   int gx_scan, gx_work, gx_item, gx_clear;
   bool scan, last_any, inner_any;
   bool row_scan = false;  // filter: some job's pull needs the (item, constraint) row scan
+  bool hit_bitmaps = false;  // filter: the jobs record hits in bitmaps (top-down steps)
 };
 
 // Builds every record of the CPI construction and the fast enumeration of
@@ -1052,7 +1053,8 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       any_cons |= f.ncons > 0;
     }
     L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), flat_grid(item_ch),
-                       gx_for((uint64_t)g->n / 32 + 1, nj, 64), any_cons, false, false});
+                       gx_for((uint64_t)g->n / 32 + 1, nj, 64), any_cons, false, false, false,
+                       true});
   }
   // bottom-up, reverse BFS order: drop dead ends
   for (int j = maxk - 1; j >= 0; j--) {
@@ -1333,7 +1335,9 @@ static void run_launches(Ctx& c, const std::vector<Launch>& L) {
         auto* r = (const FilterJob*)(base + l.off);
         if (l.scan) {
           if (l.row_scan) c.tm.run(K_SCAN, [&] { filter_scan(c.st, g, r, l.njobs, l.gx_scan); });
-          c.tm.run(K_PULL, [&] { filter_pull(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_PULL)); });
+          c.tm.run(K_PULL, [&] {
+            filter_pull(c.st, g, r, l.njobs, l.gx_work, l.hit_bitmaps, cls_bytes(c, K_PULL));
+          });
         }
         c.tm.run(K_OTHER, [&] { filter_clear(c.st, r, l.njobs, l.gx_clear); });
         c.tm.run(K_FILTER,

@@ -292,8 +292,10 @@ struct SelJob {
 // blocks shared by all jobs.  `bytes`, when not null, accumulates the
 // algorithmic bytes the kernel touched.
 void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
+// bitmaps: the launch's jobs record hits in bitmaps (hitmode 1) rather than
+// bytes; every job of one launch uses the same form
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
-                 unsigned long long* bytes);
+                 bool bitmaps, unsigned long long* bytes);
 void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                     unsigned long long* bytes);
 // zero the output bitmap of every active job

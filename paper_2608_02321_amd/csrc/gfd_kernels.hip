@@ -684,6 +684,9 @@ struct ItemRun {
 };
 
 // One thread per adjacency entry: mark constraint c of item i as met.
+// BITMAPS: every job of the launch records hits in bitmaps (hitmode 1), else
+// in bytes (hitmode 0); one instantiation per form keeps each lean.
+template <bool BITMAPS>
 __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob* __restrict__ jobs,
                                                     int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
@@ -717,7 +720,7 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const uint64_t c1 = c0 + LBS_CHUNK < P[0] + T ? c0 + LBS_CHUNK : P[0] + T;
       // the job's fields in registers: the hit stores below cannot make the
       // compiler reload them
-      const bool bitmaps = J.hitmode != 0;
+      constexpr bool bitmaps = BITMAPS;
       uint32_t* const hb = J.hits + (uint64_t)c * J.hit_words;
       uint8_t* const hb8 = hit_bytes(J, c);
       const CandSet w = cs.w;
@@ -725,7 +728,7 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       HitRun run;
       ItemRun irun;
       auto hit = [&](uint64_t item) {
-        if (bitmaps) run.set(hb, item);
+        if constexpr (bitmaps) run.set(hb, item);
         else irun.set(hb8 + item);
       };
       if (cs.blk) {  // only e-labelled entries; the block names each row's item
@@ -747,14 +750,14 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
           if (member(w, rw.nbr[x])) hit(i);
         });
       }
-      if (bitmaps) run.flush_wave();
+      if constexpr (bitmaps) run.flush_wave();
     } else {
       const uint32_t nc = (uint32_t)J.ncons;
       const uint64_t NP = filter_items(J) * (uint64_t)nc;
       const uint64_t T = *J.sc.d_total;
       const uint64_t c0 = r * LBS_CHUNK;
       const uint64_t c1 = c0 + LBS_CHUNK < T ? c0 + LBS_CHUNK : T;
-      const bool bitmaps = J.hitmode != 0;
+      constexpr bool bitmaps = BITMAPS;
       uint32_t* const hits = J.hits;
       const uint64_t hwords = J.hit_words;
       const int32_t* const list = J.list;
@@ -772,10 +775,10 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
         by += (o == 0 ? 12 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
         if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
         if (!member(cs.w, rw.nbr[x])) return;
-        if (bitmaps) run.set(hits + (uint64_t)c * hwords, i);
+        if constexpr (bitmaps) run.set(hits + (uint64_t)c * hwords, i);
         else irun.set((uint8_t*)hits + (uint64_t)c * 32 * hwords + i);
       });
-      if (bitmaps) run.flush_wave();
+      if constexpr (bitmaps) run.flush_wave();
     }
   }
   if (bytes) block_add(bytes, by);
@@ -896,8 +899,11 @@ void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int n
   hipLaunchKernelGGL(k_filter_scan, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
 }
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
-                 unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_filter_pull, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+                 bool bitmaps, unsigned long long* bytes) {
+  if (bitmaps)
+    hipLaunchKernelGGL(k_filter_pull<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  else
+    hipLaunchKernelGGL(k_filter_pull<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                     unsigned long long* bytes) {
