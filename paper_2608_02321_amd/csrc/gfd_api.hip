@@ -1038,7 +1038,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       make_direct(g, p, u, bs, f);
       f.hits = J.mem.hits;
       f.hit_words = J.caps.hit_words;
-      f.hitmode = 1;  // top-down: few items meet a constraint
+      f.hitmode = 1;  // top-down: few items meet a constraint (settled per launch below)
       f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       J.cur[u] = 0;
       f.out = J.mem.cand[u][0];
@@ -1047,14 +1047,23 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
       f.bits = J.mem.bits[u][0];
       f.nwords = (uint64_t)g->n / 32 + 1;
       items = std::max(items, bs);
-      item_ch += f.ncons ? (bs + 32ull * BS - 1) / (32ull * BS) : chunks_of(bs);
       pairs = std::max(pairs, bs * (uint64_t)std::max(f.ncons, 1));
       for (int q = 0; q < f.ncons; q++) pull_ub += chunks_of(rows_ub(g, p.qlab[u], f.cons[q].dir));
       any_cons |= f.ncons > 0;
     }
+    // bitmaps when every active job has a constraint (all but the roots' step)
+    bool all_cons = true;
+    for (const FilterJob& f : F) all_cons &= !f.active || f.ncons > 0;
+    item_ch = 0;
+    for (int x = 0; x < nj; x++) {
+      FilterJob& f = F[x];
+      f.hitmode = all_cons ? 1 : 0;
+      if (f.active)
+        item_ch += all_cons ? (f.n_host + 32ull * BS - 1) / (32ull * BS) : chunks_of(f.n_host);
+    }
     L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), flat_grid(item_ch),
                        gx_for((uint64_t)g->n / 32 + 1, nj, 64), any_cons, false, false, false,
-                       true});
+                       all_cons});
   }
   // bottom-up, reverse BFS order: drop dead ends
   for (int j = maxk - 1; j >= 0; j--) {
@@ -1341,7 +1350,7 @@ static void run_launches(Ctx& c, const std::vector<Launch>& L) {
         }
         c.tm.run(K_OTHER, [&] { filter_clear(c.st, r, l.njobs, l.gx_clear); });
         c.tm.run(K_FILTER,
-                 [&] { filter_compact(c.st, g, r, l.njobs, l.gx_item, cls_bytes(c, K_FILTER)); });
+                 [&] { filter_compact(c.st, g, r, l.njobs, l.gx_item, l.hit_bitmaps, cls_bytes(c, K_FILTER)); });
         break;
       }
       case 1: {

@@ -297,7 +297,7 @@ void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int n
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                  bool bitmaps, unsigned long long* bytes);
 void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
-                    unsigned long long* bytes);
+                    bool bitmaps, unsigned long long* bytes);
 // zero the output bitmap of every active job
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx);
 void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);

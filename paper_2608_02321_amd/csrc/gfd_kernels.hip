@@ -786,19 +786,14 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
 
 // Items meeting the degree filter and every constraint join C(u) (a set: no
 // fixed order).  The items of all jobs share one chunk space: a chunk is
-// LBS_CHUNK items of a job with hit bytes (8 consecutive items per thread),
-// or 32 * BS items of a job with hit bitmaps (one 32-item word per thread,
+// LBS_CHUNK items with hit bytes (8 consecutive items per thread), or 32 * BS
+// items when the launch's jobs have hit bitmaps (one 32-item word per thread,
 // whose constraint words, ANDed, pick the items to examine, so items no
 // constraint touched cost a bit, not a load).  Hit bytes and words are
 // cleared as they are read.  A block reserves its output with one atomic add, and runs of
 // members in one bitmap word are set with one atomic.
-__device__ __forceinline__ bool filter_bitmaps(const FilterJob& J) {
-  return J.hitmode && J.ncons;
-}
-__device__ __forceinline__ uint64_t compact_chunk_items(const FilterJob& J) {
-  return filter_bitmaps(J) ? 32ull * BS : LBS_CHUNK;
-}
-
+// BITMAPS: every job of the launch has hit bitmaps (hitmode 1).
+template <bool BITMAPS>
 __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
                                                        const FilterJob* __restrict__ jobs,
                                                        int njobs, unsigned long long* bytes) {
@@ -809,7 +804,7 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
   chunk_map_build(cm, njobs, [&](int j) -> uint64_t {
     const FilterJob& J = jobs[j];
     if (!J.active) return 0ull;
-    const uint64_t per = compact_chunk_items(J);
+    constexpr uint64_t per = BITMAPS ? 32ull * BS : LBS_CHUNK;
     return (filter_items(J) + per - 1) / per;
   });
   unsigned long long by = 0;
@@ -817,11 +812,10 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
     const int jb = __builtin_amdgcn_readfirstlane(chunk_job(cm, njobs, ch));
     const FilterJob& J = jobs[jb];
     const uint64_t N = filter_items(J);
-    const bool bm = filter_bitmaps(J);
     // candidates of this thread: items i0 + r for the set bits r of m
     uint64_t i0;
     uint32_t m = 0;
-    if (bm) {
+    if constexpr (BITMAPS) {
       const uint64_t wi = (ch - cm.cs[jb]) * BS + threadIdx.x;
       i0 = 32 * wi;
       if (i0 < N) m = N - i0 >= 32 ? ~0u : ((1u << (N - i0)) - 1u);
@@ -906,8 +900,11 @@ void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int n
     hipLaunchKernelGGL(k_filter_pull<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
-                    unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_filter_compact, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+                    bool bitmaps, unsigned long long* bytes) {
+  if (bitmaps)
+    hipLaunchKernelGGL(k_filter_compact<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  else
+    hipLaunchKernelGGL(k_filter_compact<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_filter_clear, dim3(gx, njobs), dim3(BS), 0, st, jobs);
