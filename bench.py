@@ -38,11 +38,11 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "9eaff960c6300a4519420243dcd16919563c965c05afd9531e518e70b107f901",
+    "sources_sha256": "1dcfb0a4f98748bf5ff3aaab9a1ea8646c9992e64f1fdcf6d021218f7e708e6e",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true>
-    # (1,483.46 MB read + 551.04 MB written) per dispatch, calibrated
-    "bytes_per_launch": 2.0345e9,
+    # (1,147.95 MB read + 11.98 MB written) per dispatch, calibrated
+    "bytes_per_launch": 1.15993e9,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
