@@ -27,6 +27,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <functional>
 #include <vector>
 
 #include "gfd.h"
@@ -1005,9 +1006,21 @@ struct Launch {
   bool hit_bitmaps = false;  // filter: the jobs record hits in bitmaps (top-down steps)
 };
 
+// The launches of a batch in order.  When on_add is set (the fast path), it
+// runs as each launch is appended, so the GPU starts on the first filter step
+// while the host still builds the records of later ones.
+struct LaunchList {
+  std::vector<Launch> v;
+  std::function<void(const Launch&)> on_add;
+  void push_back(const Launch& l) {
+    v.push_back(l);
+    if (on_add) on_add(l);
+  }
+};
+
 // Builds every record of the CPI construction and the fast enumeration of
 // `jobs` (Section IV-B steps 1 and 2) into `R` and the launch list `L`.
-static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Launch>& L,
+static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
                        bool fast_enum) {
   const gfd_graph* g = c.g;
   const int nj = (int)jobs.size();
@@ -1335,10 +1348,10 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, std::vector<Laun
   }
 }
 
-static void run_launches(Ctx& c, const std::vector<Launch>& L) {
+static void run_launch(Ctx& c, const Launch& l) {
   const DevGraph& g = c.g->dg;
   uint8_t* base = c.ws->jobrec;
-  for (const Launch& l : L) {
+  {
     switch (l.kind) {
       case 0: {
         auto* r = (const FilterJob*)(base + l.off);
@@ -1390,10 +1403,48 @@ static void run_launches(Ctx& c, const std::vector<Launch>& L) {
   }
 }
 
+static void run_launches(Ctx& c, const std::vector<Launch>& L) {
+  for (const Launch& l : L) run_launch(c, l);
+}
+
 static void upload_recs(Ctx& c, const Recs& R) {
   ensure_recs(c.ws, std::max<size_t>(R.blob.size(), 256));
   std::memcpy(c.ws->hjobrec, R.blob.data(), R.blob.size());
   HIPCHK(hipMemcpyAsync(c.ws->jobrec, c.ws->hjobrec, R.blob.size(), hipMemcpyHostToDevice, c.st));
+}
+
+// Upper bound of the record bytes plan_batch writes for a batch: at most 2k
+// filter steps, k CPI edges, k enumeration launches of each form, the leaf
+// counts and the top-K records, each array aligned.
+static size_t recs_bound(const std::vector<Job>& jobs) {
+  int maxk = 1;
+  for (const Job& J : jobs) maxk = std::max(maxk, J.plan.k);
+  const size_t nj = jobs.size();
+  const size_t per = 2 * (size_t)maxk * sizeof(FilterJob) + (size_t)maxk * sizeof(CpiJob) +
+                     2 * (size_t)maxk * sizeof(ExtJob) + sizeof(LeafJob) + sizeof(TopkJob);
+  return nj * per + 256 * (6 * (size_t)maxk + 4);
+}
+
+// Records and launches of a batch, each launch enqueued as soon as its records
+// are built and uploaded (to the same offsets of the device buffer, from
+// disjoint parts of the pinned staging).
+static void plan_and_run_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L) {
+  Workspace* ws = c.ws;
+  ensure_recs(ws, std::max<size_t>(recs_bound(jobs), 256));
+  size_t up = 0;
+  L.on_add = [&](const Launch& l) {
+    const size_t end = R.blob.size();
+    if (end > ws->jobrec_bytes) throw GfdError{GFD_EDEVICE, "internal: record bound exceeded"};
+    if (end > up) {
+      std::memcpy(ws->hjobrec + up, R.blob.data() + up, end - up);
+      HIPCHK(hipMemcpyAsync(ws->jobrec + up, ws->hjobrec + up, end - up, hipMemcpyHostToDevice,
+                            c.st));
+      up = end;
+    }
+    run_launch(c, l);
+  };
+  plan_batch(c, jobs, R, L, true);
+  L.on_add = nullptr;
 }
 
 // Arena of a batch: [control blocks][tile states][results][job regions].
@@ -1698,10 +1749,10 @@ static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
   layout_batch(c, one);
   Job& B = one[0];
   Recs R;
-  std::vector<Launch> L;
+  LaunchList L;
   plan_batch(c, one, R, L, false);
   upload_recs(c, R);
-  run_launches(c, L);
+  run_launches(c, L.v);
   HIPCHK(hipMemcpyAsync(ws->hctl, B.mem.ctl, sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
   HIPCHK(hipStreamSynchronize(c.st));
   if (ws->hctl[CTL_FLAGS] & 4u)
@@ -2013,7 +2064,11 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     }
     const bool force_bounded = (o.flags & GFD_FLAG_FORCE_CHUNKED) != 0;
     std::vector<uint64_t> H((size_t)num_specs * CTL_WORDS);
-    std::vector<int32_t> hres((size_t)num_specs * std::max(K, 1) * MAXK);
+    // first K of GFD i, straight into results[i].violations (counts come
+    // from the control words)
+    auto reported = [&](int32_t i) -> uint64_t {
+      return std::min<uint64_t>((uint64_t)K, H[(size_t)i * CTL_WORDS + CTL_VIOL]);
+    };
     uint64_t cpi_entries = 0;
     for (const auto& bidx : batches) {
       std::vector<Job> jobs;
@@ -2022,10 +2077,8 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       std::vector<char> redo(jobs.size(), force_bounded ? 1 : 0);
       if (!force_bounded) {
         Recs R;
-        std::vector<Launch> L;
-        plan_batch(c, jobs, R, L, true);
-        upload_recs(c, R);
-        run_launches(c, L);
+        LaunchList L;
+        plan_and_run_batch(c, jobs, R, L);
         HIPCHK(hipMemcpyAsync(ws->hctl, jobs[0].mem.ctl, sizeof(uint64_t) * CTL_WORDS * jobs.size(),
                               hipMemcpyDeviceToHost, c.st));
         unsigned long long cursor = 0;
@@ -2066,9 +2119,13 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
         HIPCHK(hipStreamSynchronize(c.st));
         if (K > 0)
           for (size_t x = 0; x < jobs.size(); x++)
-            if (!redo[x])
-              std::memcpy(hres.data() + (size_t)jobs[x].spec * K * MAXK, ws->hres + (size_t)x * K * MAXK,
-                          sizeof(int32_t) * K * jobs[x].plan.k);
+            if (!redo[x]) {
+              const int32_t i = jobs[x].spec;
+              const uint64_t n = reported(i);
+              if (n)
+                std::memcpy(results[i].violations, ws->hres + (size_t)x * K * MAXK,
+                            sizeof(int32_t) * n * jobs[x].plan.k);
+            }
         if (stats)
           for (size_t x = 0; x < jobs.size(); x++) {
             if (redo[x]) continue;
@@ -2088,10 +2145,14 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
         run_bounded(c, jobs[x], vbig);
         HIPCHK(hipMemcpyAsync(&H[(size_t)jobs[x].spec * CTL_WORDS], jobs[x].mem.ctl,
                               sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
-        if (K > 0)
-          HIPCHK(hipMemcpyAsync(hres.data() + (size_t)jobs[x].spec * K * MAXK, jobs[x].mem.res,
-                                sizeof(int32_t) * K * jobs[x].plan.k, hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipStreamSynchronize(c.st));
+        const int32_t i = jobs[x].spec;
+        const uint64_t n = reported(i);
+        if (K > 0 && n) {
+          HIPCHK(hipMemcpyAsync(results[i].violations, jobs[x].mem.res,
+                                sizeof(int32_t) * n * jobs[x].plan.k, hipMemcpyDeviceToHost, c.st));
+          HIPCHK(hipStreamSynchronize(c.st));
+        }
       }
     }
     uint32_t err = 0;
@@ -2106,10 +2167,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       r.match_fp = count_only ? 0 : h[CTL_MFP];  // not computed for postponed leaves
       r.violation_fp = count_only ? 0 : h[CTL_VFP];
       r.satisfied = r.violation_count == 0;
-      r.num_reported = (int32_t)std::min<uint64_t>((uint64_t)K, r.violation_count);
-      if (K > 0 && r.num_reported)
-        std::memcpy(r.violations, hres.data() + (size_t)i * K * MAXK,
-                    sizeof(int32_t) * r.num_reported * specs[i].num_vertices);
+      r.num_reported = (int32_t)reported(i);  // its tuples were copied with its batch
       if ((r.match_count >> 63) || (r.violation_count >> 63))
         rc = set_error(GFD_EOVERFLOW, "spec %d: counter passed 2^63", i);
     }
