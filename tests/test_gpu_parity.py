@@ -96,6 +96,26 @@ def test_random_medium(P, seed):
         _check(P, g, gfds, sem, K=100)
 
 
+def test_many_labels_without_label_triple_blocks(P):
+    """300 vertex labels and 200 edge labels give 300 * 200 * 300 > 2^24
+    (vertex label, edge label, far label) keys, so the loader builds only the
+    (vertex label, edge label) blocks and every pull and CPI edge reads those:
+    results equal the oracle's as with the finer blocks."""
+    rng = np.random.default_rng(77)
+    g = random_graph(77, 1500, 15000, n_vlabels=3, n_elabels=2, n_attrs=2, attr_values=4,
+                     absent_frac=0.1)
+    g.vlabel[0] = 299  # one vertex and one edge with high labels widen the key space
+    g.elabel[0] = 199
+    gfds = [random_gfd(7700 + j, int(rng.integers(2, 6)), n_vlabels=3, n_elabels=2, n_attrs=2,
+                       attr_values=4, wildcard_frac=0.15, extra_edge_frac=0.4)
+            for j in range(8)]
+    gh = P.load(g)
+    for sem in SEMS:
+        for batched in (False, True):
+            _check(P, g, gfds, sem, K=50, gh=gh, batched=batched)
+    gh.free()
+
+
 def test_chunked_paths_agree(P):
     """Tiny frontier / staging budgets force the chunked path and compaction."""
     g = random_graph(7, 300, 4000, n_vlabels=2, n_elabels=2, n_attrs=1, attr_values=3)
