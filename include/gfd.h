@@ -141,7 +141,8 @@ typedef struct {
   uint64_t attempts;          /* extension attempts over all enumeration levels */
   uint64_t partials;          /* partial matches written over all levels */
   uint64_t cpi_candidates;    /* sum of final candidate-set sizes */
-  uint64_t cpi_entries;       /* sum of CPI adjacency entries */
+  uint64_t cpi_entries;       /* CPI arena entries reserved: the rows of every tree
+                                 parent's candidates, which bound their lists */
   /* per kernel class: [0] candidate compaction, [1] candidate pull constraints,
    * [2] CPI adjacency, [3] enumeration (inner levels), [4] enumeration + literal
    * check (last level), [5] scans, [6] top-K selection, [7] other */

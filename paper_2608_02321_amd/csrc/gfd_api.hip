@@ -87,7 +87,7 @@ constexpr int CTL_WORDS = 64;
 enum {
   CTL_MATCH = 0, CTL_VIOL = 1, CTL_MFP = 2, CTL_VFP = 3, CTL_VCOUNT = 4, CTL_FLAGS = 5,
   CTL_NEEDSEL = 6, CTL_THRVALID = 7, CTL_LEVEL_N = 8 /* +i */, CTL_LEVEL_T = 16 /* +i */,
-  CTL_TOTAL = 24, CTL_OUTCOUNT = 25, CTL_TICKET = 26, CTL_CAND = 32 /* +2u+b */,
+  CTL_TOTAL = 24, CTL_OUTCOUNT = 25, CTL_TICKET = 26, CTL_CPIBASE = 27, CTL_CAND = 32 /* +2u+b */,
   CTL_THR = 48 /* 4 words = 8 int32 */
 };
 
@@ -757,7 +757,6 @@ struct JobMem {
   uint64_t* P;
   uint32_t* cpi_beg[MAXK];
   uint32_t* cpi_len[MAXK];
-  uint32_t* cpi_cur[MAXK];
   int32_t* cols[MAXK];
   uint32_t* begs;
   int32_t* vbuf;
@@ -817,7 +816,7 @@ static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t
   for (int u = 0; u < k; u++) b += 2 * align_up(4 * c.cap_u[u]);       // candidate lists
   b += align_up(8 * c.pcap);
   for (int u = 0; u < k; u++)
-    if (u != p.root) b += 3 * align_up(4 * c.cap_u[p.parent[u]]);    // CPI list heads
+    if (u != p.root) b += 2 * align_up(4 * c.cap_u[p.parent[u]]);    // CPI list heads
   for (int i = 2; i < k; i++) b += align_up(4ull * i * c.cap_f);      // frontier columns
   b += align_up(4 * c.begs);
   b += align_up(4 * c.vcap * k);
@@ -848,12 +847,11 @@ static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const J
   }
   m.P = (uint64_t*)take(8 * c.pcap);
   for (int u = 0; u < k; u++) {
-    m.cpi_beg[u] = m.cpi_len[u] = m.cpi_cur[u] = nullptr;
+    m.cpi_beg[u] = m.cpi_len[u] = nullptr;
     if (u == p.root) continue;
     const uint64_t cp = c.cap_u[p.parent[u]];
     m.cpi_beg[u] = (uint32_t*)take(4 * cp);
     m.cpi_len[u] = (uint32_t*)take(4 * cp);
-    m.cpi_cur[u] = (uint32_t*)take(4 * cp);
   }
   for (int i = 0; i < MAXK; i++) m.cols[i] = nullptr;
   for (int i = 2; i < k; i++) m.cols[i] = (int32_t*)take(4ull * i * c.cap_f);
@@ -1148,7 +1146,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       a.cap_p = J.caps.cap_u[q];
       a.beg = J.mem.cpi_beg[u];
       a.len = J.mem.cpi_len[u];
-      a.cur = J.mem.cpi_cur[u];
+      a.d_base = J.mem.ctl + CTL_CPIBASE;
       a.arena = c.ws->cpi_arena;
       a.arena_cursor = c.ws->misc;
       a.arena_cap = c.ws->cpi_cap;
@@ -1369,8 +1367,7 @@ static void run_launch(Ctx& c, const Launch& l) {
       case 1: {
         auto* r = (const CpiJob*)(base + l.off);
         c.tm.run(K_SCAN, [&] { cpi_scan(c.st, g, r, l.njobs, l.gx_scan); });
-        c.tm.run(K_CPI, [&] { cpi_count(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_CPI)); });
-        c.tm.run(K_CPI, [&] { cpi_alloc(c.st, g, r, l.njobs, l.gx_item); });
+        c.tm.run(K_OTHER, [&] { cpi_reserve(c.st, r, l.njobs); });
         c.tm.run(K_CPI, [&] { cpi_fill(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_CPI)); });
         break;
       }

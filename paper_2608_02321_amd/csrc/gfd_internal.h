@@ -173,11 +173,11 @@ struct CpiJob {
   uint64_t cap_p;
   uint32_t* beg;
   uint32_t* len;
-  uint32_t* cur;
   int32_t* arena;
   unsigned long long* arena_cursor;
   uint64_t arena_cap;
   uint32_t* flags;       // bit 2: arena overflow
+  uint64_t* d_base;      // the job's region of the arena (~0: out of arena)
   JobScan sc;            // over rows of C(p)
   // labelled p and prim: the edge-label block (p's bucket, prim) of direction
   // dir is rows [rb, re); bucket base position `base`
@@ -301,9 +301,7 @@ void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, in
 // zero the output bitmap of every active job
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx);
 void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
-void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
-               unsigned long long* bytes);
-void cpi_alloc(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
+void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs);
 void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
               unsigned long long* bytes);
 void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx);
