@@ -953,6 +953,13 @@ static int flat_grid(uint64_t chunks) {
   if (g >= (uint64_t)NXCD) g = std::min<uint64_t>((g + NXCD - 1) / NXCD * NXCD, FLAT_GRID_MAX);
   return (int)g;
 }
+// 1-D grid of a level scan whose njobs jobs have at most max_items sources
+// each: the blocks are shared among the jobs by their tiles.
+static int scan_grid(int njobs, uint64_t max_items) {
+  const uint64_t t = (max_items + SCAN_TILE - 1) / SCAN_TILE;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)std::max(njobs, 1) * std::max<uint64_t>(t, 1),
+                                                       FLAT_GRID_MAX));
+}
 static int gx_scan(uint64_t items) {
   const uint64_t t = (items + SCAN_TILE - 1) / SCAN_TILE;
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(t, 64));
@@ -1234,7 +1241,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
     const size_t off = R.add(E);
     for (int x = 0; x < nj; x++)
       if (E[x].active && E[x].last) jobs[x].last_rec = off + sizeof(ExtJob) * x;
-    L.push_back(Launch{2, off, nj, gx_scan(srcs), flat_grid(FLAT_GRID_MAX), 0, 0, true, any_last,
+    L.push_back(Launch{2, off, nj, scan_grid(nj, srcs), flat_grid(FLAT_GRID_MAX), 0, 0, true, any_last,
                        any_inner});
   }
   // single-vertex patterns
@@ -1688,7 +1695,7 @@ struct Bounded {
     upload_one(e);
     const DevGraph& g = c.g->dg;
     const ExtJob* rec = (const ExtJob*)c.ws->jobrec;
-    c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, rec, 1, gx_scan(e.src_cap)); });
+    c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, rec, 1, scan_grid(1, e.src_cap)); });
     const uint64_t T = rd(CTL_LEVEL_T + i);
     if (c.stats) c.stats->attempts += T;
     const uint64_t W = e.last ? (c.K > 0 ? c.ws->vbig_cap - (uint64_t)c.K : std::max<uint64_t>(T, 1))
@@ -1835,7 +1842,7 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     uint64_t srcs = 1;
     for (auto& e : E[0]) srcs = std::max(srcs, e.src_cap);
     if (n0)  // attempts again, without the sources the threshold rules out
-      c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, (const ExtJob*)ws->jobrec, n0, gx_scan(srcs)); });
+      c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, (const ExtJob*)ws->jobrec, n0, scan_grid(n0, srcs)); });
     if (n0)
       c.tm.run(K_LAST, [&] {
         ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, flat_grid(FLAT_GRID_MAX), true,

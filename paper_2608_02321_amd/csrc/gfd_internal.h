@@ -304,7 +304,8 @@ void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, 
 void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs);
 void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
               unsigned long long* bytes);
-void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx);
+// 1-D grid of `grid` blocks shared among the jobs by their scan tiles
+void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid);
 void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
              unsigned long long* bytes);
 // k == 1: every member of the root's candidate set is a match.

@@ -221,11 +221,12 @@ __device__ uint64_t tile_prefix_wave(const JobScan& sc, uint64_t t, uint64_t agg
   return prefix;
 }
 
-// Exclusive scan of f(0..N-1) into sc.P[0..N] and *sc.d_total, by the gridDim.x
-// blocks of one job row.  Tiles are handed out by the job's ticket; the block
-// taking the last ticket resets it.  All threads of the block must call it.
+// Exclusive scan of f(0..N-1) into sc.P[0..N] and *sc.d_total, by the nb
+// blocks given to one job (each calls it once).  Tiles are handed out by the
+// job's ticket; the block taking the last ticket resets it.  All threads of
+// the block must call it.
 template <class F>
-__device__ void job_scan(uint64_t N, F f, const JobScan& sc) {
+__device__ void job_scan(uint64_t N, F f, const JobScan& sc, uint64_t nb) {
   const uint64_t ntiles = (N + SCAN_TILE - 1) / SCAN_TILE;
   __shared__ uint32_t s_t;
   __shared__ uint64_t s_pre;
@@ -237,7 +238,7 @@ __device__ void job_scan(uint64_t N, F f, const JobScan& sc) {
     __syncthreads();
     const uint64_t t = s_t;
     if (t >= ntiles) {
-      if (threadIdx.x == 0 && t == ntiles + gridDim.x - 1) {
+      if (threadIdx.x == 0 && t == ntiles + nb - 1) {
         if (ntiles == 0) {
           sc.P[0] = 0;
           *sc.d_total = 0;
@@ -589,7 +590,7 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
     if (!degree_ok(g, J, i, v, by)) return 0u;
     const uint32_t* off = J.cons[c].dir ? g.in_off : g.out_off;
     return off[v + 1] - off[v];
-  }, J.sc);
+  }, J.sc, gridDim.x);
 }
 
 // Arrays of the edge-label blocks a job uses (blk 1: keyed by vertex and edge
@@ -944,7 +945,7 @@ __global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __res
     const int32_t vp = J.p.list[s];
     J.len[s] = 0;
     return off[vp + 1] - off[vp];
-  }, J.sc);
+  }, J.sc, gridDim.x);
 }
 
 // Entry v (far end, label already prim) of the row of v_p in an edge-label
@@ -1220,20 +1221,42 @@ __device__ __forceinline__ bool source_past(const ExtJob& J, uint64_t s,
 }
 
 // CPI list length of every partial match's spanning-tree parent.
-__global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __restrict__ jobs) {
-  const ExtJob& J = jobs[blockIdx.y];
-  if (!J.active) return;
-  const int32_t* par = J.src_cols + (uint64_t)J.par_pos * J.src_stride;
-  const bool prune = J.prune && J.thr != nullptr && *J.d_thr_valid != 0;
-  int32_t thr[MAXK];
+// The launch's blocks are shared among its jobs in proportion to their scan
+// tiles (at least one each, so a job with no sources still writes its zero
+// total): the grid walks these virtual blocks, and a job's virtual blocks run
+// its scan together.  One large frontier thus gets most of the chip instead
+// of a fixed row of blocks.
+__global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __restrict__ jobs,
+                                                 int njobs) {
+  __shared__ ChunkMap tm;  // tiles per job, prefix
+  __shared__ ChunkMap vm;  // virtual blocks per job, prefix
+  chunk_map_build(tm, njobs, [&](int j) -> uint64_t {
+    const ExtJob& J = jobs[j];
+    return J.active ? (ext_sources(J) + SCAN_TILE - 1) / SCAN_TILE : 0ull;
+  });
+  const uint64_t T = tm.cs[njobs], G = gridDim.x;
+  chunk_map_build(vm, njobs, [&](int j) -> uint64_t {
+    if (!jobs[j].active) return 0ull;
+    const uint64_t t = tm.cs[j + 1] - tm.cs[j];
+    uint64_t nb = T ? (G * t + T - 1) / T : 1;
+    if (nb > t) nb = t;
+    return nb ? nb : 1;
+  });
+  for (uint64_t vb = blockIdx.x; vb < vm.cs[njobs]; vb += gridDim.x) {
+    const int jb = chunk_job(vm, njobs, vb);
+    const ExtJob& J = jobs[jb];
+    const int32_t* par = J.src_cols + (uint64_t)J.par_pos * J.src_stride;
+    const bool prune = J.prune && J.thr != nullptr && *J.d_thr_valid != 0;
+    int32_t thr[MAXK];
 #pragma unroll
-  for (int v = 0; v < MAXK; v++) thr[v] = prune && v < J.k ? J.thr[v] : 0;
-  job_scan(ext_sources(J), [&](uint64_t s) -> uint32_t {
-    const int32_t c = J.par_posmap[par[s]];
-    J.begs[s] = J.cpi_beg[c];
-    if (prune && source_past(J, s, thr)) return 0u;
-    return J.cpi_len[c];
-  }, J.sc);
+    for (int v = 0; v < MAXK; v++) thr[v] = prune && v < J.k ? J.thr[v] : 0;
+    job_scan(ext_sources(J), [&](uint64_t s) -> uint32_t {
+      const int32_t c = J.par_posmap[par[s]];
+      J.begs[s] = J.cpi_beg[c];
+      if (prune && source_past(J, s, thr)) return 0u;
+      return J.cpi_len[c];
+    }, J.sc, vm.cs[jb + 1] - vm.cs[jb]);
+  }
 }
 
 // Attempt window of one job in the launch's chunk space (0 for a job of the
@@ -1398,8 +1421,8 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
   if (bytes) block_add(bytes, by);
 }
 
-void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_ext_scan, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid) {
+  hipLaunchKernelGGL(k_ext_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
 }
 void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
              unsigned long long* bytes) {
