@@ -960,10 +960,6 @@ static int scan_grid(int njobs, uint64_t max_items) {
   return (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)std::max(njobs, 1) * std::max<uint64_t>(t, 1),
                                                        FLAT_GRID_MAX));
 }
-static int gx_scan(uint64_t items) {
-  const uint64_t t = (items + SCAN_TILE - 1) / SCAN_TILE;
-  return (int)std::max<uint64_t>(1, std::min<uint64_t>(t, 64));
-}
 
 static uint64_t rows_ub(const gfd_graph* g, int32_t L, int dir) {
   if (L == ANY) return (uint64_t)g->m;
@@ -1079,7 +1075,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       if (f.active)
         item_ch += all_cons ? (f.n_host + 32ull * BS - 1) / (32ull * BS) : chunks_of(f.n_host);
     }
-    L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), flat_grid(item_ch),
+    L.push_back(Launch{0, R.add(F), nj, scan_grid(nj, pairs), flat_grid(pull_ub), flat_grid(item_ch),
                        gx_for((uint64_t)g->n / 32 + 1, nj, 64), any_cons, false, false, false,
                        all_cons});
   }
@@ -1128,7 +1124,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       any = true;
     }
     if (any)
-      L.push_back(Launch{0, R.add(F), nj, gx_scan(pairs), flat_grid(pull_ub), flat_grid(item_ch),
+      L.push_back(Launch{0, R.add(F), nj, scan_grid(nj, pairs), flat_grid(pull_ub), flat_grid(item_ch),
                          gx_for((uint64_t)g->n / 32 + 1, nj, 64), true, false, false, row_scan});
   }
   // CPI adjacency lists per spanning-tree edge, in BFS order
@@ -1169,7 +1165,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       any = true;
     }
     if (any)
-      L.push_back(Launch{1, R.add(C), nj, gx_scan(items), flat_grid(rows), gx_for(items, nj), 0,
+      L.push_back(Launch{1, R.add(C), nj, scan_grid(nj, items), flat_grid(rows), gx_for(items, nj), 0,
                          true, false, false});
   }
   if (!fast_enum) return;

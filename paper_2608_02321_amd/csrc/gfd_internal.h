@@ -288,10 +288,11 @@ struct SelJob {
 
 // Launch wrappers (gfd_kernels.hip).  All asynchronous on `st`; `jobs` points
 // to `njobs` (<= MAX_JOBS) device-resident job records.  Per-job kernels run
-// on a (gx, njobs) grid; the flat (load-balanced) ones on a 1-D grid of `grid`
-// blocks shared by all jobs.  `bytes`, when not null, accumulates the
-// algorithmic bytes the kernel touched.
-void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx);
+// on a (gx, njobs) grid; the flat (load-balanced) ones and the scans on a 1-D
+// grid of `grid` blocks shared by all jobs (the scans share it by their
+// tiles).  `bytes`, when not null, accumulates the algorithmic bytes the
+// kernel touched.
+void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid);
 // bitmaps: the launch's jobs record hits in bitmaps (hitmode 1) rather than
 // bytes; every job of one launch uses the same form
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
@@ -300,7 +301,7 @@ void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, in
                     bool bitmaps, unsigned long long* bytes);
 // zero the output bitmap of every active job
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx);
-void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
+void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid);
 void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs);
 void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
               unsigned long long* bytes);

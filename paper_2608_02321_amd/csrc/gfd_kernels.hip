@@ -509,6 +509,34 @@ __device__ __forceinline__ int chunk_job(const ChunkMap& m, int njobs, uint64_t 
   return lo;
 }
 
+// The blocks of a scan launch shared among its jobs in proportion to their
+// scan tiles: job j, scanning items(j) positions (UINT64_MAX: it does not
+// scan), gets at least one virtual block (so an empty scan still writes its
+// zero total), the grid walks the virtual blocks, and body(j, nb) runs on each
+// of job j's nb virtual blocks.  One large job thus gets most of the chip
+// instead of a fixed row of blocks.
+template <class Items, class Body>
+__device__ __forceinline__ void shared_scan_blocks(int njobs, Items items, Body body) {
+  __shared__ ChunkMap tm;  // tiles per job, prefix
+  __shared__ ChunkMap vm;  // virtual blocks per job, prefix
+  chunk_map_build(tm, njobs, [&](int j) -> uint64_t {
+    const uint64_t n = items(j);
+    return n == ~0ull ? 0ull : (n + SCAN_TILE - 1) / SCAN_TILE;
+  });
+  const uint64_t T = tm.cs[njobs], G = gridDim.x;
+  chunk_map_build(vm, njobs, [&](int j) -> uint64_t {
+    if (items(j) == ~0ull) return 0ull;
+    const uint64_t t = tm.cs[j + 1] - tm.cs[j];
+    uint64_t nb = T ? (G * t + T - 1) / T : 1;
+    if (nb > t) nb = t;
+    return nb ? nb : 1;
+  });
+  for (uint64_t vb = blockIdx.x; vb < vm.cs[njobs]; vb += gridDim.x) {
+    const int jb = chunk_job(vm, njobs, vb);
+    body(jb, vm.cs[jb + 1] - vm.cs[jb]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // fills
 // ---------------------------------------------------------------------------
@@ -577,20 +605,25 @@ __device__ __forceinline__ bool degree_ok(const DevGraph& g, const FilterJob& J,
 
 // Row lengths of (item, constraint) pairs, item-major.  A direct job needs no
 // scan: its rows are contiguous.
-__global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob* __restrict__ jobs) {
-  const FilterJob& J = jobs[blockIdx.y];
-  if (!J.active || J.ncons == 0 || J.direct) return;
-  const uint64_t N = filter_items(J);
-  const uint32_t nc = (uint32_t)J.ncons;
-  unsigned long long by = 0;
-  job_scan(N * nc, [&](uint64_t q) -> uint32_t {
-    const uint64_t i = q / nc;
-    const uint32_t c = (uint32_t)(q - i * nc);
-    const int32_t v = filter_item(J, i);
-    if (!degree_ok(g, J, i, v, by)) return 0u;
-    const uint32_t* off = J.cons[c].dir ? g.in_off : g.out_off;
-    return off[v + 1] - off[v];
-  }, J.sc, gridDim.x);
+__global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob* __restrict__ jobs,
+                                                    int njobs) {
+  shared_scan_blocks(njobs, [&](int j) -> uint64_t {
+    const FilterJob& J = jobs[j];
+    if (!J.active || J.ncons == 0 || J.direct) return ~0ull;
+    return filter_items(J) * (uint64_t)J.ncons;
+  }, [&](int jb, uint64_t nb) {
+    const FilterJob& J = jobs[jb];
+    const uint32_t nc = (uint32_t)J.ncons;
+    unsigned long long by = 0;
+    job_scan(filter_items(J) * nc, [&](uint64_t q) -> uint32_t {
+      const uint64_t i = q / nc;
+      const uint32_t c = (uint32_t)(q - i * nc);
+      const int32_t v = filter_item(J, i);
+      if (!degree_ok(g, J, i, v, by)) return 0u;
+      const uint32_t* off = J.cons[c].dir ? g.in_off : g.out_off;
+      return off[v + 1] - off[v];
+    }, J.sc, nb);
+  });
 }
 
 // Arrays of the edge-label blocks a job uses (blk 1: keyed by vertex and edge
@@ -890,8 +923,8 @@ __global__ __launch_bounds__(BS) void k_filter_clear(const FilterJob* __restrict
     J.bits[w] = 0;
 }
 
-void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_filter_scan, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid) {
+  hipLaunchKernelGGL(k_filter_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
 }
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                  bool bitmaps, unsigned long long* bytes) {
@@ -937,15 +970,19 @@ __device__ __forceinline__ bool cpi_keep(const DevGraph& g, const CpiJob& J, int
 }
 
 // Row lengths of the members of C(p); clears the per-source counters.
-__global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __restrict__ jobs) {
-  const CpiJob& J = jobs[blockIdx.y];
-  if (!J.active) return;
-  const uint32_t* off = J.dir ? g.in_off : g.out_off;
-  job_scan(cpi_sources(J), [&](uint64_t s) -> uint32_t {
-    const int32_t vp = J.p.list[s];
-    J.len[s] = 0;
-    return off[vp + 1] - off[vp];
-  }, J.sc, gridDim.x);
+__global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __restrict__ jobs,
+                                                 int njobs) {
+  shared_scan_blocks(njobs, [&](int j) -> uint64_t {
+    return jobs[j].active ? cpi_sources(jobs[j]) : ~0ull;
+  }, [&](int jb, uint64_t nb) {
+    const CpiJob& J = jobs[jb];
+    const uint32_t* off = J.dir ? g.in_off : g.out_off;
+    job_scan(cpi_sources(J), [&](uint64_t s) -> uint32_t {
+      const int32_t vp = J.p.list[s];
+      J.len[s] = 0;
+      return off[vp + 1] - off[vp];
+    }, J.sc, nb);
+  });
 }
 
 // Entry v (far end, label already prim) of the row of v_p in an edge-label
@@ -1056,8 +1093,8 @@ __global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __res
   if (bytes) block_add(bytes, by);
 }
 
-void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_cpi_scan, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid) {
+  hipLaunchKernelGGL(k_cpi_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
 }
 void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs) {
   hipLaunchKernelGGL(k_cpi_reserve, dim3(1, njobs), dim3(64), 0, st, jobs);
@@ -1221,29 +1258,11 @@ __device__ __forceinline__ bool source_past(const ExtJob& J, uint64_t s,
 }
 
 // CPI list length of every partial match's spanning-tree parent.
-// The launch's blocks are shared among its jobs in proportion to their scan
-// tiles (at least one each, so a job with no sources still writes its zero
-// total): the grid walks these virtual blocks, and a job's virtual blocks run
-// its scan together.  One large frontier thus gets most of the chip instead
-// of a fixed row of blocks.
 __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __restrict__ jobs,
                                                  int njobs) {
-  __shared__ ChunkMap tm;  // tiles per job, prefix
-  __shared__ ChunkMap vm;  // virtual blocks per job, prefix
-  chunk_map_build(tm, njobs, [&](int j) -> uint64_t {
-    const ExtJob& J = jobs[j];
-    return J.active ? (ext_sources(J) + SCAN_TILE - 1) / SCAN_TILE : 0ull;
-  });
-  const uint64_t T = tm.cs[njobs], G = gridDim.x;
-  chunk_map_build(vm, njobs, [&](int j) -> uint64_t {
-    if (!jobs[j].active) return 0ull;
-    const uint64_t t = tm.cs[j + 1] - tm.cs[j];
-    uint64_t nb = T ? (G * t + T - 1) / T : 1;
-    if (nb > t) nb = t;
-    return nb ? nb : 1;
-  });
-  for (uint64_t vb = blockIdx.x; vb < vm.cs[njobs]; vb += gridDim.x) {
-    const int jb = chunk_job(vm, njobs, vb);
+  shared_scan_blocks(njobs, [&](int j) -> uint64_t {
+    return jobs[j].active ? ext_sources(jobs[j]) : ~0ull;
+  }, [&](int jb, uint64_t nb) {
     const ExtJob& J = jobs[jb];
     const int32_t* par = J.src_cols + (uint64_t)J.par_pos * J.src_stride;
     const bool prune = J.prune && J.thr != nullptr && *J.d_thr_valid != 0;
@@ -1255,8 +1274,8 @@ __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __res
       J.begs[s] = J.cpi_beg[c];
       if (prune && source_past(J, s, thr)) return 0u;
       return J.cpi_len[c];
-    }, J.sc, vm.cs[jb + 1] - vm.cs[jb]);
-  }
+    }, J.sc, nb);
+  });
 }
 
 // Attempt window of one job in the launch's chunk space (0 for a job of the
