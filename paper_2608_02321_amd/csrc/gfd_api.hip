@@ -251,6 +251,11 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     std::vector<uint32_t> fill(lab_off.begin(), lab_off.end() - 1);
     for (int64_t v = 0; v < n; v++) lab_vtx[fill[vlabel[v]]++] = (int32_t)v;
   }
+  std::vector<uint32_t> lab_pos(n);  // position of v within its label bucket
+  for (int32_t l = 0; l < nvl; l++)
+    for (uint32_t p = lab_off[l]; p < lab_off[l + 1]; p++) lab_pos[lab_vtx[p]] = p - lab_off[l];
+  {
+  }
   // label-ordered view: the rows of lab_vtx[0..n) laid out in that order, so
   // the rows of one label bucket form one contiguous slice
   std::vector<uint32_t> lv_out_off(n + 1, 0), lv_in_off(n + 1, 0);
@@ -426,6 +431,7 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     g->dg.attr = (const int32_t*)up(attr_flat.data(), 4 * attr_flat.size());
     g->dg.lab_off = (const uint32_t*)up(lab_off.data(), 4 * lab_off.size());
     g->dg.lab_vtx = (const int32_t*)up(lab_vtx.data(), 4 * n);
+    g->dg.lab_pos = (const uint32_t*)up(lab_pos.data(), 4 * n);
     g->dg.lv_out_off = (const uint32_t*)up(lv_out_off.data(), 4 * (n + 1));
     g->dg.lv_out_nbr = (const int32_t*)up(lv_out_nbr.data(), 4 * m);
     g->dg.lv_out_lab = (const int32_t*)up(lv_out_lab.data(), 4 * m);
@@ -1105,6 +1111,12 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
         f.list = cur.list;
         f.d_n = cur.cnt;
         f.cap = J.caps.cap_u[u];
+        // labelled constraints read the item's run in the edge-label block
+        for (int q = 0; q < f.ncons; q++) {
+          PullC& pc = f.cons[q];
+          if (p.qlab[u] != ANY && pc.elab != ANY && p.qlab[u] < g->nvl && pc.elab < g->nel)
+            set_block(g, p.qlab[u], pc.elab, pc.nlab, pc.dir, pc.blk, pc.rb, pc.re);
+        }
       }
       f.hits = J.mem.hits;
       f.hit_words = J.caps.hit_words;

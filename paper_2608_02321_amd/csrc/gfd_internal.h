@@ -54,6 +54,7 @@ struct DevGraph {
   const int32_t* attr;      // [num_attrs * n]
   const uint32_t* lab_off;  // [num_vlabels+1]
   const int32_t* lab_vtx;   // [n], vertices grouped by label, ascending ids
+  const uint32_t* lab_pos;  // [n], v's position within its label bucket
   // label-ordered view: row p is the row of lab_vtx[p], so one label bucket's
   // rows are one contiguous slice of these arrays
   const uint32_t* lv_out_off;  // [n+1]
@@ -121,9 +122,10 @@ struct JobScan {
 struct PullC {
   int32_t dir, elab;
   CandSet w;
-  // direct jobs with a labelled vertex and edge: the edge-label block's rows
-  // [rb, re); blk 1 the (vertex label, edge label) blocks, 2 those keyed by
-  // the far end's label too, 0 none
+  // a labelled vertex and edge: the edge-label block's rows [rb, re) (direct
+  // jobs stream them; listed items find their own row among them); blk 1 the
+  // (vertex label, edge label) blocks, 2 those keyed by the far end's label
+  // too, 0 none
   uint32_t rb, re;
   int32_t blk;
   int32_t nlab;  // label of the constraining pattern vertex (ANY: wildcard)

@@ -603,6 +603,31 @@ __device__ __forceinline__ bool degree_ok(const DevGraph& g, const FilterJob& J,
   return true;
 }
 
+// Arrays of the edge-label blocks a job uses (blk 1: keyed by vertex and edge
+// label; 2: by the far end's label too).
+struct BlockArrays {
+  const uint32_t* row;
+  const uint32_t* start;
+  const int32_t* nbr;
+};
+__device__ __forceinline__ BlockArrays block_arrays(const DevGraph& g, int blk, int dir) {
+  return blk == 2 ? BlockArrays{g.elt_row[dir], g.elt_start[dir], g.elt_nbr[dir]}
+                  : BlockArrays{g.elb_row[dir], g.elb_start[dir], g.elb_nbr[dir]};
+}
+
+// Row of bucket position p in rows [rb, re) of a block (rows ascending by
+// position), or re when the bucket row has no entries there.
+__device__ __forceinline__ uint32_t block_row_of(const uint32_t* rows, uint32_t rb, uint32_t re,
+                                                 uint32_t p, unsigned long long& by) {
+  uint32_t lo = rb, hi = re;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    by += 4;
+    if (rows[mid] < p) lo = mid + 1; else hi = mid;
+  }
+  return (lo < re && rows[lo] == p) ? lo : re;
+}
+
 // Row lengths of (item, constraint) pairs, item-major.  A direct job needs no
 // scan: its rows are contiguous.
 __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob* __restrict__ jobs,
@@ -620,22 +645,16 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
       const uint32_t c = (uint32_t)(q - i * nc);
       const int32_t v = filter_item(J, i);
       if (!degree_ok(g, J, i, v, by)) return 0u;
-      const uint32_t* off = J.cons[c].dir ? g.in_off : g.out_off;
+      const PullC& cs = J.cons[c];
+      if (cs.blk) {  // the item's run in the edge-label block
+        const BlockArrays ba = block_arrays(g, cs.blk, cs.dir);
+        const uint32_t r = block_row_of(ba.row, cs.rb, cs.re, g.lab_pos[v], by);
+        return r < cs.re ? ba.start[r + 1] - ba.start[r] : 0u;
+      }
+      const uint32_t* off = cs.dir ? g.in_off : g.out_off;
       return off[v + 1] - off[v];
     }, J.sc, nb);
   });
-}
-
-// Arrays of the edge-label blocks a job uses (blk 1: keyed by vertex and edge
-// label; 2: by the far end's label too).
-struct BlockArrays {
-  const uint32_t* row;
-  const uint32_t* start;
-  const int32_t* nbr;
-};
-__device__ __forceinline__ BlockArrays block_arrays(const DevGraph& g, int blk, int dir) {
-  return blk == 2 ? BlockArrays{g.elt_row[dir], g.elt_start[dir], g.elt_nbr[dir]}
-                  : BlockArrays{g.elb_row[dir], g.elb_start[dir], g.elb_nbr[dir]};
 }
 
 // Flat entries of constraint c of a direct job: its items' rows in one slice
@@ -797,18 +816,33 @@ __global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob*
       const int32_t* const list = J.list;
       HitRun run;
       ItemRun irun;
+      uint64_t run_q = ~0ull;  // the (item, constraint) pair whose block row is run_x
+      uint32_t run_x = 0;
       flat_chunk<true>(J.sc.P, NP, c0, c1, sh, [&](bool valid, uint64_t q, uint64_t o, uint64_t) {
         if (!valid) return;
         const uint64_t i = q / nc;
         const uint32_t c = (uint32_t)(q - i * nc);
         const PullC& cs = J.cons[c];
         const int32_t v = list ? list[i] : (int32_t)i;
-        const Rows rw = plain_rows(g, cs.dir);
-        const uint32_t x = rw.off[v] + (uint32_t)o;
-        // per row: item and its two offsets; per entry: neighbour (+ label)
-        by += (o == 0 ? 12 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
-        if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
-        if (!member(cs.w, rw.nbr[x])) return;
+        int32_t w;
+        if (cs.blk) {  // only the item's run in the edge-label block
+          const BlockArrays ba = block_arrays(g, cs.blk, cs.dir);
+          if (q != run_q) {  // found once per run of this thread's positions
+            run_q = q;
+            run_x = ba.start[block_row_of(ba.row, cs.rb, cs.re, g.lab_pos[v], by)];
+            by += 12;  // item, bucket position, start
+          }
+          w = ba.nbr[run_x + (uint32_t)o];
+          by += 4;
+        } else {
+          const Rows rw = plain_rows(g, cs.dir);
+          const uint32_t x = rw.off[v] + (uint32_t)o;
+          // per row: item and its two offsets; per entry: neighbour (+ label)
+          by += (o == 0 ? 12 : 0) + 4 + (cs.elab != ANY ? 4 : 0);
+          if (cs.elab != ANY && rw.lab[x] != cs.elab) return;
+          w = rw.nbr[x];
+        }
+        if (!member(cs.w, w)) return;
         if constexpr (bitmaps) run.set(hits + (uint64_t)c * hwords, i);
         else irun.set((uint8_t*)hits + (uint64_t)c * 32 * hwords + i);
       });
