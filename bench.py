@@ -38,11 +38,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "1dcfb0a4f98748bf5ff3aaab9a1ea8646c9992e64f1fdcf6d021218f7e708e6e",
+    "sources_sha256": "6bacf10e712ebc550af3d2b121223900695497c3da1cd0a45f6506a9b6c9be7e",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true>
-    # (1,147.95 MB read + 11.98 MB written) per dispatch, calibrated
-    "bytes_per_launch": 1.15993e9,
+    "semantics": "induced",
+    "count_only": False,
+    # (1,155.05 MB read + 12.07 MB written) per dispatch, calibrated
+    "bytes_per_launch": 1.16712e9,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
@@ -280,6 +282,8 @@ def main():
         traffic = None
         if (TRAFFIC["bytes_per_launch"] and TRAFFIC["kernel_class"] == name
                 and TRAFFIC["workload"] == args.workload
+                and TRAFFIC["semantics"] == args.semantics
+                and TRAFFIC["count_only"] == bool(args.count_only)
                 and TRAFFIC["sources_sha256"] == sources_sha256()):
             traffic = TRAFFIC["bytes_per_launch"]
         roofline = {"bound": "hbm", "kernel_class": name, "achieved": ach, "peak": HBM_PEAK_GBS,
