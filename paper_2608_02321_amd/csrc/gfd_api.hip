@@ -763,6 +763,7 @@ struct JobMem {
   uint64_t* P;
   uint32_t* cpi_beg[MAXK];
   uint32_t* cpi_len[MAXK];
+  uint32_t* cpi_cur[MAXK];
   int32_t* cols[MAXK];
   uint32_t* begs;
   int32_t* vbuf;
@@ -822,7 +823,7 @@ static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t
   for (int u = 0; u < k; u++) b += 2 * align_up(4 * c.cap_u[u]);       // candidate lists
   b += align_up(8 * c.pcap);
   for (int u = 0; u < k; u++)
-    if (u != p.root) b += 2 * align_up(4 * c.cap_u[p.parent[u]]);    // CPI list heads
+    if (u != p.root) b += 3 * align_up(4 * c.cap_u[p.parent[u]]);    // CPI list heads
   for (int i = 2; i < k; i++) b += align_up(4ull * i * c.cap_f);      // frontier columns
   b += align_up(4 * c.begs);
   b += align_up(4 * c.vcap * k);
@@ -853,11 +854,12 @@ static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const J
   }
   m.P = (uint64_t*)take(8 * c.pcap);
   for (int u = 0; u < k; u++) {
-    m.cpi_beg[u] = m.cpi_len[u] = nullptr;
+    m.cpi_beg[u] = m.cpi_len[u] = m.cpi_cur[u] = nullptr;
     if (u == p.root) continue;
     const uint64_t cp = c.cap_u[p.parent[u]];
     m.cpi_beg[u] = (uint32_t*)take(4 * cp);
     m.cpi_len[u] = (uint32_t*)take(4 * cp);
+    m.cpi_cur[u] = (uint32_t*)take(4 * cp);
   }
   for (int i = 0; i < MAXK; i++) m.cols[i] = nullptr;
   for (int i = 2; i < k; i++) m.cols[i] = (int32_t*)take(4ull * i * c.cap_f);
@@ -1011,6 +1013,7 @@ struct Launch {
   bool scan, last_any, inner_any;
   bool row_scan = false;  // filter: some job's pull needs the (item, constraint) row scan
   bool hit_bitmaps = false;  // filter: the jobs record hits in bitmaps (top-down steps)
+  bool cpi_two_pass = false;  // CPI: count kept entries first (the bounded path)
 };
 
 // The launches of a batch in order.  When on_add is set (the fast path), it
@@ -1161,6 +1164,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       a.cap_p = J.caps.cap_u[q];
       a.beg = J.mem.cpi_beg[u];
       a.len = J.mem.cpi_len[u];
+      a.cur = J.mem.cpi_cur[u];
       a.d_base = J.mem.ctl + CTL_CPIBASE;
       a.arena = c.ws->cpi_arena;
       a.arena_cursor = c.ws->misc;
@@ -1178,7 +1182,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
     }
     if (any)
       L.push_back(Launch{1, R.add(C), nj, scan_grid(nj, items), flat_grid(rows), gx_for(items, nj), 0,
-                         true, false, false});
+                         true, false, false, false, false, !fast_enum});
   }
   if (!fast_enum) return;
   // enumeration levels (core-first matching order) with the fused check
@@ -1382,8 +1386,15 @@ static void run_launch(Ctx& c, const Launch& l) {
       case 1: {
         auto* r = (const CpiJob*)(base + l.off);
         c.tm.run(K_SCAN, [&] { cpi_scan(c.st, g, r, l.njobs, l.gx_scan); });
-        c.tm.run(K_OTHER, [&] { cpi_reserve(c.st, r, l.njobs); });
-        c.tm.run(K_CPI, [&] { cpi_fill(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_CPI)); });
+        if (l.cpi_two_pass) {  // lists sized by their kept entries
+          c.tm.run(K_CPI, [&] { cpi_count(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_CPI)); });
+          c.tm.run(K_CPI, [&] { cpi_alloc(c.st, g, r, l.njobs, l.gx_item); });
+        } else {  // lists placed by their members' rows
+          c.tm.run(K_OTHER, [&] { cpi_reserve(c.st, r, l.njobs); });
+        }
+        c.tm.run(K_CPI, [&] {
+          cpi_fill(c.st, g, r, l.njobs, l.gx_work, !l.cpi_two_pass, cls_bytes(c, K_CPI));
+        });
         break;
       }
       case 2: {

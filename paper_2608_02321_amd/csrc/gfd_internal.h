@@ -175,11 +175,12 @@ struct CpiJob {
   uint64_t cap_p;
   uint32_t* beg;
   uint32_t* len;
+  uint32_t* cur;         // two-pass fill: entries written per member
   int32_t* arena;
   unsigned long long* arena_cursor;
   uint64_t arena_cap;
   uint32_t* flags;       // bit 2: arena overflow
-  uint64_t* d_base;      // the job's region of the arena (~0: out of arena)
+  uint64_t* d_base;      // one pass: the job's region of the arena (~0: out of arena)
   JobScan sc;            // over rows of C(p)
   // labelled p and prim: the edge-label block (p's bucket, prim) of direction
   // dir is rows [rb, re); bucket base position `base`
@@ -305,8 +306,12 @@ void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, in
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx);
 void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid);
 void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs);
+// one pass (reserve, then fill) or two (count, alloc, fill) per tree edge
+void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
+               unsigned long long* bytes);
+void cpi_alloc(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx);
 void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
-              unsigned long long* bytes);
+              bool onepass, unsigned long long* bytes);
 // 1-D grid of `grid` blocks shared among the jobs by their scan tiles
 void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid);
 void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,

@@ -1014,6 +1014,7 @@ __global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __res
     job_scan(cpi_sources(J), [&](uint64_t s) -> uint32_t {
       const int32_t vp = J.p.list[s];
       J.len[s] = 0;
+      J.cur[s] = 0;
       return off[vp + 1] - off[vp];
     }, J.sc, nb);
   });
@@ -1086,6 +1087,50 @@ __device__ __forceinline__ void cpi_chunk(const DevGraph& g, const CpiJob& J, ui
   }
 }
 
+// Two passes per tree edge (the bounded path, whose job may not fit its
+// members' rows in the arena): count the kept entries of every member, give
+// each member a list of that length, then fill.
+__global__ __launch_bounds__(BS) void k_cpi_count(DevGraph g, const CpiJob* __restrict__ jobs,
+                                                  int njobs, unsigned long long* bytes) {
+  __shared__ LbsShared sh;
+  __shared__ ChunkMap cm;
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return cpi_chunks(g, jobs[j]); });
+  unsigned long long by = 0;
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+    const int jb = chunk_job(cm, njobs, ch);
+    const CpiJob& J = jobs[jb];
+    cpi_chunk(g, J, ch - cm.cs[jb], sh, by, [&](uint64_t s, int32_t) { atomicAdd(&J.len[s], 1u); });
+  }
+  if (bytes) block_add(bytes, by);
+}
+
+// Each tile of members reserves their lists in the arena with one atomic add.
+__global__ __launch_bounds__(BS) void k_cpi_alloc(DevGraph g, const CpiJob* __restrict__ jobs) {
+  __shared__ unsigned long long s_base;
+  const CpiJob& J = jobs[blockIdx.y];
+  if (!J.active) return;
+  const uint64_t N = cpi_sources(J);
+  for (uint64_t t0 = (uint64_t)blockIdx.x * BS; t0 < N; t0 += (uint64_t)gridDim.x * BS) {
+    const uint64_t s = t0 + threadIdx.x;
+    const uint32_t len = s < N ? J.len[s] : 0u;
+    uint32_t total;
+    const uint32_t pre = block_excl_scan(len, total);
+    if (threadIdx.x == 0)
+      s_base = total ? atomicAdd(J.arena_cursor, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    if (s < N) {
+      if (s_base + total > J.arena_cap) {  // out of arena: the job is redone in bounded mode
+        J.len[s] = 0;
+        J.beg[s] = 0;
+        if (threadIdx.x == 0) atomicOr(J.flags, 4u);
+      } else {
+        J.beg[s] = (uint32_t)(s_base + pre);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // One pass per tree edge: the job reserves, in one atomic add, a region of
 // the arena as large as the rows of C(p)'s members (the scan's total), and
 // member s's list starts at the region's base plus the row prefix P[s] -- its
@@ -1103,26 +1148,39 @@ __global__ void k_cpi_reserve(const CpiJob* __restrict__ jobs) {
   }
 }
 
-// Kept entries go to their member's list directly; the list length is the
-// member's cursor, and the first entry also records the list's start.
+// Kept entries go to their member's list.  ONEPASS: at the member's row
+// prefix in the job's reserved region, the list length being the member's
+// cursor, and the first entry also records the list's start; otherwise into
+// the list the counting pass sized.
+template <bool ONEPASS>
 __global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __restrict__ jobs,
                                                  int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
   __shared__ ChunkMap cm;
   chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return cpi_chunks(g, jobs[j]); });
-  unsigned long long by = 0;
+  unsigned long long by = 0, dummy = 0;
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
     const int jb = chunk_job(cm, njobs, ch);
     const CpiJob& J = jobs[jb];
-    const uint64_t base = *J.d_base;
-    if (base == ~0ull) continue;  // out of arena (uniform per chunk)
-    cpi_chunk(g, J, ch - cm.cs[jb], sh, by, [&](uint64_t s, int32_t v) {
-      const uint64_t start = base + J.sc.P[s];
-      const uint32_t at = atomicAdd(&J.len[s], 1u);
-      J.arena[start + at] = v;
-      if (at == 0) J.beg[s] = (uint32_t)start;
-      by += 4 + (at == 0 ? 12 : 0);  // the entry; per list: prefix, start
-    });
+    if constexpr (ONEPASS) {
+      const uint64_t base = *J.d_base;
+      if (base == ~0ull) continue;  // out of arena (uniform per chunk)
+      cpi_chunk(g, J, ch - cm.cs[jb], sh, by, [&](uint64_t s, int32_t v) {
+        const uint64_t start = base + J.sc.P[s];
+        const uint32_t at = atomicAdd(&J.len[s], 1u);
+        J.arena[start + at] = v;
+        if (at == 0) J.beg[s] = (uint32_t)start;
+        by += 4 + (at == 0 ? 12 : 0);  // the entry; per list: prefix, start
+      });
+    } else {
+      cpi_chunk(g, J, ch - cm.cs[jb], sh, dummy, [&](uint64_t s, int32_t v) {
+        const uint32_t at = atomicAdd(&J.cur[s], 1u);
+        if (at < J.len[s]) {
+          J.arena[(uint64_t)J.beg[s] + at] = v;
+          by += 4;
+        }
+      });
+    }
   }
   if (bytes) block_add(bytes, by);
 }
@@ -1133,9 +1191,19 @@ void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, 
 void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs) {
   hipLaunchKernelGGL(k_cpi_reserve, dim3(1, njobs), dim3(64), 0, st, jobs);
 }
+void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
+               unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_cpi_count, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+}
+void cpi_alloc(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int gx) {
+  hipLaunchKernelGGL(k_cpi_alloc, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+}
 void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
-              unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_cpi_fill, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+              bool onepass, unsigned long long* bytes) {
+  if (onepass)
+    hipLaunchKernelGGL(k_cpi_fill<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  else
+    hipLaunchKernelGGL(k_cpi_fill<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 
 // ---------------------------------------------------------------------------

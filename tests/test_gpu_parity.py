@@ -116,6 +116,39 @@ def test_many_labels_without_label_triple_blocks(P):
     gh.free()
 
 
+def test_cpi_rows_past_the_arena(P):
+    """CPI lists are placed by their members' rows on the fast path.  Five hubs
+    with 250,000 edges each make a tree edge's rows (1.25M entries) exceed the
+    smallest arena (1M entries, at a 64 MiB budget): the job is redone on the
+    bounded path, whose lists are sized by their kept entries, and the results
+    equal the oracle's."""
+    from synth.graphs import Graph
+    hubs, leaves, deg = 5, 260_000, 250_000
+    n = hubs + leaves
+    rng = np.random.default_rng(91)
+    vlabel = np.zeros(n, dtype=np.int32)
+    vlabel[:hubs] = 1
+    rare = hubs + rng.choice(deg, size=100, replace=False)  # inside every hub's row
+    vlabel[rare] = 2
+    col = np.concatenate([np.arange(hubs + h, hubs + h + deg, dtype=np.int32) for h in range(hubs)])
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    row_ptr[1:hubs + 1] = np.arange(1, hubs + 1) * deg
+    row_ptr[hubs + 1:] = hubs * deg
+    attrs = rng.integers(0, 3, size=(1, n)).astype(np.int32)
+    g = Graph(n=n, m=int(col.size), row_ptr=row_ptr, col=col, vlabel=vlabel,
+              elabel=np.zeros(col.size, dtype=np.int32), attrs=attrs, meta={"model": "hand"})
+    gfds = [{"k": 2, "vlabels": [1, 2], "edges": [[0, 1, 0]], "x": [],
+             "y": [{"kind": "const", "var": 1, "attr": 0, "value": 1}], "y_false": False}]
+    gh = P.load(g)
+    for sem in SEMS:
+        got, st = P.validate(gh, gfds, K=64, semantics=sem, mem_budget_bytes=64 << 20, stats=True)
+        og = O.OracleGraph(g)
+        assert got == [O.validate(og, d, sem, K=64, threads=4) for d in gfds]
+        assert got[0]["match_count"] == hubs * 100
+        assert st["chunked_gfds"] == 1
+    gh.free()
+
+
 def test_chunked_paths_agree(P):
     """Tiny frontier / staging budgets force the chunked path and compaction."""
     g = random_graph(7, 300, 4000, n_vlabels=2, n_elabels=2, n_attrs=1, attr_values=3)
