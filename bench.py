@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import statistics
 import os
 import sys
 import time
@@ -56,6 +57,27 @@ def sources_sha256():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def copy_gbs(torch):
+    """Achievable HBM rate on this device: a plain elementwise int32 kernel
+    reading 1 GiB and writing 1 GiB, best of five launches timed with events."""
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    best = None
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.neg(src, out=dst)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 8.0 * n / (best * 1e-3) / 1e9
 
 
 def log(*a):
@@ -218,6 +240,7 @@ def main():
         [{k: v for k, v in d.items() if k != "meta"} for d in configs.gfds(args.workload, g)]
     log(f"inputs: {args.workload} n={g.n} m={g.m} gfds={len(gfds)} ({time.perf_counter() - t:.1f}s)")
     stream = torch.cuda.current_stream()
+    free0 = torch.cuda.mem_get_info()[0]
     t = time.perf_counter()
     gh = P.load(g, stream=stream)
     torch.cuda.synchronize()
@@ -240,8 +263,12 @@ def main():
         st = pc.run(flags=base_flags | (0 if args.no_timing or w < args.warmup - 1
                                         else P.GFD_FLAG_TIMING))
     torch.cuda.synchronize()
+    # the library keeps its workspaces between calls, so what the device lost
+    # since before the load is the graph plus the largest workspace: the peak
+    held_bytes = free0 - torch.cuda.mem_get_info()[0]
     res = pc.results()
     dom = None
+    enum_rate = None
     if not args.no_timing:
         dom = max(range(8), key=lambda c: st["class_ms"][KERNEL_CLASSES[c]])
         log("warm-up per class: " + ", ".join(
@@ -251,12 +278,18 @@ def main():
         log(f"warm-up: wall {st['wall_ms']:.1f} ms, kernel time {sum(st['class_ms'].values()):.1f} ms, "
             f"chunked {st['chunked_gfds']}, threshold {st['threshold_gfds']}/{st['threshold_passes']}, "
             f"counted leaves {st['leaf_gfds']}")
+        enum_ms = st["class_ms"]["extend"] + st["class_ms"]["extend_last"]
+        if enum_ms > 0:
+            enum_rate = sum(r["match_count"] for r in res) / (enum_ms * 1e-3)
     flags = base_flags | (0 if dom is None else (1 << (8 + dom)))  # events: dominant class only
     agg_ms = agg_bytes = agg_launch = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for _ in range(args.steps):
-        st = pc.run(flags=flags)
+        ts = time.perf_counter()
+        st = pc.run(flags=flags)  # synchronous: returns with the results on the host
+        step_ms.append((time.perf_counter() - ts) * 1e3)
         if dom is not None:
             name = KERNEL_CLASSES[dom]
             agg_ms += st["class_ms"][name]
@@ -286,10 +319,12 @@ def main():
                 and TRAFFIC["count_only"] == bool(args.count_only)
                 and TRAFFIC["sources_sha256"] == sources_sha256()):
             traffic = TRAFFIC["bytes_per_launch"]
+        copy = copy_gbs(torch)
         roofline = {"bound": "hbm", "kernel_class": name, "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": per_launch,
-                    "launches_per_step": agg_launch / args.steps}
+                    "launches_per_step": agg_launch / args.steps,
+                    "copy_gbs": copy, "frac_of_copy": ach / copy}
 
     if args.per_gfd:
         rows = []
@@ -336,11 +371,14 @@ def main():
                       "gfds": len(gfds), "semantics": args.semantics, "K": K,
                       "count_only": bool(args.count_only),
                       "parallelism": "single_gpu"},
+           "ms_per_step_median": statistics.median(step_ms), "ms_per_step_min": min(step_ms),
+           "enumeration_embeddings_per_s": enum_rate,
+           "device_bytes": {"graph": gh.info["device_bytes"], "held": held_bytes},
            "load_s": load_s, "roofline": roofline, "compare": compare}
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
         frac = args.cpu_frac if args.cpu_frac is not None else (
-            0.02 if args.workload.endswith("batch256") else 0.25)
+            0.12 if args.workload.endswith("batch256") else 0.25)
         out["cpu_baseline"] = cpu_baseline(g, gfds, args.semantics, frac, threads)
     gh.free()
     print(json.dumps(out), flush=True)

@@ -329,3 +329,22 @@ def test_full_size_configs(P, name):
             for i, (r, e) in enumerate(zip(got, exp["results"][sem])):
                 assert r == e, (name, sem, batched, i)
     gh.free()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_full_size_batch_at_small_budgets(P):
+    """The 256-GFD batch over the 4M/20M graph with the device budget cut to
+    1 GiB and 256 MiB: GFDs whose frontiers no longer fit are redone on the
+    bounded path, and every result still equals the oracle's."""
+    exp = _expected("kg_4m_batch256")
+    g = configs.graph(configs.CONFIG_GRAPH["kg_4m_batch256"])
+    assert g.sha256() == exp["graph_sha256"], "generated graph differs from the stored one"
+    gh = P.load(g)
+    for budget in (1 << 30, 256 << 20):
+        got, st = P.validate(gh, exp["gfds"], K=exp["K"], semantics="induced", batched=True,
+                             mem_budget_bytes=budget, stats=True)
+        assert st["chunked_gfds"] > 0, budget
+        for i, (r, e) in enumerate(zip(got, exp["results"]["induced"])):
+            assert r == e, (budget, i)
+    gh.free()
