@@ -28,6 +28,7 @@
 #include <thread>
 #include <unordered_map>
 #include <functional>
+#include <memory>
 #include <vector>
 
 #include "gfd.h"
@@ -77,6 +78,16 @@ static T* dalloc(size_t count, int64_t* tally = nullptr) {
 static void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
+// Device-side address of mapped pinned host memory, or null if the runtime
+// gives none (uploads from it then take the DMA copy).
+static const uint8_t* mapped_ptr(void* h) {
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return static_cast<const uint8_t*>(d);
+}
 
 // ---------------------------------------------------------------------------
 // workspace: device memory for one validate call at a time
@@ -101,6 +112,7 @@ struct Workspace {
   uint8_t* jobrec = nullptr;        // device job records
   size_t jobrec_bytes = 0;
   uint8_t* hjobrec = nullptr;       // pinned staging for the records
+  const uint8_t* hjobrec_dev = nullptr;  // its device-side address (mapped), or null
   size_t hjobrec_bytes = 0;
   uint64_t* hctl = nullptr;         // pinned mirror of control blocks
   size_t hctl_words = 0;
@@ -123,6 +135,11 @@ struct Workspace {
   int32_t* sel_out = nullptr;       // [SORT_MAX * MAXK]
   uint8_t* selrec = nullptr;        // [MAX_JOBS] SelJob records
   uint8_t* hselrec = nullptr;       // pinned staging for them
+  const uint8_t* hselrec_dev = nullptr;
+  uint64_t* hmisc = nullptr;        // pinned: [0] CPI cursor, [1] error word, [2..9] class bytes
+  int32_t* pack = nullptr;          // a batch's reported tuples, back to back
+  size_t pack_words = 0;
+  hipEvent_t pack_ev = nullptr;     // the last packed copy to ws->hres has landed
   int64_t budget = 0;
 
   ~Workspace() {
@@ -130,6 +147,9 @@ struct Workspace {
     dfree(vbig); dfree(sel_state); dfree(sel_hist); dfree(sel_out); dfree(selrec);
     if (hjobrec) (void)hipHostFree(hjobrec);
     if (hselrec) (void)hipHostFree(hselrec);
+    if (hmisc) (void)hipHostFree(hmisc);
+    dfree(pack);
+    if (pack_ev) (void)hipEventDestroy(pack_ev);
     if (hctl) (void)hipHostFree(hctl);
     if (hres) (void)hipHostFree(hres);
   }
@@ -660,21 +680,27 @@ static void make_plan(const gfd_graph* g, const gfd_spec& s, bool induced, Plan&
       p.adj_other[u] = pair_code(p, q, u, induced);
     }
   }
-  // probes per step
+  // probes per step: pairs that need an edge first (a random pair rarely has
+  // one, so they reject most candidates), the absence-only pairs of the
+  // induced reading after them (they rarely fail); the order only changes
+  // how soon a conjunction stops
   p.nchk[0] = 0;
   for (int i = 1; i < k; i++) {
     int u = p.order[i], ppos = p.pos[p.parent[u]];
     p.nchk[i] = 0;
-    for (int j = 0; j < i; j++) {
-      if (j == ppos) continue;
-      int w = p.order[j];
-      int32_t f = pair_code(p, w, u, induced), b = pair_code(p, u, w, induced);
-      if (f == PC_FREE && b == PC_FREE) continue;
-      int c = p.nchk[i]++;
-      p.chk_pos[i][c] = j;
-      p.chk_fwd[i][c] = f;
-      p.chk_bwd[i][c] = b;
-    }
+    for (int pass = 0; pass < 2; pass++)
+      for (int j = 0; j < i; j++) {
+        if (j == ppos) continue;
+        int w = p.order[j];
+        int32_t f = pair_code(p, w, u, induced), b = pair_code(p, u, w, induced);
+        if (f == PC_FREE && b == PC_FREE) continue;
+        const bool needs_edge = (f != PC_FREE && f != PC_ABSENT) || (b != PC_FREE && b != PC_ABSENT);
+        if (needs_edge != (pass == 0)) continue;
+        int c = p.nchk[i]++;
+        p.chk_pos[i][c] = j;
+        p.chk_fwd[i][c] = f;
+        p.chk_bwd[i][c] = b;
+      }
   }
   // literals, variables mapped to matching-order positions
   p.nx = s.num_x;
@@ -999,9 +1025,29 @@ static void ensure_recs(Workspace* ws, size_t bytes) {
     if (ws->hjobrec) (void)hipHostFree(ws->hjobrec);
     ws->hjobrec = nullptr;
     ws->hjobrec_bytes = 0;
-    HIPCHK(hipHostMalloc((void**)&ws->hjobrec, bytes, hipHostMallocDefault));
+    ws->hjobrec_dev = nullptr;
+    HIPCHK(hipHostMalloc((void**)&ws->hjobrec, bytes, hipHostMallocMapped));
     ws->hjobrec_bytes = bytes;
+    ws->hjobrec_dev = mapped_ptr(ws->hjobrec);
   }
+}
+
+// Small host-to-device upload of staged records on the call's stream.  A copy
+// kernel that reads the mapped pinned staging keeps the upload on the compute
+// queue: a DMA copy between kernels costs a hand-off between engines of about
+// 20 us each time, and a batch uploads records before most of its phases.
+static void upload(Ctx& c, void* dst, const void* hsrc, const uint8_t* hsrc_dev, size_t bytes) {
+  if (bytes == 0) return;
+  const uintptr_t h = (uintptr_t)hsrc, d = (uintptr_t)dst;
+  if (hsrc_dev && (h % 8) == 0 && (d % 8) == 0 && (bytes % 8) == 0 && bytes <= (size_t(1) << 20)) {
+    copy_words(c.st, (const uint64_t*)hsrc_dev, (uint64_t*)dst, bytes / 8);
+    return;
+  }
+  HIPCHK(hipMemcpyAsync(dst, hsrc, bytes, hipMemcpyHostToDevice, c.st));
+}
+static void upload_recs(Ctx& c, size_t off, size_t bytes) {
+  upload(c, c.ws->jobrec + off, c.ws->hjobrec + off, c.ws->hjobrec_dev ? c.ws->hjobrec_dev + off : nullptr,
+         bytes);
 }
 
 // Phase plan of a batch: which kernels run, on which record arrays.
@@ -1433,7 +1479,7 @@ static void run_launches(Ctx& c, const std::vector<Launch>& L) {
 static void upload_recs(Ctx& c, const Recs& R) {
   ensure_recs(c.ws, std::max<size_t>(R.blob.size(), 256));
   std::memcpy(c.ws->hjobrec, R.blob.data(), R.blob.size());
-  HIPCHK(hipMemcpyAsync(c.ws->jobrec, c.ws->hjobrec, R.blob.size(), hipMemcpyHostToDevice, c.st));
+  upload_recs(c, 0, R.blob.size());
 }
 
 // Upper bound of the record bytes plan_batch writes for a batch: at most 2k
@@ -1460,8 +1506,7 @@ static void plan_and_run_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchLi
     if (end > ws->jobrec_bytes) throw GfdError{GFD_EDEVICE, "internal: record bound exceeded"};
     if (end > up) {
       std::memcpy(ws->hjobrec + up, R.blob.data() + up, end - up);
-      HIPCHK(hipMemcpyAsync(ws->jobrec + up, ws->hjobrec + up, end - up, hipMemcpyHostToDevice,
-                            c.st));
+      upload_recs(c, up, end - up);
       up = end;
     }
     run_launch(c, l);
@@ -1479,6 +1524,67 @@ static void ensure_hres(Workspace* ws, size_t words) {
   HIPCHK(hipHostMalloc((void**)&ws->hres, sizeof(int32_t) * words, hipHostMallocDefault));
   ws->hres_words = words;
 }
+
+// A batch's first-K tuples go to the callers' buffers in at most two rounds:
+// the device packs the listed jobs' tuples back to back, one copy brings them
+// into pinned memory, and the host moves them out, while the device works on
+// the jobs still open where there are any.
+struct ResultDrain {
+  Ctx& c;
+  const std::vector<Job>& jobs;
+  gfd_result* results;
+  const std::vector<uint64_t>& H;  // control words per spec
+  int K;
+  size_t used = 0;                 // words of ws->pack / ws->hres handed out
+  struct Item { int x; size_t off, words; };
+  std::vector<Item> pending;       // copied or in flight, not yet moved out
+
+  ResultDrain(Ctx& c_, const std::vector<Job>& j, gfd_result* r, const std::vector<uint64_t>& h, int k)
+      : c(c_), jobs(j), results(r), H(h), K(k) {
+    // both only grow, and before anything of this batch is in them
+    const size_t words = (size_t)K * MAXK * jobs.size();
+    ensure_hres(c.ws, words);
+    if (c.ws->pack_words < words) {
+      dfree(c.ws->pack);
+      c.ws->pack = nullptr;
+      c.ws->pack_words = 0;
+      c.ws->pack = dalloc<int32_t>(words);
+      c.ws->pack_words = words;
+    }
+  }
+  void issue(const std::vector<int>& xs) {
+    Workspace* ws = c.ws;
+    std::vector<PackJob> P;
+    for (int x : xs) {
+      const uint64_t n = std::min<uint64_t>((uint64_t)K, H[(size_t)jobs[x].spec * CTL_WORDS + CTL_VIOL]);
+      const size_t words = (size_t)n * jobs[x].plan.k;
+      if (!words) continue;
+      P.push_back(PackJob{jobs[x].mem.res, used, words});
+      pending.push_back(Item{x, used, words});
+      used += words;
+    }
+    if (P.empty()) return;
+    const size_t w0 = P.front().dst, nw = used - w0;
+    const int32_t* src = P.front().src;  // one job: its slot is already contiguous
+    if (P.size() > 1) {
+      ensure_recs(ws, sizeof(PackJob) * P.size());
+      HIPCHK(hipStreamSynchronize(c.st));  // the record staging is reused per launch
+      std::memcpy(ws->hjobrec, P.data(), sizeof(PackJob) * P.size());
+      upload_recs(c, 0, sizeof(PackJob) * P.size());
+      pack_results(c.st, (const PackJob*)ws->jobrec, (int)P.size(), ws->pack);
+      src = ws->pack + w0;
+    }
+    HIPCHK(hipMemcpyAsync(ws->hres + w0, src, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipEventRecord(ws->pack_ev, c.st));
+  }
+  void drain() {
+    if (pending.empty()) return;
+    HIPCHK(hipEventSynchronize(c.ws->pack_ev));
+    for (const Item& it : pending)
+      std::memcpy(results[jobs[it.x].spec].violations, c.ws->hres + it.off, sizeof(int32_t) * it.words);
+    pending.clear();
+  }
+};
 
 // The batch arena only grows (allocations of this size are slow).
 static void ensure_arena(Workspace* ws, size_t bytes) {
@@ -1579,7 +1685,7 @@ static void run_select(Ctx& c, std::vector<SelJob>& S, bool threshold) {
   }
   HIPCHK(hipStreamSynchronize(c.st));  // the pinned staging is reused per call
   std::memcpy(ws->hselrec, S.data(), sizeof(SelJob) * nj);
-  HIPCHK(hipMemcpyAsync(ws->selrec, ws->hselrec, sizeof(SelJob) * nj, hipMemcpyHostToDevice, c.st));
+  upload(c, ws->selrec, ws->hselrec, ws->hselrec_dev, sizeof(SelJob) * nj);
   const SelJob* r = (const SelJob*)ws->selrec;
   const int gx = (int)std::max<uint64_t>(
       1, std::min<uint64_t>((maxcap + BS - 1) / BS, (uint64_t)std::max(4, 1024 / nj)));
@@ -1638,7 +1744,7 @@ struct Bounded {
     ensure_recs(c.ws, sizeof(ExtJob));
     HIPCHK(hipStreamSynchronize(c.st));  // the staging buffer is reused per launch
     std::memcpy(c.ws->hjobrec, &e, sizeof e);
-    HIPCHK(hipMemcpyAsync(c.ws->jobrec, c.ws->hjobrec, sizeof e, hipMemcpyHostToDevice, c.st));
+    upload_recs(c, 0, sizeof e);
   }
   void compact_if_needed(uint64_t incoming) {
     Workspace* ws = c.ws;
@@ -1799,7 +1905,7 @@ static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
     ensure_recs(ws, sizeof(TopkJob));
     HIPCHK(hipStreamSynchronize(c.st));
     std::memcpy(ws->hjobrec, T.data(), sizeof(TopkJob));
-    HIPCHK(hipMemcpyAsync(ws->jobrec, ws->hjobrec, sizeof(TopkJob), hipMemcpyHostToDevice, c.st));
+    upload_recs(c, 0, sizeof(TopkJob));
     c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)ws->jobrec, 1); });
     HIPCHK(hipMemcpyAsync(ws->hctl, B.mem.ctl, sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
     HIPCHK(hipStreamSynchronize(c.st));
@@ -1821,7 +1927,8 @@ static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
 // Leaves each finished job's control block in ws->hctl; jobs still over after
 // the pass limit go to the bounded path (redo).
 static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> over, const Recs& R,
-                              uint64_t vsmall, std::vector<char>& redo) {
+                              uint64_t vsmall, std::vector<char>& redo,
+                              const std::function<void()>& while_busy) {
   Workspace* ws = c.ws;
   const DevGraph& g = c.g->dg;
   for (int pass = 0; !over.empty(); pass++) {
@@ -1856,7 +1963,7 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
                           vsmall, jobs[x].mem.res, (uint32_t*)(jobs[x].mem.ctl + CTL_NEEDSEL)});
     const size_t bt = b0 + sizeof(ExtJob) * E[1].size();
     std::memcpy(ws->hjobrec + bt, T.data(), sizeof(TopkJob) * T.size());
-    HIPCHK(hipMemcpyAsync(ws->jobrec, ws->hjobrec, bytes, hipMemcpyHostToDevice, c.st));
+    upload_recs(c, 0, bytes);
     const int n0 = (int)E[0].size(), n1 = (int)E[1].size();
     uint64_t srcs = 1;
     for (auto& e : E[0]) srcs = std::max(srcs, e.src_cap);
@@ -1881,6 +1988,7 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     for (int x : over)
       HIPCHK(hipMemcpyAsync(ws->hctl + CTL_WORDS * x, jobs[x].mem.ctl, sizeof(uint64_t) * CTL_WORDS,
                             hipMemcpyDeviceToHost, c.st));
+    while_busy();
     HIPCHK(hipStreamSynchronize(c.st));
     if (c.stats) c.stats->threshold_passes++;
     std::vector<int> next;
@@ -1987,7 +2095,10 @@ static Workspace* acquire_ws(gfd_graph* g, int64_t budget) {
     w->sel_hist = dalloc<uint32_t>((size_t)MAX_JOBS * RADIX_BINS);
     w->sel_out = dalloc<int32_t>((size_t)SORT_MAX * MAXK);
     w->selrec = dalloc<uint8_t>(sizeof(SelJob) * MAX_JOBS);
-    HIPCHK(hipHostMalloc((void**)&w->hselrec, sizeof(SelJob) * MAX_JOBS, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&w->hselrec, sizeof(SelJob) * MAX_JOBS, hipHostMallocMapped));
+    w->hselrec_dev = mapped_ptr(w->hselrec);
+    HIPCHK(hipHostMalloc((void**)&w->hmisc, sizeof(uint64_t) * 16, hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&w->pack_ev, hipEventDisableTiming));
     HIPCHK(hipMemset(w->sel_hist, 0, 4 * (size_t)MAX_JOBS * RADIX_BINS));
     HIPCHK(hipMemset(w->err, 0, 4));
     HIPCHK(hipDeviceSynchronize());
@@ -2104,10 +2215,9 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
         plan_and_run_batch(c, jobs, R, L);
         HIPCHK(hipMemcpyAsync(ws->hctl, jobs[0].mem.ctl, sizeof(uint64_t) * CTL_WORDS * jobs.size(),
                               hipMemcpyDeviceToHost, c.st));
-        unsigned long long cursor = 0;
-        HIPCHK(hipMemcpyAsync(&cursor, ws->misc, 8, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipMemcpyAsync(ws->hmisc, ws->misc, 8, hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipStreamSynchronize(c.st));
-        cpi_entries += cursor;
+        cpi_entries += ws->hmisc[0];
         std::vector<int> over;  // only the violation staging overflowed
         for (size_t x = 0; x < jobs.size(); x++) {
           const uint64_t* h = ws->hctl + CTL_WORDS * x;
@@ -2115,9 +2225,24 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
           if (h[CTL_FLAGS] & 5u) redo[x] = 1;  // frontier or CPI arena overflow
           else if (K > 0 && h[CTL_VCOUNT] > vsmall) over.push_back((int)x);
         }
+        // jobs whose first K the last level's sort already wrote go out now
+        std::unique_ptr<ResultDrain> D;
+        std::vector<char> done(jobs.size(), 0);
+        if (K > 0) {
+          D.reset(new ResultDrain(c, jobs, results, H, K));
+          std::vector<char> isover(jobs.size(), 0);
+          for (int x : over) isover[x] = 1;
+          std::vector<int> fin;
+          for (size_t x = 0; x < jobs.size(); x++)
+            if (!redo[x] && !isover[x] && !H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL]) {
+              fin.push_back((int)x);
+              done[x] = 1;
+            }
+          D->issue(fin);
+        }
         if (!over.empty()) {
           if (stats) stats->threshold_gfds += (int32_t)over.size();
-          rerun_last_levels(c, jobs, over, R, vsmall, redo);
+          rerun_last_levels(c, jobs, over, R, vsmall, redo, [&] { if (D) D->drain(); });
           for (int x : over)
             if (!redo[x]) {
               H[(size_t)jobs[x].spec * CTL_WORDS + CTL_VCOUNT] = ws->hctl[CTL_WORDS * x + CTL_VCOUNT];
@@ -2133,22 +2258,14 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
             S.back().out = jobs[x].mem.res;
           }
           run_select(c, S, false);
-          // the batch's result slots are contiguous: one copy into pinned memory
-          const size_t words = (size_t)K * MAXK * jobs.size();
-          ensure_hres(ws, words);
-          HIPCHK(hipMemcpyAsync(ws->hres, jobs[0].mem.res, sizeof(int32_t) * words,
-                                hipMemcpyDeviceToHost, c.st));
+          D->drain();  // while the selection runs
+          std::vector<int> rest;
+          for (size_t x = 0; x < jobs.size(); x++)
+            if (!redo[x] && !done[x]) rest.push_back((int)x);
+          D->issue(rest);
         }
         HIPCHK(hipStreamSynchronize(c.st));
-        if (K > 0)
-          for (size_t x = 0; x < jobs.size(); x++)
-            if (!redo[x]) {
-              const int32_t i = jobs[x].spec;
-              const uint64_t n = reported(i);
-              if (n)
-                std::memcpy(results[i].violations, ws->hres + (size_t)x * K * MAXK,
-                            sizeof(int32_t) * n * jobs[x].plan.k);
-            }
+        if (D) D->drain();
         if (stats)
           for (size_t x = 0; x < jobs.size(); x++) {
             if (redo[x]) continue;
@@ -2178,9 +2295,12 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
         }
       }
     }
-    uint32_t err = 0;
-    HIPCHK(hipMemcpy(&err, ws->err, 4, hipMemcpyDeviceToHost));
-    if (err) throw GfdError{GFD_EDEVICE, "scan look-back did not complete"};
+    // the error word and the per-class bytes, through pinned memory in one wait
+    ws->hmisc[1] = 0;
+    HIPCHK(hipMemcpyAsync(ws->hmisc + 1, ws->err, 4, hipMemcpyDeviceToHost, c.st));
+    if (stats) HIPCHK(hipMemcpyAsync(ws->hmisc + 2, ws->misc + 8, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+    if ((uint32_t)ws->hmisc[1]) throw GfdError{GFD_EDEVICE, "scan look-back did not complete"};
     int32_t rc = GFD_OK;
     for (int32_t i = 0; i < num_specs; i++) {
       const uint64_t* h = &H[(size_t)i * CTL_WORDS];
@@ -2195,9 +2315,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
         rc = set_error(GFD_EOVERFLOW, "spec %d: counter passed 2^63", i);
     }
     if (stats) {
-      unsigned long long hb[8];
-      HIPCHK(hipMemcpy(hb, ws->misc + 8, sizeof hb, hipMemcpyDeviceToHost));
-      for (int j = 0; j < 8; j++) stats->class_bytes[j] = hb[j];
+      for (int j = 0; j < 8; j++) stats->class_bytes[j] = ws->hmisc[2 + j];
       stats->cpi_entries = cpi_entries;
       if (c.tm.on) c.tm.collect(stats->class_ms);
       for (int j = 0; j < 8; j++) {

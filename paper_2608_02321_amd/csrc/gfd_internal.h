@@ -320,6 +320,18 @@ void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, i
 void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
                 unsigned long long* bytes);
 void topk_small(hipStream_t st, const TopkJob* jobs, int njobs);
+
+// n 8-byte words from src (mapped pinned host memory) to dst (device memory)
+void copy_words(hipStream_t st, const uint64_t* src, uint64_t* dst, uint64_t n);
+
+// One job's reported tuples: `words` int32 from `src`, packed at word `dst`.
+struct PackJob {
+  const int32_t* src;
+  uint64_t dst;
+  uint64_t words;
+};
+// packs the listed jobs' first-K tuples back to back into `out` (one block per job)
+void pack_results(hipStream_t st, const PackJob* jobs, int njobs, int32_t* out);
 // per member of C(p): how many of its leaf-list members meet each predicate subset
 void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx);
 // per partial match: its injective leaf completions, counted into the job's counters

@@ -1252,8 +1252,8 @@ struct FinalAcc {
 // precedes the current threshold); `t` then holds it in variable order.
 __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
                                          const int32_t (&h)[MAXK], int32_t (&t)[MAXK],
-                                         FinalAcc& acc, bool thr_on, const int32_t* thr,
-                                         unsigned long long& by) {
+                                         FinalAcc& acc, bool count, bool thr_on,
+                                         const int32_t* thr, unsigned long long& by) {
   uint64_t hs = 0x9E3779B97F4A7C15ull * (uint64_t)J.k;
 #pragma unroll
   for (int v = 0; v < MAXK; v++) {
@@ -1270,11 +1270,15 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
       Y = literal_holds(g, J.lit[J.nx + j], h);
       by += J.lit[J.nx + j].kind == 0 ? 4 : 8;
     }
-  acc.match += 1;
-  acc.mfp += hs;
+  if (count) {
+    acc.match += 1;
+    acc.mfp += hs;
+  }
   if (!(X && !Y)) return false;
-  acc.viol += 1;
-  acc.vfp += hs;
+  if (count) {
+    acc.viol += 1;
+    acc.vfp += hs;
+  }
   if (J.vcap == 0) return false;
   // stage only if t < thr (t <= thr when thr_incl), lexicographically on unsigned ids
   return !(thr_on && past_threshold(J, h, thr));
@@ -1483,22 +1487,37 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
       } else {
         int32_t t[MAXK];
         bool want = false;
-        if (ok) {
-          FinalAcc one{0, 0, 0, 0};
-          want = finalize(g, J, h, t, one, thr_on, thr, by);
-          if (!J.collect_only) {
-            acc.match += one.match;
-            acc.viol += one.viol;
-            acc.mfp += one.mfp;
-            acc.vfp += one.vfp;
-          }
-        }
+        if (ok) want = finalize(g, J, h, t, acc, !J.collect_only, thr_on, thr, by);
         stage(J, want, t, full);
       }
     });
     if (LAST && !J.collect_only) flush_acc(J.counters, acc);
   }
   if (bytes) block_add(bytes, by);
+}
+
+// Job records from the mapped pinned staging into device memory.
+__global__ __launch_bounds__(BS) void k_copy_words(const uint64_t* __restrict__ src,
+                                                   uint64_t* __restrict__ dst, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (uint64_t)gridDim.x * BS)
+    dst[i] = src[i];
+}
+
+void copy_words(hipStream_t st, const uint64_t* src, uint64_t* dst, uint64_t n) {
+  if (n == 0) return;
+  const uint64_t b = (n + BS - 1) / BS;
+  hipLaunchKernelGGL(k_copy_words, dim3((unsigned)(b > 64 ? 64 : b)), dim3(BS), 0, st, src, dst, n);
+}
+
+// Reported tuples of a batch's jobs, back to back, for one copy to the host.
+__global__ __launch_bounds__(BS) void k_pack_results(const PackJob* __restrict__ jobs,
+                                                     int32_t* __restrict__ out) {
+  const PackJob J = jobs[blockIdx.x];
+  for (uint64_t w = threadIdx.x; w < J.words; w += BS) out[J.dst + w] = J.src[w];
+}
+
+void pack_results(hipStream_t st, const PackJob* jobs, int njobs, int32_t* out) {
+  if (njobs > 0) hipLaunchKernelGGL(k_pack_results, dim3(njobs), dim3(BS), 0, st, jobs, out);
 }
 
 // k == 1: every member of C(root) is a match; the window is over list indices.
@@ -1527,14 +1546,7 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
       by += 4;
 #pragma unroll
       for (int j = 0; j < MAXK; j++) h[j] = v;
-      FinalAcc one{0, 0, 0, 0};
-      want = finalize(g, J, h, t, one, thr_on, thr, by);
-      if (!J.collect_only) {
-        acc.match += one.match;
-        acc.viol += one.viol;
-        acc.mfp += one.mfp;
-        acc.vfp += one.vfp;
-      }
+      want = finalize(g, J, h, t, acc, !J.collect_only, thr_on, thr, by);
     }
     stage(J, want, t, full);
   }
