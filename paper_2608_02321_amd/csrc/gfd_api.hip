@@ -336,16 +336,16 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     }
     hub_off[v + 1] = hub_off[v] + t;
   }
-  std::vector<int32_t> hub_tab(hub_off[n], HUB_EMPTY);
+  std::vector<uint8_t> hub_tab(hub_off[n], 0);
   parallel_for(n, [&](int64_t a, int64_t b) {
     for (int64_t v = a; v < b; v++) {
       const uint64_t t = hub_off[v + 1] - hub_off[v];
       if (!t) continue;
-      int32_t* tab = hub_tab.data() + hub_off[v];
+      uint8_t* tab = hub_tab.data() + hub_off[v];
       for (uint64_t e = sym_off[v]; e < sym_off[v + 1]; e++) {
         uint64_t i = hub_slot(sym_nbr[e], t);
-        while (tab[i] != HUB_EMPTY) i = (i + 1) & (t - 1);
-        tab[i] = sym_nbr[e];
+        while (tab[i] != 0) i = (i + 1) & (t - 1);
+        tab[i] = hub_fp(sym_nbr[e]);
       }
     }
   });
@@ -459,7 +459,7 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     g->dg.lv_in_nbr = (const int32_t*)up(lv_in_nbr.data(), 4 * m);
     g->dg.lv_in_lab = (const int32_t*)up(lv_in_lab.data(), 4 * m);
     g->dg.hub_off = (const uint64_t*)up(hub_off.data(), 8 * (n + 1));
-    g->dg.hub_tab = (const int32_t*)up(hub_tab.data(), 4 * hub_tab.size());
+    g->dg.hub_tab = (const uint8_t*)up(hub_tab.data(), hub_tab.size());
     g->dg.sym_off = (const uint64_t*)up(sym_off.data(), 8 * (n + 1));
     g->dg.sym_nbr = (const int32_t*)up(sym_nbr.data(), 4 * sym_nbr.size());
     g->dg.sym_lab = (const int2*)up(sym_lab.data(), 4 * sym_lab.size());

@@ -114,21 +114,23 @@ __device__ __forceinline__ int32_t edge_label_at(const DevGraph& g, int32_t a, i
 
 // Labels of both data edges between a and b, (a -> b, b -> a), NOEDGE where
 // absent: one search of a's combined row instead of one in each direction.
-// A long row is first looked up in its neighbour table, which settles the
+// A long row is first looked up in its fingerprint table, which settles the
 // common case (not adjacent) in about one access; the row search then runs
-// only for neighbours, to read their labels.
+// only for neighbours (to read their labels) and for the rare fingerprint
+// that matches by chance.
 __device__ __forceinline__ int2 edge_labels_both(const DevGraph& g, int32_t a, int32_t b,
                                                  unsigned long long& by) {
   const uint64_t t0 = g.hub_off[a], t1 = g.hub_off[a + 1];
   by += 16;
   if (t1 > t0) {
     const uint64_t mask = t1 - t0 - 1;
+    const uint8_t f = hub_fp(b);
     // at least half the slots are free, so the probe sequence ends
     for (uint64_t i = hub_slot(b, t1 - t0);; i = (i + 1) & mask) {
-      const int32_t e = g.hub_tab[t0 + i];
-      by += 4;
-      if (e == b) break;
-      if (e == HUB_EMPTY) return make_int2(NOEDGE, NOEDGE);
+      const uint8_t e = g.hub_tab[t0 + i];
+      by += 1;
+      if (e == f) break;
+      if (e == 0) return make_int2(NOEDGE, NOEDGE);
     }
   }
   uint64_t lo = g.sym_off[a], hi = g.sym_off[a + 1];
@@ -1795,7 +1797,9 @@ void topk_small(hipStream_t st, const TopkJob* jobs, int njobs) {
 // Radix select, batched over jobs (grid row y = job).  State words of a job:
 // [0..MAXK) the tuple being decided, [MAXK] the remaining rank (1-based) among
 // staged tuples that agree with it so far, [MAXK + 1] blocks done in the
-// current pass.
+// current pass, [MAXK + 2] set once a single staged tuple agrees with the
+// decided prefix, [MAXK + 3] set once that tuple has been copied whole into
+// [0..MAXK): the passes left then have nothing to decide and return at once.
 __global__ void k_sel_begin(const SelJob* __restrict__ jobs) {
   const SelJob& J = jobs[blockIdx.y];
   if (!J.active) return;
@@ -1803,6 +1807,8 @@ __global__ void k_sel_begin(const SelJob* __restrict__ jobs) {
   if (threadIdx.x == 0) {
     J.state[MAXK] = (uint32_t)J.K;
     J.state[MAXK + 1] = 0;
+    J.state[MAXK + 2] = 0;
+    J.state[MAXK + 3] = 0;
     if (J.d_outcount) *J.d_outcount = 0;
   }
 }
@@ -1827,7 +1833,10 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
   __shared__ uint32_t sh[RADIX_BINS];
   __shared__ uint32_t s_last, s_seen;
   const SelJob& J = jobs[blockIdx.y];
-  if (!J.active || word >= J.k) return;
+  if (!J.active || word >= J.k || J.state[MAXK + 3]) return;
+  // one staged tuple agrees with the prefix: it is the one sought, and the
+  // thread that meets it copies it whole instead of voting
+  const bool single = J.state[MAXK + 2] != 0;
   for (int b = threadIdx.x; b < RADIX_BINS; b += BS) sh[b] = 0;
   if (threadIdx.x == 0) s_seen = 0;
   uint32_t st[MAXK];
@@ -1847,6 +1856,11 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
     if (!match) continue;
     const uint32_t x = t[word];
     if ((x & hi_mask) != want_hi) continue;
+    if (single) {
+      for (int w = word; w < k; w++) J.state[w] = t[w];
+      J.state[MAXK + 3] = 1;
+      continue;
+    }
     atomicAdd(&sh[(x >> shift) & ((1u << bits) - 1)], 1u);
   }
   __syncthreads();
@@ -1873,16 +1887,18 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
   uint32_t total;
   const uint32_t pre = block_excl_scan(sum, total);
   if (pre < r && r <= pre + sum) {  // exactly one thread
-    uint32_t cum = pre, d = threadIdx.x * PER;
+    uint32_t cum = pre, d = threadIdx.x * PER, in_bin = 0;
     for (int j = 0; j < PER; j++) {
       if (cum + h[j] >= r) {
         d = threadIdx.x * PER + j;
+        in_bin = h[j];
         break;
       }
       cum += h[j];
     }
     J.state[MAXK] = r - cum;
     J.state[word] |= d << shift;
+    if (in_bin == 1u) J.state[MAXK + 2] = 1;
   }
 #pragma unroll
   for (int j = 0; j < PER; j++) J.hist[threadIdx.x * PER + j] = 0;
