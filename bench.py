@@ -39,13 +39,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "71e1e1413a61e76b878ef16878fc1e80853edf1a02d95b6644d459f9015c787c",
+    "sources_sha256": "3293cf33ec74f55152de6000139549546f74a0dd3edbcb74b0c947244f975021",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true>
     "semantics": "induced",
     "count_only": False,
-    # (1,164.78 MB read + 11.80 MB written) per dispatch, calibrated
-    "bytes_per_launch": 1.17658e9,
+    # (672.19 MB read + 11.90 MB written) per dispatch, calibrated
+    "bytes_per_launch": 6.8409e8,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
