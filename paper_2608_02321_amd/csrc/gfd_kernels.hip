@@ -1223,11 +1223,11 @@ __device__ __forceinline__ T pick(const T (&h)[N], int idx) {
   return r;
 }
 
-__device__ __forceinline__ bool literal_holds(const DevGraph& g, const DevLit& l,
-                                              const int32_t (&h)[MAXK]) {
-  const int32_t x = g.attr[(int64_t)l.attr * g.n + pick(h, l.pos)];
+template <class Col>
+__device__ __forceinline__ bool literal_holds(const DevGraph& g, const DevLit& l, Col col) {
+  const int32_t x = g.attr[(int64_t)l.attr * g.n + col(l.pos)];
   if (l.kind == 0) return x != ABSENT && x == l.value;
-  const int32_t y = g.attr[(int64_t)l.attr2 * g.n + pick(h, l.pos2)];
+  const int32_t y = g.attr[(int64_t)l.attr2 * g.n + col(l.pos2)];
   return x != ABSENT && y != ABSENT && x == y;
 }
 
@@ -1245,6 +1245,19 @@ __device__ __forceinline__ bool past_threshold(const ExtJob& J, const int32_t (&
   return c > 0 || (c == 0 && !J.thr_incl);
 }
 
+// The same on the tuple already in variable order.
+__device__ __forceinline__ bool past_threshold_t(const ExtJob& J, const int32_t (&t)[MAXK],
+                                                 const int32_t* thr) {
+  int c = 0;
+#pragma unroll
+  for (int v = 0; v < MAXK; v++)
+    if (c == 0 && v < J.k) {
+      const uint32_t x = (uint32_t)t[v], y = (uint32_t)thr[v];
+      c = x < y ? -1 : (x > y ? 1 : 0);
+    }
+  return c > 0 || (c == 0 && !J.thr_incl);
+}
+
 struct FinalAcc {
   unsigned long long match, viol, mfp, vfp;
 };
@@ -1252,24 +1265,28 @@ struct FinalAcc {
 // One complete match h (matching order): count it, fingerprint it in variable
 // order, check X -> Y; returns whether a violation must be staged (it
 // precedes the current threshold); `t` then holds it in variable order.
+// col(p) reads the match at matching-order position p again (p is the
+// same for the whole wave): a cached load or a register, cheaper than
+// selecting the entry out of h.
+template <class Col>
 __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
                                          const int32_t (&h)[MAXK], int32_t (&t)[MAXK],
                                          FinalAcc& acc, bool count, bool thr_on,
-                                         const int32_t* thr, unsigned long long& by) {
+                                         const int32_t* thr, unsigned long long& by, Col col) {
   uint64_t hs = 0x9E3779B97F4A7C15ull * (uint64_t)J.k;
 #pragma unroll
   for (int v = 0; v < MAXK; v++) {
-    t[v] = pick(h, J.var_pos[v]);
+    t[v] = v < J.k ? col(J.var_pos[v]) : 0;
     if (v < J.k) hs = mix64(hs ^ (uint64_t)(uint32_t)t[v]);
   }
   bool X = true, Y = !J.y_false;
   for (int j = 0; j < J.nx && X; j++) {
-    X = literal_holds(g, J.lit[j], h);
+    X = literal_holds(g, J.lit[j], col);
     by += J.lit[j].kind == 0 ? 4 : 8;  // the attribute values read
   }
   if (X && Y)
     for (int j = 0; j < J.ny && Y; j++) {
-      Y = literal_holds(g, J.lit[J.nx + j], h);
+      Y = literal_holds(g, J.lit[J.nx + j], col);
       by += J.lit[J.nx + j].kind == 0 ? 4 : 8;
     }
   if (count) {
@@ -1283,7 +1300,7 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
   }
   if (J.vcap == 0) return false;
   // stage only if t < thr (t <= thr when thr_incl), lexicographically on unsigned ids
-  return !(thr_on && past_threshold(J, h, thr));
+  return !(thr_on && past_threshold_t(J, t, thr));
 }
 
 // Whether a job's staging is already past its capacity: a wave that starts
@@ -1489,7 +1506,10 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
       } else {
         int32_t t[MAXK];
         bool want = false;
-        if (ok) want = finalize(g, J, h, t, acc, !J.collect_only, thr_on, thr, by);
+        if (ok)
+          want = finalize(g, J, h, t, acc, !J.collect_only, thr_on, thr, by, [&](int p) -> int32_t {
+            return p < i ? J.src_cols[(uint64_t)p * J.src_stride + s] : v;
+          });
         stage(J, want, t, full);
       }
     });
@@ -1548,7 +1568,7 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
       by += 4;
 #pragma unroll
       for (int j = 0; j < MAXK; j++) h[j] = v;
-      want = finalize(g, J, h, t, acc, !J.collect_only, thr_on, thr, by);
+      want = finalize(g, J, h, t, acc, !J.collect_only, thr_on, thr, by, [&](int) { return v; });
     }
     stage(J, want, t, full);
   }
@@ -1682,7 +1702,7 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
     bool X = true, Y = !J.y_false;
     for (int t = 0; t < J.nx + J.ny; t++) {
       if (J.lit_leaf[t] >= 0) continue;
-      const bool v = literal_holds(g, J.lit[t], h);
+      const bool v = literal_holds(g, J.lit[t], [&](int p) { return pick(h, p); });
       if (t < J.nx) X = X && v;
       else Y = Y && v;
     }
