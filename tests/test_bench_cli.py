@@ -1,0 +1,28 @@
+"""bench.py's command-line contract on the host: more than one GPU is refused
+with a message, and the kernel-sources hash that keys the stored HBM traffic
+figures is printed on request."""
+import json
+import os
+import re
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                          capture_output=True, text=True, cwd=ROOT, timeout=120)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _bench("--gpus", "2")
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+def test_sources_hash():
+    r = _bench("--sources-sha256")
+    assert r.returncode == 0
+    assert re.fullmatch(r"[0-9a-f]{64}", r.stdout.strip())
