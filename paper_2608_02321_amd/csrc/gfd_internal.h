@@ -321,8 +321,10 @@ void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, 
               bool onepass, unsigned long long* bytes);
 // 1-D grid of `grid` blocks shared among the jobs by their scan tiles
 void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid);
+// ahead (last level only): load every round's first probe slot before the
+// rounds run -- more loads in flight, fewer waves; for cache-resident graphs
 void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
-             unsigned long long* bytes);
+             bool ahead, unsigned long long* bytes);
 // k == 1: every member of the root's candidate set is a match.
 void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
                 unsigned long long* bytes);

@@ -393,12 +393,13 @@ __device__ __forceinline__ void flat_chunk(const T* __restrict__ P, uint64_t N, 
   __syncthreads();
 }
 
-// flat_chunk<false> split in two phases: every round's position is placed and
+// flat_chunk<false> split in phases: every round's position is placed and
 // its value loaded by pre(s, o) first -- LBS_ROUNDS independent loads in
-// flight per thread -- and only then f(valid, s, o, value) runs per round.
-template <class T, class Pre, class F>
+// flight per thread --, then mid(s, value) per round (more independent
+// loads), and only then f(valid, s, first, value, mid's bit) runs per round.
+template <class T, class Pre, class Mid, class F>
 __device__ __forceinline__ void flat_chunk_pre(const T* __restrict__ P, uint64_t N, uint64_t c0,
-                                               uint64_t c1, LbsShared& sh, Pre pre, F f) {
+                                               uint64_t c1, LbsShared& sh, Pre pre, Mid mid, F f) {
   if (threadIdx.x < WAVE) {
     const uint64_t lo = wave_last_le(P, 0, N - 1, c0);
     if (threadIdx.x == 0) sh.lo = lo;
@@ -450,9 +451,16 @@ __device__ __forceinline__ void flat_chunk_pre(const T* __restrict__ P, uint64_t
       pv[r] = pre(ss[r], o);
     }
   }
+  // a second batch of independent loads per round, issued before any round
+  // runs: mid(s, value) gives one bit that f receives
+  uint32_t known = 0;
 #pragma unroll
   for (int r = 0; r < LBS_ROUNDS; r++)
-    f(((valid >> r) & 1u) != 0, (uint64_t)ss[r], ((first >> r) & 1u) != 0, pv[r]);
+    if ((valid >> r) & 1u) known |= (mid(ss[r], pv[r]) & 1u) << r;
+#pragma unroll
+  for (int r = 0; r < LBS_ROUNDS; r++)
+    f(((valid >> r) & 1u) != 0, (uint64_t)ss[r], ((first >> r) & 1u) != 0, pv[r],
+      ((known >> r) & 1u) != 0);
   __syncthreads();
 }
 
@@ -1414,7 +1422,7 @@ __device__ __forceinline__ uint64_t ext_width(const ExtJob& J) {
   return A1 > J.a_begin ? A1 - J.a_begin : 0ull;
 }
 
-template <bool LAST>
+template <bool LAST, bool AHEAD>
 __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __restrict__ jobs,
                                                 int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
@@ -1447,8 +1455,20 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
     auto cpi_entry = [&](uint32_t s, uint32_t o) -> int32_t {
       return J.cpi_ent[(uint64_t)J.begs[s] + o];
     };
-    flat_chunk_pre(J.sc.P, N, c0, c1, sh, cpi_entry, [&](bool valid, uint64_t s, bool first,
-                                                          int32_t v) {
+    // AHEAD: the first probe's table slot for every round at once; a free
+    // slot settles that probe (the pair is not adjacent), and the eight
+    // lookups overlap instead of waiting one round each.  It costs registers
+    // (4 waves per SIMD instead of 5), which pays where the graph sits in
+    // cache and the kernel waits on issue and cache latency, not on HBM.
+    auto first_probe_free = [&](uint32_t s, int32_t v) -> uint32_t {
+      if (!AHEAD || J.nchk == 0 || J.chk_fwd[0] == PC_FREE || J.chk_bwd[0] == PC_FREE) return 0u;
+      const int32_t hw = J.src_cols[(uint64_t)J.chk_pos[0] * J.src_stride + s];
+      const uint64_t t0 = g.hub_off[hw], t1 = g.hub_off[hw + 1];
+      if (t1 <= t0) return 0u;
+      return g.hub_tab[t0 + hub_slot(v, t1 - t0)] == 0 ? 1u : 0u;
+    };
+    flat_chunk_pre(J.sc.P, N, c0, c1, sh, cpi_entry, first_probe_free,
+                   [&](bool valid, uint64_t s, bool first, int32_t v, bool free0) {
       int32_t h[MAXK];
       bool ok = false;
       if (valid) {
@@ -1469,7 +1489,13 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
           // rows of hw, which the wave's threads share: the combined row when
           // both directions are constrained, else the one direction's row
           if (cf != PC_FREE && cb != PC_FREE) {
-            const int2 l = edge_labels_both(g, hw, v, by);
+            int2 l;
+            if (c == 0 && free0) {
+              l = make_int2(NOEDGE, NOEDGE);
+              by += 17;  // what the probe reads: the table bounds and one slot
+            } else {
+              l = edge_labels_both(g, hw, v, by);
+            }
             ok = constraint_ok(l.x, cf) && constraint_ok(l.y, cb);
           } else {
             ok = pair_ok(g, hw, v, true, cf, by) && pair_ok(g, v, hw, false, cb, by);
@@ -1580,11 +1606,13 @@ void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, 
   hipLaunchKernelGGL(k_ext_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
 }
 void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
-             unsigned long long* bytes) {
-  if (last)
-    hipLaunchKernelGGL(k_ext_run<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+             bool ahead, unsigned long long* bytes) {
+  if (last && ahead)
+    hipLaunchKernelGGL((k_ext_run<true, true>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  else if (last)
+    hipLaunchKernelGGL((k_ext_run<true, false>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
   else
-    hipLaunchKernelGGL(k_ext_run<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+    hipLaunchKernelGGL((k_ext_run<false, false>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
                 unsigned long long* bytes) {
