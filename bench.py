@@ -39,13 +39,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "969f253e0f6c4086af6e4673df101ea3f9a0dbb838d92e602c58f2b156c305e0",
+    "sources_sha256": "b493b426faa7f34c9a309f80cf6ae6ea877ef1c0e02e35c5c404b0a1d1fdce48",
     "workload": "kg_4m_batch256",
-    "kernel_class": "extend_last",  # k_ext_run<true>
+    "kernel_class": "extend_last",  # k_ext_run<true, false>
     "semantics": "induced",
     "count_only": False,
-    # (668.61 MB read + 12.14 MB written) per dispatch, calibrated
-    "bytes_per_launch": 6.8075e8,
+    # (667.26 MB read + 11.96 MB written) per dispatch, calibrated
+    "bytes_per_launch": 6.7922e8,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
