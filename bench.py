@@ -187,8 +187,8 @@ def serve(args, torch, P, g, gh):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="kg_4m_batch256")
     ap.add_argument("--mode", choices=["batched", "plain"], default=None,
                     help="default: batched for the 256-GFD workload, plain otherwise")
