@@ -1407,7 +1407,9 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       srcs = std::max(srcs, f.src_cap);
       any = true;
     }
-    if (any) L.push_back(Launch{5, R.add(F), nj, 0, gx_for(srcs, nj), gx_for(np, nj), 0, false, false, false});
+    if (any)
+      L.push_back(Launch{5, R.add(F), nj, 0, flat_grid(FLAT_GRID_MAX), gx_for(np, nj), 0, false, false,
+                         false});
   }
   if (c.K > 0) {
     std::vector<TopkJob> T(nj);
@@ -1471,7 +1473,7 @@ static void run_launch(Ctx& c, const Launch& l) {
       case 5: {
         auto* r = (const LeafJob*)(base + l.off);
         c.tm.run(K_OTHER, [&] { leaf_prep(c.st, g, r, l.njobs, l.gx_item); });
-        c.tm.run(K_LAST, [&] { leaf_count(c.st, g, r, l.njobs, l.gx_work); });
+        c.tm.run(K_LAST, [&] { leaf_count(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_LAST)); });
         break;
       }
       case 4: {

@@ -344,7 +344,8 @@ void pack_results(hipStream_t st, const PackJob* jobs, int njobs, int32_t* out);
 // per member of C(p): how many of its leaf-list members meet each predicate subset
 void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx);
 // per partial match: its injective leaf completions, counted into the job's counters
-void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx);
+void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid,
+                unsigned long long* bytes);
 
 // Batched radix select (grid row = job); requires more than K staged tuples
 // per active job.  sel_pass decides `bits` bits of tuple word `word` starting

@@ -1688,14 +1688,28 @@ __device__ __forceinline__ int64_t injective(int r, const int64_t (&c)[LEAF_SUBS
   return c[1] * c[2] * c[4] - c[3] * c[4] - c[5] * c[2] - c[6] * c[1] + 2 * c[7];
 }
 
-__global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __restrict__ jobs) {
-  __shared__ unsigned long long s_acc[2][BS / WAVE];
-  const LeafJob& J = jobs[blockIdx.y];
-  if (!J.active) return;
-  const uint64_t N = *J.d_nsrc < J.src_cap ? *J.d_nsrc : J.src_cap;
+__device__ __forceinline__ uint64_t leaf_sources(const LeafJob& J) {
+  return !J.active ? 0ull : (*J.d_nsrc < J.src_cap ? *J.d_nsrc : J.src_cap);
+}
+
+// The partial matches of every job share one chunk space (LBS_CHUNK sources a
+// chunk), so a job with most of the work gets most of the chip.
+__global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __restrict__ jobs,
+                                                   int njobs, unsigned long long* bytes) {
+  __shared__ ChunkMap cm;
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(leaf_sources(jobs[j])); });
+  unsigned long long by = 0;
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+  const int jb = chunk_job(cm, njobs, ch);
+  const LeafJob& J = jobs[jb];
+  const uint64_t N = leaf_sources(J);
+  const uint64_t s0 = (ch - cm.cs[jb]) * LBS_CHUNK;
+  const uint64_t s1 = s0 + LBS_CHUNK < N ? s0 + LBS_CHUNK : N;
   const uint32_t nsub = 1u << J.r;
-  unsigned long long matches = 0, viol = 0;
-  for (uint64_t s = (uint64_t)blockIdx.x * BS + threadIdx.x; s < N; s += (uint64_t)gridDim.x * BS) {
+  FinalAcc acc{0, 0, 0, 0};
+  for (uint64_t s = s0 + threadIdx.x; s < s1; s += BS) {
+    // the partial match, its parent's row in the count table and the words read
+    by += 4ull * (uint64_t)J.i + 4 + 4ull * LEAF_WORDS;
     int32_t h[MAXK];
 #pragma unroll
     for (int j = 0; j < MAXK; j++) h[j] = j < J.i ? J.src_cols[(uint64_t)j * J.src_stride + s] : 0;
@@ -1707,7 +1721,6 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
 #pragma unroll
       for (int B = 0; B < LEAF_SUBSETS; B++) c[f][B] = cc[f * LEAF_SUBSETS + B];
     // matched inner vertices that sit in vp's leaf list are not available
-    unsigned long long by = 0;
     for (int j = 0; j < J.i; j++) {
       const int32_t x = h[j];
       if (x == vp || !member(J.u, x)) continue;
@@ -1731,34 +1744,27 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
     for (int t = 0; t < J.nx + J.ny; t++) {
       if (J.lit_leaf[t] >= 0) continue;
       const bool v = literal_holds(g, J.lit[t], [&](int p) { return pick(h, p); });
+      by += J.lit[t].kind == 0 ? 4 : 8;  // the attribute values read
       if (t < J.nx) X = X && v;
       else Y = Y && v;
     }
-    matches += (unsigned long long)injective(J.r, c[0]);
+    acc.match += (unsigned long long)injective(J.r, c[0]);
     if (X) {
       const int64_t ix = injective(J.r, c[1]);
-      viol += (unsigned long long)(Y ? ix - injective(J.r, c[2]) : ix);
+      acc.viol += (unsigned long long)(Y ? ix - injective(J.r, c[2]) : ix);
     }
   }
-  matches = wave_sum(matches);
-  viol = wave_sum(viol);
-  if (lane() == 0) {
-    s_acc[0][threadIdx.x / WAVE] = matches;
-    s_acc[1][threadIdx.x / WAVE] = viol;
+  flush_acc(J.counters, acc);  // counts only: the fingerprint sums stay zero
   }
-  __syncthreads();
-  if (threadIdx.x < 2) {
-    unsigned long long t = 0;
-    for (int w = 0; w < BS / WAVE; w++) t += s_acc[threadIdx.x][w];
-    if (t) atomicAdd(&J.counters[threadIdx.x], t);
-  }
+  if (bytes) block_add(bytes, by);
 }
 
 void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx) {
   hipLaunchKernelGGL(k_leaf_prep, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
 }
-void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_leaf_count, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid,
+                unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_leaf_count, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 
 // ---------------------------------------------------------------------------
