@@ -39,13 +39,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "b493b426faa7f34c9a309f80cf6ae6ea877ef1c0e02e35c5c404b0a1d1fdce48",
+    "sources_sha256": "c2f7ab15c217d69b7f934b299ab47bc0af8163505d56139bc34a04e47304b75a",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true, false>
     "semantics": "induced",
     "count_only": False,
-    # (667.26 MB read + 11.96 MB written) per dispatch, calibrated
-    "bytes_per_launch": 6.7922e8,
+    # (668.10 MB read + 11.93 MB written) per dispatch, calibrated
+    "bytes_per_launch": 6.8003e8,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
