@@ -26,3 +26,17 @@ def test_sources_hash():
     r = _bench("--sources-sha256")
     assert r.returncode == 0
     assert re.fullmatch(r"[0-9a-f]{64}", r.stdout.strip())
+
+
+def test_cpu_baseline_fields():
+    """The oracle leg of the bench line on the 2,000-vertex configuration:
+    the contract's fields, a multi-threaded figure and a one-thread one."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from synth import configs
+    g = configs.graph(configs.CONFIG_GRAPH["small_uniform"])
+    gfds = [{k: v for k, v in d.items() if k != "meta"} for d in configs.gfds("small_uniform", g)]
+    out = bench.cpu_baseline(g, gfds, "induced", 0.5, 2)
+    for leg, cores in ((out, 2), (out["single_thread"], 1)):
+        assert leg["kind"] == "oracle" and leg["unit"] == "embeddings/s"
+        assert leg["cores"] == cores and leg["value"] >= 0 and leg["sample"]
