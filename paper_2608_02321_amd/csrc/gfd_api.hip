@@ -1408,8 +1408,9 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       any = true;
     }
     if (any)
-      L.push_back(Launch{5, R.add(F), nj, 0, flat_grid(FLAT_GRID_MAX), gx_for(np, nj), 0, false, false,
-                         false});
+      L.push_back(Launch{5, R.add(F), nj, 0, flat_grid(FLAT_GRID_MAX), (int)std::min<uint64_t>(
+                             FLAT_GRID_MAX, std::max<uint64_t>(1, (np + BS - 1) / BS * (uint64_t)nj)),
+                         0, false, false, false});
   }
   if (c.K > 0) {
     std::vector<TopkJob> T(nj);

@@ -342,7 +342,7 @@ struct PackJob {
 // packs the listed jobs' first-K tuples back to back into `out` (one block per job)
 void pack_results(hipStream_t st, const PackJob* jobs, int njobs, int32_t* out);
 // per member of C(p): how many of its leaf-list members meet each predicate subset
-void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx);
+void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid);
 // per partial match: its injective leaf completions, counted into the job's counters
 void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid,
                 unsigned long long* bytes);

@@ -1651,12 +1651,24 @@ __device__ __forceinline__ void leaf_masks(const DevGraph& g, const LeafJob& J, 
 
 // One thread per member c of C(p): cnt[c][f][B] = members of c's leaf list
 // whose family-f masks contain B (f = 0: every member, 1: X, 2: X and Y).
-__global__ __launch_bounds__(BS) void k_leaf_prep(DevGraph g, const LeafJob* __restrict__ jobs) {
-  const LeafJob& J = jobs[blockIdx.y];
-  if (!J.active) return;
-  const uint64_t np = *J.d_np < J.cap_p ? *J.d_np : J.cap_p;
+__device__ __forceinline__ uint64_t leaf_members(const LeafJob& J) {
+  return !J.active ? 0ull : (*J.d_np < J.cap_p ? *J.d_np : J.cap_p);
+}
+
+// The members of every job's C(p) share one space of BS-member chunks: a
+// member's work is its whole CPI list, so each thread takes one member and
+// the blocks move on to whichever job still has members.
+__global__ __launch_bounds__(BS) void k_leaf_prep(DevGraph g, const LeafJob* __restrict__ jobs,
+                                                  int njobs) {
+  __shared__ ChunkMap cm;
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return (leaf_members(jobs[j]) + BS - 1) / BS; });
+  for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
+  const int jb = chunk_job(cm, njobs, ch);
+  const LeafJob& J = jobs[jb];
+  const uint64_t np = leaf_members(J);
   const uint32_t nsub = 1u << J.r;
-  for (uint64_t c = (uint64_t)blockIdx.x * BS + threadIdx.x; c < np; c += (uint64_t)gridDim.x * BS) {
+  const uint64_t c = (ch - cm.cs[jb]) * BS + threadIdx.x;
+  if (c < np) {
     uint32_t cx[LEAF_SUBSETS] = {}, cxy[LEAF_SUBSETS] = {};
     const uint32_t b = J.cpi_beg[c], len = J.cpi_len[c];
     for (uint32_t e = 0; e < len; e++) {
@@ -1675,6 +1687,7 @@ __global__ __launch_bounds__(BS) void k_leaf_prep(DevGraph g, const LeafJob* __r
       out[LEAF_SUBSETS + B] = cx[B];
       out[2 * LEAF_SUBSETS + B] = cxy[B];
     }
+  }
   }
 }
 
@@ -1759,8 +1772,8 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
   if (bytes) block_add(bytes, by);
 }
 
-void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_leaf_prep, dim3(gx, njobs), dim3(BS), 0, st, g, jobs);
+void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid) {
+  hipLaunchKernelGGL(k_leaf_prep, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
 }
 void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid,
                 unsigned long long* bytes) {
