@@ -39,13 +39,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "c2f7ab15c217d69b7f934b299ab47bc0af8163505d56139bc34a04e47304b75a",
+    "sources_sha256": "a50065b81a11e9a2acebcf1535036aacbcd7c4b1fcaa7cfe0054a883bf8ba21d",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true, false>
     "semantics": "induced",
     "count_only": False,
-    # (668.10 MB read + 11.93 MB written) per dispatch, calibrated
-    "bytes_per_launch": 6.8003e8,
+    # (669.12 MB read + 11.98 MB written) per dispatch, calibrated
+    "bytes_per_launch": 6.8110e8,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
