@@ -104,8 +104,30 @@ typedef struct {
 /* H(t): splitmix64 finaliser mix (Steele, Lea & Flood 2014) chained over the
  * tuple: h = 0x9E3779B97F4A7C15 * k; for each t_i: h = mix(h ^ (uint32)t_i). */
 
+/* Device memory callbacks.  alloc returns `bytes` of device memory, aligned to
+ * at least 256 bytes, that work on `hip_stream` may use (NULL on failure: the
+ * call then fails with GFD_ENOMEM); free returns a block alloc gave, with its
+ * size.  ctx is passed back unchanged.  alloc == NULL means the library's own
+ * hipMalloc / hipFree.  Callbacks may be called from any thread that calls
+ * into the library (and from server worker threads).  Memory given to a graph
+ * is returned by gfd_free_graph; workspace memory a graph keeps between
+ * validate calls is returned by gfd_trim or gfd_free_graph, so the callbacks
+ * must stay valid until then. */
 typedef struct {
-  void* hip_stream; /* hipStream_t for the upload; NULL = the null stream */
+  void* (*alloc)(void* ctx, int64_t bytes, void* hip_stream);
+  void (*free)(void* ctx, void* ptr, int64_t bytes);
+  void* ctx;
+} gfd_allocator;
+
+#define GFD_MEM_HOST 0   /* input arrays are host memory */
+#define GFD_MEM_DEVICE 1 /* input arrays are device memory of the current device */
+
+typedef struct {
+  void* hip_stream;        /* hipStream_t for the upload; NULL = the null stream */
+  int32_t mem_kind;        /* GFD_MEM_HOST or GFD_MEM_DEVICE: where row_ptr, col, vlabel,
+                              elabel and the attribute columns live (the array of
+                              column pointers itself is always host memory) */
+  gfd_allocator allocator; /* device memory of the graph; alloc == NULL: hipMalloc */
 } gfd_load_opts;
 
 typedef struct {
@@ -118,6 +140,9 @@ typedef struct {
   int32_t flags;            /* GFD_FLAG_* bits */
   int64_t frontier_cap;     /* testing: max partial matches per level (0 = from budget) */
   int64_t violation_cap;    /* testing: violation staging capacity in tuples (0 = default) */
+  gfd_allocator allocator;  /* device memory of the call's workspace; alloc == NULL:
+                               hipMalloc.  The graph keeps a workspace per allocator
+                               between calls (see gfd_trim) */
 } gfd_validate_opts;
 
 #define GFD_FLAG_FORCE_CHUNKED 1 /* skip the single-pass fast path */
@@ -155,24 +180,42 @@ typedef struct {
                                  violations up to a bound on the K-th smallest */
   int32_t threshold_passes;   /* such re-runs (one launch each for all those GFDs) */
   int32_t leaf_gfds;          /* GFDs whose last leaves were counted (GFD_FLAG_COUNT_ONLY) */
+  int32_t regrown_gfds;       /* GFDs run again in the fast path after the frontier pool or
+                                 the CPI entry arena grew to what their batch asked for */
+  int64_t front_pool_bytes;   /* frontier pool and CPI entry arena sizes after the call */
+  int64_t cpi_arena_bytes;
 } gfd_stats;
 
-/* Load a graph given as out-CSR on the host.  Inputs are read and copied: the
- * caller may free them on return.  Rows need not be sorted.  attr is an array
- * of num_attrs pointers to columns of n int32 (values >= 0 or GFD_ABSENT).
- * Errors: GFD_EINVAL for row_ptr not starting at 0 / not non-decreasing / not
- * ending at m, col out of range, a self-loop, a duplicate ordered pair,
- * negative labels, attribute values < -1, null pointers; GFD_EUNSUPPORTED for
- * n >= 2^31 or m >= 2^32; GFD_ENOMEM / GFD_EDEVICE from the device.
+/* Load a graph given as out-CSR, in host memory or (opts->mem_kind ==
+ * GFD_MEM_DEVICE) in device memory of the current device.  Inputs are read
+ * and copied: the caller may free them on return.  Rows need not be sorted.
+ * attr is a host array of num_attrs pointers to columns of n int32 (values
+ * >= 0 or GFD_ABSENT).  The graph's device memory comes from opts->allocator
+ * (hipMalloc when none is given).  Errors: GFD_EINVAL for row_ptr not
+ * starting at 0 / not non-decreasing / not ending at m, col out of range, a
+ * self-loop, a duplicate ordered pair, negative labels, attribute values
+ * < -1, null pointers, an allocator with alloc but no free, an unknown
+ * mem_kind; GFD_EUNSUPPORTED for n >= 2^31, m >= 2^32, a label id above
+ * GFD_MAX_LABEL or more than GFD_MAX_LABEL_PAIRS (vertex label, edge label)
+ * combinations (max vertex label + 1 times max edge label + 1); GFD_ENOMEM
+ * (host or device allocation) / GFD_EDEVICE from the device.
  * (Section II: E is a subset of V x V, one label per vertex and per edge,
  * attributes on vertices only.) */
+#define GFD_MAX_LABEL ((1 << 24) - 1)
+#define GFD_MAX_LABEL_PAIRS (1 << 24)
 int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
                        const int32_t* vlabel, const int32_t* elabel, int32_t num_attrs,
                        const int32_t* const* attr, const gfd_load_opts* opts,
                        gfd_graph** out);
 
-/* Release a graph and every device buffer it owns.  NULL is ignored. */
+/* Release a graph and every device buffer it owns (through the allocators
+ * they came from).  NULL is ignored. */
 void gfd_free_graph(gfd_graph* g);
+
+/* Return the device workspaces the graph keeps between validate calls (one
+ * per allocator used) to their allocators.  The next call allocates again.
+ * Must not overlap a validate call or a server on the same graph. */
+int32_t gfd_trim(gfd_graph* g);
 
 /* Validate num_specs GFDs over g (Section II's validation problem, per GFD).
  * Synchronous: returns once every result is on the host.  results is
@@ -215,6 +258,9 @@ typedef struct {
   int64_t mem_budget_bytes; /* device bytes per worker; 0 = default share */
   int32_t k_max;            /* violations reported per GFD (0..2048) */
   int32_t semantics;        /* GFD_SEM_INDUCED or GFD_SEM_MONO */
+  gfd_allocator allocator;  /* device memory of the workers' workspaces; alloc == NULL:
+                               hipMalloc.  Must stay valid until gfd_trim or
+                               gfd_free_graph on the graph */
 } gfd_server_opts;
 
 typedef struct {
@@ -237,8 +283,11 @@ int32_t gfd_server_submit(gfd_server* s, const gfd_spec* specs, int32_t num_spec
 /* Wait for a request: timeout_ms < 0 waits without limit; GFD_EAGAIN if it has
  * not finished in time (wait again later).  On completion fills results
  * [num_specs] (each violations buffer caller-owned, room for k_max tuples of
- * that GFD) and info (may be NULL), forgets the request and returns the
- * status of its batch.  Each request is waited for successfully once. */
+ * that GFD) and info (may be NULL), forgets the request and returns its
+ * status: a batch that fails is validated again request by request, so a
+ * failing request does not fail the others.  Each request is waited for
+ * successfully once; while one thread waits for a request, another wait for
+ * the same request fails with GFD_EINVAL. */
 int32_t gfd_server_wait(gfd_server* s, uint64_t request_id, int32_t timeout_ms,
                         gfd_result* results, gfd_request_info* info);
 

@@ -58,15 +58,25 @@ class gfd_result(C.Structure):
                 ("violations", C.POINTER(C.c_int32))]
 
 
+GFD_MEM_HOST, GFD_MEM_DEVICE = 0, 1
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_int64)
+
+
+class gfd_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 class gfd_load_opts(C.Structure):
-    _fields_ = [("hip_stream", C.c_void_p)]
+    _fields_ = [("hip_stream", C.c_void_p), ("mem_kind", C.c_int32), ("allocator", gfd_allocator)]
 
 
 class gfd_validate_opts(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("semantics", C.c_int32),
                 ("mem_budget_bytes", C.c_int64), ("hip_stream", C.c_void_p),
                 ("batched", C.c_int32), ("flags", C.c_int32),
-                ("frontier_cap", C.c_int64), ("violation_cap", C.c_int64)]
+                ("frontier_cap", C.c_int64), ("violation_cap", C.c_int64),
+                ("allocator", gfd_allocator)]
 
 
 class gfd_stats(C.Structure):
@@ -75,7 +85,9 @@ class gfd_stats(C.Structure):
                 ("cpi_candidates", C.c_uint64), ("cpi_entries", C.c_uint64),
                 ("class_launches", C.c_int32 * 8), ("class_ms", C.c_double * 8),
                 ("class_bytes", C.c_uint64 * 8), ("threshold_gfds", C.c_int32),
-                ("threshold_passes", C.c_int32), ("leaf_gfds", C.c_int32)]
+                ("threshold_passes", C.c_int32), ("leaf_gfds", C.c_int32),
+                ("regrown_gfds", C.c_int32), ("front_pool_bytes", C.c_int64),
+                ("cpi_arena_bytes", C.c_int64)]
 
 
 class gfd_graph_info(C.Structure):
@@ -86,7 +98,8 @@ class gfd_graph_info(C.Structure):
 
 class gfd_server_opts(C.Structure):
     _fields_ = [("workers", C.c_int32), ("max_batch_gfds", C.c_int32),
-                ("mem_budget_bytes", C.c_int64), ("k_max", C.c_int32), ("semantics", C.c_int32)]
+                ("mem_budget_bytes", C.c_int64), ("k_max", C.c_int32), ("semantics", C.c_int32),
+                ("allocator", gfd_allocator)]
 
 
 class gfd_request_info(C.Structure):
@@ -95,7 +108,7 @@ class gfd_request_info(C.Structure):
                 ("batch_requests", C.c_int32), ("worker", C.c_int32)]
 
 
-EXPORTS = ("gfd_load_graph", "gfd_free_graph", "gfd_validate", "gfd_validate_ex",
+EXPORTS = ("gfd_load_graph", "gfd_free_graph", "gfd_trim", "gfd_validate", "gfd_validate_ex",
            "gfd_get_graph_info", "gfd_server_create", "gfd_server_submit", "gfd_server_wait",
            "gfd_server_destroy", "gfd_last_error", "gfd_version")
 
@@ -119,6 +132,8 @@ def _load():
                                  C.POINTER(gfd_load_opts), C.POINTER(C.c_void_p)]
     L.gfd_free_graph.restype = None
     L.gfd_free_graph.argtypes = [C.c_void_p]
+    L.gfd_trim.restype = C.c_int32
+    L.gfd_trim.argtypes = [C.c_void_p]
     L.gfd_validate.restype = C.c_int32
     L.gfd_validate.argtypes = [C.c_void_p, C.POINTER(gfd_spec), C.c_int32,
                                C.POINTER(gfd_validate_opts), C.POINTER(gfd_result)]
@@ -177,12 +192,80 @@ def current_torch_stream():
     return None
 
 
-class GraphHandle:
-    """A graph resident on the device (gfd_load_graph / gfd_free_graph)."""
+class TorchAllocator:
+    """gfd_allocator callbacks backed by torch's caching allocator, so the
+    library's device memory is torch's: it shows in torch.cuda.memory_allocated
+    and returns to torch's cache when freed.  Counts its calls (tests)."""
 
-    def __init__(self, h, info):
+    def __init__(self, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.allocs = self.frees = 0
+        self.live_bytes = self.peak_bytes = 0
+        self._sizes = {}
+        self._alloc = ALLOC_FN(self._on_alloc)
+        self._free = FREE_FN(self._on_free)
+        self.c = gfd_allocator(self._alloc, self._free, None)
+
+    def _on_alloc(self, ctx, nbytes, stream):
+        try:
+            p = self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+        except Exception:  # out of memory: the library reports GFD_ENOMEM
+            return None
+        self.allocs += 1
+        self._sizes[p] = int(nbytes)
+        self.live_bytes += int(nbytes)
+        self.peak_bytes = max(self.peak_bytes, self.live_bytes)
+        return p
+
+    def _on_free(self, ctx, ptr, nbytes):
+        if not ptr:
+            return
+        self.frees += 1
+        self.live_bytes -= self._sizes.pop(ptr, int(nbytes))
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
+_default_alloc = None
+
+
+def torch_allocator():
+    """The process-wide TorchAllocator (made on first use)."""
+    global _default_alloc
+    if _default_alloc is None:
+        _default_alloc = TorchAllocator()
+    return _default_alloc
+
+
+def _torch_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except ImportError:
+        return False
+
+
+def _allocator(alloc):
+    """gfd_allocator for an `allocator=` argument: "torch" (default) = the
+    process-wide TorchAllocator (the library's own hipMalloc where torch sees
+    no GPU), None = the library's own hipMalloc, or a TorchAllocator."""
+    if isinstance(alloc, str) and alloc == "torch":
+        alloc = torch_allocator() if _torch_gpu() else None
+    if alloc is None:
+        return gfd_allocator(), None
+    return alloc.c, alloc
+
+
+class GraphHandle:
+    """A graph resident on the device (gfd_load_graph / gfd_free_graph).
+    Holds the allocators its memory and workspaces came from, so their
+    callbacks outlive the graph."""
+
+    def __init__(self, h, info, allocators=()):
         self._h = h
         self.info = info
+        self._allocators = list(allocators)
 
     @property
     def handle(self):
@@ -190,37 +273,73 @@ class GraphHandle:
             raise ValueError("graph already freed")
         return self._h
 
+    def keep(self, alloc):
+        if alloc is not None and all(a is not alloc for a in self._allocators):
+            self._allocators.append(alloc)
+
+    def trim(self):
+        """gfd_trim: return the workspaces kept between calls."""
+        _check(lib.gfd_trim(self.handle))
+
     def free(self):
-        if getattr(self, "_h", None):
-            lib.gfd_free_graph(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        if h and lib is not None:
+            lib.gfd_free_graph(h)
+        self._h = None
 
-    __del__ = free
+    def __del__(self):
+        try:  # at interpreter exit the module globals may already be gone
+            self.free()
+        except Exception:
+            pass
 
 
-def load_graph(n, m, row_ptr, col, vlabel, elabel, attrs=None, stream=None) -> GraphHandle:
-    """gfd_load_graph: out-CSR on the host; copies to the device."""
-    keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
-            np.ascontiguousarray(col, dtype=np.int32),
-            np.ascontiguousarray(vlabel, dtype=np.int32),
-            np.ascontiguousarray(elabel, dtype=np.int32)]
-    A = 0 if attrs is None else int(np.asarray(attrs).shape[0])
-    cols = [np.ascontiguousarray(np.asarray(attrs)[a], dtype=np.int32) for a in range(A)]
-    ptrs = (C.c_void_p * max(A, 1))(*[c.ctypes.data for c in cols])
-    opts = gfd_load_opts(_stream_handle(stream))
+def _device_ptr(x):
+    return int(x.data_ptr())
+
+
+def load_graph(n, m, row_ptr, col, vlabel, elabel, attrs=None, stream=None,
+               allocator="torch") -> GraphHandle:
+    """gfd_load_graph: out-CSR as host arrays, or as torch tensors on the
+    current GPU (mem_kind GFD_MEM_DEVICE: the library reads them there)."""
+    try:
+        import torch
+        on_dev = isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda
+    except ImportError:
+        torch, on_dev = None, False
+    if on_dev:
+        keep = [row_ptr.to(torch.int64).contiguous(), col.to(torch.int32).contiguous(),
+                vlabel.to(torch.int32).contiguous(), elabel.to(torch.int32).contiguous()]
+        A = 0 if attrs is None else int(attrs.shape[0])
+        cols = [attrs[a].to(torch.int32).contiguous() for a in range(A)]
+        ptrs = (C.c_void_p * max(A, 1))(*[_device_ptr(c) for c in cols])
+        args = [_device_ptr(x) for x in keep]
+        kind = GFD_MEM_DEVICE
+    else:
+        keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
+                np.ascontiguousarray(col, dtype=np.int32),
+                np.ascontiguousarray(vlabel, dtype=np.int32),
+                np.ascontiguousarray(elabel, dtype=np.int32)]
+        A = 0 if attrs is None else int(np.asarray(attrs).shape[0])
+        cols = [np.ascontiguousarray(np.asarray(attrs)[a], dtype=np.int32) for a in range(A)]
+        ptrs = (C.c_void_p * max(A, 1))(*[c.ctypes.data for c in cols])
+        args = [x.ctypes.data for x in keep]
+        kind = GFD_MEM_HOST
+    ca, alloc = _allocator(allocator)
+    opts = gfd_load_opts(_stream_handle(stream), kind, ca)
     out = C.c_void_p()
-    rc = lib.gfd_load_graph(int(n), int(m), keep[0].ctypes.data, keep[1].ctypes.data,
-                            keep[2].ctypes.data, keep[3].ctypes.data, A, ptrs, C.byref(opts),
-                            C.byref(out))
+    rc = lib.gfd_load_graph(int(n), int(m), *args, A, ptrs, C.byref(opts), C.byref(out))
     _check(rc)
     info = gfd_graph_info()
     _check(lib.gfd_get_graph_info(out, C.byref(info)))
-    return GraphHandle(out.value, {f: getattr(info, f) for f, _ in gfd_graph_info._fields_})
+    return GraphHandle(out.value, {f: getattr(info, f) for f, _ in gfd_graph_info._fields_},
+                       [alloc] if alloc is not None else [])
 
 
-def load(g, stream=None) -> GraphHandle:
+def load(g, stream=None, allocator="torch") -> GraphHandle:
     """Load an object with n, m, row_ptr, col, vlabel, elabel, attrs attributes."""
-    return load_graph(g.n, g.m, g.row_ptr, g.col, g.vlabel, g.elabel, g.attrs, stream=stream)
+    return load_graph(g.n, g.m, g.row_ptr, g.col, g.vlabel, g.elabel, g.attrs, stream=stream,
+                      allocator=allocator)
 
 
 def free_graph(gh: GraphHandle):
@@ -263,7 +382,8 @@ class PreparedCall:
     call's outputs to the dicts validate() returns."""
 
     def __init__(self, graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
-                 mem_budget_bytes: int = 0, stream=None, flags: int = 0, batched: bool = False):
+                 mem_budget_bytes: int = 0, stream=None, flags: int = 0, batched: bool = False,
+                 allocator="torch"):
         self.graph, self.gfds, self.K = graph, list(gfds), int(K)
         n = len(self.gfds)
         self.n = n
@@ -273,9 +393,11 @@ class PreparedCall:
         self.buf = np.zeros((max(n, 1), max(1, self.K * GFD_MAX_K)), dtype=np.int32)
         for i in range(n):
             self.res[i].violations = self.buf[i].ctypes.data_as(C.POINTER(C.c_int32))
+        ca, alloc = _allocator(allocator)
+        graph.keep(alloc)
         self.opts = gfd_validate_opts(self.K, GFD_SEM_INDUCED if semantics == "induced"
                                       else GFD_SEM_MONO, int(mem_budget_bytes),
-                                      _stream_handle(stream), int(bool(batched)), int(flags), 0, 0)
+                                      _stream_handle(stream), int(bool(batched)), int(flags), 0, 0, ca)
         self.st = gfd_stats()
 
     def run(self, flags=None, stats=True):
@@ -308,7 +430,8 @@ class PreparedCall:
 
 def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
              mem_budget_bytes: int = 0, stream=None, flags: int = 0, frontier_cap: int = 0,
-             violation_cap: int = 0, stats: bool = False, batched: bool = False):
+             violation_cap: int = 0, stats: bool = False, batched: bool = False,
+             allocator="torch"):
     """gfd_validate(_ex): one result dict per GFD (plus a stats dict if asked)."""
     n = len(gfds)
     specs = (gfd_spec * max(n, 1))(*[make_spec(d) for d in gfds])
@@ -318,10 +441,12 @@ def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced"
         b = np.zeros(max(1, K * int(d["k"])), dtype=np.int32)
         bufs.append(b)
         results[i].violations = b.ctypes.data_as(C.POINTER(C.c_int32))
+    ca, alloc = _allocator(allocator)
+    graph.keep(alloc)
     opts = gfd_validate_opts(K, GFD_SEM_INDUCED if semantics == "induced" else GFD_SEM_MONO,
                              int(mem_budget_bytes), _stream_handle(stream), int(bool(batched)),
                              int(flags),
-                             int(frontier_cap), int(violation_cap))
+                             int(frontier_cap), int(violation_cap), ca)
     st = gfd_stats()
     rc = lib.gfd_validate_ex(graph.handle, specs, n, C.byref(opts), results,
                              C.byref(st) if stats else None)
@@ -348,10 +473,14 @@ class Server:
     request's result dicts (as validate() gives them) and its timing info."""
 
     def __init__(self, graph: GraphHandle, K: int = 1024, semantics: str = "induced",
-                 workers: int = 2, max_batch_gfds: int = 256, mem_budget_bytes: int = 0):
+                 workers: int = 2, max_batch_gfds: int = 256, mem_budget_bytes: int = 0,
+                 allocator="torch"):
         self.graph, self.K = graph, int(K)
+        self.handle = None
+        ca, alloc = _allocator(allocator)
+        graph.keep(alloc)
         opts = gfd_server_opts(int(workers), int(max_batch_gfds), int(mem_budget_bytes), self.K,
-                               GFD_SEM_INDUCED if semantics == "induced" else GFD_SEM_MONO)
+                               GFD_SEM_INDUCED if semantics == "induced" else GFD_SEM_MONO, ca)
         h = C.c_void_p()
         _check(lib.gfd_server_create(graph.handle, C.byref(opts), C.byref(h)))
         self.handle = h
@@ -395,9 +524,10 @@ class Server:
         return out, {f: getattr(info, f) for f, _ in gfd_request_info._fields_}
 
     def close(self):
-        if self.handle:
-            lib.gfd_server_destroy(self.handle)
-            self.handle = None
+        h = getattr(self, "handle", None)
+        if h and lib is not None:
+            lib.gfd_server_destroy(h)
+        self.handle = None
 
     def __del__(self):
         try:

@@ -67,16 +67,56 @@ struct GfdError {
     }                                                                                   \
   } while (0)
 
-template <class T>
-static T* dalloc(size_t count, int64_t* tally = nullptr) {
-  void* p = nullptr;
-  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  HIPCHK(hipMalloc(&p, bytes));
-  if (tally) *tally += (int64_t)bytes;
-  return static_cast<T*>(p);
+// Device memory of a graph or a workspace: the caller's allocator callbacks,
+// or hipMalloc / hipFree when none is given.
+struct DevAlloc {
+  gfd_allocator cb{};
+  hipStream_t st = nullptr;  // the stream handed to cb.alloc
+  int64_t live = 0;          // bytes handed out and not yet returned
+  void* get(size_t bytes) {
+    bytes = std::max<size_t>(bytes, 1);
+    void* p = nullptr;
+    if (cb.alloc) {
+      p = cb.alloc(cb.ctx, (int64_t)bytes, (void*)st);
+      if (!p)
+        throw GfdError{GFD_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
+      if ((uintptr_t)p % 256) {
+        cb.free(cb.ctx, p, (int64_t)bytes);
+        throw GfdError{GFD_EINVAL, "allocator callback returned memory not aligned to 256 bytes"};
+      }
+    } else {
+      HIPCHK(hipMalloc(&p, bytes));
+    }
+    live += (int64_t)bytes;
+    return p;
+  }
+  void put(void* p, size_t bytes) {
+    if (!p) return;
+    bytes = std::max<size_t>(bytes, 1);
+    live -= (int64_t)bytes;
+    if (cb.alloc) cb.free(cb.ctx, p, (int64_t)bytes);
+    else (void)hipFree(p);
+  }
+  bool same(const gfd_allocator& o) const {
+    return cb.alloc == o.alloc && cb.free == o.free && cb.ctx == o.ctx;
+  }
+};
+
+// An allocator option: alloc without free is malformed.
+static int32_t check_allocator(const gfd_allocator& a) {
+  if (a.alloc && !a.free) return set_error(GFD_EINVAL, "allocator has alloc but no free");
+  return GFD_OK;
 }
-static void dfree(void* p) {
-  if (p) (void)hipFree(p);
+
+template <class T>
+static T* dalloc(DevAlloc& al, size_t count) {
+  return static_cast<T*>(al.get(std::max<size_t>(count, 1) * sizeof(T)));
+}
+// Returns p (count elements of T) to al and clears it.
+template <class T>
+static void dfree(DevAlloc& al, T*& p, size_t count) {
+  al.put((void*)p, std::max<size_t>(count, 1) * sizeof(T));
+  p = nullptr;
 }
 // Device-side address of mapped pinned host memory, or null if the runtime
 // gives none (uploads from it then take the DMA copy).
@@ -136,24 +176,44 @@ struct Workspace {
   uint8_t* selrec = nullptr;        // [MAX_JOBS] SelJob records
   uint8_t* hselrec = nullptr;       // pinned staging for them
   const uint8_t* hselrec_dev = nullptr;
-  uint64_t* hmisc = nullptr;        // pinned: [0] CPI cursor, [1] error word, [2..9] class bytes
+  uint64_t* hmisc = nullptr;        // pinned: [0] CPI cursor, [1] error word, [2..9] class bytes,
+                                    // [10] frontier pool cursor
   int32_t* pack = nullptr;          // a batch's reported tuples, back to back
   size_t pack_words = 0;
+  uint8_t* front = nullptr;         // frontier pool of a batch (fast path), bump-allocated
+  size_t front_bytes = 0;           //   on the device level by level (cursor misc[1])
+  size_t front_want = 0;            // pool size the next batch should have (grows with use)
+  size_t cpi_want = 0;              // CPI arena entries the next batch should have
   hipEvent_t pack_ev = nullptr;     // the last packed copy to ws->hres has landed
   int64_t budget = 0;
+  DevAlloc al;                      // where every device buffer above comes from
 
   ~Workspace() {
-    dfree(arena); dfree(cpi_arena); dfree(hitpool); dfree(jobrec); dfree(misc); dfree(err); dfree(chunk);
-    dfree(vbig); dfree(sel_state); dfree(sel_hist); dfree(sel_out); dfree(selrec);
+    dfree(al, arena, arena_bytes);
+    dfree(al, cpi_arena, cpi_cap);
+    dfree(al, hitpool, hitpool_words);
+    dfree(al, jobrec, jobrec_bytes);
+    dfree(al, misc, 16);
+    dfree(al, err, 1);
+    dfree(al, chunk, chunk_bytes);
+    dfree(al, vbig, (size_t)vbig_cap * MAXK);
+    dfree(al, sel_state, (size_t)MAX_JOBS * SEL_STATE_WORDS);
+    dfree(al, sel_hist, (size_t)MAX_JOBS * RADIX_BINS);
+    dfree(al, sel_out, (size_t)SORT_MAX * MAXK);
+    dfree(al, selrec, sizeof(SelJob) * MAX_JOBS);
+    dfree(al, pack, pack_words);
+    dfree(al, front, front_bytes);
     if (hjobrec) (void)hipHostFree(hjobrec);
     if (hselrec) (void)hipHostFree(hselrec);
     if (hmisc) (void)hipHostFree(hmisc);
-    dfree(pack);
     if (pack_ev) (void)hipEventDestroy(pack_ev);
     if (hctl) (void)hipHostFree(hctl);
     if (hres) (void)hipHostFree(hres);
   }
 };
+
+static uint64_t front_usable(const Workspace* ws);
+static uint64_t cpi_usable(const Workspace* ws);
 
 struct gfd_graph {
   int device = 0;
@@ -163,17 +223,32 @@ struct gfd_graph {
   std::vector<uint32_t> lab_off;       // host copy [nvl+1]
   std::vector<uint32_t> elb_blk[2];    // host: first row of each (vertex label, edge label) block
   std::vector<uint32_t> elt_blk[2];    // host: the same per (vertex label, edge label, far label)
+  std::vector<uint32_t> elb_ent[2];    // host: first entry of each (vertex label, edge label) block
+  std::vector<uint32_t> elt_ent[2];    // host: the same per (vertex label, edge label, far label)
   bool triples = false;                // elt_* built
   std::vector<uint64_t> lab_out_sum;   // sum of out-degrees per vertex label
   std::vector<uint64_t> lab_in_sum;
-  std::vector<void*> owned;
+  DevAlloc al;                         // where the graph's device arrays come from
+  std::vector<std::pair<void*, size_t>> owned;
   int64_t device_bytes = 0;
   std::mutex mu;
   std::vector<Workspace*> pool;        // idle workspaces
   std::vector<Workspace*> all;
-  ~gfd_graph() {
+  void drop_workspaces() {
+    if (!all.empty()) {  // with this graph's device current (restored after)
+      int cur = -1;
+      (void)hipGetDevice(&cur);
+      if (cur != device) (void)hipSetDevice(device);
+      (void)hipDeviceSynchronize();
+      if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+    }
     for (auto w : all) delete w;
-    for (auto p : owned) dfree(p);
+    all.clear();
+    pool.clear();
+  }
+  ~gfd_graph() {
+    drop_workspaces();
+    for (auto& p : owned) al.put(p.first, p.second);
   }
 };
 
@@ -194,12 +269,19 @@ static void parallel_for(int64_t n, F f) {
   for (auto& x : th) x.join();
 }
 
-extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
-                                  const int32_t* vlabel, const int32_t* elabel, int32_t num_attrs,
-                                  const int32_t* const* attr, const gfd_load_opts* opts,
-                                  gfd_graph** out) {
+// The loader proper; may throw (GfdError, std::bad_alloc, ...), which the
+// C entry point turns into status codes.
+static int32_t load_graph_impl(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                               const int32_t* vlabel, const int32_t* elabel, int32_t num_attrs,
+                               const int32_t* const* attr, const gfd_load_opts* opts,
+                               gfd_graph** out) {
   if (!out) return set_error(GFD_EINVAL, "out is NULL");
   *out = nullptr;
+  gfd_load_opts lo{};
+  if (opts) lo = *opts;
+  if (lo.mem_kind != GFD_MEM_HOST && lo.mem_kind != GFD_MEM_DEVICE)
+    return set_error(GFD_EINVAL, "mem_kind %d", lo.mem_kind);
+  if (int32_t rc = check_allocator(lo.allocator)) return rc;
   if (n < 0 || m < 0 || num_attrs < 0) return set_error(GFD_EINVAL, "negative size");
   if (n >= (int64_t(1) << 31)) return set_error(GFD_EUNSUPPORTED, "n >= 2^31");
   if (m >= (int64_t(1) << 32) - 1) return set_error(GFD_EUNSUPPORTED, "m >= 2^32-1");
@@ -207,6 +289,35 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     return set_error(GFD_EINVAL, "null input array");
   for (int32_t a = 0; a < num_attrs; a++)
     if (n > 0 && !attr[a]) return set_error(GFD_EINVAL, "attribute column %d is NULL", a);
+  hipStream_t st = (hipStream_t)lo.hip_stream;
+  // device-resident inputs are read into host copies first (the views below
+  // are built on the host)
+  std::vector<int64_t> h_row;
+  std::vector<int32_t> h_col, h_vl, h_el, h_attr;
+  std::vector<const int32_t*> h_attr_ptr;
+  if (lo.mem_kind == GFD_MEM_DEVICE) {
+    auto rd = [&](auto& vec, const void* src, size_t count) {
+      vec.resize(count);
+      if (count)
+        HIPCHK(hipMemcpyAsync(vec.data(), src, count * sizeof(vec[0]), hipMemcpyDeviceToHost, st));
+    };
+    rd(h_row, row_ptr, (size_t)n + 1);
+    rd(h_col, col, (size_t)m);
+    rd(h_vl, vlabel, (size_t)n);
+    rd(h_el, elabel, (size_t)m);
+    h_attr.resize((size_t)num_attrs * n);
+    for (int32_t a = 0; a < num_attrs; a++)
+      if (n)
+        HIPCHK(hipMemcpyAsync(h_attr.data() + (size_t)a * n, attr[a], sizeof(int32_t) * n,
+                              hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int32_t a = 0; a < num_attrs; a++) h_attr_ptr.push_back(h_attr.data() + (size_t)a * n);
+    row_ptr = h_row.data();
+    col = h_col.data();
+    vlabel = h_vl.data();
+    elabel = h_el.data();
+    attr = h_attr_ptr.data();
+  }
   if (row_ptr[0] != 0 || row_ptr[n] != m) return set_error(GFD_EINVAL, "row_ptr must run from 0 to m");
   for (int64_t v = 0; v < n; v++)
     if (row_ptr[v + 1] < row_ptr[v]) return set_error(GFD_EINVAL, "row_ptr decreases at %lld", (long long)v);
@@ -220,6 +331,12 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     if (elabel[e] < 0) return set_error(GFD_EINVAL, "negative edge label at %lld", (long long)e);
     maxel = std::max(maxel, elabel[e]);
   }
+  // host tables are sized by the largest label ids (label buckets) and by
+  // their product (edge-label block keys)
+  if (maxvl > GFD_MAX_LABEL || maxel > GFD_MAX_LABEL)
+    return set_error(GFD_EUNSUPPORTED, "label id above %d (vertex %d, edge %d)", GFD_MAX_LABEL, maxvl, maxel);
+  if ((int64_t)(maxvl + 1) * (int64_t)std::max(maxel + 1, 1) > (int64_t)GFD_MAX_LABEL_PAIRS)
+    return set_error(GFD_EUNSUPPORTED, "more than %d (vertex label, edge label) pairs", GFD_MAX_LABEL_PAIRS);
   for (int32_t a = 0; a < num_attrs; a++)
     for (int64_t v = 0; v < n; v++)
       if (attr[a][v] < GFD_ABSENT) return set_error(GFD_EINVAL, "attribute %d value < -1 at %lld", a, (long long)v);
@@ -257,7 +374,7 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
       }
   }
   // label buckets (counting sort, ascending ids within a label)
-  int32_t nvl = maxvl + 1;
+  const int32_t nvl = maxvl + 1;  // <= GFD_MAX_LABEL + 1: no overflow
   std::vector<uint32_t> lab_off(nvl + 1, 0);
   std::vector<int32_t> lab_vtx(n);
   std::vector<uint64_t> lab_out(nvl, 0), lab_in(nvl, 0);
@@ -359,6 +476,7 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
   const bool triples = npair * (size_t)nvl <= LABEL_TRIPLES_MAX;
   struct Blocks {
     std::vector<uint32_t> row, start, blk;  // blk: [keys + 1] first row of each block
+    std::vector<uint32_t> ent;              // [keys + 1] first entry of each block
     std::vector<int32_t> nbr;
   };
   Blocks elb[2], elt[2];
@@ -400,6 +518,7 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     B.start.assign(rows[nkeys] + 1, 0);
     B.nbr.assign(ents[nkeys], 0);
     B.blk.assign(rows.begin(), rows.end());
+    B.ent.assign(ents.begin(), ents.end());
     std::vector<uint64_t> rcur(rows.begin(), rows.end() - 1), ecur(ents.begin(), ents.end() - 1);
     parallel_for(nvl, [&](int64_t l0, int64_t l1) {
       std::vector<std::pair<int64_t, int32_t>> es;
@@ -427,13 +546,16 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
   for (int32_t a = 0; a < num_attrs; a++)
     std::memcpy(attr_flat.data() + (size_t)a * n, attr[a], sizeof(int32_t) * n);
 
-  gfd_graph* g = new gfd_graph();
-  try {
+  std::unique_ptr<gfd_graph> gp(new gfd_graph());
+  gfd_graph* g = gp.get();
+  {
     HIPCHK(hipGetDevice(&g->device));
-    hipStream_t st = opts ? (hipStream_t)opts->hip_stream : nullptr;
+    g->al.cb = lo.allocator;
+    g->al.st = st;
     auto up = [&](const void* src, size_t bytes) -> void* {
-      void* p = dalloc<uint8_t>(bytes, &g->device_bytes);
-      g->owned.push_back(p);
+      void* p = g->al.get(bytes);
+      g->owned.push_back({p, std::max<size_t>(bytes, 1)});
+      g->device_bytes += (int64_t)std::max<size_t>(bytes, 1);
       if (bytes) HIPCHK(hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, st));
       return p;
     };
@@ -468,11 +590,13 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
       g->dg.elb_start[d] = (const uint32_t*)up(elb[d].start.data(), 4 * elb[d].start.size());
       g->dg.elb_nbr[d] = (const int32_t*)up(elb[d].nbr.data(), 4 * elb[d].nbr.size());
       g->elb_blk[d] = std::move(elb[d].blk);
+      g->elb_ent[d] = std::move(elb[d].ent);
       if (triples) {
         g->dg.elt_row[d] = (const uint32_t*)up(elt[d].row.data(), 4 * elt[d].row.size());
         g->dg.elt_start[d] = (const uint32_t*)up(elt[d].start.data(), 4 * elt[d].start.size());
         g->dg.elt_nbr[d] = (const int32_t*)up(elt[d].nbr.data(), 4 * elt[d].nbr.size());
         g->elt_blk[d] = std::move(elt[d].blk);
+        g->elt_ent[d] = std::move(elt[d].ent);
       }
     }
     g->triples = triples;
@@ -480,15 +604,56 @@ extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, 
     g->lab_off = std::move(lab_off);
     g->lab_out_sum = std::move(lab_out);
     g->lab_in_sum = std::move(lab_in);
-  } catch (const GfdError& e) {
-    delete g;
-    return set_error(e.code, "%s", e.msg.c_str());
   }
-  *out = g;
+  *out = gp.release();
   return GFD_OK;
 }
 
-extern "C" void gfd_free_graph(gfd_graph* g) { delete g; }
+// Runs f, turning every exception into a status code and message: no C++
+// exception crosses the C ABI.
+template <class F>
+static int32_t guarded(F f) {
+  try {
+    return f();
+  } catch (const GfdError& e) {
+    return set_error(e.code, "%s", e.msg.c_str());
+  } catch (const std::bad_alloc&) {
+    return set_error(GFD_ENOMEM, "host allocation failed");
+  } catch (const std::length_error& e) {
+    return set_error(GFD_ENOMEM, "host allocation too large: %s", e.what());
+  } catch (const std::exception& e) {
+    return set_error(GFD_EDEVICE, "unexpected failure: %s", e.what());
+  } catch (...) {
+    return set_error(GFD_EDEVICE, "unexpected failure");
+  }
+}
+
+extern "C" int32_t gfd_load_graph(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                                  const int32_t* vlabel, const int32_t* elabel, int32_t num_attrs,
+                                  const int32_t* const* attr, const gfd_load_opts* opts,
+                                  gfd_graph** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    return load_graph_impl(n, m, row_ptr, col, vlabel, elabel, num_attrs, attr, opts, out);
+  });
+}
+
+extern "C" void gfd_free_graph(gfd_graph* g) {
+  try {
+    delete g;
+  } catch (...) {
+  }
+}
+
+extern "C" int32_t gfd_trim(gfd_graph* g) {
+  if (!g) return set_error(GFD_EINVAL, "graph is NULL");
+  return guarded([&] {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (g->pool.size() != g->all.size()) return set_error(GFD_EINVAL, "a validate call is running");
+    g->drop_workspaces();
+    return GFD_OK;
+  });
+}
 
 extern "C" int32_t gfd_get_graph_info(const gfd_graph* g, gfd_graph_info* info) {
   if (!g || !info) return set_error(GFD_EINVAL, "null argument");
@@ -771,7 +936,8 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Host-side capacities of one job.
 struct JobCaps {
-  uint64_t cap_u[MAXK];
+  uint64_t cap_u[MAXK];   // label bucket of u (items of its direct filters, position maps)
+  uint64_t lcap_u[MAXK];  // bound on |C(u)| (list_cap): candidate lists, CPI heads
   uint64_t cap_f;   // frontier partial matches per level
   uint64_t pcap;    // largest scan (items) + 1
   uint64_t tiles;   // scan tile states
@@ -809,6 +975,35 @@ struct Job {
   bool last_single = false;    // that record is a single-vertex (k == 1) one
 };
 
+// Data edges of the label block (bucket L, edge label e, far end's label
+// far) in direction dir: an upper bound on the distinct far ends it holds.
+static uint64_t block_entries(const gfd_graph* g, int32_t L, int32_t e, int32_t far, int dir) {
+  if (L == ANY) return (uint64_t)g->m;
+  if (L >= g->nvl) return 0;
+  if (e == ANY) return dir ? g->lab_in_sum[L] : g->lab_out_sum[L];
+  if (e >= g->nel) return 0;
+  const size_t b = (size_t)L * g->nel + e;
+  if (g->triples && far != ANY) {
+    if (far >= g->nvl) return 0;
+    const size_t t = b * g->nvl + far;
+    return g->elt_ent[dir][t + 1] - g->elt_ent[dir][t];
+  }
+  return g->elb_ent[dir][b + 1] - g->elb_ent[dir][b];
+}
+
+// Upper bound on |C(u)| at every step: u's label bucket, and for each
+// pattern edge to an earlier neighbour w in BFS order, the far ends of that
+// edge's label block -- the top-down step keeps only vertices adjacent to a
+// candidate of w through such an edge, and later steps only drop members.
+static uint64_t list_cap(const gfd_graph* g, const Plan& p, int u) {
+  uint64_t cap = bucket_size(g, p.qlab[u]);
+  for (int w : p.down[u]) {
+    if (p.qe[w][u] != NOEDGE) cap = std::min(cap, block_entries(g, p.qlab[w], p.qe[w][u], p.qlab[u], 0));
+    if (p.qe[u][w] != NOEDGE) cap = std::min(cap, block_entries(g, p.qlab[w], p.qe[u][w], p.qlab[u], 1));
+  }
+  return cap;
+}
+
 static int pattern_edges_between(const Plan& p, int u, const std::vector<int>& nbrs) {
   int c = 0;
   for (int w : nbrs) c += (p.qe[w][u] != NOEDGE) + (p.qe[u][w] != NOEDGE);
@@ -821,21 +1016,26 @@ static uint64_t per_slot_bytes(int k) {
   return b;
 }
 
-static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t vcap, JobCaps& c) {
+// frontiers: the job gets its own frontier columns of cap_f partial matches
+// for every level (the bounded path); the fast path reserves its frontiers
+// from the batch's pool instead, by the attempts each level counts.
+static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t vcap, bool frontiers,
+                     JobCaps& c) {
   const int k = p.k;
   uint64_t items = 1, hits = 1, cons = 1;
   for (int u = 0; u < k; u++) {
     c.cap_u[u] = bucket_size(g, p.qlab[u]);
+    c.lcap_u[u] = list_cap(g, p, u);
     hits = std::max(hits, c.cap_u[u]);
     const uint64_t nc = (uint64_t)std::max(pattern_edges_between(p, u, p.down[u]),
                                            pattern_edges_between(p, u, p.up[u]));
     cons = std::max(cons, nc);
-    items = std::max(items, c.cap_u[u] * std::max<uint64_t>(nc, 1));
+    items = std::max(items, c.lcap_u[u] * std::max<uint64_t>(nc, 1));
   }
   c.hit_words = hits / 32 + 1;
   c.hit_cons = cons;
   c.hit_region = cons * c.hit_words * 8;  // hit bytes (32 * hit_words per constraint) or bitmaps
-  c.cap_f = k > 2 ? cap_f : 1;
+  c.cap_f = (frontiers && k > 2) ? cap_f : 0;
   items = std::max(items, c.cap_f);
   c.pcap = items + 1;
   c.tiles = items / SCAN_TILE + 2;
@@ -843,17 +1043,17 @@ static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t
   c.begs = std::max(c.cap_u[p.root], c.cap_f);
   c.vcap = vcap;
   size_t b = 0;
-  for (int u = 0; u < k; u++)                                          // positions (parents)
-    if (p.is_parent[u]) b += align_up(sizeof(int32_t) * (size_t)g->n);
+  for (int u = 0; u < k; u++)  // positions (parents), indexed by bucket position
+    if (p.is_parent[u]) b += align_up(sizeof(int32_t) * std::max<size_t>(c.cap_u[u], 1));
   b += 2 * align_up(4 * ((size_t)g->n / 32 + 1)) * k;                  // membership bitmaps
-  for (int u = 0; u < k; u++) b += 2 * align_up(4 * c.cap_u[u]);       // candidate lists
+  for (int u = 0; u < k; u++) b += 2 * align_up(4 * c.lcap_u[u]);      // candidate lists
   b += align_up(8 * c.pcap);
   for (int u = 0; u < k; u++)
-    if (u != p.root) b += 3 * align_up(4 * c.cap_u[p.parent[u]]);    // CPI list heads
+    if (u != p.root) b += 3 * align_up(4 * c.lcap_u[p.parent[u]]);   // CPI list heads
   for (int i = 2; i < k; i++) b += align_up(4ull * i * c.cap_f);      // frontier columns
   b += align_up(4 * c.begs);
   b += align_up(4 * c.vcap * k);
-  if (p.leaf_r) b += align_up(4ull * LEAF_WORDS * c.cap_u[p.leaf_par]);
+  if (p.leaf_r) b += align_up(4ull * LEAF_WORDS * c.lcap_u[p.leaf_par]);
   c.bytes = b;
 }
 
@@ -869,20 +1069,20 @@ static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const J
   std::memset(&m.pos, 0, sizeof m.pos);
   // position maps are read only through the CPI lists of tree children
   for (int u = 0; u < k; u++)
-    m.pos[u] = p.is_parent[u] ? (int32_t*)take(sizeof(int32_t) * (size_t)g->n) : nullptr;
+    m.pos[u] = p.is_parent[u] ? (int32_t*)take(sizeof(int32_t) * std::max<size_t>(c.cap_u[u], 1)) : nullptr;
   for (int u = 0; u < k; u++) {
     m.bits[u][0] = (uint32_t*)take(4 * ((size_t)g->n / 32 + 1));
     m.bits[u][1] = (uint32_t*)take(4 * ((size_t)g->n / 32 + 1));
   }
   for (int u = 0; u < k; u++) {
-    m.cand[u][0] = (int32_t*)take(4 * c.cap_u[u]);
-    m.cand[u][1] = (int32_t*)take(4 * c.cap_u[u]);
+    m.cand[u][0] = (int32_t*)take(4 * c.lcap_u[u]);
+    m.cand[u][1] = (int32_t*)take(4 * c.lcap_u[u]);
   }
   m.P = (uint64_t*)take(8 * c.pcap);
   for (int u = 0; u < k; u++) {
     m.cpi_beg[u] = m.cpi_len[u] = m.cpi_cur[u] = nullptr;
     if (u == p.root) continue;
-    const uint64_t cp = c.cap_u[p.parent[u]];
+    const uint64_t cp = c.lcap_u[p.parent[u]];
     m.cpi_beg[u] = (uint32_t*)take(4 * cp);
     m.cpi_len[u] = (uint32_t*)take(4 * cp);
     m.cpi_cur[u] = (uint32_t*)take(4 * cp);
@@ -891,7 +1091,7 @@ static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const J
   for (int i = 2; i < k; i++) m.cols[i] = (int32_t*)take(4ull * i * c.cap_f);
   m.begs = (uint32_t*)take(4 * c.begs);
   m.vbuf = (int32_t*)take(4 * c.vcap * k);
-  m.leaf_cnt = p.leaf_r ? (uint32_t*)take(4ull * LEAF_WORDS * c.cap_u[p.leaf_par]) : nullptr;
+  m.leaf_cnt = p.leaf_r ? (uint32_t*)take(4ull * LEAF_WORDS * c.lcap_u[p.leaf_par]) : nullptr;
 }
 
 struct Ctx {
@@ -900,6 +1100,7 @@ struct Ctx {
   hipStream_t st;
   bool induced;
   int K;
+  uint64_t front_limit;  // testing: at most this many partial matches per level (0: none)
   Timer tm;
   gfd_stats* stats;
   unsigned long long* stat_bytes;  // device [8] per kernel class, or nullptr
@@ -917,7 +1118,7 @@ static uint32_t next_epoch(Ctx& c) {
 
 static CandSet cand_set(const Job& J, int u) {
   return CandSet{J.mem.cand[u][J.cur[u]], J.mem.ctl + CTL_CAND + 2 * u + J.cur[u], J.mem.pos[u],
-                 J.mem.bits[u][J.cur[u]]};
+                 J.mem.bits[u][J.cur[u]], J.plan.qlab[u] != ANY ? 1 : 0};
 }
 
 static JobScan job_scan_rec(Ctx& c, const Job& J, uint64_t* d_total, uint32_t epoch) {
@@ -1010,6 +1211,39 @@ static uint64_t rows_ub(const gfd_graph* g, int32_t L, int dir) {
   return dir ? g->lab_in_sum[L] : g->lab_out_sum[L];
 }
 
+// Estimated frontier-pool bytes of one job's fast enumeration: the level-i
+// reservation takes (attempts of level i) slots, and attempts are estimated
+// level by level as sources times the tree edge's mean fan-out -- the data
+// edges from the parent's label bucket with the edge's label and direction
+// and the child's label, over the bucket's size.  Non-tree checks and
+// injectivity are ignored, so inner levels are over-estimated, while skewed
+// degrees can make real fan-outs larger than the mean: the estimate sizes the
+// pool of a fresh workspace and serving admission, and the pool still grows
+// to what batches ask for.
+static double fan_out(const gfd_graph* g, int32_t L, int32_t e, int32_t far, int dir) {
+  const double nb = (double)std::max<uint64_t>(1, L == ANY ? (uint64_t)g->n
+                                                   : (L < g->nvl ? g->lab_off[L + 1] - g->lab_off[L] : 0));
+  if (L == ANY || L >= g->nvl) return (double)g->m / std::max<int64_t>(1, g->n);
+  if (e == ANY || e >= g->nel) return (double)rows_ub(g, L, dir) / nb;
+  const size_t b = (size_t)L * g->nel + e;
+  if (g->triples && far != ANY && far < g->nvl) {
+    const size_t t = b * g->nvl + far;
+    return (double)(g->elt_ent[dir][t + 1] - g->elt_ent[dir][t]) / nb;
+  }
+  return (double)(g->elb_ent[dir][b + 1] - g->elb_ent[dir][b]) / nb;
+}
+static uint64_t est_front_bytes(const gfd_graph* g, const Plan& p) {
+  double N = (double)bucket_size(g, p.qlab[p.root]), bytes = 0;
+  for (int i = 1; i < p.k_enum; i++) {
+    const int u = p.order[i], q = p.parent[u];
+    const double T = N * fan_out(g, p.qlab[q], p.adj_prim[u], p.qlab[u], p.adj_dir[u]);
+    const bool last = p.leaf_r == 0 && i == p.k - 1;
+    if (!last) bytes += T * (4.0 * (i + 1) + 12.0) + 1024.0;
+    N = T;
+  }
+  return (uint64_t)std::min(bytes, 1e18);
+}
+
 // Job records of every step of a batch, staged host side and uploaded once.
 struct Recs {
   std::vector<uint8_t> blob;
@@ -1024,10 +1258,9 @@ struct Recs {
 
 static void ensure_recs(Workspace* ws, size_t bytes) {
   if (ws->jobrec_bytes < bytes) {
-    dfree(ws->jobrec);
-    ws->jobrec = nullptr;
+    dfree(ws->al, ws->jobrec, ws->jobrec_bytes);
     ws->jobrec_bytes = 0;
-    ws->jobrec = dalloc<uint8_t>(bytes);
+    ws->jobrec = dalloc<uint8_t>(ws->al, bytes);
     ws->jobrec_bytes = bytes;
   }
   if (ws->hjobrec_bytes < bytes) {
@@ -1069,6 +1302,8 @@ struct Launch {
   bool row_scan = false;  // filter: some job's pull needs the (item, constraint) row scan
   bool hit_bitmaps = false;  // filter: the jobs record hits in bitmaps (top-down steps)
   bool cpi_two_pass = false;  // CPI: count kept entries first (the bounded path)
+  size_t next_off = SIZE_MAX;  // enumeration: the next level's records (frontier reservation)
+  size_t leaf_off = SIZE_MAX;  // enumeration: the leaf-count records, if any
 };
 
 // The launches of a batch in order.  When on_add is set (the fast path), it
@@ -1120,8 +1355,10 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       J.cur[u] = 0;
       f.out = J.mem.cand[u][0];
+      f.out_cap = J.caps.lcap_u[u];
       f.d_out_n = J.mem.ctl + CTL_CAND + 2 * u;
       f.pos = J.mem.pos[u];
+      f.pos_by_bucket = p.qlab[u] != ANY ? 1 : 0;
       f.bits = J.mem.bits[u][0];
       f.nwords = (uint64_t)g->n / 32 + 1;
       items = std::max(items, bs);
@@ -1168,7 +1405,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       } else {
         f.list = cur.list;
         f.d_n = cur.cnt;
-        f.cap = J.caps.cap_u[u];
+        f.cap = J.caps.lcap_u[u];
         // labelled constraints read the item's run in the edge-label block
         for (int q = 0; q < f.ncons; q++) {
           PullC& pc = f.cons[q];
@@ -1182,8 +1419,10 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       f.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       J.cur[u] ^= 1;
       f.out = J.mem.cand[u][J.cur[u]];
+      f.out_cap = J.caps.lcap_u[u];
       f.d_out_n = J.mem.ctl + CTL_CAND + 2 * u + J.cur[u];
       f.pos = J.mem.pos[u];
+      f.pos_by_bucket = p.qlab[u] != ANY ? 1 : 0;
       f.bits = J.mem.bits[u][J.cur[u]];
       f.nwords = (uint64_t)g->n / 32 + 1;
       items = std::max(items, f.cap);
@@ -1216,14 +1455,14 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       a.other = p.adj_other[u];
       a.p = cand_set(J, q);
       a.u = cand_set(J, u);
-      a.cap_p = J.caps.cap_u[q];
+      a.cap_p = J.caps.lcap_u[q];
       a.beg = J.mem.cpi_beg[u];
       a.len = J.mem.cpi_len[u];
       a.cur = J.mem.cpi_cur[u];
       a.d_base = J.mem.ctl + CTL_CPIBASE;
       a.arena = c.ws->cpi_arena;
       a.arena_cursor = c.ws->misc;
-      a.arena_cap = c.ws->cpi_cap;
+      a.arena_cap = cpi_usable(c.ws);
       a.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
       a.sc = job_scan_rec(c, J, J.mem.ctl + CTL_TOTAL, ep);
       a.blk = 0;
@@ -1240,16 +1479,21 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
                          true, false, false, false, false, !fast_enum});
   }
   if (!fast_enum) return;
-  // enumeration levels (core-first matching order) with the fused check
+  // enumeration levels (core-first matching order) with the fused check.
+  // Every level's records (and the leaf counts') are built and added before
+  // the first level is enqueued: an inner level's frontier reservation
+  // writes the next level's records on the device.
+  std::vector<std::vector<ExtJob>> E(maxk);
+  std::vector<LeafJob> F(nj);
+  bool any_leaf = false;
+  uint64_t leaf_np = 1;
   for (int i = 1; i < maxk; i++) {
-    std::vector<ExtJob> E(nj);
-    uint64_t srcs = 1;
-    bool any_last = false, any_inner = false;
+    E[i].resize(nj);
     const uint32_t ep = next_epoch(c);
     for (int x = 0; x < nj; x++) {
       Job& J = jobs[x];
       const Plan& p = J.plan;
-      ExtJob& e = E[x];
+      ExtJob& e = E[i][x];
       e = ExtJob{};
       if (i >= p.k_enum) continue;  // postponed leaves are counted, not enumerated
       const int u = p.order[i], q = p.parent[u];
@@ -1257,25 +1501,30 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       e.i = i;
       e.k = p.k;
       e.last = p.leaf_r == 0 && i == p.k - 1;
+      e.begs = J.mem.begs;
+      e.sc = job_scan_rec(c, J, J.mem.ctl + CTL_LEVEL_T + i, ep);
       if (i == 1) {
         const CandSet r = cand_set(J, p.root);
         e.src_cols = r.list;
         e.src_stride = 0;
         e.d_nsrc = r.cnt;
-        e.src_cap = J.caps.cap_u[p.root];
+        e.src_cap = J.caps.lcap_u[p.root];
       } else {
-        e.src_cols = J.mem.cols[i];
-        e.src_stride = J.caps.cap_f;
+        // the previous level's reservation points src_*, begs and the scan's
+        // prefix and tile states at its pool slots; until then (and if the
+        // pool could not hold it) the level has no sources and its scan
+        // writes only its zero total into the job's own arrays
+        e.src_cols = J.mem.cand[p.root][0];
+        e.src_stride = 0;
         e.d_nsrc = J.mem.ctl + CTL_LEVEL_N + i;
-        e.src_cap = J.caps.cap_f;
+        e.src_cap = 0;
       }
       e.par_pos = p.pos[q];
       e.par_posmap = J.mem.pos[q];
+      e.par_by_bucket = p.qlab[q] != ANY ? 1 : 0;
       e.cpi_beg = J.mem.cpi_beg[u];
       e.cpi_len = J.mem.cpi_len[u];
       e.cpi_ent = c.ws->cpi_arena;
-      e.begs = J.mem.begs;
-      e.sc = job_scan_rec(c, J, J.mem.ctl + CTL_LEVEL_T + i, ep);
       e.a_begin = 0;
       e.a_end = ~0ull;
       e.nchk = p.nchk[i];
@@ -1284,9 +1533,8 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
         e.chk_fwd[t] = t < p.nchk[i] ? p.chk_fwd[i][t] : PC_FREE;
         e.chk_bwd[t] = t < p.nchk[i] ? p.chk_bwd[i][t] : PC_FREE;
       }
-      if (!e.last) {
-        e.dst_cols = J.mem.cols[i + 1];
-        e.dst_cap = J.caps.cap_f;
+      if (!e.last) {  // dst_* come from the reservation
+        e.front_limit = c.front_limit;
         e.d_ndst = J.mem.ctl + CTL_LEVEL_N + i + 1;
       }
       e.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
@@ -1301,25 +1549,90 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       e.vcap = c.K > 0 ? J.caps.vcap : 0;
       e.thr = nullptr;
       e.d_thr_valid = (const uint32_t*)(J.mem.ctl + CTL_THRVALID);
-      srcs = std::max(srcs, e.src_cap);
+    }
+  }
+  // postponed leaves: completions counted per partial match of the inner part
+  for (int x = 0; x < nj; x++) {
+    Job& J = jobs[x];
+    const Plan& p = J.plan;
+    LeafJob& f = F[x];
+    f = LeafJob{};
+    if (!p.leaf_r) continue;
+    const int u0 = p.order[p.k - 1], q = p.leaf_par;
+    f.active = 1;
+    f.i = p.k_enum;
+    f.r = p.leaf_r;
+    if (p.k_enum == 1) {
+      const CandSet r = cand_set(J, p.root);
+      f.src_cols = r.list;
+      f.src_stride = 0;
+      f.d_nsrc = r.cnt;
+      f.src_cap = J.caps.lcap_u[p.root];
+    } else {  // the last inner level's reservation sets src_*
+      f.src_cols = J.mem.cand[p.root][0];
+      f.src_stride = 0;
+      f.d_nsrc = J.mem.ctl + CTL_LEVEL_N + p.k_enum;
+      f.src_cap = 0;
+    }
+    f.par_pos = p.pos[q];
+    f.par_posmap = J.mem.pos[q];
+    f.par_by_bucket = p.qlab[q] != ANY ? 1 : 0;
+    const CandSet pc = cand_set(J, q);
+    f.d_np = pc.cnt;
+    f.cap_p = J.caps.lcap_u[q];
+    f.cpi_beg = J.mem.cpi_beg[u0];
+    f.cpi_len = J.mem.cpi_len[u0];
+    f.cpi_ent = c.ws->cpi_arena;
+    f.u = cand_set(J, u0);
+    f.dir = p.adj_dir[u0];
+    f.prim = p.adj_prim[u0];
+    f.other = p.adj_other[u0];
+    f.cnt = J.mem.leaf_cnt;
+    f.nx = p.nx;
+    f.ny = p.ny;
+    f.y_false = p.y_false;
+    for (int t = 0; t < 2 * MAXLIT; t++) {
+      f.lit[t] = p.lit[t];
+      f.lit_leaf[t] = p.lit_leaf[t];
+    }
+    f.counters = (unsigned long long*)(J.mem.ctl + CTL_MATCH);
+    f.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
+    leaf_np = std::max(leaf_np, f.cap_p);
+    any_leaf = true;
+  }
+  std::vector<size_t> eoff(maxk, SIZE_MAX);
+  for (int i = 1; i < maxk; i++) eoff[i] = R.add(E[i]);
+  const size_t leaf_off = any_leaf ? R.add(F) : SIZE_MAX;
+  for (int i = 1; i < maxk; i++) {
+    bool any_last = false, any_inner = false;
+    for (int x = 0; x < nj; x++) {
+      const ExtJob& e = E[i][x];
+      if (!e.active) continue;
       any_last |= e.last != 0;
       any_inner |= e.last == 0;
+      if (e.last) jobs[x].last_rec = eoff[i] + sizeof(ExtJob) * x;
     }
-    const size_t off = R.add(E);
-    for (int x = 0; x < nj; x++)
-      if (E[x].active && E[x].last) jobs[x].last_rec = off + sizeof(ExtJob) * x;
-    L.push_back(Launch{2, off, nj, scan_grid(nj, srcs), flat_grid(FLAT_GRID_MAX), 0, 0, true, any_last,
-                       any_inner});
+    // level 1's sources are the roots' candidates; deeper levels' sizes are
+    // known only on the device, so their scans get the full grid
+    uint64_t srcs = i == 1 ? 1 : ~0ull;
+    if (i == 1)
+      for (int x = 0; x < nj; x++)
+        if (E[i][x].active) srcs = std::max(srcs, E[i][x].src_cap);
+    Launch l{2, eoff[i], nj, i == 1 ? scan_grid(nj, srcs) : (int)FLAT_GRID_MAX, flat_grid(FLAT_GRID_MAX), 0, 0,
+             true, any_last, any_inner};
+    l.next_off = i + 1 < maxk ? eoff[i + 1] : SIZE_MAX;
+    l.leaf_off = leaf_off;
+    L.push_back(l);
   }
   // single-vertex patterns
   {
-    std::vector<ExtJob> E(nj);
+    std::vector<ExtJob> S(nj);
     bool any = false;
     uint64_t items = 1;
     for (int x = 0; x < nj; x++) {
       Job& J = jobs[x];
       const Plan& p = J.plan;
-      ExtJob& e = E[x];
+      ExtJob& e = S[x];
       e = ExtJob{};
       if (p.k != 1) continue;
       const CandSet r = cand_set(J, p.root);
@@ -1328,7 +1641,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       e.last = 1;
       e.src_cols = r.list;
       e.d_nsrc = r.cnt;
-      e.src_cap = J.caps.cap_u[p.root];
+      e.src_cap = J.caps.lcap_u[p.root];
       e.a_begin = 0;
       e.a_end = ~0ull;
       e.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
@@ -1346,72 +1659,19 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       any = true;
     }
     if (any) {
-      const size_t off = R.add(E);
+      const size_t off = R.add(S);
       for (int x = 0; x < nj; x++)
-        if (E[x].active) {
+        if (S[x].active) {
           jobs[x].last_rec = off + sizeof(ExtJob) * x;
           jobs[x].last_single = true;
         }
       L.push_back(Launch{3, off, nj, 0, gx_for(items, nj), 0, 0, false, true, false});
     }
   }
-  // postponed leaves: completions counted per partial match of the inner part
-  {
-    std::vector<LeafJob> F(nj);
-    bool any = false;
-    uint64_t np = 1, srcs = 1;
-    for (int x = 0; x < nj; x++) {
-      Job& J = jobs[x];
-      const Plan& p = J.plan;
-      LeafJob& f = F[x];
-      f = LeafJob{};
-      if (!p.leaf_r) continue;
-      const int u0 = p.order[p.k - 1], q = p.leaf_par;
-      f.active = 1;
-      f.i = p.k_enum;
-      f.r = p.leaf_r;
-      if (p.k_enum == 1) {
-        const CandSet r = cand_set(J, p.root);
-        f.src_cols = r.list;
-        f.src_stride = 0;
-        f.d_nsrc = r.cnt;
-        f.src_cap = J.caps.cap_u[p.root];
-      } else {
-        f.src_cols = J.mem.cols[p.k_enum];
-        f.src_stride = J.caps.cap_f;
-        f.d_nsrc = J.mem.ctl + CTL_LEVEL_N + p.k_enum;
-        f.src_cap = J.caps.cap_f;
-      }
-      f.par_pos = p.pos[q];
-      f.par_posmap = J.mem.pos[q];
-      const CandSet pc = cand_set(J, q);
-      f.d_np = pc.cnt;
-      f.cap_p = J.caps.cap_u[q];
-      f.cpi_beg = J.mem.cpi_beg[u0];
-      f.cpi_len = J.mem.cpi_len[u0];
-      f.cpi_ent = c.ws->cpi_arena;
-      f.u = cand_set(J, u0);
-      f.dir = p.adj_dir[u0];
-      f.prim = p.adj_prim[u0];
-      f.other = p.adj_other[u0];
-      f.cnt = J.mem.leaf_cnt;
-      f.nx = p.nx;
-      f.ny = p.ny;
-      f.y_false = p.y_false;
-      for (int t = 0; t < 2 * MAXLIT; t++) {
-        f.lit[t] = p.lit[t];
-        f.lit_leaf[t] = p.lit_leaf[t];
-      }
-      f.counters = (unsigned long long*)(J.mem.ctl + CTL_MATCH);
-      np = std::max(np, f.cap_p);
-      srcs = std::max(srcs, f.src_cap);
-      any = true;
-    }
-    if (any)
-      L.push_back(Launch{5, R.add(F), nj, 0, flat_grid(FLAT_GRID_MAX), (int)std::min<uint64_t>(
-                             FLAT_GRID_MAX, std::max<uint64_t>(1, (np + BS - 1) / BS * (uint64_t)nj)),
-                         0, false, false, false});
-  }
+  if (any_leaf)
+    L.push_back(Launch{5, leaf_off, nj, 0, flat_grid(FLAT_GRID_MAX), (int)std::min<uint64_t>(
+                           FLAT_GRID_MAX, std::max<uint64_t>(1, (leaf_np + BS - 1) / BS * (uint64_t)nj)),
+                       0, false, false, false});
   if (c.K > 0) {
     std::vector<TopkJob> T(nj);
     for (int x = 0; x < nj; x++) {
@@ -1458,6 +1718,13 @@ static void run_launch(Ctx& c, const Launch& l) {
       case 2: {
         auto* r = (const ExtJob*)(base + l.off);
         c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, r, l.njobs, l.gx_scan); });
+        if (l.inner_any)  // next frontiers, sized by this level's attempts
+          c.tm.run(K_OTHER, [&] {
+            front_reserve(c.st, (ExtJob*)(base + l.off),
+                          l.next_off == SIZE_MAX ? nullptr : (ExtJob*)(base + l.next_off),
+                          l.leaf_off == SIZE_MAX ? nullptr : (LeafJob*)(base + l.leaf_off), l.njobs,
+                          c.ws->front, front_usable(c.ws), c.ws->misc + 1);
+          });
         if (l.inner_any)
           c.tm.run(K_EXT, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, false, false, cls_bytes(c, K_EXT)); });
         if (l.last_any)
@@ -1559,10 +1826,9 @@ struct ResultDrain {
     const size_t words = (size_t)K * MAXK * jobs.size();
     ensure_hres(c.ws, words);
     if (c.ws->pack_words < words) {
-      dfree(c.ws->pack);
-      c.ws->pack = nullptr;
+      dfree(c.ws->al, c.ws->pack, c.ws->pack_words);
       c.ws->pack_words = 0;
-      c.ws->pack = dalloc<int32_t>(words);
+      c.ws->pack = dalloc<int32_t>(c.ws->al, words);
       c.ws->pack_words = words;
     }
   }
@@ -1600,13 +1866,64 @@ struct ResultDrain {
   }
 };
 
+// Frontier pool and CPI arena: sized by what batches asked of them.  They
+// start at a sixteenth of the budget (at most 256 MiB) and, when a batch asks
+// for more, grow to its demand plus a quarter, up to a quarter of the budget
+// (frontiers) and an eighth (CPI entries); the jobs that overflowed then run
+// again in the fast path.
+constexpr int64_t ADAPT_START_MAX = int64_t(256) << 20;
+constexpr int MAX_REGROW = 4;  // fast-path retries of one GFD while the pool or arena grows
+static size_t adapt_start(const Workspace* ws) {
+  return (size_t)std::max<int64_t>(int64_t(4) << 20, std::min<int64_t>(ws->budget / 16, ADAPT_START_MAX));
+}
+static bool grow_to(size_t& want, size_t have, uint64_t asked, int64_t limit) {
+  if (asked <= have) return false;
+  const size_t lim = (size_t)std::max<int64_t>(limit, (int64_t)have);
+  const size_t w = std::min<size_t>(lim, std::max<size_t>(2 * have, asked + asked / 4));
+  if (w <= have) return false;
+  want = std::max(want, w);
+  return true;
+}
+// What a call may use of them: a workspace kept from calls with larger
+// budgets can hold more than this call's share.
+static uint64_t front_usable(const Workspace* ws) {
+  return std::min<uint64_t>(ws->front_bytes, (uint64_t)std::max<int64_t>(ws->budget / 4, int64_t(4) << 20));
+}
+static uint64_t cpi_usable(const Workspace* ws) {
+  return std::min<uint64_t>(ws->cpi_cap, (uint64_t)std::max<int64_t>(ws->budget / 32, int64_t(1) << 20));
+}
+static bool grow_front(Workspace* ws, uint64_t asked_bytes) {
+  return grow_to(ws->front_want, front_usable(ws), asked_bytes, ws->budget / 4);
+}
+static bool grow_cpi(Workspace* ws, uint64_t asked_entries) {
+  size_t want = ws->cpi_want * 4;
+  const bool g = grow_to(want, cpi_usable(ws) * 4, asked_entries * 4, ws->budget / 8);
+  ws->cpi_want = want / 4;
+  return g;
+}
+static void ensure_front(Workspace* ws) {
+  const size_t want = std::max(ws->front_want, adapt_start(ws));
+  if (ws->front_bytes >= want) return;
+  dfree(ws->al, ws->front, ws->front_bytes);
+  ws->front_bytes = 0;
+  ws->front = dalloc<uint8_t>(ws->al, want);
+  ws->front_bytes = want;
+}
+static void ensure_cpi(Workspace* ws) {
+  const size_t want = std::max(ws->cpi_want, adapt_start(ws) / 4);
+  if (ws->cpi_cap >= want) return;
+  dfree(ws->al, ws->cpi_arena, ws->cpi_cap);
+  ws->cpi_cap = 0;
+  ws->cpi_arena = dalloc<int32_t>(ws->al, want);
+  ws->cpi_cap = want;
+}
+
 // The batch arena only grows (allocations of this size are slow).
 static void ensure_arena(Workspace* ws, size_t bytes) {
   if (ws->arena_bytes >= bytes) return;
-  dfree(ws->arena);
-  ws->arena = nullptr;
+  dfree(ws->al, ws->arena, ws->arena_bytes);
   ws->arena_bytes = 0;
-  ws->arena = dalloc<uint8_t>(bytes);
+  ws->arena = dalloc<uint8_t>(ws->al, bytes);
   ws->arena_bytes = bytes;
 }
 
@@ -1630,10 +1947,9 @@ static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
   size_t hw = 0;
   for (auto& J : jobs) hw += (J.caps.hit_region + 63) / 64 * 64;
   if (ws->hitpool_words < hw) {
-    dfree(ws->hitpool);
-    ws->hitpool = nullptr;
+    dfree(ws->al, ws->hitpool, ws->hitpool_words);
     ws->hitpool_words = 0;
-    ws->hitpool = dalloc<uint32_t>(hw);
+    ws->hitpool = dalloc<uint32_t>(ws->al, hw);
     ws->hitpool_words = hw;
     fill_u32(c.st, ws->hitpool, 0u, hw);
   }
@@ -1655,26 +1971,27 @@ static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
     HIPCHK(hipHostMalloc((void**)&ws->hctl, sizeof(uint64_t) * CTL_WORDS * nj, hipHostMallocDefault));
     ws->hctl_words = CTL_WORDS * nj;
   }
-  // zero the control blocks and tile states; the CPI arena starts empty
+  ensure_front(ws);
+  ensure_cpi(ws);
+  // zero the control blocks and tile states; the CPI arena and the frontier
+  // pool start empty
   fill_u64(c.st, (uint64_t*)ws->arena, 0, (ctl_b + ts_b) / 8);
-  fill_u64(c.st, (uint64_t*)ws->misc, 0, 1);
+  fill_u64(c.st, (uint64_t*)ws->misc, 0, 2);
 }
 
 static void ensure_chunk(Workspace* ws, size_t bytes) {
   if (ws->chunk_bytes >= bytes) return;
-  dfree(ws->chunk);
-  ws->chunk = nullptr;
+  dfree(ws->al, ws->chunk, ws->chunk_bytes);
   ws->chunk_bytes = 0;
-  ws->chunk = dalloc<uint8_t>(bytes);
+  ws->chunk = dalloc<uint8_t>(ws->al, bytes);
   ws->chunk_bytes = bytes;
 }
 
 static void ensure_vbig(Workspace* ws, uint64_t vcap) {
   if (ws->vbig_cap >= vcap) return;
-  dfree(ws->vbig);
-  ws->vbig = nullptr;
+  dfree(ws->al, ws->vbig, (size_t)ws->vbig_cap * MAXK);
   ws->vbig_cap = 0;
-  ws->vbig = dalloc<int32_t>((size_t)vcap * MAXK);
+  ws->vbig = dalloc<int32_t>(ws->al, (size_t)vcap * MAXK);
   ws->vbig_cap = vcap;
 }
 
@@ -1805,7 +2122,7 @@ struct Bounded {
       e.src_cols = r.list;
       e.src_stride = 0;
       e.d_nsrc = r.cnt;
-      e.src_cap = J.caps.cap_u[p.root];
+      e.src_cap = J.caps.lcap_u[p.root];
     } else {
       e.src_cols = J.mem.cols[i];
       e.src_stride = J.caps.cap_f;
@@ -1814,6 +2131,7 @@ struct Bounded {
     }
     e.par_pos = p.pos[q];
     e.par_posmap = J.mem.pos[q];
+    e.par_by_bucket = p.qlab[q] != ANY ? 1 : 0;
     e.cpi_beg = J.mem.cpi_beg[u];
     e.cpi_len = J.mem.cpi_len[u];
     e.cpi_ent = c.ws->cpi_arena;
@@ -1866,7 +2184,7 @@ struct Bounded {
     e.last = 1;
     e.src_cols = r.list;
     e.d_nsrc = r.cnt;
-    e.src_cap = J.caps.cap_u[p.root];
+    e.src_cap = J.caps.lcap_u[p.root];
     HIPCHK(hipMemcpyAsync(c.ws->hctl, r.cnt, 8, hipMemcpyDeviceToHost, c.st));
     HIPCHK(hipStreamSynchronize(c.st));
     const uint64_t N = c.ws->hctl[0];
@@ -1887,9 +2205,15 @@ struct Bounded {
   }
 };
 
+static uint64_t frontier_cap_of(const gfd_graph* g, const Plan& p, int64_t fbytes, int64_t forced);
+
 static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
   Workspace* ws = c.ws;
   std::vector<Job> one{J};
+  // the job alone, with its own frontier columns for every level: a quarter
+  // of the budget (or the testing cap)
+  job_caps(c.g, J.plan, frontier_cap_of(c.g, J.plan, ws->budget / 4, (int64_t)c.front_limit), J.caps.vcap,
+           true, one[0].caps);
   layout_batch(c, one);
   Job& B = one[0];
   Recs R;
@@ -1941,8 +2265,8 @@ static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
 // collected ones fit.  Every pass is one launch for all such jobs of a batch.
 // Leaves each finished job's control block in ws->hctl; jobs still over after
 // the pass limit go to the bounded path (redo).
-static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> over, const Recs& R,
-                              uint64_t vsmall, std::vector<char>& redo,
+static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> over,
+                              const std::vector<ExtJob>& lastrec, uint64_t vsmall, std::vector<char>& redo,
                               const std::function<void()>& while_busy) {
   Workspace* ws = c.ws;
   const DevGraph& g = c.g->dg;
@@ -1957,8 +2281,7 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     // last-level records in collect-only form, multi-vertex and single-vertex
     std::vector<ExtJob> E[2];
     for (int x : over) {
-      ExtJob e;
-      std::memcpy(&e, R.blob.data() + jobs[x].last_rec, sizeof e);
+      ExtJob e = lastrec[x];
       e.collect_only = 1;
       e.thr = (const int32_t*)(jobs[x].mem.ctl + CTL_THR);
       e.thr_incl = 1;
@@ -2084,32 +2407,43 @@ static uint64_t frontier_cap_of(const gfd_graph* g, const Plan& p, int64_t fbyte
       4096, std::min<int64_t>(fbytes / (int64_t)per_slot_bytes(p.k), 64 * g->m));
 }
 
+// Default limit on a call's device memory: a quarter of what is free, at most
+// 64 GiB.  A call allocates by need within it (candidate structures by label
+// bucket, frontiers and CPI entries by what the batches ask for), not the
+// limit itself.
 static int64_t default_budget() {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return int64_t(4) << 30;
-  const int64_t b = (int64_t)(fr / 2);
-  return std::max<int64_t>(int64_t(256) << 20, std::min<int64_t>(b, int64_t(128) << 30));
+  const int64_t b = (int64_t)(fr / 4);
+  return std::max<int64_t>(int64_t(256) << 20, std::min<int64_t>(b, int64_t(64) << 30));
 }
 
-static Workspace* acquire_ws(gfd_graph* g, int64_t budget) {
+// An idle workspace of g whose device memory comes from `alloc` (made if
+// there is none); its buffers grow as calls need them.
+static Workspace* acquire_ws(gfd_graph* g, int64_t budget, const gfd_allocator& alloc,
+                             hipStream_t st) {
   {
     std::lock_guard<std::mutex> lk(g->mu);
-    if (!g->pool.empty()) {
-      Workspace* w = g->pool.back();
-      g->pool.pop_back();
+    for (size_t i = 0; i < g->pool.size(); i++) {
+      Workspace* w = g->pool[i];
+      if (!w->al.same(alloc)) continue;
+      g->pool.erase(g->pool.begin() + (ptrdiff_t)i);
       w->budget = budget;
+      w->al.st = st;
       return w;
     }
   }
   Workspace* w = new Workspace();
   try {
     w->budget = budget;
-    w->misc = dalloc<unsigned long long>(16);
-    w->err = dalloc<uint32_t>(1);
-    w->sel_state = dalloc<uint32_t>((size_t)MAX_JOBS * SEL_STATE_WORDS);
-    w->sel_hist = dalloc<uint32_t>((size_t)MAX_JOBS * RADIX_BINS);
-    w->sel_out = dalloc<int32_t>((size_t)SORT_MAX * MAXK);
-    w->selrec = dalloc<uint8_t>(sizeof(SelJob) * MAX_JOBS);
+    w->al.cb = alloc;
+    w->al.st = st;
+    w->misc = dalloc<unsigned long long>(w->al, 16);
+    w->err = dalloc<uint32_t>(w->al, 1);
+    w->sel_state = dalloc<uint32_t>(w->al, (size_t)MAX_JOBS * SEL_STATE_WORDS);
+    w->sel_hist = dalloc<uint32_t>(w->al, (size_t)MAX_JOBS * RADIX_BINS);
+    w->sel_out = dalloc<int32_t>(w->al, (size_t)SORT_MAX * MAXK);
+    w->selrec = dalloc<uint8_t>(w->al, sizeof(SelJob) * MAX_JOBS);
     HIPCHK(hipHostMalloc((void**)&w->hselrec, sizeof(SelJob) * MAX_JOBS, hipHostMallocMapped));
     w->hselrec_dev = mapped_ptr(w->hselrec);
     HIPCHK(hipHostMalloc((void**)&w->hmisc, sizeof(uint64_t) * 16, hipHostMallocDefault));
@@ -2148,6 +2482,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
   if (o.semantics != GFD_SEM_INDUCED && o.semantics != GFD_SEM_MONO) return set_error(GFD_EINVAL, "semantics");
   if (o.batched != 0 && o.batched != 1) return set_error(GFD_EINVAL, "batched must be 0 or 1");
   if (o.mem_budget_bytes < 0 || o.frontier_cap < 0 || o.violation_cap < 0) return set_error(GFD_EINVAL, "negative option");
+  if (int32_t rc = check_allocator(o.allocator)) return rc;
   const bool count_only = (o.flags & GFD_FLAG_COUNT_ONLY) != 0;
   if (count_only && o.k_max != 0) return set_error(GFD_EINVAL, "a count-only call needs k_max = 0");
   for (int32_t i = 0; i < num_specs; i++) {
@@ -2163,14 +2498,10 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
   Workspace* ws = nullptr;
   try {
     const int64_t budget = o.mem_budget_bytes ? o.mem_budget_bytes : default_budget();
-    ws = acquire_ws(g, budget);
+    ws = acquire_ws(g, budget, o.allocator, (hipStream_t)o.hip_stream);
     if (ws->hitpool_dirty && ws->hitpool)  // an earlier call stopped midway
       fill_u32((hipStream_t)o.hip_stream, ws->hitpool, 0u, ws->hitpool_words);
     ws->hitpool_dirty = true;
-    if (ws->cpi_cap == 0) {
-      ws->cpi_cap = (uint64_t)std::max<int64_t>(1 << 20, std::min<int64_t>(budget / 16, int64_t(1) << 30) / 4);
-      ws->cpi_arena = dalloc<int32_t>(ws->cpi_cap);
-    }
     const int max_batch = o.batched ? MAX_JOBS : 1;
     const int64_t njobs_hint = std::min<int64_t>(num_specs, max_batch);
     int64_t deep = 0;
@@ -2178,8 +2509,8 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     const Sizing sz = call_sizing(budget, njobs_hint, std::min<int64_t>(deep, max_batch), K,
                                   o.violation_cap);
     const uint64_t vsmall = sz.vsmall, vbig = sz.vbig;
-    Ctx c{g, ws, (hipStream_t)o.hip_stream, o.semantics == GFD_SEM_INDUCED, K, Timer{}, stats,
-          stats ? ws->misc + 8 : nullptr};
+    Ctx c{g, ws, (hipStream_t)o.hip_stream, o.semantics == GFD_SEM_INDUCED, K, (uint64_t)o.frontier_cap,
+          Timer{}, stats, stats ? ws->misc + 8 : nullptr};
     const uint32_t cls_mask = ((uint32_t)o.flags >> 8) & 0xFFu;
     c.tm.on = stats && ((o.flags & GFD_FLAG_TIMING) || cls_mask);
     c.tm.mask = cls_mask ? cls_mask : 0xFFu;
@@ -2192,8 +2523,15 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       all[i].spec = i;
       make_plan(g, specs[i], c.induced, all[i].plan);
       plan_leaves(specs[i], c.induced, count_only, all[i].plan);
-      job_caps(g, all[i].plan, frontier_cap_of(g, all[i].plan, sz.fbytes, o.frontier_cap), vsmall,
-               all[i].caps);
+      job_caps(g, all[i].plan, 0, vsmall, false, all[i].caps);
+    }
+    {
+      // a fresh pool is sized by the frontier estimate of the call's GFDs (at
+      // most 1 GiB); it grows from there to what batches ask for
+      double est = 0;
+      for (int32_t i = 0; i < num_specs; i++) est += (double)est_front_bytes(g, all[i].plan);
+      const double cap = (double)std::min<int64_t>(budget / 4, int64_t(1) << 30);
+      ws->front_want = std::max(ws->front_want, (size_t)std::min(est * 1.25, cap));
     }
     std::vector<std::vector<int>> batches;
     {
@@ -2219,9 +2557,12 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       return std::min<uint64_t>((uint64_t)K, H[(size_t)i * CTL_WORDS + CTL_VIOL]);
     };
     uint64_t cpi_entries = 0;
-    for (const auto& bidx : batches) {
+    std::vector<char> retried(num_specs, 0);
+    // redo[x]: 1 the job runs again on the bounded path; 2 it runs again in a
+    // later fast batch (the frontier pool or CPI arena it overflowed has grown)
+    for (size_t bi = 0; bi < batches.size(); bi++) {
       std::vector<Job> jobs;
-      for (int i : bidx) jobs.push_back(all[i]);
+      for (int i : batches[bi]) jobs.push_back(all[i]);
       layout_batch(c, jobs);
       std::vector<char> redo(jobs.size(), force_bounded ? 1 : 0);
       if (!force_bounded) {
@@ -2231,14 +2572,45 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
         HIPCHK(hipMemcpyAsync(ws->hctl, jobs[0].mem.ctl, sizeof(uint64_t) * CTL_WORDS * jobs.size(),
                               hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipMemcpyAsync(ws->hmisc, ws->misc, 8, hipMemcpyDeviceToHost, c.st));
+        HIPCHK(hipMemcpyAsync(ws->hmisc + 10, ws->misc + 1, 8, hipMemcpyDeviceToHost, c.st));
         HIPCHK(hipStreamSynchronize(c.st));
-        cpi_entries += ws->hmisc[0];
+        cpi_entries += std::min<uint64_t>(ws->hmisc[0], ws->cpi_cap);
+        // what the batch asked of the frontier pool and the CPI arena (failed
+        // reservations included): they grow to it for the next batch
+        const bool grew_f = grow_front(ws, ws->hmisc[10]);
+        const bool grew_c = grow_cpi(ws, ws->hmisc[0]);
+        const bool grew = grew_f || grew_c;
         std::vector<int> over;  // only the violation staging overflowed
+        std::vector<int> again;
         for (size_t x = 0; x < jobs.size(); x++) {
           const uint64_t* h = ws->hctl + CTL_WORDS * x;
           std::memcpy(&H[(size_t)jobs[x].spec * CTL_WORDS], h, sizeof(uint64_t) * CTL_WORDS);
-          if (h[CTL_FLAGS] & 5u) redo[x] = 1;  // frontier or CPI arena overflow
-          else if (K > 0 && h[CTL_VCOUNT] > vsmall) over.push_back((int)x);
+          if (h[CTL_FLAGS] & 5u) {  // frontier or CPI arena overflow
+            // a job that failed at one level asks again at the next one, so
+            // a few rounds of growth may be needed before its frontiers fit
+            if (grew && retried[jobs[x].spec] < MAX_REGROW) {
+              redo[x] = 2;
+              retried[jobs[x].spec]++;
+              again.push_back(jobs[x].spec);
+            } else {
+              redo[x] = 1;
+            }
+          } else if (K > 0 && h[CTL_VCOUNT] > vsmall) {
+            over.push_back((int)x);
+          }
+        }
+        if (!again.empty()) {
+          batches.push_back(again);
+          if (stats) stats->regrown_gfds += (int32_t)again.size();
+        }
+        // the last-level records of the jobs to re-run, as the device holds
+        // them (their sources were placed by the frontier reservations)
+        std::vector<ExtJob> lastrec(jobs.size());
+        if (!over.empty()) {
+          for (int x : over)
+            HIPCHK(hipMemcpyAsync(&lastrec[x], ws->jobrec + jobs[x].last_rec, sizeof(ExtJob),
+                                  hipMemcpyDeviceToHost, c.st));
+          HIPCHK(hipStreamSynchronize(c.st));
         }
         // jobs whose first K the last level's sort already wrote go out now
         std::unique_ptr<ResultDrain> D;
@@ -2257,7 +2629,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
         }
         if (!over.empty()) {
           if (stats) stats->threshold_gfds += (int32_t)over.size();
-          rerun_last_levels(c, jobs, over, R, vsmall, redo, [&] { if (D) D->drain(); });
+          rerun_last_levels(c, jobs, over, lastrec, vsmall, redo, [&] { if (D) D->drain(); });
           for (int x : over)
             if (!redo[x]) {
               H[(size_t)jobs[x].spec * CTL_WORDS + CTL_VCOUNT] = ws->hctl[CTL_WORDS * x + CTL_VCOUNT];
@@ -2295,7 +2667,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
           }
       }
       for (size_t x = 0; x < jobs.size(); x++) {
-        if (!redo[x]) continue;
+        if (redo[x] != 1) continue;
         if (stats) stats->chunked_gfds++;
         run_bounded(c, jobs[x], vbig);
         HIPCHK(hipMemcpyAsync(&H[(size_t)jobs[x].spec * CTL_WORDS], jobs[x].mem.ctl,
@@ -2315,7 +2687,8 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     HIPCHK(hipMemcpyAsync(ws->hmisc + 1, ws->err, 4, hipMemcpyDeviceToHost, c.st));
     if (stats) HIPCHK(hipMemcpyAsync(ws->hmisc + 2, ws->misc + 8, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, c.st));
     HIPCHK(hipStreamSynchronize(c.st));
-    if ((uint32_t)ws->hmisc[1]) throw GfdError{GFD_EDEVICE, "scan look-back did not complete"};
+    if ((uint32_t)ws->hmisc[1] & 1u) throw GfdError{GFD_EDEVICE, "scan look-back did not complete"};
+    if ((uint32_t)ws->hmisc[1] & 2u) throw GfdError{GFD_EDEVICE, "internal: a candidate list passed its bound"};
     int32_t rc = GFD_OK;
     for (int32_t i = 0; i < num_specs; i++) {
       const uint64_t* h = &H[(size_t)i * CTL_WORDS];
@@ -2326,12 +2699,14 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
       r.violation_fp = count_only ? 0 : h[CTL_VFP];
       r.satisfied = r.violation_count == 0;
       r.num_reported = (int32_t)reported(i);  // its tuples were copied with its batch
-      if ((r.match_count >> 63) || (r.violation_count >> 63))
+      if ((r.match_count >> 63) || (r.violation_count >> 63) || (h[CTL_FLAGS] & FLAG_COUNTER_OVERFLOW))
         rc = set_error(GFD_EOVERFLOW, "spec %d: counter passed 2^63", i);
     }
     if (stats) {
       for (int j = 0; j < 8; j++) stats->class_bytes[j] = ws->hmisc[2 + j];
       stats->cpi_entries = cpi_entries;
+      stats->front_pool_bytes = (int64_t)ws->front_bytes;
+      stats->cpi_arena_bytes = (int64_t)ws->cpi_cap * 4;
       if (c.tm.on) c.tm.collect(stats->class_ms);
       for (int j = 0; j < 8; j++) {
         stats->class_launches[j] = c.tm.launches[j];
@@ -2343,12 +2718,9 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     ws->hitpool_dirty = false;
     release_ws(g, ws);
     return rc;
-  } catch (const GfdError& e) {
+  } catch (...) {
     if (ws) release_ws(g, ws);
-    return set_error(e.code, "%s", e.msg.c_str());
-  } catch (const std::bad_alloc&) {
-    if (ws) release_ws(g, ws);
-    return set_error(GFD_ENOMEM, "host allocation failed");
+    return guarded([] () -> int32_t { throw; });
   }
 }
 
@@ -2380,6 +2752,7 @@ struct ServerReq {
   int32_t status = GFD_OK;
   std::string err;
   bool done = false;
+  bool claimed = false;  // a waiter holds it
 };
 
 }  // namespace
@@ -2437,15 +2810,28 @@ struct gfd_server {
       vo.mem_budget_bytes = budget;
       vo.hip_stream = streams[w];
       vo.batched = 1;
+      vo.allocator = o.allocator;
       const int32_t rc = gfd_validate(g, specs.data(), (int32_t)specs.size(), &vo, res.data());
-      const std::string msg = rc ? gfd_last_error() : "";
+      std::vector<int32_t> st(batch.size(), rc);
+      std::vector<std::string> msg(batch.size(), rc ? gfd_last_error() : "");
+      if (rc && batch.size() > 1) {
+        // the batch failed: each request alone, so only a failing one reports it
+        size_t at = 0;
+        for (size_t b = 0; b < batch.size(); b++) {
+          const int32_t nb = (int32_t)batch[b]->specs.size();
+          st[b] = gfd_validate(g, specs.data() + at, nb, &vo, res.data() + at);
+          msg[b] = st[b] ? gfd_last_error() : "";
+          at += (size_t)nb;
+        }
+      }
       const int64_t t_done = now_ns();
       std::lock_guard<std::mutex> lk(mu);
       size_t at = 0;
-      for (ServerReq* r : batch) {
+      for (size_t b = 0; b < batch.size(); b++) {
+        ServerReq* r = batch[b];
         for (size_t i = 0; i < r->specs.size(); i++) r->res[i] = res[at++];
-        r->status = rc;
-        r->err = msg;
+        r->status = st[b];
+        r->err = msg[b];
         r->info.start_ns = t_start;
         r->info.done_ns = t_done;
         r->info.batch_id = bid;
@@ -2478,6 +2864,7 @@ extern "C" int32_t gfd_server_create(const gfd_graph* gc, const gfd_server_opts*
   if (o.k_max < 0 || o.k_max > SORT_MAX) return set_error(GFD_EINVAL, "k_max");
   if (o.semantics != GFD_SEM_INDUCED && o.semantics != GFD_SEM_MONO) return set_error(GFD_EINVAL, "semantics");
   if (o.mem_budget_bytes < 0) return set_error(GFD_EINVAL, "negative budget");
+  if (int32_t rc = check_allocator(o.allocator)) return rc;
   gfd_server* s = new gfd_server();
   s->g = const_cast<gfd_graph*>(gc);
   s->o = o;
@@ -2506,16 +2893,21 @@ extern "C" int32_t gfd_server_create(const gfd_graph* gc, const gfd_server_opts*
       const Sizing sz = call_sizing(s->budget, o.max_batch_gfds, o.max_batch_gfds, o.k_max, 0);
       Plan p;
       make_plan(s->g, path, o.semantics == GFD_SEM_INDUCED, p);
+      plan_leaves(path, o.semantics == GFD_SEM_INDUCED, false, p);
       JobCaps caps;
-      job_caps(s->g, p, frontier_cap_of(s->g, p, sz.fbytes, 0), sz.vsmall, caps);
+      job_caps(s->g, p, 0, sz.vsmall, false, caps);
       reserve = std::min<int64_t>(s->budget, (int64_t)o.max_batch_gfds * (int64_t)align_up(caps.bytes) +
                                                  (int64_t(64) << 20));
     }
     std::vector<Workspace*> ws;
     try {
       for (int w = 0; w < o.workers; w++) {
-        ws.push_back(acquire_ws(s->g, s->budget));
+        ws.push_back(acquire_ws(s->g, s->budget, o.allocator, s->streams[w]));
         ensure_arena(ws.back(), (size_t)reserve);
+        // and a frontier pool of an eighth of the budget (at most 1 GiB)
+        ws.back()->front_want =
+            std::max(ws.back()->front_want, (size_t)std::min<int64_t>(s->budget / 8, int64_t(1) << 30));
+        ensure_front(ws.back());
       }
     } catch (...) {
       for (Workspace* x : ws) release_ws(s->g, x);
@@ -2523,10 +2915,18 @@ extern "C" int32_t gfd_server_create(const gfd_graph* gc, const gfd_server_opts*
     }
     for (Workspace* x : ws) release_ws(s->g, x);
     for (int w = 0; w < o.workers; w++) s->workers.emplace_back([s, w] { s->work(w); });
-  } catch (const GfdError& e) {
+  } catch (...) {
+    // stop and join the workers already started, then report
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->workers)
+      if (t.joinable()) t.join();
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     delete s;
-    return set_error(e.code, "%s", e.msg.c_str());
+    return guarded([] () -> int32_t { throw; });
   }
   *out = s;
   return GFD_OK;
@@ -2537,41 +2937,37 @@ extern "C" int32_t gfd_server_submit(gfd_server* s, const gfd_spec* specs, int32
   if (!s || !request_id || num_specs < 1 || !specs) return set_error(GFD_EINVAL, "server/specs/id");
   if (num_specs > s->o.max_batch_gfds)
     return set_error(GFD_EINVAL, "request of %d GFDs exceeds max_batch_gfds", num_specs);
-  auto* r = new ServerReq();
+  std::unique_ptr<ServerReq> rp(new ServerReq());
+  ServerReq* r = rp.get();
   try {
     const bool induced = s->o.semantics == GFD_SEM_INDUCED;
     // estimated device bytes of the request's jobs, sized as in a full batch
     const Sizing sz = call_sizing(s->budget, s->o.max_batch_gfds, s->o.max_batch_gfds, s->o.k_max, 0);
     for (int32_t i = 0; i < num_specs; i++) {
       const int32_t rc = check_spec(s->g, specs[i], i);
-      if (rc) {
-        delete r;
-        return rc;
-      }
+      if (rc) return rc;
       Plan p;
       make_plan(s->g, specs[i], induced, p);
+      plan_leaves(specs[i], induced, false, p);
       JobCaps caps;
-      job_caps(s->g, p, frontier_cap_of(s->g, p, sz.fbytes, 0), sz.vsmall, caps);
-      r->est_bytes += (int64_t)caps.bytes;
+      job_caps(s->g, p, 0, sz.vsmall, false, caps);
+      // its candidate and CPI structures, staging and estimated frontiers
+      r->est_bytes += (int64_t)caps.bytes +
+                      (int64_t)std::min<uint64_t>(est_front_bytes(s->g, p), (uint64_t)s->budget / 4);
     }
-  } catch (const GfdError& e) {
-    delete r;
-    return set_error(e.code, "%s", e.msg.c_str());
-  }
-  r->specs.assign(specs, specs + num_specs);
-  r->res.resize(num_specs);
-  r->viol.resize((size_t)num_specs * std::max(s->o.k_max, 1) * GFD_MAX_K);
-  {
+    r->specs.assign(specs, specs + num_specs);
+    r->res.resize(num_specs);
+    r->viol.resize((size_t)num_specs * std::max(s->o.k_max, 1) * GFD_MAX_K);
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) {
-      delete r;
-      return set_error(GFD_EINVAL, "server is stopping");
-    }
+    if (s->stop) return set_error(GFD_EINVAL, "server is stopping");
     r->id = s->next_id++;
     r->info.submit_ns = now_ns();
     s->reqs[r->id] = r;
     s->queue.push_back(r);
     *request_id = r->id;
+    rp.release();
+  } catch (...) {
+    return guarded([] () -> int32_t { throw; });
   }
   s->cv_work.notify_one();
   return GFD_OK;
@@ -2586,11 +2982,18 @@ extern "C" int32_t gfd_server_wait(gfd_server* s, uint64_t request_id, int32_t t
     auto it = s->reqs.find(request_id);
     if (it == s->reqs.end()) return set_error(GFD_EINVAL, "unknown request %llu", (unsigned long long)request_id);
     r = it->second;
+    // one waiter at a time: a second one would find the request freed
+    if (r->claimed) return set_error(GFD_EINVAL, "request %llu is being waited for", (unsigned long long)request_id);
+    r->claimed = true;
     auto ready = [&] { return r->done; };
+    bool ok = true;
     if (timeout_ms < 0) s->cv_done.wait(lk, ready);
-    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+    else ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
+    if (!ok) {
+      r->claimed = false;
       return set_error(GFD_EAGAIN, "request %llu not finished", (unsigned long long)request_id);
-    s->reqs.erase(it);
+    }
+    s->reqs.erase(request_id);  // the map may have changed while waiting
   }
   const int32_t rc = r->status;
   if (rc) set_error(rc, "%s", r->err.c_str());

@@ -104,14 +104,22 @@ __host__ __device__ __forceinline__ uint8_t hub_fp(int32_t w) {
 }
 
 // A candidate set C(u): its members (list, *cnt), their positions in the list
-// (pos[x], meaningful for members only) and an n-bit membership bitmap, small
-// enough to stay in L2 (512 KB for 4M vertices).
+// (meaningful for members only) and an n-bit membership bitmap, small enough
+// to stay in L2 (512 KB for 4M vertices).  The positions of a labelled u are
+// indexed by the member's position in u's label bucket (lab_pos), so they take
+// the bucket's size rather than n; a wildcard u's are indexed by vertex id.
 struct CandSet {
   const int32_t* list;
   const uint64_t* cnt;
-  const int32_t* pos;    // [n]
+  const int32_t* pos;    // [bucket size] (by_bucket) or [n]
   const uint32_t* bits;  // [ceil(n/32)]
+  int32_t by_bucket;
 };
+
+// Index of member x's entry in a position map.
+__device__ __forceinline__ uint32_t pos_index(const DevGraph& g, int32_t by_bucket, int32_t x) {
+  return by_bucket ? g.lab_pos[x] : (uint32_t)x;
+}
 
 // Prefix over one job's items, computed by a single-pass scan with a
 // decoupled look-back (per-job tile states and ticket).
@@ -165,8 +173,10 @@ struct FilterJob {
   int32_t hitmode;
   JobScan sc;            // over (constraint, item) pairs
   int32_t* out;          // the new C(u): list, count (atomic cursor), positions, bits
+  uint64_t out_cap;      // the list's capacity (a bound on |C(u)|; passing it is an error)
   uint64_t* d_out_n;
   int32_t* pos;
+  int32_t pos_by_bucket; // positions indexed by bucket position (CandSet::by_bucket)
   uint32_t* bits;        // cleared by filter_clear before the compaction
   uint64_t nwords;
 };
@@ -211,16 +221,22 @@ struct ExtJob {
   uint64_t src_cap;
   int32_t par_pos;          // position of the spanning-tree parent
   const int32_t* par_posmap;  // C(parent) positions
+  int32_t par_by_bucket;      // ... indexed by bucket position
   const uint32_t* cpi_beg;
   const uint32_t* cpi_len;
   const int32_t* cpi_ent;
   uint32_t* begs;           // [src_cap] list start per source
   JobScan sc;               // over sources
+  // inner levels of the fast path: the next frontier is reserved from the
+  // batch's frontier pool once this level's attempts are counted (at most
+  // front_limit slots when nonzero), and dst_* / the next level's src_*,
+  // begs and scan arrays are pointed at it on the device
   uint64_t a_begin, a_end;  // attempt window
   int32_t nchk;
   int32_t chk_pos[MAXK];
   int32_t chk_fwd[MAXK];    // constraint on data edge h(x_pos) -> v
   int32_t chk_bwd[MAXK];    // constraint on data edge v -> h(x_pos)
+  uint64_t front_limit;
   int32_t* dst_cols;
   uint64_t dst_cap;
   uint64_t* d_ndst;
@@ -249,6 +265,24 @@ constexpr int MAX_LEAVES = 3;
 constexpr int LEAF_SUBSETS = 1 << MAX_LEAVES;  // masks 1 .. 2^r - 1 are used
 constexpr int LEAF_FAMILIES = 3;               // no literal, X, X and Y
 constexpr int LEAF_WORDS = LEAF_FAMILIES * LEAF_SUBSETS;
+// Injective assignments of r leaves to sets A_0 .. A_{r-1}, from c[B] =
+// |intersection of A_j, j in B| (bit j of B: leaf j): the sum over set
+// partitions of the leaves of the product over blocks of
+// (-1)^(|B|-1) (|B|-1)! c[B] (Moebius inversion on the partition lattice).
+// Exact in 128 bits for counts below 2^32.
+__host__ __device__ inline __int128 leaf_injective(int r, const int64_t (&c)[LEAF_SUBSETS]) {
+  const __int128 c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5], c6 = c[6], c7 = c[7];
+  if (r == 1) return c1;
+  if (r == 2) return c1 * c2 - c3;
+  return c1 * c2 * c4 - c3 * c4 - c5 * c2 - c6 * c1 + 2 * c7;
+}
+// Largest per-partial-match leaf count added to a 64-bit counter: a thread
+// adds at most LBS_ROUNDS of them per chunk and a block 256 threads' sums, so
+// the block's partial stays below 2^62; a larger count (or a negative one,
+// which exact inputs never give) marks the job's counters as overflowed.
+constexpr int64_t LEAF_COUNT_MAX = int64_t(1) << 50;
+constexpr uint32_t FLAG_COUNTER_OVERFLOW = 8u;  // job flags bit: a counter would pass 2^63
+
 struct LeafJob {
   int32_t active, i, r;       // i: matched vertices in a source; r: leaves
   const int32_t* src_cols;    // column j (j < i) at src_cols + j * src_stride
@@ -257,6 +291,7 @@ struct LeafJob {
   uint64_t src_cap;
   int32_t par_pos;            // the parent's position in a source
   const int32_t* par_posmap;  // C(p) positions
+  int32_t par_by_bucket;      // ... indexed by bucket position
   const uint64_t* d_np;       // |C(p)|
   uint64_t cap_p;
   const uint32_t* cpi_beg;    // the leaves' CPI lists (one set: the leaves are identical)
@@ -269,6 +304,7 @@ struct LeafJob {
   DevLit lit[2 * MAXLIT];
   int32_t lit_leaf[2 * MAXLIT];  // leaf slot of a literal, or -1 (inner vertices)
   unsigned long long* counters;  // match, violation
+  uint32_t* flags;               // FLAG_COUNTER_OVERFLOW
 };
 
 struct TopkJob {
@@ -321,6 +357,14 @@ void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, 
               bool onepass, unsigned long long* bytes);
 // 1-D grid of `grid` blocks shared among the jobs by their scan tiles
 void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid);
+// After the scan of inner level i (records `cur`): reserves every job's next
+// frontier from `pool` (bump cursor *cursor, pool_bytes in all) and points
+// cur's dst_*, next's src_* / begs / scan arrays (next may be null) and leaf's
+// src_* (for a job whose postponed leaves follow; may be null) at it.  A job
+// the pool cannot hold keeps dst_cap = 0 (its first kept match flags a
+// frontier overflow).
+void front_reserve(hipStream_t st, ExtJob* cur, ExtJob* next, LeafJob* leaf, int njobs,
+                   uint8_t* pool, uint64_t pool_bytes, unsigned long long* cursor);
 // ahead (last level only): load every round's first probe slot before the
 // rounds run -- more loads in flight, fewer waves; for cache-resident graphs
 void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,

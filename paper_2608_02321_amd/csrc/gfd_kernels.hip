@@ -941,8 +941,14 @@ __global__ __launch_bounds__(BS) void k_filter_compact(DevGraph g,
     for (uint32_t q = keep; q; q &= q - 1) {
       const int r = __ffs(q) - 1;
       const int32_t v = filter_item(J, i0 + r);
-      J.out[idx] = v;
-      if (J.pos) J.pos[v] = (int32_t)idx;
+      if (idx < J.out_cap) {
+        J.out[idx] = v;
+        // a direct labelled filter's item index is the bucket position itself
+        if (J.pos) J.pos[J.pos_by_bucket && J.direct && J.list ? (uint32_t)(i0 + r)
+                                                                : pos_index(g, J.pos_by_bucket, v)] = (int32_t)idx;
+      } else {  // the host's bound on |C(u)| does not hold: reported, nothing written
+        atomicOr(J.sc.err, 2u);
+      }
       idx++;
       by += 12;
       const uint32_t w = (uint32_t)v >> 5;
@@ -1080,7 +1086,8 @@ __device__ __forceinline__ void cpi_chunk(const DevGraph& g, const CpiJob& J, ui
       if (!member(J.p, vp)) return;
       const int32_t v = nbr[x];
       by += 4;
-      if (cpi_keep_v(g, J, vp, v, by)) f((uint64_t)J.p.pos[vp], v);
+      // the block's rows are bucket positions of p's label
+      if (cpi_keep_v(g, J, vp, v, by)) f((uint64_t)J.p.pos[J.p.by_bucket ? rows[s] : (uint32_t)vp], v);
     });
   } else {
     const uint32_t* off = J.dir ? g.in_off : g.out_off;
@@ -1403,7 +1410,7 @@ __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __res
 #pragma unroll
     for (int v = 0; v < MAXK; v++) thr[v] = prune && v < J.k ? J.thr[v] : 0;
     job_scan(ext_sources(J), [&](uint64_t s) -> uint32_t {
-      const int32_t c = J.par_posmap[par[s]];
+      const int32_t c = J.par_posmap[pos_index(g, J.par_by_bucket, par[s])];
       J.begs[s] = J.cpi_beg[c];
       if (prune && source_past(J, s, thr)) return 0u;
       return J.cpi_len[c];
@@ -1605,6 +1612,73 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
 void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid) {
   hipLaunchKernelGGL(k_ext_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
 }
+
+// Next-frontier reservation (see front_reserve): one thread per job takes
+// its slots from the pool with one atomic add, then the block zeroes the tile
+// states of every reserved scan (the scan's look-back reads them before any
+// tile writes its own).
+__global__ __launch_bounds__(BS) void k_front_reserve(ExtJob* __restrict__ cur, ExtJob* __restrict__ next,
+                                                      LeafJob* __restrict__ leaf, int njobs,
+                                                      uint8_t* __restrict__ pool, uint64_t pool_bytes,
+                                                      unsigned long long* cursor) {
+  __shared__ uint64_t* s_ts[MAX_JOBS];
+  __shared__ uint64_t s_tw[MAX_JOBS];
+  const int x = (int)threadIdx.x;
+  uint64_t* ts = nullptr;
+  uint64_t tw = 0;
+  if (x < njobs && cur[x].active && !cur[x].last) {
+    ExtJob& E = cur[x];
+    uint64_t T = *E.sc.d_total;  // attempts: the level keeps at most this many
+    if (E.front_limit && T > E.front_limit) T = E.front_limit;
+    const int w = E.i + 1;  // matched vertices per partial match of the next level
+    auto al = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+    const uint64_t cb = al(4ull * (uint64_t)w * T), pb = al(8ull * (T + 1)), bb = al(4ull * T + 4),
+                   tws = T / SCAN_TILE + 2, tb = al(8ull * tws);
+    const uint64_t need = cb + pb + bb + tb;
+    const unsigned long long base = atomicAdd(cursor, (unsigned long long)need);
+    if (base + need <= pool_bytes) {
+      uint8_t* p = pool + base;
+      int32_t* cols = (int32_t*)p;
+      E.dst_cols = cols;
+      E.dst_cap = T;
+      ts = (uint64_t*)(p + cb + pb + bb);
+      tw = tws;
+      if (next && next[x].active && next[x].i == w) {
+        ExtJob& N = next[x];
+        N.src_cols = cols;
+        N.src_stride = T;
+        N.src_cap = T;
+        N.sc.P = (uint64_t*)(p + cb);
+        N.begs = (uint32_t*)(p + cb + pb);
+        N.sc.tstate = ts;
+      }
+      if (leaf && leaf[x].active && leaf[x].i == w) {
+        LeafJob& F = leaf[x];
+        F.src_cols = cols;
+        F.src_stride = T;
+        F.src_cap = T;
+      }
+    } else {
+      E.dst_cols = nullptr;
+      E.dst_cap = 0;
+    }
+  }
+  if (x < MAX_JOBS) {
+    s_ts[x] = ts;
+    s_tw[x] = tw;
+  }
+  __syncthreads();
+  for (int j = 0; j < njobs; j++) {
+    uint64_t* t = s_ts[j];
+    for (uint64_t q = threadIdx.x; q < s_tw[j]; q += BS) t[q] = 0;
+  }
+}
+
+void front_reserve(hipStream_t st, ExtJob* cur, ExtJob* next, LeafJob* leaf, int njobs,
+                   uint8_t* pool, uint64_t pool_bytes, unsigned long long* cursor) {
+  hipLaunchKernelGGL(k_front_reserve, dim3(1), dim3(BS), 0, st, cur, next, leaf, njobs, pool, pool_bytes,
+                     cursor);
+}
 void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
              bool ahead, unsigned long long* bytes) {
   if (last && ahead)
@@ -1691,14 +1765,43 @@ __global__ __launch_bounds__(BS) void k_leaf_prep(DevGraph g, const LeafJob* __r
   }
 }
 
-// Injective assignments of r leaves to sets A_0 .. A_{r-1}, from c[B] =
-// |intersection of A_j, j in B|: the sum over set partitions of the leaves of
-// the product over blocks of (-1)^(|B|-1) (|B|-1)! c[B] (Moebius inversion on
-// the partition lattice).
-__device__ __forceinline__ int64_t injective(int r, const int64_t (&c)[LEAF_SUBSETS]) {
-  if (r == 1) return c[1];
-  if (r == 2) return c[1] * c[2] - c[3];
-  return c[1] * c[2] * c[4] - c[3] * c[4] - c[5] * c[2] - c[6] * c[1] + 2 * c[7];
+// A leaf count as a counter increment; out of range sets `ovf`.
+__device__ __forceinline__ unsigned long long leaf_add(__int128 x, bool& ovf) {
+  if (x < 0 || x > (__int128)LEAF_COUNT_MAX) {
+    ovf = true;
+    return 0ull;
+  }
+  return (unsigned long long)x;
+}
+
+// flush_acc for counts that may be large: an add whose result would pass
+// 2^63 (judged from the value before it) sets the job's overflow flag.
+__device__ __forceinline__ void flush_acc_checked(unsigned long long* counters, FinalAcc acc,
+                                                  uint32_t* flags, bool ovf) {
+  __shared__ unsigned long long s_acc2[2][BS / WAVE];
+  __shared__ uint32_t s_ovf;
+  acc.match = wave_sum(acc.match);
+  acc.viol = wave_sum(acc.viol);
+  const uint32_t wv = threadIdx.x / WAVE;
+  __syncthreads();
+  if (threadIdx.x == 0) s_ovf = 0;
+  __syncthreads();
+  if (ovf) s_ovf = 1;
+  if (lane() == 0) {
+    s_acc2[0][wv] = acc.match;
+    s_acc2[1][wv] = acc.viol;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    unsigned long long s = 0;
+    for (int w = 0; w < BS / WAVE; w++) s += s_acc2[threadIdx.x][w];
+    bool bad = s_ovf != 0;
+    if (s) {
+      const unsigned long long old = atomicAdd(&counters[threadIdx.x], s);
+      bad |= old + s < old || ((old + s) >> 63) != 0;
+    }
+    if (bad) atomicOr(flags, FLAG_COUNTER_OVERFLOW);
+  }
 }
 
 __device__ __forceinline__ uint64_t leaf_sources(const LeafJob& J) {
@@ -1720,6 +1823,7 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
   const uint64_t s1 = s0 + LBS_CHUNK < N ? s0 + LBS_CHUNK : N;
   const uint32_t nsub = 1u << J.r;
   FinalAcc acc{0, 0, 0, 0};
+  bool ovf = false;
   for (uint64_t s = s0 + threadIdx.x; s < s1; s += BS) {
     // the partial match, its parent's row in the count table and the words read
     by += 4ull * (uint64_t)J.i + 4 + 4ull * LEAF_WORDS;
@@ -1727,7 +1831,7 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
 #pragma unroll
     for (int j = 0; j < MAXK; j++) h[j] = j < J.i ? J.src_cols[(uint64_t)j * J.src_stride + s] : 0;
     const int32_t vp = pick(h, J.par_pos);
-    const uint32_t* cc = J.cnt + (uint64_t)J.par_posmap[vp] * LEAF_WORDS;
+    const uint32_t* cc = J.cnt + (uint64_t)J.par_posmap[pos_index(g, J.par_by_bucket, vp)] * LEAF_WORDS;
     int64_t c[LEAF_FAMILIES][LEAF_SUBSETS];
 #pragma unroll
     for (int f = 0; f < LEAF_FAMILIES; f++)
@@ -1761,13 +1865,14 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
       if (t < J.nx) X = X && v;
       else Y = Y && v;
     }
-    acc.match += (unsigned long long)injective(J.r, c[0]);
+    acc.match += leaf_add(leaf_injective(J.r, c[0]), ovf);
     if (X) {
-      const int64_t ix = injective(J.r, c[1]);
-      acc.viol += (unsigned long long)(Y ? ix - injective(J.r, c[2]) : ix);
+      const __int128 ix = leaf_injective(J.r, c[1]);
+      acc.viol += leaf_add(Y ? ix - leaf_injective(J.r, c[2]) : ix, ovf);
     }
   }
-  flush_acc(J.counters, acc);  // counts only: the fingerprint sums stay zero
+  // counts only: the fingerprint sums stay zero
+  flush_acc_checked(J.counters, acc, J.flags, ovf);
   }
   if (bytes) block_add(bytes, by);
 }

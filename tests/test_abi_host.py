@@ -37,7 +37,7 @@ def test_exports_every_declared_function():
 STRUCTS = {
     "gfd_literal": B.gfd_literal, "gfd_edge": B.gfd_edge, "gfd_spec": B.gfd_spec,
     "gfd_result": B.gfd_result, "gfd_load_opts": B.gfd_load_opts,
-    "gfd_validate_opts": B.gfd_validate_opts, "gfd_stats": B.gfd_stats,
+    "gfd_validate_opts": B.gfd_validate_opts, "gfd_stats": B.gfd_stats, "gfd_allocator": B.gfd_allocator,
     "gfd_graph_info": B.gfd_graph_info, "gfd_server_opts": B.gfd_server_opts,
     "gfd_request_info": B.gfd_request_info,
 }
@@ -129,3 +129,47 @@ def test_server_rejects_bad_arguments():
     assert B.lib.gfd_server_submit(None, C.byref(spec), 1, C.byref(rid)) == B.GFD_EINVAL
     assert B.lib.gfd_server_wait(None, 1, 0, None, None) == B.GFD_EINVAL
     B.lib.gfd_server_destroy(None)  # ignored
+
+
+def test_load_graph_rejects_malformed_options():
+    """An allocator with alloc but no free, or an unknown mem_kind, is refused
+    before anything touches a device."""
+    n, rp, col, vl, el, at = _graph_arrays()
+    out = C.c_void_p()
+    ptrs = (C.c_void_p * 1)(at[0].ctypes.data)
+    args = (n, len(col), rp.ctypes.data, col.ctypes.data, vl.ctypes.data, el.ctypes.data, 1, ptrs)
+    half = B.gfd_allocator(B.ALLOC_FN(lambda ctx, nb, st: None), B.FREE_FN(), None)
+    opts = B.gfd_load_opts(None, B.GFD_MEM_HOST, half)
+    assert B.lib.gfd_load_graph(*args, C.byref(opts), C.byref(out)) == B.GFD_EINVAL
+    assert "free" in P.last_error()
+    opts = B.gfd_load_opts(None, 7, B.gfd_allocator())
+    assert B.lib.gfd_load_graph(*args, C.byref(opts), C.byref(out)) == B.GFD_EINVAL
+    assert "mem_kind" in P.last_error()
+
+
+@pytest.mark.parametrize("which,value,code", [
+    ("vlabel", (1 << 24), B.GFD_EUNSUPPORTED),   # above GFD_MAX_LABEL
+    ("elabel", (1 << 24), B.GFD_EUNSUPPORTED),
+    ("vlabel", (1 << 31) - 1, B.GFD_EUNSUPPORTED),  # INT32_MAX: no signed overflow
+    ("both", 5000, B.GFD_EUNSUPPORTED),          # 5001 * 5001 label pairs > 2^24
+    ("vlabel", 4095, None),                      # 4096 * 1 pairs: accepted (no device here)
+])
+def test_label_id_limits(which, value, code):
+    """Host tables are sized by the largest label ids: ids above GFD_MAX_LABEL
+    and key spaces above GFD_MAX_LABEL_PAIRS are refused with a status code
+    (not an allocation failure or a crash) before any device work."""
+    n, rp, col, vl, el, at = _graph_arrays()
+    if which in ("vlabel", "both"):
+        vl[0] = value
+    if which in ("elabel", "both"):
+        el[0] = value
+    if code is None:
+        try:
+            P.load_graph(n, len(col), rp, col, vl, el, at)
+        except P.GfdError as e:  # no GPU in this container: the device step fails
+            assert e.code in (B.GFD_EDEVICE, B.GFD_ENOMEM), e
+        return
+    with pytest.raises(P.GfdError) as ei:
+        P.load_graph(n, len(col), rp, col, vl, el, at)
+    assert ei.value.code == code
+    assert "label" in P.last_error()
