@@ -230,6 +230,24 @@ int32_t gfd_validate(const gfd_graph* g, const gfd_spec* specs, int32_t num_spec
 int32_t gfd_validate_ex(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
                         const gfd_validate_opts* opts, gfd_result* results, gfd_stats* stats);
 
+/* gfd_validate for callers that cannot allocate (code that must not call
+ * hipMalloc or an allocator: tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as gfd_validate, but no
+ * device or pinned host memory is allocated and no HIP event is created:
+ * every device byte comes from a scratch area of GFD_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it runs on, from its first use until
+ * the process ends.  Host staging is ordinary memory, so copies to and from
+ * the device are synchronous.  opts->allocator must be empty and opts->flags
+ * may hold only GFD_FLAG_FORCE_CHUNKED and GFD_FLAG_COUNT_ONLY; the current
+ * device must be the graph's.  A call whose working set does not fit the area
+ * fails with GFD_ENOMEM (a smaller batch, or one GFD at a time, needs less).
+ * Calls on one device share its area, which keeps the last call's contents:
+ * the library runs them one at a time (a second call waits for the first),
+ * and nothing else may use the area. */
+#define GFD_NOALLOC_SCRATCH_BYTES (256u << 20)
+int32_t gfd_validate_noalloc(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
+                             const gfd_validate_opts* opts, gfd_result* results);
+
 /* Graph facts: sizes and the device bytes it holds. */
 typedef struct {
   int64_t n, m;

@@ -109,6 +109,7 @@ class gfd_request_info(C.Structure):
 
 
 EXPORTS = ("gfd_load_graph", "gfd_free_graph", "gfd_trim", "gfd_validate", "gfd_validate_ex",
+           "gfd_validate_noalloc",
            "gfd_get_graph_info", "gfd_server_create", "gfd_server_submit", "gfd_server_wait",
            "gfd_server_destroy", "gfd_last_error", "gfd_version")
 
@@ -137,6 +138,9 @@ def _load():
     L.gfd_validate.restype = C.c_int32
     L.gfd_validate.argtypes = [C.c_void_p, C.POINTER(gfd_spec), C.c_int32,
                                C.POINTER(gfd_validate_opts), C.POINTER(gfd_result)]
+    L.gfd_validate_noalloc.restype = C.c_int32
+    L.gfd_validate_noalloc.argtypes = [C.c_void_p, C.POINTER(gfd_spec), C.c_int32,
+                                       C.POINTER(gfd_validate_opts), C.POINTER(gfd_result)]
     L.gfd_validate_ex.restype = C.c_int32
     L.gfd_validate_ex.argtypes = [C.c_void_p, C.POINTER(gfd_spec), C.c_int32,
                                   C.POINTER(gfd_validate_opts), C.POINTER(gfd_result),
@@ -431,8 +435,11 @@ class PreparedCall:
 def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
              mem_budget_bytes: int = 0, stream=None, flags: int = 0, frontier_cap: int = 0,
              violation_cap: int = 0, stats: bool = False, batched: bool = False,
-             allocator="torch"):
-    """gfd_validate(_ex): one result dict per GFD (plus a stats dict if asked)."""
+             allocator="torch", noalloc: bool = False):
+    """gfd_validate(_ex): one result dict per GFD (plus a stats dict if asked).
+    noalloc: gfd_validate_noalloc instead (no allocator, no statistics)."""
+    if noalloc:
+        allocator = None
     n = len(gfds)
     specs = (gfd_spec * max(n, 1))(*[make_spec(d) for d in gfds])
     results = (gfd_result * max(n, 1))()
@@ -448,8 +455,13 @@ def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced"
                              int(flags),
                              int(frontier_cap), int(violation_cap), ca)
     st = gfd_stats()
-    rc = lib.gfd_validate_ex(graph.handle, specs, n, C.byref(opts), results,
-                             C.byref(st) if stats else None)
+    if noalloc:
+        if stats:
+            raise ValueError("gfd_validate_noalloc keeps no statistics")
+        rc = lib.gfd_validate_noalloc(graph.handle, specs, n, C.byref(opts), results)
+    else:
+        rc = lib.gfd_validate_ex(graph.handle, specs, n, C.byref(opts), results,
+                                 C.byref(st) if stats else None)
     _check(rc)
     out = []
     for i, d in enumerate(gfds):

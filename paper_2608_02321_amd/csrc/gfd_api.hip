@@ -73,10 +73,21 @@ struct DevAlloc {
   gfd_allocator cb{};
   hipStream_t st = nullptr;  // the stream handed to cb.alloc
   int64_t live = 0;          // bytes handed out and not yet returned
+  // fixed area (the entry point that allocates nothing): blocks are carved
+  // from [area, area + area_cap) in order; returning the last one takes it back
+  uint8_t* area = nullptr;
+  size_t area_cap = 0, area_top = 0;
+  static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
   void* get(size_t bytes) {
     bytes = std::max<size_t>(bytes, 1);
     void* p = nullptr;
-    if (cb.alloc) {
+    if (area) {
+      if (area_top + round(bytes) > area_cap)
+        throw GfdError{GFD_ENOMEM, "the call needs more than the " + std::to_string(area_cap >> 20) +
+                                       " MiB scratch area (" + std::to_string(bytes) + " more bytes)"};
+      p = area + area_top;
+      area_top += round(bytes);
+    } else if (cb.alloc) {
       p = cb.alloc(cb.ctx, (int64_t)bytes, (void*)st);
       if (!p)
         throw GfdError{GFD_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
@@ -94,8 +105,13 @@ struct DevAlloc {
     if (!p) return;
     bytes = std::max<size_t>(bytes, 1);
     live -= (int64_t)bytes;
-    if (cb.alloc) cb.free(cb.ctx, p, (int64_t)bytes);
-    else (void)hipFree(p);
+    if (area) {
+      if ((uint8_t*)p + round(bytes) == area + area_top) area_top -= round(bytes);
+    } else if (cb.alloc) {
+      cb.free(cb.ctx, p, (int64_t)bytes);
+    } else {
+      (void)hipFree(p);
+    }
   }
   bool same(const gfd_allocator& o) const {
     return cb.alloc == o.alloc && cb.free == o.free && cb.ctx == o.ctx;
@@ -187,6 +203,37 @@ struct Workspace {
   hipEvent_t pack_ev = nullptr;     // the last packed copy to ws->hres has landed
   int64_t budget = 0;
   DevAlloc al;                      // where every device buffer above comes from
+  bool pageable = false;            // host staging in ordinary memory (no pinned allocation)
+
+  void* host_get(size_t bytes, bool mapped) {
+    if (pageable) return ::operator new(std::max<size_t>(bytes, 1));
+    void* p = nullptr;
+    HIPCHK(hipHostMalloc(&p, std::max<size_t>(bytes, 1), mapped ? hipHostMallocMapped : hipHostMallocDefault));
+    return p;
+  }
+  void host_put(void* p) {
+    if (!p) return;
+    if (pageable) ::operator delete(p);
+    else (void)hipHostFree(p);
+  }
+  // Drops every device buffer without returning it: a fixed area is carved
+  // again from its start by the next call.
+  void forget_device_buffers() {
+    forget_call_buffers();
+    misc = nullptr; err = nullptr; sel_state = nullptr; sel_hist = nullptr; sel_out = nullptr;
+    selrec = nullptr; front_want = 0; cpi_want = 0;
+    al.area_top = 0;
+    area_mark = 0;
+    al.live = 0;
+  }
+  // The buffers above the fixed ones (control words, selection state).
+  void forget_call_buffers() {
+    arena = nullptr; arena_bytes = 0; cpi_arena = nullptr; cpi_cap = 0; jobrec = nullptr;
+    jobrec_bytes = 0; hitpool = nullptr; hitpool_words = 0; hitpool_dirty = false;
+    chunk = nullptr; chunk_bytes = 0; vbig = nullptr; vbig_cap = 0; pack = nullptr; pack_words = 0;
+    front = nullptr; front_bytes = 0;
+  }
+  size_t area_mark = 0;             // fixed area: where the fixed buffers end
 
   ~Workspace() {
     dfree(al, arena, arena_bytes);
@@ -203,12 +250,12 @@ struct Workspace {
     dfree(al, selrec, sizeof(SelJob) * MAX_JOBS);
     dfree(al, pack, pack_words);
     dfree(al, front, front_bytes);
-    if (hjobrec) (void)hipHostFree(hjobrec);
-    if (hselrec) (void)hipHostFree(hselrec);
-    if (hmisc) (void)hipHostFree(hmisc);
+    host_put(hjobrec);
+    host_put(hselrec);
+    host_put(hmisc);
     if (pack_ev) (void)hipEventDestroy(pack_ev);
-    if (hctl) (void)hipHostFree(hctl);
-    if (hres) (void)hipHostFree(hres);
+    host_put(hctl);
+    host_put(hres);
   }
 };
 
@@ -1264,13 +1311,13 @@ static void ensure_recs(Workspace* ws, size_t bytes) {
     ws->jobrec_bytes = bytes;
   }
   if (ws->hjobrec_bytes < bytes) {
-    if (ws->hjobrec) (void)hipHostFree(ws->hjobrec);
+    ws->host_put(ws->hjobrec);
     ws->hjobrec = nullptr;
     ws->hjobrec_bytes = 0;
     ws->hjobrec_dev = nullptr;
-    HIPCHK(hipHostMalloc((void**)&ws->hjobrec, bytes, hipHostMallocMapped));
+    ws->hjobrec = (uint8_t*)ws->host_get(bytes, true);
     ws->hjobrec_bytes = bytes;
-    ws->hjobrec_dev = mapped_ptr(ws->hjobrec);
+    ws->hjobrec_dev = ws->pageable ? nullptr : mapped_ptr(ws->hjobrec);
   }
 }
 
@@ -1799,10 +1846,10 @@ static void plan_and_run_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchLi
 // Arena of a batch: [control blocks][tile states][results][job regions].
 static void ensure_hres(Workspace* ws, size_t words) {
   if (ws->hres_words >= words) return;
-  if (ws->hres) (void)hipHostFree(ws->hres);
+  ws->host_put(ws->hres);
   ws->hres = nullptr;
   ws->hres_words = 0;
-  HIPCHK(hipHostMalloc((void**)&ws->hres, sizeof(int32_t) * words, hipHostMallocDefault));
+  ws->hres = (int32_t*)ws->host_get(sizeof(int32_t) * words, false);
   ws->hres_words = words;
 }
 
@@ -1855,11 +1902,12 @@ struct ResultDrain {
       src = ws->pack + w0;
     }
     HIPCHK(hipMemcpyAsync(ws->hres + w0, src, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, c.st));
-    HIPCHK(hipEventRecord(ws->pack_ev, c.st));
+    if (ws->pack_ev) HIPCHK(hipEventRecord(ws->pack_ev, c.st));
   }
   void drain() {
     if (pending.empty()) return;
-    HIPCHK(hipEventSynchronize(c.ws->pack_ev));
+    if (c.ws->pack_ev) HIPCHK(hipEventSynchronize(c.ws->pack_ev));
+    else HIPCHK(hipStreamSynchronize(c.st));
     for (const Item& it : pending)
       std::memcpy(results[jobs[it.x].spec].violations, c.ws->hres + it.off, sizeof(int32_t) * it.words);
     pending.clear();
@@ -1965,10 +2013,10 @@ static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
     p += align_up(J.caps.bytes);
   }
   if (ws->hctl_words < CTL_WORDS * nj) {
-    if (ws->hctl) (void)hipHostFree(ws->hctl);
+    ws->host_put(ws->hctl);
     ws->hctl = nullptr;
     ws->hctl_words = 0;
-    HIPCHK(hipHostMalloc((void**)&ws->hctl, sizeof(uint64_t) * CTL_WORDS * nj, hipHostMallocDefault));
+    ws->hctl = (uint64_t*)ws->host_get(sizeof(uint64_t) * CTL_WORDS * nj, false);
     ws->hctl_words = CTL_WORDS * nj;
   }
   ensure_front(ws);
@@ -2207,12 +2255,22 @@ struct Bounded {
 
 static uint64_t frontier_cap_of(const gfd_graph* g, const Plan& p, int64_t fbytes, int64_t forced);
 
+// Fixed area (the entry point that allocates nothing): nothing above the
+// fixed buffers is needed from one batch to the next, or by a bounded run, so
+// each of them carves the area again from the same point (no holes).
+static void rewind_area(Workspace* ws) {
+  if (!ws->al.area) return;
+  ws->forget_call_buffers();
+  ws->al.area_top = ws->area_mark;
+}
+
 static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
   Workspace* ws = c.ws;
+  rewind_area(ws);
   std::vector<Job> one{J};
-  // the job alone, with its own frontier columns for every level: a quarter
+  // the job alone, with its own frontier columns for every level: an eighth
   // of the budget (or the testing cap)
-  job_caps(c.g, J.plan, frontier_cap_of(c.g, J.plan, ws->budget / 4, (int64_t)c.front_limit), J.caps.vcap,
+  job_caps(c.g, J.plan, frontier_cap_of(c.g, J.plan, ws->budget / 8, (int64_t)c.front_limit), J.caps.vcap,
            true, one[0].caps);
   layout_batch(c, one);
   Job& B = one[0];
@@ -2392,7 +2450,10 @@ static Sizing call_sizing(int64_t budget, int64_t njobs, int64_t deep, int K, in
   const uint64_t vdef = (uint64_t)std::max<int64_t>(
       16384, std::min<int64_t>(budget / (16 * njobs) / (4 * MAXK), int64_t(1) << 18));
   z.vsmall = std::max<uint64_t>(violation_cap ? (uint64_t)violation_cap : vdef, (uint64_t)K + 1);
-  z.vbig = std::max<uint64_t>(violation_cap ? (uint64_t)violation_cap : (4u << 20), (uint64_t)K + 64);
+  // the bounded path's staging: an eighth of the budget, 2^16 to 2^22 tuples
+  const uint64_t vb = (uint64_t)std::max<int64_t>(
+      65536, std::min<int64_t>(budget / (8 * 4 * MAXK), int64_t(4) << 20));
+  z.vbig = std::max<uint64_t>(violation_cap ? (uint64_t)violation_cap : vb, (uint64_t)K + 64);
   // half of the budget holds frontiers, shared evenly by the jobs of a batch
   // that have any (k > 2), each sized for its own pattern size
   z.fbytes = std::min<int64_t>(budget / (2 * std::max<int64_t>(1, deep)), int64_t(8) << 30);
@@ -2418,6 +2479,26 @@ static int64_t default_budget() {
   return std::max<int64_t>(int64_t(256) << 20, std::min<int64_t>(b, int64_t(64) << 30));
 }
 
+// The fixed device buffers of a workspace, its host staging and its event;
+// the selection histograms and the error word start at zero.
+static void init_ws_buffers(Workspace* w, hipStream_t st) {
+  w->misc = dalloc<unsigned long long>(w->al, 16);
+  w->err = dalloc<uint32_t>(w->al, 1);
+  w->sel_state = dalloc<uint32_t>(w->al, (size_t)MAX_JOBS * SEL_STATE_WORDS);
+  w->sel_hist = dalloc<uint32_t>(w->al, (size_t)MAX_JOBS * RADIX_BINS);
+  w->sel_out = dalloc<int32_t>(w->al, (size_t)SORT_MAX * MAXK);
+  w->selrec = dalloc<uint8_t>(w->al, sizeof(SelJob) * MAX_JOBS);
+  if (!w->hselrec) {
+    w->hselrec = (uint8_t*)w->host_get(sizeof(SelJob) * MAX_JOBS, true);
+    w->hselrec_dev = w->pageable ? nullptr : mapped_ptr(w->hselrec);
+  }
+  if (!w->hmisc) w->hmisc = (uint64_t*)w->host_get(sizeof(uint64_t) * 16, false);
+  if (!w->pageable && !w->pack_ev) HIPCHK(hipEventCreateWithFlags(&w->pack_ev, hipEventDisableTiming));
+  fill_u32(st, w->sel_hist, 0u, (uint64_t)MAX_JOBS * RADIX_BINS);
+  fill_u32(st, w->err, 0u, 1);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
 // An idle workspace of g whose device memory comes from `alloc` (made if
 // there is none); its buffers grow as calls need them.
 static Workspace* acquire_ws(gfd_graph* g, int64_t budget, const gfd_allocator& alloc,
@@ -2438,19 +2519,7 @@ static Workspace* acquire_ws(gfd_graph* g, int64_t budget, const gfd_allocator& 
     w->budget = budget;
     w->al.cb = alloc;
     w->al.st = st;
-    w->misc = dalloc<unsigned long long>(w->al, 16);
-    w->err = dalloc<uint32_t>(w->al, 1);
-    w->sel_state = dalloc<uint32_t>(w->al, (size_t)MAX_JOBS * SEL_STATE_WORDS);
-    w->sel_hist = dalloc<uint32_t>(w->al, (size_t)MAX_JOBS * RADIX_BINS);
-    w->sel_out = dalloc<int32_t>(w->al, (size_t)SORT_MAX * MAXK);
-    w->selrec = dalloc<uint8_t>(w->al, sizeof(SelJob) * MAX_JOBS);
-    HIPCHK(hipHostMalloc((void**)&w->hselrec, sizeof(SelJob) * MAX_JOBS, hipHostMallocMapped));
-    w->hselrec_dev = mapped_ptr(w->hselrec);
-    HIPCHK(hipHostMalloc((void**)&w->hmisc, sizeof(uint64_t) * 16, hipHostMallocDefault));
-    HIPCHK(hipEventCreateWithFlags(&w->pack_ev, hipEventDisableTiming));
-    HIPCHK(hipMemset(w->sel_hist, 0, 4 * (size_t)MAX_JOBS * RADIX_BINS));
-    HIPCHK(hipMemset(w->err, 0, 4));
-    HIPCHK(hipDeviceSynchronize());
+    init_ws_buffers(w, st);
   } catch (...) {
     delete w;
     throw;
@@ -2465,9 +2534,11 @@ static void release_ws(gfd_graph* g, Workspace* w) {
   g->pool.push_back(w);
 }
 
-extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, int32_t num_specs,
-                                   const gfd_validate_opts* opts, gfd_result* results,
-                                   gfd_stats* stats) {
+// gfd_validate_ex on a workspace from the graph's pool (fixed == nullptr) or
+// on the given one, whose budget is set.
+static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t num_specs,
+                             const gfd_validate_opts* opts, gfd_result* results, gfd_stats* stats,
+                             Workspace* fixed) {
   const auto t_start = std::chrono::steady_clock::now();
   gfd_graph* g = const_cast<gfd_graph*>(gc);
   if (!g) return set_error(GFD_EINVAL, "graph is NULL");
@@ -2497,8 +2568,9 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
   const int K = o.k_max;
   Workspace* ws = nullptr;
   try {
-    const int64_t budget = o.mem_budget_bytes ? o.mem_budget_bytes : default_budget();
-    ws = acquire_ws(g, budget, o.allocator, (hipStream_t)o.hip_stream);
+    const int64_t budget =
+        fixed ? fixed->budget : (o.mem_budget_bytes ? o.mem_budget_bytes : default_budget());
+    ws = fixed ? fixed : acquire_ws(g, budget, o.allocator, (hipStream_t)o.hip_stream);
     if (ws->hitpool_dirty && ws->hitpool)  // an earlier call stopped midway
       fill_u32((hipStream_t)o.hip_stream, ws->hitpool, 0u, ws->hitpool_words);
     ws->hitpool_dirty = true;
@@ -2516,7 +2588,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     c.tm.mask = cls_mask ? cls_mask : 0xFFu;
     c.tm.st = c.st;
     if (stats) fill_u64(c.st, (uint64_t*)(ws->misc + 8), 0, 8);
-    HIPCHK(hipMemsetAsync(ws->err, 0, 4, c.st));
+    fill_u32(c.st, ws->err, 0u, 1);
     // plans, capacities and batches
     std::vector<Job> all(num_specs);
     for (int32_t i = 0; i < num_specs; i++) {
@@ -2563,6 +2635,7 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
     for (size_t bi = 0; bi < batches.size(); bi++) {
       std::vector<Job> jobs;
       for (int i : batches[bi]) jobs.push_back(all[i]);
+      rewind_area(ws);
       layout_batch(c, jobs);
       std::vector<char> redo(jobs.size(), force_bounded ? 1 : 0);
       if (!force_bounded) {
@@ -2716,12 +2789,91 @@ extern "C" int32_t gfd_validate_ex(const gfd_graph* gc, const gfd_spec* specs, i
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
     ws->hitpool_dirty = false;
-    release_ws(g, ws);
+    if (!fixed) release_ws(g, ws);
     return rc;
   } catch (...) {
-    if (ws) release_ws(g, ws);
+    if (ws && !fixed) release_ws(g, ws);
     return guarded([] () -> int32_t { throw; });
   }
+}
+
+extern "C" int32_t gfd_validate_ex(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
+                                   const gfd_validate_opts* opts, gfd_result* results,
+                                   gfd_stats* stats) {
+  return validate_impl(g, specs, num_specs, opts, results, stats, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// the entry point that allocates nothing
+// ---------------------------------------------------------------------------
+
+// Every device byte of gfd_validate_noalloc's workspace is carved from this
+// array (one copy per device the library runs on, held until the process
+// ends).  Host code never uses its name as an address: the device address of
+// each device's copy comes from hipGetSymbolAddress.
+static __device__ __align__(256) uint8_t scratch[GFD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+struct NoAllocDevice {
+  std::mutex mu;            // calls on one device share its scratch: one at a time
+  uint8_t* ptr = nullptr;   // device address of this device's scratch
+  Workspace* ws = nullptr;  // host state of those calls (pageable host staging)
+};
+std::mutex g_noalloc_mu;
+std::unordered_map<int, NoAllocDevice*> g_noalloc;  // by device, never freed
+
+NoAllocDevice* noalloc_device(int dev) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  NoAllocDevice*& d = g_noalloc[dev];
+  if (!d) d = new NoAllocDevice();
+  return d;
+}
+}  // namespace
+
+extern "C" int32_t gfd_validate_noalloc(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
+                                        const gfd_validate_opts* opts, gfd_result* results) {
+  if (!g) return set_error(GFD_EINVAL, "graph is NULL");
+  gfd_validate_opts o{};
+  o.k_max = 1024;
+  o.semantics = GFD_SEM_INDUCED;
+  if (opts) o = *opts;
+  if (o.flags & ~(GFD_FLAG_FORCE_CHUNKED | GFD_FLAG_COUNT_ONLY))
+    return set_error(GFD_EINVAL, "timing flags need events, which this entry point does not create");
+  if (o.allocator.alloc) return set_error(GFD_EINVAL, "this entry point takes no allocator");
+  if (o.mem_budget_bytes < 0) return set_error(GFD_EINVAL, "negative option");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(GFD_EDEVICE, "no current device");
+  }
+  if (dev != g->device) return set_error(GFD_EINVAL, "the graph lives on device %d, not the current %d", g->device, dev);
+  NoAllocDevice* d = noalloc_device(dev);
+  std::lock_guard<std::mutex> lk(d->mu);
+  return guarded([&] {
+    if (!d->ptr) {  // once per device, with that device current
+      void* p = nullptr;
+      HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      d->ptr = (uint8_t*)p;
+    }
+    if (!d->ws) {
+      d->ws = new Workspace();
+      d->ws->pageable = true;
+    }
+    Workspace* w = d->ws;
+    // every call carves the area again from its start; what must start at
+    // zero is cleared on the call's stream
+    w->forget_device_buffers();
+    w->al.area = d->ptr;
+    w->al.area_cap = (size_t)GFD_NOALLOC_SCRATCH_BYTES;
+    w->al.st = (hipStream_t)o.hip_stream;
+    // half of the area for the batches' candidate structures; the rest holds
+    // the fixed buffers, records, frontier pool, CPI arena and staging
+    const int64_t half = (int64_t)GFD_NOALLOC_SCRATCH_BYTES / 2;
+    w->budget = o.mem_budget_bytes ? std::min<int64_t>(o.mem_budget_bytes, half) : half;
+    init_ws_buffers(w, (hipStream_t)o.hip_stream);
+    w->area_mark = w->al.area_top;
+    return validate_impl(g, specs, num_specs, &o, results, nullptr, w);
+  });
 }
 
 extern "C" int32_t gfd_validate(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
