@@ -265,7 +265,9 @@ def main():
     pc = P.PreparedCall(gh, gfds, K=K, semantics=args.semantics, stream=stream,
                         batched=batched)
 
-    # warm-up; the last warm-up step records every kernel class to find the dominant one
+    # warm-up (the first step captures the batch's main pass as a graph, later
+    # ones replay it); the last warm-up step runs eagerly with events on every
+    # kernel class to find the dominant one
     for w in range(max(1, args.warmup)):
         st = pc.run(flags=base_flags | (0 if args.no_timing or w < args.warmup - 1
                                         else P.GFD_FLAG_TIMING))
@@ -284,34 +286,43 @@ def main():
             for k, v in st["class_ms"].items()))
         log(f"warm-up: wall {st['wall_ms']:.1f} ms, kernel time {sum(st['class_ms'].values()):.1f} ms, "
             f"chunked {st['chunked_gfds']}, threshold {st['threshold_gfds']}/{st['threshold_passes']}, "
-            f"counted leaves {st['leaf_gfds']}, regrown {st['regrown_gfds']}, frontier pool "
+            f"counted leaves {st['leaf_gfds']}, regrown {st['regrown_gfds']}, graphs "
+            f"{st['graph_captures']} captured / {st['graph_replays']} replayed, frontier pool "
             f"{st['front_pool_bytes'] / 1e6:.0f} MB, CPI arena {st['cpi_arena_bytes'] / 1e6:.0f} MB")
         enum_ms = st["class_ms"]["extend"] + st["class_ms"]["extend_last"]
         if enum_ms > 0:
             enum_rate = sum(r["match_count"] for r in res) / (enum_ms * 1e-3)
-    flags = base_flags | (0 if dom is None else (1 << (8 + dom)))  # events: dominant class only
-    agg_ms = agg_bytes = agg_launch = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step_ms = []
     for _ in range(args.steps):
         ts = time.perf_counter()
-        st = pc.run(flags=flags)  # synchronous: returns with the results on the host
+        st = pc.run(flags=base_flags)  # synchronous: returns with the results on the host
         step_ms.append((time.perf_counter() - ts) * 1e3)
-        if dom is not None:
-            name = KERNEL_CLASSES[dom]
-            agg_ms += st["class_ms"][name]
-            agg_bytes += st["class_bytes"][name]
-            agg_launch += st["class_launches"][name]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
     assert pc.results() == res, "results changed between steps"
+    graph_replays = st["graph_replays"]
+    # the dominant kernel's launches, timed with HIP events on the call's
+    # stream over further steps run eagerly (events around kernels inside a
+    # replayed graph are not available); the kernels are the same
+    agg_ms = agg_bytes = agg_launch = 0.0
+    roof_steps = 0
+    if dom is not None:
+        roof_steps = max(3, min(args.steps, 10))
+        name = KERNEL_CLASSES[dom]
+        for _ in range(roof_steps):
+            s2 = pc.run(flags=base_flags | P.GFD_FLAG_NO_GRAPH | (1 << (8 + dom)))
+            agg_ms += s2["class_ms"][name]
+            agg_bytes += s2["class_bytes"][name]
+            agg_launch += s2["class_launches"][name]
+        assert pc.results() == res, "eager results differ from the replayed ones"
     matches = sum(r["match_count"] for r in res)
     value = matches * args.steps / elapsed
     gfds_per_s = len(gfds) * args.steps / elapsed
     log(f"{mode}: step {ms_per_step:.3f} ms, {matches} matches, {value:.4g} embeddings/s, "
-        f"{gfds_per_s:.1f} GFDs/s, launches/step {st['launches']}, "
+        f"{gfds_per_s:.1f} GFDs/s, launches/step {st['launches']} (graph replays {graph_replays}), "
         f"bounded re-runs {st['chunked_gfds']}")
 
     roofline = None
@@ -331,7 +342,9 @@ def main():
         roofline = {"bound": "hbm", "kernel_class": name, "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": per_launch,
-                    "launches_per_step": agg_launch / args.steps,
+                    "launches_per_step": agg_launch / roof_steps,
+                    "timed_over": f"{roof_steps} eager steps after the timed ones, HIP events "
+                                  f"around each launch of the class on the call's stream",
                     "copy_gbs": copy, "frac_of_copy": ach / copy}
 
     if args.per_gfd:
@@ -355,8 +368,9 @@ def main():
         # up front like the batched call
         one = [P.PreparedCall(gh, [d], K=K, semantics=args.semantics, stream=stream)
                for d in gfds]
-        for q in one[:8]:
-            q.run(flags=base_flags, stats=False)
+        for _ in range(2):  # warm: each call's main pass runs once, is captured, then replayed
+            for q in one:
+                q.run(flags=base_flags, stats=False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for q in one:

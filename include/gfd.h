@@ -154,6 +154,13 @@ typedef struct {
  * per partial match (inclusion-exclusion over their candidate lists) instead
  * of enumerated: the leaf postponement of CFL-Match that Section IV-B adopts. */
 #define GFD_FLAG_COUNT_ONLY 4
+/* Run every launch eagerly.  By default a batch's main pass (its clears, the
+ * candidate filter, CPI construction, enumeration with the literal check and
+ * the first K, and the read-back of its counters) is captured as a HIP graph
+ * the first time a batch of that shape runs on a workspace and replayed as
+ * one graph launch afterwards; results are the same either way.  Calls with
+ * timing flags run eagerly. */
+#define GFD_FLAG_NO_GRAPH 8
 /* record HIP event timings for kernel class c (0..7, see gfd_stats) only */
 #define GFD_FLAG_TIMING_CLASS(c) (1 << (8 + (c)))
 
@@ -184,6 +191,8 @@ typedef struct {
                                  the CPI entry arena grew to what their batch asked for */
   int64_t front_pool_bytes;   /* frontier pool and CPI entry arena sizes after the call */
   int64_t cpi_arena_bytes;
+  int32_t graph_captures;     /* batches whose main pass was captured as a graph */
+  int32_t graph_replays;      /* batches whose main pass replayed a captured graph */
 } gfd_stats;
 
 /* Load a graph given as out-CSR, in host memory or (opts->mem_kind ==

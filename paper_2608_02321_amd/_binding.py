@@ -22,7 +22,7 @@ GFD_MAX_LITERALS = 8
 GFD_MAX_PATTERN_EDGES = GFD_MAX_K * (GFD_MAX_K - 1)
 GFD_LIT_CONST, GFD_LIT_VAR = 0, 1
 GFD_SEM_INDUCED, GFD_SEM_MONO = 0, 1
-GFD_FLAG_FORCE_CHUNKED, GFD_FLAG_TIMING, GFD_FLAG_COUNT_ONLY = 1, 2, 4
+GFD_FLAG_FORCE_CHUNKED, GFD_FLAG_TIMING, GFD_FLAG_COUNT_ONLY, GFD_FLAG_NO_GRAPH = 1, 2, 4, 8
 STATUS_NAMES = {0: "GFD_OK", -1: "GFD_EINVAL", -2: "GFD_ENOMEM", -3: "GFD_EDEVICE",
                 -4: "GFD_EUNSUPPORTED", -5: "GFD_EOVERFLOW", -6: "GFD_EAGAIN"}
 KERNEL_CLASSES = ("filter", "pull", "cpi", "extend", "extend_last", "scan", "topk", "other")
@@ -87,7 +87,8 @@ class gfd_stats(C.Structure):
                 ("class_bytes", C.c_uint64 * 8), ("threshold_gfds", C.c_int32),
                 ("threshold_passes", C.c_int32), ("leaf_gfds", C.c_int32),
                 ("regrown_gfds", C.c_int32), ("front_pool_bytes", C.c_int64),
-                ("cpi_arena_bytes", C.c_int64)]
+                ("cpi_arena_bytes", C.c_int64), ("graph_captures", C.c_int32),
+                ("graph_replays", C.c_int32)]
 
 
 class gfd_graph_info(C.Structure):

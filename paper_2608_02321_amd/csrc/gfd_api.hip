@@ -160,6 +160,10 @@ enum {
 
 constexpr int SEL_STATE_WORDS = 16;
 
+struct GraphEntry;
+struct Workspace;
+static void drop_graphs(Workspace* ws);
+
 struct Workspace {
   uint8_t* arena = nullptr;         // per-job regions of the current batch
   size_t arena_bytes = 0;
@@ -234,8 +238,17 @@ struct Workspace {
     front = nullptr; front_bytes = 0;
   }
   size_t area_mark = 0;             // fixed area: where the fixed buffers end
+  // captured main passes of batches, replayed when a batch of the same shape
+  // comes again (oldest first); a graph is valid only for the generation of
+  // the buffers it was captured on
+  uint64_t gen = 0;
+  std::vector<GraphEntry*> graphs;
+  hipStream_t cap_stream = nullptr;
+  std::deque<size_t> seen;          // hashes of batch shapes run once (captured on the second run)
 
   ~Workspace() {
+    drop_graphs(this);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     dfree(al, arena, arena_bytes);
     dfree(al, cpi_arena, cpi_cap);
     dfree(al, hitpool, hitpool_words);
@@ -1151,6 +1164,7 @@ struct Ctx {
   Timer tm;
   gfd_stats* stats;
   unsigned long long* stat_bytes;  // device [8] per kernel class, or nullptr
+  uint8_t* recbase = nullptr;  // device records the launches read (nullptr: ws->jobrec)
 };
 
 static unsigned long long* cls_bytes(Ctx& c, int cls) {
@@ -1550,6 +1564,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       e.last = p.leaf_r == 0 && i == p.k - 1;
       e.begs = J.mem.begs;
       e.sc = job_scan_rec(c, J, J.mem.ctl + CTL_LEVEL_T + i, ep);
+      e.home_P = J.mem.P;
       if (i == 1) {
         const CandSet r = cand_set(J, p.root);
         e.src_cols = r.list;
@@ -1732,7 +1747,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
 
 static void run_launch(Ctx& c, const Launch& l) {
   const DevGraph& g = c.g->dg;
-  uint8_t* base = c.ws->jobrec;
+  uint8_t* base = c.recbase ? c.recbase : c.ws->jobrec;
   {
     switch (l.kind) {
       case 0: {
@@ -1956,6 +1971,7 @@ static void ensure_front(Workspace* ws) {
   ws->front_bytes = 0;
   ws->front = dalloc<uint8_t>(ws->al, want);
   ws->front_bytes = want;
+  ws->gen++;
 }
 static void ensure_cpi(Workspace* ws) {
   const size_t want = std::max(ws->cpi_want, adapt_start(ws) / 4);
@@ -1964,6 +1980,7 @@ static void ensure_cpi(Workspace* ws) {
   ws->cpi_cap = 0;
   ws->cpi_arena = dalloc<int32_t>(ws->al, want);
   ws->cpi_cap = want;
+  ws->gen++;
 }
 
 // The batch arena only grows (allocations of this size are slow).
@@ -1973,9 +1990,20 @@ static void ensure_arena(Workspace* ws, size_t bytes) {
   ws->arena_bytes = 0;
   ws->arena = dalloc<uint8_t>(ws->al, bytes);
   ws->arena_bytes = bytes;
+  ws->gen++;
 }
 
-static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
+// Places every job's buffers (growing the workspace where needed) and, when
+// `fills` is set, enqueues the clears a batch starts from; returns the bytes
+// of control blocks and tile states those clears zero (batch_fills).
+static size_t layout_batch(Ctx& c, std::vector<Job>& jobs, bool fills = true);
+static void batch_fills(Ctx& c, size_t zero_bytes) {
+  // zero the control blocks and tile states; the CPI arena and the frontier
+  // pool start empty
+  fill_u64(c.st, (uint64_t*)c.ws->arena, 0, zero_bytes / 8);
+  fill_u64(c.st, (uint64_t*)c.ws->misc, 0, 2);
+}
+static size_t layout_batch(Ctx& c, std::vector<Job>& jobs, bool fills) {
   Workspace* ws = c.ws;
   const size_t nj = jobs.size();
   uint64_t tiles = 0;
@@ -1999,6 +2027,7 @@ static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
     ws->hitpool_words = 0;
     ws->hitpool = dalloc<uint32_t>(ws->al, hw);
     ws->hitpool_words = hw;
+    ws->gen++;
     fill_u32(c.st, ws->hitpool, 0u, hw);
   }
   size_t hoff = 0;
@@ -2018,14 +2047,128 @@ static void layout_batch(Ctx& c, std::vector<Job>& jobs) {
     ws->hctl_words = 0;
     ws->hctl = (uint64_t*)ws->host_get(sizeof(uint64_t) * CTL_WORDS * nj, false);
     ws->hctl_words = CTL_WORDS * nj;
+    ws->gen++;
   }
   ensure_front(ws);
   ensure_cpi(ws);
-  // zero the control blocks and tile states; the CPI arena and the frontier
-  // pool start empty
-  fill_u64(c.st, (uint64_t*)ws->arena, 0, (ctl_b + ts_b) / 8);
-  fill_u64(c.st, (uint64_t*)ws->misc, 0, 2);
+  if (fills) batch_fills(c, ctl_b + ts_b);
+  return ctl_b + ts_b;
 }
+
+// ---------------------------------------------------------------------------
+// captured main passes (HIP graphs): a batch's clears, every launch of its
+// CPI construction and enumeration, the first K and the read-back of its
+// control words, replayed as one graph launch when a batch of the same shape
+// comes again on the same workspace
+// ---------------------------------------------------------------------------
+
+struct GraphEntry {
+  std::string key;
+  uint64_t gen = 0;
+  hipGraphExec_t exec = nullptr;
+  uint8_t* recs = nullptr;  // the batch's records, uploaded once at capture
+  size_t recs_bytes = 0;
+  std::vector<Job> jobs;    // the jobs as planned (record offsets, candidate buffers)
+  int launches[8] = {};
+};
+constexpr size_t GRAPHS_MAX = 512;  // captured shapes kept per workspace
+
+static void drop_entry(Workspace* ws, GraphEntry* e) {
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  dfree(ws->al, e->recs, e->recs_bytes);
+  delete e;
+}
+static void drop_graphs(Workspace* ws) {
+  for (GraphEntry* e : ws->graphs) drop_entry(ws, e);
+  ws->graphs.clear();
+}
+
+// What the main pass of a batch depends on besides the buffers' generation:
+// the GFDs, the reading, K, the staging and frontier limits, the pool and
+// arena shares and whether class bytes are counted.
+static std::string graph_key(const Ctx& c, const std::vector<Job>& jobs, const gfd_spec* specs,
+                             bool count_only, uint64_t vsmall) {
+  std::string k;
+  auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+  const uint64_t w[] = {(uint64_t)c.K, (uint64_t)c.induced, (uint64_t)count_only, c.front_limit, vsmall,
+                        front_usable(c.ws), cpi_usable(c.ws), (uint64_t)(c.stat_bytes != nullptr),
+                        (uint64_t)jobs.size()};
+  put(w, sizeof w);
+  for (const Job& J : jobs) put(&specs[J.spec], sizeof(gfd_spec));
+  return k;
+}
+
+static GraphEntry* find_graph(Workspace* ws, const std::string& key) {
+  for (size_t i = 0; i < ws->graphs.size(); i++) {
+    GraphEntry* e = ws->graphs[i];
+    if (e->key != key) continue;
+    if (e->gen == ws->gen) return e;
+    drop_entry(ws, e);  // captured on buffers that have moved since
+    ws->graphs.erase(ws->graphs.begin() + (ptrdiff_t)i);
+    return nullptr;
+  }
+  return nullptr;
+}
+
+// Reads the batch's control words and the CPI and frontier cursors back.
+static void read_back(Ctx& c, const std::vector<Job>& jobs) {
+  Workspace* ws = c.ws;
+  HIPCHK(hipMemcpyAsync(ws->hctl, jobs[0].mem.ctl, sizeof(uint64_t) * CTL_WORDS * jobs.size(),
+                        hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipMemcpyAsync(ws->hmisc, ws->misc, 8, hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipMemcpyAsync(ws->hmisc + 10, ws->misc + 1, 8, hipMemcpyDeviceToHost, c.st));
+}
+
+// Plans the batch, uploads its records to a buffer of their own and captures
+// the main pass on the workspace's capture stream.
+static GraphEntry* capture_batch(Ctx& c, std::vector<Job>& jobs, size_t zero_bytes, std::string key) {
+  Workspace* ws = c.ws;
+  Recs R;
+  LaunchList L;
+  plan_batch(c, jobs, R, L, true);
+  std::unique_ptr<GraphEntry> e(new GraphEntry());
+  e->key = std::move(key);
+  e->gen = ws->gen;
+  e->recs_bytes = std::max<size_t>(R.blob.size(), 256);
+  e->recs = dalloc<uint8_t>(ws->al, e->recs_bytes);
+  HIPCHK(hipMemcpyAsync(e->recs, R.blob.data(), R.blob.size(), hipMemcpyHostToDevice, c.st));
+  if (!ws->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ws->cap_stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamSynchronize(c.st));  // the capture stream does not order after the call's
+  // one capture at a time in the process
+  static std::mutex capture_mu;
+  std::lock_guard<std::mutex> cap_lock(capture_mu);
+  const hipStream_t st0 = c.st;
+  int before[8];
+  std::memcpy(before, c.tm.launches, sizeof before);
+  c.st = ws->cap_stream;
+  c.recbase = e->recs;
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(c.st, hipStreamCaptureModeRelaxed));
+  try {
+    batch_fills(c, zero_bytes);
+    run_launches(c, L.v);
+    read_back(c, jobs);
+  } catch (...) {
+    (void)hipStreamEndCapture(c.st, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    c.st = st0;
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(c.st, &graph));
+  c.st = st0;
+  const hipError_t ie = hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(ie);
+  for (int j = 0; j < 8; j++) e->launches[j] = c.tm.launches[j] - before[j];
+  e->jobs = jobs;
+  if (ws->graphs.size() >= GRAPHS_MAX) {  // the oldest shape goes
+    drop_entry(ws, ws->graphs.front());
+    ws->graphs.erase(ws->graphs.begin());
+  }
+  ws->graphs.push_back(e.get());
+  return e.release();
+}
+
 
 static void ensure_chunk(Workspace* ws, size_t bytes) {
   if (ws->chunk_bytes >= bytes) return;
@@ -2632,21 +2775,53 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     std::vector<char> retried(num_specs, 0);
     // redo[x]: 1 the job runs again on the bounded path; 2 it runs again in a
     // later fast batch (the frontier pool or CPI arena it overflowed has grown)
+    // the batches formed here run their main pass from captured graphs (not
+    // the retries appended below, which follow a growth of the buffers)
+    const bool use_graphs = !(o.flags & GFD_FLAG_NO_GRAPH) && !c.tm.on && !ws->al.area && !force_bounded;
+    const size_t n_planned = batches.size();
     for (size_t bi = 0; bi < batches.size(); bi++) {
       std::vector<Job> jobs;
       for (int i : batches[bi]) jobs.push_back(all[i]);
       rewind_area(ws);
-      layout_batch(c, jobs);
+      const bool graph = use_graphs && bi < n_planned;
+      const size_t zero_bytes = layout_batch(c, jobs, !graph);
       std::vector<char> redo(jobs.size(), force_bounded ? 1 : 0);
       if (!force_bounded) {
-        Recs R;
-        LaunchList L;
-        plan_and_run_batch(c, jobs, R, L);
-        HIPCHK(hipMemcpyAsync(ws->hctl, jobs[0].mem.ctl, sizeof(uint64_t) * CTL_WORDS * jobs.size(),
-                              hipMemcpyDeviceToHost, c.st));
-        HIPCHK(hipMemcpyAsync(ws->hmisc, ws->misc, 8, hipMemcpyDeviceToHost, c.st));
-        HIPCHK(hipMemcpyAsync(ws->hmisc + 10, ws->misc + 1, 8, hipMemcpyDeviceToHost, c.st));
+        GraphEntry* e = nullptr;
+        if (graph) {
+          // a shape seen once before is captured now; one seen for the first
+          // time runs eagerly (most shapes of a serving mix never repeat)
+          std::string key = graph_key(c, jobs, specs, count_only, vsmall);
+          e = find_graph(ws, key);
+          if (e) {  // the same plans, records and buffers as when it was captured
+            jobs = e->jobs;
+            for (size_t x = 0; x < jobs.size(); x++) jobs[x].spec = batches[bi][x];
+            for (int j = 0; j < 8; j++) c.tm.launches[j] += e->launches[j];
+            if (stats) stats->graph_replays++;
+          } else {
+            const size_t h = std::hash<std::string>()(key);
+            if (std::find(ws->seen.begin(), ws->seen.end(), h) != ws->seen.end()) {
+              e = capture_batch(c, jobs, zero_bytes, std::move(key));
+              if (stats) stats->graph_captures++;
+            } else {
+              ws->seen.push_back(h);
+              if (ws->seen.size() > 4 * GRAPHS_MAX) ws->seen.pop_front();
+              batch_fills(c, zero_bytes);  // the eager pass below starts from them
+            }
+          }
+        }
+        if (e) {
+          c.recbase = e->recs;
+          HIPCHK(hipGraphLaunch(e->exec, c.st));
+        } else {
+          Recs R;
+          LaunchList L;
+          plan_and_run_batch(c, jobs, R, L);
+          read_back(c, jobs);
+        }
         HIPCHK(hipStreamSynchronize(c.st));
+        uint8_t* const recbase = c.recbase ? c.recbase : ws->jobrec;  // where the main pass's records are
+        c.recbase = nullptr;
         cpi_entries += std::min<uint64_t>(ws->hmisc[0], ws->cpi_cap);
         // what the batch asked of the frontier pool and the CPI arena (failed
         // reservations included): they grow to it for the next batch
@@ -2681,7 +2856,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         std::vector<ExtJob> lastrec(jobs.size());
         if (!over.empty()) {
           for (int x : over)
-            HIPCHK(hipMemcpyAsync(&lastrec[x], ws->jobrec + jobs[x].last_rec, sizeof(ExtJob),
+            HIPCHK(hipMemcpyAsync(&lastrec[x], recbase + jobs[x].last_rec, sizeof(ExtJob),
                                   hipMemcpyDeviceToHost, c.st));
           HIPCHK(hipStreamSynchronize(c.st));
         }
@@ -2963,6 +3138,7 @@ struct gfd_server {
       vo.hip_stream = streams[w];
       vo.batched = 1;
       vo.allocator = o.allocator;
+      vo.flags = GFD_FLAG_NO_GRAPH;  // a serving mix rarely repeats a batch's shape
       const int32_t rc = gfd_validate(g, specs.data(), (int32_t)specs.size(), &vo, res.data());
       std::vector<int32_t> st(batch.size(), rc);
       std::vector<std::string> msg(batch.size(), rc ? gfd_last_error() : "");

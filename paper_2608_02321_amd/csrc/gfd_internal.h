@@ -237,6 +237,8 @@ struct ExtJob {
   int32_t chk_fwd[MAXK];    // constraint on data edge h(x_pos) -> v
   int32_t chk_bwd[MAXK];    // constraint on data edge v -> h(x_pos)
   uint64_t front_limit;
+  uint64_t* home_P;         // the job's own prefix array: a level whose frontier
+                            // could not be reserved scans no sources into it
   int32_t* dst_cols;
   uint64_t dst_cap;
   uint64_t* d_ndst;

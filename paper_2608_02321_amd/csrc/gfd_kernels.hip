@@ -1659,8 +1659,16 @@ __global__ __launch_bounds__(BS) void k_front_reserve(ExtJob* __restrict__ cur, 
         F.src_cap = T;
       }
     } else {
+      // no slots: this level's kept matches flag an overflow and the next
+      // level (or leaf count) has no sources -- also when a replayed graph
+      // finds the records as an earlier replay left them
       E.dst_cols = nullptr;
       E.dst_cap = 0;
+      if (next && next[x].active && next[x].i == w) {
+        next[x].src_cap = 0;
+        next[x].sc.P = next[x].home_P;
+      }
+      if (leaf && leaf[x].active && leaf[x].i == w) leaf[x].src_cap = 0;
     }
   }
   if (x < MAX_JOBS) {
