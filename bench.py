@@ -39,13 +39,32 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "a50065b81a11e9a2acebcf1535036aacbcd7c4b1fcaa7cfe0054a883bf8ba21d",
+    "sources_sha256": "f088ff7e6901831260960c43bbc98f005bdb8cb34a91966300296c4074479b1e",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true, false>
     "semantics": "induced",
     "count_only": False,
-    # (669.12 MB read + 11.98 MB written) per dispatch, calibrated
-    "bytes_per_launch": 6.8110e8,
+    # (510.69 MB read + 10.18 MB written) per dispatch, calibrated (x1.9999, x1.0)
+    "bytes_per_launch": 5.2087e8,
+}
+# Units of work of the dominant kernel per launch, from the counting build
+# (bench.py --units; see profiles/), and the algorithmic bytes the per-unit
+# model gives them: 4 B per attempt, 8 B per source, 4 B per search step of
+# ceil(log2 d) over a row of d entries for a one-direction probe and twice
+# that for a check of both directions, 4 B per attribute value a literal
+# reads.  Valid only for the kernel sources it was counted on.
+UNITS = {
+    "sources_sha256": "f088ff7e6901831260960c43bbc98f005bdb8cb34a91966300296c4074479b1e",
+    "workload": "kg_4m_batch256",
+    "kernel_class": "extend_last",
+    "semantics": "induced",
+    "count_only": False,
+    "per_launch": {"attempts": 19786060.4, "sources": 1575688.4, "injective": 19784612.0,
+                   "checks_both": 52013171.1, "table_free": 45152484.6, "table_hit": 1033808.9,
+                   "short_row": 5826877.6, "both_steps": 25710580.0, "both_log2d": 481591478.9,
+                   "checks_one": 0.0, "one_steps": 0.0, "one_log2d": 0.0, "matches": 18486402.8,
+                   "literal_reads": 20324108.8, "violations": 8510302.8, "inner_attempts": 2435247.3},
+    "model_bytes_per_launch": 4.02578e9,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
@@ -108,6 +127,40 @@ def cpu_baseline(g, gfds, semantics, frac, threads):
     out = run(frac, threads)
     out["single_thread"] = run(frac / 16, 1)
     return out
+
+
+def unit_report(args, P, gh, gfds, stream, batched):
+    """Unit counts of the last enumeration level (the dominant kernel class)
+    from the counting build, per launch, and the algorithmic bytes they imply
+    under the per-unit model: 4 B per attempt (its CPI entry), 8 B per source
+    (its list's offsets), 4 B per search step of ceil(log2 d) over a row of d
+    entries for a one-direction probe and twice that for a check of both
+    directions, 4 B per attribute value a literal reads.  Printed beside the
+    bytes the kernels count on the device, which price what they touch: table
+    bounds and one byte per fingerprint slot instead of a row search."""
+    K = 0 if args.count_only else K_REPORT
+    flags = (P.GFD_FLAG_COUNT_ONLY if args.count_only else 0) | P.GFD_FLAG_NO_GRAPH
+    pc = P.PreparedCall(gh, gfds, K=K, semantics=args.semantics, stream=stream, batched=batched)
+    pc.run(flags=flags)
+    st = pc.run(flags=flags | P.GFD_FLAG_TIMING)
+    assert st["units_counted"], "GFD_LIBRARY did not load the counting build"
+    u = st["units"]
+    n = max(1, st["class_launches"]["extend_last"])
+    model = (4 * u["attempts"] + 8 * u["sources"] + 8 * u["both_log2d"] + 4 * u["one_log2d"]
+             + 4 * u["literal_reads"])
+    dev = st["class_bytes"]["extend_last"]
+    ms = st["class_ms"]["extend_last"]
+    out = {"units_per_step": u, "extend_last_launches": n,
+           "units_per_launch": {k: v / n for k, v in u.items()},
+           "model_bytes_per_launch": model / n, "device_bytes_per_launch": dev / n,
+           "extend_last_ms_per_step": ms, "matches_per_step": pc.match_count(),
+           "config": {"workload": args.workload, "semantics": args.semantics,
+                      "count_only": bool(args.count_only), "library": "libgfd_count.so"}}
+    if ms > 0:
+        out["model_gbs"] = model / (ms * 1e-3) / 1e9
+        out["device_gbs"] = dev / (ms * 1e-3) / 1e9
+    log(json.dumps(out, indent=1))
+    print(json.dumps(out), flush=True)
 
 
 def serve(args, torch, P, g, gh):
@@ -210,6 +263,10 @@ def main():
                          "(int32 negation) three times: the calibration run for HBM counters")
     ap.add_argument("--sources-sha256", action="store_true",
                     help="print the hash of the kernel sources that counter figures are keyed on")
+    ap.add_argument("--units", action="store_true",
+                    help="measurement run on the unit-counting build (libgfd_count.so): the "
+                         "dominant class's unit counts per launch and the byte model priced "
+                         "from them, beside the device-counted algorithmic bytes")
     ap.add_argument("--per-gfd", type=int, default=0, metavar="N",
                     help="diagnostic: validate each GFD alone with statistics and print the "
                          "N slowest to stderr")
@@ -237,6 +294,8 @@ def main():
         print(json.dumps({"copy_probe": {"launches": 3, "read_bytes_per_launch": 4 * n,
                                          "write_bytes_per_launch": 4 * n}}), flush=True)
         return
+    if args.units:  # before the package loads its library
+        os.environ["GFD_LIBRARY"] = os.path.join(ROOT, "paper_2608_02321_amd", "libgfd_count.so")
     import paper_2608_02321_amd as P
     from paper_2608_02321_amd._binding import KERNEL_CLASSES
     from synth import configs
@@ -257,6 +316,11 @@ def main():
         gh.free()
         return
     batched = mode == "batched"
+
+    if args.units:
+        unit_report(args, P, gh, gfds, stream, batched)
+        gh.free()
+        return
 
     # specs, options and result buffers are marshalled once; a step is one
     # gfd_validate_ex call through the C ABI
@@ -329,18 +393,32 @@ def main():
     if dom is not None and agg_launch:
         name = KERNEL_CLASSES[dom]
         avg_ms = agg_ms / agg_launch
-        per_launch = agg_bytes / agg_launch
-        ach = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-        traffic = None
-        if (TRAFFIC["bytes_per_launch"] and TRAFFIC["kernel_class"] == name
-                and TRAFFIC["workload"] == args.workload
-                and TRAFFIC["semantics"] == args.semantics
-                and TRAFFIC["count_only"] == bool(args.count_only)
-                and TRAFFIC["sources_sha256"] == sources_sha256()):
-            traffic = TRAFFIC["bytes_per_launch"]
+        dev_per_launch = agg_bytes / agg_launch  # counted on the device
+        gbs = lambda b: b / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0  # noqa: E731
+
+        def valid(tab):
+            return (tab["kernel_class"] == name and tab["workload"] == args.workload
+                    and tab["semantics"] == args.semantics
+                    and tab["count_only"] == bool(args.count_only)
+                    and tab["sources_sha256"] == sources_sha256())
+        traffic = TRAFFIC["bytes_per_launch"] if valid(TRAFFIC) else None
+        # algorithmic bytes: the per-unit model over the units one launch
+        # processes (counting build), else the bytes counted on the device
+        if valid(UNITS):
+            per_launch, basis = UNITS["model_bytes_per_launch"], "per-unit model x counted units"
+        else:
+            per_launch, basis = dev_per_launch, "device-counted bytes (unit counts stale)"
+        ach = gbs(per_launch)
         copy = copy_gbs(torch)
         roofline = {"bound": "hbm", "kernel_class": name, "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                    "basis": basis,
+                    # the bytes the kernel as built touches (tables instead of
+                    # row searches), counted on the device over the same launches
+                    "device_bytes_per_launch": dev_per_launch,
+                    "device_frac": gbs(dev_per_launch) / HBM_PEAK_GBS,
+                    # measured HBM bytes (rocprofv3 counters, calibrated) over the same time
+                    "measured_frac": (gbs(traffic) / HBM_PEAK_GBS if traffic else None),
                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": per_launch,
                     "launches_per_step": agg_launch / roof_steps,
                     "timed_over": f"{roof_steps} eager steps after the timed ones, HIP events "

@@ -193,6 +193,16 @@ typedef struct {
   int64_t cpi_arena_bytes;
   int32_t graph_captures;     /* batches whose main pass was captured as a graph */
   int32_t graph_replays;      /* batches whose main pass replayed a captured graph */
+  int32_t units_counted;      /* 1 in a counting build of the library (units filled) */
+  /* enumeration units of a counting build: [0] last-level attempts, [1] their
+   * sources, [2] attempts past injectivity, [3] checks of both directions,
+   * [4] of them settled by a free table slot, [5] by a fingerprint match and
+   * a row search, [6] by a search of a short row, [7] combined-row search
+   * steps, [8] sum of ceil(log2 d) over the anchors' combined rows, [9]
+   * one-direction probes, [10] their search steps, [11] sum of ceil(log2 d)
+   * over their rows, [12] matches, [13] attribute values read by literals,
+   * [14] violations, [15] inner-level attempts */
+  uint64_t units[16];
 } gfd_stats;
 
 /* Load a graph given as out-CSR, in host memory or (opts->mem_kind ==

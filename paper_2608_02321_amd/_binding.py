@@ -12,7 +12,12 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libgfd.so")
+# GFD_LIBRARY names another build of the same library (the unit-counting one,
+# libgfd_count.so, for measurement runs)
+LIB_PATH = os.environ.get("GFD_LIBRARY") or os.path.join(PKG, "libgfd.so")
+UNIT_NAMES = ("attempts", "sources", "injective", "checks_both", "table_free", "table_hit",
+              "short_row", "both_steps", "both_log2d", "checks_one", "one_steps", "one_log2d",
+              "matches", "literal_reads", "violations", "inner_attempts")
 
 GFD_OK, GFD_EINVAL, GFD_ENOMEM, GFD_EDEVICE, GFD_EUNSUPPORTED, GFD_EOVERFLOW = 0, -1, -2, -3, -4, -5
 GFD_EAGAIN = -6
@@ -88,7 +93,8 @@ class gfd_stats(C.Structure):
                 ("threshold_passes", C.c_int32), ("leaf_gfds", C.c_int32),
                 ("regrown_gfds", C.c_int32), ("front_pool_bytes", C.c_int64),
                 ("cpi_arena_bytes", C.c_int64), ("graph_captures", C.c_int32),
-                ("graph_replays", C.c_int32)]
+                ("graph_replays", C.c_int32), ("units_counted", C.c_int32),
+                ("units", C.c_uint64 * 16)]
 
 
 class gfd_graph_info(C.Structure):
@@ -413,10 +419,7 @@ class PreparedCall:
         _check(rc)
         if not stats:
             return None
-        sd = {f: getattr(self.st, f) for f, _ in gfd_stats._fields_}
-        for f in ("class_launches", "class_ms", "class_bytes"):
-            sd[f] = dict(zip(KERNEL_CLASSES, list(sd[f])))
-        return sd
+        return _stats_dict(self.st)
 
     def match_count(self):
         return sum(int(self.res[i].match_count) for i in range(self.n))
@@ -473,11 +476,16 @@ def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced"
                     "satisfied": bool(r.satisfied),
                     "violations": bufs[i][:r.num_reported * k].reshape(-1, k).tolist()})
     if stats:
-        sd = {f: getattr(st, f) for f, _ in gfd_stats._fields_}
-        for f in ("class_launches", "class_ms", "class_bytes"):
-            sd[f] = dict(zip(KERNEL_CLASSES, list(sd[f])))
-        return out, sd
+        return out, _stats_dict(st)
     return out
+
+
+def _stats_dict(st):
+    sd = {f: getattr(st, f) for f, _ in gfd_stats._fields_}
+    for f in ("class_launches", "class_ms", "class_bytes"):
+        sd[f] = dict(zip(KERNEL_CLASSES, list(sd[f])))
+    sd["units"] = dict(zip(UNIT_NAMES, list(sd["units"])))
+    return sd
 
 
 class Server:

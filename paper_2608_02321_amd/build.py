@@ -17,21 +17,42 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link the shared library (always rebuilds)."""
-    objs = []
-    os.makedirs(os.path.join(PKG, "_build"), exist_ok=True)
+# the unit-counting build (measurement only): the same sources with the
+# enumeration's unit counters compiled in
+LIB_COUNT = os.path.join(PKG, "libgfd_count.so")
+
+
+def _compile_jobs(out: str, extra, sub: str):
+    bdir = os.path.join(PKG, "_build", sub)
+    os.makedirs(bdir, exist_ok=True)
+    jobs = []
     for src in SOURCES:
-        obj = os.path.join(PKG, "_build", src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
+        obj = os.path.join(bdir, src.replace(".hip", ".o"))
+        jobs.append((obj, [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]))
+    return out, jobs
+
+
+def build(verbose: bool = False, counting: bool = True) -> str:
+    """Compile every HIP source and link the shared library, and the
+    unit-counting build beside it (always rebuilds; the compiles run in
+    parallel)."""
+    variants = [_compile_jobs(LIB, [], "main")]
+    if counting:
+        variants.append(_compile_jobs(LIB_COUNT, ["-DGFD_COUNT_UNITS"], "count"))
+    procs = []
+    for _, jobs in variants:
+        for obj, cmd in jobs:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((cmd, subprocess.Popen(cmd)))
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    for out, jobs in variants:
+        tmp = out + ".tmp"
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in jobs], "-o", tmp]
         subprocess.run(cmd, check=True)
-        objs.append(obj)
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+        os.replace(tmp, out)
     return LIB
 
 

@@ -2730,7 +2730,10 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     c.tm.on = stats && ((o.flags & GFD_FLAG_TIMING) || cls_mask);
     c.tm.mask = cls_mask ? cls_mask : 0xFFu;
     c.tm.st = c.st;
-    if (stats) fill_u64(c.st, (uint64_t*)(ws->misc + 8), 0, 8);
+    if (stats) {
+      fill_u64(c.st, (uint64_t*)(ws->misc + 8), 0, 8);
+      units_clear(c.st);
+    }
     fill_u32(c.st, ws->err, 0u, 1);
     // plans, capacities and batches
     std::vector<Job> all(num_specs);
@@ -2953,6 +2956,8 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     if (stats) {
       for (int j = 0; j < 8; j++) stats->class_bytes[j] = ws->hmisc[2 + j];
       stats->cpi_entries = cpi_entries;
+      stats->units_counted = units_counted() ? 1 : 0;
+      units_read(c.st, stats->units);
       stats->front_pool_bytes = (int64_t)ws->front_bytes;
       stats->cpi_arena_bytes = (int64_t)ws->cpi_cap * 4;
       if (c.tm.on) c.tm.collect(stats->class_ms);

@@ -334,6 +334,24 @@ struct SelJob {
   uint32_t* d_thr_valid;
 };
 
+// Unit counts of the enumeration, kept by a counting build (compiled with
+// -DGFD_COUNT_UNITS) beside the algorithmic bytes: what the last level does
+// -- attempts, sources, attempts past injectivity, checks by kind and how
+// they were settled, search steps, the sum of ceil(log2 d) over the searched
+// rows, matches, literal values read, violations -- and the inner levels'
+// attempts.  A normal build keeps none (units_counted() is false).
+enum {
+  U_ATTEMPTS, U_SOURCES, U_INJECTIVE, U_CHK_BOTH, U_TABLE_FREE, U_TABLE_HIT, U_SHORT_ROW,
+  U_BOTH_STEPS, U_BOTH_LOG2D, U_CHK_ONE, U_ONE_STEPS, U_ONE_LOG2D, U_MATCHES, U_LIT_READS,
+  U_VIOLATIONS, U_INNER_ATTEMPTS, UNIT_KINDS
+};
+struct Units {
+  unsigned long long c[UNIT_KINDS];
+};
+bool units_counted();
+void units_clear(hipStream_t st);
+void units_read(hipStream_t st, uint64_t* host);  // [UNIT_KINDS], synchronous
+
 // Launch wrappers (gfd_kernels.hip).  All asynchronous on `st`; `jobs` points
 // to `njobs` (<= MAX_JOBS) device-resident job records.  Per-job kernels run
 // on a (gx, njobs) grid; the flat (load-balanced) ones and the scans on a 1-D

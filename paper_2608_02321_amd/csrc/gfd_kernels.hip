@@ -21,6 +21,10 @@ namespace gfd {
 
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 
+#ifdef GFD_COUNT_UNITS
+extern __device__ unsigned long long unit_counts[UNIT_KINDS];
+#endif
+
 // number of set bits of `mask` below this lane
 __device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -91,8 +95,14 @@ __device__ __forceinline__ bool constraint_ok(int32_t found, int32_t code) {
 // anchor on the vertex that neighbouring threads share (the earlier matched
 // vertex, the CPI source), so the searched row stays in cache across the
 // wave instead of each thread fetching its own candidate's row.
+// ceil(log2 d) for d >= 1 (0 for d <= 1)
+__device__ __forceinline__ uint32_t clog2(uint64_t d) {
+  return d <= 1 ? 0u : 64u - (uint32_t)__clzll((long long)(d - 1));
+}
+
 __device__ __forceinline__ int32_t edge_label_at(const DevGraph& g, int32_t a, int32_t b,
-                                                 bool anchor_a, unsigned long long& by) {
+                                                 bool anchor_a, unsigned long long& by,
+                                                 Units* U = nullptr) {
   const uint32_t* off = anchor_a ? g.out_off : g.in_off;
   const int32_t* nbr = anchor_a ? g.out_nbr : g.in_nbr;
   const int32_t* lab = anchor_a ? g.out_lab : g.in_lab;
@@ -100,9 +110,14 @@ __device__ __forceinline__ int32_t edge_label_at(const DevGraph& g, int32_t a, i
   uint32_t lo = off[row], hi = off[row + 1];
   const uint32_t end = hi;
   by += 8;
+  if (U) {
+    U->c[U_CHK_ONE]++;
+    U->c[U_ONE_LOG2D] += clog2(hi - lo);
+  }
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
     by += 4;
+    if (U) U->c[U_ONE_STEPS]++;
     if (nbr[mid] < key) lo = mid + 1; else hi = mid;
   }
   if (lo < end && nbr[lo] == key) {
@@ -119,9 +134,10 @@ __device__ __forceinline__ int32_t edge_label_at(const DevGraph& g, int32_t a, i
 // only for neighbours (to read their labels) and for the rare fingerprint
 // that matches by chance.
 __device__ __forceinline__ int2 edge_labels_both(const DevGraph& g, int32_t a, int32_t b,
-                                                 unsigned long long& by) {
+                                                 unsigned long long& by, Units* U = nullptr) {
   const uint64_t t0 = g.hub_off[a], t1 = g.hub_off[a + 1];
   by += 16;
+  if (U) U->c[U_BOTH_LOG2D] += clog2(g.sym_off[a + 1] - g.sym_off[a]);
   if (t1 > t0) {
     const uint64_t mask = t1 - t0 - 1;
     const uint8_t f = hub_fp(b);
@@ -130,8 +146,14 @@ __device__ __forceinline__ int2 edge_labels_both(const DevGraph& g, int32_t a, i
       const uint8_t e = g.hub_tab[t0 + i];
       by += 1;
       if (e == f) break;
-      if (e == 0) return make_int2(NOEDGE, NOEDGE);
+      if (e == 0) {
+        if (U) U->c[U_TABLE_FREE]++;
+        return make_int2(NOEDGE, NOEDGE);
+      }
     }
+    if (U) U->c[U_TABLE_HIT]++;
+  } else if (U) {
+    U->c[U_SHORT_ROW]++;
   }
   uint64_t lo = g.sym_off[a], hi = g.sym_off[a + 1];
   const uint64_t end = hi;
@@ -139,6 +161,7 @@ __device__ __forceinline__ int2 edge_labels_both(const DevGraph& g, int32_t a, i
   while (lo < hi) {
     const uint64_t mid = (lo + hi) >> 1;
     by += 4;
+    if (U) U->c[U_BOTH_STEPS]++;
     if (g.sym_nbr[mid] < b) lo = mid + 1; else hi = mid;
   }
   if (lo < end && g.sym_nbr[lo] == b) {
@@ -150,9 +173,9 @@ __device__ __forceinline__ int2 edge_labels_both(const DevGraph& g, int32_t a, i
 
 // Constraint `code` on data edge a -> b, probed in the anchor's row.
 __device__ __forceinline__ bool pair_ok(const DevGraph& g, int32_t a, int32_t b, bool anchor_a,
-                                        int32_t code, unsigned long long& by) {
+                                        int32_t code, unsigned long long& by, Units* U = nullptr) {
   if (code == PC_FREE) return true;
-  return constraint_ok(edge_label_at(g, a, b, anchor_a, by), code);
+  return constraint_ok(edge_label_at(g, a, b, anchor_a, by, U), code);
 }
 
 // Membership bitmaps (n bits, 512 KB at 4M vertices) stay in L2: their probes
@@ -1287,7 +1310,8 @@ template <class Col>
 __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
                                          const int32_t (&h)[MAXK], int32_t (&t)[MAXK],
                                          FinalAcc& acc, bool count, bool thr_on,
-                                         const int32_t* thr, unsigned long long& by, Col col) {
+                                         const int32_t* thr, unsigned long long& by, Col col,
+                                         Units* U = nullptr) {
   uint64_t hs = 0x9E3779B97F4A7C15ull * (uint64_t)J.k;
 #pragma unroll
   for (int v = 0; v < MAXK; v++) {
@@ -1298,20 +1322,24 @@ __device__ __forceinline__ bool finalize(const DevGraph& g, const ExtJob& J,
   for (int j = 0; j < J.nx && X; j++) {
     X = literal_holds(g, J.lit[j], col);
     by += J.lit[j].kind == 0 ? 4 : 8;  // the attribute values read
+    if (U) U->c[U_LIT_READS] += J.lit[j].kind == 0 ? 1 : 2;
   }
   if (X && Y)
     for (int j = 0; j < J.ny && Y; j++) {
       Y = literal_holds(g, J.lit[J.nx + j], col);
       by += J.lit[J.nx + j].kind == 0 ? 4 : 8;
+      if (U) U->c[U_LIT_READS] += J.lit[J.nx + j].kind == 0 ? 1 : 2;
     }
   if (count) {
     acc.match += 1;
     acc.mfp += hs;
+    if (U) U->c[U_MATCHES]++;
   }
   if (!(X && !Y)) return false;
   if (count) {
     acc.viol += 1;
     acc.vfp += hs;
+    if (U) U->c[U_VIOLATIONS]++;
   }
   if (J.vcap == 0) return false;
   // stage only if t < thr (t <= thr when thr_incl), lexicographically on unsigned ids
@@ -1440,6 +1468,12 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
   chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(ext_width<LAST>(jobs[j])); });
   const uint32_t wv = threadIdx.x / WAVE;
   unsigned long long by = 0;
+#ifdef GFD_COUNT_UNITS
+  Units units{};
+  Units* U = &units;
+#else
+  Units* U = nullptr;
+#endif
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
     const int jb = chunk_job(cm, njobs, ch);
     const ExtJob& J = jobs[jb];
@@ -1481,12 +1515,17 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
       if (valid) {
         // the CPI entry; the source's list start, prefix and partial once per source
         by += 4 + (first ? 12ull + 4ull * (uint64_t)i : 0ull);
+        if (U) {
+          U->c[LAST ? U_ATTEMPTS : U_INNER_ATTEMPTS]++;
+          if (LAST && first) U->c[U_SOURCES]++;
+        }
         ok = true;
 #pragma unroll
         for (int j = 0; j < MAXK; j++) {
           h[j] = (j < i) ? J.src_cols[(uint64_t)j * J.src_stride + s] : v;
           if (j < i && h[j] == v) ok = false;
         }
+        if (U && LAST && ok) U->c[U_INJECTIVE]++;
         // a collect-only pass keeps nothing past its threshold: such tuples
         // skip the edge probes and the literal check
         if (LAST && ok && thr_on && J.collect_only) ok = !past_threshold(J, h, thr);
@@ -1495,17 +1534,23 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
           const int32_t cf = J.chk_fwd[c], cb = J.chk_bwd[c];
           // rows of hw, which the wave's threads share: the combined row when
           // both directions are constrained, else the one direction's row
+          Units* UL = LAST ? U : nullptr;  // units of the last level only
           if (cf != PC_FREE && cb != PC_FREE) {
             int2 l;
+            if (UL) UL->c[U_CHK_BOTH]++;
             if (c == 0 && free0) {
               l = make_int2(NOEDGE, NOEDGE);
               by += 17;  // what the probe reads: the table bounds and one slot
+              if (UL) {
+                UL->c[U_TABLE_FREE]++;
+                UL->c[U_BOTH_LOG2D] += clog2(g.sym_off[hw + 1] - g.sym_off[hw]);
+              }
             } else {
-              l = edge_labels_both(g, hw, v, by);
+              l = edge_labels_both(g, hw, v, by, UL);
             }
             ok = constraint_ok(l.x, cf) && constraint_ok(l.y, cb);
           } else {
-            ok = pair_ok(g, hw, v, true, cf, by) && pair_ok(g, v, hw, false, cb, by);
+            ok = pair_ok(g, hw, v, true, cf, by, UL) && pair_ok(g, v, hw, false, cb, by, UL);
           }
         }
       }
@@ -1542,14 +1587,46 @@ __global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __rest
         if (ok)
           want = finalize(g, J, h, t, acc, !J.collect_only, thr_on, thr, by, [&](int p) -> int32_t {
             return p < i ? J.src_cols[(uint64_t)p * J.src_stride + s] : v;
-          });
+          }, U);
         stage(J, want, t, full);
       }
     });
     if (LAST && !J.collect_only) flush_acc(J.counters, acc);
   }
   if (bytes) block_add(bytes, by);
+#ifdef GFD_COUNT_UNITS
+  for (int u = 0; u < UNIT_KINDS; u++) block_add(&unit_counts[u], units.c[u]);
+#endif
 }
+
+// Unit counts of a counting build (see Units); nothing in a normal build.
+#ifdef GFD_COUNT_UNITS
+__device__ unsigned long long unit_counts[UNIT_KINDS];
+bool units_counted() { return true; }
+static unsigned long long* unit_counts_ptr() {
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(unit_counts)) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return (unsigned long long*)p;
+}
+void units_clear(hipStream_t st) {
+  if (unsigned long long* p = unit_counts_ptr()) fill_u64(st, (uint64_t*)p, 0, UNIT_KINDS);
+}
+void units_read(hipStream_t st, uint64_t* host) {
+  unsigned long long* p = unit_counts_ptr();
+  if (!p || hipMemcpyAsync(host, p, sizeof(uint64_t) * UNIT_KINDS, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    (void)hipGetLastError();
+}
+#else
+bool units_counted() { return false; }
+void units_clear(hipStream_t) {}
+void units_read(hipStream_t, uint64_t* host) {
+  for (int u = 0; u < UNIT_KINDS; u++) host[u] = 0;
+}
+#endif
 
 // Job records from the mapped pinned staging into device memory.
 __global__ __launch_bounds__(BS) void k_copy_words(const uint64_t* __restrict__ src,
