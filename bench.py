@@ -263,6 +263,8 @@ def main():
                          "(int32 negation) three times: the calibration run for HBM counters")
     ap.add_argument("--sources-sha256", action="store_true",
                     help="print the hash of the kernel sources that counter figures are keyed on")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="run with the library's default launch shapes (no autotuning)")
     ap.add_argument("--units", action="store_true",
                     help="measurement run on the unit-counting build (libgfd_count.so): the "
                          "dominant class's unit counts per launch and the byte model priced "
@@ -326,8 +328,21 @@ def main():
     # gfd_validate_ex call through the C ABI
     K = 0 if args.count_only else K_REPORT
     base_flags = P.GFD_FLAG_COUNT_ONLY if args.count_only else 0
+    # launch shapes: the autotuner's choice for this call shape (tried and
+    # checked for identical results on this graph, or read from its cache)
+    tuning, tune_info = None, None
+    if not args.no_tune:
+        from paper_2608_02321_amd import tune as T
+        t = time.perf_counter()
+        tune_info = T.tune(gh, gfds, g.sha256(), K=K, semantics=args.semantics, batched=batched,
+                           count_only=args.count_only, stream=stream, log=log)
+        tuning = tune_info["tuning"]
+        gh.trim()  # the candidates' workspaces go: what is held is what the chosen shapes need
+        log(f"tuning: {tuning} ({'cached' if tune_info['cached'] else 'tuned'} in "
+            f"{time.perf_counter() - t:.1f} s): {tune_info['tuned_ms']:.2f} ms against "
+            f"{tune_info['default_ms']:.2f} ms with the defaults")
     pc = P.PreparedCall(gh, gfds, K=K, semantics=args.semantics, stream=stream,
-                        batched=batched)
+                        batched=batched, tuning=tuning)
 
     # warm-up (the first step captures the batch's main pass as a graph, later
     # ones replay it); the last warm-up step runs eagerly with events on every
@@ -385,6 +400,19 @@ def main():
     matches = sum(r["match_count"] for r in res)
     value = matches * args.steps / elapsed
     gfds_per_s = len(gfds) * args.steps / elapsed
+    fixed_ms = None
+    if tuning and any(tuning.values()):  # the same steps with the default launch shapes
+        pf = P.PreparedCall(gh, gfds, K=K, semantics=args.semantics, stream=stream,
+                            batched=batched)
+        for _ in range(3):
+            pf.run(flags=base_flags)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            pf.run(flags=base_flags)
+        torch.cuda.synchronize()
+        fixed_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        assert pf.results() == res, "default launch shapes changed a result"
     log(f"{mode}: step {ms_per_step:.3f} ms, {matches} matches, {value:.4g} embeddings/s, "
         f"{gfds_per_s:.1f} GFDs/s, launches/step {st['launches']} (graph replays {graph_replays}), "
         f"bounded re-runs {st['chunked_gfds']}")
@@ -474,7 +502,12 @@ def main():
            "ms_per_step_median": statistics.median(step_ms), "ms_per_step_min": min(step_ms),
            "enumeration_embeddings_per_s": enum_rate,
            "device_bytes": {"graph": gh.info["device_bytes"], "held": held_bytes},
-           "load_s": load_s, "roofline": roofline, "compare": compare}
+           "load_s": load_s, "roofline": roofline, "compare": compare,
+           "tuning": None if tune_info is None else {
+               "choice": tuning, "cached": tune_info["cached"],
+               "tuned_ms_per_step": ms_per_step,
+               "fixed_ms_per_step": fixed_ms if fixed_ms is not None else ms_per_step,
+               "tuner_ms": {"tuned": tune_info["tuned_ms"], "default": tune_info["default_ms"]}}}
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
         frac = args.cpu_frac if args.cpu_frac is not None else (

@@ -130,6 +130,18 @@ typedef struct {
   gfd_allocator allocator; /* device memory of the graph; alloc == NULL: hipMalloc */
 } gfd_load_opts;
 
+/* Launch shapes of a call (an autotuner's choices; 0 keeps the library's
+ * default).  They change only how work is spread over the GPU, never a
+ * result.  Out-of-range values are GFD_EINVAL. */
+typedef struct {
+  int32_t flat_grid;     /* blocks of the enumeration launches (64..16384; 0: 2048) */
+  int32_t scan_grid;     /* blocks of the enumeration level scans (64..16384; 0: 2048) */
+  int32_t probe_ahead;   /* last level: 1 loads every round's first probe slot before
+                            any round runs, 2 does not, 0 picks by graph size */
+  int32_t staging_log2;  /* violation staging per GFD in a batch, 2^n tuples (10..24;
+                            0: from the budget, at most 2^18) */
+} gfd_tuning;
+
 typedef struct {
   int32_t k_max;            /* K: violations to report per GFD, >= 0 */
   int32_t semantics;        /* GFD_SEM_INDUCED or GFD_SEM_MONO */
@@ -143,6 +155,7 @@ typedef struct {
   gfd_allocator allocator;  /* device memory of the call's workspace; alloc == NULL:
                                hipMalloc.  The graph keeps a workspace per allocator
                                between calls (see gfd_trim) */
+  gfd_tuning tuning;        /* launch shapes; all zero = the defaults */
 } gfd_validate_opts;
 
 #define GFD_FLAG_FORCE_CHUNKED 1 /* skip the single-pass fast path */

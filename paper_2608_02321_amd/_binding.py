@@ -76,12 +76,24 @@ class gfd_load_opts(C.Structure):
     _fields_ = [("hip_stream", C.c_void_p), ("mem_kind", C.c_int32), ("allocator", gfd_allocator)]
 
 
+class gfd_tuning(C.Structure):
+    _fields_ = [("flat_grid", C.c_int32), ("scan_grid", C.c_int32), ("probe_ahead", C.c_int32),
+                ("staging_log2", C.c_int32)]
+
+
+def make_tuning(t) -> gfd_tuning:
+    """gfd_tuning from a dict (missing keys: the library's defaults)."""
+    t = t or {}
+    return gfd_tuning(int(t.get("flat_grid", 0)), int(t.get("scan_grid", 0)),
+                      int(t.get("probe_ahead", 0)), int(t.get("staging_log2", 0)))
+
+
 class gfd_validate_opts(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("semantics", C.c_int32),
                 ("mem_budget_bytes", C.c_int64), ("hip_stream", C.c_void_p),
                 ("batched", C.c_int32), ("flags", C.c_int32),
                 ("frontier_cap", C.c_int64), ("violation_cap", C.c_int64),
-                ("allocator", gfd_allocator)]
+                ("allocator", gfd_allocator), ("tuning", gfd_tuning)]
 
 
 class gfd_stats(C.Structure):
@@ -394,7 +406,7 @@ class PreparedCall:
 
     def __init__(self, graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
                  mem_budget_bytes: int = 0, stream=None, flags: int = 0, batched: bool = False,
-                 allocator="torch"):
+                 allocator="torch", tuning=None):
         self.graph, self.gfds, self.K = graph, list(gfds), int(K)
         n = len(self.gfds)
         self.n = n
@@ -408,7 +420,8 @@ class PreparedCall:
         graph.keep(alloc)
         self.opts = gfd_validate_opts(self.K, GFD_SEM_INDUCED if semantics == "induced"
                                       else GFD_SEM_MONO, int(mem_budget_bytes),
-                                      _stream_handle(stream), int(bool(batched)), int(flags), 0, 0, ca)
+                                      _stream_handle(stream), int(bool(batched)), int(flags), 0, 0, ca,
+                                      make_tuning(tuning))
         self.st = gfd_stats()
 
     def run(self, flags=None, stats=True):
@@ -439,7 +452,7 @@ class PreparedCall:
 def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced",
              mem_budget_bytes: int = 0, stream=None, flags: int = 0, frontier_cap: int = 0,
              violation_cap: int = 0, stats: bool = False, batched: bool = False,
-             allocator="torch", noalloc: bool = False):
+             allocator="torch", noalloc: bool = False, tuning=None):
     """gfd_validate(_ex): one result dict per GFD (plus a stats dict if asked).
     noalloc: gfd_validate_noalloc instead (no allocator, no statistics)."""
     if noalloc:
@@ -457,7 +470,7 @@ def validate(graph: GraphHandle, gfds, K: int = 1024, semantics: str = "induced"
     opts = gfd_validate_opts(K, GFD_SEM_INDUCED if semantics == "induced" else GFD_SEM_MONO,
                              int(mem_budget_bytes), _stream_handle(stream), int(bool(batched)),
                              int(flags),
-                             int(frontier_cap), int(violation_cap), ca)
+                             int(frontier_cap), int(violation_cap), ca, make_tuning(tuning))
     st = gfd_stats()
     if noalloc:
         if stats:

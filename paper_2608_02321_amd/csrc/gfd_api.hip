@@ -1165,7 +1165,9 @@ struct Ctx {
   gfd_stats* stats;
   unsigned long long* stat_bytes;  // device [8] per kernel class, or nullptr
   uint8_t* recbase = nullptr;  // device records the launches read (nullptr: ws->jobrec)
+  gfd_tuning tune{};           // launch shapes (0: defaults)
 };
+
 
 static unsigned long long* cls_bytes(Ctx& c, int cls) {
   return c.stat_bytes ? c.stat_bytes + cls : nullptr;
@@ -1253,9 +1255,16 @@ static uint64_t chunks_of(uint64_t positions) { return (positions + LBS_CHUNK - 
 constexpr int64_t PROBE_AHEAD_MAX_BYTES = int64_t(128) << 20;
 static bool probe_ahead(const gfd_graph* g) { return g->device_bytes <= PROBE_AHEAD_MAX_BYTES; }
 
-static int flat_grid(uint64_t chunks) {
-  uint64_t g = std::max<uint64_t>(1, std::min<uint64_t>(chunks, FLAT_GRID_MAX));
-  if (g >= (uint64_t)NXCD) g = std::min<uint64_t>((g + NXCD - 1) / NXCD * NXCD, FLAT_GRID_MAX);
+// Launch shapes of the enumeration (tuned or default).
+static uint64_t enum_grid(const Ctx& c) { return c.tune.flat_grid ? (uint64_t)c.tune.flat_grid : FLAT_GRID_MAX; }
+static int enum_scan_grid(const Ctx& c) { return c.tune.scan_grid ? c.tune.scan_grid : (int)FLAT_GRID_MAX; }
+static bool use_ahead(const Ctx& c) {
+  return c.tune.probe_ahead == 1 || (c.tune.probe_ahead == 0 && probe_ahead(c.g));
+}
+
+static int flat_grid(uint64_t chunks, uint64_t cap = FLAT_GRID_MAX) {
+  uint64_t g = std::max<uint64_t>(1, std::min<uint64_t>(chunks, cap));
+  if (g >= (uint64_t)NXCD) g = std::min<uint64_t>((g + NXCD - 1) / NXCD * NXCD, cap);
   return (int)g;
 }
 // 1-D grid of a level scan whose njobs jobs have at most max_items sources
@@ -1680,7 +1689,8 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
     if (i == 1)
       for (int x = 0; x < nj; x++)
         if (E[i][x].active) srcs = std::max(srcs, E[i][x].src_cap);
-    Launch l{2, eoff[i], nj, i == 1 ? scan_grid(nj, srcs) : (int)FLAT_GRID_MAX, flat_grid(FLAT_GRID_MAX), 0, 0,
+    Launch l{2, eoff[i], nj, i == 1 ? std::min(scan_grid(nj, srcs), enum_scan_grid(c)) : enum_scan_grid(c),
+             flat_grid(enum_grid(c), enum_grid(c)), 0, 0,
              true, any_last, any_inner};
     l.next_off = i + 1 < maxk ? eoff[i + 1] : SIZE_MAX;
     l.leaf_off = leaf_off;
@@ -1731,7 +1741,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
     }
   }
   if (any_leaf)
-    L.push_back(Launch{5, leaf_off, nj, 0, flat_grid(FLAT_GRID_MAX), (int)std::min<uint64_t>(
+    L.push_back(Launch{5, leaf_off, nj, 0, flat_grid(enum_grid(c), enum_grid(c)), (int)std::min<uint64_t>(
                            FLAT_GRID_MAX, std::max<uint64_t>(1, (leaf_np + BS - 1) / BS * (uint64_t)nj)),
                        0, false, false, false});
   if (c.K > 0) {
@@ -1791,7 +1801,7 @@ static void run_launch(Ctx& c, const Launch& l) {
           c.tm.run(K_EXT, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, false, false, cls_bytes(c, K_EXT)); });
         if (l.last_any)
           c.tm.run(K_LAST, [&] {
-            ext_run(c.st, g, r, l.njobs, l.gx_work, true, probe_ahead(c.g), cls_bytes(c, K_LAST));
+            ext_run(c.st, g, r, l.njobs, l.gx_work, true, use_ahead(c), cls_bytes(c, K_LAST));
           });
         break;
       }
@@ -2091,6 +2101,7 @@ static std::string graph_key(const Ctx& c, const std::vector<Job>& jobs, const g
   std::string k;
   auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
   const uint64_t w[] = {(uint64_t)c.K, (uint64_t)c.induced, (uint64_t)count_only, c.front_limit, vsmall,
+                        (uint64_t)c.tune.flat_grid, (uint64_t)c.tune.scan_grid, (uint64_t)use_ahead(c),
                         front_usable(c.ws), cpi_usable(c.ws), (uint64_t)(c.stat_bytes != nullptr),
                         (uint64_t)jobs.size()};
   put(w, sizeof w);
@@ -2357,7 +2368,7 @@ struct Bounded {
       upload_one(e);
       const int cls = e.last ? K_LAST : K_EXT;
       c.tm.run(cls, [&] {
-        ext_run(c.st, g, rec, 1, flat_grid(chunks_of(A1 - A0)), e.last != 0, e.last != 0 && probe_ahead(c.g),
+        ext_run(c.st, g, rec, 1, flat_grid(chunks_of(A1 - A0), enum_grid(c)), e.last != 0, e.last != 0 && use_ahead(c),
                 cls_bytes(c, cls));
       });
       if (!e.last) {
@@ -2510,7 +2521,7 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
       c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, (const ExtJob*)ws->jobrec, n0, scan_grid(n0, srcs)); });
     if (n0)
       c.tm.run(K_LAST, [&] {
-        ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, flat_grid(FLAT_GRID_MAX), true, probe_ahead(c.g),
+        ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, flat_grid(enum_grid(c), enum_grid(c)), true, use_ahead(c),
                 cls_bytes(c, K_LAST));
       });
     if (n1) {
@@ -2697,6 +2708,13 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
   if (o.batched != 0 && o.batched != 1) return set_error(GFD_EINVAL, "batched must be 0 or 1");
   if (o.mem_budget_bytes < 0 || o.frontier_cap < 0 || o.violation_cap < 0) return set_error(GFD_EINVAL, "negative option");
   if (int32_t rc = check_allocator(o.allocator)) return rc;
+  {
+    const gfd_tuning& t = o.tuning;
+    auto grid_ok = [](int32_t x) { return x == 0 || (x >= 64 && x <= 16384); };
+    if (!grid_ok(t.flat_grid) || !grid_ok(t.scan_grid) || t.probe_ahead < 0 || t.probe_ahead > 2 ||
+        !(t.staging_log2 == 0 || (t.staging_log2 >= 10 && t.staging_log2 <= 24)))
+      return set_error(GFD_EINVAL, "tuning out of range");
+  }
   const bool count_only = (o.flags & GFD_FLAG_COUNT_ONLY) != 0;
   if (count_only && o.k_max != 0) return set_error(GFD_EINVAL, "a count-only call needs k_max = 0");
   for (int32_t i = 0; i < num_specs; i++) {
@@ -2721,11 +2739,13 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     const int64_t njobs_hint = std::min<int64_t>(num_specs, max_batch);
     int64_t deep = 0;
     for (int32_t i = 0; i < num_specs; i++) deep += specs[i].num_vertices > 2;
-    const Sizing sz = call_sizing(budget, njobs_hint, std::min<int64_t>(deep, max_batch), K,
-                                  o.violation_cap);
+    Sizing sz = call_sizing(budget, njobs_hint, std::min<int64_t>(deep, max_batch), K, o.violation_cap);
+    if (o.tuning.staging_log2 && !o.violation_cap)  // the tuned staging per GFD of a batch
+      sz.vsmall = std::max<uint64_t>(uint64_t(1) << o.tuning.staging_log2, (uint64_t)K + 1);
     const uint64_t vsmall = sz.vsmall, vbig = sz.vbig;
     Ctx c{g, ws, (hipStream_t)o.hip_stream, o.semantics == GFD_SEM_INDUCED, K, (uint64_t)o.frontier_cap,
           Timer{}, stats, stats ? ws->misc + 8 : nullptr};
+    c.tune = o.tuning;
     const uint32_t cls_mask = ((uint32_t)o.flags >> 8) & 0xFFu;
     c.tm.on = stats && ((o.flags & GFD_FLAG_TIMING) || cls_mask);
     c.tm.mask = cls_mask ? cls_mask : 0xFFu;

@@ -38,6 +38,7 @@ STRUCTS = {
     "gfd_literal": B.gfd_literal, "gfd_edge": B.gfd_edge, "gfd_spec": B.gfd_spec,
     "gfd_result": B.gfd_result, "gfd_load_opts": B.gfd_load_opts,
     "gfd_validate_opts": B.gfd_validate_opts, "gfd_stats": B.gfd_stats, "gfd_allocator": B.gfd_allocator,
+    "gfd_tuning": B.gfd_tuning,
     "gfd_graph_info": B.gfd_graph_info, "gfd_server_opts": B.gfd_server_opts,
     "gfd_request_info": B.gfd_request_info,
 }
