@@ -75,8 +75,9 @@ typedef struct {
 } gfd_edge;
 
 /* One GFD.  Variable order x = (x_0 .. x_{k-1}) is the index order below; it is
- * the order of every reported tuple.  The pattern must be connected (through
- * edges in either direction); at most one edge per ordered pair. */
+ * the order of every reported tuple.  At most one edge per ordered pair.  The
+ * pattern may have several connected components (Section IV-A); a further
+ * component is joined to the first by a cross product of candidates. */
 typedef struct {
   int32_t num_vertices;                 /* k, 1..GFD_MAX_K */
   int32_t vertex_labels[GFD_MAX_K];     /* label or GFD_WILDCARD */
@@ -252,9 +253,8 @@ int32_t gfd_trim(gfd_graph* g);
 /* Validate num_specs GFDs over g (Section II's validation problem, per GFD).
  * Synchronous: returns once every result is on the host.  results is
  * caller-allocated [num_specs], each with its violations buffer.  A malformed
- * spec fails the whole call with GFD_EINVAL before any launch; a disconnected
- * pattern is GFD_EUNSUPPORTED.  Concurrent calls on one graph are allowed on
- * distinct streams. */
+ * spec fails the whole call with GFD_EINVAL before any launch.  Concurrent
+ * calls on one graph are allowed on distinct streams. */
 int32_t gfd_validate(const gfd_graph* g, const gfd_spec* specs, int32_t num_specs,
                      const gfd_validate_opts* opts, gfd_result* results);
 
@@ -325,8 +325,8 @@ typedef struct {
 int32_t gfd_server_create(const gfd_graph* g, const gfd_server_opts* opts, gfd_server** out);
 
 /* Queue one request of num_specs (1..max_batch_gfds) GFDs; specs are copied.
- * A malformed spec fails the submit with GFD_EINVAL (nothing is queued); a
- * disconnected pattern with GFD_EUNSUPPORTED.  Thread-safe. */
+ * A malformed spec fails the submit with GFD_EINVAL (nothing is queued).
+ * Thread-safe. */
 int32_t gfd_server_submit(gfd_server* s, const gfd_spec* specs, int32_t num_specs,
                           uint64_t* request_id);
 

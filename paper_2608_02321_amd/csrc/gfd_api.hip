@@ -735,6 +735,7 @@ struct Plan {
   int32_t qlab[MAXK];
   int32_t qe[MAXK][MAXK];  // label of pattern edge a->b, ANY, or NOEDGE
   int bfs[MAXK], parent[MAXK], order[MAXK], pos[MAXK];
+  bool virt[MAXK];  // the tree edge from parent[u] is virtual (u roots a further component)
   int min_out[MAXK], min_in[MAXK];
   bool core[MAXK];
   // pattern neighbours processed before / after each vertex in BFS order
@@ -788,19 +789,8 @@ static int32_t check_spec(const gfd_graph* g, const gfd_spec& s, int idx) {
     if (l.kind == GFD_LIT_VAR && (l.var2 < 0 || l.var2 >= k || l.attr2 < 0 || l.attr2 >= g->num_attrs))
       return set_error(GFD_EINVAL, "spec %d: literal %d second variable/attribute", idx, i);
   }
-  // connectivity of the undirected skeleton
-  int comp[MAXK];
-  for (int i = 0; i < k; i++) comp[i] = i;
-  bool changed = true;
-  while (changed) {
-    changed = false;
-    for (int e = 0; e < s.num_edges; e++) {
-      int a = s.edges[e].src, b = s.edges[e].dst, c = std::min(comp[a], comp[b]);
-      if (comp[a] != c || comp[b] != c) { comp[a] = comp[b] = c; changed = true; }
-    }
-  }
-  for (int i = 0; i < k; i++)
-    if (comp[i] != 0) return set_error(GFD_EUNSUPPORTED, "spec %d: disconnected pattern", idx);
+  // a pattern of several connected components is allowed (Section IV-A):
+  // its components are joined by a cross product in the enumeration
   return GFD_OK;
 }
 
@@ -842,28 +832,63 @@ static void make_plan(const gfd_graph* g, const gfd_spec& s, bool induced, Plan&
           if (adj[a][b]) d2[b]--;
       }
   }
-  bool any_core = false;
-  for (int a = 0; a < k; a++) { p.core[a] = alive[a]; any_core |= alive[a]; }
-  // root: smallest estimated candidates per skeleton degree among core
-  // vertices (all vertices for a tree pattern); ties to the lower index
-  double best = 1e300;
-  p.root = 0;
+  for (int a = 0; a < k; a++) p.core[a] = alive[a];
+  // connected components of the skeleton (a pattern may have several,
+  // Section IV-A)
+  int comp[MAXK];
+  for (int a = 0; a < k; a++) comp[a] = -1;
+  int ncomp = 0;
   for (int a = 0; a < k; a++) {
-    if (any_core && !p.core[a]) continue;
-    double c = (double)bucket_size(g, p.qlab[a]) / std::max(1, deg[a]);
-    if (c < best) { best = c; p.root = a; }
+    if (comp[a] >= 0) continue;
+    int st[MAXK], sp = 0;
+    st[sp++] = a;
+    comp[a] = ncomp;
+    while (sp) {
+      const int x = st[--sp];
+      for (int b = 0; b < k; b++)
+        if (adj[x][b] && comp[b] < 0) { comp[b] = ncomp; st[sp++] = b; }
+    }
+    ncomp++;
   }
-  if (!any_core) p.core[p.root] = true;
-  // BFS spanning tree
+  // a root per component: smallest estimated candidates per skeleton degree
+  // among its core vertices (all its vertices when it is a tree, the root
+  // then being its core); ties to the lower index.  Components go most
+  // selective root first.
+  int croot[MAXK];
+  double cbest[MAXK];
+  for (int cc = 0; cc < ncomp; cc++) {
+    bool has_core = false;
+    for (int a = 0; a < k; a++) has_core |= comp[a] == cc && p.core[a];
+    cbest[cc] = 1e300;
+    croot[cc] = -1;
+    for (int a = 0; a < k; a++) {
+      if (comp[a] != cc || (has_core && !p.core[a])) continue;
+      const double c = (double)bucket_size(g, p.qlab[a]) / std::max(1, deg[a]);
+      if (c < cbest[cc]) { cbest[cc] = c; croot[cc] = a; }
+    }
+    if (!has_core) p.core[croot[cc]] = true;
+  }
+  int corder[MAXK];
+  for (int cc = 0; cc < ncomp; cc++) corder[cc] = cc;
+  std::stable_sort(corder, corder + ncomp, [&](int x, int y) { return cbest[x] < cbest[y]; });
+  p.root = croot[corder[0]];
+  // BFS spanning tree of each component from its root, one after another; a
+  // later component's root hangs from the first root by a virtual tree edge
+  // (no pattern edge: its candidates are all of C(root'), the cross product)
   int head = 0, tail = 0;
   bool vis[MAXK] = {};
-  p.bfs[tail++] = p.root;
-  vis[p.root] = true;
-  p.parent[p.root] = -1;
-  while (head < tail) {
-    int a = p.bfs[head++];
-    for (int b = 0; b < k; b++)
-      if (adj[a][b] && !vis[b]) { vis[b] = true; p.parent[b] = a; p.bfs[tail++] = b; }
+  for (int a = 0; a < k; a++) p.virt[a] = false;
+  for (int ci = 0; ci < ncomp; ci++) {
+    const int r = croot[corder[ci]];
+    p.bfs[tail++] = r;
+    vis[r] = true;
+    p.parent[r] = ci == 0 ? -1 : p.root;
+    p.virt[r] = ci > 0;
+    while (head < tail) {
+      int a = p.bfs[head++];
+      for (int b = 0; b < k; b++)
+        if (adj[a][b] && !vis[b]) { vis[b] = true; p.parent[b] = a; p.bfs[tail++] = b; }
+    }
   }
   // matching order: core (BFS order), then forest non-leaves, then leaves
   int o = 0;
@@ -894,6 +919,12 @@ static void make_plan(const gfd_graph* g, const gfd_spec& s, bool induced, Plan&
   for (int u = 0; u < k; u++) {
     if (u == p.root) continue;
     int q = p.parent[u];
+    if (p.virt[u]) {  // no CPI lists: the enumeration takes all of C(u)
+      p.adj_dir[u] = 0;
+      p.adj_prim[u] = ANY;
+      p.adj_other[u] = PC_FREE;
+      continue;
+    }
     p.is_parent[q] = true;
     if (p.qe[q][u] != NOEDGE) {
       p.adj_dir[u] = 0;
@@ -915,7 +946,7 @@ static void make_plan(const gfd_graph* g, const gfd_spec& s, bool induced, Plan&
     p.nchk[i] = 0;
     for (int pass = 0; pass < 2; pass++)
       for (int j = 0; j < i; j++) {
-        if (j == ppos) continue;
+        if (j == ppos && !p.virt[u]) continue;  // the CPI list holds that edge
         int w = p.order[j];
         int32_t f = pair_code(p, w, u, induced), b = pair_code(p, u, w, induced);
         if (f == PC_FREE && b == PC_FREE) continue;
@@ -1184,6 +1215,17 @@ static CandSet cand_set(const Job& J, int u) {
                  J.mem.bits[u][J.cur[u]], J.plan.qlab[u] != ANY ? 1 : 0};
 }
 
+// The level of u when u roots a further component: its attempts are all of
+// C(u) for every source.
+static void set_cross(const Job& J, int u, ExtJob& e) {
+  if (!J.plan.virt[u]) return;
+  const CandSet cs = cand_set(J, u);
+  e.cross = 1;
+  e.cpi_ent = cs.list;
+  e.cross_n = cs.cnt;
+  e.cross_cap = J.caps.lcap_u[u];
+}
+
 static JobScan job_scan_rec(Ctx& c, const Job& J, uint64_t* d_total, uint32_t epoch) {
   return JobScan{J.mem.P, d_total, J.mem.tstate, (uint32_t*)(J.mem.ctl + CTL_TICKET), c.ws->err,
                  epoch};
@@ -1306,7 +1348,8 @@ static uint64_t est_front_bytes(const gfd_graph* g, const Plan& p) {
   double N = (double)bucket_size(g, p.qlab[p.root]), bytes = 0;
   for (int i = 1; i < p.k_enum; i++) {
     const int u = p.order[i], q = p.parent[u];
-    const double T = N * fan_out(g, p.qlab[q], p.adj_prim[u], p.qlab[u], p.adj_dir[u]);
+    const double T = N * (p.virt[u] ? (double)bucket_size(g, p.qlab[u])
+                                     : fan_out(g, p.qlab[q], p.adj_prim[u], p.qlab[u], p.adj_dir[u]));
     const bool last = p.leaf_r == 0 && i == p.k - 1;
     if (!last) bytes += T * (4.0 * (i + 1) + 12.0) + 1024.0;
     N = T;
@@ -1519,6 +1562,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       a = CpiJob{};
       if (j >= p.k) continue;
       const int u = p.bfs[j], q = p.parent[u];
+      if (p.virt[u]) continue;  // a further component's root: no CPI lists
       a.active = 1;
       a.dir = p.adj_dir[u];
       a.prim = p.adj_prim[u];
@@ -1596,6 +1640,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       e.cpi_beg = J.mem.cpi_beg[u];
       e.cpi_len = J.mem.cpi_len[u];
       e.cpi_ent = c.ws->cpi_arena;
+      set_cross(J, u, e);
       e.a_begin = 0;
       e.a_end = ~0ull;
       e.nchk = p.nchk[i];
@@ -2337,6 +2382,7 @@ struct Bounded {
     e.cpi_beg = J.mem.cpi_beg[u];
     e.cpi_len = J.mem.cpi_len[u];
     e.cpi_ent = c.ws->cpi_arena;
+    set_cross(J, u, e);
     e.begs = begs[i];
     e.sc = JobScan{P[i], J.mem.ctl + CTL_LEVEL_T + i, J.mem.tstate,
                    (uint32_t*)(J.mem.ctl + CTL_TICKET), c.ws->err, next_epoch(c)};

@@ -225,6 +225,12 @@ struct ExtJob {
   const uint32_t* cpi_beg;
   const uint32_t* cpi_len;
   const int32_t* cpi_ent;
+  // the vertex of this level roots a further component of the pattern: every
+  // source's list is all of its candidate set (cpi_ent = that list, of
+  // min(*cross_n, cross_cap) members) instead of a CPI list
+  int32_t cross;
+  const uint64_t* cross_n;
+  uint64_t cross_cap;
   uint32_t* begs;           // [src_cap] list start per source
   JobScan sc;               // over sources
   // inner levels of the fast path: the next frontier is reserved from the

@@ -268,7 +268,6 @@ def test_errors(P):
     g = random_graph(12, 20, 40)
     gh = P.load(g)
     bad = [
-        ({"k": 3, "vlabels": [0, 0, 0], "edges": [[0, 1, 0]], "x": [], "y": []}, P.GfdError),
         ({"k": 2, "vlabels": [0, 0], "edges": [[0, 0, 0]], "x": [], "y": []}, P.GfdError),
         ({"k": 2, "vlabels": [0, 0], "edges": [[0, 1, 0], [0, 1, 1]], "x": [], "y": []},
          P.GfdError),
@@ -282,7 +281,7 @@ def test_errors(P):
         with pytest.raises(exc) as ei:
             P.validate(gh, [d])
         codes.append(ei.value.code)
-    assert codes == [-4, -1, -1, -1, -1]
+    assert codes == [-1, -1, -1, -1]
     with pytest.raises(P.GfdError) as ei:
         P.validate(gh, [{"k": 1, "vlabels": [0], "edges": [], "x": [], "y": []}], K=4096)
     assert ei.value.code == -4
@@ -353,3 +352,46 @@ def test_full_size_batch_at_small_budgets(P):
         for i, (r, e) in enumerate(zip(got, exp["results"]["induced"])):
             assert r == e, (budget, i)
     gh.free()
+
+
+def test_disconnected_patterns(P):
+    """Patterns of several connected components (Section IV-A): every further
+    component's root takes all of its candidates for every partial match (a
+    cross product), with injectivity and, under the induced reading, the
+    absence of edges between components checked like any other pair."""
+    g = random_graph(14, 200, 1200, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3,
+                     absent_frac=0.1, reciprocal_frac=0.3)
+    gfds = [
+        {"k": 2, "vlabels": [0, 1], "edges": [], "x": [],
+         "y": [{"kind": "var", "var": 0, "attr": 0, "var2": 1, "attr2": 0}], "y_false": False},
+        {"k": 4, "vlabels": [0, -1, 1, 1], "edges": [[0, 1, 0], [2, 3, -1]],
+         "x": [{"kind": "const", "var": 2, "attr": 1, "value": 1}], "y": [], "y_false": True},
+        {"k": 4, "vlabels": [0, 0, 0, 1], "edges": [[0, 1, -1], [1, 2, -1], [2, 0, -1]], "x": [],
+         "y": [{"kind": "const", "var": 3, "attr": 0, "value": 2}], "y_false": False},
+        {"k": 3, "vlabels": [-1, -1, -1], "edges": [], "x": [], "y": [], "y_false": True},
+        {"k": 5, "vlabels": [1, 0, 1, 0, -1], "edges": [[1, 0, 1], [3, 2, -1], [4, 3, 0]],
+         "x": [], "y": [{"kind": "var", "var": 0, "attr": 1, "var2": 4, "attr2": 1}],
+         "y_false": False},
+    ]
+    # random patterns, mostly disconnected, on a graph small enough for the
+    # oracle to enumerate their cross products
+    g2 = random_graph(15, 30, 150, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3)
+    rand = [random_gfd(1400 + j, int(np.random.default_rng(j).integers(2, 5)), n_vlabels=2,
+                       n_elabels=2, n_attrs=2, attr_values=3, connected=False,
+                       extra_edge_frac=0.25) for j in range(16)]
+    gh, gh2 = P.load(g), P.load(g2)
+    for sem in SEMS:
+        for batched in (False, True):
+            _check(P, g, gfds, sem, K=24, gh=gh, batched=batched)
+            _check(P, g2, rand, sem, K=24, gh=gh2, batched=batched)
+        _check(P, g, gfds, sem, K=24, gh=gh, frontier_cap=500)
+        _check(P, g, gfds, sem, K=24, gh=gh, flags=P.GFD_FLAG_FORCE_CHUNKED)
+        # count-only calls report counts and no fingerprints
+        cnt = P.validate(gh2, rand, K=0, semantics=sem, flags=P.GFD_FLAG_COUNT_ONLY)
+        og2 = O.OracleGraph(g2)
+        for i, (d, r) in enumerate(zip(rand, cnt)):
+            e = O.validate(og2, d, sem, K=0, threads=4)
+            assert (r["match_count"], r["violation_count"], r["match_fp"]) == \
+                (e["match_count"], e["violation_count"], 0), (i, sem)
+    gh.free()
+    gh2.free()
