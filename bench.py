@@ -39,32 +39,34 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "f088ff7e6901831260960c43bbc98f005bdb8cb34a91966300296c4074479b1e",
+    "sources_sha256": "09f97fdf1db7c91dfe9ad0f9669eecad0f4ee083c99568a08f1c6ad71689ee14",
     "workload": "kg_4m_batch256",
-    "kernel_class": "extend_last",  # k_ext_run<true, false>
+    "kernel_class": "extend_last",  # k_ext_run<true, false, 8>
     "semantics": "induced",
     "count_only": False,
-    # (510.69 MB read + 10.18 MB written) per dispatch, calibrated (x1.9999, x1.0)
-    "bytes_per_launch": 5.2087e8,
+    # (600.60 MB read + 38.27 MB written) per dispatch, calibrated (x1.9999, x1.0)
+    "bytes_per_launch": 6.3887e8,
 }
-# Units of work of the dominant kernel per launch, from the counting build
-# (bench.py --units; see profiles/), and the algorithmic bytes the per-unit
-# model gives them: 4 B per attempt, 8 B per source, 4 B per search step of
-# ceil(log2 d) over a row of d entries for a one-direction probe and twice
-# that for a check of both directions, 4 B per attribute value a literal
-# reads.  Valid only for the kernel sources it was counted on.
+# Units of work of the dominant kernel class per step (one validate call),
+# from the counting build (bench.py --units; see profiles/), and the
+# algorithmic bytes the per-unit model gives them: 4 B per attempt, 8 B per
+# source, 4 B per search step of ceil(log2 d) over a row of d entries for a
+# one-direction probe and twice that for a check of both directions, 4 B per
+# attribute value a literal reads.  Per step, not per launch: a call may add a
+# small threshold re-run launch or not, which leaves the work per step as it
+# is.  Valid only for the kernel sources it was counted on.
 UNITS = {
-    "sources_sha256": "f088ff7e6901831260960c43bbc98f005bdb8cb34a91966300296c4074479b1e",
+    "sources_sha256": "09f97fdf1db7c91dfe9ad0f9669eecad0f4ee083c99568a08f1c6ad71689ee14",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",
     "semantics": "induced",
     "count_only": False,
-    "per_launch": {"attempts": 19786060.4, "sources": 1575688.4, "injective": 19784612.0,
-                   "checks_both": 52013171.1, "table_free": 45152484.6, "table_hit": 1033808.9,
-                   "short_row": 5826877.6, "both_steps": 25710580.0, "both_log2d": 481591478.9,
-                   "checks_one": 0.0, "one_steps": 0.0, "one_log2d": 0.0, "matches": 18486402.8,
-                   "literal_reads": 20324108.8, "violations": 8510302.8, "inner_attempts": 2435247.3},
-    "model_bytes_per_launch": 4.02578e9,
+    "per_step": {"attempts": 158465184, "sources": 12610132, "injective": 158453597,
+                 "checks_both": 416647418, "table_free": 361686429, "table_hit": 8278219,
+                 "short_row": 46682770, "both_steps": 205916298, "both_log2d": 3857108160,
+                 "checks_one": 0, "one_steps": 0, "one_log2d": 0, "matches": 147891222,
+                 "literal_reads": 162853957, "violations": 68082422, "inner_attempts": 19554114},
+    "model_bytes_per_step": 3.22430e10,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
@@ -152,7 +154,8 @@ def unit_report(args, P, gh, gfds, stream, batched):
     ms = st["class_ms"]["extend_last"]
     out = {"units_per_step": u, "extend_last_launches": n,
            "units_per_launch": {k: v / n for k, v in u.items()},
-           "model_bytes_per_launch": model / n, "device_bytes_per_launch": dev / n,
+           "model_bytes_per_step": model, "model_bytes_per_launch": model / n,
+           "device_bytes_per_launch": dev / n,
            "extend_last_ms_per_step": ms, "matches_per_step": pc.match_count(),
            "config": {"workload": args.workload, "semantics": args.semantics,
                       "count_only": bool(args.count_only), "library": "libgfd_count.so"}}
@@ -432,8 +435,9 @@ def main():
         traffic = TRAFFIC["bytes_per_launch"] if valid(TRAFFIC) else None
         # algorithmic bytes: the per-unit model over the units one launch
         # processes (counting build), else the bytes counted on the device
-        if valid(UNITS):
-            per_launch, basis = UNITS["model_bytes_per_launch"], "per-unit model x counted units"
+        if valid(UNITS):  # the step's model bytes over this run's launches per step
+            per_launch = UNITS["model_bytes_per_step"] / (agg_launch / roof_steps)
+            basis = "per-unit model x counted units"
         else:
             per_launch, basis = dev_per_launch, "device-counted bytes (unit counts stale)"
         ach = gbs(per_launch)

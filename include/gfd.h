@@ -141,6 +141,12 @@ typedef struct {
                             any round runs, 2 does not, 0 picks by graph size */
   int32_t staging_log2;  /* violation staging per GFD in a batch, 2^n tuples (10..24;
                             0: from the budget, at most 2^18) */
+  int32_t ext_occupancy; /* enumeration levels: 1 runs the kernels with the registers
+                            the compiler allocates (5 waves per SIMD at the last
+                            level), 2 with at most 64 per lane so that 8 waves share
+                            a SIMD (the rest spilled to scratch), which hides more
+                            HBM latency when the graph does not fit in cache; 0
+                            picks by graph size */
 } gfd_tuning;
 
 typedef struct {

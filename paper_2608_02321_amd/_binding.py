@@ -78,14 +78,15 @@ class gfd_load_opts(C.Structure):
 
 class gfd_tuning(C.Structure):
     _fields_ = [("flat_grid", C.c_int32), ("scan_grid", C.c_int32), ("probe_ahead", C.c_int32),
-                ("staging_log2", C.c_int32)]
+                ("staging_log2", C.c_int32), ("ext_occupancy", C.c_int32)]
 
 
 def make_tuning(t) -> gfd_tuning:
     """gfd_tuning from a dict (missing keys: the library's defaults)."""
     t = t or {}
     return gfd_tuning(int(t.get("flat_grid", 0)), int(t.get("scan_grid", 0)),
-                      int(t.get("probe_ahead", 0)), int(t.get("staging_log2", 0)))
+                      int(t.get("probe_ahead", 0)), int(t.get("staging_log2", 0)),
+                      int(t.get("ext_occupancy", 0)))
 
 
 class gfd_validate_opts(C.Structure):

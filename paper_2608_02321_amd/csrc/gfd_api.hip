@@ -1303,6 +1303,11 @@ static int enum_scan_grid(const Ctx& c) { return c.tune.scan_grid ? c.tune.scan_
 static bool use_ahead(const Ctx& c) {
   return c.tune.probe_ahead == 1 || (c.tune.probe_ahead == 0 && probe_ahead(c.g));
 }
+// Enumeration kernels limited to 64 VGPRs (8 waves per SIMD): by default for
+// graphs too large to stay in cache, where the last level waits on HBM.
+static bool use_occ8(const Ctx& c) {
+  return c.tune.ext_occupancy == 2 || (c.tune.ext_occupancy == 0 && !probe_ahead(c.g));
+}
 
 static int flat_grid(uint64_t chunks, uint64_t cap = FLAT_GRID_MAX) {
   uint64_t g = std::max<uint64_t>(1, std::min<uint64_t>(chunks, cap));
@@ -1843,10 +1848,10 @@ static void run_launch(Ctx& c, const Launch& l) {
                           c.ws->front, front_usable(c.ws), c.ws->misc + 1);
           });
         if (l.inner_any)
-          c.tm.run(K_EXT, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, false, false, cls_bytes(c, K_EXT)); });
+          c.tm.run(K_EXT, [&] { ext_run(c.st, g, r, l.njobs, l.gx_work, false, false, use_occ8(c), cls_bytes(c, K_EXT)); });
         if (l.last_any)
           c.tm.run(K_LAST, [&] {
-            ext_run(c.st, g, r, l.njobs, l.gx_work, true, use_ahead(c), cls_bytes(c, K_LAST));
+            ext_run(c.st, g, r, l.njobs, l.gx_work, true, use_ahead(c), use_occ8(c), cls_bytes(c, K_LAST));
           });
         break;
       }
@@ -2146,7 +2151,7 @@ static std::string graph_key(const Ctx& c, const std::vector<Job>& jobs, const g
   std::string k;
   auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
   const uint64_t w[] = {(uint64_t)c.K, (uint64_t)c.induced, (uint64_t)count_only, c.front_limit, vsmall,
-                        (uint64_t)c.tune.flat_grid, (uint64_t)c.tune.scan_grid, (uint64_t)use_ahead(c),
+                        (uint64_t)c.tune.flat_grid, (uint64_t)c.tune.scan_grid, (uint64_t)use_ahead(c), (uint64_t)use_occ8(c),
                         front_usable(c.ws), cpi_usable(c.ws), (uint64_t)(c.stat_bytes != nullptr),
                         (uint64_t)jobs.size()};
   put(w, sizeof w);
@@ -2415,7 +2420,7 @@ struct Bounded {
       const int cls = e.last ? K_LAST : K_EXT;
       c.tm.run(cls, [&] {
         ext_run(c.st, g, rec, 1, flat_grid(chunks_of(A1 - A0), enum_grid(c)), e.last != 0, e.last != 0 && use_ahead(c),
-                cls_bytes(c, cls));
+                use_occ8(c), cls_bytes(c, cls));
       });
       if (!e.last) {
         const uint64_t N = rd(CTL_LEVEL_N + i + 1);
@@ -2568,7 +2573,7 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     if (n0)
       c.tm.run(K_LAST, [&] {
         ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, flat_grid(enum_grid(c), enum_grid(c)), true, use_ahead(c),
-                cls_bytes(c, K_LAST));
+                use_occ8(c), cls_bytes(c, K_LAST));
       });
     if (n1) {
       uint64_t items = 1;
@@ -2758,6 +2763,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     const gfd_tuning& t = o.tuning;
     auto grid_ok = [](int32_t x) { return x == 0 || (x >= 64 && x <= 16384); };
     if (!grid_ok(t.flat_grid) || !grid_ok(t.scan_grid) || t.probe_ahead < 0 || t.probe_ahead > 2 ||
+        t.ext_occupancy < 0 || t.ext_occupancy > 2 ||
         !(t.staging_log2 == 0 || (t.staging_log2 >= 10 && t.staging_log2 <= 24)))
       return set_error(GFD_EINVAL, "tuning out of range");
   }

@@ -394,7 +394,7 @@ void front_reserve(hipStream_t st, ExtJob* cur, ExtJob* next, LeafJob* leaf, int
 // ahead (last level only): load every round's first probe slot before the
 // rounds run -- more loads in flight, fewer waves; for cache-resident graphs
 void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
-             bool ahead, unsigned long long* bytes);
+             bool ahead, bool occ8, unsigned long long* bytes);
 // k == 1: every member of the root's candidate set is a match.
 void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
                 unsigned long long* bytes);

@@ -1463,9 +1463,13 @@ __device__ __forceinline__ uint64_t ext_width(const ExtJob& J) {
   return A1 > J.a_begin ? A1 - J.a_begin : 0ull;
 }
 
-template <bool LAST, bool AHEAD>
-__global__ __launch_bounds__(BS) void k_ext_run(DevGraph g, const ExtJob* __restrict__ jobs,
-                                                int njobs, unsigned long long* bytes) {
+// WAVES: the least number of waves per SIMD the register allocation must
+// allow (1: the compiler's own choice; 8: at most 64 VGPRs per lane, the rest
+// spilled).  The last level waits on chains of dependent loads; where they go
+// to HBM, more waves in flight pay for the spills.
+template <bool LAST, bool AHEAD, int WAVES>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WAVES)))
+void k_ext_run(DevGraph g, const ExtJob* __restrict__ jobs, int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
   __shared__ ChunkMap cm;
   __shared__ unsigned long long s_wcnt[BS / WAVE];
@@ -1770,14 +1774,23 @@ void front_reserve(hipStream_t st, ExtJob* cur, ExtJob* next, LeafJob* leaf, int
   hipLaunchKernelGGL(k_front_reserve, dim3(1), dim3(BS), 0, st, cur, next, leaf, njobs, pool, pool_bytes,
                      cursor);
 }
-void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
-             bool ahead, unsigned long long* bytes) {
+template <int WAVES>
+static void ext_run_w(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid,
+                      bool last, bool ahead, unsigned long long* bytes) {
   if (last && ahead)
-    hipLaunchKernelGGL((k_ext_run<true, true>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+    hipLaunchKernelGGL((k_ext_run<true, true, WAVES>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
   else if (last)
-    hipLaunchKernelGGL((k_ext_run<true, false>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+    hipLaunchKernelGGL((k_ext_run<true, false, WAVES>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
   else
-    hipLaunchKernelGGL((k_ext_run<false, false>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+    hipLaunchKernelGGL((k_ext_run<false, false, WAVES>), dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+}
+
+void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid, bool last,
+             bool ahead, bool occ8, unsigned long long* bytes) {
+  if (occ8)
+    ext_run_w<8>(st, g, jobs, njobs, grid, last, ahead, bytes);
+  else
+    ext_run_w<1>(st, g, jobs, njobs, grid, last, ahead, bytes);
 }
 void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
                 unsigned long long* bytes) {

@@ -6,7 +6,7 @@ enumeration launches and of their scans, the last level's probe-ahead form
 and the violation staging per GFD -- checks that every choice gives exactly
 the results of the defaults, and keeps the fastest.  The choice is cached in
 a JSON file keyed by the graph's sha256, the sha256 of the HIP sources and
-the call's shape class (batched or not, number of GFDs, largest pattern,
+of the loaded library file, and the call's shape class (batched or not, number of GFDs, largest pattern,
 reading, K, counts only).  Only how the work is spread over the GPU changes,
 never a result (the tests check every candidate against the oracle).
 """
@@ -26,6 +26,7 @@ CANDIDATES = {
     "scan_grid": [0, 512, 4096],
     "probe_ahead": [0, 1, 2],
     "staging_log2": [0, 16, 20],
+    "ext_occupancy": [0, 1, 2],
 }
 DEFAULTS = {k: 0 for k in CANDIDATES}
 
@@ -38,6 +39,15 @@ def sources_sha256() -> str:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def library_sha256() -> str:
+    """sha256 of the loaded library file (another build of the same sources,
+    e.g. one chosen with GFD_LIBRARY, keeps its own choices)."""
+    h = hashlib.sha256()
+    with open(B.LIB_PATH, "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()
 
 
@@ -90,7 +100,8 @@ def tune(gh, gfds, graph_sha256, K=1024, semantics="induced", batched=True, coun
     holds one for this graph and these sources), with the default and tuned
     times and every candidate tried."""
     path = path or cache_path()
-    key = f"{graph_sha256}:{sources_sha256()}:{shape_class(gfds, K, semantics, batched, count_only)}"
+    key = (f"{graph_sha256}:{sources_sha256()}:{library_sha256()[:16]}:"
+           f"{shape_class(gfds, K, semantics, batched, count_only)}")
     cache = _load(path)
     if not retune and key in cache:
         return dict(cache[key], cached=True)

@@ -40,3 +40,17 @@ def test_cpu_baseline_fields():
     for leg, cores in ((out, 2), (out["single_thread"], 1)):
         assert leg["kind"] == "oracle" and leg["unit"] == "embeddings/s"
         assert leg["cores"] == cores and leg["value"] >= 0 and leg["sample"]
+
+
+def test_stored_tables_agree():
+    """The stored model bytes are the per-unit model over the stored units,
+    and the units are consistent with one another."""
+    sys.path.insert(0, ROOT)
+    import bench
+    u = bench.UNITS["per_step"]
+    model = (4 * u["attempts"] + 8 * u["sources"] + 8 * u["both_log2d"] + 4 * u["one_log2d"]
+             + 4 * u["literal_reads"])
+    assert abs(model - bench.UNITS["model_bytes_per_step"]) <= 1e-5 * model
+    # checks of both directions end in a table slot, a fingerprint match or a short row
+    assert u["table_free"] + u["table_hit"] + u["short_row"] == u["checks_both"]
+    assert u["matches"] <= u["injective"] <= u["attempts"]

@@ -2,8 +2,11 @@
 cross-compiles for gfx950 without a GPU).  No kernel may use per-lane scratch
 memory: a tuple held in a runtime-indexed private array ends up there, and
 every enumeration attempt then stores and reloads it through the memory
-hierarchy.  The enumeration kernels must also keep enough waves per SIMD to
-hide the latency of their random loads."""
+hierarchy.  The one exception is the enumeration kernels' 8-wave form, whose
+registers are capped at 64 per lane on purpose (for graphs in HBM, more waves
+in flight pay for a few spilled values); its spills stay small.  The
+enumeration kernels must also keep enough waves per SIMD to hide the latency
+of their random loads."""
 import os
 import re
 import shutil
@@ -40,14 +43,31 @@ def report(tmp_path_factory):
     return kernels
 
 
+def _eight_wave(name):
+    return "k_ext_run" in name and name.split("ELi")[-1].startswith("8E")
+
+
 def test_no_kernel_uses_scratch(report):
     bad = {k: v.get("ScratchSize [bytes/lane]") for k, v in report.items()
-           if v.get("ScratchSize [bytes/lane]") != "0"}
+           if v.get("ScratchSize [bytes/lane]") != "0" and not _eight_wave(k)}
     assert not bad, bad
+
+
+def test_eight_wave_form_spills_little(report):
+    eight = {k: v for k, v in report.items() if _eight_wave(k)}
+    assert len(eight) == 3, list(report)
+    for k, v in eight.items():
+        assert int(v["Occupancy [waves/SIMD]"]) == 8, k
+        assert int(v["ScratchSize [bytes/lane]"]) <= 512, (k, v["ScratchSize [bytes/lane]"])
+    # the forms a default choice runs: inner levels and the plain last level
+    plain = [k for k in eight if "ILb1ELb1" not in k]
+    for k in plain:
+        assert int(eight[k]["ScratchSize [bytes/lane]"]) <= 128, k
 
 
 def test_enumeration_occupancy(report):
     ext = {k: int(v["Occupancy [waves/SIMD]"]) for k, v in report.items() if "k_ext_run" in k}
-    assert len(ext) == 3, list(report)  # inner levels; last level plain and probing ahead
+    # inner levels, last level plain and probing ahead; each in its two forms
+    assert len(ext) == 6, list(report)
     for k, occ in ext.items():
         assert occ >= 4, (k, occ)
