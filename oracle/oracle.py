@@ -62,10 +62,16 @@ def load(path: str):
 
 
 def lib():
+    """The oracle library: the built one, or the build named by GFD_ORACLE_LIB
+    (a sanitizer build of the same source, for the tests)."""
     global _lib
     if _lib is None:
-        build()
-        _lib = load(LIB)
+        other = os.environ.get("GFD_ORACLE_LIB")
+        if other:
+            _lib = load(other)
+        else:
+            build()
+            _lib = load(LIB)
     return _lib
 
 

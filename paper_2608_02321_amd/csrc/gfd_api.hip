@@ -12,6 +12,7 @@
 // violation staging overflowed its share of the budget is re-run on the
 // chunked path, which bounds every level by the budget.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <atomic>
@@ -23,6 +24,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <optional>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -35,6 +37,16 @@
 #include "gfd_internal.h"
 
 using namespace gfd;
+
+// A named range of host time for profilers (roctx: `rocprofv3 --marker-trace`
+// lists it beside the kernels the range enqueued); nearly free when no tool
+// is attached.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // ---------------------------------------------------------------------------
 // errors
@@ -337,6 +349,7 @@ static int32_t load_graph_impl(int64_t n, int64_t m, const int64_t* row_ptr, con
                                gfd_graph** out) {
   if (!out) return set_error(GFD_EINVAL, "out is NULL");
   *out = nullptr;
+  const Range whole("gfd_load_graph");
   gfd_load_opts lo{};
   if (opts) lo = *opts;
   if (lo.mem_kind != GFD_MEM_HOST && lo.mem_kind != GFD_MEM_DEVICE)
@@ -2745,6 +2758,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
                              const gfd_validate_opts* opts, gfd_result* results, gfd_stats* stats,
                              Workspace* fixed) {
   const auto t_start = std::chrono::steady_clock::now();
+  const Range whole("gfd_validate");
   gfd_graph* g = const_cast<gfd_graph*>(gc);
   if (!g) return set_error(GFD_EINVAL, "graph is NULL");
   if (num_specs < 0 || (num_specs > 0 && (!specs || !results)))
@@ -2808,6 +2822,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     }
     fill_u32(c.st, ws->err, 0u, 1);
     // plans, capacities and batches
+    std::optional<Range> phase(std::in_place, "plan");
     std::vector<Job> all(num_specs);
     for (int32_t i = 0; i < num_specs; i++) {
       all[i].spec = i;
@@ -2854,7 +2869,9 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     // the retries appended below, which follow a growth of the buffers)
     const bool use_graphs = !(o.flags & GFD_FLAG_NO_GRAPH) && !c.tm.on && !ws->al.area && !force_bounded;
     const size_t n_planned = batches.size();
+    phase.reset();
     for (size_t bi = 0; bi < batches.size(); bi++) {
+      const Range batch_range("batch");
       std::vector<Job> jobs;
       for (int i : batches[bi]) jobs.push_back(all[i]);
       rewind_area(ws);
@@ -2885,16 +2902,20 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
             }
           }
         }
-        if (e) {
-          c.recbase = e->recs;
-          HIPCHK(hipGraphLaunch(e->exec, c.st));
-        } else {
-          Recs R;
-          LaunchList L;
-          plan_and_run_batch(c, jobs, R, L);
-          read_back(c, jobs);
+        {
+          // filter, CPI, enumeration with the literal check, first K
+          const Range main_pass(e ? "main pass (graph replay)" : "main pass");
+          if (e) {
+            c.recbase = e->recs;
+            HIPCHK(hipGraphLaunch(e->exec, c.st));
+          } else {
+            Recs R;
+            LaunchList L;
+            plan_and_run_batch(c, jobs, R, L);
+            read_back(c, jobs);
+          }
+          HIPCHK(hipStreamSynchronize(c.st));
         }
-        HIPCHK(hipStreamSynchronize(c.st));
         uint8_t* const recbase = c.recbase ? c.recbase : ws->jobrec;  // where the main pass's records are
         c.recbase = nullptr;
         cpi_entries += std::min<uint64_t>(ws->hmisc[0], ws->cpi_cap);
@@ -2952,6 +2973,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         }
         if (!over.empty()) {
           if (stats) stats->threshold_gfds += (int32_t)over.size();
+          const Range rerun("threshold re-run");
           rerun_last_levels(c, jobs, over, lastrec, vsmall, redo, [&] { if (D) D->drain(); });
           for (int x : over)
             if (!redo[x]) {
@@ -2961,6 +2983,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         }
         // staged violations beyond one workgroup's sort: batched radix select
         if (K > 0) {
+          const Range sel("violation select");
           std::vector<SelJob> S;
           for (size_t x = 0; x < jobs.size(); x++) {
             if (redo[x] || !H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL]) continue;
@@ -2992,6 +3015,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
       for (size_t x = 0; x < jobs.size(); x++) {
         if (redo[x] != 1) continue;
         if (stats) stats->chunked_gfds++;
+        const Range bounded("bounded re-run");
         run_bounded(c, jobs[x], vbig);
         HIPCHK(hipMemcpyAsync(&H[(size_t)jobs[x].spec * CTL_WORDS], jobs[x].mem.ctl,
                               sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
@@ -3198,6 +3222,7 @@ struct gfd_server {
         bid = next_batch++;
       }
       const int64_t t_start = now_ns();
+      const Range batch_range("server batch");
       std::vector<gfd_spec> specs;
       std::vector<gfd_result> res;
       for (ServerReq* r : batch) {

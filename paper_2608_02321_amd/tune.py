@@ -122,6 +122,17 @@ def tune(gh, gfds, graph_sha256, K=1024, semantics="induced", batched=True, coun
                 log(f"tune: {cand} {ms:.3f} ms (best {best_ms:.3f})")
             if ms < best_ms * 0.98:  # keep a change only when it clearly pays
                 best, best_ms = cand, ms
+    if best != DEFAULTS:
+        # confirm against the defaults, measured in turn (the first shapes
+        # measured run on a colder device, which favours later candidates)
+        a, b = [], []
+        for _ in range(2):
+            a.append(measure(gh, gfds, DEFAULTS, K, semantics, batched, flags, stream, reps)[0])
+            b.append(measure(gh, gfds, best, K, semantics, batched, flags, stream, reps)[0])
+        base_ms, best_ms = statistics.median(a), statistics.median(b)
+        tried.append({"confirm": {"default_ms": a, "tuned_ms": b}})
+        if not best_ms < base_ms * 0.98:
+            best, best_ms = dict(DEFAULTS), base_ms
     out = {"tuning": best, "tuned_ms": best_ms, "default_ms": base_ms, "tried": tried}
     cache[key] = out
     _save(path, cache)

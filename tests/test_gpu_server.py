@@ -101,7 +101,9 @@ def test_concurrent_submitters_and_wait_timeouts(P):
 @pytest.mark.timeout(900)
 def test_serving_full_size_against_stored_oracle(P):
     """Requests drawn from the 256-GFD pool on the 4M-vertex graph, served with
-    continuous batching; every result equals the stored oracle result."""
+    continuous batching; every result equals the stored oracle result, under
+    the default per-worker budget and under one small enough that admission
+    by estimated device bytes splits the queue into smaller batches."""
     with gzip.open(os.path.join(GOLDEN, "expected_kg_4m_batch256.json.gz"), "rt") as f:
         exp = json.load(f)
     g = configs.graph("kg_4m")
@@ -110,11 +112,22 @@ def test_serving_full_size_against_stored_oracle(P):
     ref = exp["results"]["induced"]
     rng = np.random.default_rng(4)
     gh = P.load(g)
-    srv = P.Server(gh, K=exp["K"], workers=2)
     reqs = _requests(rng, pool, 120)
-    ids = [srv.submit([pool[i] for i in r]) for r in reqs]
-    for rid, r in zip(ids, reqs):
-        got, _ = srv.wait(rid)
-        assert got == [ref[i] for i in r], r
-    srv.close()
+    batches = {}
+    # the default per-worker budget, then one so small that the estimated
+    # device bytes of a few requests fill it: the queue is then split into
+    # many smaller batches, with the same results
+    for budget in (0, 1 << 30):
+        srv = P.Server(gh, K=exp["K"], workers=1, mem_budget_bytes=budget)
+        ids = [srv.submit([pool[i] for i in r]) for r in reqs]
+        sizes = {}
+        for rid, r in zip(ids, reqs):
+            got, info = srv.wait(rid)
+            assert got == [ref[i] for i in r], (budget, r)
+            sizes[info["batch_id"]] = info["batch_gfds"]
+        srv.close()
+        batches[budget] = sizes
+    big, small = batches[0], batches[1 << 30]
+    assert len(small) > len(big), (len(small), len(big))
+    assert max(small.values()) < max(big.values()), (max(small.values()), max(big.values()))
     gh.free()
