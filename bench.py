@@ -11,11 +11,12 @@ also timed one at a time (256 sequential single-GFD calls) for the
 batched-vs-one-at-a-time ratio.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload kg_4m_batch256|kg_4m|powerlaw_1m|twitch_trio]
-    python bench.py --workload kg_4m_serving [--serve-seconds S]
+    python bench.py --workload kg_4m_serving [--serve-seconds S] [--serve-rates R1,R2,..]
 
 The serving workload replays Poisson arrivals (200 requests/s, each 1-4 GFDs
-of 3-8 vertices drawn from the 256-GFD pool) against gfd_server_* with
-continuous batching and reports p50/p99 latency beside throughput.
+of 3-8 vertices, taken in order from a pool of 4,000 walk-sampled GFDs)
+against gfd_server_* with continuous batching and reports p50/p99 latency
+beside throughput, then the same at each rate of a sweep of offered loads.
 """
 from __future__ import annotations
 
@@ -167,76 +168,85 @@ def unit_report(args, P, gh, gfds, stream, batched):
 
 
 def serve(args, torch, P, g, gh):
-    """Continuous-batching server under Poisson arrivals; every served result is
-    checked against the same GFD validated alone."""
+    """Continuous-batching server under Poisson arrivals, at the headline rate
+    and at each rate of a sweep; every served result is checked against the
+    same GFD validated alone."""
     import threading
     import numpy as np
     from synth import configs
-    pool = [{k: v for k, v in d.items() if k != "meta"} for d in configs.gfds("kg_4m_batch256", g)
-            if d["k"] >= 3]
-    rng = np.random.default_rng(4)
-    t, arrivals = 0.0, []
-    while True:
-        t += float(rng.exponential(1.0 / args.serve_rate))
-        if t >= args.serve_seconds:
-            break
-        arrivals.append((t, [int(i) for i in rng.integers(0, len(pool), int(rng.integers(1, 5)))]))
-    log(f"serving: {len(arrivals)} requests over {args.serve_seconds} s from a pool of {len(pool)}")
-    # each pool GFD alone (the reference for the served results)
-    alone = []
-    for d in pool:
-        q = P.PreparedCall(gh, [d], K=K_REPORT, semantics=args.semantics)
-        q.run(stats=False)
-        alone.append(q.results()[0])
-    srv = P.Server(gh, K=K_REPORT, semantics=args.semantics, workers=args.serve_workers)
-    for w in range(3):  # warm-up: workspaces and first launches
-        srv.wait(srv.submit([pool[i] for i in arrivals[w][1]]))
-    done = [None] * len(arrivals)
-    ids = [None] * len(arrivals)
-    ready = [threading.Event() for _ in arrivals]
+    pool = [{k: v for k, v in d.items() if k != "meta"} for d in configs.serving_pool(g)]
+    alone = {}  # pool index -> its result validated alone (one single-GFD call)
 
-    def waiter():
-        for j in range(len(arrivals)):
-            ready[j].wait()
-            done[j] = srv.wait(ids[j])
+    def alone_result(i):
+        if i not in alone:
+            q = P.PreparedCall(gh, [pool[i]], K=K_REPORT, semantics=args.semantics)
+            q.run(stats=False, flags=P.GFD_FLAG_NO_GRAPH)
+            alone[i] = q.results()[0]
+        return alone[i]
 
-    th = threading.Thread(target=waiter)
-    th.start()
-    t0 = time.perf_counter()
-    for j, (ta, req) in enumerate(arrivals):
-        dt = t0 + ta - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        ids[j] = srv.submit([pool[i] for i in req])
-        ready[j].set()
-    th.join()
-    srv.close()
-    lat = np.array([(info["done_ns"] - info["submit_ns"]) / 1e6 for _, info in done])
-    first = min(info["submit_ns"] for _, info in done)
-    last = max(info["done_ns"] for _, info in done)
-    wall = (last - first) / 1e9
-    ngfd = sum(len(req) for _, req in arrivals)
-    matches = 0
-    for (res, _), (_, req) in zip(done, arrivals):
-        assert res == [alone[i] for i in req], "a served result differs from the GFD alone"
-        matches += sum(r["match_count"] for r in res)
-    batches = {info["batch_id"]: info["batch_gfds"] for _, info in done}
-    out = {"metric": METRIC, "value": matches / wall, "unit": "embeddings/s", "n_gpus": 1,
-           "steps": len(arrivals), "warmup": 3, "ms_per_step": float(np.mean(lat)),
+    def run(rate, seconds, seed):
+        reqs = configs.serving_requests(g, rate=rate, duration_s=seconds, seed=seed, pool=pool)
+        # pool positions of each request's GFDs (taken in order, wrapping)
+        idx, at = [], 0
+        for r in reqs:
+            idx.append([(at + j) % len(pool) for j in range(len(r["gfds"]))])
+            at += len(r["gfds"])
+        srv = P.Server(gh, K=K_REPORT, semantics=args.semantics, workers=args.serve_workers)
+        for w in range(3):  # warm-up: workspaces and first launches
+            srv.wait(srv.submit(reqs[w]["gfds"]))
+        done = [None] * len(reqs)
+        ids = [None] * len(reqs)
+        ready = [threading.Event() for _ in reqs]
+
+        def waiter():
+            for j in range(len(reqs)):
+                ready[j].wait()
+                done[j] = srv.wait(ids[j])
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for j, r in enumerate(reqs):
+            dt = t0 + r["t"] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            ids[j] = srv.submit(r["gfds"])
+            ready[j].set()
+        th.join()
+        srv.close()
+        lat = np.array([(info["done_ns"] - info["submit_ns"]) / 1e6 for _, info in done])
+        wall = (max(i["done_ns"] for _, i in done) - min(i["submit_ns"] for _, i in done)) / 1e9
+        matches = 0
+        for (res, _), ix in zip(done, idx):
+            assert res == [alone_result(i) for i in ix], "a served result differs from the GFD alone"
+            matches += sum(r["match_count"] for r in res)
+        batches = {info["batch_id"]: info["batch_gfds"] for _, info in done}
+        ngfd = sum(len(x) for x in idx)
+        return {"rate_per_s": rate, "seconds": seconds, "requests": len(reqs), "gfds": ngfd,
+                "distinct_gfds": len({i for x in idx for i in x}),
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "max_ms": float(lat.max()), "gfds_per_s": ngfd / wall,
+                "embeddings_per_s": matches / wall, "batches": len(batches),
+                "mean_batch_gfds": float(np.mean(list(batches.values())))}
+
+    head = run(args.serve_rate, args.serve_seconds, 4)
+    log(f"serving at {args.serve_rate:g}/s: {head['requests']} requests, p50 {head['p50_ms']:.1f} ms, "
+        f"p99 {head['p99_ms']:.1f} ms, {head['gfds_per_s']:.0f} GFDs/s, {head['batches']} batches")
+    sweep = []
+    for k, rate in enumerate(args.serve_rates):
+        row = run(rate, args.sweep_seconds, 40 + k)
+        log(f"  offered {rate:g}/s: p50 {row['p50_ms']:.1f} ms, p99 {row['p99_ms']:.1f} ms, "
+            f"{row['gfds_per_s']:.0f} GFDs/s, mean batch {row['mean_batch_gfds']:.1f} GFDs")
+        sweep.append(row)
+    out = {"metric": METRIC, "value": head["embeddings_per_s"], "unit": "embeddings/s", "n_gpus": 1,
+           "steps": head["requests"], "warmup": 3, "ms_per_step": head["p50_ms"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-           "data": "synthetic", "gfds_per_s": ngfd / wall,
+           "data": "synthetic", "gfds_per_s": head["gfds_per_s"],
            "config": {"workload": "kg_4m_serving", "mode": "serving", "n": g.n, "m": g.m,
                       "rate_per_s": args.serve_rate, "seconds": args.serve_seconds,
-                      "semantics": args.semantics, "K": K_REPORT, "workers": args.serve_workers,
-                      "parallelism": "single_gpu"},
-           "serving": {"requests": len(arrivals), "gfds": ngfd, "p50_ms": float(np.percentile(lat, 50)),
-                       "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
-                       "batches": len(batches),
-                       "mean_batch_gfds": float(np.mean(list(batches.values()))),
-                       "identical_to_alone": True},
-           "roofline": None}
-    log(f"serving: p50 {out['serving']['p50_ms']:.1f} ms, p99 {out['serving']['p99_ms']:.1f} ms, "
-        f"{out['gfds_per_s']:.0f} GFDs/s, {len(batches)} batches")
+                      "pool_gfds": len(pool), "semantics": args.semantics, "K": K_REPORT,
+                      "workers": args.serve_workers, "parallelism": "single_gpu"},
+           "serving": dict(head, identical_to_alone=True), "sweep": sweep, "roofline": None}
     print(json.dumps(out), flush=True)
 
 
@@ -250,7 +260,11 @@ def main():
                     help="default: batched for the 256-GFD workload, plain otherwise")
     ap.add_argument("--semantics", default="induced", choices=["induced", "mono"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rates", type=lambda x: [float(v) for v in x.split(",") if v],
+                    default=[100.0, 400.0, 800.0, 1600.0, 3200.0],
+                    help="offered loads (requests/s) of the sweep after the headline rate")
+    ap.add_argument("--sweep-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--cpu-frac", type=float, default=None)

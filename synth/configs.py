@@ -196,19 +196,66 @@ def gfds_sha256(gl) -> str:
     return hashlib.sha256(json.dumps(strip, sort_keys=True).encode()).hexdigest()
 
 
-def serving_requests(g: Graph, rate: float = 200.0, duration_s: float = 60.0, seed: int = 4):
-    """Poisson arrivals; each request holds 1-4 GFDs of 3-8 vertices (walk sampled)."""
-    rng, spec = gfd_stream("kg_4m_serving")
+SERVING_POOL = 4000  # walk-sampled GFDs the serving requests draw from, in order
+SERVING_PARTS = 8    # independently seeded parts, sampled in parallel
+
+
+def _serving_part(part: int, n: int):
+    g = graph(CONFIG_GRAPH["kg_4m_serving"])
+    spec = GRAPHS[CONFIG_GRAPH["kg_4m_serving"]]
+    ss = np.random.SeedSequence(4).spawn(5)[4].spawn(SERVING_PARTS)[part]
+    rng = np.random.Generator(np.random.PCG64(ss))
     view = P.GraphView(g)
-    t, reqs = 0.0, []
+    return [P.sample_walk_gfd(rng, view, (3, 8), (1, 3), spec["attr_values"], spec["attr_zipf"],
+                              cyc_range=(0, 3)) for _ in range(n)]
+
+
+def serving_pool_path() -> str:
+    return os.path.join(FROZEN_DIR, "gfds_kg_4m_serving_pool.json.gz")
+
+
+def serving_pool(g: Graph | None = None, procs: int = SERVING_PARTS):
+    """SERVING_POOL walk-sampled GFDs (3-8 vertices, 1-3 literals, cyclomatic
+    number 0-3) on the serving graph: SERVING_PARTS parts of equal size, each
+    from its own seed.  Read from its frozen file when it matches the graph
+    (sampling takes minutes)."""
+    import gzip
+    if g is None:
+        g = graph(CONFIG_GRAPH["kg_4m_serving"])
+    path = serving_pool_path()
+    if os.path.exists(path):
+        with gzip.open(path, "rt") as f:
+            d = json.load(f)
+        if d.get("gen_version") == GEN_VERSION and d.get("graph_sha256") == g.sha256():
+            return d["gfds"]
+    from concurrent.futures import ProcessPoolExecutor
+    per = SERVING_POOL // SERVING_PARTS
+    with ProcessPoolExecutor(max_workers=procs) as ex:
+        parts = list(ex.map(_serving_part, range(SERVING_PARTS), [per] * SERVING_PARTS))
+    out = [d for part in parts for d in part]
+    os.makedirs(FROZEN_DIR, exist_ok=True)
+    with gzip.open(path + ".tmp", "wt") as f:
+        json.dump({"workload": "kg_4m_serving", "gen_version": GEN_VERSION,
+                   "graph_sha256": g.sha256(), "gfds": out}, f)
+    os.replace(path + ".tmp", path)
+    return out
+
+
+def serving_requests(g: Graph, rate: float = 200.0, duration_s: float = 60.0, seed: int = 4,
+                     pool=None, start: int = 0):
+    """Poisson arrivals of `rate` requests per second over `duration_s`; each
+    request holds 1-4 GFDs, taken in order from the walk-sampled serving pool
+    (from position `start`, wrapping around), so requests rarely repeat a GFD."""
+    rng = np.random.default_rng(seed)
+    pool = serving_pool(g) if pool is None else pool
+    t, reqs, at = 0.0, [], start
     while True:
         t += float(rng.exponential(1.0 / rate))
         if t >= duration_s:
             break
         nq = int(rng.integers(1, 5))
-        reqs.append({"t": t, "gfds": [
-            P.sample_walk_gfd(rng, view, (3, 8), (1, 3), spec["attr_values"], spec["attr_zipf"],
-                              cyc_range=(0, 3)) for _ in range(nq)]})
+        reqs.append({"t": t, "gfds": [pool[(at + j) % len(pool)] for j in range(nq)]})
+        at += nq
     return reqs
 
 
@@ -217,3 +264,5 @@ if __name__ == "__main__":
     if len(sys.argv) >= 3 and sys.argv[1] == "freeze":
         for nm in sys.argv[2:]:
             print(freeze(nm))
+    if len(sys.argv) >= 2 and sys.argv[1] == "serving-pool":
+        print(len(serving_pool()), serving_pool_path())
