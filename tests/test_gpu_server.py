@@ -131,3 +131,42 @@ def test_serving_full_size_against_stored_oracle(P):
     assert len(small) > len(big), (len(small), len(big))
     assert max(small.values()) < max(big.values()), (max(small.values()), max(big.values()))
     gh.free()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_serving_sampled_requests_against_oracle(P):
+    """Requests as the serving bench makes them (1-4 GFDs each, taken in order
+    from the pool of 4,000 walk-sampled GFDs): every served result equals the
+    same GFD validated alone, and the GFDs at every 100th pool position (a 1%
+    sample) equal the stored oracle results, in both readings."""
+    with open(os.path.join(GOLDEN, "expected_kg_4m_serving.json")) as f:
+        exp = json.load(f)
+    g = configs.graph("kg_4m")
+    assert g.sha256() == exp["graph_sha256"]
+    pool = [{k: v for k, v in d.items() if k != "meta"} for d in configs.serving_pool(g)]
+    stride = exp["pool_stride"]
+    assert [pool[i] for i in range(0, len(pool), stride)] == exp["gfds"]
+    reqs = configs.serving_requests(g, rate=200.0, duration_s=4.0, seed=4, pool=pool)
+    idx, at = [], 0
+    for r in reqs:
+        idx.append([(at + j) % len(pool) for j in range(len(r["gfds"]))])
+        at += len(r["gfds"])
+    gh = P.load(g)
+    for sem in ("induced", "mono"):
+        ref = exp["results"][sem]
+        srv = P.Server(gh, K=exp["K"], semantics=sem, workers=2)
+        ids = [srv.submit(r["gfds"]) for r in reqs]
+        served = {}
+        for rid, ix in zip(ids, idx):
+            got, _ = srv.wait(rid)
+            served.update(zip(ix, got))
+        srv.close()
+        sampled = [i for i in served if i % stride == 0]
+        assert len(sampled) >= 15, len(sampled)
+        for i in sampled:
+            assert served[i] == ref[i // stride], (sem, i)
+        if sem == "induced":
+            for i, r in served.items():
+                assert r == P.validate(gh, [pool[i]], K=exp["K"], semantics=sem)[0], i
+    gh.free()
