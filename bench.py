@@ -280,6 +280,9 @@ def main():
                          "(int32 negation) three times: the calibration run for HBM counters")
     ap.add_argument("--sources-sha256", action="store_true",
                     help="print the hash of the kernel sources that counter figures are keyed on")
+    ap.add_argument("--mem-budget", type=int, default=0, metavar="BYTES",
+                    help="device bytes a call may use for its workspace (0: the library's "
+                         "default); implies --no-tune")
     ap.add_argument("--no-tune", action="store_true",
                     help="run with the library's default launch shapes (no autotuning)")
     ap.add_argument("--units", action="store_true",
@@ -348,18 +351,19 @@ def main():
     # launch shapes: the autotuner's choice for this call shape (tried and
     # checked for identical results on this graph, or read from its cache)
     tuning, tune_info = None, None
-    if not args.no_tune:
+    if not args.no_tune and not args.mem_budget:
         from paper_2608_02321_amd import tune as T
         t = time.perf_counter()
         tune_info = T.tune(gh, gfds, g.sha256(), K=K, semantics=args.semantics, batched=batched,
                            count_only=args.count_only, stream=stream, log=log)
         tuning = tune_info["tuning"]
         gh.trim()  # the candidates' workspaces go: what is held is what the chosen shapes need
+        torch.cuda.empty_cache()  # and torch's allocator returns them to the device
         log(f"tuning: {tuning} ({'cached' if tune_info['cached'] else 'tuned'} in "
             f"{time.perf_counter() - t:.1f} s): {tune_info['tuned_ms']:.2f} ms against "
             f"{tune_info['default_ms']:.2f} ms with the defaults")
     pc = P.PreparedCall(gh, gfds, K=K, semantics=args.semantics, stream=stream,
-                        batched=batched, tuning=tuning)
+                        batched=batched, tuning=tuning, mem_budget_bytes=args.mem_budget)
 
     # warm-up (the first step captures the batch's main pass as a graph, later
     # ones replay it); the last warm-up step runs eagerly with events on every
@@ -515,7 +519,7 @@ def main():
            "data": "synthetic", "gfds_per_s": gfds_per_s, "matches_per_step": matches,
            "config": {"workload": args.workload, "mode": mode, "n": g.n, "m": g.m,
                       "gfds": len(gfds), "semantics": args.semantics, "K": K,
-                      "count_only": bool(args.count_only),
+                      "count_only": bool(args.count_only), "mem_budget_bytes": args.mem_budget,
                       "parallelism": "single_gpu"},
            "ms_per_step_median": statistics.median(step_ms), "ms_per_step_min": min(step_ms),
            "enumeration_embeddings_per_s": enum_rate,

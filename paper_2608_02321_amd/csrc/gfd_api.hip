@@ -737,7 +737,7 @@ extern "C" int32_t gfd_get_graph_info(const gfd_graph* g, gfd_graph_info* info) 
 }
 
 extern "C" const char* gfd_last_error(void) { return g_last_error.c_str(); }
-extern "C" int32_t gfd_version(void) { return 100; }
+extern "C" int32_t gfd_version(void) { return 200; }
 
 // ---------------------------------------------------------------------------
 // planner (host): Section IV-B -- root, spanning tree, core-first order
