@@ -207,8 +207,9 @@ typedef struct {
                                  violations up to a bound on the K-th smallest */
   int32_t threshold_passes;   /* such re-runs (one launch each for all those GFDs) */
   int32_t leaf_gfds;          /* GFDs whose last leaves were counted (GFD_FLAG_COUNT_ONLY) */
-  int32_t regrown_gfds;       /* GFDs run again in the fast path after the frontier pool or
-                                 the CPI entry arena grew to what their batch asked for */
+  int32_t regrown_gfds;       /* GFDs run again in the fast path: after the frontier pool or
+                                 the CPI entry arena grew to what their batch asked for,
+                                 or alone when a shared pool or arena was at its cap */
   int64_t front_pool_bytes;   /* frontier pool and CPI entry arena sizes after the call */
   int64_t cpi_arena_bytes;
   int32_t graph_captures;     /* batches whose main pass was captured as a graph */

@@ -2863,6 +2863,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     };
     uint64_t cpi_entries = 0;
     std::vector<char> retried(num_specs, 0);
+    std::vector<char> alone(num_specs, 0);  // ran again in a batch of its own
     // redo[x]: 1 the job runs again on the bounded path; 2 it runs again in a
     // later fast batch (the frontier pool or CPI arena it overflowed has grown)
     // the batches formed here run their main pass from captured graphs (not
@@ -2925,7 +2926,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         const bool grew_c = grow_cpi(ws, ws->hmisc[0]);
         const bool grew = grew_f || grew_c;
         std::vector<int> over;  // only the violation staging overflowed
-        std::vector<int> again;
+        std::vector<int> again, solo;
         for (size_t x = 0; x < jobs.size(); x++) {
           const uint64_t* h = ws->hctl + CTL_WORDS * x;
           std::memcpy(&H[(size_t)jobs[x].spec * CTL_WORDS], h, sizeof(uint64_t) * CTL_WORDS);
@@ -2936,6 +2937,13 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
               redo[x] = 2;
               retried[jobs[x].spec]++;
               again.push_back(jobs[x].spec);
+            } else if (jobs.size() > 1 && !alone[jobs[x].spec]) {
+              // the pool or arena is at its cap but was shared: alone, the
+              // job has all of it, which is usually enough (and much faster
+              // than the bounded path)
+              redo[x] = 2;
+              alone[jobs[x].spec] = 1;
+              solo.push_back(jobs[x].spec);
             } else {
               redo[x] = 1;
             }
@@ -2947,6 +2955,8 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
           batches.push_back(again);
           if (stats) stats->regrown_gfds += (int32_t)again.size();
         }
+        for (int sp : solo) batches.push_back({sp});
+        if (stats) stats->regrown_gfds += (int32_t)solo.size();
         // the last-level records of the jobs to re-run, as the device holds
         // them (their sources were placed by the frontier reservations)
         std::vector<ExtJob> lastrec(jobs.size());

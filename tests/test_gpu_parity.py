@@ -336,8 +336,9 @@ def test_full_size_configs(P, name):
 @pytest.mark.timeout(600)
 def test_full_size_batch_at_small_budgets(P):
     """The 256-GFD batch over the 4M/20M graph with the device budget cut to
-    1 GiB and 256 MiB: GFDs whose frontiers no longer fit are redone on the
-    bounded path, and every result still equals the oracle's."""
+    1 GiB and 256 MiB: GFDs whose frontiers or CPI lists no longer fit the
+    shared pool run again alone, and those that still do not fit on the
+    bounded path; every result still equals the oracle's."""
     exp = _expected("kg_4m_batch256")
     g = configs.graph(configs.CONFIG_GRAPH["kg_4m_batch256"])
     assert g.sha256() == exp["graph_sha256"], "generated graph differs from the stored one"
@@ -349,6 +350,7 @@ def test_full_size_batch_at_small_budgets(P):
         # largest GFDs' frontiers: those run on the bounded path
         if budget == 256 << 20:
             assert st["chunked_gfds"] > 0, budget
+        assert st["regrown_gfds"] > 0, budget
         for i, (r, e) in enumerate(zip(got, exp["results"]["induced"])):
             assert r == e, (budget, i)
     gh.free()
