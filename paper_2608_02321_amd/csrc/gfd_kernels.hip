@@ -771,9 +771,11 @@ struct ItemRun {
 
 // One thread per adjacency entry: mark constraint c of item i as met.
 // BITMAPS: every job of the launch records hits in bitmaps (hitmode 1), else
-// in bytes (hitmode 0); one instantiation per form keeps each lean.
+// in bytes (hitmode 0); one instantiation per form keeps each lean.  Both
+// forms keep 8 waves per SIMD (the bitmap form spills one value for it):
+// the pulls wait on scattered row and bitmap reads.
 template <bool BITMAPS>
-__global__ __launch_bounds__(BS) void k_filter_pull(DevGraph g, const FilterJob* __restrict__ jobs,
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_filter_pull(DevGraph g, const FilterJob* __restrict__ jobs,
                                                     int njobs, unsigned long long* bytes) {
   __shared__ LbsShared sh;
   __shared__ ChunkMap cm;

@@ -397,3 +397,38 @@ def test_disconnected_patterns(P):
                 (e["match_count"], e["violation_count"], 0), (i, sem)
     gh.free()
     gh2.free()
+
+
+def test_degenerate_graphs_and_calls(P):
+    """Graphs with no edges (one vertex, five vertices) and no attributes, an
+    empty GFD list, and GFDs with the most literals X and Y may hold."""
+    for n in (1, 5):
+        g = from_edge_list(n, [], [i % 2 for i in range(n)])
+        gfds = [{"k": 1, "vlabels": [0], "edges": [], "x": [], "y": [], "y_false": True},
+                {"k": 1, "vlabels": [-1], "edges": [], "x": [], "y": [], "y_false": False},
+                {"k": 2, "vlabels": [-1, -1], "edges": [], "x": [], "y": [], "y_false": True},
+                {"k": 2, "vlabels": [0, 1], "edges": [[0, 1, -1]], "x": [], "y": [],
+                 "y_false": True},
+                {"k": 3, "vlabels": [-1, 0, -1], "edges": [[2, 0, 0]], "x": [], "y": [],
+                 "y_false": True}]
+        gh = P.load(g)
+        for sem in SEMS:
+            for batched in (False, True):
+                _check(P, g, gfds, sem, K=8, gh=gh, batched=batched)
+        assert P.validate(gh, [], K=8) == []
+        gh.free()
+    g = random_graph(16, 300, 2400, n_vlabels=2, n_elabels=2, n_attrs=4, attr_values=3,
+                     absent_frac=0.1)
+    lit = lambda v, a, c: {"kind": "const", "var": v, "attr": a, "value": c}  # noqa: E731
+    var = lambda v, a, w, b: {"kind": "var", "var": v, "attr": a, "var2": w, "attr2": b}  # noqa: E731
+    many_x = [lit(i % 3, i % 4, i % 3) for i in range(7)] + [var(0, 0, 1, 0)]
+    many_y = [var(i % 3, i % 4, (i + 1) % 3, (i + 2) % 4) for i in range(8)]
+    gfds = [{"k": 3, "vlabels": [0, -1, 1], "edges": [[0, 1, -1], [1, 2, -1]], "x": many_x[:2],
+             "y": many_y, "y_false": False},
+            {"k": 3, "vlabels": [0, -1, 1], "edges": [[0, 1, -1], [1, 2, -1]],
+             "x": [lit(0, 0, 1)], "y": many_x, "y_false": False},
+            {"k": 2, "vlabels": [-1, -1], "edges": [[0, 1, -1]],
+             "x": [lit(i % 2, i % 4, i % 3) for i in range(7)] + [var(0, 0, 1, 0)], "y": [],
+             "y_false": True}]
+    for sem in SEMS:
+        _check(P, g, gfds, sem, K=32)

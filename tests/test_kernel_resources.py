@@ -2,9 +2,9 @@
 cross-compiles for gfx950 without a GPU).  No kernel may use per-lane scratch
 memory: a tuple held in a runtime-indexed private array ends up there, and
 every enumeration attempt then stores and reloads it through the memory
-hierarchy.  The one exception is the enumeration kernels' 8-wave form, whose
-registers are capped at 64 per lane on purpose (for graphs in HBM, more waves
-in flight pay for a few spilled values); its spills stay small.  The
+hierarchy.  The exceptions are the enumeration kernels' 8-wave form and the
+candidate pulls, whose registers are capped at 64 per lane on purpose (more
+waves in flight pay for a few spilled values); their spills stay small.  The
 enumeration kernels must also keep enough waves per SIMD to hide the latency
 of their random loads."""
 import os
@@ -49,8 +49,17 @@ def _eight_wave(name):
 
 def test_no_kernel_uses_scratch(report):
     bad = {k: v.get("ScratchSize [bytes/lane]") for k, v in report.items()
-           if v.get("ScratchSize [bytes/lane]") != "0" and not _eight_wave(k)}
+           if v.get("ScratchSize [bytes/lane]") != "0" and not _eight_wave(k)
+           and "k_filter_pull" not in k}
     assert not bad, bad
+
+
+def test_filter_pulls_keep_eight_waves(report):
+    pulls = {k: v for k, v in report.items() if "k_filter_pull" in k}
+    assert len(pulls) == 2, list(report)
+    for k, v in pulls.items():
+        assert int(v["Occupancy [waves/SIMD]"]) == 8, k
+        assert int(v["ScratchSize [bytes/lane]"]) <= 16, (k, v["ScratchSize [bytes/lane]"])
 
 
 def test_eight_wave_form_spills_little(report):
