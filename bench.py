@@ -167,31 +167,38 @@ def unit_report(args, P, gh, gfds, stream, batched):
     print(json.dumps(out), flush=True)
 
 
-def serve(args, torch, P, g, gh):
-    """Continuous-batching server under Poisson arrivals, at the headline rate
-    and at each rate of a sweep; every served result is checked against the
-    same GFD validated alone."""
-    import threading
-    import numpy as np
-    from synth import configs
-    pool = [{k: v for k, v in d.items() if k != "meta"} for d in configs.serving_pool(g)]
-    alone = {}  # pool index -> its result validated alone (one single-GFD call)
+class ServingRig:
+    """Poisson arrivals of requests (1-4 GFDs each, taken in order from the
+    4,000-GFD walk-sampled pool) against gfd_server_* with continuous
+    batching; every served result is checked against the same GFD validated
+    alone (one single-GFD call, cached per pool position)."""
 
-    def alone_result(i):
-        if i not in alone:
-            q = P.PreparedCall(gh, [pool[i]], K=K_REPORT, semantics=args.semantics)
-            q.run(stats=False, flags=P.GFD_FLAG_NO_GRAPH)
-            alone[i] = q.results()[0]
-        return alone[i]
+    def __init__(self, P, g, gh, semantics, workers):
+        from synth import configs
+        self.P, self.g, self.gh, self.semantics, self.workers = P, g, gh, semantics, workers
+        self.configs = configs
+        self.pool = [{k: v for k, v in d.items() if k != "meta"} for d in configs.serving_pool(g)]
+        self.alone = {}
 
-    def run(rate, seconds, seed):
-        reqs = configs.serving_requests(g, rate=rate, duration_s=seconds, seed=seed, pool=pool)
+    def alone_result(self, i):
+        if i not in self.alone:
+            q = self.P.PreparedCall(self.gh, [self.pool[i]], K=K_REPORT, semantics=self.semantics)
+            q.run(stats=False, flags=self.P.GFD_FLAG_NO_GRAPH)
+            self.alone[i] = q.results()[0]
+        return self.alone[i]
+
+    def run(self, rate, seconds, seed):
+        import threading
+        import numpy as np
+        P, pool = self.P, self.pool
+        reqs = self.configs.serving_requests(self.g, rate=rate, duration_s=seconds, seed=seed,
+                                             pool=pool)
         # pool positions of each request's GFDs (taken in order, wrapping)
         idx, at = [], 0
         for r in reqs:
             idx.append([(at + j) % len(pool) for j in range(len(r["gfds"]))])
             at += len(r["gfds"])
-        srv = P.Server(gh, K=K_REPORT, semantics=args.semantics, workers=args.serve_workers)
+        srv = P.Server(self.gh, K=K_REPORT, semantics=self.semantics, workers=self.workers)
         for w in range(3):  # warm-up: workspaces and first launches
             srv.wait(srv.submit(reqs[w]["gfds"]))
         done = [None] * len(reqs)
@@ -218,7 +225,7 @@ def serve(args, torch, P, g, gh):
         wall = (max(i["done_ns"] for _, i in done) - min(i["submit_ns"] for _, i in done)) / 1e9
         matches = 0
         for (res, _), ix in zip(done, idx):
-            assert res == [alone_result(i) for i in ix], "a served result differs from the GFD alone"
+            assert res == [self.alone_result(i) for i in ix], "a served result differs from the GFD alone"
             matches += sum(r["match_count"] for r in res)
         batches = {info["batch_id"]: info["batch_gfds"] for _, info in done}
         ngfd = sum(len(x) for x in idx)
@@ -227,14 +234,19 @@ def serve(args, torch, P, g, gh):
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "max_ms": float(lat.max()), "gfds_per_s": ngfd / wall,
                 "embeddings_per_s": matches / wall, "batches": len(batches),
-                "mean_batch_gfds": float(np.mean(list(batches.values())))}
+                "mean_batch_gfds": float(np.mean(list(batches.values()))),
+                "workers": self.workers, "identical_to_alone": True}
 
-    head = run(args.serve_rate, args.serve_seconds, 4)
+
+def serve(args, torch, P, g, gh):
+    """The serving workload: the headline rate, then each rate of a sweep."""
+    rig = ServingRig(P, g, gh, args.semantics, args.serve_workers)
+    head = rig.run(args.serve_rate, args.serve_seconds, 4)
     log(f"serving at {args.serve_rate:g}/s: {head['requests']} requests, p50 {head['p50_ms']:.1f} ms, "
         f"p99 {head['p99_ms']:.1f} ms, {head['gfds_per_s']:.0f} GFDs/s, {head['batches']} batches")
     sweep = []
     for k, rate in enumerate(args.serve_rates):
-        row = run(rate, args.sweep_seconds, 40 + k)
+        row = rig.run(rate, args.sweep_seconds, 40 + k)
         log(f"  offered {rate:g}/s: p50 {row['p50_ms']:.1f} ms, p99 {row['p99_ms']:.1f} ms, "
             f"{row['gfds_per_s']:.0f} GFDs/s, mean batch {row['mean_batch_gfds']:.1f} GFDs")
         sweep.append(row)
@@ -244,9 +256,9 @@ def serve(args, torch, P, g, gh):
            "data": "synthetic", "gfds_per_s": head["gfds_per_s"],
            "config": {"workload": "kg_4m_serving", "mode": "serving", "n": g.n, "m": g.m,
                       "rate_per_s": args.serve_rate, "seconds": args.serve_seconds,
-                      "pool_gfds": len(pool), "semantics": args.semantics, "K": K_REPORT,
+                      "pool_gfds": len(rig.pool), "semantics": args.semantics, "K": K_REPORT,
                       "workers": args.serve_workers, "parallelism": "single_gpu"},
-           "serving": dict(head, identical_to_alone=True), "sweep": sweep, "roofline": None}
+           "serving": head, "sweep": sweep, "roofline": None}
     print(json.dumps(out), flush=True)
 
 
@@ -265,6 +277,9 @@ def main():
                     default=[100.0, 400.0, 800.0, 1600.0, 3200.0],
                     help="offered loads (requests/s) of the sweep after the headline rate")
     ap.add_argument("--sweep-seconds", type=float, default=3.0)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the short serving leg of the default workload")
+    ap.add_argument("--serving-leg-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--cpu-frac", type=float, default=None)
@@ -490,6 +505,16 @@ def main():
                 f"cand={s1['cpi_candidates']} cpi={s1['cpi_entries']} chunked={s1['chunked_gfds']} "
                 f"thr={s1['threshold_gfds']}/{s1['threshold_passes']} | {cm}")
 
+    # the serving form on the same graph, briefly (the kg_4m_serving workload
+    # runs it at length and sweeps the offered load)
+    serving = None
+    if args.workload == "kg_4m_batch256" and not args.no_serving and not args.count_only:
+        rig = ServingRig(P, g, gh, args.semantics, args.serve_workers)
+        serving = rig.run(args.serve_rate, args.serving_leg_seconds, 4)
+        log(f"serving leg at {args.serve_rate:g}/s: {serving['requests']} requests, "
+            f"p50 {serving['p50_ms']:.1f} ms, p99 {serving['p99_ms']:.1f} ms, "
+            f"{serving['gfds_per_s']:.0f} GFDs/s")
+
     compare = None
     if batched and not args.no_compare:
         # the same GFDs, one gfd_validate call each (one-at-a-time), marshalled
@@ -524,7 +549,7 @@ def main():
            "ms_per_step_median": statistics.median(step_ms), "ms_per_step_min": min(step_ms),
            "enumeration_embeddings_per_s": enum_rate,
            "device_bytes": {"graph": gh.info["device_bytes"], "held": held_bytes},
-           "load_s": load_s, "roofline": roofline, "compare": compare,
+           "load_s": load_s, "roofline": roofline, "compare": compare, "serving": serving,
            "tuning": None if tune_info is None else {
                "choice": tuning, "cached": tune_info["cached"],
                "tuned_ms_per_step": ms_per_step,

@@ -80,3 +80,42 @@ def test_enumeration_occupancy(report):
     assert len(ext) == 6, list(report)
     for k, occ in ext.items():
         assert occ >= 4, (k, occ)
+
+
+FLOAT2_SAMPLE = r"""
+#include <hip/hip_runtime.h>
+__global__ void axpy2(const float2* __restrict__ x, float2* __restrict__ y, float a, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float2 v = x[i], w = y[i];
+    w.x = a * v.x + w.x; w.y = a * v.y + w.y; w.x += v.y; w.y *= v.x;
+    y[i] = w;
+  }
+}
+"""
+PACKED_F32 = re.compile(r"\bv_pk_(fma|add|mul)_f32\b")
+
+
+def _device_asm(src, flags, out):
+    r = subprocess.run([B.HIPCC, *flags, "--cuda-device-only", "-S", str(src), "-o", str(out)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    return out.read_text()
+
+
+def test_packed_fp32_ops_are_off(tmp_path):
+    """The build's target-feature flag keeps packed FP32 instructions out of
+    device code: a float2 kernel compiled with the library's flags has none,
+    the same kernel without the flag has them, and the library's kernels have
+    none."""
+    if not shutil.which(B.HIPCC) and not os.path.exists(B.HIPCC):
+        pytest.skip("hipcc not available")
+    src = tmp_path / "f2.hip"
+    src.write_text(FLOAT2_SAMPLE)
+    flags = [f for f in B.FLAGS if f != "-Wall"]
+    i = flags.index("-packed-fp32-ops")
+    plain = flags[:i - 3] + flags[i + 1:]  # without -Xclang -target-feature -Xclang -packed-fp32-ops
+    assert len(plain) == len(flags) - 4
+    assert not PACKED_F32.search(_device_asm(src, flags, tmp_path / "with_flag.s"))
+    assert PACKED_F32.search(_device_asm(src, plain, tmp_path / "without_flag.s"))
+    assert not PACKED_F32.search(_device_asm(KERNELS, flags, tmp_path / "kernels.s"))
