@@ -150,3 +150,16 @@ def test_frontier_pool_grows_to_the_batch(P):
     assert st2["front_pool_bytes"] == st["front_pool_bytes"]
     gh.free()
     assert ta.live_bytes == 0
+
+
+def test_budget_below_the_minimum_is_enomem(P):
+    """A memory budget below 64 MiB is refused with GFD_ENOMEM before any
+    launch, and the graph serves the next call exactly."""
+    g, gfds = _case(23)
+    gh = P.load(g)
+    with pytest.raises(P.GfdError) as ei:
+        P.validate(gh, gfds, K=16, batched=True, mem_budget_bytes=32 << 20)
+    assert ei.value.code == -2 and "64 MiB" in P.last_error()  # GFD_ENOMEM
+    got = P.validate(gh, gfds, K=16, batched=True, mem_budget_bytes=64 << 20)
+    assert got == _oracle(g, gfds, "induced", 16)
+    gh.free()
