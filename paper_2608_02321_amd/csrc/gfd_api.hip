@@ -2599,9 +2599,10 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     // the jobs whose collection now fits get their first K (sorted, or flagged
     // for the radix select)
     c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)(ws->jobrec + bt), (int)T.size()); });
-    for (int x : over)
-      HIPCHK(hipMemcpyAsync(ws->hctl + CTL_WORDS * x, jobs[x].mem.ctl, sizeof(uint64_t) * CTL_WORDS,
-                            hipMemcpyDeviceToHost, c.st));
+    // the batch's control blocks are contiguous: one copy (the other jobs'
+    // words are unchanged since the main pass's read-back)
+    HIPCHK(hipMemcpyAsync(ws->hctl, jobs[0].mem.ctl, sizeof(uint64_t) * CTL_WORDS * jobs.size(),
+                          hipMemcpyDeviceToHost, c.st));
     while_busy();
     HIPCHK(hipStreamSynchronize(c.st));
     if (c.stats) c.stats->threshold_passes++;
@@ -2961,10 +2962,24 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         // them (their sources were placed by the frontier reservations)
         std::vector<ExtJob> lastrec(jobs.size());
         if (!over.empty()) {
-          for (int x : over)
-            HIPCHK(hipMemcpyAsync(&lastrec[x], recbase + jobs[x].last_rec, sizeof(ExtJob),
-                                  hipMemcpyDeviceToHost, c.st));
-          HIPCHK(hipStreamSynchronize(c.st));
+          static_assert(sizeof(ExtJob) % 8 == 0, "records are copied as 8-byte words");
+          if (ws->hjobrec_dev && ws->hjobrec_bytes >= sizeof(ExtJob) * over.size()) {
+            // one gather launch into the mapped staging (the main pass is
+            // done with it) instead of a small DMA copy per job
+            RecGather gr{};
+            gr.n = (int32_t)over.size();
+            gr.words = (uint32_t)(sizeof(ExtJob) / 8);
+            for (size_t i = 0; i < over.size(); i++) gr.off[i] = jobs[over[i]].last_rec;
+            gather_recs(c.st, recbase, gr, (uint64_t*)ws->hjobrec_dev);
+            HIPCHK(hipStreamSynchronize(c.st));
+            for (size_t i = 0; i < over.size(); i++)
+              std::memcpy(&lastrec[over[i]], ws->hjobrec + i * sizeof(ExtJob), sizeof(ExtJob));
+          } else {
+            for (int x : over)
+              HIPCHK(hipMemcpyAsync(&lastrec[x], recbase + jobs[x].last_rec, sizeof(ExtJob),
+                                    hipMemcpyDeviceToHost, c.st));
+            HIPCHK(hipStreamSynchronize(c.st));
+          }
         }
         // jobs whose first K the last level's sort already wrote go out now
         std::unique_ptr<ResultDrain> D;

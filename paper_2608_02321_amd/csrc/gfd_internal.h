@@ -402,6 +402,15 @@ void topk_small(hipStream_t st, const TopkJob* jobs, int njobs);
 
 // n 8-byte words from src (mapped pinned host memory) to dst (device memory)
 void copy_words(hipStream_t st, const uint64_t* src, uint64_t* dst, uint64_t n);
+// Records of `words` 8-byte words at base + off[r], r < n, back to back into
+// dst (which may be mapped host memory): one launch for what would be n
+// small device-to-host copies.
+struct RecGather {
+  uint64_t off[MAX_JOBS];
+  int32_t n;
+  uint32_t words;
+};
+void gather_recs(hipStream_t st, const uint8_t* base, const RecGather& g, uint64_t* dst);
 
 // One job's reported tuples: `words` int32 from `src`, packed at word `dst`.
 struct PackJob {

@@ -1653,6 +1653,19 @@ void copy_words(hipStream_t st, const uint64_t* src, uint64_t* dst, uint64_t n) 
   hipLaunchKernelGGL(k_copy_words, dim3((unsigned)(b > 64 ? 64 : b)), dim3(BS), 0, st, src, dst, n);
 }
 
+__global__ __launch_bounds__(BS) void k_gather_recs(const uint8_t* __restrict__ base, RecGather g,
+                                                    uint64_t* __restrict__ dst) {
+  for (int r = blockIdx.x; r < g.n; r += gridDim.x) {
+    const uint64_t* src = (const uint64_t*)(base + g.off[r]);
+    for (uint32_t w = threadIdx.x; w < g.words; w += BS) dst[(uint64_t)r * g.words + w] = src[w];
+  }
+}
+
+void gather_recs(hipStream_t st, const uint8_t* base, const RecGather& g, uint64_t* dst) {
+  if (g.n <= 0) return;
+  hipLaunchKernelGGL(k_gather_recs, dim3((unsigned)g.n), dim3(BS), 0, st, base, g, dst);
+}
+
 // Reported tuples of a batch's jobs, back to back, for one copy to the host.
 __global__ __launch_bounds__(BS) void k_pack_results(const PackJob* __restrict__ jobs,
                                                      int32_t* __restrict__ out) {
