@@ -257,6 +257,10 @@ struct Workspace {
   std::vector<GraphEntry*> graphs;
   hipStream_t cap_stream = nullptr;
   std::deque<size_t> seen;          // hashes of batch shapes run once (captured on the second run)
+  // the last call's plans and batches, reused by a call with the same GFDs and
+  // options (validating one set again and again): planning is host time the
+  // GPU waits through at the start of every call
+  std::shared_ptr<struct PlanMemo> memo;
 
   ~Workspace() {
     drop_graphs(this);
@@ -1077,6 +1081,17 @@ struct Job {
   int cur[MAXK];  // which candidate buffer holds C(u) at the current step
   size_t last_rec = SIZE_MAX;  // offset of its last-level record in the batch's records
   bool last_single = false;    // that record is a single-vertex (k == 1) one
+};
+
+// A call's plans, capacities and batches, with what they depend on besides
+// the graph: the GFDs and (reading, counts only, staging per job, budget,
+// batch size).
+struct PlanMemo {
+  std::vector<gfd_spec> specs;
+  uint64_t key[5] = {};
+  std::vector<Job> all;
+  std::vector<std::vector<int>> batches;
+  double est = 0;  // frontier bytes estimated for the call's GFDs
 };
 
 // Data edges of the label block (bucket L, edge label e, far end's label
@@ -2159,16 +2174,17 @@ static void drop_graphs(Workspace* ws) {
 // What the main pass of a batch depends on besides the buffers' generation:
 // the GFDs, the reading, K, the staging and frontier limits, the pool and
 // arena shares and whether class bytes are counted.
-static std::string graph_key(const Ctx& c, const std::vector<Job>& jobs, const gfd_spec* specs,
+static std::string graph_key(const Ctx& c, const std::vector<int>& batch, const gfd_spec* specs,
                              bool count_only, uint64_t vsmall) {
   std::string k;
   auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
   const uint64_t w[] = {(uint64_t)c.K, (uint64_t)c.induced, (uint64_t)count_only, c.front_limit, vsmall,
                         (uint64_t)c.tune.flat_grid, (uint64_t)c.tune.scan_grid, (uint64_t)use_ahead(c), (uint64_t)use_occ8(c),
                         front_usable(c.ws), cpi_usable(c.ws), (uint64_t)(c.stat_bytes != nullptr),
-                        (uint64_t)jobs.size()};
+                        (uint64_t)batch.size()};
+  k.reserve(sizeof w + sizeof(gfd_spec) * batch.size());
   put(w, sizeof w);
-  for (const Job& J : jobs) put(&specs[J.spec], sizeof(gfd_spec));
+  for (int i : batch) put(&specs[i], sizeof(gfd_spec));
   return k;
 }
 
@@ -2822,39 +2838,50 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
       units_clear(c.st);
     }
     fill_u32(c.st, ws->err, 0u, 1);
-    // plans, capacities and batches
+    // plans, capacities and batches (those of the last call on this
+    // workspace when it had the same GFDs and options)
     std::optional<Range> phase(std::in_place, "plan");
-    std::vector<Job> all(num_specs);
-    for (int32_t i = 0; i < num_specs; i++) {
-      all[i].spec = i;
-      make_plan(g, specs[i], c.induced, all[i].plan);
-      plan_leaves(specs[i], c.induced, count_only, all[i].plan);
-      job_caps(g, all[i].plan, 0, vsmall, false, all[i].caps);
-    }
-    {
-      // a fresh pool is sized by the frontier estimate of the call's GFDs (at
-      // most 1 GiB); it grows from there to what batches ask for
-      double est = 0;
-      for (int32_t i = 0; i < num_specs; i++) est += (double)est_front_bytes(g, all[i].plan);
-      const double cap = (double)std::min<int64_t>(budget / 4, int64_t(1) << 30);
-      ws->front_want = std::max(ws->front_want, (size_t)std::min(est * 1.25, cap));
-    }
-    std::vector<std::vector<int>> batches;
-    {
+    const uint64_t mkey[5] = {(uint64_t)c.induced, (uint64_t)count_only, vsmall, (uint64_t)budget,
+                              (uint64_t)max_batch};
+    PlanMemo* pm = ws->memo.get();
+    if (!(pm && pm->specs.size() == (size_t)num_specs && !std::memcmp(pm->key, mkey, sizeof mkey) &&
+          !std::memcmp(pm->specs.data(), specs, sizeof(gfd_spec) * (size_t)num_specs))) {
+      auto m = std::make_shared<PlanMemo>();
+      m->all.resize(num_specs);
+      for (int32_t i = 0; i < num_specs; i++) {
+        Job& J = m->all[i];
+        J.spec = i;
+        make_plan(g, specs[i], c.induced, J.plan);
+        plan_leaves(specs[i], c.induced, count_only, J.plan);
+        job_caps(g, J.plan, 0, vsmall, false, J.caps);
+        m->est += (double)est_front_bytes(g, J.plan);
+      }
       std::vector<int> cur;
       int64_t used = 0;
       for (int32_t i = 0; i < num_specs; i++) {
-        const int64_t b = (int64_t)all[i].caps.bytes + 4096 * CTL_WORDS;
+        const int64_t b = (int64_t)m->all[i].caps.bytes + 4096 * CTL_WORDS;
         if (!cur.empty() && ((int)cur.size() >= max_batch || used + b > budget)) {
-          batches.push_back(cur);
+          m->batches.push_back(cur);
           cur.clear();
           used = 0;
         }
         cur.push_back(i);
         used += b;
       }
-      if (!cur.empty()) batches.push_back(cur);
+      if (!cur.empty()) m->batches.push_back(cur);
+      m->specs.assign(specs, specs + num_specs);
+      std::memcpy(m->key, mkey, sizeof mkey);
+      ws->memo = m;
+      pm = m.get();
     }
+    const std::vector<Job>& all = pm->all;
+    {
+      // a fresh pool is sized by the frontier estimate of the call's GFDs (at
+      // most 1 GiB); it grows from there to what batches ask for
+      const double cap = (double)std::min<int64_t>(budget / 4, int64_t(1) << 30);
+      ws->front_want = std::max(ws->front_want, (size_t)std::min(pm->est * 1.25, cap));
+    }
+    std::vector<std::vector<int>> batches = pm->batches;
     const bool force_bounded = (o.flags & GFD_FLAG_FORCE_CHUNKED) != 0;
     std::vector<uint64_t> H((size_t)num_specs * CTL_WORDS);
     // first K of GFD i, straight into results[i].violations (counts come
@@ -2874,25 +2901,35 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     phase.reset();
     for (size_t bi = 0; bi < batches.size(); bi++) {
       const Range batch_range("batch");
-      std::vector<Job> jobs;
-      for (int i : batches[bi]) jobs.push_back(all[i]);
       rewind_area(ws);
       const bool graph = use_graphs && bi < n_planned;
-      const size_t zero_bytes = layout_batch(c, jobs, !graph);
+      // a batch whose main pass was captured replays it with the plans,
+      // records and buffers it was captured with: no layout, no records
+      GraphEntry* e = nullptr;
+      std::string key;
+      if (graph) {
+        const Range lookup_range("graph lookup");
+        key = graph_key(c, batches[bi], specs, count_only, vsmall);
+        e = find_graph(ws, key);
+      }
+      std::vector<Job> jobs;
+      size_t zero_bytes = 0;
+      if (e) {
+        jobs = e->jobs;
+        for (size_t x = 0; x < jobs.size(); x++) jobs[x].spec = batches[bi][x];
+        for (int j = 0; j < 8; j++) c.tm.launches[j] += e->launches[j];
+        if (stats) stats->graph_replays++;
+      } else {
+        const Range layout_range("layout");
+        for (int i : batches[bi]) jobs.push_back(all[i]);
+        zero_bytes = layout_batch(c, jobs, !graph);
+      }
       std::vector<char> redo(jobs.size(), force_bounded ? 1 : 0);
       if (!force_bounded) {
-        GraphEntry* e = nullptr;
-        if (graph) {
+        if (graph && !e) {
           // a shape seen once before is captured now; one seen for the first
           // time runs eagerly (most shapes of a serving mix never repeat)
-          std::string key = graph_key(c, jobs, specs, count_only, vsmall);
-          e = find_graph(ws, key);
-          if (e) {  // the same plans, records and buffers as when it was captured
-            jobs = e->jobs;
-            for (size_t x = 0; x < jobs.size(); x++) jobs[x].spec = batches[bi][x];
-            for (int j = 0; j < 8; j++) c.tm.launches[j] += e->launches[j];
-            if (stats) stats->graph_replays++;
-          } else {
+          {
             const size_t h = std::hash<std::string>()(key);
             if (std::find(ws->seen.begin(), ws->seen.end(), h) != ws->seen.end()) {
               e = capture_batch(c, jobs, zero_bytes, std::move(key));
