@@ -36,6 +36,11 @@ def test_replays_equal_eager_and_oracle(P):
     og = O.OracleGraph(g)
     gh = P.load(g)
     batch, other = _gfds(41, 24), _gfds(42, 6)
+    # patterns of two components (a cross-product level) in the captured pass
+    batch += [{"k": 3, "vlabels": [0, 1, 1], "edges": [[1, 2, 0]], "x": [],
+               "y": [{"kind": "var", "var": 0, "attr": 0, "var2": 2, "attr2": 0}], "y_false": False},
+              {"k": 2, "vlabels": [0, 1], "edges": [],
+               "x": [{"kind": "const", "var": 0, "attr": 1, "value": 2}], "y": [], "y_false": True}]
     cases = [dict(K=64, semantics="induced", batched=True),
              dict(K=64, semantics="mono", batched=True),
              dict(K=16, semantics="induced", batched=True, violation_cap=40),   # threshold re-runs
