@@ -172,7 +172,9 @@ typedef struct {
  * pattern whose matching order ends in up to 3 leaves with one parent, equal
  * labels and edges, and literals on themselves alone has those leaves counted
  * per partial match (inclusion-exclusion over their candidate lists) instead
- * of enumerated: the leaf postponement of CFL-Match that Section IV-B adopts. */
+ * of enumerated: the leaf postponement of CFL-Match that Section IV-B adopts.
+ * Two last leaves under different parents are counted together too: the
+ * product of their lists' sizes less the vertices both lists hold. */
 #define GFD_FLAG_COUNT_ONLY 4
 /* Run every launch eagerly.  By default a batch's main pass (its clears, the
  * candidate filter, CPI construction, enumeration with the literal check and
@@ -224,6 +226,8 @@ typedef struct {
    * over their rows, [12] matches, [13] attribute values read by literals,
    * [14] violations, [15] inner-level attempts */
   uint64_t units[16];
+  int32_t leaf_split_gfds;    /* of leaf_gfds, those whose last two leaves hang from different
+                                 parents (counted as list products less shared vertices) */
 } gfd_stats;
 
 /* Load a graph given as out-CSR, in host memory or (opts->mem_kind ==

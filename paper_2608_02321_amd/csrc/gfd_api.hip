@@ -770,6 +770,10 @@ struct Plan {
   // matching order are counted, not enumerated; k_enum vertices are enumerated
   int leaf_r = 0, k_enum = 0, leaf_par = -1;
   int32_t lit_leaf[2 * MAXLIT];
+  // two leaves under different parents (leaf_r == 2): order[k-2] (slot 0,
+  // parent leaf_par2) and order[k-1] (slot 1, parent leaf_par)
+  bool leaf_split = false;
+  int leaf_par2 = -1;
 };
 
 static int32_t pair_code(const Plan& p, int a, int b, bool induced) {
@@ -1071,6 +1075,7 @@ struct JobMem {
   uint64_t* tstate;
   int32_t* res;
   uint32_t* leaf_cnt;  // leaf postponement: [|C(parent)| * LEAF_WORDS]
+  uint32_t* leaf_cnt2;  // split leaves: the same for the other leaf's parent
 };
 
 struct Job {
@@ -1173,6 +1178,7 @@ static void job_caps(const gfd_graph* g, const Plan& p, uint64_t cap_f, uint64_t
   b += align_up(4 * c.begs);
   b += align_up(4 * c.vcap * k);
   if (p.leaf_r) b += align_up(4ull * LEAF_WORDS * c.lcap_u[p.leaf_par]);
+  if (p.leaf_split) b += align_up(4ull * LEAF_WORDS * c.lcap_u[p.leaf_par2]);
   c.bytes = b;
 }
 
@@ -1211,6 +1217,7 @@ static void job_layout(uint8_t* base, const gfd_graph* g, const Plan& p, const J
   m.begs = (uint32_t*)take(4 * c.begs);
   m.vbuf = (int32_t*)take(4 * c.vcap * k);
   m.leaf_cnt = p.leaf_r ? (uint32_t*)take(4ull * LEAF_WORDS * c.lcap_u[p.leaf_par]) : nullptr;
+  m.leaf_cnt2 = p.leaf_split ? (uint32_t*)take(4ull * LEAF_WORDS * c.lcap_u[p.leaf_par2]) : nullptr;
 }
 
 struct Ctx {
@@ -1450,6 +1457,7 @@ struct Launch {
   bool cpi_two_pass = false;  // CPI: count kept entries first (the bounded path)
   size_t next_off = SIZE_MAX;  // enumeration: the next level's records (frontier reservation)
   size_t leaf_off = SIZE_MAX;  // enumeration: the leaf-count records, if any
+  size_t prep2_off = SIZE_MAX; // leaf counts: the records that fill split leaves' second tables
 };
 
 // The launches of a batch in order.  When on_add is set (the fast path), it
@@ -1631,8 +1639,8 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
   // the first level is enqueued: an inner level's frontier reservation
   // writes the next level's records on the device.
   std::vector<std::vector<ExtJob>> E(maxk);
-  std::vector<LeafJob> F(nj);
-  bool any_leaf = false;
+  std::vector<LeafJob> F(nj), F2(nj);
+  bool any_leaf = false, any_split = false;
   uint64_t leaf_np = 1;
   for (int i = 1; i < maxk; i++) {
     E[i].resize(nj);
@@ -1748,10 +1756,54 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
     f.flags = (uint32_t*)(J.mem.ctl + CTL_FLAGS);
     leaf_np = std::max(leaf_np, f.cap_p);
     any_leaf = true;
+    if (p.leaf_split) {
+      // this record counts the last leaf (slot 1 of the plan) as a leaf of its
+      // own; F2 fills the table of the other (slot 0) under its parent
+      const int ua = p.order[p.k - 2], q2 = p.leaf_par2;
+      f.r = 1;
+      for (int t = 0; t < 2 * MAXLIT; t++) {
+        f.lit_leaf[t] = p.lit_leaf[t] == 1 ? 0 : -1;
+        f.lit_leaf2[t] = p.lit_leaf[t] == 0 ? 0 : -1;
+      }
+      f.split = 1;
+      f.par2_pos = p.pos[q2];
+      f.par2_posmap = J.mem.pos[q2];
+      f.par2_by_bucket = p.qlab[q2] != ANY ? 1 : 0;
+      f.cpi2_beg = J.mem.cpi_beg[ua];
+      f.cpi2_len = J.mem.cpi_len[ua];
+      f.u2 = cand_set(J, ua);
+      f.dir2 = p.adj_dir[ua];
+      f.prim2 = p.adj_prim[ua];
+      f.other2 = p.adj_other[ua];
+      f.cnt2 = J.mem.leaf_cnt2;
+      LeafJob& f2 = F2[x];
+      f2 = LeafJob{};
+      f2.active = 1;
+      f2.i = f.i;
+      f2.r = 1;
+      const CandSet pc2 = cand_set(J, q2);
+      f2.d_np = pc2.cnt;
+      f2.cap_p = J.caps.lcap_u[q2];
+      f2.cpi_beg = J.mem.cpi_beg[ua];
+      f2.cpi_len = J.mem.cpi_len[ua];
+      f2.cpi_ent = c.ws->cpi_arena;
+      f2.u = f.u2;
+      f2.cnt = J.mem.leaf_cnt2;
+      f2.nx = p.nx;
+      f2.ny = p.ny;
+      f2.y_false = p.y_false;
+      for (int t = 0; t < 2 * MAXLIT; t++) {
+        f2.lit[t] = p.lit[t];
+        f2.lit_leaf[t] = f.lit_leaf2[t];
+      }
+      leaf_np = std::max(leaf_np, f2.cap_p);
+      any_split = true;
+    }
   }
   std::vector<size_t> eoff(maxk, SIZE_MAX);
   for (int i = 1; i < maxk; i++) eoff[i] = R.add(E[i]);
   const size_t leaf_off = any_leaf ? R.add(F) : SIZE_MAX;
+  const size_t prep2_off = any_split ? R.add(F2) : SIZE_MAX;
   for (int i = 1; i < maxk; i++) {
     bool any_last = false, any_inner = false;
     for (int x = 0; x < nj; x++) {
@@ -1818,10 +1870,13 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       L.push_back(Launch{3, off, nj, 0, gx_for(items, nj), 0, 0, false, true, false});
     }
   }
-  if (any_leaf)
-    L.push_back(Launch{5, leaf_off, nj, 0, flat_grid(enum_grid(c), enum_grid(c)), (int)std::min<uint64_t>(
-                           FLAT_GRID_MAX, std::max<uint64_t>(1, (leaf_np + BS - 1) / BS * (uint64_t)nj)),
-                       0, false, false, false});
+  if (any_leaf) {
+    Launch l{5, leaf_off, nj, 0, flat_grid(enum_grid(c), enum_grid(c)), (int)std::min<uint64_t>(
+                 FLAT_GRID_MAX, std::max<uint64_t>(1, (leaf_np + BS - 1) / BS * (uint64_t)nj)),
+             0, false, false, false};
+    l.prep2_off = prep2_off;
+    L.push_back(l);
+  }
   if (c.K > 0) {
     std::vector<TopkJob> T(nj);
     for (int x = 0; x < nj; x++) {
@@ -1891,6 +1946,8 @@ static void run_launch(Ctx& c, const Launch& l) {
       case 5: {
         auto* r = (const LeafJob*)(base + l.off);
         c.tm.run(K_OTHER, [&] { leaf_prep(c.st, g, r, l.njobs, l.gx_item); });
+        if (l.prep2_off != SIZE_MAX)  // the split leaves' second tables
+          c.tm.run(K_OTHER, [&] { leaf_prep(c.st, g, (const LeafJob*)(base + l.prep2_off), l.njobs, l.gx_item); });
         c.tm.run(K_LAST, [&] { leaf_count(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_LAST)); });
         break;
       }
@@ -1915,14 +1972,15 @@ static void upload_recs(Ctx& c, const Recs& R) {
 
 // Upper bound of the record bytes plan_batch writes for a batch: at most 2k
 // filter steps, k CPI edges, k enumeration launches of each form, the leaf
-// counts and the top-K records, each array aligned.
+// counts (two arrays with split leaves) and the top-K records, each array
+// aligned.
 static size_t recs_bound(const std::vector<Job>& jobs) {
   int maxk = 1;
   for (const Job& J : jobs) maxk = std::max(maxk, J.plan.k);
   const size_t nj = jobs.size();
   const size_t per = 2 * (size_t)maxk * sizeof(FilterJob) + (size_t)maxk * sizeof(CpiJob) +
-                     2 * (size_t)maxk * sizeof(ExtJob) + sizeof(LeafJob) + sizeof(TopkJob);
-  return nj * per + 256 * (6 * (size_t)maxk + 4);
+                     2 * (size_t)maxk * sizeof(ExtJob) + 2 * sizeof(LeafJob) + sizeof(TopkJob);
+  return nj * per + 256 * (6 * (size_t)maxk + 5);
 }
 
 // Records and launches of a batch, each launch enqueued as soon as its records
@@ -2634,12 +2692,17 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
 // one common parent, the same vertex label and the same edges to it, and
 // literals that touch no vertex but themselves.  Their completions of a
 // partial match are then counted per parent candidate instead of enumerated.
+// When only the last leaf has that form but the one before it is a leaf too,
+// under another parent, the two are counted together (split leaves): the
+// product of their lists' counts less the vertices both lists hold.
 // (Under the induced reading a leaf must also avoid edges to every other
 // matched vertex, which the per-list counts cannot see.)
 static void plan_leaves(const gfd_spec& s, bool induced, bool count_only, Plan& p) {
   p.leaf_r = 0;
   p.k_enum = p.k;
   p.leaf_par = -1;
+  p.leaf_split = false;
+  p.leaf_par2 = -1;
   for (int t = 0; t < 2 * MAXLIT; t++) p.lit_leaf[t] = -1;
   if (!count_only || induced || p.k < 2) return;
   int deg[MAXK] = {};
@@ -2656,16 +2719,35 @@ static void plan_leaves(const gfd_spec& s, bool induced, bool count_only, Plan& 
   if (r == 0) return;
   // literals: each on one leaf alone, or on inner vertices alone
   int32_t lit_leaf[2 * MAXLIT];
-  for (int t = 0; t < s.num_x + s.num_y; t++) {
-    const gfd_literal& l = t < s.num_x ? s.x[t] : s.y[t - s.num_x];
-    const bool a = p.pos[l.var] >= p.k - r;
-    const bool b = l.kind == GFD_LIT_VAR && p.pos[l.var2] >= p.k - r;
-    if (l.kind == GFD_LIT_VAR && (a != b || (a && l.var2 != l.var))) return;
-    lit_leaf[t] = a ? p.pos[l.var] - (p.k - r) : -1;
+  auto literals_fit = [&](int rr) {
+    for (int t = 0; t < s.num_x + s.num_y; t++) {
+      const gfd_literal& l = t < s.num_x ? s.x[t] : s.y[t - s.num_x];
+      const bool a = p.pos[l.var] >= p.k - rr;
+      const bool b = l.kind == GFD_LIT_VAR && p.pos[l.var2] >= p.k - rr;
+      if (l.kind == GFD_LIT_VAR && (a != b || (a && l.var2 != l.var))) return false;
+      lit_leaf[t] = a ? p.pos[l.var] - (p.k - rr) : -1;
+    }
+    return true;
+  };
+  bool split = false;
+  if (r == 1 && p.k >= 3) {
+    const int ua = p.order[p.k - 2], ub = p.order[p.k - 1];
+    const int qa = p.parent[ua], qb = p.parent[ub];
+    split = deg[ua] == 1 && !p.core[ua] && !p.virt[ua] && qa != qb && p.pos[qa] < p.k - 2 &&
+            p.pos[qb] < p.k - 2 && literals_fit(2);
+  }
+  if (split) {
+    r = 2;
+  } else if (!literals_fit(r)) {
+    return;
   }
   p.leaf_r = r;
   p.k_enum = p.k - r;
   p.leaf_par = p.parent[p.order[p.k - 1]];
+  if (split) {
+    p.leaf_split = true;
+    p.leaf_par2 = p.parent[p.order[p.k - 2]];
+  }
   for (int t = 0; t < s.num_x + s.num_y; t++) p.lit_leaf[t] = lit_leaf[t];
 }
 
@@ -3072,6 +3154,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
             for (int u = 0; u < jobs[x].plan.k; u++)
               stats->cpi_candidates += h[CTL_CAND + 2 * u + jobs[x].cur[u]];
             stats->leaf_gfds += jobs[x].plan.leaf_r > 0;
+            stats->leaf_split_gfds += jobs[x].plan.leaf_split;
           }
       }
       for (size_t x = 0; x < jobs.size(); x++) {

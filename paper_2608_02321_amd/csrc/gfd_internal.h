@@ -313,6 +313,19 @@ struct LeafJob {
   int32_t lit_leaf[2 * MAXLIT];  // leaf slot of a literal, or -1 (inner vertices)
   unsigned long long* counters;  // match, violation
   uint32_t* flags;               // FLAG_COUNTER_OVERFLOW
+  // split leaves: this record counts the last leaf (slot 0 of lit_leaf, r = 1);
+  // the other leaf, under another parent, has the fields below (its literals
+  // in slot 0 of lit_leaf2, its counts in cnt2, filled by a record of its own)
+  int32_t split;
+  int32_t par2_pos;
+  const int32_t* par2_posmap;
+  int32_t par2_by_bucket;
+  const uint32_t* cpi2_beg;
+  const uint32_t* cpi2_len;
+  CandSet u2;
+  int32_t dir2, prim2, other2;
+  const uint32_t* cnt2;
+  int32_t lit_leaf2[2 * MAXLIT];
 };
 
 struct TopkJob {

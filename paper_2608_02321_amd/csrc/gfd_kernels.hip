@@ -1826,12 +1826,13 @@ __device__ __forceinline__ bool leaf_literal(const DevGraph& g, const DevLit& l,
 
 // Predicate masks of vertex x over the leaf slots: bit j of mx when leaf j's X
 // literals hold at x, of mxy when its X and Y literals do.
-__device__ __forceinline__ void leaf_masks(const DevGraph& g, const LeafJob& J, int32_t x,
-                                           uint32_t& mx, uint32_t& mxy) {
-  const uint32_t all = (1u << J.r) - 1;
+__device__ __forceinline__ void leaf_masks_of(const DevGraph& g, const LeafJob& J,
+                                              const int32_t* lit_leaf, int r, int32_t x,
+                                              uint32_t& mx, uint32_t& mxy) {
+  const uint32_t all = (1u << r) - 1;
   uint32_t failx = 0, faily = 0;
   for (int t = 0; t < J.nx + J.ny; t++) {
-    const int j = J.lit_leaf[t];
+    const int j = lit_leaf[t];
     if (j < 0) continue;
     if (!leaf_literal(g, J.lit[t], x)) {
       if (t < J.nx) failx |= 1u << j;
@@ -1840,6 +1841,87 @@ __device__ __forceinline__ void leaf_masks(const DevGraph& g, const LeafJob& J, 
   }
   mx = all & ~failx;
   mxy = all & ~(failx | faily);
+}
+
+__device__ __forceinline__ void leaf_masks(const DevGraph& g, const LeafJob& J, int32_t x,
+                                           uint32_t& mx, uint32_t& mxy) {
+  leaf_masks_of(g, J, J.lit_leaf, J.r, x, mx, mxy);
+}
+
+// Whether x is in the leaf list of parent image vp: the list holds the
+// candidates x != vp for which the tree edge and its reverse constraint hold.
+__device__ __forceinline__ bool in_leaf_list(const DevGraph& g, const CandSet& u, int32_t dir,
+                                             int32_t prim, int32_t other, int32_t x, int32_t vp,
+                                             unsigned long long& by) {
+  if (x == vp || !member(u, x)) return false;
+  return dir ? (constraint_ok(edge_label_at(g, x, vp, false, by), prim) &&
+                pair_ok(g, vp, x, true, other, by))
+             : (constraint_ok(edge_label_at(g, vp, x, true, by), prim) &&
+                pair_ok(g, x, vp, false, other, by));
+}
+
+// Split leaves of one partial match h (parents' images vb, va): completions
+// are the pairs (a, b) of list members, both off h and distinct, so per
+// literal family f the count is |A_f| |B_f| less the vertices in both lists
+// that meet both leaves' family-f literals.
+__device__ __forceinline__ void leaf_split_counts(const DevGraph& g, const LeafJob& J,
+                                                  const int32_t (&h)[MAXK], int32_t vb,
+                                                  uint32_t rowb, __int128 (&inj)[LEAF_FAMILIES],
+                                                  unsigned long long& by) {
+  const int32_t va = pick(h, J.par2_pos);
+  const uint32_t rowa = (uint32_t)J.par2_posmap[pos_index(g, J.par2_by_bucket, va)];
+  const uint32_t* tb = J.cnt + (uint64_t)rowb * LEAF_WORDS;
+  const uint32_t* ta = J.cnt2 + (uint64_t)rowa * LEAF_WORDS;
+  by += 4ull * LEAF_WORDS + 4;  // the other table row and position
+  int64_t ca[LEAF_FAMILIES], cb[LEAF_FAMILIES], both[LEAF_FAMILIES];
+#pragma unroll
+  for (int f = 0; f < LEAF_FAMILIES; f++) {
+    ca[f] = ta[f * LEAF_SUBSETS + 1];
+    cb[f] = tb[f * LEAF_SUBSETS + 1];
+    both[f] = 0;
+  }
+  // matched inner vertices in either list are not available
+  for (int j = 0; j < J.i; j++) {
+    const int32_t x = pick(h, j);
+    uint32_t mx, mxy;
+    if (in_leaf_list(g, J.u, J.dir, J.prim, J.other, x, vb, by)) {
+      leaf_masks_of(g, J, J.lit_leaf, 1, x, mx, mxy);
+      cb[0] -= 1;
+      cb[1] -= mx & 1u;
+      cb[2] -= mxy & 1u;
+    }
+    if (in_leaf_list(g, J.u2, J.dir2, J.prim2, J.other2, x, va, by)) {
+      leaf_masks_of(g, J, J.lit_leaf2, 1, x, mx, mxy);
+      ca[0] -= 1;
+      ca[1] -= mx & 1u;
+      ca[2] -= mxy & 1u;
+    }
+  }
+  // vertices in both lists: walk the shorter, test membership in the other
+  const uint32_t la = J.cpi2_len[rowa], lb = J.cpi_len[rowb];
+  const bool walk_a = la <= lb;
+  const uint64_t b0 = walk_a ? J.cpi2_beg[rowa] : J.cpi_beg[rowb];
+  const uint32_t len = walk_a ? la : lb;
+  by += 16;  // both lists' bounds
+  for (uint32_t e = 0; e < len; e++) {
+    const int32_t x = J.cpi_ent[b0 + e];
+    by += 4;
+    bool inner = false;
+#pragma unroll
+    for (int j = 0; j < MAXK; j++) inner |= j < J.i && h[j] == x;
+    if (inner) continue;
+    const bool in_other = walk_a ? in_leaf_list(g, J.u, J.dir, J.prim, J.other, x, vb, by)
+                                 : in_leaf_list(g, J.u2, J.dir2, J.prim2, J.other2, x, va, by);
+    if (!in_other) continue;
+    uint32_t ma, mya, mb, myb;
+    leaf_masks_of(g, J, J.lit_leaf2, 1, x, ma, mya);
+    leaf_masks_of(g, J, J.lit_leaf, 1, x, mb, myb);
+    both[0] += 1;
+    both[1] += ma & mb & 1u;
+    both[2] += mya & myb & 1u;
+  }
+#pragma unroll
+  for (int f = 0; f < LEAF_FAMILIES; f++) inj[f] = (__int128)ca[f] * cb[f] - both[f];
 }
 
 // One thread per member c of C(p): cnt[c][f][B] = members of c's leaf list
@@ -1950,7 +2032,23 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
 #pragma unroll
     for (int j = 0; j < MAXK; j++) h[j] = j < J.i ? J.src_cols[(uint64_t)j * J.src_stride + s] : 0;
     const int32_t vp = pick(h, J.par_pos);
-    const uint32_t* cc = J.cnt + (uint64_t)J.par_posmap[pos_index(g, J.par_by_bucket, vp)] * LEAF_WORDS;
+    const uint32_t rowp = (uint32_t)J.par_posmap[pos_index(g, J.par_by_bucket, vp)];
+    if (J.split) {
+      __int128 inj[LEAF_FAMILIES];
+      leaf_split_counts(g, J, h, vp, rowp, inj, by);
+      bool X = true, Y = !J.y_false;
+      for (int t = 0; t < J.nx + J.ny; t++) {
+        if (J.lit_leaf[t] >= 0 || J.lit_leaf2[t] >= 0) continue;
+        const bool v = literal_holds(g, J.lit[t], [&](int p) { return pick(h, p); });
+        by += J.lit[t].kind == 0 ? 4 : 8;
+        if (t < J.nx) X = X && v;
+        else Y = Y && v;
+      }
+      acc.match += leaf_add(inj[0], ovf);
+      if (X) acc.viol += leaf_add(Y ? inj[1] - inj[2] : inj[1], ovf);
+      continue;
+    }
+    const uint32_t* cc = J.cnt + (uint64_t)rowp * LEAF_WORDS;
     int64_t c[LEAF_FAMILIES][LEAF_SUBSETS];
 #pragma unroll
     for (int f = 0; f < LEAF_FAMILIES; f++)
@@ -1959,13 +2057,7 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
     // matched inner vertices that sit in vp's leaf list are not available
     for (int j = 0; j < J.i; j++) {
       const int32_t x = h[j];
-      if (x == vp || !member(J.u, x)) continue;
-      // the list holds x iff the tree edge and its reverse constraint hold
-      const bool in = J.dir ? (constraint_ok(edge_label_at(g, x, vp, false, by), J.prim) &&
-                               pair_ok(g, vp, x, true, J.other, by))
-                            : (constraint_ok(edge_label_at(g, vp, x, true, by), J.prim) &&
-                               pair_ok(g, x, vp, false, J.other, by));
-      if (!in) continue;
+      if (!in_leaf_list(g, J.u, J.dir, J.prim, J.other, x, vp, by)) continue;
       uint32_t mx, mxy;
       leaf_masks(g, J, x, mx, mxy);
 #pragma unroll

@@ -62,6 +62,32 @@ CASES = [
 ]
 
 
+# Triangles (matched first, as the core) with one leaf on each of two corners:
+# the last two leaves of the order hang from different parents and are counted
+# together as the product of their lists' counts less the shared vertices.
+TRI = [[0, 1, 0], [1, 2, 0], [2, 0, 1]]
+SPLIT_CASES = [
+    # same label and edge form on both leaves: shared list vertices are common;
+    # literals on each leaf and on an inner vertex
+    {"k": 5, "vlabels": [0, 0, 1, 1, 1], "edges": TRI + [[0, 3, 2], [1, 4, 2]],
+     "x": [c(3, 0, 1)], "y": [c(4, 1, 2), c(2, 0, 0)], "y_false": False},
+    # wildcard leaves on undirected edges: matched inner vertices sit in the
+    # lists; a variable literal on one leaf alone
+    {"k": 5, "vlabels": [0, 1, 0, -1, -1], "edges": TRI + und([(0, 3), (1, 4)]),
+     "x": [c(4, 0, 2)], "y": [v(3, 0, 3, 1)], "y_false": False},
+    # leaf edges in opposite directions, X -> false
+    {"k": 5, "vlabels": [0, 0, 1, 1, 1], "edges": TRI + [[3, 0, 1], [1, 4, 1]],
+     "x": [c(3, 1, 0), c(4, 1, 0)], "y": [], "y_false": True},
+    # leaves of different labels: the lists share nothing
+    {"k": 5, "vlabels": [0, 0, 1, 1, 0], "edges": TRI + [[0, 3, 0], [1, 4, 0]],
+     "x": [], "y": [c(3, 0, 1), c(4, 0, 2)], "y_false": False},
+    # a literal tying one leaf to an inner vertex: only the other is counted
+    {"k": 5, "vlabels": [0, 0, 1, 1, 1], "edges": TRI + [[0, 3, 2], [1, 4, 2]],
+     "x": [v(3, 0, 2, 1)], "y": [c(4, 1, 2)], "y_false": False},
+]
+SPLIT_COUNTED = 4  # the first four have both leaves counted together
+
+
 def _oracle_counts(og, d, sem):
     r = O.validate(og, d, sem, K=0, threads=4)
     return {"match_count": r["match_count"], "violation_count": r["violation_count"],
@@ -94,13 +120,45 @@ def test_counted_leaves_match_oracle(P, batched):
     gh.free()
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_split_leaves_match_oracle(P, batched):
+    """Two last leaves under different parents: counts equal the oracle's and
+    those of the same GFDs enumerated; the statistics show which GFDs took the
+    split form."""
+    g = random_graph(33, 250, 12000, n_vlabels=2, n_elabels=3, n_attrs=2, attr_values=3,
+                     absent_frac=0.1, reciprocal_frac=0.4)
+    og = O.OracleGraph(g)
+    # not vacuous: the two leaves merged into one vertex on both corners has
+    # matches, so the lists of the first two GFDs share vertices and the count
+    # of pairs must take out the pairs of one vertex to agree with the oracle
+    for d in SPLIT_CASES[:2]:
+        assert d["vlabels"][3] == d["vlabels"][4]
+        merged = {"k": 4, "vlabels": d["vlabels"][:4], "x": [], "y": [], "y_false": False,
+                  "edges": [[min(a, 3), min(b, 3), lab] for a, b, lab in d["edges"]]}
+        assert O.validate(og, merged, "mono", K=0, threads=4)["match_count"] > 0
+    gh = P.load(g)
+    for sem in ("mono", "induced"):
+        got, st = P.validate(gh, SPLIT_CASES, K=0, semantics=sem, flags=P.GFD_FLAG_COUNT_ONLY,
+                             stats=True, batched=batched)
+        for i, (d, r) in enumerate(zip(SPLIT_CASES, got)):
+            assert r == _oracle_counts(og, d, sem), (sem, i)
+        assert st["leaf_split_gfds"] == (SPLIT_COUNTED if sem == "mono" else 0), (sem, st)
+        assert st["leaf_gfds"] == (len(SPLIT_CASES) if sem == "mono" else 0), (sem, st)
+    full = P.validate(gh, SPLIT_CASES, K=0, semantics="mono", batched=batched)
+    cnt = P.validate(gh, SPLIT_CASES, K=0, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
+                     batched=batched)
+    for a, b in zip(full, cnt):
+        assert (a["match_count"], a["violation_count"]) == (b["match_count"], b["violation_count"])
+    gh.free()
+
+
 def test_counted_leaves_under_frontier_overflow(P):
     """A job whose inner frontier overflows is redone on the bounded path,
     which enumerates everything: counts stay exact."""
     g = random_graph(32, 400, 8000, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3)
     og = O.OracleGraph(g)
     gh = P.load(g)
-    gfds = [d for d, q in CASES if q]
+    gfds = [d for d, q in CASES if q] + SPLIT_CASES[:SPLIT_COUNTED]
     got = P.validate(gh, gfds, K=0, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
                      frontier_cap=50, batched=True)
     for d, r in zip(gfds, got):
