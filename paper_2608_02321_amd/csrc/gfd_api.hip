@@ -1766,6 +1766,8 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
         f.lit_leaf2[t] = p.lit_leaf[t] == 0 ? 0 : -1;
       }
       f.split = 1;
+      const int ub = p.order[p.k - 1];
+      f.split_overlap = p.qlab[ua] == ANY || p.qlab[ub] == ANY || p.qlab[ua] == p.qlab[ub];
       f.par2_pos = p.pos[q2];
       f.par2_posmap = J.mem.pos[q2];
       f.par2_by_bucket = p.qlab[q2] != ANY ? 1 : 0;
@@ -1948,7 +1950,9 @@ static void run_launch(Ctx& c, const Launch& l) {
         c.tm.run(K_OTHER, [&] { leaf_prep(c.st, g, r, l.njobs, l.gx_item); });
         if (l.prep2_off != SIZE_MAX)  // the split leaves' second tables
           c.tm.run(K_OTHER, [&] { leaf_prep(c.st, g, (const LeafJob*)(base + l.prep2_off), l.njobs, l.gx_item); });
-        c.tm.run(K_LAST, [&] { leaf_count(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_LAST)); });
+        c.tm.run(K_LAST, [&] { leaf_count(c.st, g, r, l.njobs, l.gx_work, false, cls_bytes(c, K_LAST)); });
+        if (l.prep2_off != SIZE_MAX)  // the jobs with split leaves
+          c.tm.run(K_LAST, [&] { leaf_count(c.st, g, r, l.njobs, l.gx_work, true, cls_bytes(c, K_LAST)); });
         break;
       }
       case 4: {

@@ -317,6 +317,7 @@ struct LeafJob {
   // the other leaf, under another parent, has the fields below (its literals
   // in slot 0 of lit_leaf2, its counts in cnt2, filled by a record of its own)
   int32_t split;
+  int32_t split_overlap;  // 0: the two leaves' labels differ, their lists share nothing
   int32_t par2_pos;
   const int32_t* par2_posmap;
   int32_t par2_by_bucket;
@@ -435,9 +436,10 @@ struct PackJob {
 void pack_results(hipStream_t st, const PackJob* jobs, int njobs, int32_t* out);
 // per member of C(p): how many of its leaf-list members meet each predicate subset
 void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid);
-// per partial match: its injective leaf completions, counted into the job's counters
+// per partial match: its injective leaf completions, counted into the job's
+// counters; `split` picks the jobs with split leaves, else the others
 void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid,
-                unsigned long long* bytes);
+                bool split, unsigned long long* bytes);
 
 // Batched radix select (grid row = job); requires more than K staged tuples
 // per active job.  sel_pass decides `bits` bits of tuple word `word` starting

@@ -70,6 +70,29 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total)
   return pre + inc - x;
 }
 
+// The same scan over one u64 per thread.
+__device__ __forceinline__ uint64_t block_excl_scan64(uint64_t x, uint64_t& total) {
+  __shared__ uint64_t s_w64[BS / WAVE];
+  uint64_t inc = x;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint64_t y = __shfl_up(inc, (unsigned)d);
+    if (lane() >= (uint32_t)d) inc += y;
+  }
+  __syncthreads();
+  if (lane() == WAVE - 1) s_w64[threadIdx.x / WAVE] = inc;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+  const uint32_t wv = threadIdx.x / WAVE;
+#pragma unroll
+  for (int w = 0; w < BS / WAVE; w++) {
+    if ((uint32_t)w < wv) pre += s_w64[w];
+    tot += s_w64[w];
+  }
+  total = tot;
+  return pre + inc - x;
+}
+
 // Adds every thread's x into *dst once per block.  All threads must call it.
 __device__ __forceinline__ void block_add(unsigned long long* dst, unsigned long long x) {
   __shared__ unsigned long long s_part[BS / WAVE];
@@ -1860,70 +1883,6 @@ __device__ __forceinline__ bool in_leaf_list(const DevGraph& g, const CandSet& u
                 pair_ok(g, x, vp, false, other, by));
 }
 
-// Split leaves of one partial match h (parents' images vb, va): completions
-// are the pairs (a, b) of list members, both off h and distinct, so per
-// literal family f the count is |A_f| |B_f| less the vertices in both lists
-// that meet both leaves' family-f literals.
-__device__ __forceinline__ void leaf_split_counts(const DevGraph& g, const LeafJob& J,
-                                                  const int32_t (&h)[MAXK], int32_t vb,
-                                                  uint32_t rowb, __int128 (&inj)[LEAF_FAMILIES],
-                                                  unsigned long long& by) {
-  const int32_t va = pick(h, J.par2_pos);
-  const uint32_t rowa = (uint32_t)J.par2_posmap[pos_index(g, J.par2_by_bucket, va)];
-  const uint32_t* tb = J.cnt + (uint64_t)rowb * LEAF_WORDS;
-  const uint32_t* ta = J.cnt2 + (uint64_t)rowa * LEAF_WORDS;
-  by += 4ull * LEAF_WORDS + 4;  // the other table row and position
-  int64_t ca[LEAF_FAMILIES], cb[LEAF_FAMILIES], both[LEAF_FAMILIES];
-#pragma unroll
-  for (int f = 0; f < LEAF_FAMILIES; f++) {
-    ca[f] = ta[f * LEAF_SUBSETS + 1];
-    cb[f] = tb[f * LEAF_SUBSETS + 1];
-    both[f] = 0;
-  }
-  // matched inner vertices in either list are not available
-  for (int j = 0; j < J.i; j++) {
-    const int32_t x = pick(h, j);
-    uint32_t mx, mxy;
-    if (in_leaf_list(g, J.u, J.dir, J.prim, J.other, x, vb, by)) {
-      leaf_masks_of(g, J, J.lit_leaf, 1, x, mx, mxy);
-      cb[0] -= 1;
-      cb[1] -= mx & 1u;
-      cb[2] -= mxy & 1u;
-    }
-    if (in_leaf_list(g, J.u2, J.dir2, J.prim2, J.other2, x, va, by)) {
-      leaf_masks_of(g, J, J.lit_leaf2, 1, x, mx, mxy);
-      ca[0] -= 1;
-      ca[1] -= mx & 1u;
-      ca[2] -= mxy & 1u;
-    }
-  }
-  // vertices in both lists: walk the shorter, test membership in the other
-  const uint32_t la = J.cpi2_len[rowa], lb = J.cpi_len[rowb];
-  const bool walk_a = la <= lb;
-  const uint64_t b0 = walk_a ? J.cpi2_beg[rowa] : J.cpi_beg[rowb];
-  const uint32_t len = walk_a ? la : lb;
-  by += 16;  // both lists' bounds
-  for (uint32_t e = 0; e < len; e++) {
-    const int32_t x = J.cpi_ent[b0 + e];
-    by += 4;
-    bool inner = false;
-#pragma unroll
-    for (int j = 0; j < MAXK; j++) inner |= j < J.i && h[j] == x;
-    if (inner) continue;
-    const bool in_other = walk_a ? in_leaf_list(g, J.u, J.dir, J.prim, J.other, x, vb, by)
-                                 : in_leaf_list(g, J.u2, J.dir2, J.prim2, J.other2, x, va, by);
-    if (!in_other) continue;
-    uint32_t ma, mya, mb, myb;
-    leaf_masks_of(g, J, J.lit_leaf2, 1, x, ma, mya);
-    leaf_masks_of(g, J, J.lit_leaf, 1, x, mb, myb);
-    both[0] += 1;
-    both[1] += ma & mb & 1u;
-    both[2] += mya & myb & 1u;
-  }
-#pragma unroll
-  for (int f = 0; f < LEAF_FAMILIES; f++) inj[f] = (__int128)ca[f] * cb[f] - both[f];
-}
-
 // One thread per member c of C(p): cnt[c][f][B] = members of c's leaf list
 // whose family-f masks contain B (f = 0: every member, 1: X, 2: X and Y).
 __device__ __forceinline__ uint64_t leaf_members(const LeafJob& J) {
@@ -1946,7 +1905,13 @@ __global__ __launch_bounds__(BS) void k_leaf_prep(DevGraph g, const LeafJob* __r
   if (c < np) {
     uint32_t cx[LEAF_SUBSETS] = {}, cxy[LEAF_SUBSETS] = {};
     const uint32_t b = J.cpi_beg[c], len = J.cpi_len[c];
-    for (uint32_t e = 0; e < len; e++) {
+    // with no literal on the leaves every member meets every subset: the
+    // counts are the list's length, and the list is not read
+    bool leaf_lits = false;
+    for (int t = 0; t < J.nx + J.ny; t++) leaf_lits |= J.lit_leaf[t] >= 0;
+    if (!leaf_lits)
+      for (uint32_t B = 1; B < LEAF_SUBSETS; B++) cx[B] = cxy[B] = B < nsub ? len : 0u;
+    for (uint32_t e = 0; e < (leaf_lits ? len : 0u); e++) {
       uint32_t mx, mxy;
       leaf_masks(g, J, J.cpi_ent[(uint64_t)b + e], mx, mxy);
 #pragma unroll
@@ -2009,12 +1974,140 @@ __device__ __forceinline__ uint64_t leaf_sources(const LeafJob& J) {
   return !J.active ? 0ull : (*J.d_nsrc < J.src_cap ? *J.d_nsrc : J.src_cap);
 }
 
+// Split leaves, one chunk of partial matches [s0, s1) of job J (the whole
+// block, uniformly).  A partial match h with parent images vb (last leaf)
+// and va (the leaf before it) completes to the pairs (a, b) of list members,
+// both off h and distinct, so per literal family f the count is
+// |A_f| |B_f| less the vertices in both lists that meet both leaves'
+// family-f literals.  The shorter list of each match is walked by the whole
+// block: its entries across all the round's matches form one index space
+// (a block scan of the lengths), so a long list does not hold up the others.
+__device__ void leaf_split_chunk(const DevGraph& g, const LeafJob& J, uint64_t s0, uint64_t s1,
+                                 FinalAcc& acc, bool& ovf, unsigned long long& by) {
+  __shared__ uint64_t s_pre[BS], s_beg[BS];
+  __shared__ int32_t s_h[MAXK][BS];
+  __shared__ int32_t s_vo[BS];      // the other list's parent image
+  __shared__ uint32_t s_walk_a[BS];  // 1: A's list is walked, B's tested
+  __shared__ uint32_t s_both[LEAF_FAMILIES][BS];
+  for (uint64_t base = s0; base < s1; base += BS) {
+    const uint64_t s = base + threadIdx.x;
+    const bool act = s < s1;
+    int32_t h[MAXK];
+#pragma unroll
+    for (int j = 0; j < MAXK; j++)
+      h[j] = act && j < J.i ? J.src_cols[(uint64_t)j * J.src_stride + s] : -1;
+    int64_t ca[LEAF_FAMILIES] = {}, cb[LEAF_FAMILIES] = {};
+    bool X = true, Y = !J.y_false, walk_a = false;
+    uint64_t len = 0, beg = 0;
+    int32_t vo = -1;
+    if (act) {
+      const int32_t vb = pick(h, J.par_pos), va = pick(h, J.par2_pos);
+      const uint32_t rowb = (uint32_t)J.par_posmap[pos_index(g, J.par_by_bucket, vb)];
+      const uint32_t rowa = (uint32_t)J.par2_posmap[pos_index(g, J.par2_by_bucket, va)];
+      const uint32_t* tb = J.cnt + (uint64_t)rowb * LEAF_WORDS;
+      const uint32_t* ta = J.cnt2 + (uint64_t)rowa * LEAF_WORDS;
+      // the partial match, both parents' positions and table rows
+      by += 4ull * (uint64_t)J.i + 8 + 8ull * LEAF_WORDS;
+#pragma unroll
+      for (int f = 0; f < LEAF_FAMILIES; f++) {
+        ca[f] = ta[f * LEAF_SUBSETS + 1];
+        cb[f] = tb[f * LEAF_SUBSETS + 1];
+      }
+      // matched inner vertices in either list are not available
+      for (int j = 0; j < J.i; j++) {
+        const int32_t x = pick(h, j);
+        uint32_t mx, mxy;
+        if (in_leaf_list(g, J.u, J.dir, J.prim, J.other, x, vb, by)) {
+          leaf_masks_of(g, J, J.lit_leaf, 1, x, mx, mxy);
+          cb[0] -= 1;
+          cb[1] -= mx & 1u;
+          cb[2] -= mxy & 1u;
+        }
+        if (in_leaf_list(g, J.u2, J.dir2, J.prim2, J.other2, x, va, by)) {
+          leaf_masks_of(g, J, J.lit_leaf2, 1, x, mx, mxy);
+          ca[0] -= 1;
+          ca[1] -= mx & 1u;
+          ca[2] -= mxy & 1u;
+        }
+      }
+      for (int t = 0; t < J.nx + J.ny; t++) {
+        if (J.lit_leaf[t] >= 0 || J.lit_leaf2[t] >= 0) continue;
+        const bool v = literal_holds(g, J.lit[t], [&](int p) { return pick(h, p); });
+        by += J.lit[t].kind == 0 ? 4 : 8;
+        if (t < J.nx) X = X && v;
+        else Y = Y && v;
+      }
+      if (J.split_overlap) {  // else no vertex is in both lists
+        const uint32_t la = J.cpi2_len[rowa], lb = J.cpi_len[rowb];
+        by += 16;  // both lists' bounds
+        walk_a = la <= lb;
+        beg = walk_a ? J.cpi2_beg[rowa] : J.cpi_beg[rowb];
+        len = walk_a ? la : lb;
+        vo = walk_a ? vb : va;
+      }
+    }
+    uint64_t total;
+    const uint64_t pre = block_excl_scan64(len, total);
+    s_pre[threadIdx.x] = pre;
+    s_beg[threadIdx.x] = beg;
+#pragma unroll
+    for (int j = 0; j < MAXK; j++) s_h[j][threadIdx.x] = h[j];
+    s_vo[threadIdx.x] = vo;
+    s_walk_a[threadIdx.x] = walk_a ? 1u : 0u;
+#pragma unroll
+    for (int f = 0; f < LEAF_FAMILIES; f++) s_both[f][threadIdx.x] = 0;
+    __syncthreads();
+    for (uint64_t it = threadIdx.x; it < total; it += BS) {
+      // the match whose entries hold `it`: the last t with s_pre[t] <= it
+      // (a match with an empty list shares its prefix with the next one)
+      int lo = 0, hi = BS - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= it) lo = mid;
+        else hi = mid - 1;
+      }
+      const int t = lo;
+      const int32_t x = J.cpi_ent[s_beg[t] + (it - s_pre[t])];
+      by += 4;
+      bool inner = false;
+#pragma unroll
+      for (int j = 0; j < MAXK; j++) inner |= j < J.i && s_h[j][t] == x;
+      if (inner) continue;
+      const bool wa = s_walk_a[t] != 0;
+      const bool in_other = wa ? in_leaf_list(g, J.u, J.dir, J.prim, J.other, x, s_vo[t], by)
+                               : in_leaf_list(g, J.u2, J.dir2, J.prim2, J.other2, x, s_vo[t], by);
+      if (!in_other) continue;
+      uint32_t ma, mya, mb, myb;
+      leaf_masks_of(g, J, J.lit_leaf2, 1, x, ma, mya);
+      leaf_masks_of(g, J, J.lit_leaf, 1, x, mb, myb);
+      atomicAdd(&s_both[0][t], 1u);
+      if (ma & mb & 1u) atomicAdd(&s_both[1][t], 1u);
+      if (mya & myb & 1u) atomicAdd(&s_both[2][t], 1u);
+    }
+    __syncthreads();
+    if (act) {
+      __int128 inj[LEAF_FAMILIES];
+#pragma unroll
+      for (int f = 0; f < LEAF_FAMILIES; f++)
+        inj[f] = (__int128)ca[f] * cb[f] - (__int128)s_both[f][threadIdx.x];
+      acc.match += leaf_add(inj[0], ovf);
+      if (X) acc.viol += leaf_add(Y ? inj[1] - inj[2] : inj[1], ovf);
+    }
+    __syncthreads();  // the next round rewrites the shared arrays
+  }
+}
+
 // The partial matches of every job share one chunk space (LBS_CHUNK sources a
 // chunk), so a job with most of the work gets most of the chip.
+// SPLIT selects the jobs of one form (split leaves or not): the two forms are
+// separate kernels so the common one keeps its register budget.
+template <bool SPLIT>
 __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __restrict__ jobs,
                                                    int njobs, unsigned long long* bytes) {
   __shared__ ChunkMap cm;
-  chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return chunks_of(leaf_sources(jobs[j])); });
+  chunk_map_build(cm, njobs, [&](int j) -> uint64_t {
+    return (jobs[j].split != 0) == SPLIT ? chunks_of(leaf_sources(jobs[j])) : 0ull;
+  });
   unsigned long long by = 0;
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
   const int jb = chunk_job(cm, njobs, ch);
@@ -2025,7 +2118,8 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
   const uint32_t nsub = 1u << J.r;
   FinalAcc acc{0, 0, 0, 0};
   bool ovf = false;
-  for (uint64_t s = s0 + threadIdx.x; s < s1; s += BS) {
+  if (SPLIT) leaf_split_chunk(g, J, s0, s1, acc, ovf, by);
+  for (uint64_t s = s0 + threadIdx.x; s < s1 && !SPLIT; s += BS) {
     // the partial match, its parent's row in the count table and the words read
     by += 4ull * (uint64_t)J.i + 4 + 4ull * LEAF_WORDS;
     int32_t h[MAXK];
@@ -2033,21 +2127,6 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
     for (int j = 0; j < MAXK; j++) h[j] = j < J.i ? J.src_cols[(uint64_t)j * J.src_stride + s] : 0;
     const int32_t vp = pick(h, J.par_pos);
     const uint32_t rowp = (uint32_t)J.par_posmap[pos_index(g, J.par_by_bucket, vp)];
-    if (J.split) {
-      __int128 inj[LEAF_FAMILIES];
-      leaf_split_counts(g, J, h, vp, rowp, inj, by);
-      bool X = true, Y = !J.y_false;
-      for (int t = 0; t < J.nx + J.ny; t++) {
-        if (J.lit_leaf[t] >= 0 || J.lit_leaf2[t] >= 0) continue;
-        const bool v = literal_holds(g, J.lit[t], [&](int p) { return pick(h, p); });
-        by += J.lit[t].kind == 0 ? 4 : 8;
-        if (t < J.nx) X = X && v;
-        else Y = Y && v;
-      }
-      acc.match += leaf_add(inj[0], ovf);
-      if (X) acc.viol += leaf_add(Y ? inj[1] - inj[2] : inj[1], ovf);
-      continue;
-    }
     const uint32_t* cc = J.cnt + (uint64_t)rowp * LEAF_WORDS;
     int64_t c[LEAF_FAMILIES][LEAF_SUBSETS];
 #pragma unroll
@@ -2092,8 +2171,9 @@ void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs
   hipLaunchKernelGGL(k_leaf_prep, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
 }
 void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid,
-                unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_leaf_count, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+                bool split, unsigned long long* bytes) {
+  if (split) hipLaunchKernelGGL(k_leaf_count<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  else hipLaunchKernelGGL(k_leaf_count<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 
 // ---------------------------------------------------------------------------

@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from synth import configs
-from synth.small import random_graph
+from synth.small import random_gfd, random_graph
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -149,6 +149,28 @@ def test_split_leaves_match_oracle(P, batched):
                      batched=batched)
     for a, b in zip(full, cnt):
         assert (a["match_count"], a["violation_count"]) == (b["match_count"], b["violation_count"])
+    gh.free()
+
+
+def test_count_only_random_shapes(P):
+    """Count-only calls over seeded random connected GFDs (k = 3..7,
+    wildcards, extra edges), batched, in both readings: every count equals the
+    oracle's, whichever form (common-parent leaves, split leaves, enumeration)
+    the planner picked for it."""
+    g = random_graph(34, 300, 3000, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3,
+                     absent_frac=0.1, reciprocal_frac=0.3)
+    og = O.OracleGraph(g)
+    gh = P.load(g)
+    gfds = [random_gfd(3400 + j, 3 + j % 5, n_vlabels=2, n_elabels=2, n_attrs=2, attr_values=3,
+                       wildcard_frac=0.2, extra_edge_frac=0.2)
+            for j in range(60)]
+    for sem in ("mono", "induced"):
+        got, st = P.validate(gh, gfds, K=0, semantics=sem, flags=P.GFD_FLAG_COUNT_ONLY,
+                             stats=True, batched=True)
+        for i, (d, r) in enumerate(zip(gfds, got)):
+            assert r == _oracle_counts(og, d, sem), (sem, i)
+        if sem == "mono":
+            assert st["leaf_gfds"] > 10 and st["leaf_split_gfds"] > 0, st
     gh.free()
 
 
