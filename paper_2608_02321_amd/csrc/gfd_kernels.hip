@@ -1464,14 +1464,15 @@ __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __res
     for (int v = 0; v < MAXK; v++) thr[v] = prune && v < J.k ? J.thr[v] : 0;
     const uint64_t xn = J.cross ? (*J.cross_n < J.cross_cap ? *J.cross_n : J.cross_cap) : 0ull;
     job_scan(ext_sources(J), [&](uint64_t s) -> uint32_t {
+      // a source the threshold rules out gets no attempts, so its list start
+      // is never read: decided first, it skips the parent's row lookups
+      if (prune && source_past(J, s, thr)) return 0u;
       if (J.cross) {  // all of the new component root's candidates
         J.begs[s] = 0;
-        if (prune && source_past(J, s, thr)) return 0u;
         return (uint32_t)xn;
       }
       const int32_t c = J.par_posmap[pos_index(g, J.par_by_bucket, par[s])];
       J.begs[s] = J.cpi_beg[c];
-      if (prune && source_past(J, s, thr)) return 0u;
       return J.cpi_len[c];
     }, J.sc, nb);
   });
