@@ -40,13 +40,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "5f31add8b50621cd1d8cfb6f80cd290e74157b03a1d7b7c9c70e16a136981b07",
+    "sources_sha256": "6788e38304d21008daf7212ce70f02eb9353745b4c97b9a4cfcc0b7a0986314c",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true, false, 8>
     "semantics": "induced",
     "count_only": False,
-    # (591.61 MB read + 38.30 MB written) per dispatch, calibrated (x1.9999, x1.0)
-    "bytes_per_launch": 6.2991e+08,
+    # (601.24 MB read + 38.24 MB written) per dispatch, calibrated (x1.9999, x1.0)
+    "bytes_per_launch": 6.3948e+08,
 }
 # Units of work of the dominant kernel class per step (one validate call),
 # from the counting build (bench.py --units; see profiles/), and the
@@ -57,17 +57,17 @@ TRAFFIC = {
 # small threshold re-run launch or not, which leaves the work per step as it
 # is.  Valid only for the kernel sources it was counted on.
 UNITS = {
-    "sources_sha256": "5f31add8b50621cd1d8cfb6f80cd290e74157b03a1d7b7c9c70e16a136981b07",
+    "sources_sha256": "6788e38304d21008daf7212ce70f02eb9353745b4c97b9a4cfcc0b7a0986314c",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",
     "semantics": "induced",
     "count_only": False,
-    "per_step": {"attempts": 158362497, "sources": 12606822, "injective": 158350910,
-                 "checks_both": 416324448, "table_free": 361413787, "table_hit": 8275693,
-                 "short_row": 46634968, "both_steps": 205786300, "both_log2d": 3854751071,
+    "per_step": {"attempts": 158354818, "sources": 12610581, "injective": 158343231,
+                 "checks_both": 416247167, "table_free": 361338655, "table_hit": 8271768,
+                 "short_row": 46636744, "both_steps": 205750170, "both_log2d": 3853948926,
                  "checks_one": 0, "one_steps": 0, "one_log2d": 0, "matches": 147891222,
-                 "literal_reads": 162668068, "violations": 68082422, "inner_attempts": 19554114},
-    "model_bytes_per_step": 3.22230e10,
+                 "literal_reads": 162656672, "violations": 68082422, "inner_attempts": 19554114},
+    "model_bytes_per_step": 3.22165e10,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
