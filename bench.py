@@ -290,6 +290,10 @@ def main():
     ap.add_argument("--count-only", action="store_true",
                     help="counts and satisfied flags only (K = 0, no fingerprints): postponed "
                          "leaves are counted, not enumerated (with --semantics mono)")
+    ap.add_argument("--k", type=int, default=None, metavar="K",
+                    help="violations listed per GFD (default 1024, or 0 with --count-only; "
+                         "a count-only call with K > 0 lists the first K from the window its "
+                         "counts bound)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write elementwise kernel "
                          "(int32 negation) three times: the calibration run for HBM counters")
@@ -361,7 +365,7 @@ def main():
 
     # specs, options and result buffers are marshalled once; a step is one
     # gfd_validate_ex call through the C ABI
-    K = 0 if args.count_only else K_REPORT
+    K = args.k if args.k is not None else (0 if args.count_only else K_REPORT)
     base_flags = P.GFD_FLAG_COUNT_ONLY if args.count_only else 0
     # launch shapes: the autotuner's choice for this call shape (tried and
     # checked for identical results on this graph, or read from its cache)
@@ -463,7 +467,7 @@ def main():
         def valid(tab):
             return (tab["kernel_class"] == name and tab["workload"] == args.workload
                     and tab["semantics"] == args.semantics
-                    and tab["count_only"] == bool(args.count_only)
+                    and tab["count_only"] == bool(args.count_only) and args.k is None
                     and tab["sources_sha256"] == sources_sha256())
         traffic = TRAFFIC["bytes_per_launch"] if valid(TRAFFIC) else None
         # algorithmic bytes: the per-unit model over the units one launch

@@ -167,14 +167,18 @@ typedef struct {
 
 #define GFD_FLAG_FORCE_CHUNKED 1 /* skip the single-pass fast path */
 #define GFD_FLAG_TIMING 2        /* record HIP event timings for every kernel class */
-/* Counts only: match and violation counts and satisfied flags, with k_max = 0
- * (no tuples) and both fingerprints reported as 0.  Under GFD_SEM_MONO, a
- * pattern whose matching order ends in up to 3 leaves with one parent, equal
- * labels and edges, and literals on themselves alone has those leaves counted
- * per partial match (inclusion-exclusion over their candidate lists) instead
- * of enumerated: the leaf postponement of CFL-Match that Section IV-B adopts.
- * Two last leaves under different parents are counted together too: the
- * product of their lists' sizes less the vertices both lists hold. */
+/* Counts only: match and violation counts, satisfied flags and (k_max > 0)
+ * the first k_max violations; both fingerprints are reported as 0.  Under
+ * GFD_SEM_MONO, a pattern whose matching order ends in up to 3 leaves with
+ * one parent, equal labels and edges, and literals on themselves alone has
+ * those leaves counted per partial match (inclusion-exclusion over their
+ * candidate lists) instead of enumerated: the leaf postponement of CFL-Match
+ * that Section IV-B adopts.  Two last leaves under different parents are
+ * counted together too: the product of their lists' sizes less the vertices
+ * both lists hold.  With k_max > 0 only the last leaf is counted, and only
+ * when it is not variable 0; its level then runs again over the first-K
+ * window alone: the partial matches whose variable-0 vertex is at most that
+ * of the k_max-th violation (found from the per-match counts). */
 #define GFD_FLAG_COUNT_ONLY 4
 /* Run every launch eagerly.  By default a batch's main pass (its clears, the
  * candidate filter, CPI construction, enumeration with the literal check and

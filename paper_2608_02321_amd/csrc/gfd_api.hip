@@ -774,6 +774,9 @@ struct Plan {
   // parent leaf_par2) and order[k-1] (slot 1, parent leaf_par)
   bool leaf_split = false;
   int leaf_par2 = -1;
+  // a count-only call with K > 0: the one counted leaf's level is laid out
+  // but deferred; after the counts, it runs over the first-K window only
+  bool leaf_window = false;
 };
 
 static int32_t pair_code(const Plan& p, int a, int b, bool induced) {
@@ -1086,6 +1089,7 @@ struct Job {
   int cur[MAXK];  // which candidate buffer holds C(u) at the current step
   size_t last_rec = SIZE_MAX;  // offset of its last-level record in the batch's records
   bool last_single = false;    // that record is a single-vertex (k == 1) one
+  size_t leaf_rec = SIZE_MAX;  // offset of its leaf-count record, if any
 };
 
 // A call's plans, capacities and batches, with what they depend on besides
@@ -1093,7 +1097,7 @@ struct Job {
 // batch size).
 struct PlanMemo {
   std::vector<gfd_spec> specs;
-  uint64_t key[5] = {};
+  uint64_t key[6] = {};
   std::vector<Job> all;
   std::vector<std::vector<int>> batches;
   double est = 0;  // frontier bytes estimated for the call's GFDs
@@ -1650,12 +1654,16 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       const Plan& p = J.plan;
       ExtJob& e = E[i][x];
       e = ExtJob{};
-      if (i >= p.k_enum) continue;  // postponed leaves are counted, not enumerated
+      // postponed leaves are counted, not enumerated; a window job keeps its
+      // last level's record, deferred
+      const bool deferred = p.leaf_window && i == p.k - 1;
+      if (i >= p.k_enum && !deferred) continue;
       const int u = p.order[i], q = p.parent[u];
       e.active = 1;
+      e.deferred = deferred ? 1 : 0;
       e.i = i;
       e.k = p.k;
-      e.last = p.leaf_r == 0 && i == p.k - 1;
+      e.last = (p.leaf_r == 0 || deferred) && i == p.k - 1;
       e.begs = J.mem.begs;
       e.sc = job_scan_rec(c, J, J.mem.ctl + CTL_LEVEL_T + i, ep);
       e.home_P = J.mem.P;
@@ -1806,14 +1814,18 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
   for (int i = 1; i < maxk; i++) eoff[i] = R.add(E[i]);
   const size_t leaf_off = any_leaf ? R.add(F) : SIZE_MAX;
   const size_t prep2_off = any_split ? R.add(F2) : SIZE_MAX;
+  if (any_leaf)
+    for (int x = 0; x < nj; x++)
+      if (F[x].active) jobs[x].leaf_rec = leaf_off + sizeof(LeafJob) * x;
   for (int i = 1; i < maxk; i++) {
     bool any_last = false, any_inner = false;
     for (int x = 0; x < nj; x++) {
       const ExtJob& e = E[i][x];
       if (!e.active) continue;
+      if (e.last) jobs[x].last_rec = eoff[i] + sizeof(ExtJob) * x;
+      if (e.deferred) continue;  // runs after the main pass, over its window
       any_last |= e.last != 0;
       any_inner |= e.last == 0;
-      if (e.last) jobs[x].last_rec = eoff[i] + sizeof(ExtJob) * x;
     }
     // level 1's sources are the roots' candidates; deeper levels' sizes are
     // known only on the device, so their scans get the full grid
@@ -2621,7 +2633,7 @@ static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
 // the pass limit go to the bounded path (redo).
 static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> over,
                               const std::vector<ExtJob>& lastrec, uint64_t vsmall, std::vector<char>& redo,
-                              const std::function<void()>& while_busy) {
+                              const std::function<void()>& while_busy, bool preset = false) {
   Workspace* ws = c.ws;
   const DevGraph& g = c.g->dg;
   for (int pass = 0; !over.empty(); pass++) {
@@ -2629,13 +2641,16 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
       for (int x : over) redo[x] = 1;
       return;
     }
-    std::vector<SelJob> S;
-    for (int x : over) S.push_back(sel_job(c, jobs[x].plan.k, jobs[x].mem.vbuf, jobs[x].mem.ctl, vsmall));
-    run_select(c, S, true);
+    if (pass > 0 || !preset) {  // preset: the first pass's thresholds are already set
+      std::vector<SelJob> S;
+      for (int x : over) S.push_back(sel_job(c, jobs[x].plan.k, jobs[x].mem.vbuf, jobs[x].mem.ctl, vsmall));
+      run_select(c, S, true);
+    }
     // last-level records in collect-only form, multi-vertex and single-vertex
     std::vector<ExtJob> E[2];
     for (int x : over) {
       ExtJob e = lastrec[x];
+      e.deferred = 0;
       e.collect_only = 1;
       e.thr = (const int32_t*)(jobs[x].mem.ctl + CTL_THR);
       e.thr_incl = 1;
@@ -2691,6 +2706,100 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
   }
 }
 
+// Device records of jobs xs (offset off(x) in the batch's records at base)
+// into out[x]: one gather launch into the mapped staging (the main pass is
+// done with it) instead of a small DMA copy per job, where there is one.
+template <class Rec, class Off>
+static void read_recs(Ctx& c, const uint8_t* base, const std::vector<int>& xs, Off off,
+                      std::vector<Rec>& out) {
+  static_assert(sizeof(Rec) % 8 == 0, "records are copied as 8-byte words");
+  Workspace* ws = c.ws;
+  if (xs.empty()) return;
+  if (xs.size() > (size_t)MAX_JOBS) throw GfdError{GFD_EINVAL, "internal: too many records to read"};
+  if (ws->hjobrec_dev && ws->hjobrec_bytes >= sizeof(Rec) * xs.size()) {
+    RecGather gr{};
+    gr.n = (int32_t)xs.size();
+    gr.words = (uint32_t)(sizeof(Rec) / 8);
+    for (size_t i = 0; i < xs.size(); i++) gr.off[i] = off(xs[i]);
+    gather_recs(c.st, base, gr, (uint64_t*)ws->hjobrec_dev);
+    HIPCHK(hipStreamSynchronize(c.st));
+    for (size_t i = 0; i < xs.size(); i++) std::memcpy(&out[xs[i]], ws->hjobrec + i * sizeof(Rec), sizeof(Rec));
+  } else {
+    for (int x : xs)
+      HIPCHK(hipMemcpyAsync(&out[x], base + off(x), sizeof(Rec), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipStreamSynchronize(c.st));
+  }
+}
+
+// First-K windows of count-only jobs whose last leaf was counted (their
+// counts are final): a radix select over the variable-0 vertices of the
+// partial matches, weighted by each one's violating completions (the leaf
+// count again, in window form, over the partial matches of the decided
+// prefix), gives the variable-0 vertex d of the K-th violation, or no bound
+// when the job has fewer than K.  The deferred last level then runs
+// collect-only with the threshold (d, all ones): sources past d get no
+// attempts, and what it stages holds the first K.  Records: leafrec and
+// lastrec hold the jobs' device records as the main pass left them.
+static void run_windows(Ctx& c, std::vector<Job>& jobs, const std::vector<int>& win,
+                        const std::vector<LeafJob>& leafrec, const std::vector<ExtJob>& lastrec,
+                        uint64_t vsmall, std::vector<char>& redo, const std::function<void()>& while_busy) {
+  Workspace* ws = c.ws;
+  const DevGraph& g = c.g->dg;
+  const int nw = (int)win.size();
+  if (nw == 0) return;
+  int idbits = 1;
+  while (idbits < 31 && (int64_t(1) << idbits) < (int64_t)c.g->n) idbits++;
+  const int npass = (idbits + RADIX_BITS - 1) / RADIX_BITS;
+  std::vector<WinJob> W(nw);
+  std::vector<LeafJob> F(nw);
+  // per job: the histogram, prefix and rank, in the bounded path's chunk
+  // buffer (that path runs after the windows, if at all)
+  ensure_chunk(ws, sizeof(unsigned long long) * (RADIX_BINS + 2) * (size_t)nw);
+  for (int i = 0; i < nw; i++) {
+    Job& J = jobs[win[i]];
+    auto* hist = (unsigned long long*)ws->chunk + (size_t)i * (RADIX_BINS + 2);
+    W[i] = WinJob{1, J.plan.k, (uint64_t)c.K, hist, (uint32_t*)(hist + RADIX_BINS), hist + RADIX_BINS + 1,
+                  (int32_t*)(J.mem.ctl + CTL_THR), (uint32_t*)(J.mem.ctl + CTL_THRVALID),
+                  J.mem.ctl + CTL_VCOUNT};
+    F[i] = leafrec[win[i]];
+    F[i].whist = hist;
+    F[i].wprefix = W[i].prefix;
+    F[i].wkey_pos = J.plan.pos[0];
+  }
+  // every pass's records at once (the staging is read when the copy runs)
+  const size_t wb = align_up(sizeof(WinJob) * nw), fb = align_up(sizeof(LeafJob) * nw);
+  const size_t bytes = wb + fb * npass;
+  ensure_recs(ws, bytes);
+  HIPCHK(hipStreamSynchronize(c.st));
+  std::memcpy(ws->hjobrec, W.data(), sizeof(WinJob) * nw);
+  auto digit = [&](int ps, int& shift, int& bits) {
+    shift = std::max(0, idbits - RADIX_BITS * (ps + 1));
+    bits = idbits - RADIX_BITS * ps - shift;
+  };
+  for (int ps = 0; ps < npass; ps++) {
+    int shift, bits;
+    digit(ps, shift, bits);
+    for (LeafJob& f : F) {
+      f.wshift = shift;
+      f.wbits = bits;
+    }
+    std::memcpy(ws->hjobrec + wb + fb * ps, F.data(), sizeof(LeafJob) * nw);
+  }
+  upload_recs(c, 0, bytes);
+  const WinJob* wr = (const WinJob*)ws->jobrec;
+  c.tm.run(K_TOPK, [&] { win_begin(c.st, wr, nw); });
+  for (int ps = 0; ps < npass; ps++) {
+    int shift, bits;
+    digit(ps, shift, bits);
+    const LeafJob* fr = (const LeafJob*)(ws->jobrec + wb + fb * ps);
+    c.tm.run(K_LAST, [&] {
+      leaf_count(c.st, g, fr, nw, flat_grid(enum_grid(c), enum_grid(c)), false, cls_bytes(c, K_LAST));
+    });
+    c.tm.run(K_TOPK, [&] { win_digit(c.st, wr, nw, shift, bits, ps == npass - 1); });
+  }
+  rerun_last_levels(c, jobs, win, lastrec, vsmall, redo, while_busy, true);
+}
+
 // Leaf postponement for a count-only call under the non-induced reading: the
 // longest tail of the matching order made of leaves (skeleton degree 1) with
 // one common parent, the same vertex label and the same edges to it, and
@@ -2700,21 +2809,27 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
 // under another parent, the two are counted together (split leaves): the
 // product of their lists' counts less the vertices both lists hold.
 // (Under the induced reading a leaf must also avoid edges to every other
-// matched vertex, which the per-list counts cannot see.)
-static void plan_leaves(const gfd_spec& s, bool induced, bool count_only, Plan& p) {
+// matched vertex, which the per-list counts cannot see.)  A call that lists
+// the first K > 0 violations counts only the last leaf, and only when it is
+// not variable 0: the window of the first K is bounded by the variable-0
+// vertex of the partial matches, whose violating completions the counts give.
+static void plan_leaves(const gfd_spec& s, bool induced, bool count_only, int K, Plan& p) {
   p.leaf_r = 0;
   p.k_enum = p.k;
   p.leaf_par = -1;
   p.leaf_split = false;
   p.leaf_par2 = -1;
+  p.leaf_window = false;
   for (int t = 0; t < 2 * MAXLIT; t++) p.lit_leaf[t] = -1;
   if (!count_only || induced || p.k < 2) return;
+  if (K > 0 && p.order[p.k - 1] == 0) return;
   int deg[MAXK] = {};
   for (int a = 0; a < p.k; a++)
     for (int b = 0; b < p.k; b++)
       if (a != b && (p.qe[a][b] != NOEDGE || p.qe[b][a] != NOEDGE)) deg[a]++;
   int r = 0;
-  for (int i = p.k - 1; i >= 1 && r < MAX_LEAVES; i--) {
+  const int rmax = K > 0 ? 1 : MAX_LEAVES;
+  for (int i = p.k - 1; i >= 1 && r < rmax; i--) {
     const int u = p.order[i], u0 = p.order[p.k - 1], q = p.parent[u];
     if (deg[u] != 1 || p.core[u] || q != p.parent[u0] || p.pos[q] >= p.k - 1 - r) break;
     if (p.qlab[u] != p.qlab[u0] || p.qe[q][u] != p.qe[q][u0] || p.qe[u][q] != p.qe[u0][q]) break;
@@ -2734,7 +2849,7 @@ static void plan_leaves(const gfd_spec& s, bool induced, bool count_only, Plan& 
     return true;
   };
   bool split = false;
-  if (r == 1 && p.k >= 3) {
+  if (r == 1 && p.k >= 3 && K == 0) {
     const int ua = p.order[p.k - 2], ub = p.order[p.k - 1];
     const int qa = p.parent[ua], qb = p.parent[ub];
     split = deg[ua] == 1 && !p.core[ua] && !p.virt[ua] && qa != qb && p.pos[qa] < p.k - 2 &&
@@ -2748,6 +2863,7 @@ static void plan_leaves(const gfd_spec& s, bool induced, bool count_only, Plan& 
   p.leaf_r = r;
   p.k_enum = p.k - r;
   p.leaf_par = p.parent[p.order[p.k - 1]];
+  p.leaf_window = K > 0;
   if (split) {
     p.leaf_split = true;
     p.leaf_par2 = p.parent[p.order[p.k - 2]];
@@ -2885,7 +3001,6 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
       return set_error(GFD_EINVAL, "tuning out of range");
   }
   const bool count_only = (o.flags & GFD_FLAG_COUNT_ONLY) != 0;
-  if (count_only && o.k_max != 0) return set_error(GFD_EINVAL, "a count-only call needs k_max = 0");
   for (int32_t i = 0; i < num_specs; i++) {
     const int32_t rc = check_spec(g, specs[i], i);
     if (rc) return rc;
@@ -2927,8 +3042,8 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     // plans, capacities and batches (those of the last call on this
     // workspace when it had the same GFDs and options)
     std::optional<Range> phase(std::in_place, "plan");
-    const uint64_t mkey[5] = {(uint64_t)c.induced, (uint64_t)count_only, vsmall, (uint64_t)budget,
-                              (uint64_t)max_batch};
+    const uint64_t mkey[6] = {(uint64_t)c.induced, (uint64_t)count_only, vsmall, (uint64_t)budget,
+                              (uint64_t)max_batch, (uint64_t)c.K};
     PlanMemo* pm = ws->memo.get();
     if (!(pm && pm->specs.size() == (size_t)num_specs && !std::memcmp(pm->key, mkey, sizeof mkey) &&
           !std::memcmp(pm->specs.data(), specs, sizeof(gfd_spec) * (size_t)num_specs))) {
@@ -2938,7 +3053,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         Job& J = m->all[i];
         J.spec = i;
         make_plan(g, specs[i], c.induced, J.plan);
-        plan_leaves(specs[i], c.induced, count_only, J.plan);
+        plan_leaves(specs[i], c.induced, count_only, c.K, J.plan);
         job_caps(g, J.plan, 0, vsmall, false, J.caps);
         m->est += (double)est_front_bytes(g, J.plan);
       }
@@ -3050,6 +3165,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         const bool grew_c = grow_cpi(ws, ws->hmisc[0]);
         const bool grew = grew_f || grew_c;
         std::vector<int> over;  // only the violation staging overflowed
+        std::vector<int> win;   // counted last leaf, violations to list: a first-K window
         std::vector<int> again, solo;
         for (size_t x = 0; x < jobs.size(); x++) {
           const uint64_t* h = ws->hctl + CTL_WORDS * x;
@@ -3071,6 +3187,8 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
             } else {
               redo[x] = 1;
             }
+          } else if (K > 0 && jobs[x].plan.leaf_window) {
+            if (h[CTL_VIOL] > 0 && !(h[CTL_FLAGS] & FLAG_COUNTER_OVERFLOW)) win.push_back((int)x);
           } else if (K > 0 && h[CTL_VCOUNT] > vsmall) {
             over.push_back((int)x);
           }
@@ -3083,26 +3201,14 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         if (stats) stats->regrown_gfds += (int32_t)solo.size();
         // the last-level records of the jobs to re-run, as the device holds
         // them (their sources were placed by the frontier reservations)
+        // (and the leaf-count records of the window jobs)
         std::vector<ExtJob> lastrec(jobs.size());
-        if (!over.empty()) {
-          static_assert(sizeof(ExtJob) % 8 == 0, "records are copied as 8-byte words");
-          if (ws->hjobrec_dev && ws->hjobrec_bytes >= sizeof(ExtJob) * over.size()) {
-            // one gather launch into the mapped staging (the main pass is
-            // done with it) instead of a small DMA copy per job
-            RecGather gr{};
-            gr.n = (int32_t)over.size();
-            gr.words = (uint32_t)(sizeof(ExtJob) / 8);
-            for (size_t i = 0; i < over.size(); i++) gr.off[i] = jobs[over[i]].last_rec;
-            gather_recs(c.st, recbase, gr, (uint64_t*)ws->hjobrec_dev);
-            HIPCHK(hipStreamSynchronize(c.st));
-            for (size_t i = 0; i < over.size(); i++)
-              std::memcpy(&lastrec[over[i]], ws->hjobrec + i * sizeof(ExtJob), sizeof(ExtJob));
-          } else {
-            for (int x : over)
-              HIPCHK(hipMemcpyAsync(&lastrec[x], recbase + jobs[x].last_rec, sizeof(ExtJob),
-                                    hipMemcpyDeviceToHost, c.st));
-            HIPCHK(hipStreamSynchronize(c.st));
-          }
+        std::vector<LeafJob> leafrec(jobs.size());
+        {
+          std::vector<int> xs(over);
+          xs.insert(xs.end(), win.begin(), win.end());
+          read_recs(c, recbase, xs, [&](int x) { return jobs[x].last_rec; }, lastrec);
+          read_recs(c, recbase, win, [&](int x) { return jobs[x].leaf_rec; }, leafrec);
         }
         // jobs whose first K the last level's sort already wrote go out now
         std::unique_ptr<ResultDrain> D;
@@ -3111,6 +3217,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
           D.reset(new ResultDrain(c, jobs, results, H, K));
           std::vector<char> isover(jobs.size(), 0);
           for (int x : over) isover[x] = 1;
+          for (int x : win) isover[x] = 1;
           std::vector<int> fin;
           for (size_t x = 0; x < jobs.size(); x++)
             if (!redo[x] && !isover[x] && !H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL]) {
@@ -3124,6 +3231,15 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
           const Range rerun("threshold re-run");
           rerun_last_levels(c, jobs, over, lastrec, vsmall, redo, [&] { if (D) D->drain(); });
           for (int x : over)
+            if (!redo[x]) {
+              H[(size_t)jobs[x].spec * CTL_WORDS + CTL_VCOUNT] = ws->hctl[CTL_WORDS * x + CTL_VCOUNT];
+              H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL] = ws->hctl[CTL_WORDS * x + CTL_NEEDSEL];
+            }
+        }
+        if (!win.empty()) {
+          const Range window("first-K window");
+          run_windows(c, jobs, win, leafrec, lastrec, vsmall, redo, [&] { if (D) D->drain(); });
+          for (int x : win)
             if (!redo[x]) {
               H[(size_t)jobs[x].spec * CTL_WORDS + CTL_VCOUNT] = ws->hctl[CTL_WORDS * x + CTL_VCOUNT];
               H[(size_t)jobs[x].spec * CTL_WORDS + CTL_NEEDSEL] = ws->hctl[CTL_WORDS * x + CTL_NEEDSEL];
@@ -3472,7 +3588,7 @@ extern "C" int32_t gfd_server_create(const gfd_graph* gc, const gfd_server_opts*
       const Sizing sz = call_sizing(s->budget, o.max_batch_gfds, o.max_batch_gfds, o.k_max, 0);
       Plan p;
       make_plan(s->g, path, o.semantics == GFD_SEM_INDUCED, p);
-      plan_leaves(path, o.semantics == GFD_SEM_INDUCED, false, p);
+      plan_leaves(path, o.semantics == GFD_SEM_INDUCED, false, 0, p);
       JobCaps caps;
       job_caps(s->g, p, 0, sz.vsmall, false, caps);
       reserve = std::min<int64_t>(s->budget, (int64_t)o.max_batch_gfds * (int64_t)align_up(caps.bytes) +
@@ -3527,7 +3643,7 @@ extern "C" int32_t gfd_server_submit(gfd_server* s, const gfd_spec* specs, int32
       if (rc) return rc;
       Plan p;
       make_plan(s->g, specs[i], induced, p);
-      plan_leaves(specs[i], induced, false, p);
+      plan_leaves(specs[i], induced, false, 0, p);
       JobCaps caps;
       job_caps(s->g, p, 0, sz.vsmall, false, caps);
       // its candidate and CPI structures, staging and estimated frontiers

@@ -262,6 +262,11 @@ struct ExtJob {
   uint64_t vcap;
   const int32_t* thr;
   const uint32_t* d_thr_valid;
+  // the last level of a count-only job whose last leaf is counted: its
+  // record is laid out (the frontier reservation points it at its sources)
+  // but the main pass skips it; it runs later only over the window of
+  // sources that can hold the first K violations
+  int32_t deferred;
 };
 
 // Leaf postponement (count-only calls): the last r (<= MAX_LEAVES) vertices
@@ -327,6 +332,29 @@ struct LeafJob {
   int32_t dir2, prim2, other2;
   const uint32_t* cnt2;
   int32_t lit_leaf2[2 * MAXLIT];
+  // window pass (whist != nullptr): nothing is counted; each partial match
+  // whose variable-0 vertex (at position wkey_pos) agrees with the decided
+  // high bits *wprefix above bit wshift + wbits adds its violating
+  // completions to whist[bits wshift .. wshift + wbits of that vertex]
+  unsigned long long* whist;
+  const uint32_t* wprefix;
+  int32_t wkey_pos, wshift, wbits;
+};
+
+// The first-K window of a job whose last leaf was counted: a radix select over
+// the variable-0 vertices of the partial matches, weighted by their violating
+// completions, finds the variable-0 vertex d of the K-th violation.  Its
+// threshold (d, then all ones) then bounds a collect-only run of the last
+// level: sources past it get no attempts.
+struct WinJob {
+  int32_t active, k;
+  uint64_t K;
+  unsigned long long* hist;  // [RADIX_BINS], zero at rest
+  uint32_t* prefix;          // decided bits of d
+  unsigned long long* rank;  // remaining rank within the decided prefix
+  int32_t* thr;              // [k]
+  uint32_t* d_thr_valid;
+  uint64_t* d_vcount;
 };
 
 struct TopkJob {
@@ -440,6 +468,11 @@ void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs
 // counters; `split` picks the jobs with split leaves, else the others
 void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid,
                 bool split, unsigned long long* bytes);
+// window select: before the first digit, prefix = 0 and rank = K; each call
+// decides `bits` bits at `shift` from the histogram (and clears it); the
+// last writes the threshold and restarts the staging count
+void win_begin(hipStream_t st, const WinJob* jobs, int njobs);
+void win_digit(hipStream_t st, const WinJob* jobs, int njobs, int shift, int bits, bool last);
 
 // Batched radix select (grid row = job); requires more than K staged tuples
 // per active job.  sel_pass decides `bits` bits of tuple word `word` starting

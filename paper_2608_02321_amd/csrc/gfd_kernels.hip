@@ -1454,7 +1454,7 @@ __device__ __forceinline__ bool source_past(const ExtJob& J, uint64_t s,
 __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __restrict__ jobs,
                                                  int njobs) {
   shared_scan_blocks(njobs, [&](int j) -> uint64_t {
-    return jobs[j].active ? ext_sources(jobs[j]) : ~0ull;
+    return jobs[j].active && !jobs[j].deferred ? ext_sources(jobs[j]) : ~0ull;
   }, [&](int jb, uint64_t nb) {
     const ExtJob& J = jobs[jb];
     const int32_t* par = J.src_cols + (uint64_t)J.par_pos * J.src_stride;
@@ -1483,7 +1483,7 @@ __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __res
 // inner-level variant skips it, and the other way round).
 template <bool LAST>
 __device__ __forceinline__ uint64_t ext_width(const ExtJob& J) {
-  if (!J.active || (J.last != 0) != LAST) return 0;
+  if (!J.active || J.deferred || (J.last != 0) != LAST) return 0;
   const uint64_t T = ext_sources(J) ? *J.sc.d_total : 0ull;
   const uint64_t A1 = J.a_end < T ? J.a_end : T;
   return A1 > J.a_begin ? A1 - J.a_begin : 0ull;
@@ -2120,7 +2120,13 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
   FinalAcc acc{0, 0, 0, 0};
   bool ovf = false;
   if (SPLIT) leaf_split_chunk(g, J, s0, s1, acc, ovf, by);
+  // window pass: the decided high bits of the variable-0 vertex
+  const int whs = J.wshift + J.wbits;
+  const uint32_t wpre = J.whist && whs < 32 ? *J.wprefix >> whs : 0u;
   for (uint64_t s = s0 + threadIdx.x; s < s1 && !SPLIT; s += BS) {
+    if (J.whist && whs < 32 &&
+        ((uint32_t)J.src_cols[(uint64_t)J.wkey_pos * J.src_stride + s] >> whs) != wpre)
+      continue;  // outside the decided prefix
     // the partial match, its parent's row in the count table and the words read
     by += 4ull * (uint64_t)J.i + 4 + 4ull * LEAF_WORDS;
     int32_t h[MAXK];
@@ -2156,6 +2162,16 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
       if (t < J.nx) X = X && v;
       else Y = Y && v;
     }
+    if (J.whist) {  // window pass: this match's violating completions, by digit
+      if (X) {
+        const __int128 ix = leaf_injective(J.r, c[1]);
+        const __int128 v = Y ? ix - leaf_injective(J.r, c[2]) : ix;
+        const uint32_t key = (uint32_t)pick(h, J.wkey_pos);
+        if (v > 0 && v <= (__int128)LEAF_COUNT_MAX)
+          atomicAdd(&J.whist[(key >> J.wshift) & ((1u << J.wbits) - 1u)], (unsigned long long)v);
+      }
+      continue;
+    }
     acc.match += leaf_add(leaf_injective(J.r, c[0]), ovf);
     if (X) {
       const __int128 ix = leaf_injective(J.r, c[1]);
@@ -2171,6 +2187,77 @@ __global__ __launch_bounds__(BS) void k_leaf_count(DevGraph g, const LeafJob* __
 void leaf_prep(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid) {
   hipLaunchKernelGGL(k_leaf_prep, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
 }
+// Window select (one block per job).  win_begin clears the histogram and
+// starts the rank at K.  A digit step finds the bin holding the remaining
+// rank (a block scan of the weighted histogram), records its digit in the
+// prefix and clears the bins; a prefix whose group holds fewer violations
+// than the rank (only when the job has fewer than K) leaves the window
+// unbounded: rank 0 and a prefix of all ones.  The last step writes the
+// threshold (d, then all ones, in variable order) and restarts the staging.
+__global__ __launch_bounds__(BS) void k_win_begin(const WinJob* __restrict__ jobs) {
+  const WinJob& J = jobs[blockIdx.x];
+  if (!J.active) return;
+  for (int b = threadIdx.x; b < RADIX_BINS; b += BS) J.hist[b] = 0ull;
+  if (threadIdx.x == 0) {
+    *J.prefix = 0u;
+    *J.rank = J.K;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_win_digit(const WinJob* __restrict__ jobs, int shift,
+                                                  int bits, int last) {
+  constexpr int PER = RADIX_BINS / BS;
+  const WinJob& J = jobs[blockIdx.x];
+  if (!J.active) return;
+  const unsigned long long r = *J.rank;  // read before the barriers, written after
+  const uint32_t nb = 1u << bits;
+  unsigned long long h[PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < PER; j++) {
+    const uint32_t bin = threadIdx.x * PER + j;
+    h[j] = bin < nb ? J.hist[bin] : 0ull;
+    sum += h[j];
+  }
+  uint64_t total;
+  const uint64_t pre = block_excl_scan64(sum, total);
+  __syncthreads();
+  if (r != 0) {
+    if (total < r) {
+      if (threadIdx.x == 0) {
+        *J.prefix = 0xFFFFFFFFu;
+        *J.rank = 0ull;
+      }
+    } else if (pre < r && r <= pre + sum) {  // exactly one thread
+      unsigned long long cum = pre;
+      uint32_t d = threadIdx.x * PER;
+      for (int j = 0; j < PER; j++) {
+        if (cum + h[j] >= r) {
+          d = threadIdx.x * PER + j;
+          break;
+        }
+        cum += h[j];
+      }
+      *J.prefix |= d << shift;
+      *J.rank = r - cum;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; j++) J.hist[threadIdx.x * PER + j] = 0ull;
+  __syncthreads();  // the prefix is final
+  if (last && threadIdx.x < (uint32_t)J.k) J.thr[threadIdx.x] = threadIdx.x == 0 ? (int32_t)*J.prefix : -1;
+  if (last && threadIdx.x == 0) {
+    *J.d_thr_valid = 1u;
+    *J.d_vcount = 0ull;
+  }
+}
+
+void win_begin(hipStream_t st, const WinJob* jobs, int njobs) {
+  hipLaunchKernelGGL(k_win_begin, dim3(njobs), dim3(BS), 0, st, jobs);
+}
+void win_digit(hipStream_t st, const WinJob* jobs, int njobs, int shift, int bits, bool last) {
+  hipLaunchKernelGGL(k_win_digit, dim3(njobs), dim3(BS), 0, st, jobs, shift, bits, last ? 1 : 0);
+}
+
 void leaf_count(hipStream_t st, const DevGraph& g, const LeafJob* jobs, int njobs, int grid,
                 bool split, unsigned long long* bytes) {
   if (split) hipLaunchKernelGGL(k_leaf_count<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);

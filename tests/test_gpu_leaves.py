@@ -114,9 +114,6 @@ def test_counted_leaves_match_oracle(P, batched):
                      batched=batched)
     for a, b in zip(full, cnt):
         assert (a["match_count"], a["violation_count"]) == (b["match_count"], b["violation_count"])
-    with pytest.raises(P.GfdError) as ei:
-        P.validate(gh, gfds[:1], K=4, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY)
-    assert ei.value.code == -1
     gh.free()
 
 
@@ -174,6 +171,61 @@ def test_count_only_random_shapes(P):
     gh.free()
 
 
+def _oracle_first_k(og, d, sem, K):
+    return dict(O.validate(og, d, sem, K=K, threads=4), match_fp=0, violation_fp=0)
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_counted_leaf_with_first_k(P, batched):
+    """Count-only calls that also list the first K violations: the last leaf
+    is counted, then only the window of partial matches whose variable-0
+    vertex is at most that of the K-th violation is enumerated.  Counts,
+    flags and the listed violations equal the oracle's (fingerprints are 0)
+    for K below, near and above the violation counts, in both readings."""
+    g = random_graph(33, 250, 12000, n_vlabels=2, n_elabels=3, n_attrs=2, attr_values=3,
+                     absent_frac=0.1, reciprocal_frac=0.4)
+    og = O.OracleGraph(g)
+    gh = P.load(g)
+    gfds = [d for d, _ in CASES] + SPLIT_CASES
+    viol = [O.validate(og, d, "mono", K=0, threads=4)["violation_count"] for d in gfds]
+    assert sum(v > 2048 for v in viol) >= 3 and sum(0 < v < 2048 for v in viol) >= 3, viol
+    for K in (1, 7, 100, 2048):
+        for sem in ("mono", "induced"):
+            got, st = P.validate(gh, gfds, K=K, semantics=sem, flags=P.GFD_FLAG_COUNT_ONLY,
+                                 stats=True, batched=batched)
+            for i, (d, r) in enumerate(zip(gfds, got)):
+                assert r == _oracle_first_k(og, d, sem, K), (K, sem, i)
+            if sem == "mono":  # the counted last leaf with its window
+                assert st["leaf_gfds"] >= 6 and st["leaf_split_gfds"] == 0, (K, st)
+    if batched:  # the same call again: captured, then replayed as a graph
+        exp = [_oracle_first_k(og, d, "mono", 100) for d in gfds]
+        replays = 0
+        for _ in range(3):
+            got, st = P.validate(gh, gfds, K=100, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
+                                 stats=True, batched=True)
+            assert got == exp
+            replays += st["graph_replays"]
+        assert replays > 0
+    gh.free()
+
+
+def test_counted_leaf_window_past_the_staging(P):
+    """A window whose violations overflow the (small, testing) staging runs
+    the threshold re-runs over the deferred last level: still exact."""
+    g = random_graph(33, 250, 12000, n_vlabels=2, n_elabels=3, n_attrs=2, attr_values=3,
+                     absent_frac=0.1, reciprocal_frac=0.4)
+    og = O.OracleGraph(g)
+    gh = P.load(g)
+    gfds = [d for d, q in CASES if q] + SPLIT_CASES[:SPLIT_COUNTED]
+    for K, cap in ((5, 6), (40, 41), (300, 512)):
+        got, st = P.validate(gh, gfds, K=K, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
+                             violation_cap=cap, stats=True, batched=True)
+        for i, (d, r) in enumerate(zip(gfds, got)):
+            assert r == _oracle_first_k(og, d, "mono", K), (K, i)
+        assert st["threshold_passes"] > 0, st
+    gh.free()
+
+
 def test_counted_leaves_under_frontier_overflow(P):
     """A job whose inner frontier overflows is redone on the bounded path,
     which enumerates everything: counts stay exact."""
@@ -203,6 +255,26 @@ def test_twitch_star_counted(P):
         assert (r["match_count"], r["violation_count"], r["satisfied"]) == \
             (e["match_count"], e["violation_count"], e["satisfied"])
     assert st["leaf_gfds"] >= 2  # both star forms
+    gh.free()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_counted_leaf_windows_full_size_batch(P):
+    """The 256-GFD workload under the non-induced reading, count-only with
+    the first K listed: counts, flags and the first K violations of every GFD
+    equal the stored oracle results."""
+    import gzip
+    with gzip.open(os.path.join(GOLDEN, "expected_kg_4m_batch256.json.gz"), "rt") as f:
+        exp = json.load(f)
+    g = configs.graph("kg_4m")
+    assert g.sha256() == exp["graph_sha256"]
+    gh = P.load(g)
+    got, st = P.validate(gh, exp["gfds"], K=exp["K"], semantics="mono",
+                         flags=P.GFD_FLAG_COUNT_ONLY, stats=True, batched=True)
+    for i, (r, e) in enumerate(zip(got, exp["results"]["mono"])):
+        assert r == dict(e, match_fp=0, violation_fp=0), i
+    assert st["leaf_gfds"] > 50
     gh.free()
 
 
