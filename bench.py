@@ -40,13 +40,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "6788e38304d21008daf7212ce70f02eb9353745b4c97b9a4cfcc0b7a0986314c",
+    "sources_sha256": "246fa0866a7e2e933270b6abe17241568898d53363f81da3736f6b88e01103e8",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true, false, 8>
     "semantics": "induced",
     "count_only": False,
-    # (601.24 MB read + 38.24 MB written) per dispatch, calibrated (x1.9999, x1.0)
-    "bytes_per_launch": 6.3948e+08,
+    # (614.81 MB read + 39.80 MB written) per dispatch, calibrated (x1.9999, x1.0)
+    "bytes_per_launch": 6.5461e+08,
 }
 # Units of work of the dominant kernel class per step (one validate call),
 # from the counting build (bench.py --units; see profiles/), and the
@@ -57,17 +57,17 @@ TRAFFIC = {
 # small threshold re-run launch or not, which leaves the work per step as it
 # is.  Valid only for the kernel sources it was counted on.
 UNITS = {
-    "sources_sha256": "6788e38304d21008daf7212ce70f02eb9353745b4c97b9a4cfcc0b7a0986314c",
+    "sources_sha256": "246fa0866a7e2e933270b6abe17241568898d53363f81da3736f6b88e01103e8",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",
     "semantics": "induced",
     "count_only": False,
-    "per_step": {"attempts": 158354818, "sources": 12610581, "injective": 158343231,
-                 "checks_both": 416247167, "table_free": 361338655, "table_hit": 8271768,
-                 "short_row": 46636744, "both_steps": 205750170, "both_log2d": 3853948926,
+    "per_step": {"attempts": 158411055, "sources": 12610005, "injective": 158399468,
+                 "checks_both": 416450140, "table_free": 361509556, "table_hit": 8276218,
+                 "short_row": 46664366, "both_steps": 205852888, "both_log2d": 3855567436,
                  "checks_one": 0, "one_steps": 0, "one_log2d": 0, "matches": 147891222,
-                 "literal_reads": 162656672, "violations": 68082422, "inner_attempts": 19554114},
-    "model_bytes_per_step": 3.22165e10,
+                 "literal_reads": 162738923, "violations": 68082422, "inner_attempts": 19481978},
+    "model_bytes_per_step": 3.22300e10,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
