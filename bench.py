@@ -40,13 +40,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "246fa0866a7e2e933270b6abe17241568898d53363f81da3736f6b88e01103e8",
+    "sources_sha256": "a4499f7efbe1847f251d4015c41128cef1d5c369d7a6f554482bf96c42ab3325",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true, false, 8>
     "semantics": "induced",
     "count_only": False,
-    # (614.81 MB read + 39.80 MB written) per dispatch, calibrated (x1.9999, x1.0)
-    "bytes_per_launch": 6.5461e+08,
+    # (614.96 MB read + 38.52 MB written) per dispatch, calibrated (x1.9999, x1.0)
+    "bytes_per_launch": 6.5348e+08,
 }
 # Units of work of the dominant kernel class per step (one validate call),
 # from the counting build (bench.py --units; see profiles/), and the
@@ -57,17 +57,17 @@ TRAFFIC = {
 # small threshold re-run launch or not, which leaves the work per step as it
 # is.  Valid only for the kernel sources it was counted on.
 UNITS = {
-    "sources_sha256": "246fa0866a7e2e933270b6abe17241568898d53363f81da3736f6b88e01103e8",
+    "sources_sha256": "a4499f7efbe1847f251d4015c41128cef1d5c369d7a6f554482bf96c42ab3325",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",
     "semantics": "induced",
     "count_only": False,
-    "per_step": {"attempts": 158411055, "sources": 12610005, "injective": 158399468,
-                 "checks_both": 416450140, "table_free": 361509556, "table_hit": 8276218,
-                 "short_row": 46664366, "both_steps": 205852888, "both_log2d": 3855567436,
+    "per_step": {"attempts": 158308686, "sources": 12606490, "injective": 158297099,
+                 "checks_both": 416145054, "table_free": 361254429, "table_hit": 8270603,
+                 "short_row": 46620022, "both_steps": 205695920, "both_log2d": 3853021239,
                  "checks_one": 0, "one_steps": 0, "one_log2d": 0, "matches": 147891222,
-                 "literal_reads": 162738923, "violations": 68082422, "inner_attempts": 19481978},
-    "model_bytes_per_step": 3.22300e10,
+                 "literal_reads": 162615135, "violations": 68082422, "inner_attempts": 19481978},
+    "model_bytes_per_step": 3.22087e10,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 

@@ -1910,7 +1910,7 @@ static void run_launch(Ctx& c, const Launch& l) {
       case 0: {
         auto* r = (const FilterJob*)(base + l.off);
         if (l.scan) {
-          if (l.row_scan) c.tm.run(K_SCAN, [&] { filter_scan(c.st, g, r, l.njobs, l.gx_scan); });
+          if (l.row_scan) c.tm.run(K_SCAN, [&] { filter_scan(c.st, g, r, l.njobs, l.gx_scan, cls_bytes(c, K_SCAN)); });
           c.tm.run(K_PULL, [&] {
             filter_pull(c.st, g, r, l.njobs, l.gx_work, l.hit_bitmaps, cls_bytes(c, K_PULL));
           });
@@ -1922,7 +1922,7 @@ static void run_launch(Ctx& c, const Launch& l) {
       }
       case 1: {
         auto* r = (const CpiJob*)(base + l.off);
-        c.tm.run(K_SCAN, [&] { cpi_scan(c.st, g, r, l.njobs, l.gx_scan); });
+        c.tm.run(K_SCAN, [&] { cpi_scan(c.st, g, r, l.njobs, l.gx_scan, cls_bytes(c, K_SCAN)); });
         if (l.cpi_two_pass) {  // lists sized by their kept entries
           c.tm.run(K_CPI, [&] { cpi_count(c.st, g, r, l.njobs, l.gx_work, cls_bytes(c, K_CPI)); });
           c.tm.run(K_CPI, [&] { cpi_alloc(c.st, g, r, l.njobs, l.gx_item); });
@@ -1936,7 +1936,7 @@ static void run_launch(Ctx& c, const Launch& l) {
       }
       case 2: {
         auto* r = (const ExtJob*)(base + l.off);
-        c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, r, l.njobs, l.gx_scan); });
+        c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, r, l.njobs, l.gx_scan, cls_bytes(c, K_SCAN)); });
         if (l.inner_any)  // next frontiers, sized by this level's attempts
           c.tm.run(K_OTHER, [&] {
             front_reserve(c.st, (ExtJob*)(base + l.off),
@@ -1969,7 +1969,7 @@ static void run_launch(Ctx& c, const Launch& l) {
       }
       case 4: {
         auto* r = (const TopkJob*)(base + l.off);
-        c.tm.run(K_TOPK, [&] { topk_small(c.st, r, l.njobs); });
+        c.tm.run(K_TOPK, [&] { topk_small(c.st, r, l.njobs, cls_bytes(c, K_TOPK)); });
         break;
       }
     }
@@ -2385,10 +2385,10 @@ static void run_select(Ctx& c, std::vector<SelJob>& S, bool threshold) {
     for (int ps = 0; ps < npass; ps++) {
       const int shift = std::max(0, idbits - RADIX_BITS * (ps + 1));
       const int bits = idbits - RADIX_BITS * ps - shift;
-      c.tm.run(K_TOPK, [&] { sel_pass(c.st, r, nj, w, shift, bits, gx); });
+      c.tm.run(K_TOPK, [&] { sel_pass(c.st, r, nj, w, shift, bits, gx, cls_bytes(c, K_TOPK)); });
     }
   if (threshold) c.tm.run(K_TOPK, [&] { sel_threshold(c.st, r, nj); });
-  else c.tm.run(K_TOPK, [&] { sel_first_k(c.st, r, nj, gx); });
+  else c.tm.run(K_TOPK, [&] { sel_first_k(c.st, r, nj, gx, cls_bytes(c, K_TOPK)); });
 }
 
 static SelJob sel_job(Ctx& c, int k, const int32_t* vbuf, uint64_t* ctl, uint64_t vcap) {
@@ -2508,7 +2508,7 @@ struct Bounded {
     upload_one(e);
     const DevGraph& g = c.g->dg;
     const ExtJob* rec = (const ExtJob*)c.ws->jobrec;
-    c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, rec, 1, scan_grid(1, e.src_cap)); });
+    c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, rec, 1, scan_grid(1, e.src_cap), cls_bytes(c, K_SCAN)); });
     const uint64_t T = rd(CTL_LEVEL_T + i);
     if (c.stats) c.stats->attempts += T;
     const uint64_t W = e.last ? (c.K > 0 ? c.ws->vbig_cap - (uint64_t)c.K : std::max<uint64_t>(T, 1))
@@ -2611,7 +2611,7 @@ static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
     HIPCHK(hipStreamSynchronize(c.st));
     std::memcpy(ws->hjobrec, T.data(), sizeof(TopkJob));
     upload_recs(c, 0, sizeof(TopkJob));
-    c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)ws->jobrec, 1); });
+    c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)ws->jobrec, 1, cls_bytes(c, K_TOPK)); });
     HIPCHK(hipMemcpyAsync(ws->hctl, B.mem.ctl, sizeof(uint64_t) * CTL_WORDS, hipMemcpyDeviceToHost, c.st));
     HIPCHK(hipStreamSynchronize(c.st));
     if (ws->hctl[CTL_NEEDSEL]) {
@@ -2675,7 +2675,9 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     uint64_t srcs = 1;
     for (auto& e : E[0]) srcs = std::max(srcs, e.src_cap);
     if (n0)  // attempts again, without the sources the threshold rules out
-      c.tm.run(K_SCAN, [&] { ext_scan(c.st, g, (const ExtJob*)ws->jobrec, n0, scan_grid(n0, srcs)); });
+      c.tm.run(K_SCAN, [&] {
+        ext_scan(c.st, g, (const ExtJob*)ws->jobrec, n0, scan_grid(n0, srcs), cls_bytes(c, K_SCAN));
+      });
     if (n0)
       c.tm.run(K_LAST, [&] {
         ext_run(c.st, g, (const ExtJob*)ws->jobrec, n0, flat_grid(enum_grid(c), enum_grid(c)), true, use_ahead(c),
@@ -2691,7 +2693,7 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     }
     // the jobs whose collection now fits get their first K (sorted, or flagged
     // for the radix select)
-    c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)(ws->jobrec + bt), (int)T.size()); });
+    c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)(ws->jobrec + bt), (int)T.size(), cls_bytes(c, K_TOPK)); });
     // the batch's control blocks are contiguous: one copy (the other jobs'
     // words are unchanged since the main pass's read-back)
     HIPCHK(hipMemcpyAsync(ws->hctl, jobs[0].mem.ctl, sizeof(uint64_t) * CTL_WORDS * jobs.size(),

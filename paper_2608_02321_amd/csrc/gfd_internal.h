@@ -406,7 +406,8 @@ void units_read(hipStream_t st, uint64_t* host);  // [UNIT_KINDS], synchronous
 // grid of `grid` blocks shared by all jobs (the scans share it by their
 // tiles).  `bytes`, when not null, accumulates the algorithmic bytes the
 // kernel touched.
-void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid);
+void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
+                 unsigned long long* bytes = nullptr);
 // bitmaps: the launch's jobs record hits in bitmaps (hitmode 1) rather than
 // bytes; every job of one launch uses the same form
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
@@ -415,7 +416,8 @@ void filter_compact(hipStream_t st, const DevGraph& g, const FilterJob* jobs, in
                     bool bitmaps, unsigned long long* bytes);
 // zero the output bitmap of every active job
 void filter_clear(hipStream_t st, const FilterJob* jobs, int njobs, int gx);
-void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid);
+void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
+              unsigned long long* bytes = nullptr);
 void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs);
 // one pass (reserve, then fill) or two (count, alloc, fill) per tree edge
 void cpi_count(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
@@ -424,7 +426,8 @@ void cpi_alloc(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs,
 void cpi_fill(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
               bool onepass, unsigned long long* bytes);
 // 1-D grid of `grid` blocks shared among the jobs by their scan tiles
-void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid);
+void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid,
+              unsigned long long* bytes = nullptr);
 // After the scan of inner level i (records `cur`): reserves every job's next
 // frontier from `pool` (bump cursor *cursor, pool_bytes in all) and points
 // cur's dst_*, next's src_* / begs / scan arrays (next may be null) and leaf's
@@ -440,7 +443,7 @@ void ext_run(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, i
 // k == 1: every member of the root's candidate set is a match.
 void ext_single(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int gx,
                 unsigned long long* bytes);
-void topk_small(hipStream_t st, const TopkJob* jobs, int njobs);
+void topk_small(hipStream_t st, const TopkJob* jobs, int njobs, unsigned long long* bytes = nullptr);
 
 // n 8-byte words from src (mapped pinned host memory) to dst (device memory)
 void copy_words(hipStream_t st, const uint64_t* src, uint64_t* dst, uint64_t n);
@@ -478,8 +481,9 @@ void win_digit(hipStream_t st, const WinJob* jobs, int njobs, int shift, int bit
 // per active job.  sel_pass decides `bits` bits of tuple word `word` starting
 // at bit `shift` (jobs with k <= word are skipped).
 void sel_begin(hipStream_t st, const SelJob* jobs, int njobs);
-void sel_pass(hipStream_t st, const SelJob* jobs, int njobs, int word, int shift, int bits, int gx);
-void sel_first_k(hipStream_t st, const SelJob* jobs, int njobs, int gx);
+void sel_pass(hipStream_t st, const SelJob* jobs, int njobs, int word, int shift, int bits, int gx,
+              unsigned long long* bytes = nullptr);
+void sel_first_k(hipStream_t st, const SelJob* jobs, int njobs, int gx, unsigned long long* bytes = nullptr);
 void sel_threshold(hipStream_t st, const SelJob* jobs, int njobs);
 
 void fill_u8(hipStream_t st, uint8_t* p, uint8_t v, uint64_t n);

@@ -686,8 +686,12 @@ __device__ __forceinline__ uint32_t block_row_of(const uint32_t* rows, uint32_t 
 
 // Row lengths of (item, constraint) pairs, item-major.  A direct job needs no
 // scan: its rows are contiguous.
+// Algorithmic bytes (when `bytes` is set): per pair, the item, what the
+// degree filter and the row lookup read, the row's two bounds and the
+// prefix written.
 __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob* __restrict__ jobs,
-                                                    int njobs) {
+                                                    int njobs, unsigned long long* bytes) {
+  unsigned long long by = 0;
   shared_scan_blocks(njobs, [&](int j) -> uint64_t {
     const FilterJob& J = jobs[j];
     if (!J.active || J.ncons == 0 || J.direct) return ~0ull;
@@ -695,13 +699,14 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
   }, [&](int jb, uint64_t nb) {
     const FilterJob& J = jobs[jb];
     const uint32_t nc = (uint32_t)J.ncons;
-    unsigned long long by = 0;
     job_scan(filter_items(J) * nc, [&](uint64_t q) -> uint32_t {
       const uint64_t i = q / nc;
       const uint32_t c = (uint32_t)(q - i * nc);
       const int32_t v = filter_item(J, i);
+      by += 4 + 8;  // the item, the prefix
       if (!degree_ok(g, J, i, v, by)) return 0u;
       const PullC& cs = J.cons[c];
+      by += 8;  // the row's bounds
       if (cs.blk) {  // the item's run in the edge-label block
         const BlockArrays ba = block_arrays(g, cs.blk, cs.dir);
         const uint32_t r = block_row_of(ba.row, cs.rb, cs.re, g.lab_pos[v], by);
@@ -711,6 +716,7 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
       return off[v + 1] - off[v];
     }, J.sc, nb);
   });
+  if (bytes) block_add(bytes, by);
 }
 
 // Flat entries of constraint c of a direct job: its items' rows in one slice
@@ -1021,8 +1027,9 @@ __global__ __launch_bounds__(BS) void k_filter_clear(const FilterJob* __restrict
     J.bits[w] = 0;
 }
 
-void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid) {
-  hipLaunchKernelGGL(k_filter_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
+void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
+                 unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_filter_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                  bool bitmaps, unsigned long long* bytes) {
@@ -1068,8 +1075,11 @@ __device__ __forceinline__ bool cpi_keep(const DevGraph& g, const CpiJob& J, int
 }
 
 // Row lengths of the members of C(p); clears the per-source counters.
+// Algorithmic bytes: per parent candidate, the candidate, its row's bounds,
+// the two list heads cleared and the prefix written (28).
 __global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __restrict__ jobs,
-                                                 int njobs) {
+                                                 int njobs, unsigned long long* bytes) {
+  unsigned long long by = 0;
   shared_scan_blocks(njobs, [&](int j) -> uint64_t {
     return jobs[j].active ? cpi_sources(jobs[j]) : ~0ull;
   }, [&](int jb, uint64_t nb) {
@@ -1079,9 +1089,11 @@ __global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __res
       const int32_t vp = J.p.list[s];
       J.len[s] = 0;
       J.cur[s] = 0;
+      by += 28;
       return off[vp + 1] - off[vp];
     }, J.sc, nb);
   });
+  if (bytes) block_add(bytes, by);
 }
 
 // Entry v (far end, label already prim) of the row of v_p in an edge-label
@@ -1250,8 +1262,9 @@ __global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __res
   if (bytes) block_add(bytes, by);
 }
 
-void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid) {
-  hipLaunchKernelGGL(k_cpi_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
+void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
+              unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_cpi_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs) {
   hipLaunchKernelGGL(k_cpi_reserve, dim3(1, njobs), dim3(64), 0, st, jobs);
@@ -1439,10 +1452,11 @@ __device__ __forceinline__ uint64_t ext_sources(const ExtJob& J) {
 // variables, read in variable order up to the first unbound one, already
 // exceed thr.
 __device__ __forceinline__ bool source_past(const ExtJob& J, uint64_t s,
-                                            const int32_t (&thr)[MAXK]) {
+                                            const int32_t (&thr)[MAXK], unsigned long long& by) {
   for (int v = 0; v < J.k; v++) {
     const int p = J.var_pos[v];
     if (p >= J.i) return false;  // unbound: undecided
+    by += 4;
     const uint32_t x = (uint32_t)J.src_cols[(uint64_t)p * J.src_stride + s];
     const uint32_t y = (uint32_t)thr[v];
     if (x != y) return x > y;
@@ -1451,8 +1465,12 @@ __device__ __forceinline__ bool source_past(const ExtJob& J, uint64_t s,
 }
 
 // CPI list length of every partial match's spanning-tree parent.
+// Algorithmic bytes: per source, the prefix written, the bound words the
+// threshold test reads, and (when it gets attempts) the parent's vertex and
+// position, its list's bounds and the list start written.
 __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __restrict__ jobs,
-                                                 int njobs) {
+                                                 int njobs, unsigned long long* bytes) {
+  unsigned long long by = 0;
   shared_scan_blocks(njobs, [&](int j) -> uint64_t {
     return jobs[j].active && !jobs[j].deferred ? ext_sources(jobs[j]) : ~0ull;
   }, [&](int jb, uint64_t nb) {
@@ -1464,18 +1482,22 @@ __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __res
     for (int v = 0; v < MAXK; v++) thr[v] = prune && v < J.k ? J.thr[v] : 0;
     const uint64_t xn = J.cross ? (*J.cross_n < J.cross_cap ? *J.cross_n : J.cross_cap) : 0ull;
     job_scan(ext_sources(J), [&](uint64_t s) -> uint32_t {
+      by += 8;  // the prefix
       // a source the threshold rules out gets no attempts, so its list start
       // is never read: decided first, it skips the parent's row lookups
-      if (prune && source_past(J, s, thr)) return 0u;
+      if (prune && source_past(J, s, thr, by)) return 0u;
       if (J.cross) {  // all of the new component root's candidates
         J.begs[s] = 0;
+        by += 4;
         return (uint32_t)xn;
       }
       const int32_t c = J.par_posmap[pos_index(g, J.par_by_bucket, par[s])];
       J.begs[s] = J.cpi_beg[c];
+      by += 20;
       return J.cpi_len[c];
     }, J.sc, nb);
   });
+  if (bytes) block_add(bytes, by);
 }
 
 // Attempt window of one job in the launch's chunk space (0 for a job of the
@@ -1735,8 +1757,9 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
   if (bytes) block_add(bytes, by);
 }
 
-void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid) {
-  hipLaunchKernelGGL(k_ext_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs);
+void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid,
+              unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_ext_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 
 // Next-frontier reservation (see front_reserve): one thread per job takes
@@ -2324,7 +2347,9 @@ __device__ void bitonic_lds(uint32_t* s, uint32_t p2, int k) {
 // One workgroup per job: sort the staged tuples when there are at most
 // SORT_MAX of them and keep the first min(K, count); otherwise flag the job
 // for the radix select.
-__global__ __launch_bounds__(SORT_THREADS) void k_topk_small(const TopkJob* __restrict__ jobs) {
+// Algorithmic bytes: the staged tuples read and the first K written.
+__global__ __launch_bounds__(SORT_THREADS) void k_topk_small(const TopkJob* __restrict__ jobs,
+                                                             unsigned long long* bytes) {
   __shared__ uint32_t s[SORT_MAX * MAXK];
   const TopkJob& J = jobs[blockIdx.y];
   if (!J.active) return;
@@ -2338,11 +2363,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_topk_small(const TopkJob* __re
   while (p2 < cnt) p2 <<= 1;
   sort_load(s, J.vbuf, (uint32_t)cnt, p2, J.k);
   bitonic_lds(s, p2, J.k);
-  sort_store(s, J.res, (uint32_t)(cnt < (uint64_t)J.K ? cnt : (uint64_t)J.K), J.k);
+  const uint64_t out = cnt < (uint64_t)J.K ? cnt : (uint64_t)J.K;
+  sort_store(s, J.res, (uint32_t)out, J.k);
+  if (bytes && threadIdx.x == 0 && cnt) atomicAdd(bytes, 4ull * (uint64_t)J.k * (cnt + out));
 }
 
-void topk_small(hipStream_t st, const TopkJob* jobs, int njobs) {
-  hipLaunchKernelGGL(k_topk_small, dim3(1, njobs), dim3(SORT_THREADS), 0, st, jobs);
+void topk_small(hipStream_t st, const TopkJob* jobs, int njobs, unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_topk_small, dim3(1, njobs), dim3(SORT_THREADS), 0, st, jobs, bytes);
 }
 
 // Radix select, batched over jobs (grid row y = job).  State words of a job:
@@ -2378,8 +2405,9 @@ __device__ __forceinline__ uint64_t sel_count(const SelJob& J) {
 // before the barrier, so they have been performed before the block's counter
 // add is issued; the last block reads the bins with agent-scope atomic loads
 // issued after it has seen the final count.
+// Algorithmic bytes: the tuple words each pass reads.
 __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs, int word,
-                                                 int shift, int bits) {
+                                                 int shift, int bits, unsigned long long* bytes) {
   constexpr int PER = RADIX_BINS / BS;
   __shared__ uint32_t sh[RADIX_BINS];
   __shared__ uint32_t s_last, s_seen;
@@ -2399,11 +2427,14 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
   const uint64_t cnt = sel_count(J);
   const uint32_t hi_mask = (shift + bits >= 32) ? 0u : (0xFFFFFFFFu << (shift + bits));
   const uint32_t want_hi = pick(st, word) & hi_mask;
+  unsigned long long by = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < cnt;
        i += (uint64_t)gridDim.x * BS) {
     const uint32_t* t = (const uint32_t*)J.vbuf + i * (uint64_t)k;
     bool match = true;
-    for (int w = 0; w < word && match; w++) match = t[w] == pick(st, w);
+    int w = 0;
+    for (; w < word && match; w++) match = t[w] == pick(st, w);
+    by += 4ull * (uint64_t)(w + (match ? 1 : 0));
     if (!match) continue;
     const uint32_t x = t[word];
     if ((x & hi_mask) != want_hi) continue;
@@ -2414,6 +2445,7 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
     }
     atomicAdd(&sh[(x >> shift) & ((1u << bits) - 1)], 1u);
   }
+  if (bytes) block_add(bytes, by);
   __syncthreads();
   uint32_t seen = 0;
   for (int b = threadIdx.x; b < RADIX_BINS; b += BS)
@@ -2458,7 +2490,9 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
 
 // Staged tuples <= the selected one (exactly K of them, tuples being
 // distinct) into out.
-__global__ __launch_bounds__(BS) void k_sel_compact(const SelJob* __restrict__ jobs) {
+// (Algorithmic bytes: the words compared and the tuples written.)
+__global__ __launch_bounds__(BS) void k_sel_compact(const SelJob* __restrict__ jobs,
+                                                    unsigned long long* bytes) {
   const SelJob& J = jobs[blockIdx.y];
   if (!J.active) return;
   const int k = J.k;
@@ -2466,24 +2500,30 @@ __global__ __launch_bounds__(BS) void k_sel_compact(const SelJob* __restrict__ j
 #pragma unroll
   for (int w = 0; w < MAXK; w++) st[w] = J.state[w];
   const uint64_t cnt = sel_count(J);
+  unsigned long long by = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < cnt;
        i += (uint64_t)gridDim.x * BS) {
     const uint32_t* t = (const uint32_t*)J.vbuf + i * (uint64_t)k;
-    int c = 0;
-    for (int w = 0; w < k && c == 0; w++) {
+    int c = 0, w = 0;
+    for (; w < k && c == 0; w++) {
       const uint32_t y = pick(st, w);
       c = t[w] < y ? -1 : (t[w] > y ? 1 : 0);
     }
+    by += 4ull * (uint64_t)w;
     if (c <= 0) {
       const unsigned long long slot = atomicAdd(J.d_outcount, 1ull);
-      if (slot < (unsigned long long)J.K)
-        for (int w = 0; w < k; w++) J.out[slot * k + w] = (int32_t)t[w];
+      if (slot < (unsigned long long)J.K) {
+        for (int q = 0; q < k; q++) J.out[slot * k + q] = (int32_t)t[q];
+        by += 4ull * (uint64_t)(2 * k - w);  // the rest of the tuple read, all of it written
+      }
     }
   }
+  if (bytes) block_add(bytes, by);
 }
 
 // Sorts the K selected tuples of every job in place.
-__global__ __launch_bounds__(SORT_THREADS) void k_sel_sort(const SelJob* __restrict__ jobs) {
+__global__ __launch_bounds__(SORT_THREADS) void k_sel_sort(const SelJob* __restrict__ jobs,
+                                                           unsigned long long* bytes) {
   __shared__ uint32_t s[SORT_MAX * MAXK];
   const SelJob& J = jobs[blockIdx.y];
   if (!J.active) return;
@@ -2493,6 +2533,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sel_sort(const SelJob* __restr
   sort_load(s, J.out, (uint32_t)n, p2, J.k);
   bitonic_lds(s, p2, J.k);  // every tuple is in LDS before any is written back
   sort_store(s, J.out, (uint32_t)n, J.k);
+  if (bytes && threadIdx.x == 0 && n) atomicAdd(bytes, 8ull * (uint64_t)J.k * n);  // read, written
 }
 
 // The selected tuple becomes the job's staging threshold; staging restarts.
@@ -2510,12 +2551,12 @@ void sel_begin(hipStream_t st, const SelJob* jobs, int njobs) {
   hipLaunchKernelGGL(k_sel_begin, dim3(1, njobs), dim3(64), 0, st, jobs);
 }
 void sel_pass(hipStream_t st, const SelJob* jobs, int njobs, int word, int shift, int bits,
-              int gx) {
-  hipLaunchKernelGGL(k_sel_pass, dim3(gx, njobs), dim3(BS), 0, st, jobs, word, shift, bits);
+              int gx, unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_sel_pass, dim3(gx, njobs), dim3(BS), 0, st, jobs, word, shift, bits, bytes);
 }
-void sel_first_k(hipStream_t st, const SelJob* jobs, int njobs, int gx) {
-  hipLaunchKernelGGL(k_sel_compact, dim3(gx, njobs), dim3(BS), 0, st, jobs);
-  hipLaunchKernelGGL(k_sel_sort, dim3(1, njobs), dim3(SORT_THREADS), 0, st, jobs);
+void sel_first_k(hipStream_t st, const SelJob* jobs, int njobs, int gx, unsigned long long* bytes) {
+  hipLaunchKernelGGL(k_sel_compact, dim3(gx, njobs), dim3(BS), 0, st, jobs, bytes);
+  hipLaunchKernelGGL(k_sel_sort, dim3(1, njobs), dim3(SORT_THREADS), 0, st, jobs, bytes);
 }
 void sel_threshold(hipStream_t st, const SelJob* jobs, int njobs) {
   hipLaunchKernelGGL(k_sel_thr, dim3(1, njobs), dim3(64), 0, st, jobs);
