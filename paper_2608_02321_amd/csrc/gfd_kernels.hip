@@ -686,9 +686,10 @@ __device__ __forceinline__ uint32_t block_row_of(const uint32_t* rows, uint32_t 
 
 // Row lengths of (item, constraint) pairs, item-major.  A direct job needs no
 // scan: its rows are contiguous.
-// Algorithmic bytes (when `bytes` is set): per pair, the item, what the
+// Algorithmic bytes (COUNT: the timing form): per pair, the item, what the
 // degree filter and the row lookup read, the row's two bounds and the
 // prefix written.
+template <bool COUNT>
 __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob* __restrict__ jobs,
                                                     int njobs, unsigned long long* bytes) {
   unsigned long long by = 0;
@@ -703,10 +704,10 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
       const uint64_t i = q / nc;
       const uint32_t c = (uint32_t)(q - i * nc);
       const int32_t v = filter_item(J, i);
-      by += 4 + 8;  // the item, the prefix
+      if (COUNT) by += 4 + 8;  // the item, the prefix
       if (!degree_ok(g, J, i, v, by)) return 0u;
       const PullC& cs = J.cons[c];
-      by += 8;  // the row's bounds
+      if (COUNT) by += 8;  // the row's bounds
       if (cs.blk) {  // the item's run in the edge-label block
         const BlockArrays ba = block_arrays(g, cs.blk, cs.dir);
         const uint32_t r = block_row_of(ba.row, cs.rb, cs.re, g.lab_pos[v], by);
@@ -716,7 +717,7 @@ __global__ __launch_bounds__(BS) void k_filter_scan(DevGraph g, const FilterJob*
       return off[v + 1] - off[v];
     }, J.sc, nb);
   });
-  if (bytes) block_add(bytes, by);
+  if (COUNT) block_add(bytes, by);
 }
 
 // Flat entries of constraint c of a direct job: its items' rows in one slice
@@ -1029,7 +1030,8 @@ __global__ __launch_bounds__(BS) void k_filter_clear(const FilterJob* __restrict
 
 void filter_scan(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                  unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_filter_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  if (bytes) hipLaunchKernelGGL(k_filter_scan<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  else hipLaunchKernelGGL(k_filter_scan<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void filter_pull(hipStream_t st, const DevGraph& g, const FilterJob* jobs, int njobs, int grid,
                  bool bitmaps, unsigned long long* bytes) {
@@ -1075,8 +1077,9 @@ __device__ __forceinline__ bool cpi_keep(const DevGraph& g, const CpiJob& J, int
 }
 
 // Row lengths of the members of C(p); clears the per-source counters.
-// Algorithmic bytes: per parent candidate, the candidate, its row's bounds,
-// the two list heads cleared and the prefix written (28).
+// Algorithmic bytes (COUNT): per parent candidate, the candidate, its row's
+// bounds, the two list heads cleared and the prefix written (28).
+template <bool COUNT>
 __global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __restrict__ jobs,
                                                  int njobs, unsigned long long* bytes) {
   unsigned long long by = 0;
@@ -1089,11 +1092,11 @@ __global__ __launch_bounds__(BS) void k_cpi_scan(DevGraph g, const CpiJob* __res
       const int32_t vp = J.p.list[s];
       J.len[s] = 0;
       J.cur[s] = 0;
-      by += 28;
+      if (COUNT) by += 28;
       return off[vp + 1] - off[vp];
     }, J.sc, nb);
   });
-  if (bytes) block_add(bytes, by);
+  if (COUNT) block_add(bytes, by);
 }
 
 // Entry v (far end, label already prim) of the row of v_p in an edge-label
@@ -1264,7 +1267,8 @@ __global__ __launch_bounds__(BS) void k_cpi_fill(DevGraph g, const CpiJob* __res
 
 void cpi_scan(hipStream_t st, const DevGraph& g, const CpiJob* jobs, int njobs, int grid,
               unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_cpi_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  if (bytes) hipLaunchKernelGGL(k_cpi_scan<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  else hipLaunchKernelGGL(k_cpi_scan<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 void cpi_reserve(hipStream_t st, const CpiJob* jobs, int njobs) {
   hipLaunchKernelGGL(k_cpi_reserve, dim3(1, njobs), dim3(64), 0, st, jobs);
@@ -1465,9 +1469,10 @@ __device__ __forceinline__ bool source_past(const ExtJob& J, uint64_t s,
 }
 
 // CPI list length of every partial match's spanning-tree parent.
-// Algorithmic bytes: per source, the prefix written, the bound words the
-// threshold test reads, and (when it gets attempts) the parent's vertex and
-// position, its list's bounds and the list start written.
+// Algorithmic bytes (COUNT): per source, the prefix written, the bound words
+// the threshold test reads, and (when it gets attempts) the parent's vertex
+// and position, its list's bounds and the list start written.
+template <bool COUNT>
 __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __restrict__ jobs,
                                                  int njobs, unsigned long long* bytes) {
   unsigned long long by = 0;
@@ -1482,22 +1487,22 @@ __global__ __launch_bounds__(BS) void k_ext_scan(DevGraph g, const ExtJob* __res
     for (int v = 0; v < MAXK; v++) thr[v] = prune && v < J.k ? J.thr[v] : 0;
     const uint64_t xn = J.cross ? (*J.cross_n < J.cross_cap ? *J.cross_n : J.cross_cap) : 0ull;
     job_scan(ext_sources(J), [&](uint64_t s) -> uint32_t {
-      by += 8;  // the prefix
+      if (COUNT) by += 8;  // the prefix
       // a source the threshold rules out gets no attempts, so its list start
       // is never read: decided first, it skips the parent's row lookups
       if (prune && source_past(J, s, thr, by)) return 0u;
       if (J.cross) {  // all of the new component root's candidates
         J.begs[s] = 0;
-        by += 4;
+        if (COUNT) by += 4;
         return (uint32_t)xn;
       }
       const int32_t c = J.par_posmap[pos_index(g, J.par_by_bucket, par[s])];
       J.begs[s] = J.cpi_beg[c];
-      by += 20;
+      if (COUNT) by += 20;
       return J.cpi_len[c];
     }, J.sc, nb);
   });
-  if (bytes) block_add(bytes, by);
+  if (COUNT) block_add(bytes, by);
 }
 
 // Attempt window of one job in the launch's chunk space (0 for a job of the
@@ -1759,7 +1764,8 @@ __global__ __launch_bounds__(BS) void k_ext_single(DevGraph g, const ExtJob* __r
 
 void ext_scan(hipStream_t st, const DevGraph& g, const ExtJob* jobs, int njobs, int grid,
               unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_ext_scan, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  if (bytes) hipLaunchKernelGGL(k_ext_scan<true>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
+  else hipLaunchKernelGGL(k_ext_scan<false>, dim3(grid), dim3(BS), 0, st, g, jobs, njobs, bytes);
 }
 
 // Next-frontier reservation (see front_reserve): one thread per job takes
@@ -2405,7 +2411,8 @@ __device__ __forceinline__ uint64_t sel_count(const SelJob& J) {
 // before the barrier, so they have been performed before the block's counter
 // add is issued; the last block reads the bins with agent-scope atomic loads
 // issued after it has seen the final count.
-// Algorithmic bytes: the tuple words each pass reads.
+// Algorithmic bytes (COUNT): the tuple words each pass reads.
+template <bool COUNT>
 __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs, int word,
                                                  int shift, int bits, unsigned long long* bytes) {
   constexpr int PER = RADIX_BINS / BS;
@@ -2434,7 +2441,7 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
     bool match = true;
     int w = 0;
     for (; w < word && match; w++) match = t[w] == pick(st, w);
-    by += 4ull * (uint64_t)(w + (match ? 1 : 0));
+    if (COUNT) by += 4ull * (uint64_t)(w + (match ? 1 : 0));
     if (!match) continue;
     const uint32_t x = t[word];
     if ((x & hi_mask) != want_hi) continue;
@@ -2445,7 +2452,7 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
     }
     atomicAdd(&sh[(x >> shift) & ((1u << bits) - 1)], 1u);
   }
-  if (bytes) block_add(bytes, by);
+  if (COUNT) block_add(bytes, by);
   __syncthreads();
   uint32_t seen = 0;
   for (int b = threadIdx.x; b < RADIX_BINS; b += BS)
@@ -2490,7 +2497,8 @@ __global__ __launch_bounds__(BS) void k_sel_pass(const SelJob* __restrict__ jobs
 
 // Staged tuples <= the selected one (exactly K of them, tuples being
 // distinct) into out.
-// (Algorithmic bytes: the words compared and the tuples written.)
+// (Algorithmic bytes, COUNT: the words compared and the tuples written.)
+template <bool COUNT>
 __global__ __launch_bounds__(BS) void k_sel_compact(const SelJob* __restrict__ jobs,
                                                     unsigned long long* bytes) {
   const SelJob& J = jobs[blockIdx.y];
@@ -2509,16 +2517,16 @@ __global__ __launch_bounds__(BS) void k_sel_compact(const SelJob* __restrict__ j
       const uint32_t y = pick(st, w);
       c = t[w] < y ? -1 : (t[w] > y ? 1 : 0);
     }
-    by += 4ull * (uint64_t)w;
+    if (COUNT) by += 4ull * (uint64_t)w;
     if (c <= 0) {
       const unsigned long long slot = atomicAdd(J.d_outcount, 1ull);
       if (slot < (unsigned long long)J.K) {
         for (int q = 0; q < k; q++) J.out[slot * k + q] = (int32_t)t[q];
-        by += 4ull * (uint64_t)(2 * k - w);  // the rest of the tuple read, all of it written
+        if (COUNT) by += 4ull * (uint64_t)(2 * k - w);  // the rest read, all of it written
       }
     }
   }
-  if (bytes) block_add(bytes, by);
+  if (COUNT) block_add(bytes, by);
 }
 
 // Sorts the K selected tuples of every job in place.
@@ -2552,10 +2560,14 @@ void sel_begin(hipStream_t st, const SelJob* jobs, int njobs) {
 }
 void sel_pass(hipStream_t st, const SelJob* jobs, int njobs, int word, int shift, int bits,
               int gx, unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_sel_pass, dim3(gx, njobs), dim3(BS), 0, st, jobs, word, shift, bits, bytes);
+  if (bytes)
+    hipLaunchKernelGGL(k_sel_pass<true>, dim3(gx, njobs), dim3(BS), 0, st, jobs, word, shift, bits, bytes);
+  else
+    hipLaunchKernelGGL(k_sel_pass<false>, dim3(gx, njobs), dim3(BS), 0, st, jobs, word, shift, bits, bytes);
 }
 void sel_first_k(hipStream_t st, const SelJob* jobs, int njobs, int gx, unsigned long long* bytes) {
-  hipLaunchKernelGGL(k_sel_compact, dim3(gx, njobs), dim3(BS), 0, st, jobs, bytes);
+  if (bytes) hipLaunchKernelGGL(k_sel_compact<true>, dim3(gx, njobs), dim3(BS), 0, st, jobs, bytes);
+  else hipLaunchKernelGGL(k_sel_compact<false>, dim3(gx, njobs), dim3(BS), 0, st, jobs, bytes);
   hipLaunchKernelGGL(k_sel_sort, dim3(1, njobs), dim3(SORT_THREADS), 0, st, jobs, bytes);
 }
 void sel_threshold(hipStream_t st, const SelJob* jobs, int njobs) {
