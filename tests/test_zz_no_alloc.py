@@ -51,6 +51,11 @@ def test_noalloc_matches_validate_twice(P):
         _same(P, gb, _gfds(33, 6), K=32, semantics=sem, batched=False)
         _same(P, gs, _gfds(34, 4), K=8, semantics=sem, flags=P.GFD_FLAG_FORCE_CHUNKED)
         _same(P, gb, _gfds(35, 5), K=16, semantics=sem, violation_cap=40, batched=True)
+        # count-only: postponed leaves, and (K > 0) their first-K windows
+        _same(P, gb, _gfds(36, 12), K=0, semantics=sem, flags=P.GFD_FLAG_COUNT_ONLY,
+              batched=True)
+        _same(P, gb, _gfds(36, 12), K=24, semantics=sem, flags=P.GFD_FLAG_COUNT_ONLY,
+              batched=True)
     gb.free()
     gs.free()
 
