@@ -1919,45 +1919,65 @@ __device__ __forceinline__ uint64_t leaf_members(const LeafJob& J) {
   return !J.active ? 0ull : (*J.d_np < J.cap_p ? *J.d_np : J.cap_p);
 }
 
-// The members of every job's C(p) share one space of BS-member chunks: a
-// member's work is its whole CPI list, so each thread takes one member and
-// the blocks move on to whichever job still has members.
+// The members of every job's C(p) share one space of BS-member chunks (one
+// job per chunk).  With no literal on the leaves a member's counts are its
+// list's length and the list is not read.  Otherwise the lists of a chunk's
+// members are walked by the whole block: their entries form one index space
+// (a block scan of the lengths), so a hub's long list does not hold up its
+// wave, and each entry adds to its member's counts in LDS.
 __global__ __launch_bounds__(BS) void k_leaf_prep(DevGraph g, const LeafJob* __restrict__ jobs,
                                                   int njobs) {
   __shared__ ChunkMap cm;
+  __shared__ uint64_t s_pre[BS];
+  __shared__ uint32_t s_beg[BS];
+  __shared__ uint32_t s_cx[LEAF_SUBSETS][BS], s_cxy[LEAF_SUBSETS][BS];
   chunk_map_build(cm, njobs, [&](int j) -> uint64_t { return (leaf_members(jobs[j]) + BS - 1) / BS; });
   for (uint64_t ch = blockIdx.x; ch < cm.cs[njobs]; ch += gridDim.x) {
-  const int jb = chunk_job(cm, njobs, ch);
-  const LeafJob& J = jobs[jb];
-  const uint64_t np = leaf_members(J);
-  const uint32_t nsub = 1u << J.r;
-  const uint64_t c = (ch - cm.cs[jb]) * BS + threadIdx.x;
-  if (c < np) {
-    uint32_t cx[LEAF_SUBSETS] = {}, cxy[LEAF_SUBSETS] = {};
-    const uint32_t b = J.cpi_beg[c], len = J.cpi_len[c];
-    // with no literal on the leaves every member meets every subset: the
-    // counts are the list's length, and the list is not read
-    bool leaf_lits = false;
+    const int jb = chunk_job(cm, njobs, ch);
+    const LeafJob& J = jobs[jb];
+    const uint64_t np = leaf_members(J);
+    const uint32_t nsub = 1u << J.r;
+    const uint64_t c = (ch - cm.cs[jb]) * BS + threadIdx.x;
+    const bool act = c < np;
+    const uint32_t b = act ? J.cpi_beg[c] : 0u, len = act ? J.cpi_len[c] : 0u;
+    bool leaf_lits = false;  // the same for the whole block
     for (int t = 0; t < J.nx + J.ny; t++) leaf_lits |= J.lit_leaf[t] >= 0;
-    if (!leaf_lits)
-      for (uint32_t B = 1; B < LEAF_SUBSETS; B++) cx[B] = cxy[B] = B < nsub ? len : 0u;
-    for (uint32_t e = 0; e < (leaf_lits ? len : 0u); e++) {
-      uint32_t mx, mxy;
-      leaf_masks(g, J, J.cpi_ent[(uint64_t)b + e], mx, mxy);
+    if (leaf_lits) {
+      uint64_t total;
+      const uint64_t pre = block_excl_scan64(len, total);
+      s_pre[threadIdx.x] = pre;
+      s_beg[threadIdx.x] = b;
 #pragma unroll
-      for (uint32_t B = 1; B < LEAF_SUBSETS; B++) {
-        cx[B] += (B < nsub && (mx & B) == B) ? 1u : 0u;
-        cxy[B] += (B < nsub && (mxy & B) == B) ? 1u : 0u;
+      for (int B = 0; B < LEAF_SUBSETS; B++) s_cx[B][threadIdx.x] = s_cxy[B][threadIdx.x] = 0u;
+      __syncthreads();
+      for (uint64_t it = threadIdx.x; it < total; it += BS) {
+        // the member whose entries hold `it`: the last t with s_pre[t] <= it
+        int lo = 0, hi = BS - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= it) lo = mid;
+          else hi = mid - 1;
+        }
+        uint32_t mx, mxy;
+        leaf_masks(g, J, J.cpi_ent[(uint64_t)s_beg[lo] + (it - s_pre[lo])], mx, mxy);
+        for (uint32_t B = 1; B < nsub; B++) {
+          if ((mx & B) == B) atomicAdd(&s_cx[B][lo], 1u);
+          if ((mxy & B) == B) atomicAdd(&s_cxy[B][lo], 1u);
+        }
+      }
+      __syncthreads();
+    }
+    if (act) {
+      uint32_t* out = J.cnt + c * LEAF_WORDS;
+#pragma unroll
+      for (uint32_t B = 0; B < LEAF_SUBSETS; B++) {
+        const bool used = B > 0 && B < nsub;
+        out[B] = B ? len : 0u;
+        out[LEAF_SUBSETS + B] = used ? (leaf_lits ? s_cx[B][threadIdx.x] : len) : 0u;
+        out[2 * LEAF_SUBSETS + B] = used ? (leaf_lits ? s_cxy[B][threadIdx.x] : len) : 0u;
       }
     }
-    uint32_t* out = J.cnt + c * LEAF_WORDS;
-#pragma unroll
-    for (uint32_t B = 0; B < LEAF_SUBSETS; B++) {
-      out[B] = B ? len : 0u;
-      out[LEAF_SUBSETS + B] = cx[B];
-      out[2 * LEAF_SUBSETS + B] = cxy[B];
-    }
-  }
+    if (leaf_lits) __syncthreads();  // the next chunk rewrites the shared arrays
   }
 }
 
