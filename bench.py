@@ -428,11 +428,7 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
     assert pc.results() == res, "results changed between steps"
-    # two more (untimed) steps with statistics, for the log: the second
-    # replays the graph of calls with statistics
-    pc.run(flags=base_flags)
-    st = pc.run(flags=base_flags)
-    graph_replays = st["graph_replays"]
+    # (the log's launch counts come from the last warm-up step's statistics)
     # the dominant kernel's launches, timed with HIP events on the call's
     # stream over further steps run eagerly (events around kernels inside a
     # replayed graph are not available); the kernels are the same
@@ -464,7 +460,7 @@ def main():
         fixed_ms = (time.perf_counter() - t1) * 1e3 / args.steps
         assert pf.results() == res, "default launch shapes changed a result"
     log(f"{mode}: step {ms_per_step:.3f} ms, {matches} matches, {value:.4g} embeddings/s, "
-        f"{gfds_per_s:.1f} GFDs/s, launches/step {st['launches']} (graph replays {graph_replays}), "
+        f"{gfds_per_s:.1f} GFDs/s, launches/step {st['launches']}, "
         f"bounded re-runs {st['chunked_gfds']}")
 
     roofline = None

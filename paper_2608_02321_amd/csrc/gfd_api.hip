@@ -1413,6 +1413,8 @@ struct Recs {
   }
 };
 
+// Grows the record buffers; the caller has synchronised its stream, since a
+// copy kernel still in flight may be reading the old host staging.
 static void ensure_recs(Workspace* ws, size_t bytes) {
   if (ws->jobrec_bytes < bytes) {
     dfree(ws->al, ws->jobrec, ws->jobrec_bytes);
@@ -1981,6 +1983,7 @@ static void run_launches(Ctx& c, const std::vector<Launch>& L) {
 }
 
 static void upload_recs(Ctx& c, const Recs& R) {
+  HIPCHK(hipStreamSynchronize(c.st));  // nothing in flight reads the staging
   ensure_recs(c.ws, std::max<size_t>(R.blob.size(), 256));
   std::memcpy(c.ws->hjobrec, R.blob.data(), R.blob.size());
   upload_recs(c, 0, R.blob.size());
@@ -2004,6 +2007,7 @@ static size_t recs_bound(const std::vector<Job>& jobs) {
 // disjoint parts of the pinned staging).
 static void plan_and_run_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L) {
   Workspace* ws = c.ws;
+  HIPCHK(hipStreamSynchronize(c.st));  // nothing in flight reads the staging
   ensure_recs(ws, std::max<size_t>(recs_bound(jobs), 256));
   size_t up = 0;
   L.on_add = [&](const Launch& l) {
@@ -2071,8 +2075,8 @@ struct ResultDrain {
     const size_t w0 = P.front().dst, nw = used - w0;
     const int32_t* src = P.front().src;  // one job: its slot is already contiguous
     if (P.size() > 1) {
-      ensure_recs(ws, sizeof(PackJob) * P.size());
       HIPCHK(hipStreamSynchronize(c.st));  // the record staging is reused per launch
+      ensure_recs(ws, sizeof(PackJob) * P.size());
       std::memcpy(ws->hjobrec, P.data(), sizeof(PackJob) * P.size());
       upload_recs(c, 0, sizeof(PackJob) * P.size());
       pack_results(c.st, (const PackJob*)ws->jobrec, (int)P.size(), ws->pack);
@@ -2427,8 +2431,8 @@ struct Bounded {
     return c.ws->hctl[word];
   }
   void upload_one(const ExtJob& e) {
-    ensure_recs(c.ws, sizeof(ExtJob));
     HIPCHK(hipStreamSynchronize(c.st));  // the staging buffer is reused per launch
+    ensure_recs(c.ws, sizeof(ExtJob));
     std::memcpy(c.ws->hjobrec, &e, sizeof e);
     upload_recs(c, 0, sizeof e);
   }
@@ -2607,8 +2611,8 @@ static void run_bounded(Ctx& c, Job& J, uint64_t vbig) {
   if (c.K > 0) {
     std::vector<TopkJob> T{TopkJob{1, B.plan.k, c.K, ws->vbig, B.mem.ctl + CTL_VCOUNT, ws->vbig_cap,
                                    B.mem.res, (uint32_t*)(B.mem.ctl + CTL_NEEDSEL)}};
+    HIPCHK(hipStreamSynchronize(c.st));  // nothing in flight reads the staging
     ensure_recs(ws, sizeof(TopkJob));
-    HIPCHK(hipStreamSynchronize(c.st));
     std::memcpy(ws->hjobrec, T.data(), sizeof(TopkJob));
     upload_recs(c, 0, sizeof(TopkJob));
     c.tm.run(K_TOPK, [&] { topk_small(c.st, (const TopkJob*)ws->jobrec, 1, cls_bytes(c, K_TOPK)); });
@@ -2660,8 +2664,8 @@ static void rerun_last_levels(Ctx& c, std::vector<Job>& jobs, std::vector<int> o
     }
     const size_t b0 = align_up(sizeof(ExtJob) * E[0].size());
     const size_t bytes = b0 + sizeof(ExtJob) * E[1].size() + sizeof(TopkJob) * over.size();
+    HIPCHK(hipStreamSynchronize(c.st));  // nothing in flight reads the staging
     ensure_recs(ws, bytes);
-    HIPCHK(hipStreamSynchronize(c.st));
     std::memcpy(ws->hjobrec, E[0].data(), sizeof(ExtJob) * E[0].size());
     std::memcpy(ws->hjobrec + b0, E[1].data(), sizeof(ExtJob) * E[1].size());
     std::vector<TopkJob> T;
@@ -2771,8 +2775,8 @@ static void run_windows(Ctx& c, std::vector<Job>& jobs, const std::vector<int>& 
   // every pass's records at once (the staging is read when the copy runs)
   const size_t wb = align_up(sizeof(WinJob) * nw), fb = align_up(sizeof(LeafJob) * nw);
   const size_t bytes = wb + fb * npass;
+  HIPCHK(hipStreamSynchronize(c.st));  // nothing in flight reads the staging
   ensure_recs(ws, bytes);
-  HIPCHK(hipStreamSynchronize(c.st));
   std::memcpy(ws->hjobrec, W.data(), sizeof(WinJob) * nw);
   auto digit = [&](int ps, int& shift, int& bits) {
     shift = std::max(0, idbits - RADIX_BITS * (ps + 1));
