@@ -215,7 +215,8 @@ typedef struct {
   int32_t leaf_gfds;          /* GFDs whose last leaves were counted (GFD_FLAG_COUNT_ONLY) */
   int32_t regrown_gfds;       /* GFDs run again in the fast path: after the frontier pool or
                                  the CPI entry arena grew to what their batch asked for,
-                                 or alone when a shared pool or arena was at its cap */
+                                 or, when a shared pool or arena was at its cap, in a
+                                 smaller batch packed by what they asked for, then alone */
   int64_t front_pool_bytes;   /* frontier pool and CPI entry arena sizes after the call */
   int64_t cpi_arena_bytes;
   int32_t graph_captures;     /* batches whose main pass was captured as a graph */

@@ -7,10 +7,13 @@
 //     bottom-up marking pass, CPI adjacency lists per spanning-tree edge;
 //   enumeration (device): level-synchronous extension over the CPI, the
 //     X -> Y check fused into the last level, first-K selection.
-// All launches of a call are queued without host round trips; one
-// synchronisation per call reads the status words.  A GFD whose frontier or
-// violation staging overflowed its share of the budget is re-run on the
-// chunked path, which bounds every level by the budget.
+// A batch's main pass is queued without host round trips (and replayed from
+// a captured graph once its shape repeats); one synchronisation per batch
+// reads the status words.  A GFD whose frontiers or CPI lists did not fit
+// runs again once the pool or arena has grown, then in a smaller batch, then
+// alone, and last on the bounded path, which bounds every level by the
+// budget; one whose violation staging overflowed runs its last level again
+// under a threshold.
 #include <hip/hip_runtime.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
 
@@ -1399,6 +1402,29 @@ static uint64_t est_front_bytes(const gfd_graph* g, const Plan& p) {
     N = T;
   }
   return (uint64_t)std::min(bytes, 1e18);
+}
+
+// Frontier bytes a job whose frontiers overflowed the pool asks for, from its
+// control words: each inner level's attempts (known for every level it
+// reached, the failed one included) sized as the device's reservation sizes
+// them. A level past the failed one was not reached; the levels not reached
+// are counted as much again as those reached.
+static uint64_t reached_front_bytes(const Plan& p, const uint64_t* h, uint64_t front_limit) {
+  auto al = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+  uint64_t bytes = 0;
+  bool short_of = false;
+  for (int i = 1; i < p.k_enum; i++) {
+    if (p.leaf_r == 0 && i == p.k - 1) break;  // the last level keeps no frontier
+    uint64_t T = h[CTL_LEVEL_T + i];
+    if (!T) {
+      short_of = true;
+      continue;
+    }
+    if (front_limit && T > front_limit) T = front_limit;
+    bytes += al(4ull * (uint64_t)(i + 1) * T) + al(8ull * (T + 1)) + al(4ull * T + 4) +
+             al(8ull * (T / SCAN_TILE + 2));
+  }
+  return short_of ? 2 * bytes : bytes;
 }
 
 // Job records of every step of a batch, staged host side and uploaded once.
@@ -3098,7 +3124,16 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     };
     uint64_t cpi_entries = 0;
     std::vector<char> retried(num_specs, 0);
-    std::vector<char> alone(num_specs, 0);  // ran again in a batch of its own
+    // 1: ran again in a smaller batch packed with other jobs that overflowed;
+    // 2: ran again in a batch of its own
+    std::vector<char> alone(num_specs, 0);
+    // the batch each GFD runs in on the next call with the same GFDs and
+    // options: the planned one, or the smaller one it moved to because the
+    // pool at its cap could not hold its batch's frontiers
+    std::vector<int> home(num_specs, 0);
+    for (size_t b = 0; b < batches.size(); b++)
+      for (int i : batches[b]) home[i] = (int)b;
+    bool moved = false;
     // redo[x]: 1 the job runs again on the bounded path; 2 it runs again in a
     // later fast batch (the frontier pool or CPI arena it overflowed has grown)
     // the batches formed here run their main pass from captured graphs (not
@@ -3173,23 +3208,34 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         std::vector<int> over;  // only the violation staging overflowed
         std::vector<int> win;   // counted last leaf, violations to list: a first-K window
         std::vector<int> again, solo;
+        std::vector<std::pair<uint64_t, int>> pack;  // (frontier bytes asked, GFD)
+        const uint64_t pool_cap = front_usable(ws);
         for (size_t x = 0; x < jobs.size(); x++) {
           const uint64_t* h = ws->hctl + CTL_WORDS * x;
-          std::memcpy(&H[(size_t)jobs[x].spec * CTL_WORDS], h, sizeof(uint64_t) * CTL_WORDS);
+          const int sp = jobs[x].spec;
+          std::memcpy(&H[(size_t)sp * CTL_WORDS], h, sizeof(uint64_t) * CTL_WORDS);
           if (h[CTL_FLAGS] & 5u) {  // frontier or CPI arena overflow
             // a job that failed at one level asks again at the next one, so
             // a few rounds of growth may be needed before its frontiers fit
-            if (grew && retried[jobs[x].spec] < MAX_REGROW) {
+            if (grew && retried[sp] < MAX_REGROW) {
               redo[x] = 2;
-              retried[jobs[x].spec]++;
-              again.push_back(jobs[x].spec);
-            } else if (jobs.size() > 1 && !alone[jobs[x].spec]) {
-              // the pool or arena is at its cap but was shared: alone, the
-              // job has all of it, which is usually enough (and much faster
-              // than the bounded path)
+              retried[sp]++;
+              again.push_back(sp);
+            } else if (jobs.size() > 1 && alone[sp] < 2) {
+              // the pool or arena is at its cap but was shared: in a smaller
+              // batch, then alone, the job has more of it, which is usually
+              // enough (and much faster than the bounded path). Only a
+              // frontier overflow says what the job asks for.
               redo[x] = 2;
-              alone[jobs[x].spec] = 1;
-              solo.push_back(jobs[x].spec);
+              moved = true;
+              const uint64_t need = reached_front_bytes(jobs[x].plan, h, c.front_limit);
+              if (alone[sp] == 0 && !(h[CTL_FLAGS] & 4u) && need < pool_cap) {
+                alone[sp] = 1;
+                pack.push_back({need, sp});
+              } else {
+                alone[sp] = 2;
+                solo.push_back(sp);
+              }
             } else {
               redo[x] = 1;
             }
@@ -3203,7 +3249,35 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
           batches.push_back(again);
           if (stats) stats->regrown_gfds += (int32_t)again.size();
         }
-        for (int sp : solo) batches.push_back({sp});
+        if (!pack.empty()) {
+          // first fit, largest first, into batches that ask at most the pool
+          std::stable_sort(pack.begin(), pack.end(),
+                           [](const std::pair<uint64_t, int>& u, const std::pair<uint64_t, int>& v) {
+                             return u.first > v.first;
+                           });
+          std::vector<std::vector<int>> bins;
+          std::vector<uint64_t> used;
+          for (const auto& [need, sp] : pack) {
+            size_t b = 0;
+            while (b < bins.size() && used[b] + need > pool_cap) b++;
+            if (b == bins.size()) {
+              bins.emplace_back();
+              used.push_back(0);
+            }
+            bins[b].push_back(sp);
+            used[b] += need;
+          }
+          for (auto& bin : bins) {
+            std::sort(bin.begin(), bin.end());
+            for (int sp : bin) home[sp] = (int)batches.size();
+            batches.push_back(bin);
+          }
+          if (stats) stats->regrown_gfds += (int32_t)pack.size();
+        }
+        for (int sp : solo) {
+          home[sp] = (int)batches.size();
+          batches.push_back({sp});
+        }
         if (stats) stats->regrown_gfds += (int32_t)solo.size();
         // the last-level records of the jobs to re-run, as the device holds
         // them (their sources were placed by the frontier reservations)
@@ -3299,6 +3373,19 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
           HIPCHK(hipStreamSynchronize(c.st));
         }
       }
+    }
+    // the next call with these GFDs and options starts from the batches this
+    // one ended with: a GFD that moved to a smaller batch starts in it (not
+    // under a frontier cap, where a GFD overflows in any batch)
+    if (moved && !c.front_limit) {
+      std::vector<std::vector<int>> next;
+      for (size_t b = 0; b < batches.size(); b++) {
+        std::vector<int> keep;
+        for (int i : batches[b])
+          if (home[i] == (int)b) keep.push_back(i);
+        if (!keep.empty()) next.push_back(std::move(keep));
+      }
+      pm->batches = std::move(next);
     }
     // the error word and the per-class bytes, through pinned memory in one wait
     ws->hmisc[1] = 0;
