@@ -38,6 +38,7 @@
 
 #include "gfd.h"
 #include "gfd_internal.h"
+#include "gfd_serve_queue.h"
 
 using namespace gfd;
 
@@ -3520,66 +3521,20 @@ extern "C" int32_t gfd_validate(const gfd_graph* g, const gfd_spec* specs, int32
 // whatever is waiting whenever they are free (continuous batching)
 // ---------------------------------------------------------------------------
 
-namespace {
-
-int64_t now_ns() {
-  return std::chrono::duration_cast<std::chrono::nanoseconds>(
-             std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
-
-struct ServerReq {
-  uint64_t id = 0;
-  std::vector<gfd_spec> specs;
-  std::vector<gfd_result> res;
-  std::vector<int32_t> viol;  // [num_specs * k_max * GFD_MAX_K]
-  int64_t est_bytes = 0;
-  gfd_request_info info{};
-  int32_t status = GFD_OK;
-  std::string err;
-  bool done = false;
-  bool claimed = false;  // a waiter holds it
-};
-
-}  // namespace
-
 struct gfd_server {
   gfd_graph* g = nullptr;
   gfd_server_opts o{};
   int64_t budget = 0;  // per worker
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<ServerReq*> queue;
-  std::unordered_map<uint64_t, ServerReq*> reqs;
-  uint64_t next_id = 1, next_batch = 1;
-  bool stop = false;
+  ServeQueue q;
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
 
   void work(int w) {
     (void)hipSetDevice(g->device);
-    for (;;) {
-      std::vector<ServerReq*> batch;
-      uint64_t bid = 0;
-      {
-        std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
-        if (queue.empty()) return;  // stopping
-        // admit waiting requests in arrival order while the batch stays within
-        // the GFD limit and the estimated device bytes of its jobs
-        int64_t n = 0, bytes = 0;
-        while (!queue.empty()) {
-          ServerReq* r = queue.front();
-          const int64_t rn = (int64_t)r->specs.size();
-          if (!batch.empty() && (n + rn > o.max_batch_gfds || bytes + r->est_bytes > budget)) break;
-          batch.push_back(r);
-          queue.pop_front();
-          n += rn;
-          bytes += r->est_bytes;
-        }
-        bid = next_batch++;
-      }
-      const int64_t t_start = now_ns();
+    std::vector<ServerReq*> batch;
+    uint64_t bid = 0;
+    while (q.take(o.max_batch_gfds, budget, batch, bid)) {
+      const int64_t t_start = serve_now_ns();
       const Range batch_range("server batch");
       std::vector<gfd_spec> specs;
       std::vector<gfd_result> res;
@@ -3612,23 +3567,20 @@ struct gfd_server {
           at += (size_t)nb;
         }
       }
-      const int64_t t_done = now_ns();
-      std::lock_guard<std::mutex> lk(mu);
-      size_t at = 0;
-      for (size_t b = 0; b < batch.size(); b++) {
-        ServerReq* r = batch[b];
-        for (size_t i = 0; i < r->specs.size(); i++) r->res[i] = res[at++];
-        r->status = st[b];
-        r->err = msg[b];
-        r->info.start_ns = t_start;
-        r->info.done_ns = t_done;
-        r->info.batch_id = bid;
-        r->info.batch_gfds = (int32_t)specs.size();
-        r->info.batch_requests = (int32_t)batch.size();
-        r->info.worker = w;
-        r->done = true;
-      }
-      cv_done.notify_all();
+      const int64_t t_done = serve_now_ns();
+      std::vector<size_t> first(batch.size(), 0);
+      for (size_t b = 1; b < batch.size(); b++) first[b] = first[b - 1] + batch[b - 1]->specs.size();
+      q.publish(batch, [&](size_t b, ServerReq& r) {
+        for (size_t i = 0; i < r.specs.size(); i++) r.res[i] = res[first[b] + i];
+        r.status = st[b];
+        r.err = msg[b];
+        r.info.start_ns = t_start;
+        r.info.done_ns = t_done;
+        r.info.batch_id = bid;
+        r.info.batch_gfds = (int32_t)specs.size();
+        r.info.batch_requests = (int32_t)batch.size();
+        r.info.worker = w;
+      });
     }
   }
 };
@@ -3705,11 +3657,7 @@ extern "C" int32_t gfd_server_create(const gfd_graph* gc, const gfd_server_opts*
     for (int w = 0; w < o.workers; w++) s->workers.emplace_back([s, w] { s->work(w); });
   } catch (...) {
     // stop and join the workers already started, then report
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->stop = true;
-    }
-    s->cv_work.notify_all();
+    s->q.shutdown();
     for (auto& t : s->workers)
       if (t.joinable()) t.join();
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
@@ -3746,18 +3694,11 @@ extern "C" int32_t gfd_server_submit(gfd_server* s, const gfd_spec* specs, int32
     r->specs.assign(specs, specs + num_specs);
     r->res.resize(num_specs);
     r->viol.resize((size_t)num_specs * std::max(s->o.k_max, 1) * GFD_MAX_K);
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return set_error(GFD_EINVAL, "server is stopping");
-    r->id = s->next_id++;
-    r->info.submit_ns = now_ns();
-    s->reqs[r->id] = r;
-    s->queue.push_back(r);
-    *request_id = r->id;
+    if (s->q.submit(r, request_id) != ServeQueue::OK) return set_error(GFD_EINVAL, "server is stopping");
     rp.release();
   } catch (...) {
     return guarded([] () -> int32_t { throw; });
   }
-  s->cv_work.notify_one();
   return GFD_OK;
 }
 
@@ -3765,23 +3706,15 @@ extern "C" int32_t gfd_server_wait(gfd_server* s, uint64_t request_id, int32_t t
                                    gfd_result* results, gfd_request_info* info) {
   if (!s) return set_error(GFD_EINVAL, "server is NULL");
   ServerReq* r = nullptr;
-  {
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(request_id);
-    if (it == s->reqs.end()) return set_error(GFD_EINVAL, "unknown request %llu", (unsigned long long)request_id);
-    r = it->second;
-    // one waiter at a time: a second one would find the request freed
-    if (r->claimed) return set_error(GFD_EINVAL, "request %llu is being waited for", (unsigned long long)request_id);
-    r->claimed = true;
-    auto ready = [&] { return r->done; };
-    bool ok = true;
-    if (timeout_ms < 0) s->cv_done.wait(lk, ready);
-    else ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
-    if (!ok) {
-      r->claimed = false;
+  switch (s->q.wait(request_id, timeout_ms, r)) {
+    case ServeQueue::OK:
+      break;
+    case ServeQueue::UNKNOWN:
+      return set_error(GFD_EINVAL, "unknown request %llu", (unsigned long long)request_id);
+    case ServeQueue::CLAIMED:
+      return set_error(GFD_EINVAL, "request %llu is being waited for", (unsigned long long)request_id);
+    default:
       return set_error(GFD_EAGAIN, "request %llu not finished", (unsigned long long)request_id);
-    }
-    s->reqs.erase(request_id);  // the map may have changed while waiting
   }
   const int32_t rc = r->status;
   if (rc) set_error(rc, "%s", r->err.c_str());
@@ -3803,13 +3736,8 @@ extern "C" int32_t gfd_server_wait(gfd_server* s, uint64_t request_id, int32_t t
 
 extern "C" void gfd_server_destroy(gfd_server* s) {
   if (!s) return;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-  }
-  s->cv_work.notify_all();
+  s->q.shutdown();
   for (auto& t : s->workers) t.join();
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-  for (auto& kv : s->reqs) delete kv.second;
-  delete s;
+  delete s;  // and the requests nobody waited for
 }
