@@ -405,7 +405,8 @@ def main():
             for k, v in st["class_ms"].items()))
         log(f"warm-up: wall {st['wall_ms']:.1f} ms, kernel time {sum(st['class_ms'].values()):.1f} ms, "
             f"chunked {st['chunked_gfds']}, threshold {st['threshold_gfds']}/{st['threshold_passes']}, "
-            f"counted leaves {st['leaf_gfds']} ({st['leaf_split_gfds']} split), regrown {st['regrown_gfds']}, graphs "
+            f"counted leaves {st['leaf_gfds']} ({st['leaf_split_gfds']} split), regrown {st['regrown_gfds']}, "
+            f"batches {st['batches']}, graphs "
             f"{st['graph_captures']} captured / {st['graph_replays']} replayed, frontier pool "
             f"{st['front_pool_bytes'] / 1e6:.0f} MB, CPI arena {st['cpi_arena_bytes'] / 1e6:.0f} MB")
         enum_ms = st["class_ms"]["extend"] + st["class_ms"]["extend_last"]

@@ -233,6 +233,8 @@ typedef struct {
   uint64_t units[16];
   int32_t leaf_split_gfds;    /* of leaf_gfds, those whose last two leaves hang from different
                                  parents (counted as list products less shared vertices) */
+  int32_t batches;            /* batches whose main pass ran: the planned ones and those of
+                                 GFDs run again (regrown_gfds) */
 } gfd_stats;
 
 /* Load a graph given as out-CSR, in host memory or (opts->mem_kind ==

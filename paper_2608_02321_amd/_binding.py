@@ -107,7 +107,8 @@ class gfd_stats(C.Structure):
                 ("regrown_gfds", C.c_int32), ("front_pool_bytes", C.c_int64),
                 ("cpi_arena_bytes", C.c_int64), ("graph_captures", C.c_int32),
                 ("graph_replays", C.c_int32), ("units_counted", C.c_int32),
-                ("units", C.c_uint64 * 16), ("leaf_split_gfds", C.c_int32)]
+                ("units", C.c_uint64 * 16), ("leaf_split_gfds", C.c_int32),
+                ("batches", C.c_int32)]
 
 
 class gfd_graph_info(C.Structure):

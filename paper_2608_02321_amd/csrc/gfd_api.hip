@@ -170,7 +170,8 @@ constexpr int CTL_WORDS = 64;
 enum {
   CTL_MATCH = 0, CTL_VIOL = 1, CTL_MFP = 2, CTL_VFP = 3, CTL_VCOUNT = 4, CTL_FLAGS = 5,
   CTL_NEEDSEL = 6, CTL_THRVALID = 7, CTL_LEVEL_N = 8 /* +i */, CTL_LEVEL_T = 16 /* +i */,
-  CTL_TOTAL = 24, CTL_OUTCOUNT = 25, CTL_TICKET = 26, CTL_CPIBASE = 27, CTL_CAND = 32 /* +2u+b */,
+  CTL_TOTAL = 24, CTL_OUTCOUNT = 25, CTL_TICKET = 26, CTL_CPIBASE = 27, CTL_CPIASK = 28,
+  CTL_CAND = 32 /* +2u+b */,
   CTL_THR = 48 /* 4 words = 8 int32 */
 };
 
@@ -1648,6 +1649,7 @@ static void plan_batch(Ctx& c, std::vector<Job>& jobs, Recs& R, LaunchList& L,
       a.len = J.mem.cpi_len[u];
       a.cur = J.mem.cpi_cur[u];
       a.d_base = J.mem.ctl + CTL_CPIBASE;
+      a.d_asked = J.mem.ctl + CTL_CPIASK;
       a.arena = c.ws->cpi_arena;
       a.arena_cursor = c.ws->misc;
       a.arena_cap = cpi_usable(c.ws);
@@ -3128,13 +3130,8 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
     // 1: ran again in a smaller batch packed with other jobs that overflowed;
     // 2: ran again in a batch of its own
     std::vector<char> alone(num_specs, 0);
-    // the batch each GFD runs in on the next call with the same GFDs and
-    // options: the planned one, or the smaller one it moved to because the
-    // pool at its cap could not hold its batch's frontiers
-    std::vector<int> home(num_specs, 0);
-    for (size_t b = 0; b < batches.size(); b++)
-      for (int i : batches[b]) home[i] = (int)b;
-    bool moved = false;
+    bool moved = false;                         // a GFD left its batch: the pool was at its cap
+    std::vector<char> went_bounded(num_specs, 0);
     // redo[x]: 1 the job runs again on the bounded path; 2 it runs again in a
     // later fast batch (the frontier pool or CPI arena it overflowed has grown)
     // the batches formed here run their main pass from captured graphs (not
@@ -3270,15 +3267,11 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
           }
           for (auto& bin : bins) {
             std::sort(bin.begin(), bin.end());
-            for (int sp : bin) home[sp] = (int)batches.size();
             batches.push_back(bin);
           }
           if (stats) stats->regrown_gfds += (int32_t)pack.size();
         }
-        for (int sp : solo) {
-          home[sp] = (int)batches.size();
-          batches.push_back({sp});
-        }
+        for (int sp : solo) batches.push_back({sp});
         if (stats) stats->regrown_gfds += (int32_t)solo.size();
         // the last-level records of the jobs to re-run, as the device holds
         // them (their sources were placed by the frontier reservations)
@@ -3361,6 +3354,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
       for (size_t x = 0; x < jobs.size(); x++) {
         if (redo[x] != 1) continue;
         if (stats) stats->chunked_gfds++;
+        went_bounded[jobs[x].spec] = 1;
         const Range bounded("bounded re-run");
         run_bounded(c, jobs[x], vbig);
         HIPCHK(hipMemcpyAsync(&H[(size_t)jobs[x].spec * CTL_WORDS], jobs[x].mem.ctl,
@@ -3375,16 +3369,51 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
         }
       }
     }
-    // the next call with these GFDs and options starts from the batches this
-    // one ended with: a GFD that moved to a smaller batch starts in it (not
-    // under a frontier cap, where a GFD overflows in any batch)
+    // the next call with these GFDs and options: when GFDs had to leave their
+    // batches (the pool or arena was at its cap), every GFD's frontier bytes
+    // and CPI entries are now known exactly from its control words, so its
+    // batches are formed again from them, first fit, largest first by
+    // frontier bytes, within the pool and the arena (less a sixteenth for the
+    // levels that reserved without attempts), the budget and the batch
+    // limit; a GFD that needed the bounded path runs alone (not under a
+    // frontier cap, where a GFD overflows in any batch)
     if (moved && !c.front_limit) {
+      const uint64_t cap = front_usable(ws) - front_usable(ws) / 16;
+      const uint64_t cpi_cap = cpi_usable(ws) - cpi_usable(ws) / 16;
       std::vector<std::vector<int>> next;
-      for (size_t b = 0; b < batches.size(); b++) {
-        std::vector<int> keep;
-        for (int i : batches[b])
-          if (home[i] == (int)b) keep.push_back(i);
-        if (!keep.empty()) next.push_back(std::move(keep));
+      std::vector<std::pair<uint64_t, int>> order;
+      for (int32_t i = 0; i < num_specs; i++) {
+        if (went_bounded[i]) next.push_back({i});
+        else order.push_back({reached_front_bytes(all[i].plan, &H[(size_t)i * CTL_WORDS], 0), i});
+      }
+      std::stable_sort(order.begin(), order.end(),
+                       [](const std::pair<uint64_t, int>& u, const std::pair<uint64_t, int>& v) {
+                         return u.first > v.first;
+                       });
+      std::vector<std::vector<int>> bins;
+      std::vector<uint64_t> fb, cb;
+      std::vector<int64_t> ab;
+      for (const auto& [need, i] : order) {
+        const int64_t b = (int64_t)all[i].caps.bytes + 4096 * CTL_WORDS;
+        const uint64_t e = H[(size_t)i * CTL_WORDS + CTL_CPIASK];
+        size_t x = 0;
+        while (x < bins.size() && (fb[x] + need > cap || cb[x] + e > cpi_cap || ab[x] + b > budget ||
+                                   (int)bins[x].size() >= max_batch))
+          x++;
+        if (x == bins.size()) {
+          bins.emplace_back();
+          fb.push_back(0);
+          cb.push_back(0);
+          ab.push_back(0);
+        }
+        bins[x].push_back(i);
+        fb[x] += need;
+        cb[x] += e;
+        ab[x] += b;
+      }
+      for (auto& bin : bins) {
+        std::sort(bin.begin(), bin.end());
+        next.push_back(std::move(bin));
       }
       pm->batches = std::move(next);
     }
@@ -3413,6 +3442,7 @@ static int32_t validate_impl(const gfd_graph* gc, const gfd_spec* specs, int32_t
       stats->cpi_entries = cpi_entries;
       stats->units_counted = units_counted() ? 1 : 0;
       units_read(c.st, stats->units);
+      stats->batches = (int32_t)batches.size();
       stats->front_pool_bytes = (int64_t)ws->front_bytes;
       stats->cpi_arena_bytes = (int64_t)ws->cpi_cap * 4;
       if (c.tm.on) c.tm.collect(stats->class_ms);

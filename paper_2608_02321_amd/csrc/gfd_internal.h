@@ -198,6 +198,7 @@ struct CpiJob {
   uint64_t arena_cap;
   uint32_t* flags;       // bit 2: arena overflow
   uint64_t* d_base;      // one pass: the job's region of the arena (~0: out of arena)
+  uint64_t* d_asked;     // one pass: the job's entries asked, summed over its tree edges
   JobScan sc;            // over rows of C(p)
   // labelled p and prim: the edge-label block (p's bucket, prim) of direction
   // dir is rows [rb, re); bucket base position `base`

@@ -1220,6 +1220,7 @@ __global__ void k_cpi_reserve(const CpiJob* __restrict__ jobs) {
   if (!J.active || threadIdx.x != 0) return;
   const uint64_t total = cpi_sources(J) ? *J.sc.d_total : 0ull;
   const uint64_t base = total ? atomicAdd(J.arena_cursor, (unsigned long long)total) : 0ull;
+  *J.d_asked += total;  // one thread per job; the job's edges reserve one launch after another
   if (base + total > J.arena_cap) {
     atomicOr(J.flags, 4u);
     *J.d_base = ~0ull;
