@@ -40,13 +40,13 @@ K_REPORT = 1024
 # 1 GiB copy-like kernel (bench.py --copy-probe); see profiles/.  Valid only
 # for the kernel sources it was measured on (sha256 of the two files below).
 TRAFFIC = {
-    "sources_sha256": "7893ace4b3e79b2ba36147f29d13e679bacfcdde7f7757b841882028089c53ff",
+    "sources_sha256": "e17cd3e18361270f28fdf57df0686bc5f1e05d216f1b6519571bccc497f90f78",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",  # k_ext_run<true, false, 8>
     "semantics": "induced",
     "count_only": False,
-    # (601.49 MB read + 38.44 MB written) per dispatch, calibrated (x1.9999, x1.0)
-    "bytes_per_launch": 6.3993e+08,
+    # (638.27 MB read + 39.77 MB written) per dispatch, calibrated (x1.9999, x1.0)
+    "bytes_per_launch": 6.7804e+08,
 }
 # Units of work of the dominant kernel class per step (one validate call),
 # from the counting build (bench.py --units; see profiles/), and the
@@ -57,17 +57,17 @@ TRAFFIC = {
 # small threshold re-run launch or not, which leaves the work per step as it
 # is.  Valid only for the kernel sources it was counted on.
 UNITS = {
-    "sources_sha256": "7893ace4b3e79b2ba36147f29d13e679bacfcdde7f7757b841882028089c53ff",
+    "sources_sha256": "e17cd3e18361270f28fdf57df0686bc5f1e05d216f1b6519571bccc497f90f78",
     "workload": "kg_4m_batch256",
     "kernel_class": "extend_last",
     "semantics": "induced",
     "count_only": False,
-    "per_step": {"attempts": 158317805, "sources": 12607194, "injective": 158306218,
-                 "checks_both": 416171595, "table_free": 361280197, "table_hit": 8271503,
-                 "short_row": 46619895, "both_steps": 205707061, "both_log2d": 3853347660,
+    "per_step": {"attempts": 158480914, "sources": 12614816, "injective": 158469327,
+                 "checks_both": 416611439, "table_free": 361637571, "table_hit": 8274566,
+                 "short_row": 46699302, "both_steps": 205912408, "both_log2d": 3856520308,
                  "checks_one": 0, "one_steps": 0, "one_log2d": 0, "matches": 147891222,
-                 "literal_reads": 162619266, "violations": 68082422, "inner_attempts": 19481978},
-    "model_bytes_per_step": 3.22114e10,
+                 "literal_reads": 162874008, "violations": 68082422, "inner_attempts": 19555525},
+    "model_bytes_per_step": 3.22385e10,
 }
 TRAFFIC_SOURCES = ("paper_2608_02321_amd/csrc/gfd_kernels.hip", "paper_2608_02321_amd/csrc/gfd_internal.h")
 
