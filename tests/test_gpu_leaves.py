@@ -275,6 +275,13 @@ def test_counted_leaf_windows_full_size_batch(P):
     for i, (r, e) in enumerate(zip(got, exp["results"]["mono"])):
         assert r == dict(e, match_fp=0, violation_fp=0), i
     assert st["leaf_gfds"] > 50
+    # under a 1 GiB budget: GFDs overflow the capped pool and arena and run
+    # again; the next calls run in batches formed from what each asked
+    for call in range(3):
+        got, st = P.validate(gh, exp["gfds"], K=exp["K"], semantics="mono", mem_budget_bytes=1 << 30,
+                             flags=P.GFD_FLAG_COUNT_ONLY, stats=True, batched=True)
+        for i, (r, e) in enumerate(zip(got, exp["results"]["mono"])):
+            assert r == dict(e, match_fp=0, violation_fp=0), (call, i)
     gh.free()
 
 
@@ -296,4 +303,11 @@ def test_counted_leaves_full_size_batch(P):
         assert (r["match_count"], r["violation_count"], r["satisfied"]) == \
             (e["match_count"], e["violation_count"], e["satisfied"]), i
     assert st["leaf_gfds"] > 100
+    # and under a 256 MiB budget, the second call in batches formed from the first
+    for call in range(2):
+        got, st = P.validate(gh, exp["gfds"], K=0, semantics="mono", flags=P.GFD_FLAG_COUNT_ONLY,
+                             mem_budget_bytes=256 << 20, stats=True, batched=True)
+        for i, (r, e) in enumerate(zip(got, exp["results"]["mono"])):
+            assert (r["match_count"], r["violation_count"], r["satisfied"]) == \
+                (e["match_count"], e["violation_count"], e["satisfied"]), (call, i)
     gh.free()
